@@ -1,0 +1,160 @@
+/*
+ * ssl.h -- C ABI of the MI355X (gfx950) GSVD-MUSIC sound-source-localization library.
+ *
+ * The method (arXiv 2504.03373, Sec. III-A and III-B):
+ *   eq.2-3  R(w)  = (1/T) sum_t X(w,t) X(w,t)^H           correlation per frequency bin w
+ *   eq.4    K(w)^{-1} R(w) = E Lambda E_r                 GSVD against the preset noise correlation K
+ *           E_n(w) = [e_{Ns+1} .. e_M]                    noise subspace (left singular vectors)
+ *   eq.5    P(theta,w) = |H^H H| / sum_i |H^H e_i|^p      MUSIC pseudo-spectrum (p = 2 default, 1 = literal)
+ *   eq.6    Pbar(theta) = sum_w P(theta,w)                 sum over bins
+ *   Sec. III-A, last paragraph: the preset number Ns of peaks of Pbar over the direction grid.
+ *
+ * Conventions for every entry point:
+ *   - Array arguments are caller-owned DEVICE pointers (HBM of the context's device) unless the
+ *     comment says "host".  The library never frees them and never keeps them past the completion
+ *     of the work it enqueued on `stream`.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the legacy default stream).  Everything is
+ *     enqueued asynchronously on it; the call returns before the GPU has finished.
+ *   - Complex numbers are interleaved (re, im): ssl_c64 == torch.complex64, ssl_c128 == complex128.
+ *   - Matrices are row-major per bin: element (i, j) of bin f of an [F][M][M] array is at
+ *     f*M*M + i*M + j.  E_n is stored column-major per bin: column c of bin f at (f*(M-Ns)+c)*M.
+ *   - Argument, shape and budget errors are reported synchronously by the return value; nothing is
+ *     enqueued in that case and ssl_last_error() describes the problem.  Numerical failures are
+ *     reported per bin, asynchronously, in `bin_status` (ssl_bin_status codes); a failed bin
+ *     contributes 0 to Pbar and never poisons the other bins.
+ *   - No C++ exception crosses this interface.  A context is not thread-safe: use one per host
+ *     thread.  Calls that share a context must be ordered on one stream (its workspace is reused).
+ *   - Limits: 1 <= M <= 64, 1 <= Ns < M, F, T, D >= 1, p in {1, 2}.
+ */
+#ifndef SSL_MI355X_H
+#define SSL_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { float re, im; } ssl_c64;
+typedef struct { double re, im; } ssl_c128;
+
+typedef struct ssl_ctx_s *ssl_ctx;      /* library-owned: device, workspace (HBM budget) */
+typedef struct ssl_noise_s *ssl_noise;  /* library-owned: one stream's K and its FP64 factor */
+
+typedef enum {
+    SSL_OK = 0,
+    SSL_ERR_ARG = -1,     /* bad argument or shape */
+    SSL_ERR_NOMEM = -2,   /* device allocation failed */
+    SSL_ERR_BUDGET = -3,  /* workspace would exceed the context's HBM budget */
+    SSL_ERR_HIP = -4,     /* a HIP runtime call failed */
+    SSL_ERR_STATE = -5    /* object used in the wrong state (e.g. noise handle never set) */
+} ssl_status;
+
+typedef enum {
+    SSL_BIN_OK = 0,
+    SSL_BIN_NOT_PD = 1,     /* K(w) is not numerically positive definite (FP64 Cholesky pivot
+                               d_k <= 2^-40 * max_i K_ii, or not finite) */
+    SSL_BIN_NO_CONV = 2,    /* the Jacobi SVD hit max_sweeps before converging */
+    SSL_BIN_NONFINITE = 3   /* NaN or Inf in R(w) */
+} ssl_bin_status;
+
+typedef enum { SSL_FP32 = 0, SSL_BF16 = 1, SSL_FP16 = 2, SSL_FP64 = 3 } ssl_prec;
+
+/* ---------------------------------------------------------------- context */
+
+/* Creates a context on HIP device `device`.  hbm_budget_bytes bounds the workspace the context may
+ * allocate (0 = unlimited).  Returns SSL_ERR_ARG for a bad device, SSL_ERR_HIP on runtime errors. */
+ssl_status ssl_ctx_create(ssl_ctx *out, int device, size_t hbm_budget_bytes);
+void ssl_ctx_destroy(ssl_ctx ctx);
+/* Bytes of device workspace the context currently holds. */
+size_t ssl_ctx_workspace_bytes(ssl_ctx ctx);
+/* Thread-local description of the last error of this thread (never NULL; "" if none). */
+const char *ssl_last_error(void);
+/* Library version as major*10000 + minor*100 + patch. */
+int ssl_version(void);
+
+/* ------------------------------------------------------- correlation (eq.2-3) */
+
+/* AddCorrelation + NormalizeCorrelation (eq.2, eq.3):
+ *   R[f] = scale * sum_{t<T} X[f,t,:] X[f,t,:]^H   (+ R[f] when accumulate != 0)
+ * X: [F][T][M] complex64, M contiguous, element strides strideF, strideT (>= M).
+ * prec: SSL_FP32 -> R is ssl_c64 [F][M][M], accumulated in FP32 on MFMA;
+ *       SSL_BF16 / SSL_FP16 -> R is ssl_c64, X rounded to bf16/fp16 MFMA inputs, FP32 accumulation;
+ *       SSL_FP64 -> R is ssl_c128 [F][M][M], FP64 accumulation (use it for the noise correlation K).
+ * Both triangles are written from one computed value: R is Hermitian to the bit, diag imag = 0. */
+ssl_status ssl_corr_accum(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int M, int64_t strideF,
+                          int64_t strideT, double scale, int accumulate, ssl_prec prec, void *R,
+                          void *stream);
+
+/* ------------------------------------------------- noise correlation handle */
+
+/* A noise handle keeps one stream's preset noise correlation K(w) (the K of eq.4) resident on the
+ * device in complex128 together with its FP64 factorisation, so each block only pays for the
+ * whitening product.  Owned by the library; destroy with ssl_noise_destroy. */
+ssl_status ssl_noise_create(ssl_ctx ctx, int F, int M, ssl_noise *out);
+/* Copies K ([F][M][M]; ssl_c128 if kprec == SSL_FP64, ssl_c64 if SSL_FP32) into the handle and
+ * factors it in FP64: K = L L^H per bin, then K^{-1} = L^{-H} L^{-1}.  Per-bin result in
+ * bin_status ([F] int32, may be NULL): SSL_BIN_OK or SSL_BIN_NOT_PD. */
+ssl_status ssl_noise_set(ssl_noise K, const void *Kin, ssl_prec kprec, int32_t *bin_status,
+                         void *stream);
+/* Exponential averaging for streams whose noise field drifts:
+ *   K <- alpha * K + (1 - alpha) * Khat, then refactor (same outputs as ssl_noise_set). */
+ssl_status ssl_noise_update(ssl_noise K, const void *Khat, ssl_prec kprec, double alpha,
+                            int32_t *bin_status, void *stream);
+/* Copies the current K (complex128 [F][M][M]) to K_out (device) for checkpointing. */
+ssl_status ssl_noise_get(ssl_noise K, ssl_c128 *K_out, void *stream);
+void ssl_noise_destroy(ssl_noise K);
+
+/* --------------------------------------------------------------- GSVD (eq.4) */
+
+/* For every bin f: A = K^{-1} R (FP64 product with the handle's inverse, rounded to complex64),
+ * then the SVD A = U Sigma V^H by one-sided Jacobi in FP32 with the whole M x M problem resident in
+ * LDS (convergence test in FP64: |b_i^H b_j| <= M 2^-24 |b_i||b_j| for every pair of a sweep),
+ * singular values sorted descending (ties: lower column first), and
+ *   En[f] = U[:, Ns..M-1]   written column-major: [F][M-Ns][M] ssl_c64.
+ * R: [F][M][M] ssl_c64 (e.g. from ssl_corr_accum).  K: a handle set for the same F and M.
+ * sigma: [F][M] float or NULL.  bin_status: [F] int32 or NULL.
+ * conv: [F][2] int32 or NULL -> (sweeps run, rotations applied) per bin.
+ * max_sweeps: 0 selects the default (20).  Failed bins get En = 0 and sigma = 0. */
+ssl_status ssl_gsvd(ssl_ctx ctx, const ssl_c64 *R, ssl_noise K, int F, int M, int Ns, ssl_c64 *En,
+                    float *sigma, int32_t *bin_status, int32_t *conv, int max_sweeps, void *stream);
+
+/* ------------------------------------------------- MUSIC spectrum (eq.5-6) */
+
+/* den[f,d] = sum_{c<M-Ns} |H[f,d,:]^H En[f,:,c]|^p,   P[f,d] = |H[f,d,:]|^2 / max(den, FLT_MIN),
+ * Pbar[d] = sum_f P[f,d] (bins in ascending order within fixed chunks; deterministic).
+ * H: [F][D][M], ssl_c64 if hprec == SSL_FP32, or interleaved bf16/fp16 pairs (4 bytes per complex)
+ * for SSL_BF16 / SSL_FP16 (the projection then runs on bf16/fp16 MFMA with FP32 accumulation; En
+ * is rounded to the same type).  P: [F][D] float or NULL; Pbar: [D] float (required).
+ * bin_status: [F] or NULL; bins whose status is not SSL_BIN_OK contribute P = 0. */
+ssl_status ssl_music_spectrum(ssl_ctx ctx, const void *H, ssl_prec hprec, const ssl_c64 *En, int F,
+                              int D, int M, int Ns, int p, float *P, float *Pbar,
+                              const int32_t *bin_status, void *stream);
+
+/* --------------------------------------------------------------- peak search */
+
+/* The Ns largest local maxima of Pbar on the n_el x n_az grid (flat index d = el*n_az + az):
+ * d is a local maximum when Pbar[d] >= each of its 8 neighbours (azimuth circular, elevation
+ * clamped) and an equal neighbour has a higher index; maxima are ranked by value, then by lower
+ * index.  peaks: [Ns] int32 (-1 where fewer maxima exist), peak_val: [Ns] float (0 there).
+ * Non-finite Pbar entries are never peaks and never block one. */
+ssl_status ssl_peaks(ssl_ctx ctx, const float *Pbar, int n_az, int n_el, int Ns, int32_t *peaks,
+                     float *peak_val, void *stream);
+
+/* ----------------------------------------------------------- whole path */
+
+/* One block end to end: R = (1/T) sum X X^H (eq.2-3), A = K^{-1} R and E_n (eq.4), P (eq.5),
+ * Pbar (eq.6), peaks.  X as in ssl_corr_accum; H as in ssl_music_spectrum with D = n_az*n_el;
+ * prec selects the MFMA input type of the correlation and the projection (SSL_FP32, SSL_BF16 or
+ * SSL_FP16; H must be stored in that type).  Pbar ([D]) and bin_status ([F]) may be NULL.
+ * Uses the context's workspace (allocated on first use within the HBM budget). */
+ssl_status ssl_localize(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int M, int64_t strideF,
+                        int64_t strideT, ssl_noise K, const void *H, ssl_prec prec, int n_az,
+                        int n_el, int Ns, int p, int32_t *peaks, float *peak_val, float *Pbar,
+                        int32_t *bin_status, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SSL_MI355X_H */

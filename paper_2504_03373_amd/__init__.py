@@ -1,0 +1,185 @@
+"""MI355X (gfx950) GSVD-MUSIC sound-source localization -- Python binding of the C ABI.
+
+Thin ctypes layer over ``libssl_mi355x.so`` (include/ssl.h).  Functions carry the C names and
+only marshal arguments: tensors become device pointers, the current torch stream becomes the
+hipStream_t, errors become :class:`SSLError`.  Every step of the method runs in the library's
+HIP kernels; there is no other implementation behind these calls, and importing or calling them
+without the built library raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libssl_mi355x.so")
+
+# ssl_status
+SSL_OK, SSL_ERR_ARG, SSL_ERR_NOMEM, SSL_ERR_BUDGET, SSL_ERR_HIP, SSL_ERR_STATE = 0, -1, -2, -3, -4, -5
+# ssl_bin_status
+SSL_BIN_OK, SSL_BIN_NOT_PD, SSL_BIN_NO_CONV, SSL_BIN_NONFINITE = 0, 1, 2, 3
+# ssl_prec
+SSL_FP32, SSL_BF16, SSL_FP16, SSL_FP64 = 0, 1, 2, 3
+
+EXPORTED = [
+    "ssl_ctx_create", "ssl_ctx_destroy", "ssl_ctx_workspace_bytes", "ssl_last_error", "ssl_version",
+    "ssl_corr_accum", "ssl_noise_create", "ssl_noise_set", "ssl_noise_update", "ssl_noise_get",
+    "ssl_noise_destroy", "ssl_gsvd", "ssl_music_spectrum", "ssl_peaks", "ssl_localize",
+]
+
+
+class SSLError(RuntimeError):
+    def __init__(self, fn: str, code: int, msg: str):
+        super().__init__(f"{fn} failed with status {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Loads the built HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2504_03373_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, I64, D, SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    sig = {
+        "ssl_ctx_create": (I, [ctypes.POINTER(P), I, SZ]),
+        "ssl_ctx_destroy": (None, [P]),
+        "ssl_ctx_workspace_bytes": (SZ, [P]),
+        "ssl_last_error": (ctypes.c_char_p, []),
+        "ssl_version": (I, []),
+        "ssl_corr_accum": (I, [P, P, I, I, I, I64, I64, D, I, I, P, P]),
+        "ssl_noise_create": (I, [P, I, I, ctypes.POINTER(P)]),
+        "ssl_noise_set": (I, [P, P, I, P, P]),
+        "ssl_noise_update": (I, [P, P, I, D, P, P]),
+        "ssl_noise_get": (I, [P, P, P]),
+        "ssl_noise_destroy": (None, [P]),
+        "ssl_gsvd": (I, [P, P, P, I, I, I, P, P, P, P, I, P]),
+        "ssl_music_spectrum": (I, [P, P, I, P, I, I, I, I, I, P, P, P, P]),
+        "ssl_peaks": (I, [P, P, I, I, I, P, P, P]),
+        "ssl_localize": (I, [P, P, I, I, I, I64, I64, P, P, I, I, I, I, I, P, P, P, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    if not t.is_cuda:
+        raise ValueError("array arguments must be device tensors")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _check(fn: str, code: int):
+    if code != SSL_OK:
+        raise SSLError(fn, code, lib().ssl_last_error().decode())
+
+
+# ------------------------------------------------------------------------------------------------
+def ssl_version() -> int:
+    return lib().ssl_version()
+
+
+def ssl_last_error() -> str:
+    return lib().ssl_last_error().decode()
+
+
+def ssl_ctx_create(device: int = 0, hbm_budget_bytes: int = 0) -> int:
+    out = ctypes.c_void_p()
+    _check("ssl_ctx_create", lib().ssl_ctx_create(ctypes.byref(out), device, hbm_budget_bytes))
+    return out.value
+
+
+def ssl_ctx_destroy(ctx: int) -> None:
+    lib().ssl_ctx_destroy(ctx)
+
+
+def ssl_ctx_workspace_bytes(ctx: int) -> int:
+    return lib().ssl_ctx_workspace_bytes(ctx)
+
+
+def ssl_corr_accum(ctx, X, scale, accumulate, prec, R, stream=None, F=None, T=None, M=None):
+    """eq.2-3.  X: complex64 device tensor [F][T][M] (M contiguous, any F/T strides)."""
+    F_, T_, M_ = X.shape
+    sF, sT, sM = X.stride()
+    if sM != 1:
+        raise ValueError("X must be contiguous along M")
+    _check("ssl_corr_accum", lib().ssl_corr_accum(ctx, _ptr(X), F_, T_, M_, sF, sT, float(scale),
+                                                  int(accumulate), prec, _ptr(R), _stream(stream)))
+
+
+def ssl_noise_create(ctx, F: int, M: int) -> int:
+    out = ctypes.c_void_p()
+    _check("ssl_noise_create", lib().ssl_noise_create(ctx, F, M, ctypes.byref(out)))
+    return out.value
+
+
+def ssl_noise_set(noise, K, kprec, bin_status=None, stream=None):
+    _check("ssl_noise_set", lib().ssl_noise_set(noise, _ptr(K), kprec, _ptr(bin_status), _stream(stream)))
+
+
+def ssl_noise_update(noise, Khat, kprec, alpha, bin_status=None, stream=None):
+    _check("ssl_noise_update", lib().ssl_noise_update(noise, _ptr(Khat), kprec, float(alpha),
+                                                      _ptr(bin_status), _stream(stream)))
+
+
+def ssl_noise_get(noise, K_out, stream=None):
+    _check("ssl_noise_get", lib().ssl_noise_get(noise, _ptr(K_out), _stream(stream)))
+
+
+def ssl_noise_destroy(noise) -> None:
+    lib().ssl_noise_destroy(noise)
+
+
+def ssl_gsvd(ctx, R, noise, Ns, En, sigma=None, bin_status=None, conv=None, max_sweeps=0,
+             stream=None):
+    F, M, _ = R.shape
+    _check("ssl_gsvd", lib().ssl_gsvd(ctx, _ptr(R), noise, F, M, Ns, _ptr(En), _ptr(sigma),
+                                      _ptr(bin_status), _ptr(conv), max_sweeps, _stream(stream)))
+
+
+def ssl_music_spectrum(ctx, H, hprec, En, Ns, p, P=None, Pbar=None, bin_status=None, stream=None,
+                       F=None, D=None, M=None):
+    """eq.5-6.  H: [F][D][M] complex64 (SSL_FP32) or [F][D][2M] bf16/fp16 pairs."""
+    F_ = H.shape[0] if F is None else F
+    D_ = H.shape[1] if D is None else D
+    M_ = En.shape[2] if M is None else M
+    _check("ssl_music_spectrum", lib().ssl_music_spectrum(ctx, _ptr(H), hprec, _ptr(En), F_, D_, M_,
+                                                          Ns, p, _ptr(P), _ptr(Pbar),
+                                                          _ptr(bin_status), _stream(stream)))
+
+
+def ssl_peaks(ctx, Pbar, n_az, n_el, Ns, peaks, peak_val, stream=None):
+    _check("ssl_peaks", lib().ssl_peaks(ctx, _ptr(Pbar), n_az, n_el, Ns, _ptr(peaks), _ptr(peak_val),
+                                        _stream(stream)))
+
+
+def ssl_localize(ctx, X, noise, H, prec, n_az, n_el, Ns, p, peaks, peak_val, Pbar=None,
+                 bin_status=None, stream=None):
+    F, T, M = X.shape
+    sF, sT, sM = X.stride()
+    if sM != 1:
+        raise ValueError("X must be contiguous along M")
+    _check("ssl_localize", lib().ssl_localize(ctx, _ptr(X), F, T, M, sF, sT, noise, _ptr(H), prec,
+                                              n_az, n_el, Ns, p, _ptr(peaks), _ptr(peak_val),
+                                              _ptr(Pbar), _ptr(bin_status), _stream(stream)))

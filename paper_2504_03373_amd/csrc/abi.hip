@@ -1,0 +1,502 @@
+// C ABI of the GSVD-MUSIC library (declared in include/ssl.h): argument validation, contexts,
+// noise handles, workspace under an HBM budget, and the launch sequences of the entry points.
+// Every arithmetic step runs in the HIP kernels of corr.hip, noise.hip, jacobi.hip, steer.hip and
+// peaks.hip; this file only checks, allocates and enqueues.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "ssl_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+bool ok_prec(ssl_prec p) { return p == SSL_FP32 || p == SSL_BF16 || p == SSL_FP16 || p == SSL_FP64; }
+
+ssl_status hip_fail(hipError_t e, const char *what)
+{
+    ssl_set_error("%s: %s", what, hipGetErrorString(e));
+    return SSL_ERR_HIP;
+}
+
+// Makes ctx->device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+ssl_status dev_alloc(ssl_ctx ctx, void **p, size_t bytes, const char *what)
+{
+    if (ctx->budget && ctx->held + bytes > ctx->budget) {
+        ssl_set_error("%s: %zu bytes would exceed the HBM budget (%zu held of %zu)", what, bytes,
+                      ctx->held, ctx->budget);
+        return SSL_ERR_BUDGET;
+    }
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        ssl_set_error("%s: hipMalloc(%zu) failed: %s", what, bytes, hipGetErrorString(e));
+        return SSL_ERR_NOMEM;
+    }
+    ctx->held += bytes;
+    return SSL_OK;
+}
+
+void dev_free(ssl_ctx ctx, void *p, size_t bytes)
+{
+    if (p) {
+        (void)hipFree(p);
+        ctx->held -= bytes;
+    }
+}
+
+// Grows the context workspace to at least `bytes` (never shrinks).  hipFree of the old block
+// synchronises the device, so in-flight work that used it has finished.
+ssl_status ws_reserve(ssl_ctx ctx, size_t bytes)
+{
+    if (ctx->ws_bytes >= bytes) return SSL_OK;
+    if (ctx->budget && ctx->held - ctx->ws_bytes + bytes > ctx->budget) {
+        ssl_set_error("workspace of %zu bytes exceeds the HBM budget (%zu)", bytes, ctx->budget);
+        return SSL_ERR_BUDGET;
+    }
+    dev_free(ctx, ctx->ws, ctx->ws_bytes);
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+    ssl_status s = dev_alloc(ctx, &ctx->ws, bytes, "workspace");
+    if (s == SSL_OK) ctx->ws_bytes = bytes;
+    return s;
+}
+
+// Bin-sum scratch: [chunks][D] partials + a completion counter that starts (and is left) at 0.
+ssl_status binsum_reserve(ssl_ctx ctx, int F, int D)
+{
+    const size_t nch = (size_t)(F + SSL_BINSUM_CHUNK - 1) / SSL_BINSUM_CHUNK;
+    const size_t need = nch * (size_t)D;
+    if (ctx->binsum_floats >= need && ctx->binsum_counter) return SSL_OK;
+    if (ctx->binsum_counter) {
+        dev_free(ctx, ctx->binsum_counter, ctx->binsum_floats * sizeof(float) + 256);
+        ctx->binsum_part = nullptr;
+        ctx->binsum_counter = nullptr;
+        ctx->binsum_floats = 0;
+    }
+    void *p = nullptr;
+    const size_t bytes = need * sizeof(float) + 256;
+    ssl_status s = dev_alloc(ctx, &p, bytes, "bin-sum scratch");
+    if (s != SSL_OK) return s;
+    hipError_t e = hipMemset(p, 0, bytes);
+    if (e != hipSuccess) {
+        dev_free(ctx, p, bytes);
+        return hip_fail(e, "hipMemset");
+    }
+    ctx->binsum_counter = reinterpret_cast<unsigned int *>(p);
+    ctx->binsum_part = reinterpret_cast<float *>(static_cast<char *>(p) + 256);
+    ctx->binsum_floats = need;
+    return SSL_OK;
+}
+
+ssl_status check_common(int F, int M, int Ns)
+{
+    if (F < 1 || F > 65535) {
+        ssl_set_error("F = %d out of range [1, 65535]", F);
+        return SSL_ERR_ARG;
+    }
+    if (M < 1 || M > SSL_MAX_M) {
+        ssl_set_error("M = %d out of range [1, %d]", M, SSL_MAX_M);
+        return SSL_ERR_ARG;
+    }
+    if (Ns != -1 && (Ns < 1 || Ns >= M)) {
+        ssl_set_error("Ns = %d must satisfy 1 <= Ns < M = %d", Ns, M);
+        return SSL_ERR_ARG;
+    }
+    return SSL_OK;
+}
+
+ssl_status check_grid(int n_az, int n_el, int Ns)
+{
+    if (n_az < 1 || n_el < 1 || (int64_t)n_az * n_el > (1 << 24)) {
+        ssl_set_error("direction grid %d x %d invalid", n_el, n_az);
+        return SSL_ERR_ARG;
+    }
+    if (Ns < 1 || Ns >= SSL_MAX_M) {
+        ssl_set_error("Ns = %d out of range", Ns);
+        return SSL_ERR_ARG;
+    }
+    return SSL_OK;
+}
+
+ssl_status check_x(const ssl_c64 *X, int T, int M, int64_t sF, int64_t sT)
+{
+    if (!X) {
+        ssl_set_error("X is NULL");
+        return SSL_ERR_ARG;
+    }
+    if (T < 1) {
+        ssl_set_error("T = %d must be >= 1", T);
+        return SSL_ERR_ARG;
+    }
+    if (sT < M || sF < 0) {
+        ssl_set_error("strides (strideF %lld, strideT %lld) invalid for M = %d", (long long)sF,
+                      (long long)sT, M);
+        return SSL_ERR_ARG;
+    }
+    return SSL_OK;
+}
+
+}  // namespace
+
+void ssl_set_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+extern "C" {
+
+const char *ssl_last_error(void) { return g_err; }
+
+int ssl_version(void) { return 100; }
+
+ssl_status ssl_ctx_create(ssl_ctx *out, int device, size_t hbm_budget_bytes)
+{
+    if (!out) {
+        ssl_set_error("out is NULL");
+        return SSL_ERR_ARG;
+    }
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= n) {
+        ssl_set_error("device %d not present (%d devices)", device, n);
+        return SSL_ERR_ARG;
+    }
+    ssl_ctx c = new (std::nothrow) ssl_ctx_s();
+    if (!c) {
+        ssl_set_error("out of host memory");
+        return SSL_ERR_NOMEM;
+    }
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    *out = c;
+    return SSL_OK;
+}
+
+void ssl_ctx_destroy(ssl_ctx ctx)
+{
+    if (!ctx) return;
+    DeviceGuard dg(ctx->device);
+    dev_free(ctx, ctx->ws, ctx->ws_bytes);
+    if (ctx->binsum_counter)
+        dev_free(ctx, ctx->binsum_counter, ctx->binsum_floats * sizeof(float) + 256);
+    delete ctx;
+}
+
+size_t ssl_ctx_workspace_bytes(ssl_ctx ctx) { return ctx ? ctx->held : 0; }
+
+ssl_status ssl_corr_accum(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int M, int64_t strideF,
+                          int64_t strideT, double scale, int accumulate, ssl_prec prec, void *R,
+                          void *stream)
+{
+    if (!ctx || !R) {
+        ssl_set_error("ctx or R is NULL");
+        return SSL_ERR_ARG;
+    }
+    ssl_status s = check_common(F, M, -1);
+    if (s != SSL_OK) return s;
+    if ((s = check_x(X, T, M, strideF, strideT)) != SSL_OK) return s;
+    if (!ok_prec(prec)) {
+        ssl_set_error("bad precision %d", (int)prec);
+        return SSL_ERR_ARG;
+    }
+    DeviceGuard dg(ctx->device);
+    hipError_t e = launch_corr(X, F, T, M, strideF, strideT, scale, accumulate, prec, R,
+                               static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SSL_OK : hip_fail(e, "corr launch");
+}
+
+ssl_status ssl_noise_create(ssl_ctx ctx, int F, int M, ssl_noise *out)
+{
+    if (!ctx || !out) {
+        ssl_set_error("ctx or out is NULL");
+        return SSL_ERR_ARG;
+    }
+    *out = nullptr;
+    ssl_status s = check_common(F, M, -1);
+    if (s != SSL_OK) return s;
+    DeviceGuard dg(ctx->device);
+    ssl_noise n = new (std::nothrow) ssl_noise_s();
+    if (!n) {
+        ssl_set_error("out of host memory");
+        return SSL_ERR_NOMEM;
+    }
+    n->ctx = ctx;
+    n->F = F;
+    n->M = M;
+    const size_t mat = (size_t)F * M * M * sizeof(ssl_c128);
+    void *k = nullptr, *w = nullptr, *st = nullptr;
+    if ((s = dev_alloc(ctx, &k, mat, "noise K")) != SSL_OK) goto fail;
+    if ((s = dev_alloc(ctx, &w, mat, "noise K^-1")) != SSL_OK) goto fail;
+    if ((s = dev_alloc(ctx, &st, align256((size_t)F * sizeof(int32_t)), "noise status")) != SSL_OK)
+        goto fail;
+    n->K = static_cast<ssl_c128 *>(k);
+    n->Kinv = static_cast<ssl_c128 *>(w);
+    n->status = static_cast<int32_t *>(st);
+    *out = n;
+    return SSL_OK;
+fail:
+    dev_free(ctx, k, k ? mat : 0);
+    dev_free(ctx, w, w ? mat : 0);
+    delete n;
+    return s;
+}
+
+void ssl_noise_destroy(ssl_noise n)
+{
+    if (!n) return;
+    DeviceGuard dg(n->ctx->device);
+    const size_t mat = (size_t)n->F * n->M * n->M * sizeof(ssl_c128);
+    dev_free(n->ctx, n->K, mat);
+    dev_free(n->ctx, n->Kinv, mat);
+    dev_free(n->ctx, n->status, align256((size_t)n->F * sizeof(int32_t)));
+    delete n;
+}
+
+static ssl_status noise_refactor(ssl_noise n, int32_t *bin_status, hipStream_t st)
+{
+    hipError_t e = launch_noise_factor(n->K, n->Kinv, n->status, n->F, n->M, st);
+    if (e != hipSuccess) return hip_fail(e, "noise factor launch");
+    if (bin_status) {
+        e = hipMemcpyAsync(bin_status, n->status, (size_t)n->F * sizeof(int32_t),
+                           hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, "status copy");
+    }
+    n->is_set = true;
+    return SSL_OK;
+}
+
+ssl_status ssl_noise_set(ssl_noise n, const void *Kin, ssl_prec kprec, int32_t *bin_status,
+                         void *stream)
+{
+    if (!n || !Kin) {
+        ssl_set_error("noise handle or K is NULL");
+        return SSL_ERR_ARG;
+    }
+    if (kprec != SSL_FP64 && kprec != SSL_FP32) {
+        ssl_set_error("K must be complex128 (SSL_FP64) or complex64 (SSL_FP32)");
+        return SSL_ERR_ARG;
+    }
+    DeviceGuard dg(n->ctx->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_noise_load(n->K, Kin, kprec, n->F, n->M, st);
+    if (e != hipSuccess) return hip_fail(e, "noise load");
+    return noise_refactor(n, bin_status, st);
+}
+
+ssl_status ssl_noise_update(ssl_noise n, const void *Khat, ssl_prec kprec, double alpha,
+                            int32_t *bin_status, void *stream)
+{
+    if (!n || !Khat) {
+        ssl_set_error("noise handle or Khat is NULL");
+        return SSL_ERR_ARG;
+    }
+    if (!n->is_set) {
+        ssl_set_error("noise handle was never set");
+        return SSL_ERR_STATE;
+    }
+    if (kprec != SSL_FP64 && kprec != SSL_FP32) {
+        ssl_set_error("Khat must be complex128 (SSL_FP64) or complex64 (SSL_FP32)");
+        return SSL_ERR_ARG;
+    }
+    if (!(alpha >= 0.0 && alpha <= 1.0)) {
+        ssl_set_error("alpha = %g must lie in [0, 1]", alpha);
+        return SSL_ERR_ARG;
+    }
+    DeviceGuard dg(n->ctx->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_noise_blend(n->K, Khat, kprec, alpha, n->F, n->M, st);
+    if (e != hipSuccess) return hip_fail(e, "noise blend launch");
+    return noise_refactor(n, bin_status, st);
+}
+
+ssl_status ssl_noise_get(ssl_noise n, ssl_c128 *K_out, void *stream)
+{
+    if (!n || !K_out) {
+        ssl_set_error("noise handle or K_out is NULL");
+        return SSL_ERR_ARG;
+    }
+    if (!n->is_set) {
+        ssl_set_error("noise handle was never set");
+        return SSL_ERR_STATE;
+    }
+    DeviceGuard dg(n->ctx->device);
+    hipError_t e = hipMemcpyAsync(K_out, n->K, (size_t)n->F * n->M * n->M * sizeof(ssl_c128),
+                                  hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SSL_OK : hip_fail(e, "noise get");
+}
+
+ssl_status ssl_gsvd(ssl_ctx ctx, const ssl_c64 *R, ssl_noise K, int F, int M, int Ns, ssl_c64 *En,
+                    float *sigma, int32_t *bin_status, int32_t *conv, int max_sweeps,
+                    void *stream)
+{
+    if (!ctx || !R || !K || !En) {
+        ssl_set_error("ctx, R, K or En is NULL");
+        return SSL_ERR_ARG;
+    }
+    ssl_status s = check_common(F, M, Ns);
+    if (s != SSL_OK) return s;
+    if (K->F != F || K->M != M) {
+        ssl_set_error("noise handle is %d x %d, call has F = %d, M = %d", K->F, K->M, F, M);
+        return SSL_ERR_ARG;
+    }
+    if (!K->is_set) {
+        ssl_set_error("noise handle was never set");
+        return SSL_ERR_STATE;
+    }
+    if (max_sweeps < 0 || max_sweeps > 1000) {
+        ssl_set_error("max_sweeps = %d out of range [0, 1000]", max_sweeps);
+        return SSL_ERR_ARG;
+    }
+    if (max_sweeps == 0) max_sweeps = SSL_DEFAULT_SWEEPS;
+    DeviceGuard dg(ctx->device);
+    if ((s = ws_reserve(ctx, align256((size_t)F * M * M * sizeof(ssl_c64)))) != SSL_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    ssl_c64 *A = static_cast<ssl_c64 *>(ctx->ws);
+    hipError_t e = launch_whiten(K->Kinv, R, A, F, M, st);
+    if (e != hipSuccess) return hip_fail(e, "whiten launch");
+    e = launch_jacobi(A, K->status, F, M, Ns, max_sweeps, En, sigma, bin_status, conv, st);
+    return e == hipSuccess ? SSL_OK : hip_fail(e, "jacobi launch");
+}
+
+ssl_status ssl_music_spectrum(ssl_ctx ctx, const void *H, ssl_prec hprec, const ssl_c64 *En, int F,
+                              int D, int M, int Ns, int p, float *P, float *Pbar,
+                              const int32_t *bin_status, void *stream)
+{
+    if (!ctx || !H || !En || !Pbar) {
+        ssl_set_error("ctx, H, En or Pbar is NULL");
+        return SSL_ERR_ARG;
+    }
+    ssl_status s = check_common(F, M, Ns);
+    if (s != SSL_OK) return s;
+    if (D < 1 || D > (1 << 24)) {
+        ssl_set_error("D = %d out of range", D);
+        return SSL_ERR_ARG;
+    }
+    if (p != 1 && p != 2) {
+        ssl_set_error("p = %d must be 1 or 2", p);
+        return SSL_ERR_ARG;
+    }
+    if (hprec != SSL_FP32 && hprec != SSL_BF16 && hprec != SSL_FP16) {
+        ssl_set_error("H precision must be SSL_FP32, SSL_BF16 or SSL_FP16");
+        return SSL_ERR_ARG;
+    }
+    DeviceGuard dg(ctx->device);
+    float *Pw = P;
+    if (!Pw) {
+        if ((s = ws_reserve(ctx, align256((size_t)F * D * sizeof(float)))) != SSL_OK) return s;
+        Pw = static_cast<float *>(ctx->ws);
+    }
+    if ((s = binsum_reserve(ctx, F, D)) != SSL_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_steer(H, hprec, En, F, D, M, Ns, p, bin_status, Pw, st);
+    if (e != hipSuccess) return hip_fail(e, "steer launch");
+    e = launch_binsum_peaks(Pw, F, D, Pbar, ctx->binsum_part, ctx->binsum_counter, D, 1, 1,
+                            nullptr, nullptr, st);
+    return e == hipSuccess ? SSL_OK : hip_fail(e, "bin-sum launch");
+}
+
+ssl_status ssl_peaks(ssl_ctx ctx, const float *Pbar, int n_az, int n_el, int Ns, int32_t *peaks,
+                     float *peak_val, void *stream)
+{
+    if (!ctx || !Pbar || !peaks || !peak_val) {
+        ssl_set_error("ctx, Pbar, peaks or peak_val is NULL");
+        return SSL_ERR_ARG;
+    }
+    ssl_status s = check_grid(n_az, n_el, Ns);
+    if (s != SSL_OK) return s;
+    DeviceGuard dg(ctx->device);
+    hipError_t e = launch_peaks(Pbar, n_az, n_el, Ns, peaks, peak_val,
+                                static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SSL_OK : hip_fail(e, "peaks launch");
+}
+
+ssl_status ssl_localize(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int M, int64_t strideF,
+                        int64_t strideT, ssl_noise K, const void *H, ssl_prec prec, int n_az,
+                        int n_el, int Ns, int p, int32_t *peaks, float *peak_val, float *Pbar,
+                        int32_t *bin_status, void *stream)
+{
+    if (!ctx || !K || !H || !peaks || !peak_val) {
+        ssl_set_error("ctx, K, H, peaks or peak_val is NULL");
+        return SSL_ERR_ARG;
+    }
+    ssl_status s = check_common(F, M, Ns);
+    if (s != SSL_OK) return s;
+    if ((s = check_x(X, T, M, strideF, strideT)) != SSL_OK) return s;
+    if ((s = check_grid(n_az, n_el, Ns)) != SSL_OK) return s;
+    if (p != 1 && p != 2) {
+        ssl_set_error("p = %d must be 1 or 2", p);
+        return SSL_ERR_ARG;
+    }
+    if (prec != SSL_FP32 && prec != SSL_BF16 && prec != SSL_FP16) {
+        ssl_set_error("prec must be SSL_FP32, SSL_BF16 or SSL_FP16");
+        return SSL_ERR_ARG;
+    }
+    if (K->F != F || K->M != M) {
+        ssl_set_error("noise handle is %d x %d, call has F = %d, M = %d", K->F, K->M, F, M);
+        return SSL_ERR_ARG;
+    }
+    if (!K->is_set) {
+        ssl_set_error("noise handle was never set");
+        return SSL_ERR_STATE;
+    }
+    const int D = n_az * n_el;
+    const int Nn = M - Ns;
+    // workspace: R | A | En | P | Pbar | status
+    const size_t bR = align256((size_t)F * M * M * sizeof(ssl_c64));
+    const size_t bE = align256((size_t)F * Nn * M * sizeof(ssl_c64));
+    const size_t bP = align256((size_t)F * D * sizeof(float));
+    const size_t bB = align256((size_t)D * sizeof(float));
+    const size_t bS = align256((size_t)F * sizeof(int32_t));
+    DeviceGuard dg(ctx->device);
+    if ((s = ws_reserve(ctx, 2 * bR + bE + bP + bB + bS)) != SSL_OK) return s;
+    if ((s = binsum_reserve(ctx, F, D)) != SSL_OK) return s;
+    char *w = static_cast<char *>(ctx->ws);
+    ssl_c64 *R = reinterpret_cast<ssl_c64 *>(w);
+    ssl_c64 *A = reinterpret_cast<ssl_c64 *>(w + bR);
+    ssl_c64 *En = reinterpret_cast<ssl_c64 *>(w + 2 * bR);
+    float *P = reinterpret_cast<float *>(w + 2 * bR + bE);
+    float *Pb = Pbar ? Pbar : reinterpret_cast<float *>(w + 2 * bR + bE + bP);
+    int32_t *stt = bin_status ? bin_status
+                              : reinterpret_cast<int32_t *>(w + 2 * bR + bE + bP + bB);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_corr(X, F, T, M, strideF, strideT, 1.0 / T, 0, prec, R, st);
+    if (e != hipSuccess) return hip_fail(e, "corr launch");
+    e = launch_whiten(K->Kinv, R, A, F, M, st);
+    if (e != hipSuccess) return hip_fail(e, "whiten launch");
+    e = launch_jacobi(A, K->status, F, M, Ns, SSL_DEFAULT_SWEEPS, En, nullptr, stt, nullptr, st);
+    if (e != hipSuccess) return hip_fail(e, "jacobi launch");
+    e = launch_steer(H, prec, En, F, D, M, Ns, p, stt, P, st);
+    if (e != hipSuccess) return hip_fail(e, "steer launch");
+    e = launch_binsum_peaks(P, F, D, Pb, ctx->binsum_part, ctx->binsum_counter, n_az, n_el, Ns,
+                            peaks, peak_val, st);
+    return e == hipSuccess ? SSL_OK : hip_fail(e, "bin-sum launch");
+}
+
+}  // extern "C"

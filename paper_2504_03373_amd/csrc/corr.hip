@@ -1,0 +1,354 @@
+// Correlation accumulation, eq.2-3 of arXiv 2504.03373 (AddCorrelation + NormalizeCorrelation):
+//   R[f] = scale * sum_t x_t x_t^H,   x_t = X[f, t, :] in C^M.
+//
+// MFMA path (FP32, and bf16/fp16 inputs with FP32 accumulation).  With x = a + i b,
+//   Re R_ij = sum_t a_i a_j + b_i b_j,     Im R_ij = sum_t b_i a_j - a_i b_j,
+// i.e. four real rank-T products of the [T][M] panels a and b.  One workgroup per bin stages the
+// bin's frames in LDS (chunks of 64 frames, real and imaginary planes split) and each wave owns
+// 16x16 tiles of the upper block triangle (I <= J) of the MP x MP padded result; the lower
+// triangle is written as the conjugate of the same registers, so R is Hermitian to the bit.
+//
+// FP64 path (for the noise correlation K): same staging, one thread per upper-triangle entry,
+// FP64 fused multiply-adds in frame order.
+#include "ssl_internal.h"
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+
+namespace {
+
+constexpr int kChunk = 64;      // frames staged per LDS pass
+constexpr int kThreads = 256;   // 4 waves
+
+// Tile (I, J), I <= J, of an NT x NT block grid, enumerated row by row.
+__device__ __forceinline__ void tile_coords(int t, int NT, int &I, int &J)
+{
+    I = 0;
+    while (t >= NT - I) { t -= NT - I; ++I; }
+    J = I + t;
+}
+
+// Write one 16x16 MFMA result tile.  Lane l, register r holds element (4*(l/16) + r, l%16).
+template <typename OutT>
+__device__ __forceinline__ void store_tile(OutT *Rf, int M, int I, int J, const floatx4 &re,
+                                           const floatx4 &im, float scale, int accumulate,
+                                           int lane)
+{
+    const int j = 16 * J + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = 16 * I + 4 * (lane >> 4) + r;
+        if (i >= M || j >= M) continue;
+        if (I == J && i > j) continue;      // mirrored from the (j, i) lane
+        float vr = re[r] * scale;
+        float vi = (i == j) ? 0.0f : im[r] * scale;
+        OutT *p = Rf + (size_t)i * M + j;
+        OutT *q = Rf + (size_t)j * M + i;
+        if (accumulate) {
+            OutT a = *p;
+            a.x += vr;
+            a.y += vi;
+            *p = a;
+            if (i != j) {
+                OutT b = *q;
+                b.x += vr;
+                b.y -= vi;
+                *q = b;
+            }
+        } else {
+            OutT a;
+            a.x = vr;
+            a.y = vi;
+            *p = a;
+            if (i != j) {
+                a.y = -vi;
+                *q = a;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// FP32 inputs, v_mfma_f32_16x16x4f32: per 4-frame step, A[i][k] = plane[t0+k][16I+i] from lane
+// i + 16k, B[k][j] = plane[t0+k][16J+j] from lane j + 16k.
+template <int MP>
+__global__ __launch_bounds__(kThreads) void corr_f32_mfma(const float2 *__restrict__ X, int T,
+                                                          int M, int64_t sF, int64_t sT,
+                                                          float scale, int accumulate,
+                                                          float2 *__restrict__ R)
+{
+    constexpr int S = MP + 16;                 // row stride: 4 frame rows of a step hit other banks
+    constexpr int NT = MP / 16;
+    constexpr int NTILE = NT * (NT + 1) / 2;
+    constexpr int TPW = (NTILE + 3) / 4;       // tiles per wave
+    __shared__ float Zr[kChunk * S];
+    __shared__ float Zi[kChunk * S];
+
+    const int f = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const float2 *Xf = X + (size_t)f * sF;
+
+    floatx4 acc_re[TPW], acc_im[TPW];
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+        acc_re[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+        acc_im[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+
+    for (int t0 = 0; t0 < T; t0 += kChunk) {
+        const int nf = min(kChunk, T - t0);
+        __syncthreads();
+        for (int e = tid; e < kChunk * MP; e += kThreads) {
+            const int tt = e / MP, m = e - tt * MP;
+            float2 v = make_float2(0.f, 0.f);
+            if (tt < nf && m < M) v = Xf[(size_t)(t0 + tt) * sT + m];
+            Zr[tt * S + m] = v.x;
+            Zi[tt * S + m] = v.y;
+        }
+        __syncthreads();
+        const int nsteps = (nf + 3) >> 2;
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            const int tile = wave + 4 * q;
+            if (tile < NTILE) {
+                int I, J;
+                tile_coords(tile, NT, I, J);
+                const int ca = 16 * I + (lane & 15), cb = 16 * J + (lane & 15);
+                for (int s = 0; s < nsteps; ++s) {
+                    const int row = (4 * s + (lane >> 4)) * S;
+                    const float ar = Zr[row + ca], ai = Zi[row + ca];
+                    const float br = Zr[row + cb], bi = Zi[row + cb];
+                    acc_re[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, acc_re[q], 0, 0, 0);
+                    acc_re[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, bi, acc_re[q], 0, 0, 0);
+                    acc_im[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, acc_im[q], 0, 0, 0);
+                    acc_im[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ar, bi, acc_im[q], 0, 0, 0);
+                }
+            }
+        }
+    }
+    float2 *Rf = R + (size_t)f * M * M;
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+        const int tile = wave + 4 * q;
+        if (tile < NTILE) {
+            int I, J;
+            tile_coords(tile, NT, I, J);
+            store_tile(Rf, M, I, J, acc_re[q], acc_im[q], scale, accumulate, lane);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// bf16 / fp16 inputs, v_mfma_f32_16x16x32_{bf16,f16}: lane l holds 8 consecutive k (frames)
+// k = 8*(l/16) .. +7 of row (A) / column (B) l%16.  Planes are stored transposed in LDS,
+// [m][t] with t contiguous, so each operand is one 16-byte read.
+template <typename E> struct Mfma32;
+template <> struct Mfma32<__bf16> {
+    typedef bf16x8 vec;
+    static __device__ __forceinline__ floatx4 run(vec a, vec b, floatx4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mfma32<_Float16> {
+    typedef halfx8 vec;
+    static __device__ __forceinline__ floatx4 run(vec a, vec b, floatx4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+template <int MP, typename E>
+__global__ __launch_bounds__(kThreads) void corr_lp_mfma(const float2 *__restrict__ X, int T,
+                                                         int M, int64_t sF, int64_t sT,
+                                                         float scale, int accumulate,
+                                                         float2 *__restrict__ R)
+{
+    typedef typename Mfma32<E>::vec vec;
+    constexpr int S = kChunk + 8;              // elements per transposed row (16 B pad)
+    constexpr int NT = MP / 16;
+    constexpr int NTILE = NT * (NT + 1) / 2;
+    constexpr int TPW = (NTILE + 3) / 4;
+    __shared__ __attribute__((aligned(16))) E Pr[MP * S];
+    __shared__ __attribute__((aligned(16))) E Pi[MP * S];
+    __shared__ __attribute__((aligned(16))) E Pn[MP * S];   // -Re, for the Im product
+
+    const int f = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const float2 *Xf = X + (size_t)f * sF;
+
+    floatx4 acc_re[TPW], acc_im[TPW];
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+        acc_re[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+        acc_im[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+    for (int t0 = 0; t0 < T; t0 += kChunk) {
+        const int nf = min(kChunk, T - t0);
+        __syncthreads();
+        for (int e = tid; e < kChunk * MP; e += kThreads) {
+            const int tt = e / MP, m = e - tt * MP;
+            float2 v = make_float2(0.f, 0.f);
+            if (tt < nf && m < M) v = Xf[(size_t)(t0 + tt) * sT + m];
+            const E r = (E)v.x, im = (E)v.y;
+            Pr[m * S + tt] = r;
+            Pi[m * S + tt] = im;
+            Pn[m * S + tt] = -r;
+        }
+        __syncthreads();
+        const int nsteps = (nf + 31) >> 5;
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            const int tile = wave + 4 * q;
+            if (tile < NTILE) {
+                int I, J;
+                tile_coords(tile, NT, I, J);
+                const int ca = (16 * I + (lane & 15)) * S, cb = (16 * J + (lane & 15)) * S;
+                for (int s = 0; s < nsteps; ++s) {
+                    const int k0 = 32 * s + 8 * (lane >> 4);
+                    const vec ar = *(const vec *)&Pr[ca + k0];
+                    const vec ai = *(const vec *)&Pi[ca + k0];
+                    const vec an = *(const vec *)&Pn[ca + k0];
+                    const vec br = *(const vec *)&Pr[cb + k0];
+                    const vec bi = *(const vec *)&Pi[cb + k0];
+                    acc_re[q] = Mfma32<E>::run(ar, br, acc_re[q]);
+                    acc_re[q] = Mfma32<E>::run(ai, bi, acc_re[q]);
+                    acc_im[q] = Mfma32<E>::run(ai, br, acc_im[q]);
+                    acc_im[q] = Mfma32<E>::run(an, bi, acc_im[q]);
+                }
+            }
+        }
+    }
+    float2 *Rf = R + (size_t)f * M * M;
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+        const int tile = wave + 4 * q;
+        if (tile < NTILE) {
+            int I, J;
+            tile_coords(tile, NT, I, J);
+            store_tile(Rf, M, I, J, acc_re[q], acc_im[q], scale, accumulate, lane);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// FP64 accumulation (noise correlation K): one thread per upper-triangle entry (i <= j).
+__global__ __launch_bounds__(kThreads) void corr_f64(const float2 *__restrict__ X, int T, int M,
+                                                     int64_t sF, int64_t sT, double scale,
+                                                     int accumulate, double2 *__restrict__ R)
+{
+    constexpr int MAXE = (SSL_MAX_M * (SSL_MAX_M + 1) / 2 + kThreads - 1) / kThreads;
+    __shared__ float2 Z[kChunk * SSL_MAX_M];
+    const int f = blockIdx.x;
+    const int tid = threadIdx.x;
+    const float2 *Xf = X + (size_t)f * sF;
+    const int nent = M * (M + 1) / 2;
+
+    int ei[MAXE], ej[MAXE];
+    double accr[MAXE], acci[MAXE];
+#pragma unroll
+    for (int q = 0; q < MAXE; ++q) {
+        int e = tid + q * kThreads;
+        int i = 0;
+        if (e < nent) {
+            while (e >= M - i) { e -= M - i; ++i; }
+            ei[q] = i;
+            ej[q] = i + e;
+        } else {
+            ei[q] = -1;
+            ej[q] = -1;
+        }
+        accr[q] = 0.0;
+        acci[q] = 0.0;
+    }
+    for (int t0 = 0; t0 < T; t0 += kChunk) {
+        const int nf = min(kChunk, T - t0);
+        __syncthreads();
+        for (int e = tid; e < nf * M; e += kThreads) {
+            const int tt = e / M, m = e - tt * M;
+            Z[tt * SSL_MAX_M + m] = Xf[(size_t)(t0 + tt) * sT + m];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < MAXE; ++q) {
+            if (ei[q] < 0) continue;
+            const int i = ei[q], j = ej[q];
+            double sr = accr[q], si = acci[q];
+            for (int tt = 0; tt < nf; ++tt) {
+                const float2 a = Z[tt * SSL_MAX_M + i], b = Z[tt * SSL_MAX_M + j];
+                // x_i conj(x_j)
+                sr = fma((double)a.x, (double)b.x, sr);
+                sr = fma((double)a.y, (double)b.y, sr);
+                si = fma((double)a.y, (double)b.x, si);
+                si = fma(-(double)a.x, (double)b.y, si);
+            }
+            accr[q] = sr;
+            acci[q] = si;
+        }
+    }
+    double2 *Rf = R + (size_t)f * M * M;
+#pragma unroll
+    for (int q = 0; q < MAXE; ++q) {
+        if (ei[q] < 0) continue;
+        const int i = ei[q], j = ej[q];
+        const double vr = accr[q] * scale;
+        const double vi = (i == j) ? 0.0 : acci[q] * scale;
+        double2 *p = Rf + (size_t)i * M + j;
+        double2 *pq = Rf + (size_t)j * M + i;
+        if (accumulate) {
+            double2 a = *p;
+            a.x += vr;
+            a.y += vi;
+            *p = a;
+            if (i != j) {
+                double2 b = *pq;
+                b.x += vr;
+                b.y -= vi;
+                *pq = b;
+            }
+        } else {
+            *p = make_double2(vr, vi);
+            if (i != j) *pq = make_double2(vr, -vi);
+        }
+    }
+}
+
+template <int MP>
+hipError_t launch_mp(const ssl_c64 *X, int F, int T, int M, int64_t sF, int64_t sT, double scale,
+                     int accumulate, ssl_prec prec, void *R, hipStream_t st)
+{
+    const float2 *Xp = reinterpret_cast<const float2 *>(X);
+    float2 *Rp = reinterpret_cast<float2 *>(R);
+    if (prec == SSL_FP32)
+        hipLaunchKernelGGL(corr_f32_mfma<MP>, dim3(F), dim3(kThreads), 0, st, Xp, T, M, sF, sT,
+                           (float)scale, accumulate, Rp);
+    else if (prec == SSL_BF16)
+        hipLaunchKernelGGL((corr_lp_mfma<MP, __bf16>), dim3(F), dim3(kThreads), 0, st, Xp, T, M,
+                           sF, sT, (float)scale, accumulate, Rp);
+    else
+        hipLaunchKernelGGL((corr_lp_mfma<MP, _Float16>), dim3(F), dim3(kThreads), 0, st, Xp, T,
+                           M, sF, sT, (float)scale, accumulate, Rp);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_corr(const ssl_c64 *X, int F, int T, int M, int64_t sF, int64_t sT, double scale,
+                       int accumulate, ssl_prec prec, void *R, hipStream_t st)
+{
+    if (prec == SSL_FP64) {
+        hipLaunchKernelGGL(corr_f64, dim3(F), dim3(kThreads), 0, st,
+                           reinterpret_cast<const float2 *>(X), T, M, sF, sT, scale, accumulate,
+                           reinterpret_cast<double2 *>(R));
+        return hipGetLastError();
+    }
+    if (M <= 16) return launch_mp<16>(X, F, T, M, sF, sT, scale, accumulate, prec, R, st);
+    if (M <= 32) return launch_mp<32>(X, F, T, M, sF, sT, scale, accumulate, prec, R, st);
+    if (M <= 48) return launch_mp<48>(X, F, T, M, sF, sT, scale, accumulate, prec, R, st);
+    return launch_mp<64>(X, F, T, M, sF, sT, scale, accumulate, prec, R, st);
+}
