@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""GSVD-MUSIC localization throughput on one MI355X.
+
+A step is one full pass of the localization path over one block of the 60-channel workload
+(M = 60 microphones in 4 rings, F = 257 bins, T = 50 frames, D = 72 x 19 = 1368 directions,
+Ns = 2): correlation (eq.2-3) -> A = K^{-1} R in FP64 and the Jacobi SVD noise subspace (eq.4)
+-> MUSIC spectrum (eq.5) -> bin sum (eq.6) + peak search, all in the library's HIP kernels via
+ssl_localize.  Inputs (a pool of distinct seeded blocks, the steering table and the resident noise
+factor) are in HBM before the timed region starts.
+
+Prints one JSON line: blocks/s, per-block latency percentiles, the dominant kernel's roofline
+(average launch duration from HIP events on its stream) and the FP64 CPU oracle timed on a
+bounded sample of the same workload on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed FP32) x 2.4 GHz
+PEAK_HBM_GBS = 8000.0
+
+
+def jacobi_flops(M: int, sweeps, rotations) -> float:
+    """Algorithmic flops of one-sided Jacobi per bin: each pair visit forms |b_i|^2, |b_j|^2 and
+    b_i^H b_j (16 M real flops); each applied rotation rewrites two columns of B and two of the
+    accumulated J (40 M flops).  Pair visits = sweeps * M(M-1)/2."""
+    import numpy as np
+    sweeps = np.asarray(sweeps, dtype=np.float64)
+    rotations = np.asarray(rotations, dtype=np.float64)
+    visits = sweeps * M * (M - 1) / 2.0
+    return float(np.sum(visits * 16.0 * M + rotations * 40.0 * M))
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--pool", type=int, default=16, help="distinct blocks resident in HBM")
+    ap.add_argument("--prec", choices=["fp32", "bf16", "fp16"], default="fp32")
+    ap.add_argument("--cpu-blocks", type=int, default=6, help="oracle sample size (blocks)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="run one device copy of this size (for HBM counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: the localization path shards by stream/block with no "
+              f"collective, so --gpus {args.gpus} is not measured here", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2504_03373_amd as S
+    import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    dev = "cuda:0"
+    S.lib()
+    prec = {"fp32": S.SSL_FP32, "bf16": S.SSL_BF16, "fp16": S.SSL_FP16}[args.prec]
+
+    w = synth.workload_paper(n_blocks=1000)
+    F, T, M, Ns, D = w.F, w.T, w.M, w.Ns, w.D
+    t0 = time.time()
+    Xs = torch.stack([torch.from_numpy(w.block(b)[0]) for b in range(args.pool)]).to(dev)
+    H = torch.from_numpy(w.steering_table()).to(dev)
+    if prec != S.SSL_FP32:
+        # interleaved (re, im) 16-bit pairs, [F][D][2M]
+        Hf = torch.view_as_real(H).reshape(F, D, 2 * M)
+        H = Hf.to(torch.bfloat16 if prec == S.SSL_BF16 else torch.float16).contiguous()
+    Xn = torch.from_numpy(w.noise_frames()).to(dev)
+    gen_s = time.time() - t0
+
+    ctx = S.ssl_ctx_create(0, 0)
+    Kd = torch.zeros((F, M, M), dtype=torch.complex128, device=dev)
+    S.ssl_corr_accum(ctx, Xn, 1.0 / Xn.shape[1], 0, S.SSL_FP64, Kd)
+    noise = S.ssl_noise_create(ctx, F, M)
+    kst = torch.zeros(F, dtype=torch.int32, device=dev)
+    S.ssl_noise_set(noise, Kd, S.SSL_FP64, kst)
+
+    # Sweep / rotation counts of the Jacobi launches for the flop model (same kernel, same inputs,
+    # deterministic), one per pool block.
+    conv_all = []
+    R = torch.zeros((F, M, M), dtype=torch.complex64, device=dev)
+    En = torch.zeros((F, M - Ns, M), dtype=torch.complex64, device=dev)
+    conv = torch.zeros((F, 2), dtype=torch.int32, device=dev)
+    for b in range(args.pool):
+        S.ssl_corr_accum(ctx, Xs[b], 1.0 / T, 0, prec, R)
+        S.ssl_gsvd(ctx, R, noise, Ns, En, None, None, conv, 0)
+        conv_all.append(conv.cpu().numpy().copy())
+    flops_block = [jacobi_flops(M, c[:, 0], c[:, 1]) for c in conv_all]
+
+    pk = torch.zeros(Ns, dtype=torch.int32, device=dev)
+    pv = torch.zeros(Ns, dtype=torch.float32, device=dev)
+    Pbar = torch.zeros(D, dtype=torch.float32, device=dev)
+    st = torch.zeros(F, dtype=torch.int32, device=dev)
+
+    def step(k):
+        S.ssl_localize(ctx, Xs[k % args.pool], noise, H, prec, w.grid.n_az, w.grid.n_el, Ns, 2,
+                       pk, pv, Pbar, st)
+
+    if args.calib_copy_mb > 0:
+        n = args.calib_copy_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+
+    S.ssl_ctx_timing_read(ctx, reset=True)
+    S.ssl_ctx_timing(ctx, True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record()
+        step(k)
+        ev[k][1].record()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    S.ssl_ctx_timing(ctx, False)
+    ktimes = S.ssl_ctx_timing_read(ctx, reset=True)
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    status_ok = bool((st.cpu().numpy() == 0).all())
+    peaks = pk.cpu().numpy().tolist()
+
+    value = args.steps / elapsed
+    # dominant kernel by device time
+    dom = max(ktimes, key=lambda k: ktimes[k][1])
+    n_j, ms_j = ktimes["jacobi"]
+    avg_j_ms = ms_j / max(n_j, 1)
+    flops_per_launch = float(np.mean([flops_block[k % args.pool] for k in range(args.steps)]))
+    achieved_tflops = flops_per_launch / (avg_j_ms * 1e-3) / 1e12
+    roofline = {
+        "kernel": "jacobi_svd",
+        "bound": "alu",
+        "achieved": round(achieved_tflops, 3),
+        "peak": PEAK_FP32_VECTOR_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(achieved_tflops / PEAK_FP32_VECTOR_TFLOPS, 4),
+        "traffic": None,
+        "avg_launch_ms": round(avg_j_ms, 4),
+        "flops_per_launch": flops_per_launch,
+    }
+    kernels = {k: {"launches": n, "avg_ms": round(ms / max(n, 1), 4)} for k, (n, ms) in ktimes.items() if n}
+
+    out = {
+        "metric": "GSVD-MUSIC blocks/s (60ch, 257 bins, 1368 dirs) + p50/p99 served latency",
+        "value": round(value, 2),
+        "unit": "blocks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1000.0 / value, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "fp32", "bf16": "bf16", "fp16": "fp16"}[args.prec],
+        "data": "synthetic",
+        "config": {"workload": w.name, "M": M, "F": F, "T": T, "D": D, "Ns": Ns, "p": 2,
+                   "path": "per-block ssl_localize", "mfma_inputs": args.prec,
+                   "whitening": "fp64", "svd": "fp32 one-sided Jacobi",
+                   "blocks_in_pool": args.pool},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                       "p99": round(float(np.percentile(lat, 99)), 4),
+                       "kind": "per-block device time, back-to-back on one stream"},
+        "dominant_kernel": dom,
+        "kernels": kernels,
+        "roofline": roofline,
+        "jacobi_sweeps": {"mean": round(float(np.mean([c[:, 0].mean() for c in conv_all])), 3),
+                          "max": int(max(c[:, 0].max() for c in conv_all))},
+        "status_ok": status_ok,
+        "last_peaks": peaks,
+        "input_gen_s": round(gen_s, 2),
+    }
+
+    if not args.no_cpu:
+        import oracle
+        cores = len(os.sched_getaffinity(0))
+        Kh = oracle.noise_corr(Xn.cpu().numpy())
+        Hh = w.steering_table()
+        nb = max(1, args.cpu_blocks)
+        blocks = [w.block(b)[0] for b in range(nb)]
+        tc = time.perf_counter()
+        for X in blocks:
+            oracle.localize(X, Kh, Hh, w.grid.n_az, w.grid.n_el, Ns, nthreads=cores)
+        cpu_s = time.perf_counter() - tc
+        out["cpu_baseline"] = {"value": round(nb / cpu_s, 4), "unit": "blocks/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"{nb} blocks of the same 60ch/257-bin/1368-dir workload, "
+                                         f"FP64 oracle end to end, threads over bins, {cpu_s:.1f} s"}
+
+    S.ssl_noise_destroy(noise)
+    S.ssl_ctx_destroy(ctx)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

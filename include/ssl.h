@@ -69,6 +69,23 @@ ssl_status ssl_ctx_create(ssl_ctx *out, int device, size_t hbm_budget_bytes);
 void ssl_ctx_destroy(ssl_ctx ctx);
 /* Bytes of device workspace the context currently holds. */
 size_t ssl_ctx_workspace_bytes(ssl_ctx ctx);
+/* Per-kernel device timing.  While enabled, every kernel the context enqueues is bracketed by a
+ * pair of HIP events recorded on the same stream.  ssl_ctx_timing_read() waits for the recorded
+ * events and returns, per kernel class (ssl_kernel_id), the number of launches and the summed
+ * device milliseconds since the last reset; reset != 0 clears the totals.  launches and total_ms
+ * are host arrays of SSL_K_COUNT entries. */
+typedef enum {
+    SSL_K_CORR = 0,     /* correlation accumulation (eq.2-3) */
+    SSL_K_NOISE = 1,    /* noise load / blend / FP64 Cholesky + inverse */
+    SSL_K_WHITEN = 2,   /* A = K^{-1} R (FP64) */
+    SSL_K_JACOBI = 3,   /* one-sided Jacobi SVD + sort + E_n */
+    SSL_K_STEER = 4,    /* H^H E_n projection and P (eq.5) */
+    SSL_K_BINSUM = 5,   /* bin sum (eq.6) + peak search */
+    SSL_K_COUNT = 6
+} ssl_kernel_id;
+ssl_status ssl_ctx_timing(ssl_ctx ctx, int enable);
+ssl_status ssl_ctx_timing_read(ssl_ctx ctx, int64_t *launches, double *total_ms, int reset);
+
 /* Thread-local description of the last error of this thread (never NULL; "" if none). */
 const char *ssl_last_error(void);
 /* Library version as major*10000 + minor*100 + patch. */

@@ -25,7 +25,9 @@ EXPORTED = [
     "ssl_ctx_create", "ssl_ctx_destroy", "ssl_ctx_workspace_bytes", "ssl_last_error", "ssl_version",
     "ssl_corr_accum", "ssl_noise_create", "ssl_noise_set", "ssl_noise_update", "ssl_noise_get",
     "ssl_noise_destroy", "ssl_gsvd", "ssl_music_spectrum", "ssl_peaks", "ssl_localize",
+    "ssl_ctx_timing", "ssl_ctx_timing_read",
 ]
+KERNELS = ["corr", "noise", "whiten", "jacobi", "steer", "binsum"]
 
 
 class SSLError(RuntimeError):
@@ -52,6 +54,8 @@ def lib() -> ctypes.CDLL:
         "ssl_ctx_workspace_bytes": (SZ, [P]),
         "ssl_last_error": (ctypes.c_char_p, []),
         "ssl_version": (I, []),
+        "ssl_ctx_timing": (I, [P, I]),
+        "ssl_ctx_timing_read": (I, [P, P, P, I]),
         "ssl_corr_accum": (I, [P, P, I, I, I, I64, I64, D, I, I, P, P]),
         "ssl_noise_create": (I, [P, I, I, ctypes.POINTER(P)]),
         "ssl_noise_set": (I, [P, P, I, P, P]),
@@ -98,6 +102,18 @@ def _check(fn: str, code: int):
 # ------------------------------------------------------------------------------------------------
 def ssl_version() -> int:
     return lib().ssl_version()
+
+
+def ssl_ctx_timing(ctx: int, enable: bool) -> None:
+    _check("ssl_ctx_timing", lib().ssl_ctx_timing(ctx, int(bool(enable))))
+
+
+def ssl_ctx_timing_read(ctx: int, reset: bool = True) -> dict:
+    """{kernel: (launches, total device ms)} since the last reset (waits for recorded events)."""
+    n = (ctypes.c_int64 * len(KERNELS))()
+    ms = (ctypes.c_double * len(KERNELS))()
+    _check("ssl_ctx_timing_read", lib().ssl_ctx_timing_read(ctx, n, ms, int(bool(reset))))
+    return {k: (int(n[i]), float(ms[i])) for i, k in enumerate(KERNELS)}
 
 
 def ssl_last_error() -> str:

@@ -110,6 +110,29 @@ ssl_status binsum_reserve(ssl_ctx ctx, int F, int D)
     return SSL_OK;
 }
 
+// Runs one kernel launch, bracketed by timing events on its stream when the context times.
+template <class Fn>
+hipError_t timed(ssl_ctx ctx, int id, hipStream_t st, Fn &&launch)
+{
+    if (!ctx->timing) return launch();
+    ssl_ctx_s::Timed t{id, nullptr, nullptr};
+    if (!ctx->event_pool.empty()) {
+        t = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+        t.id = id;
+    } else {
+        hipError_t e = hipEventCreate(&t.start);
+        if (e == hipSuccess) e = hipEventCreate(&t.stop);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipEventRecord(t.start, st);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(t.stop, st);
+    if (e == hipSuccess) ctx->pending.push_back(t);
+    else ctx->event_pool.push_back(t);
+    return e;
+}
+
 ssl_status check_common(int F, int M, int Ns)
 {
     if (F < 1 || F > 65535) {
@@ -203,6 +226,11 @@ void ssl_ctx_destroy(ssl_ctx ctx)
 {
     if (!ctx) return;
     DeviceGuard dg(ctx->device);
+    for (auto &t : ctx->pending) ctx->event_pool.push_back(t);
+    for (auto &t : ctx->event_pool) {
+        (void)hipEventDestroy(t.start);
+        (void)hipEventDestroy(t.stop);
+    }
     dev_free(ctx, ctx->ws, ctx->ws_bytes);
     if (ctx->binsum_counter)
         dev_free(ctx, ctx->binsum_counter, ctx->binsum_floats * sizeof(float) + 256);
@@ -210,6 +238,45 @@ void ssl_ctx_destroy(ssl_ctx ctx)
 }
 
 size_t ssl_ctx_workspace_bytes(ssl_ctx ctx) { return ctx ? ctx->held : 0; }
+
+ssl_status ssl_ctx_timing(ssl_ctx ctx, int enable)
+{
+    if (!ctx) {
+        ssl_set_error("ctx is NULL");
+        return SSL_ERR_ARG;
+    }
+    ctx->timing = enable != 0;
+    return SSL_OK;
+}
+
+ssl_status ssl_ctx_timing_read(ssl_ctx ctx, int64_t *launches, double *total_ms, int reset)
+{
+    if (!ctx) {
+        ssl_set_error("ctx is NULL");
+        return SSL_ERR_ARG;
+    }
+    DeviceGuard dg(ctx->device);
+    ssl_status s = SSL_OK;
+    for (auto &t : ctx->pending) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(t.stop);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.start, t.stop);
+        if (e != hipSuccess && s == SSL_OK) s = hip_fail(e, "timing event");
+        ctx->launches[t.id] += 1;
+        ctx->total_ms[t.id] += ms;
+        ctx->event_pool.push_back(t);
+    }
+    ctx->pending.clear();
+    for (int k = 0; k < SSL_K_COUNT; ++k) {
+        if (launches) launches[k] = ctx->launches[k];
+        if (total_ms) total_ms[k] = ctx->total_ms[k];
+        if (reset) {
+            ctx->launches[k] = 0;
+            ctx->total_ms[k] = 0.0;
+        }
+    }
+    return s;
+}
 
 ssl_status ssl_corr_accum(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int M, int64_t strideF,
                           int64_t strideT, double scale, int accumulate, ssl_prec prec, void *R,
@@ -227,8 +294,10 @@ ssl_status ssl_corr_accum(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int M, in
         return SSL_ERR_ARG;
     }
     DeviceGuard dg(ctx->device);
-    hipError_t e = launch_corr(X, F, T, M, strideF, strideT, scale, accumulate, prec, R,
-                               static_cast<hipStream_t>(stream));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = timed(ctx, SSL_K_CORR, st, [&] {
+        return launch_corr(X, F, T, M, strideF, strideT, scale, accumulate, prec, R, st);
+    });
     return e == hipSuccess ? SSL_OK : hip_fail(e, "corr launch");
 }
 
@@ -281,7 +350,9 @@ void ssl_noise_destroy(ssl_noise n)
 
 static ssl_status noise_refactor(ssl_noise n, int32_t *bin_status, hipStream_t st)
 {
-    hipError_t e = launch_noise_factor(n->K, n->Kinv, n->status, n->F, n->M, st);
+    hipError_t e = timed(n->ctx, SSL_K_NOISE, st, [&] {
+        return launch_noise_factor(n->K, n->Kinv, n->status, n->F, n->M, st);
+    });
     if (e != hipSuccess) return hip_fail(e, "noise factor launch");
     if (bin_status) {
         e = hipMemcpyAsync(bin_status, n->status, (size_t)n->F * sizeof(int32_t),
@@ -305,7 +376,8 @@ ssl_status ssl_noise_set(ssl_noise n, const void *Kin, ssl_prec kprec, int32_t *
     }
     DeviceGuard dg(n->ctx->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
-    hipError_t e = launch_noise_load(n->K, Kin, kprec, n->F, n->M, st);
+    hipError_t e = timed(n->ctx, SSL_K_NOISE, st,
+                         [&] { return launch_noise_load(n->K, Kin, kprec, n->F, n->M, st); });
     if (e != hipSuccess) return hip_fail(e, "noise load");
     return noise_refactor(n, bin_status, st);
 }
@@ -331,7 +403,9 @@ ssl_status ssl_noise_update(ssl_noise n, const void *Khat, ssl_prec kprec, doubl
     }
     DeviceGuard dg(n->ctx->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
-    hipError_t e = launch_noise_blend(n->K, Khat, kprec, alpha, n->F, n->M, st);
+    hipError_t e = timed(n->ctx, SSL_K_NOISE, st, [&] {
+        return launch_noise_blend(n->K, Khat, kprec, alpha, n->F, n->M, st);
+    });
     if (e != hipSuccess) return hip_fail(e, "noise blend launch");
     return noise_refactor(n, bin_status, st);
 }
@@ -379,9 +453,12 @@ ssl_status ssl_gsvd(ssl_ctx ctx, const ssl_c64 *R, ssl_noise K, int F, int M, in
     if ((s = ws_reserve(ctx, align256((size_t)F * M * M * sizeof(ssl_c64)))) != SSL_OK) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
     ssl_c64 *A = static_cast<ssl_c64 *>(ctx->ws);
-    hipError_t e = launch_whiten(K->Kinv, R, A, F, M, st);
+    hipError_t e = timed(ctx, SSL_K_WHITEN, st,
+                         [&] { return launch_whiten(K->Kinv, R, A, F, M, st); });
     if (e != hipSuccess) return hip_fail(e, "whiten launch");
-    e = launch_jacobi(A, K->status, F, M, Ns, max_sweeps, En, sigma, bin_status, conv, st);
+    e = timed(ctx, SSL_K_JACOBI, st, [&] {
+        return launch_jacobi(A, K->status, F, M, Ns, max_sweeps, En, sigma, bin_status, conv, st);
+    });
     return e == hipSuccess ? SSL_OK : hip_fail(e, "jacobi launch");
 }
 
@@ -415,10 +492,14 @@ ssl_status ssl_music_spectrum(ssl_ctx ctx, const void *H, ssl_prec hprec, const 
     }
     if ((s = binsum_reserve(ctx, F, D)) != SSL_OK) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    hipError_t e = launch_steer(H, hprec, En, F, D, M, Ns, p, bin_status, Pw, st);
+    hipError_t e = timed(ctx, SSL_K_STEER, st, [&] {
+        return launch_steer(H, hprec, En, F, D, M, Ns, p, bin_status, Pw, st);
+    });
     if (e != hipSuccess) return hip_fail(e, "steer launch");
-    e = launch_binsum_peaks(Pw, F, D, Pbar, ctx->binsum_part, ctx->binsum_counter, D, 1, 1,
-                            nullptr, nullptr, st);
+    e = timed(ctx, SSL_K_BINSUM, st, [&] {
+        return launch_binsum_peaks(Pw, F, D, Pbar, ctx->binsum_part, ctx->binsum_counter, D, 1, 1,
+                                   nullptr, nullptr, st);
+    });
     return e == hipSuccess ? SSL_OK : hip_fail(e, "bin-sum launch");
 }
 
@@ -432,8 +513,10 @@ ssl_status ssl_peaks(ssl_ctx ctx, const float *Pbar, int n_az, int n_el, int Ns,
     ssl_status s = check_grid(n_az, n_el, Ns);
     if (s != SSL_OK) return s;
     DeviceGuard dg(ctx->device);
-    hipError_t e = launch_peaks(Pbar, n_az, n_el, Ns, peaks, peak_val,
-                                static_cast<hipStream_t>(stream));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = timed(ctx, SSL_K_BINSUM, st, [&] {
+        return launch_peaks(Pbar, n_az, n_el, Ns, peaks, peak_val, st);
+    });
     return e == hipSuccess ? SSL_OK : hip_fail(e, "peaks launch");
 }
 
@@ -486,16 +569,24 @@ ssl_status ssl_localize(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int M, int6
     int32_t *stt = bin_status ? bin_status
                               : reinterpret_cast<int32_t *>(w + 2 * bR + bE + bP + bB);
     hipStream_t st = static_cast<hipStream_t>(stream);
-    hipError_t e = launch_corr(X, F, T, M, strideF, strideT, 1.0 / T, 0, prec, R, st);
+    hipError_t e = timed(ctx, SSL_K_CORR, st, [&] {
+        return launch_corr(X, F, T, M, strideF, strideT, 1.0 / T, 0, prec, R, st);
+    });
     if (e != hipSuccess) return hip_fail(e, "corr launch");
-    e = launch_whiten(K->Kinv, R, A, F, M, st);
+    e = timed(ctx, SSL_K_WHITEN, st, [&] { return launch_whiten(K->Kinv, R, A, F, M, st); });
     if (e != hipSuccess) return hip_fail(e, "whiten launch");
-    e = launch_jacobi(A, K->status, F, M, Ns, SSL_DEFAULT_SWEEPS, En, nullptr, stt, nullptr, st);
+    e = timed(ctx, SSL_K_JACOBI, st, [&] {
+        return launch_jacobi(A, K->status, F, M, Ns, SSL_DEFAULT_SWEEPS, En, nullptr, stt,
+                             nullptr, st);
+    });
     if (e != hipSuccess) return hip_fail(e, "jacobi launch");
-    e = launch_steer(H, prec, En, F, D, M, Ns, p, stt, P, st);
+    e = timed(ctx, SSL_K_STEER, st,
+              [&] { return launch_steer(H, prec, En, F, D, M, Ns, p, stt, P, st); });
     if (e != hipSuccess) return hip_fail(e, "steer launch");
-    e = launch_binsum_peaks(P, F, D, Pb, ctx->binsum_part, ctx->binsum_counter, n_az, n_el, Ns,
-                            peaks, peak_val, st);
+    e = timed(ctx, SSL_K_BINSUM, st, [&] {
+        return launch_binsum_peaks(P, F, D, Pb, ctx->binsum_part, ctx->binsum_counter, n_az,
+                                   n_el, Ns, peaks, peak_val, st);
+    });
     return e == hipSuccess ? SSL_OK : hip_fail(e, "bin-sum launch");
 }
 

@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "ssl.h"
 
 #define SSL_MAX_M 64
@@ -26,6 +28,16 @@ struct ssl_ctx_s {
     float *binsum_part;
     unsigned int *binsum_counter;
     size_t binsum_floats;
+    // per-kernel event timing (ssl_ctx_timing)
+    struct Timed {
+        int id;
+        hipEvent_t start, stop;
+    };
+    bool timing = false;
+    std::vector<Timed> pending;
+    std::vector<Timed> event_pool;
+    int64_t launches[SSL_K_COUNT] = {};
+    double total_ms[SSL_K_COUNT] = {};
 };
 
 struct ssl_noise_s {
