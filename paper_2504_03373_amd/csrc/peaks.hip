@@ -112,10 +112,17 @@ __global__ __launch_bounds__(kThreads) void binsum_peaks(
     const int ch = blockIdx.y;
     const int nch = gridDim.y;
     if (d < D) {
+        // all loads of the chunk in flight at once, then the sum in ascending bin order
+        // (absent bins of a short last chunk add an exact 0)
         const int f0 = ch * SSL_BINSUM_CHUNK;
-        const int f1 = min(F, f0 + SSL_BINSUM_CHUNK);
+        const int nf = min(F - f0, SSL_BINSUM_CHUNK);
+        float v[SSL_BINSUM_CHUNK];
+#pragma unroll
+        for (int i = 0; i < SSL_BINSUM_CHUNK; ++i)
+            v[i] = (i < nf) ? P[(size_t)(f0 + i) * D + d] : 0.0f;
         float s = 0.f;
-        for (int f = f0; f < f1; ++f) s += P[(size_t)f * D + d];
+#pragma unroll
+        for (int i = 0; i < SSL_BINSUM_CHUNK; ++i) s += v[i];
         part[(size_t)ch * D + d] = s;
     }
     __threadfence();
@@ -130,7 +137,17 @@ __global__ __launch_bounds__(kThreads) void binsum_peaks(
     const bool lds = D <= kLdsPbar;
     for (int e = tid; e < D; e += kThreads) {
         float s = 0.f;
-        for (int c = 0; c < nch; ++c)
+        int c = 0;
+        for (; c + 8 <= nch; c += 8) {
+            float v[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                v[i] = __hip_atomic_load(&part[(size_t)(c + i) * D + e], __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) s += v[i];
+        }
+        for (; c < nch; ++c)
             s += __hip_atomic_load(&part[(size_t)c * D + e], __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
         Pbar[e] = s;

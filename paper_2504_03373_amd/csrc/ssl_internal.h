@@ -62,7 +62,8 @@ hipError_t launch_noise_blend(ssl_c128 *K, const void *Khat, ssl_prec kprec, dou
                               int F, int M, hipStream_t st);
 hipError_t launch_whiten(const ssl_c128 *Kinv, const ssl_c64 *R, ssl_c64 *A, int F, int M,
                          hipStream_t st);
-hipError_t launch_jacobi(const ssl_c64 *A, const int32_t *kstatus, int F, int M, int Ns,
+// A is library workspace and is overwritten (it parks the QR reflectors between phases).
+hipError_t launch_jacobi(ssl_c64 *A, const int32_t *kstatus, int F, int M, int Ns,
                          int max_sweeps, ssl_c64 *En, float *sigma, int32_t *bin_status,
                          int32_t *conv, hipStream_t st);
 hipError_t launch_steer(const void *H, ssl_prec hprec, const ssl_c64 *En, int F, int D, int M,
