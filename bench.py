@@ -28,14 +28,19 @@ PEAK_HBM_GBS = 8000.0
 
 
 def jacobi_flops(M: int, sweeps, rotations) -> float:
-    """Algorithmic flops of one-sided Jacobi per bin: each pair visit forms |b_i|^2, |b_j|^2 and
-    b_i^H b_j (16 M real flops); each applied rotation rewrites two columns of B and two of the
-    accumulated J (40 M flops).  Pair visits = sweeps * M(M-1)/2."""
+    """Algorithmic real flops of the SVD kernel summed over bins.
+    QR preconditioner (Householder, trailing size n = M..1): each of the n - 1 remaining columns
+    costs w = v^H x (8n), x -= v (tau w) (8n) and its trailing norm (4n): 20 n (n - 1).
+    Jacobi: each pair visit forms |z_i|^2, |z_j|^2, z_i^H z_j (16 M); each applied rotation
+    rewrites two columns of Z and two of J (40 M); pair visits = sweeps * M(M-1)/2.
+    U = Q J: reflector n applied to the M columns of J, 16 n M."""
     import numpy as np
     sweeps = np.asarray(sweeps, dtype=np.float64)
     rotations = np.asarray(rotations, dtype=np.float64)
+    n = np.arange(1, M + 1, dtype=np.float64)
+    per_bin_fixed = float(np.sum(20.0 * n * (n - 1)) + np.sum(16.0 * n * M))
     visits = sweeps * M * (M - 1) / 2.0
-    return float(np.sum(visits * 16.0 * M + rotations * 40.0 * M))
+    return float(np.sum(visits * 16.0 * M + rotations * 40.0 * M) + per_bin_fixed * sweeps.size)
 
 
 def main() -> int:

@@ -48,6 +48,13 @@ __device__ __forceinline__ float group_sum(float v)
 }
 
 __device__ __forceinline__ bool finite2(float2 v) { return isfinite(v.x) && isfinite(v.y); }
+
+// 1/sqrt(x) for normal x > 0: hardware estimate plus one Newton-Raphson step.
+__device__ __forceinline__ float rsqrt_refined(float x)
+{
+    const float y = __builtin_amdgcn_rsqf(x);
+    return y * fmaf(-0.5f * x * y, y, 1.5f);
+}
 __device__ __forceinline__ float2 conj2(float2 v) { return make_float2(v.x, -v.y); }
 
 template <int MP, int G>
@@ -283,13 +290,15 @@ __global__ __launch_bounds__((JacobiCfg<MP, G>::THREADS)) void jacobi_svd(
                     }
                     const int ci = min(a, b), cj = max(a, b);
                     if (cj < M) {
-                        float2 bi[R], bj[R];
+                        float2 bi[R], bj[R], ui[R], uj[R];
                         float al = 0.f, be = 0.f, gr = 0.f, gi = 0.f;
 #pragma unroll
                         for (int k = 0; k < R; ++k) {
                             const int r = q + G * k;
                             bi[k] = Bs[ci * MP + r];
                             bj[k] = Bs[cj * MP + r];
+                            ui[k] = Js[ci * MP + r];     // issued early: overlaps the reductions
+                            uj[k] = Js[cj * MP + r];
                             al = fmaf(bi[k].x, bi[k].x, fmaf(bi[k].y, bi[k].y, al));
                             be = fmaf(bj[k].x, bj[k].x, fmaf(bj[k].y, bj[k].y, be));
                             // conj(z_i) * z_j
@@ -305,25 +314,25 @@ __global__ __launch_bounds__((JacobiCfg<MP, G>::THREADS)) void jacobi_svd(
                         if (g2 > tol2 * ab && ab > 0.0) {
                             rotated = 1;
                             // 2x2 Hermitian Gram [[al, gamma], [conj gamma, be]]: real Jacobi angle
-                            // after removing the phase of gamma
-                            const double gm = sqrt(g2);
-                            const double zeta = ((double)be - (double)al) / (2.0 * gm);
-                            const double az = fabs(zeta);
-                            double t = (az > 1e150) ? 0.5 / az : 1.0 / (az + sqrt(1.0 + az * az));
-                            if (zeta < 0.0) t = -t;
-                            const double cd = 1.0 / sqrt(1.0 + t * t);
-                            const double sd = cd * t;
-                            const float c = (float)cd;
+                            // after removing the phase of gamma, in FP32 (tan from the smaller root
+                            // of t^2 + 2 zeta t - 1 = 0, c = 1/sqrt(1 + t^2) refined by one Newton
+                            // step so that c^2 + s^2 = 1 to FP32 rounding)
+                            // |gamma| without squaring (|gamma|^2 may be subnormal for the
+                            // columns of a numerically rank-deficient bin); gamma != 0 here
+                            const float ax = fabsf(gr), ay = fabsf(gi);
+                            const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+                            const float rt = mn * __builtin_amdgcn_rcpf(mx);
+                            const float rg = __builtin_amdgcn_rcpf(mx * sqrtf(fmaf(rt, rt, 1.0f)));
+                            const float zeta = (be - al) * 0.5f * rg;
+                            const float az = fabsf(zeta);
+                            float t = (az > 1e18f) ? 0.5f / az
+                                                   : 1.0f / (az + sqrtf(fmaf(az, az, 1.0f)));
+                            t = copysignf(t, zeta);
+                            const float c = rsqrt_refined(fmaf(t, t, 1.0f));
+                            const float s = c * t;
                             // w = s e^{-i arg gamma}:  z_i' = c z_i - w z_j,  z_j' = conj(w) z_i + c z_j
-                            const float wr = (float)(sd * gr / gm);
-                            const float wi = (float)(-sd * gi / gm);
-                            float2 ui[R], uj[R];
-#pragma unroll
-                            for (int k = 0; k < R; ++k) {
-                                const int r = q + G * k;
-                                ui[k] = Js[ci * MP + r];
-                                uj[k] = Js[cj * MP + r];
-                            }
+                            const float wr = s * gr * rg;
+                            const float wi = -s * gi * rg;
 #pragma unroll
                             for (int k = 0; k < R; ++k) {
                                 const int r = q + G * k;
