@@ -284,9 +284,11 @@ __global__ __launch_bounds__((JacobiCfg<MP, G>::THREADS)) void jacobi_svd(
                     if (g == 0) {
                         a = Me - 1;
                         b = rd;
-                    } else {
-                        a = (rd + g) % (Me - 1);
-                        b = (rd - g + (Me - 1)) % (Me - 1);
+                    } else {                         // (rd +- g) mod (Me - 1), 0 < g < Me/2
+                        a = rd + g;
+                        if (a >= Me - 1) a -= Me - 1;
+                        b = rd - g;
+                        if (b < 0) b += Me - 1;
                     }
                     const int ci = min(a, b), cj = max(a, b);
                     if (cj < M) {

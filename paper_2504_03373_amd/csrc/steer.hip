@@ -10,7 +10,7 @@
 // so G is a [D x 2M] . [2M x 2Nn] real product and |G_dc|^2 is the sum of squares of the two
 // adjacent outputs.  The B operand (E_n, <= 64 KB) is staged once per workgroup in LDS as
 // [column][k]; the A operand streams from HBM (the steering table is the dominant traffic).
-// Workgroup = 4 waves x 16 directions; a wave owns 16 rows x all 2Nn columns in accumulators.
+// Workgroup = 8 waves x 16 directions; a wave owns 16 rows x all 2Nn columns in accumulators.
 #include "ssl_internal.h"
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -19,8 +19,8 @@ typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kRowsPerBlock = 64;
+constexpr int kThreads = 512;            // 8 waves x 16 directions
+constexpr int kRowsPerBlock = 128;
 constexpr int kMaxColTiles = 8;          // 2 * Nn <= 126 -> 8 tiles of 16 columns
 
 template <int CTRL>
@@ -132,24 +132,38 @@ __global__ __launch_bounds__(kThreads) void steer_f32(const float *__restrict__ 
     const int row = d0 + wave * 16 + (lane & 15);
     const int sl = lane >> 4;
     const float *hrow = H + ((size_t)f * D + (row < D ? row : 0)) * K2;
+    // the wave's whole 16-row strip of H in registers first: every load in flight at once
+    constexpr int KQ_MAX = 8;
+    float4 a[KQ_MAX];
+    float hn = 0.f;
+#pragma unroll
+    for (int kq = 0; kq < KQ_MAX; ++kq) {
+        const int k0 = 16 * kq + 4 * sl;
+        float2 lo = make_float2(0.f, 0.f), hi = make_float2(0.f, 0.f);
+        if (kq < KQ && row < D) {
+            if (k0 < K2) lo = *(const float2 *)(hrow + k0);          // complex element k0/2
+            if (k0 + 2 < K2) hi = *(const float2 *)(hrow + k0 + 2);
+        }
+        a[kq] = make_float4(lo.x, lo.y, hi.x, hi.y);
+    }
+#pragma unroll
+    for (int kq = 0; kq < KQ_MAX; ++kq)
+        hn = fmaf(a[kq].x, a[kq].x, fmaf(a[kq].y, a[kq].y, fmaf(a[kq].z, a[kq].z, fmaf(a[kq].w, a[kq].w, hn))));
     floatx4 acc[NCT];
 #pragma unroll
     for (int ct = 0; ct < NCT; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-    float hn = 0.f;
-    for (int kq = 0; kq < KQ; ++kq) {
-        const int k0 = 16 * kq + 4 * sl;
-        float a[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) a[e] = (row < D && k0 + e < K2) ? hrow[k0 + e] : 0.f;
+    for (int kq = 0; kq < KQ_MAX; ++kq) {
+        if (kq < KQ) {
+            const int k0 = 16 * kq + 4 * sl;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) hn = fmaf(a[e], a[e], hn);
-#pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) {
-            const float4 b = *(const float4 *)&Bs[(16 * ct + (lane & 15)) * KS + k0];
-            acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b.x, acc[ct], 0, 0, 0);
-            acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b.y, acc[ct], 0, 0, 0);
-            acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], b.z, acc[ct], 0, 0, 0);
-            acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], b.w, acc[ct], 0, 0, 0);
+            for (int ct = 0; ct < NCT; ++ct) {
+                const float4 b = *(const float4 *)&Bs[(16 * ct + (lane & 15)) * KS + k0];
+                acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kq].x, b.x, acc[ct], 0, 0, 0);
+                acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kq].y, b.y, acc[ct], 0, 0, 0);
+                acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kq].z, b.z, acc[ct], 0, 0, 0);
+                acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kq].w, b.w, acc[ct], 0, 0, 0);
+            }
         }
     }
     const bool ok = bin_status == nullptr || bin_status[f] == SSL_BIN_OK;
@@ -204,24 +218,37 @@ __global__ __launch_bounds__(kThreads) void steer_lp(const E *__restrict__ H,
     const int row = d0 + wave * 16 + (lane & 15);
     const int sl = lane >> 4;
     const E *hrow = H + ((size_t)f * D + (row < D ? row : 0)) * K2;
+    // the strip in registers first; each complex element is one 32-bit (re, im) pair
+    constexpr int KQ_MAX = 4;
+    vec a[KQ_MAX];
+    float hn = 0.f;
+#pragma unroll
+    for (int kq = 0; kq < KQ_MAX; ++kq) {
+        const int m0 = 16 * kq + 4 * sl;                 // complex element of k0 = 32 kq + 8 s
+        uint32_t w[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            w[i] = (kq < KQ && row < D && m0 + i < M)
+                       ? *(const uint32_t *)(hrow + 2 * (m0 + i)) : 0u;
+        a[kq] = __builtin_bit_cast(vec, w);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float fv = (float)a[kq][e];
+            hn = fmaf(fv, fv, hn);
+        }
+    }
     floatx4 acc[NCT];
 #pragma unroll
     for (int ct = 0; ct < NCT; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-    float hn = 0.f;
-    for (int kq = 0; kq < KQ; ++kq) {
-        const int k0 = 32 * kq + 8 * sl;
-        vec a;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const E v = (row < D && k0 + e < K2) ? hrow[k0 + e] : (E)0.0f;
-            a[e] = v;
-            const float fv = (float)v;
-            hn = fmaf(fv, fv, hn);
-        }
+    for (int kq = 0; kq < KQ_MAX; ++kq) {
+        if (kq < KQ) {
+            const int k0 = 32 * kq + 8 * sl;
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) {
-            const vec b = *(const vec *)&Bs[(16 * ct + (lane & 15)) * KS + k0];
-            acc[ct] = LpMfma<E>::run(a, b, acc[ct]);
+            for (int ct = 0; ct < NCT; ++ct) {
+                const vec b = *(const vec *)&Bs[(16 * ct + (lane & 15)) * KS + k0];
+                acc[ct] = LpMfma<E>::run(a[kq], b, acc[ct]);
+            }
         }
     }
     const bool ok = bin_status == nullptr || bin_status[f] == SSL_BIN_OK;
