@@ -1,16 +1,20 @@
 #!/usr/bin/env python3
 """GSVD-MUSIC localization throughput on one MI355X.
 
-A step is one full pass of the localization path over one block of the 60-channel workload
-(M = 60 microphones in 4 rings, F = 257 bins, T = 50 frames, D = 72 x 19 = 1368 directions,
-Ns = 2): correlation (eq.2-3) -> A = K^{-1} R in FP64 and the Jacobi SVD noise subspace (eq.4)
--> MUSIC spectrum (eq.5) -> bin sum (eq.6) + peak search, all in the library's HIP kernels via
-ssl_localize.  Inputs (a pool of distinct seeded blocks, the steering table and the resident noise
-factor) are in HBM before the timed region starts.
+Workload: blocks of the 60-channel scene (M = 60 microphones in 4 rings, F = 257 bins, T = 50
+frames, D = 72 x 19 = 1368 directions, Ns = 2).  A step is one pass of the whole localization
+path -- correlation (eq.2-3), A = K^{-1} R in FP64 and the Jacobi-SVD noise subspace (eq.4), MUSIC
+spectrum (eq.5), bin sum (eq.6) and peak search -- over one batch of `--batch` distinct blocks via
+ssl_localize_batch (all HIP kernels of the library).  Inputs (distinct seeded blocks, steering
+table, resident noise factor) are in HBM before any timed region starts.
 
-Prints one JSON line: blocks/s, per-block latency percentiles, the dominant kernel's roofline
-(average launch duration from HIP events on its stream) and the FP64 CPU oracle timed on a
-bounded sample of the same workload on this host's cores.
+Timed regions (each bracketed by torch.cuda.synchronize()):
+  * main: `--steps` batch steps with per-kernel HIP events on the launch stream -> `value` and
+    the dominant kernel's roofline (algorithmic flops per launch / average launch duration);
+  * graph: the same steps replayed from the captured HIP graph (no events) -> `graph_value`;
+  * per-block: ssl_localize one block at a time -> `per_block`.
+The FP64 CPU oracle is timed on a bounded sample of the same workload on this host's cores.
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -23,8 +27,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed FP32) x 2.4 GHz
-PEAK_HBM_GBS = 8000.0
+# MI355X FP32 vector peak: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed FP32) x 2.4 GHz
+PEAK_FP32_VECTOR_TFLOPS = 157.3
 
 
 def jacobi_flops(M: int, sweeps, rotations) -> float:
@@ -46,19 +50,20 @@ def jacobi_flops(M: int, sweeps, rotations) -> float:
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--pool", type=int, default=16, help="distinct blocks resident in HBM")
+    ap.add_argument("--steps", type=int, default=20, help="timed batch steps")
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=32, help="blocks per step")
     ap.add_argument("--prec", choices=["fp32", "bf16", "fp16"], default="fp32")
+    ap.add_argument("--per-block-steps", type=int, default=100)
     ap.add_argument("--cpu-blocks", type=int, default=6, help="oracle sample size (blocks)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
-                    help="run one device copy of this size (for HBM counter calibration)")
+                    help="run one device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: the localization path shards by stream/block with no "
-              f"collective, so --gpus {args.gpus} is not measured here", file=sys.stderr)
+        print(f"bench.py measures one GPU: the localization path shards by stream/block with no "
+              f"collective, so --gpus {args.gpus} is not run here", file=sys.stderr)
         return 2
 
     import numpy as np
@@ -76,43 +81,16 @@ def main() -> int:
 
     w = synth.workload_paper(n_blocks=1000)
     F, T, M, Ns, D = w.F, w.T, w.M, w.Ns, w.D
+    B = args.batch
     t0 = time.time()
-    Xs = torch.stack([torch.from_numpy(w.block(b)[0]) for b in range(args.pool)]).to(dev)
+    Xs = torch.stack([torch.from_numpy(w.block(b)[0]) for b in range(B)]).to(dev)
     H = torch.from_numpy(w.steering_table()).to(dev)
     if prec != S.SSL_FP32:
         # interleaved (re, im) 16-bit pairs, [F][D][2M]
-        Hf = torch.view_as_real(H).reshape(F, D, 2 * M)
-        H = Hf.to(torch.bfloat16 if prec == S.SSL_BF16 else torch.float16).contiguous()
+        H = torch.view_as_real(H).reshape(F, D, 2 * M).to(
+            torch.bfloat16 if prec == S.SSL_BF16 else torch.float16).contiguous()
     Xn = torch.from_numpy(w.noise_frames()).to(dev)
     gen_s = time.time() - t0
-
-    ctx = S.ssl_ctx_create(0, 0)
-    Kd = torch.zeros((F, M, M), dtype=torch.complex128, device=dev)
-    S.ssl_corr_accum(ctx, Xn, 1.0 / Xn.shape[1], 0, S.SSL_FP64, Kd)
-    noise = S.ssl_noise_create(ctx, F, M)
-    kst = torch.zeros(F, dtype=torch.int32, device=dev)
-    S.ssl_noise_set(noise, Kd, S.SSL_FP64, kst)
-
-    # Sweep / rotation counts of the Jacobi launches for the flop model (same kernel, same inputs,
-    # deterministic), one per pool block.
-    conv_all = []
-    R = torch.zeros((F, M, M), dtype=torch.complex64, device=dev)
-    En = torch.zeros((F, M - Ns, M), dtype=torch.complex64, device=dev)
-    conv = torch.zeros((F, 2), dtype=torch.int32, device=dev)
-    for b in range(args.pool):
-        S.ssl_corr_accum(ctx, Xs[b], 1.0 / T, 0, prec, R)
-        S.ssl_gsvd(ctx, R, noise, Ns, En, None, None, conv, 0)
-        conv_all.append(conv.cpu().numpy().copy())
-    flops_block = [jacobi_flops(M, c[:, 0], c[:, 1]) for c in conv_all]
-
-    pk = torch.zeros(Ns, dtype=torch.int32, device=dev)
-    pv = torch.zeros(Ns, dtype=torch.float32, device=dev)
-    Pbar = torch.zeros(D, dtype=torch.float32, device=dev)
-    st = torch.zeros(F, dtype=torch.int32, device=dev)
-
-    def step(k):
-        S.ssl_localize(ctx, Xs[k % args.pool], noise, H, prec, w.grid.n_az, w.grid.n_el, Ns, 2,
-                       pk, pv, Pbar, st)
 
     if args.calib_copy_mb > 0:
         n = args.calib_copy_mb * (1 << 20) // 4
@@ -122,10 +100,40 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
 
-    for k in range(args.warmup):
-        step(k)
+    ctx = S.ssl_ctx_create(0, 0)
+    Kd = torch.zeros((F, M, M), dtype=torch.complex128, device=dev)
+    S.ssl_corr_accum(ctx, Xn, 1.0 / Xn.shape[1], 0, S.SSL_FP64, Kd)
+    noise = S.ssl_noise_create(ctx, F, M)
+    kst = torch.zeros(F, dtype=torch.int32, device=dev)
+    S.ssl_noise_set(noise, Kd, S.SSL_FP64, kst)
+
+    # Jacobi sweep / rotation counts for the flop model: same kernel variant, same inputs,
+    # deterministic, so they are those of the timed launches.
+    R = torch.zeros((F, M, M), dtype=torch.complex64, device=dev)
+    En = torch.zeros((F, M - Ns, M), dtype=torch.complex64, device=dev)
+    conv = torch.zeros((F, 2), dtype=torch.int32, device=dev)
+    conv_all = []
+    for b in range(B):
+        S.ssl_corr_accum(ctx, Xs[b], 1.0 / T, 0, prec, R)
+        S.ssl_gsvd(ctx, R, noise, Ns, En, None, None, conv, 0)
+        conv_all.append(conv.cpu().numpy().copy())
+    flops_batch = float(sum(jacobi_flops(M, c[:, 0], c[:, 1]) for c in conv_all))
+
+    pk = torch.zeros((B, Ns), dtype=torch.int32, device=dev)
+    pv = torch.zeros((B, Ns), dtype=torch.float32, device=dev)
+    Pbar = torch.zeros((B, D), dtype=torch.float32, device=dev)
+    st = torch.zeros((B, F), dtype=torch.int32, device=dev)
+    descs = [S.block_desc(Xs[b], noise, H, w.grid.n_az, w.grid.n_el, Ns, pk[b], pv[b], Pbar[b],
+                          st[b]) for b in range(B)]
+
+    def step():
+        S.ssl_localize_batch(ctx, descs, prec, 2)
+
+    for _ in range(args.warmup):
+        step()
     torch.cuda.synchronize()
 
+    # ---- main timed region: per-kernel events on the launch stream --------------------------
     S.ssl_ctx_timing_read(ctx, reset=True)
     S.ssl_ctx_timing(ctx, True)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -134,7 +142,7 @@ def main() -> int:
     t_start = time.perf_counter()
     for k in range(args.steps):
         ev[k][0].record()
-        step(k)
+        step()
         ev[k][1].record()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
@@ -142,27 +150,51 @@ def main() -> int:
     ktimes = S.ssl_ctx_timing_read(ctx, reset=True)
     lat = np.array([a.elapsed_time(b) for a, b in ev])
     status_ok = bool((st.cpu().numpy() == 0).all())
-    peaks = pk.cpu().numpy().tolist()
+    value = args.steps * B / elapsed
 
-    value = args.steps / elapsed
-    # dominant kernel by device time
+    # ---- graph replay region ------------------------------------------------------------------
+    step()                                   # capture (not timed)
+    torch.cuda.synchronize()
+    tg = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    graph_value = args.steps * B / (time.perf_counter() - tg)
+
+    # ---- per-block region ---------------------------------------------------------------------
+    pk1 = torch.zeros(Ns, dtype=torch.int32, device=dev)
+    pv1 = torch.zeros(Ns, dtype=torch.float32, device=dev)
+    pb1 = torch.zeros(D, dtype=torch.float32, device=dev)
+    st1 = torch.zeros(F, dtype=torch.int32, device=dev)
+    for k in range(5):
+        S.ssl_localize(ctx, Xs[k % B], noise, H, prec, w.grid.n_az, w.grid.n_el, Ns, 2, pk1, pv1,
+                       pb1, st1)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    for k in range(args.per_block_steps):
+        S.ssl_localize(ctx, Xs[k % B], noise, H, prec, w.grid.n_az, w.grid.n_el, Ns, 2, pk1, pv1,
+                       pb1, st1)
+    torch.cuda.synchronize()
+    per_block = args.per_block_steps / (time.perf_counter() - tb)
+
     dom = max(ktimes, key=lambda k: ktimes[k][1])
     n_j, ms_j = ktimes["jacobi"]
     avg_j_ms = ms_j / max(n_j, 1)
-    flops_per_launch = float(np.mean([flops_block[k % args.pool] for k in range(args.steps)]))
-    achieved_tflops = flops_per_launch / (avg_j_ms * 1e-3) / 1e12
+    achieved = flops_batch / (avg_j_ms * 1e-3) / 1e12
     roofline = {
-        "kernel": "jacobi_svd",
+        "kernel": "jacobi_persistent",
         "bound": "alu",
-        "achieved": round(achieved_tflops, 3),
+        "achieved": round(achieved, 3),
         "peak": PEAK_FP32_VECTOR_TFLOPS,
         "unit": "TFLOP/s",
-        "frac": round(achieved_tflops / PEAK_FP32_VECTOR_TFLOPS, 4),
+        "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
         "traffic": None,
         "avg_launch_ms": round(avg_j_ms, 4),
-        "flops_per_launch": flops_per_launch,
+        "flops_per_launch": flops_batch,
+        "bins_per_launch": B * F,
     }
-    kernels = {k: {"launches": n, "avg_ms": round(ms / max(n, 1), 4)} for k, (n, ms) in ktimes.items() if n}
+    kernels = {k: {"launches": n, "avg_ms": round(ms / max(n, 1), 4)}
+               for k, (n, ms) in ktimes.items() if n}
 
     out = {
         "metric": "GSVD-MUSIC blocks/s (60ch, 257 bins, 1368 dirs) + p50/p99 served latency",
@@ -171,26 +203,28 @@ def main() -> int:
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1000.0 / value, 4),
+        "ms_per_step": round(1000.0 * elapsed / args.steps, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "fp32", "bf16": "bf16", "fp16": "fp16"}[args.prec],
+        "dtype": args.prec,
         "data": "synthetic",
         "config": {"workload": w.name, "M": M, "F": F, "T": T, "D": D, "Ns": Ns, "p": 2,
-                   "path": "per-block ssl_localize", "mfma_inputs": args.prec,
-                   "whitening": "fp64", "svd": "fp32 one-sided Jacobi",
-                   "blocks_in_pool": args.pool},
+                   "blocks_per_step": B, "path": "ssl_localize_batch",
+                   "mfma_inputs": args.prec, "whitening": "fp64",
+                   "svd": "fp32 one-sided Jacobi (QR-preconditioned)"},
+        "graph_value": round(graph_value, 2),
+        "per_block": {"value": round(per_block, 2), "unit": "blocks/s",
+                      "path": "ssl_localize, one block per call"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                        "p99": round(float(np.percentile(lat, 99)), 4),
-                       "kind": "per-block device time, back-to-back on one stream"},
+                       "kind": f"device time of one {B}-block step"},
         "dominant_kernel": dom,
         "kernels": kernels,
         "roofline": roofline,
         "jacobi_sweeps": {"mean": round(float(np.mean([c[:, 0].mean() for c in conv_all])), 3),
                           "max": int(max(c[:, 0].max() for c in conv_all))},
         "status_ok": status_ok,
-        "last_peaks": peaks,
         "input_gen_s": round(gen_s, 2),
     }
 

@@ -171,6 +171,36 @@ ssl_status ssl_localize(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int M, int6
                         int n_el, int Ns, int p, int32_t *peaks, float *peak_val, float *Pbar,
                         int32_t *bin_status, void *stream);
 
+/* ------------------------------------------------------------ batched path */
+
+/* One block of a batch.  Fields as in ssl_localize; blocks may differ in F, T, M, Ns and grid. */
+typedef struct {
+    const ssl_c64 *X;          /* [F][T][M], M contiguous, strides in elements */
+    int64_t strideF, strideT;
+    int F, T, M, Ns;
+    ssl_noise K;               /* noise handle set for this F and M */
+    const void *H;             /* [F][D][M] steering table in the batch's prec, D = n_az*n_el */
+    int n_az, n_el;
+    int32_t *peaks;            /* [Ns] out */
+    float *peak_val;           /* [Ns] out */
+    float *Pbar;               /* [D] out or NULL */
+    int32_t *bin_status;       /* [F] out or NULL */
+} ssl_block_desc;
+
+/* Whole path (as ssl_localize) for nblocks blocks of possibly different shapes, in one set of
+ * launches: every kernel runs once per size class over all (block, bin) items of the batch, the
+ * Jacobi SVD as a persistent work-queue kernel (bins that converge early free their CU).  descs is
+ * a HOST array, read during the call only.  The launch sequence of a batch shape is captured once
+ * into a HIP graph and replayed for later batches of the same shape (descriptors are copied to the
+ * device each call, so pointers may change freely).  Results are bit-identical to ssl_localize
+ * on each block alone.  All blocks share prec and p.  Limits: 1 <= nblocks <= 65535. */
+ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblocks,
+                              ssl_prec prec, int p, void *stream);
+
+/* Graph replay for ssl_localize_batch (default on).  With timing enabled (ssl_ctx_timing) batches
+ * always run as individually timed launches. */
+ssl_status ssl_ctx_use_graphs(ssl_ctx ctx, int enable);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,8 +25,17 @@ EXPORTED = [
     "ssl_ctx_create", "ssl_ctx_destroy", "ssl_ctx_workspace_bytes", "ssl_last_error", "ssl_version",
     "ssl_corr_accum", "ssl_noise_create", "ssl_noise_set", "ssl_noise_update", "ssl_noise_get",
     "ssl_noise_destroy", "ssl_gsvd", "ssl_music_spectrum", "ssl_peaks", "ssl_localize",
-    "ssl_ctx_timing", "ssl_ctx_timing_read",
+    "ssl_ctx_timing", "ssl_ctx_timing_read", "ssl_localize_batch", "ssl_ctx_use_graphs",
 ]
+
+
+class BlockDesc(ctypes.Structure):
+    """ssl_block_desc."""
+    _fields_ = [("X", ctypes.c_void_p), ("strideF", ctypes.c_int64), ("strideT", ctypes.c_int64),
+                ("F", ctypes.c_int), ("T", ctypes.c_int), ("M", ctypes.c_int), ("Ns", ctypes.c_int),
+                ("K", ctypes.c_void_p), ("H", ctypes.c_void_p), ("n_az", ctypes.c_int),
+                ("n_el", ctypes.c_int), ("peaks", ctypes.c_void_p), ("peak_val", ctypes.c_void_p),
+                ("Pbar", ctypes.c_void_p), ("bin_status", ctypes.c_void_p)]
 KERNELS = ["corr", "noise", "whiten", "jacobi", "steer", "binsum"]
 
 
@@ -66,6 +75,8 @@ def lib() -> ctypes.CDLL:
         "ssl_music_spectrum": (I, [P, P, I, P, I, I, I, I, I, P, P, P, P]),
         "ssl_peaks": (I, [P, P, I, I, I, P, P, P]),
         "ssl_localize": (I, [P, P, I, I, I, I64, I64, P, P, I, I, I, I, I, P, P, P, P, P]),
+        "ssl_localize_batch": (I, [P, ctypes.POINTER(BlockDesc), I, I, I, P]),
+        "ssl_ctx_use_graphs": (I, [P, I]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -199,3 +210,24 @@ def ssl_localize(ctx, X, noise, H, prec, n_az, n_el, Ns, p, peaks, peak_val, Pba
     _check("ssl_localize", lib().ssl_localize(ctx, _ptr(X), F, T, M, sF, sT, noise, _ptr(H), prec,
                                               n_az, n_el, Ns, p, _ptr(peaks), _ptr(peak_val),
                                               _ptr(Pbar), _ptr(bin_status), _stream(stream)))
+
+
+def block_desc(X, noise, H, n_az, n_el, Ns, peaks, peak_val, Pbar=None, bin_status=None):
+    """One ssl_block_desc for ssl_localize_batch (X: complex64 device tensor [F][T][M])."""
+    F, T, M = X.shape
+    sF, sT, sM = X.stride()
+    if sM != 1:
+        raise ValueError("X must be contiguous along M")
+    return BlockDesc(_ptr(X), sF, sT, F, T, M, Ns, noise, _ptr(H), n_az, n_el, _ptr(peaks),
+                     _ptr(peak_val), _ptr(Pbar), _ptr(bin_status))
+
+
+def ssl_localize_batch(ctx, descs, prec, p, stream=None):
+    """Whole path for a list of BlockDesc (see block_desc) in one set of launches."""
+    arr = (BlockDesc * len(descs))(*descs)
+    _check("ssl_localize_batch", lib().ssl_localize_batch(ctx, arr, len(descs), prec, p,
+                                                          _stream(stream)))
+
+
+def ssl_ctx_use_graphs(ctx, enable: bool) -> None:
+    _check("ssl_ctx_use_graphs", lib().ssl_ctx_use_graphs(ctx, int(bool(enable))))

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 
 #include "ssl_internal.h"
@@ -66,6 +67,13 @@ void dev_free(ssl_ctx ctx, void *p, size_t bytes)
     }
 }
 
+// Captured graphs bake in workspace addresses: drop them whenever a buffer moves.
+void clear_graphs(ssl_ctx ctx)
+{
+    for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
+    ctx->graphs.clear();
+}
+
 // Grows the context workspace to at least `bytes` (never shrinks).  hipFree of the old block
 // synchronises the device, so in-flight work that used it has finished.
 ssl_status ws_reserve(ssl_ctx ctx, size_t bytes)
@@ -75,6 +83,7 @@ ssl_status ws_reserve(ssl_ctx ctx, size_t bytes)
         ssl_set_error("workspace of %zu bytes exceeds the HBM budget (%zu)", bytes, ctx->budget);
         return SSL_ERR_BUDGET;
     }
+    clear_graphs(ctx);
     dev_free(ctx, ctx->ws, ctx->ws_bytes);
     ctx->ws = nullptr;
     ctx->ws_bytes = 0;
@@ -218,6 +227,10 @@ ssl_status ssl_ctx_create(ssl_ctx *out, int device, size_t hbm_budget_bytes)
     }
     c->device = device;
     c->budget = hbm_budget_bytes;
+    if (hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, device) !=
+            hipSuccess ||
+        c->cu_count <= 0)
+        c->cu_count = 256;
     *out = c;
     return SSL_OK;
 }
@@ -231,6 +244,15 @@ void ssl_ctx_destroy(ssl_ctx ctx)
         (void)hipEventDestroy(t.start);
         (void)hipEventDestroy(t.stop);
     }
+    clear_graphs(ctx);
+    if (ctx->bdesc_ev) {
+        (void)hipEventSynchronize(ctx->bdesc_ev);
+        (void)hipEventDestroy(ctx->bdesc_ev);
+    }
+    if (ctx->bdesc_host) (void)hipHostFree(ctx->bdesc_host);
+    dev_free(ctx, ctx->bdesc_dev, ctx->bdesc_bytes);
+    dev_free(ctx, ctx->counters, ctx->n_counters * sizeof(unsigned int));
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     dev_free(ctx, ctx->ws, ctx->ws_bytes);
     if (ctx->binsum_counter)
         dev_free(ctx, ctx->binsum_counter, ctx->binsum_floats * sizeof(float) + 256);
@@ -588,6 +610,331 @@ ssl_status ssl_localize(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int M, int6
                                    n_el, Ns, peaks, peak_val, st);
     });
     return e == hipSuccess ? SSL_OK : hip_fail(e, "bin-sum launch");
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------------
+// batched path
+// ------------------------------------------------------------------------------------------------
+namespace {
+
+constexpr int kJacobiQueues = 4;     // counters[0..3]: work queues of Jacobi classes 8/16/32/64
+
+int jacobi_queue(int cls) { return cls == 8 ? 0 : cls == 16 ? 1 : cls == 32 ? 2 : 3; }
+int jacobi_wg_per_cu(int cls) { return cls == 64 ? 2 : cls == 32 ? 4 : 8; }
+
+struct Seg {
+    int cls, start, count, extra;
+};
+
+// Launch plan of one batch shape: per kernel, contiguous runs of items sharing a size class.
+struct Plan {
+    std::vector<Seg> corr, whiten, jac, steer;
+    int nblocks = 0, n_items = 0, max_dc = 0, max_fc = 0;
+};
+
+ssl_status counters_reserve(ssl_ctx ctx, size_t n)
+{
+    if (ctx->n_counters >= n) return SSL_OK;
+    size_t want = n < 256 ? 256 : n;
+    if (want < 2 * ctx->n_counters) want = 2 * ctx->n_counters;
+    clear_graphs(ctx);
+    dev_free(ctx, ctx->counters, ctx->n_counters * sizeof(unsigned int));
+    ctx->counters = nullptr;
+    ctx->n_counters = 0;
+    void *p = nullptr;
+    ssl_status s = dev_alloc(ctx, &p, want * sizeof(unsigned int), "batch counters");
+    if (s != SSL_OK) return s;
+    hipError_t e = hipMemset(p, 0, want * sizeof(unsigned int));
+    if (e != hipSuccess) {
+        dev_free(ctx, p, want * sizeof(unsigned int));
+        return hip_fail(e, "hipMemset");
+    }
+    ctx->counters = static_cast<unsigned int *>(p);
+    ctx->n_counters = want;
+    return SSL_OK;
+}
+
+ssl_status bdesc_reserve(ssl_ctx ctx, size_t bytes)
+{
+    if (ctx->bdesc_bytes >= bytes) return SSL_OK;
+    size_t want = bytes < (1u << 16) ? (1u << 16) : bytes;
+    if (want < 2 * ctx->bdesc_bytes) want = 2 * ctx->bdesc_bytes;
+    hipError_t e;
+    if (!ctx->bdesc_ev) {
+        e = hipEventCreateWithFlags(&ctx->bdesc_ev, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
+    (void)hipEventSynchronize(ctx->bdesc_ev);     // the old staging buffer is no longer read
+    clear_graphs(ctx);
+    if (ctx->bdesc_host) (void)hipHostFree(ctx->bdesc_host);
+    dev_free(ctx, ctx->bdesc_dev, ctx->bdesc_bytes);
+    ctx->bdesc_host = nullptr;
+    ctx->bdesc_dev = nullptr;
+    ctx->bdesc_bytes = 0;
+    ssl_status s = dev_alloc(ctx, &ctx->bdesc_dev, want, "batch descriptors");
+    if (s != SSL_OK) return s;
+    e = hipHostMalloc(&ctx->bdesc_host, want, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        dev_free(ctx, ctx->bdesc_dev, want);
+        ctx->bdesc_dev = nullptr;
+        return hip_fail(e, "hipHostMalloc");
+    }
+    ctx->bdesc_bytes = want;
+    return SSL_OK;
+}
+
+// Item lists of one kernel: blocks grouped by class (ascending), bins in order inside a block.
+void build_list(const std::vector<int> &cls_of_block, const std::vector<int> &F_of_block,
+                int2 *out, std::vector<Seg> &segs)
+{
+    std::vector<int> classes(cls_of_block);
+    std::sort(classes.begin(), classes.end());
+    classes.erase(std::unique(classes.begin(), classes.end()), classes.end());
+    int pos = 0;
+    for (int c : classes) {
+        Seg s{c, pos, 0, 0};
+        for (size_t b = 0; b < cls_of_block.size(); ++b) {
+            if (cls_of_block[b] != c) continue;
+            for (int f = 0; f < F_of_block[b]; ++f) out[pos++] = make_int2((int)b, f);
+        }
+        s.count = pos - s.start;
+        segs.push_back(s);
+    }
+}
+
+hipError_t enqueue_batch(ssl_ctx ctx, const Plan &P, const BlockDev *blk, const int2 *lists,
+                         ssl_prec prec, hipStream_t st)
+{
+    const int2 *l_corr = lists, *l_wh = lists + P.n_items, *l_jac = lists + 2 * P.n_items,
+               *l_st = lists + 3 * P.n_items;
+    hipError_t e = hipSuccess;
+    for (const Seg &s : P.corr) {
+        e = timed(ctx, SSL_K_CORR, st, [&] {
+            return launch_corr_batch(blk, l_corr + s.start, s.count, s.cls, prec, st);
+        });
+        if (e != hipSuccess) return e;
+    }
+    for (const Seg &s : P.whiten) {
+        e = timed(ctx, SSL_K_WHITEN, st,
+                  [&] { return launch_whiten_batch(blk, l_wh + s.start, s.count, s.cls, st); });
+        if (e != hipSuccess) return e;
+    }
+    for (const Seg &s : P.jac) {
+        e = timed(ctx, SSL_K_JACOBI, st, [&] {
+            return launch_jacobi_batch(blk, l_jac + s.start, s.count, s.cls, SSL_DEFAULT_SWEEPS,
+                                       ctx->counters + jacobi_queue(s.cls), s.extra, st);
+        });
+        if (e != hipSuccess) return e;
+    }
+    for (const Seg &s : P.steer) {
+        e = timed(ctx, SSL_K_STEER, st, [&] {
+            return launch_steer_batch(blk, l_st + s.start, s.count, s.cls, s.extra, prec, st);
+        });
+        if (e != hipSuccess) return e;
+    }
+    return timed(ctx, SSL_K_BINSUM, st, [&] {
+        return launch_binsum_batch(blk, P.nblocks, P.max_dc, P.max_fc, st);
+    });
+}
+
+}  // namespace
+
+extern "C" {
+
+ssl_status ssl_ctx_use_graphs(ssl_ctx ctx, int enable)
+{
+    if (!ctx) {
+        ssl_set_error("ctx is NULL");
+        return SSL_ERR_ARG;
+    }
+    ctx->use_graphs = enable != 0;
+    return SSL_OK;
+}
+
+ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblocks,
+                              ssl_prec prec, int p, void *stream)
+{
+    if (!ctx || !descs) {
+        ssl_set_error("ctx or descs is NULL");
+        return SSL_ERR_ARG;
+    }
+    if (nblocks < 1 || nblocks > 65535) {
+        ssl_set_error("nblocks = %d out of range [1, 65535]", nblocks);
+        return SSL_ERR_ARG;
+    }
+    if (p != 1 && p != 2) {
+        ssl_set_error("p = %d must be 1 or 2", p);
+        return SSL_ERR_ARG;
+    }
+    if (prec != SSL_FP32 && prec != SSL_BF16 && prec != SSL_FP16) {
+        ssl_set_error("prec must be SSL_FP32, SSL_BF16 or SSL_FP16");
+        return SSL_ERR_ARG;
+    }
+    ssl_status s;
+    size_t ws_total = 0;
+    int64_t n_items = 0;
+    std::vector<int64_t> key;
+    key.reserve(3 + 6 * (size_t)nblocks);
+    key.push_back(nblocks);
+    key.push_back(prec);
+    key.push_back(p);
+    for (int b = 0; b < nblocks; ++b) {
+        const ssl_block_desc &d = descs[b];
+        if ((s = check_common(d.F, d.M, d.Ns)) != SSL_OK ||
+            (s = check_x(d.X, d.T, d.M, d.strideF, d.strideT)) != SSL_OK ||
+            (s = check_grid(d.n_az, d.n_el, d.Ns)) != SSL_OK) {
+            char msg[512];
+            snprintf(msg, sizeof(msg), "block %d: %s", b, ssl_last_error());
+            ssl_set_error("%s", msg);
+            return s;
+        }
+        if (!d.K || !d.H || !d.peaks || !d.peak_val) {
+            ssl_set_error("block %d: K, H, peaks or peak_val is NULL", b);
+            return SSL_ERR_ARG;
+        }
+        if (d.K->F != d.F || d.K->M != d.M || !d.K->is_set) {
+            ssl_set_error("block %d: noise handle does not match (or was never set)", b);
+            return SSL_ERR_ARG;
+        }
+        const size_t F = d.F, M = d.M, D = (size_t)d.n_az * d.n_el, Nn = d.M - d.Ns;
+        const size_t nch = (F + SSL_BINSUM_CHUNK - 1) / SSL_BINSUM_CHUNK;
+        ws_total += 2 * align256(F * M * M * sizeof(ssl_c64)) + align256(F * Nn * M * sizeof(ssl_c64)) +
+                    align256(F * D * sizeof(float)) + align256(nch * D * sizeof(float)) +
+                    align256(F * sizeof(int32_t)) + align256(D * sizeof(float));
+        n_items += d.F;
+        key.push_back(d.F);
+        key.push_back(d.T);
+        key.push_back(d.M);
+        key.push_back(d.Ns);
+        key.push_back(d.n_az);
+        key.push_back(d.n_el);
+    }
+    if (n_items > (int64_t)1 << 30) {
+        ssl_set_error("batch too large");
+        return SSL_ERR_ARG;
+    }
+    DeviceGuard dg(ctx->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t desc_bytes = align256(sizeof(BlockDev) * nblocks);
+    const size_t list_bytes = sizeof(int2) * 4 * (size_t)n_items;
+    if ((s = ws_reserve(ctx, ws_total)) != SSL_OK) return s;
+    if ((s = counters_reserve(ctx, kJacobiQueues + (size_t)nblocks)) != SSL_OK) return s;
+    if ((s = bdesc_reserve(ctx, desc_bytes + list_bytes)) != SSL_OK) return s;
+
+    // the previous call's staging copy must have completed before the buffer is rewritten
+    hipError_t e = hipEventSynchronize(ctx->bdesc_ev);
+    if (e != hipSuccess) return hip_fail(e, "staging event");
+    BlockDev *hb = static_cast<BlockDev *>(ctx->bdesc_host);
+    int2 *hl = reinterpret_cast<int2 *>(static_cast<char *>(ctx->bdesc_host) + desc_bytes);
+    const BlockDev *db = static_cast<const BlockDev *>(ctx->bdesc_dev);
+    const int2 *dl =
+        reinterpret_cast<const int2 *>(static_cast<char *>(ctx->bdesc_dev) + desc_bytes);
+
+    Plan plan;
+    plan.nblocks = nblocks;
+    plan.n_items = (int)n_items;
+    std::vector<int> c_corr(nblocks), c_wh(nblocks), c_jac(nblocks), c_st(nblocks), Fs(nblocks);
+    char *w = static_cast<char *>(ctx->ws);
+    for (int b = 0; b < nblocks; ++b) {
+        const ssl_block_desc &d = descs[b];
+        const size_t F = d.F, M = d.M, D = (size_t)d.n_az * d.n_el, Nn = d.M - d.Ns;
+        const size_t nch = (F + SSL_BINSUM_CHUNK - 1) / SSL_BINSUM_CHUNK;
+        BlockDev &B = hb[b];
+        B.X = reinterpret_cast<const float2 *>(d.X);
+        B.sF = d.strideF;
+        B.sT = d.strideT;
+        B.F = d.F;
+        B.T = d.T;
+        B.M = d.M;
+        B.Ns = d.Ns;
+        B.D = (int)D;
+        B.n_az = d.n_az;
+        B.n_el = d.n_el;
+        B.p = p;
+        B.scale = (float)(1.0 / d.T);
+        B.hprec = prec;
+        B.Kinv = reinterpret_cast<const double2 *>(d.K->Kinv);
+        B.kstatus = d.K->status;
+        B.H = d.H;
+        B.R = reinterpret_cast<float2 *>(w);
+        w += align256(F * M * M * sizeof(ssl_c64));
+        B.A = reinterpret_cast<float2 *>(w);
+        w += align256(F * M * M * sizeof(ssl_c64));
+        B.En = reinterpret_cast<float2 *>(w);
+        w += align256(F * Nn * M * sizeof(ssl_c64));
+        B.P = reinterpret_cast<float *>(w);
+        w += align256(F * D * sizeof(float));
+        B.part = reinterpret_cast<float *>(w);
+        w += align256(nch * D * sizeof(float));
+        B.status = d.bin_status ? d.bin_status : reinterpret_cast<int32_t *>(w);
+        w += align256(F * sizeof(int32_t));
+        B.Pbar = d.Pbar ? d.Pbar : reinterpret_cast<float *>(w);
+        w += align256(D * sizeof(float));
+        B.counter = ctx->counters + kJacobiQueues + b;
+        B.peaks = d.peaks;
+        B.peak_val = d.peak_val;
+        c_corr[b] = corr_class(d.M);
+        c_wh[b] = whiten_class(d.M);
+        c_jac[b] = jacobi_class(d.M);
+        c_st[b] = steer_class(d.M, d.Ns);
+        Fs[b] = d.F;
+        plan.max_dc = std::max(plan.max_dc, (int)((D + binsum_threads() - 1) / binsum_threads()));
+        plan.max_fc = std::max(plan.max_fc, (int)nch);
+    }
+    build_list(c_corr, Fs, hl, plan.corr);
+    build_list(c_wh, Fs, hl + n_items, plan.whiten);
+    build_list(c_jac, Fs, hl + 2 * n_items, plan.jac);
+    build_list(c_st, Fs, hl + 3 * n_items, plan.steer);
+    for (Seg &sg : plan.jac)
+        sg.extra = std::min(sg.count, ctx->cu_count * jacobi_wg_per_cu(sg.cls));
+    const int rows = steer_rows_per_block();
+    for (Seg &sg : plan.steer) {
+        int dt = 0;
+        for (int b = 0; b < nblocks; ++b)
+            if (c_st[b] == sg.cls) dt = std::max(dt, (hb[b].D + rows - 1) / rows);
+        sg.extra = dt;
+    }
+
+    e = hipMemcpyAsync(ctx->bdesc_dev, ctx->bdesc_host, desc_bytes + list_bytes,
+                       hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipEventRecord(ctx->bdesc_ev, st);
+    if (e != hipSuccess) return hip_fail(e, "descriptor copy");
+
+    if (!ctx->use_graphs || ctx->timing) {
+        e = enqueue_batch(ctx, plan, db, dl, prec, st);
+        return e == hipSuccess ? SSL_OK : hip_fail(e, "batch launch");
+    }
+    hipGraphExec_t exec = nullptr;
+    for (auto &g : ctx->graphs)
+        if (g.key == key) {
+            exec = g.exec;
+            break;
+        }
+    if (!exec) {
+        if (!ctx->cap_stream) {
+            e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+        }
+        e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        hipError_t le = enqueue_batch(ctx, plan, db, dl, prec, ctx->cap_stream);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(ctx->cap_stream, &graph);
+        if (le != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return hip_fail(le, "batch capture");
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        if (ctx->graphs.size() >= 32) clear_graphs(ctx);
+        ctx->graphs.push_back({key, exec});
+    }
+    e = hipGraphLaunch(exec, st);
+    return e == hipSuccess ? SSL_OK : hip_fail(e, "hipGraphLaunch");
 }
 
 }  // extern "C"

@@ -73,10 +73,9 @@ __device__ __forceinline__ void store_tile(OutT *Rf, int M, int I, int J, const 
 // FP32 inputs, v_mfma_f32_16x16x4f32: per 4-frame step, A[i][k] = plane[t0+k][16I+i] from lane
 // i + 16k, B[k][j] = plane[t0+k][16J+j] from lane j + 16k.
 template <int MP>
-__global__ __launch_bounds__(kThreads) void corr_f32_mfma(const float2 *__restrict__ X, int T,
-                                                          int M, int64_t sF, int64_t sT,
-                                                          float scale, int accumulate,
-                                                          float2 *__restrict__ R)
+__device__ __forceinline__ void corr_f32_bin(const float2 *__restrict__ Xf, int T, int M,
+                                             int64_t sT, float scale, int accumulate,
+                                             float2 *__restrict__ Rf)
 {
     constexpr int S = MP + 16;                 // row stride: 4 frame rows of a step hit other banks
     constexpr int NT = MP / 16;
@@ -85,11 +84,9 @@ __global__ __launch_bounds__(kThreads) void corr_f32_mfma(const float2 *__restri
     __shared__ float Zr[kChunk * S];
     __shared__ float Zi[kChunk * S];
 
-    const int f = blockIdx.x;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const float2 *Xf = X + (size_t)f * sF;
 
     floatx4 acc_re[TPW], acc_im[TPW];
 #pragma unroll
@@ -129,7 +126,6 @@ __global__ __launch_bounds__(kThreads) void corr_f32_mfma(const float2 *__restri
             }
         }
     }
-    float2 *Rf = R + (size_t)f * M * M;
 #pragma unroll
     for (int q = 0; q < TPW; ++q) {
         const int tile = wave + 4 * q;
@@ -162,10 +158,9 @@ template <> struct Mfma32<_Float16> {
 };
 
 template <int MP, typename E>
-__global__ __launch_bounds__(kThreads) void corr_lp_mfma(const float2 *__restrict__ X, int T,
-                                                         int M, int64_t sF, int64_t sT,
-                                                         float scale, int accumulate,
-                                                         float2 *__restrict__ R)
+__device__ __forceinline__ void corr_lp_bin(const float2 *__restrict__ Xf, int T, int M,
+                                            int64_t sT, float scale, int accumulate,
+                                            float2 *__restrict__ Rf)
 {
     typedef typename Mfma32<E>::vec vec;
     constexpr int S = kChunk + 8;              // elements per transposed row (16 B pad)
@@ -176,11 +171,9 @@ __global__ __launch_bounds__(kThreads) void corr_lp_mfma(const float2 *__restric
     __shared__ __attribute__((aligned(16))) E Pi[MP * S];
     __shared__ __attribute__((aligned(16))) E Pn[MP * S];   // -Re, for the Im product
 
-    const int f = blockIdx.x;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const float2 *Xf = X + (size_t)f * sF;
 
     floatx4 acc_re[TPW], acc_im[TPW];
 #pragma unroll
@@ -224,7 +217,6 @@ __global__ __launch_bounds__(kThreads) void corr_lp_mfma(const float2 *__restric
             }
         }
     }
-    float2 *Rf = R + (size_t)f * M * M;
 #pragma unroll
     for (int q = 0; q < TPW; ++q) {
         const int tile = wave + 4 * q;
@@ -234,6 +226,38 @@ __global__ __launch_bounds__(kThreads) void corr_lp_mfma(const float2 *__restric
             store_tile(Rf, M, I, J, acc_re[q], acc_im[q], scale, accumulate, lane);
         }
     }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Launch wrappers: one workgroup per bin, either bin f of one block or item (block, bin) of a batch.
+// E = float selects the FP32 kernel, __bf16 / _Float16 the 16-bit-input kernel.
+template <int MP, typename E>
+__device__ __forceinline__ void corr_bin(const float2 *Xf, int T, int M, int64_t sT, float scale,
+                                         int accumulate, float2 *Rf)
+{
+    if constexpr (sizeof(E) == 4)
+        corr_f32_bin<MP>(Xf, T, M, sT, scale, accumulate, Rf);
+    else
+        corr_lp_bin<MP, E>(Xf, T, M, sT, scale, accumulate, Rf);
+}
+
+template <int MP, typename E>
+__global__ __launch_bounds__(kThreads) void corr_single(const float2 *__restrict__ X, int T, int M,
+                                                        int64_t sF, int64_t sT, float scale,
+                                                        int accumulate, float2 *__restrict__ R)
+{
+    const int f = blockIdx.x;
+    corr_bin<MP, E>(X + (size_t)f * sF, T, M, sT, scale, accumulate, R + (size_t)f * M * M);
+}
+
+template <int MP, typename E>
+__global__ __launch_bounds__(kThreads) void corr_batch(const BlockDev *__restrict__ blk,
+                                                       const int2 *__restrict__ items)
+{
+    const int2 it = items[blockIdx.x];
+    const BlockDev &B = blk[it.x];
+    corr_bin<MP, E>(B.X + (size_t)it.y * B.sF, B.T, B.M, B.sT, B.scale, 0,
+                    B.R + (size_t)it.y * B.M * B.M);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -325,14 +349,27 @@ hipError_t launch_mp(const ssl_c64 *X, int F, int T, int M, int64_t sF, int64_t 
     const float2 *Xp = reinterpret_cast<const float2 *>(X);
     float2 *Rp = reinterpret_cast<float2 *>(R);
     if (prec == SSL_FP32)
-        hipLaunchKernelGGL(corr_f32_mfma<MP>, dim3(F), dim3(kThreads), 0, st, Xp, T, M, sF, sT,
-                           (float)scale, accumulate, Rp);
+        hipLaunchKernelGGL((corr_single<MP, float>), dim3(F), dim3(kThreads), 0, st, Xp, T, M, sF,
+                           sT, (float)scale, accumulate, Rp);
     else if (prec == SSL_BF16)
-        hipLaunchKernelGGL((corr_lp_mfma<MP, __bf16>), dim3(F), dim3(kThreads), 0, st, Xp, T, M,
+        hipLaunchKernelGGL((corr_single<MP, __bf16>), dim3(F), dim3(kThreads), 0, st, Xp, T, M,
                            sF, sT, (float)scale, accumulate, Rp);
     else
-        hipLaunchKernelGGL((corr_lp_mfma<MP, _Float16>), dim3(F), dim3(kThreads), 0, st, Xp, T,
-                           M, sF, sT, (float)scale, accumulate, Rp);
+        hipLaunchKernelGGL((corr_single<MP, _Float16>), dim3(F), dim3(kThreads), 0, st, Xp, T, M,
+                           sF, sT, (float)scale, accumulate, Rp);
+    return hipGetLastError();
+}
+
+template <int MP>
+hipError_t launch_mp_batch(const BlockDev *blk, const int2 *items, int n, ssl_prec prec,
+                           hipStream_t st)
+{
+    if (prec == SSL_FP32)
+        hipLaunchKernelGGL((corr_batch<MP, float>), dim3(n), dim3(kThreads), 0, st, blk, items);
+    else if (prec == SSL_BF16)
+        hipLaunchKernelGGL((corr_batch<MP, __bf16>), dim3(n), dim3(kThreads), 0, st, blk, items);
+    else
+        hipLaunchKernelGGL((corr_batch<MP, _Float16>), dim3(n), dim3(kThreads), 0, st, blk, items);
     return hipGetLastError();
 }
 
@@ -347,8 +384,22 @@ hipError_t launch_corr(const ssl_c64 *X, int F, int T, int M, int64_t sF, int64_
                            reinterpret_cast<double2 *>(R));
         return hipGetLastError();
     }
-    if (M <= 16) return launch_mp<16>(X, F, T, M, sF, sT, scale, accumulate, prec, R, st);
-    if (M <= 32) return launch_mp<32>(X, F, T, M, sF, sT, scale, accumulate, prec, R, st);
-    if (M <= 48) return launch_mp<48>(X, F, T, M, sF, sT, scale, accumulate, prec, R, st);
-    return launch_mp<64>(X, F, T, M, sF, sT, scale, accumulate, prec, R, st);
+    switch (corr_class(M)) {
+    case 16: return launch_mp<16>(X, F, T, M, sF, sT, scale, accumulate, prec, R, st);
+    case 32: return launch_mp<32>(X, F, T, M, sF, sT, scale, accumulate, prec, R, st);
+    case 48: return launch_mp<48>(X, F, T, M, sF, sT, scale, accumulate, prec, R, st);
+    default: return launch_mp<64>(X, F, T, M, sF, sT, scale, accumulate, prec, R, st);
+    }
+}
+
+hipError_t launch_corr_batch(const BlockDev *blk, const int2 *items, int n_items, int cls,
+                             ssl_prec prec, hipStream_t st)
+{
+    if (n_items <= 0) return hipSuccess;
+    switch (cls) {
+    case 16: return launch_mp_batch<16>(blk, items, n_items, prec, st);
+    case 32: return launch_mp_batch<32>(blk, items, n_items, prec, st);
+    case 48: return launch_mp_batch<48>(blk, items, n_items, prec, st);
+    default: return launch_mp_batch<64>(blk, items, n_items, prec, st);
+    }
 }

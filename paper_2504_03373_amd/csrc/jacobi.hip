@@ -100,11 +100,14 @@ __device__ __forceinline__ float apply_reflector(const float2 *V, int k, float t
     return group_sum<G>(tn);
 }
 
+// One bin: Af = its A (row-major M x M, overwritten), kst = upstream status of the bin (noise
+// factorisation), Enf = [M-Ns][M] output, sigf = [M] or null, stf = status or null,
+// convf = (sweeps, rotations) or null.
 template <int MP, int G>
-__global__ __launch_bounds__((JacobiCfg<MP, G>::THREADS)) void jacobi_svd(
-    float2 *__restrict__ A, const int32_t *__restrict__ kstatus, int M, int Ns, int max_sweeps,
-    float2 *__restrict__ En, float *__restrict__ sigma, int32_t *__restrict__ bin_status,
-    int32_t *__restrict__ conv)
+__device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int M, int Ns,
+                                           int max_sweeps, float2 *__restrict__ Enf,
+                                           float *__restrict__ sigf, int32_t *__restrict__ stf,
+                                           int32_t *__restrict__ convf)
 {
     typedef JacobiCfg<MP, G> C;
     constexpr int R = C::R;
@@ -122,17 +125,16 @@ __global__ __launch_bounds__((JacobiCfg<MP, G>::THREADS)) void jacobi_svd(
     __shared__ int rot_total;
     __shared__ int piv_s;
 
-    const int f = blockIdx.x;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int g = tid / G;              // lane group
     const int q = tid % G;              // lane in group
     const int Nn = M - Ns;
-    float2 *Af = A + (size_t)f * M * M;
 
+    __syncthreads();                    // the previous bin of a persistent workgroup is done
     if (tid == 0) {
-        flag = (kstatus != nullptr && kstatus[f] != SSL_BIN_OK) ? kstatus[f] : SSL_BIN_OK;
+        flag = kst;
         amax_s = 0.0f;
         rot_total = 0;
     }
@@ -409,19 +411,60 @@ __global__ __launch_bounds__((JacobiCfg<MP, G>::THREADS)) void jacobi_svd(
     // ---- outputs ------------------------------------------------------------------------------
     const bool ok = (flag == SSL_BIN_OK) && converged;
     const int st = (flag != SSL_BIN_OK) ? flag : (converged ? SSL_BIN_OK : SSL_BIN_NO_CONV);
-    float2 *Enf = En + (size_t)f * Nn * M;
     for (int e = tid; e < Nn * M; e += NT) {
         const int c = e / M, r = e - c * M;
         Enf[e] = ok ? X1[perm[Ns + c] * MP + r] : make_float2(0.f, 0.f);
     }
-    if (sigma != nullptr)
-        for (int k = tid; k < M; k += NT) sigma[(size_t)f * M + k] = ok ? sig[perm[k]] : 0.0f;
+    if (sigf != nullptr)
+        for (int k = tid; k < M; k += NT) sigf[k] = ok ? sig[perm[k]] : 0.0f;
     if (tid == 0) {
-        if (bin_status != nullptr) bin_status[f] = st;
-        if (conv != nullptr) {
-            conv[2 * f] = sweeps;
-            conv[2 * f + 1] = rot_total;
+        if (stf != nullptr) *stf = st;
+        if (convf != nullptr) {
+            convf[0] = sweeps;
+            convf[1] = rot_total;
         }
+    }
+}
+
+// one workgroup per bin of one block
+template <int MP, int G>
+__global__ __launch_bounds__((JacobiCfg<MP, G>::THREADS)) void jacobi_svd(
+    float2 *__restrict__ A, const int32_t *__restrict__ kstatus, int M, int Ns, int max_sweeps,
+    float2 *__restrict__ En, float *__restrict__ sigma, int32_t *__restrict__ bin_status,
+    int32_t *__restrict__ conv)
+{
+    const int f = blockIdx.x;
+    jacobi_bin<MP, G>(A + (size_t)f * M * M, kstatus ? kstatus[f] : SSL_BIN_OK, M, Ns, max_sweeps,
+                      En + (size_t)f * (M - Ns) * M, sigma ? sigma + (size_t)f * M : nullptr,
+                      bin_status ? bin_status + f : nullptr, conv ? conv + 2 * f : nullptr);
+}
+
+// Persistent: a fixed grid of workgroups draws (block, bin) items from a device counter until the
+// list is exhausted, so bins that converge in fewer sweeps free their CU for the next item.  Every
+// workgroup draws exactly one ticket >= n_items; the one drawing the last ticket re-arms the
+// counter to 0 for the next launch.
+template <int MP, int G>
+__global__ __launch_bounds__((JacobiCfg<MP, G>::THREADS)) void jacobi_persistent(
+    const BlockDev *__restrict__ blk, const int2 *__restrict__ items, int n_items,
+    int max_sweeps, unsigned int *__restrict__ queue)
+{
+    __shared__ int item_s;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned int t = atomicAdd(queue, 1u);
+            item_s = (int)t;
+            if (t == (unsigned int)n_items + gridDim.x - 1u) atomicExch(queue, 0u);
+        }
+        __syncthreads();
+        const int it = item_s;
+        if (it >= n_items) break;
+        const int2 w = items[it];
+        const BlockDev &B = blk[w.x];
+        const int f = w.y, M = B.M, Ns = B.Ns;
+        jacobi_bin<MP, G>(B.A + (size_t)f * M * M, B.kstatus ? B.kstatus[f] : SSL_BIN_OK, M, Ns,
+                          max_sweeps, B.En + (size_t)f * (M - Ns) * M, nullptr, B.status + f,
+                          nullptr);
     }
 }
 
@@ -436,14 +479,47 @@ hipError_t launch_cfg(ssl_c64 *A, const int32_t *kstatus, int F, int M, int Ns, 
     return hipGetLastError();
 }
 
+template <int MP, int G>
+hipError_t launch_persistent(const BlockDev *blk, const int2 *items, int n_items, int max_sweeps,
+                             unsigned int *queue, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL((jacobi_persistent<MP, G>), dim3(grid), dim3(JacobiCfg<MP, G>::THREADS), 0,
+                       st, blk, items, n_items, max_sweeps, queue);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+int jacobi_threads(int cls)
+{
+    switch (cls) {
+    case 8: return JacobiCfg<8, 8>::THREADS;
+    case 16: return JacobiCfg<16, 16>::THREADS;
+    case 32: return JacobiCfg<32, 16>::THREADS;
+    default: return JacobiCfg<64, 16>::THREADS;
+    }
+}
 
 hipError_t launch_jacobi(ssl_c64 *A, const int32_t *kstatus, int F, int M, int Ns, int max_sweeps,
                          ssl_c64 *En, float *sigma, int32_t *bin_status, int32_t *conv,
                          hipStream_t st)
 {
-    if (M <= 8) return launch_cfg<8, 8>(A, kstatus, F, M, Ns, max_sweeps, En, sigma, bin_status, conv, st);
-    if (M <= 16) return launch_cfg<16, 16>(A, kstatus, F, M, Ns, max_sweeps, En, sigma, bin_status, conv, st);
-    if (M <= 32) return launch_cfg<32, 16>(A, kstatus, F, M, Ns, max_sweeps, En, sigma, bin_status, conv, st);
-    return launch_cfg<64, 16>(A, kstatus, F, M, Ns, max_sweeps, En, sigma, bin_status, conv, st);
+    switch (jacobi_class(M)) {
+    case 8: return launch_cfg<8, 8>(A, kstatus, F, M, Ns, max_sweeps, En, sigma, bin_status, conv, st);
+    case 16: return launch_cfg<16, 16>(A, kstatus, F, M, Ns, max_sweeps, En, sigma, bin_status, conv, st);
+    case 32: return launch_cfg<32, 16>(A, kstatus, F, M, Ns, max_sweeps, En, sigma, bin_status, conv, st);
+    default: return launch_cfg<64, 16>(A, kstatus, F, M, Ns, max_sweeps, En, sigma, bin_status, conv, st);
+    }
+}
+
+hipError_t launch_jacobi_batch(const BlockDev *blk, const int2 *items, int n_items, int cls,
+                               int max_sweeps, unsigned int *queue, int grid, hipStream_t st)
+{
+    if (n_items <= 0) return hipSuccess;
+    switch (cls) {
+    case 8: return launch_persistent<8, 8>(blk, items, n_items, max_sweeps, queue, grid, st);
+    case 16: return launch_persistent<16, 16>(blk, items, n_items, max_sweeps, queue, grid, st);
+    case 32: return launch_persistent<32, 16>(blk, items, n_items, max_sweeps, queue, grid, st);
+    default: return launch_persistent<64, 16>(blk, items, n_items, max_sweeps, queue, grid, st);
+    }
 }

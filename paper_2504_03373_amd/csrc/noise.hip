@@ -164,17 +164,14 @@ __global__ void noise_load_c64(double2 *__restrict__ K, const float2 *__restrict
 // A = K^{-1} R per bin in FP64.  One workgroup per bin, each thread a 4x4 register tile of A.
 // LDS: K^{-1} transposed (KT[k][i]) so a thread's 4 rows are contiguous, R upcast to FP64.
 template <int MP>
-__global__ __launch_bounds__(kThreads) void whiten(const double2 *__restrict__ Kinv,
-                                                   const float2 *__restrict__ R,
-                                                   float2 *__restrict__ A, int M)
+__device__ __forceinline__ void whiten_bin(const double2 *__restrict__ Wf,
+                                           const float2 *__restrict__ Rf,
+                                           float2 *__restrict__ Af, int M)
 {
     static_assert(MP % 4 == 0 && (MP / 4) * (MP / 4) <= kThreads, "tile grid must fit");
     __shared__ double2 KT[MP * MP];
     __shared__ double2 Rs[MP * MP];
-    const int f = blockIdx.x;
     const int tid = threadIdx.x;
-    const double2 *Wf = Kinv + (size_t)f * M * M;
-    const float2 *Rf = R + (size_t)f * M * M;
     for (int e = tid; e < MP * MP; e += kThreads) {
         const int i = e / MP, j = e - i * MP;
         double2 w = make_double2(0.0, 0.0), r = make_double2(0.0, 0.0);
@@ -212,7 +209,6 @@ __global__ __launch_bounds__(kThreads) void whiten(const double2 *__restrict__ K
                 acc[a][b].y = fma(w[a].y, r[b].x, acc[a][b].y);
             }
     }
-    float2 *Af = A + (size_t)f * M * M;
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -221,6 +217,25 @@ __global__ __launch_bounds__(kThreads) void whiten(const double2 *__restrict__ K
             if (i < M && j < M)
                 Af[(size_t)i * M + j] = make_float2((float)acc[a][b].x, (float)acc[a][b].y);
         }
+}
+
+template <int MP>
+__global__ __launch_bounds__(kThreads) void whiten(const double2 *__restrict__ Kinv,
+                                                   const float2 *__restrict__ R,
+                                                   float2 *__restrict__ A, int M)
+{
+    const size_t o = (size_t)blockIdx.x * M * M;
+    whiten_bin<MP>(Kinv + o, R + o, A + o, M);
+}
+
+template <int MP>
+__global__ __launch_bounds__(kThreads) void whiten_batch(const BlockDev *__restrict__ blk,
+                                                         const int2 *__restrict__ items)
+{
+    const int2 it = items[blockIdx.x];
+    const BlockDev &B = blk[it.x];
+    const size_t o = (size_t)it.y * B.M * B.M;
+    whiten_bin<MP>(B.Kinv + o, B.R + o, B.A + o, B.M);
 }
 
 }  // namespace
@@ -275,11 +290,22 @@ hipError_t launch_whiten(const ssl_c128 *Kinv, const ssl_c64 *R, ssl_c64 *A, int
     const double2 *Wp = reinterpret_cast<const double2 *>(Kinv);
     const float2 *Rp = reinterpret_cast<const float2 *>(R);
     float2 *Ap = reinterpret_cast<float2 *>(A);
-    if (M <= 16)
-        hipLaunchKernelGGL(whiten<16>, dim3(F), dim3(kThreads), 0, st, Wp, Rp, Ap, M);
-    else if (M <= 32)
-        hipLaunchKernelGGL(whiten<32>, dim3(F), dim3(kThreads), 0, st, Wp, Rp, Ap, M);
-    else
-        hipLaunchKernelGGL(whiten<64>, dim3(F), dim3(kThreads), 0, st, Wp, Rp, Ap, M);
+    switch (whiten_class(M)) {
+    case 16: hipLaunchKernelGGL(whiten<16>, dim3(F), dim3(kThreads), 0, st, Wp, Rp, Ap, M); break;
+    case 32: hipLaunchKernelGGL(whiten<32>, dim3(F), dim3(kThreads), 0, st, Wp, Rp, Ap, M); break;
+    default: hipLaunchKernelGGL(whiten<64>, dim3(F), dim3(kThreads), 0, st, Wp, Rp, Ap, M); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_whiten_batch(const BlockDev *blk, const int2 *items, int n_items, int cls,
+                               hipStream_t st)
+{
+    if (n_items <= 0) return hipSuccess;
+    switch (cls) {
+    case 16: hipLaunchKernelGGL(whiten_batch<16>, dim3(n_items), dim3(kThreads), 0, st, blk, items); break;
+    case 32: hipLaunchKernelGGL(whiten_batch<32>, dim3(n_items), dim3(kThreads), 0, st, blk, items); break;
+    default: hipLaunchKernelGGL(whiten_batch<64>, dim3(n_items), dim3(kThreads), 0, st, blk, items); break;
+    }
     return hipGetLastError();
 }

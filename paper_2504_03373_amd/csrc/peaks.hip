@@ -96,10 +96,11 @@ __device__ void search_peaks(const float *pb, int D, int n_az, int n_el, int Ns,
     }
 }
 
-__global__ __launch_bounds__(kThreads) void binsum_peaks(
+// Workgroup (dc, ch) of an ndc x nch grid over one block's [F][D] spectrum.
+__device__ __forceinline__ void binsum_peaks_body(
     const float *__restrict__ P, int F, int D, float *__restrict__ Pbar, float *__restrict__ part,
     unsigned int *__restrict__ counter, int n_az, int n_el, int Ns, int32_t *__restrict__ peaks,
-    float *__restrict__ peak_val)
+    float *__restrict__ peak_val, int dc, int ch, int ndc, int nch)
 {
     __shared__ float pb_s[kLdsPbar];
     __shared__ unsigned char cand[kLdsPbar];
@@ -108,9 +109,7 @@ __global__ __launch_bounds__(kThreads) void binsum_peaks(
     __shared__ int chosen[SSL_MAX_M];
     __shared__ int is_last;
     const int tid = threadIdx.x;
-    const int d = blockIdx.x * kThreads + tid;
-    const int ch = blockIdx.y;
-    const int nch = gridDim.y;
+    const int d = dc * kThreads + tid;
     if (d < D) {
         // all loads of the chunk in flight at once, then the sum in ascending bin order
         // (absent bins of a short last chunk add an exact 0)
@@ -129,7 +128,7 @@ __global__ __launch_bounds__(kThreads) void binsum_peaks(
     __syncthreads();
     if (tid == 0) {
         const unsigned int ticket = atomicAdd(counter, 1u);
-        is_last = (ticket == gridDim.x * gridDim.y - 1) ? 1 : 0;
+        is_last = (ticket == (unsigned int)(ndc * nch) - 1u) ? 1 : 0;
     }
     __syncthreads();
     if (!is_last) return;
@@ -160,6 +159,27 @@ __global__ __launch_bounds__(kThreads) void binsum_peaks(
                      chosen);
 }
 
+__global__ __launch_bounds__(kThreads) void binsum_peaks(
+    const float *__restrict__ P, int F, int D, float *__restrict__ Pbar, float *__restrict__ part,
+    unsigned int *__restrict__ counter, int n_az, int n_el, int Ns, int32_t *__restrict__ peaks,
+    float *__restrict__ peak_val)
+{
+    binsum_peaks_body(P, F, D, Pbar, part, counter, n_az, n_el, Ns, peaks, peak_val, blockIdx.x,
+                      blockIdx.y, gridDim.x, gridDim.y);
+}
+
+// Batch: grid z = block; workgroups outside a block's own (direction, bin) chunk grid leave at once
+// and never touch its counter.
+__global__ __launch_bounds__(kThreads) void binsum_peaks_batch(const BlockDev *__restrict__ blk)
+{
+    const BlockDev &B = blk[blockIdx.z];
+    const int ndc = (B.D + kThreads - 1) / kThreads;
+    const int nch = (B.F + SSL_BINSUM_CHUNK - 1) / SSL_BINSUM_CHUNK;
+    if ((int)blockIdx.x >= ndc || (int)blockIdx.y >= nch) return;
+    binsum_peaks_body(B.P, B.F, B.D, B.Pbar, B.part, B.counter, B.n_az, B.n_el, B.Ns, B.peaks,
+                      B.peak_val, blockIdx.x, blockIdx.y, ndc, nch);
+}
+
 __global__ __launch_bounds__(kThreads) void peaks_only(const float *__restrict__ Pbar, int D,
                                                        int n_az, int n_el, int Ns,
                                                        int32_t *__restrict__ peaks,
@@ -188,6 +208,17 @@ hipError_t launch_binsum_peaks(const float *P, int F, int D, float *Pbar, float 
     const dim3 grid((D + kThreads - 1) / kThreads, nch);
     hipLaunchKernelGGL(binsum_peaks, grid, dim3(kThreads), 0, st, P, F, D, Pbar, part, counter,
                        n_az, n_el, Ns, peaks, peak_val);
+    return hipGetLastError();
+}
+
+int binsum_threads() { return kThreads; }
+
+hipError_t launch_binsum_batch(const BlockDev *blk, int nblocks, int max_dchunks, int max_fchunks,
+                               hipStream_t st)
+{
+    if (nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(binsum_peaks_batch, dim3(max_dchunks, max_fchunks, nblocks),
+                       dim3(kThreads), 0, st, blk);
     return hipGetLastError();
 }
 

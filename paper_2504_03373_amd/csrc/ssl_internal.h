@@ -38,6 +38,21 @@ struct ssl_ctx_s {
     std::vector<Timed> event_pool;
     int64_t launches[SSL_K_COUNT] = {};
     double total_ms[SSL_K_COUNT] = {};
+    // batched path (ssl_localize_batch)
+    void *bdesc_dev = nullptr;           // device copy of descriptors + work-item lists
+    void *bdesc_host = nullptr;          // pinned staging buffer of the same
+    size_t bdesc_bytes = 0;
+    hipEvent_t bdesc_ev = nullptr;       // completion of the last staging copy
+    unsigned int *counters = nullptr;    // zero-initialised, every kernel leaves them at zero
+    size_t n_counters = 0;
+    hipStream_t cap_stream = nullptr;    // capture stream for graph construction
+    bool use_graphs = true;
+    struct GraphEntry {
+        std::vector<int64_t> key;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
+    int cu_count = 0;
 };
 
 struct ssl_noise_s {
@@ -50,6 +65,51 @@ struct ssl_noise_s {
 };
 
 void ssl_set_error(const char *fmt, ...);
+
+// Device view of one block of a batch: caller pointers, shapes and the block's slices of the
+// batch workspace.  Filled on the host, copied to HBM once per batch call.
+struct BlockDev {
+    const float2 *X;
+    int64_t sF, sT;
+    int F, T, M, Ns, D, n_az, n_el, p;
+    float scale;                    // (float)(1/T), the same value the single-block path uses
+    int hprec;                      // ssl_prec of H
+    const double2 *Kinv;            // noise handle: FP64 inverse, per-bin status
+    const int32_t *kstatus;
+    const void *H;
+    float2 *R, *A, *En;             // workspace slices
+    float *P, *part;
+    unsigned int *counter;          // bin-sum completion counter (starts and ends at 0)
+    int32_t *peaks, *status;        // caller outputs
+    float *peak_val, *Pbar;
+};
+
+// Size classes shared by the single-block and batched launches, so that a bin is computed by the
+// same kernel variant whichever entry point schedules it.
+inline int corr_class(int M) { return M <= 16 ? 16 : M <= 32 ? 32 : M <= 48 ? 48 : 64; }
+inline int whiten_class(int M) { return M <= 16 ? 16 : M <= 32 ? 32 : 64; }
+inline int jacobi_class(int M) { return M <= 8 ? 8 : M <= 16 ? 16 : M <= 32 ? 32 : 64; }
+inline int steer_class(int M, int Ns)
+{
+    const int ncol = 2 * (M - Ns);
+    return ncol <= 16 ? 1 : ncol <= 32 ? 2 : ncol <= 64 ? 4 : 8;
+}
+
+// Batched launchers.  `items` lists (block, bin) pairs whose blocks share the kernel's size class.
+hipError_t launch_corr_batch(const BlockDev *blk, const int2 *items, int n_items, int cls,
+                             ssl_prec prec, hipStream_t st);
+hipError_t launch_whiten_batch(const BlockDev *blk, const int2 *items, int n_items, int cls,
+                               hipStream_t st);
+// Persistent: `grid` workgroups draw items from *queue (0 on entry, re-armed to 0 on exit).
+hipError_t launch_jacobi_batch(const BlockDev *blk, const int2 *items, int n_items, int cls,
+                               int max_sweeps, unsigned int *queue, int grid, hipStream_t st);
+hipError_t launch_steer_batch(const BlockDev *blk, const int2 *items, int n_items, int cls,
+                              int max_dtiles, ssl_prec hprec, hipStream_t st);
+hipError_t launch_binsum_batch(const BlockDev *blk, int nblocks, int max_dchunks,
+                               int max_fchunks, hipStream_t st);
+int jacobi_threads(int cls);
+int steer_rows_per_block();
+int binsum_threads();
 
 // --- launchers (each returns hipSuccess or the launch error) ---
 hipError_t launch_corr(const ssl_c64 *X, int F, int T, int M, int64_t sF, int64_t sT, double scale,

@@ -104,18 +104,18 @@ __device__ __forceinline__ void stage_b(const float2 *__restrict__ Enf, int M, i
 // FP32: v_mfma_f32_16x16x4f32.  Lane l = (row i = l%16, slice s = l/16) reads the float4
 // h[16 kq + 4 s .. +3] of its row; MFMA step e (0..3) contracts k = 16 kq + 4 s + e, and the B
 // operand of the same k is the float4 Bs[col][16 kq + 4 s .. +3].
+// One workgroup tile: directions d0 .. d0 + kRowsPerBlock - 1 of one bin.  Hf = the bin's [D][2M]
+// table, Enf = its [Nn][M] noise subspace, Pf = its [D] output, ok = bin status is SSL_BIN_OK.
 template <int NCT>
-__global__ __launch_bounds__(kThreads) void steer_f32(const float *__restrict__ H,
-                                                      const float2 *__restrict__ En,
-                                                      const int32_t *__restrict__ bin_status,
-                                                      int D, int M, int Ns, int p,
-                                                      float *__restrict__ P)
+__device__ __forceinline__ void steer_f32_tile(const float *__restrict__ Hf,
+                                               const float2 *__restrict__ Enf, bool ok, int D,
+                                               int M, int Ns, int p, float *__restrict__ Pf,
+                                               int d0)
 {
     constexpr int KS_MAX = 128 + 4;
     __shared__ __attribute__((aligned(16))) float Bs[16 * NCT * KS_MAX];
     __shared__ float den_s[kRowsPerBlock];
     __shared__ float nrm_s[kRowsPerBlock];
-    const int f = blockIdx.y;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -125,13 +125,12 @@ __global__ __launch_bounds__(kThreads) void steer_f32(const float *__restrict__ 
     const int KP = 16 * KQ;
     const int KS = KP + 4;
     const int NCOL = 16 * NCT;
-    stage_b<float>(En + (size_t)f * Nn * M, M, Nn, Bs, KS, NCOL, KP, tid);
+    stage_b<float>(Enf, M, Nn, Bs, KS, NCOL, KP, tid);
     __syncthreads();
 
-    const int d0 = blockIdx.x * kRowsPerBlock;
     const int row = d0 + wave * 16 + (lane & 15);
     const int sl = lane >> 4;
-    const float *hrow = H + ((size_t)f * D + (row < D ? row : 0)) * K2;
+    const float *hrow = Hf + (size_t)(row < D ? row : 0) * K2;
     // the wave's whole 16-row strip of H in registers first: every load in flight at once
     constexpr int KQ_MAX = 8;
     float4 a[KQ_MAX];
@@ -166,8 +165,7 @@ __global__ __launch_bounds__(kThreads) void steer_f32(const float *__restrict__ 
             }
         }
     }
-    const bool ok = bin_status == nullptr || bin_status[f] == SSL_BIN_OK;
-    finish_rows<NCT>(acc, hn, p, lane, wave, d0, D, ok, P + (size_t)f * D, den_s, nrm_s);
+    finish_rows<NCT>(acc, hn, p, lane, wave, d0, D, ok, Pf, den_s, nrm_s);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -190,18 +188,16 @@ template <> struct LpMfma<_Float16> {
 };
 
 template <int NCT, typename E>
-__global__ __launch_bounds__(kThreads) void steer_lp(const E *__restrict__ H,
-                                                     const float2 *__restrict__ En,
-                                                     const int32_t *__restrict__ bin_status,
-                                                     int D, int M, int Ns, int p,
-                                                     float *__restrict__ P)
+__device__ __forceinline__ void steer_lp_tile(const E *__restrict__ Hf,
+                                              const float2 *__restrict__ Enf, bool ok, int D,
+                                              int M, int Ns, int p, float *__restrict__ Pf,
+                                              int d0)
 {
     typedef typename LpMfma<E>::vec vec;
     constexpr int KS_MAX = 128 + 8;
     __shared__ __attribute__((aligned(16))) E Bs[16 * NCT * KS_MAX];
     __shared__ float den_s[kRowsPerBlock];
     __shared__ float nrm_s[kRowsPerBlock];
-    const int f = blockIdx.y;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -211,13 +207,12 @@ __global__ __launch_bounds__(kThreads) void steer_lp(const E *__restrict__ H,
     const int KP = 32 * KQ;
     const int KS = KP + 8;
     const int NCOL = 16 * NCT;
-    stage_b<E>(En + (size_t)f * Nn * M, M, Nn, Bs, KS, NCOL, KP, tid);
+    stage_b<E>(Enf, M, Nn, Bs, KS, NCOL, KP, tid);
     __syncthreads();
 
-    const int d0 = blockIdx.x * kRowsPerBlock;
     const int row = d0 + wave * 16 + (lane & 15);
     const int sl = lane >> 4;
-    const E *hrow = H + ((size_t)f * D + (row < D ? row : 0)) * K2;
+    const E *hrow = Hf + (size_t)(row < D ? row : 0) * K2;
     // the strip in registers first; each complex element is one 32-bit (re, im) pair
     constexpr int KQ_MAX = 4;
     vec a[KQ_MAX];
@@ -251,8 +246,46 @@ __global__ __launch_bounds__(kThreads) void steer_lp(const E *__restrict__ H,
             }
         }
     }
+    finish_rows<NCT>(acc, hn, p, lane, wave, d0, D, ok, Pf, den_s, nrm_s);
+}
+
+// E = float selects the FP32 tile, __bf16 / _Float16 the 16-bit tile.
+template <int NCT, typename E>
+__device__ __forceinline__ void steer_tile(const E *Hf, const float2 *Enf, bool ok, int D, int M,
+                                           int Ns, int p, float *Pf, int d0)
+{
+    if constexpr (sizeof(E) == 4)
+        steer_f32_tile<NCT>(Hf, Enf, ok, D, M, Ns, p, Pf, d0);
+    else
+        steer_lp_tile<NCT, E>(Hf, Enf, ok, D, M, Ns, p, Pf, d0);
+}
+
+template <int NCT, typename E>
+__global__ __launch_bounds__(kThreads) void steer_single(const E *__restrict__ H,
+                                                         const float2 *__restrict__ En,
+                                                         const int32_t *__restrict__ bin_status,
+                                                         int D, int M, int Ns, int p,
+                                                         float *__restrict__ P)
+{
+    const int f = blockIdx.y;
     const bool ok = bin_status == nullptr || bin_status[f] == SSL_BIN_OK;
-    finish_rows<NCT>(acc, hn, p, lane, wave, d0, D, ok, P + (size_t)f * D, den_s, nrm_s);
+    steer_tile<NCT, E>(H + (size_t)f * D * 2 * M, En + (size_t)f * (M - Ns) * M, ok, D, M, Ns, p,
+                       P + (size_t)f * D, blockIdx.x * kRowsPerBlock);
+}
+
+template <int NCT, typename E>
+__global__ __launch_bounds__(kThreads) void steer_batch(const BlockDev *__restrict__ blk,
+                                                        const int2 *__restrict__ items)
+{
+    const int2 it = items[blockIdx.x];            // items on x: a batch may exceed 65535 of them
+    const BlockDev &B = blk[it.x];
+    const int d0 = blockIdx.y * kRowsPerBlock;
+    if (d0 >= B.D) return;
+    const int f = it.y, M = B.M, Ns = B.Ns, D = B.D;
+    const bool ok = B.status[f] == SSL_BIN_OK;
+    steer_tile<NCT, E>(static_cast<const E *>(B.H) + (size_t)f * D * 2 * M,
+                       B.En + (size_t)f * (M - Ns) * M, ok, D, M, Ns, B.p, B.P + (size_t)f * D,
+                       d0);
 }
 
 template <int NCT>
@@ -262,25 +295,54 @@ hipError_t launch_nct(const void *H, ssl_prec hprec, const ssl_c64 *En, int F, i
     const dim3 grid((D + kRowsPerBlock - 1) / kRowsPerBlock, F);
     const float2 *Ep = reinterpret_cast<const float2 *>(En);
     if (hprec == SSL_FP32)
-        hipLaunchKernelGGL(steer_f32<NCT>, grid, dim3(kThreads), 0, st,
+        hipLaunchKernelGGL((steer_single<NCT, float>), grid, dim3(kThreads), 0, st,
                            static_cast<const float *>(H), Ep, bin_status, D, M, Ns, p, P);
     else if (hprec == SSL_BF16)
-        hipLaunchKernelGGL((steer_lp<NCT, __bf16>), grid, dim3(kThreads), 0, st,
+        hipLaunchKernelGGL((steer_single<NCT, __bf16>), grid, dim3(kThreads), 0, st,
                            static_cast<const __bf16 *>(H), Ep, bin_status, D, M, Ns, p, P);
     else
-        hipLaunchKernelGGL((steer_lp<NCT, _Float16>), grid, dim3(kThreads), 0, st,
+        hipLaunchKernelGGL((steer_single<NCT, _Float16>), grid, dim3(kThreads), 0, st,
                            static_cast<const _Float16 *>(H), Ep, bin_status, D, M, Ns, p, P);
+    return hipGetLastError();
+}
+
+template <int NCT>
+hipError_t launch_nct_batch(const BlockDev *blk, const int2 *items, int n_items, int max_dtiles,
+                            ssl_prec hprec, hipStream_t st)
+{
+    const dim3 grid(n_items, max_dtiles);
+    if (hprec == SSL_FP32)
+        hipLaunchKernelGGL((steer_batch<NCT, float>), grid, dim3(kThreads), 0, st, blk, items);
+    else if (hprec == SSL_BF16)
+        hipLaunchKernelGGL((steer_batch<NCT, __bf16>), grid, dim3(kThreads), 0, st, blk, items);
+    else
+        hipLaunchKernelGGL((steer_batch<NCT, _Float16>), grid, dim3(kThreads), 0, st, blk, items);
     return hipGetLastError();
 }
 
 }  // namespace
 
+int steer_rows_per_block() { return kRowsPerBlock; }
+
 hipError_t launch_steer(const void *H, ssl_prec hprec, const ssl_c64 *En, int F, int D, int M,
                         int Ns, int p, const int32_t *bin_status, float *P, hipStream_t st)
 {
-    const int ncol = 2 * (M - Ns);
-    if (ncol <= 16) return launch_nct<1>(H, hprec, En, F, D, M, Ns, p, bin_status, P, st);
-    if (ncol <= 32) return launch_nct<2>(H, hprec, En, F, D, M, Ns, p, bin_status, P, st);
-    if (ncol <= 64) return launch_nct<4>(H, hprec, En, F, D, M, Ns, p, bin_status, P, st);
-    return launch_nct<kMaxColTiles>(H, hprec, En, F, D, M, Ns, p, bin_status, P, st);
+    switch (steer_class(M, Ns)) {
+    case 1: return launch_nct<1>(H, hprec, En, F, D, M, Ns, p, bin_status, P, st);
+    case 2: return launch_nct<2>(H, hprec, En, F, D, M, Ns, p, bin_status, P, st);
+    case 4: return launch_nct<4>(H, hprec, En, F, D, M, Ns, p, bin_status, P, st);
+    default: return launch_nct<kMaxColTiles>(H, hprec, En, F, D, M, Ns, p, bin_status, P, st);
+    }
+}
+
+hipError_t launch_steer_batch(const BlockDev *blk, const int2 *items, int n_items, int cls,
+                              int max_dtiles, ssl_prec hprec, hipStream_t st)
+{
+    if (n_items <= 0) return hipSuccess;
+    switch (cls) {
+    case 1: return launch_nct_batch<1>(blk, items, n_items, max_dtiles, hprec, st);
+    case 2: return launch_nct_batch<2>(blk, items, n_items, max_dtiles, hprec, st);
+    case 4: return launch_nct_batch<4>(blk, items, n_items, max_dtiles, hprec, st);
+    default: return launch_nct_batch<kMaxColTiles>(blk, items, n_items, max_dtiles, hprec, st);
+    }
 }

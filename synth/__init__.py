@@ -220,18 +220,30 @@ def workload_small(n_blocks: int = 10, seed: int = 1001) -> Workload:
                     max_src_el=0.0, seed=seed)
 
 
-def workload_paper(n_blocks: int = 1000, seed: int = 1002, M: int = 60, F: int = 257) -> Workload:
+def workload_paper(n_blocks: int = 1000, seed: int = 1002, M: int = 60, F: int = 257,
+                   Ns: int = 2) -> Workload:
     """60-mic 4-ring array, 257 bins, T = 50, Ns = 2 at random grid directions (el <= 80 deg),
     SNR ~ U[-5, 10] dB against white + 2 directional noises of equal power; K from 4M frames;
-    72 x 19 = 1368 directions (upper hemisphere, 5 degree steps)."""
+    72 x 19 = 1368 directions (upper hemisphere, 5 degree steps).  Other M use a circle of
+    r = 0.1 m, other F the matching STFT length."""
     grid = DirectionGrid(72, 19)
     nfft = 2 * (F - 1)
-    return Workload(name=f"gsvd-music-{M}ch-{F}bin-1368dir", M=M, F=F, T=50, Ns=2, grid=grid,
+    return Workload(name=f"gsvd-music-{M}ch-{F}bin-1368dir", M=M, F=F, T=50, Ns=Ns, grid=grid,
                     n_blocks=n_blocks, n_noise_frames=4 * M, pos=array_for(M),
                     freqs=bin_freqs(F, 16000.0, nfft),
                     noise_u=[unit_vector(135.0, 10.0), unit_vector(290.0, 30.0)],
                     p_noise=[1.0, 1.0], sigma_d2=1.0, snr_db_range=(-5.0, 10.0), white_ref=False,
                     max_src_el=80.0, seed=seed)
+
+
+def uneven_shapes(n_blocks: int, seed: int = 1004):
+    """Shapes of an uneven batch: M in {8, 16, 32, 60}, 512- or 1024-point STFT (F = 257 / 513) and
+    Ns in {1, 2, 3}, each uniform; returns a list of (M, F, Ns) tuples."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed))
+    Ms = rng.choice([8, 16, 32, 60], size=n_blocks)
+    Fs = rng.choice([257, 513], size=n_blocks)
+    Nss = rng.integers(1, 4, size=n_blocks)
+    return [(int(m), int(f), int(n)) for m, f, n in zip(Ms, Fs, Nss)]
 
 
 def analytic_noise_corr(pos, freqs, noise_u, sigma_d2: float, rho: float) -> np.ndarray:
