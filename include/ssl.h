@@ -201,6 +201,24 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
  * always run as individually timed launches. */
 ssl_status ssl_ctx_use_graphs(ssl_ctx ctx, int enable);
 
+/* ------------------------------------------------------------------ tuning */
+
+/* Jacobi SVD kernel variant per channel-count class (M <= 8, <= 16, <= 32, <= 64): the number of
+ * lanes that cooperate on one column pair.  Available: 4 or 8 (M <= 8); 4, 8 or 16 (M <= 16);
+ * 8 or 16 (M <= 32, M <= 64).  Defaults 8, 16, 16, 16.  A context applies its current choice to
+ * every entry point, so batched and single-block results remain bit-identical; variants differ
+ * from each other only by rounding.  Returns SSL_ERR_ARG for an unavailable variant. */
+ssl_status ssl_ctx_set_jacobi_lanes(ssl_ctx ctx, int M, int lanes);
+int ssl_ctx_get_jacobi_lanes(ssl_ctx ctx, int M);
+
+/* Autotuner: times every available Jacobi variant of M's class on the caller's problems -- the
+ * whitened products K^{-1} R[f] of F bins -- `reps` launches each (after one untimed launch),
+ * with HIP events on `stream`, keeps the fastest in the context and returns it in *best_lanes.
+ * ms_per_variant ([3], host, or NULL) receives the mean milliseconds per launch for lanes = 4, 8,
+ * 16 (-1 where unavailable).  R: [F][M][M] device, K set for F and M.  Synchronous. */
+ssl_status ssl_autotune_jacobi(ssl_ctx ctx, const ssl_c64 *R, ssl_noise K, int F, int M, int Ns,
+                               int reps, int *best_lanes, double *ms_per_variant, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,6 +26,7 @@ EXPORTED = [
     "ssl_corr_accum", "ssl_noise_create", "ssl_noise_set", "ssl_noise_update", "ssl_noise_get",
     "ssl_noise_destroy", "ssl_gsvd", "ssl_music_spectrum", "ssl_peaks", "ssl_localize",
     "ssl_ctx_timing", "ssl_ctx_timing_read", "ssl_localize_batch", "ssl_ctx_use_graphs",
+    "ssl_ctx_set_jacobi_lanes", "ssl_ctx_get_jacobi_lanes", "ssl_autotune_jacobi",
 ]
 
 
@@ -77,6 +78,10 @@ def lib() -> ctypes.CDLL:
         "ssl_localize": (I, [P, P, I, I, I, I64, I64, P, P, I, I, I, I, I, P, P, P, P, P]),
         "ssl_localize_batch": (I, [P, ctypes.POINTER(BlockDesc), I, I, I, P]),
         "ssl_ctx_use_graphs": (I, [P, I]),
+        "ssl_ctx_set_jacobi_lanes": (I, [P, I, I]),
+        "ssl_ctx_get_jacobi_lanes": (I, [P, I]),
+        "ssl_autotune_jacobi": (I, [P, P, P, I, I, I, I, ctypes.POINTER(I),
+                                    ctypes.POINTER(ctypes.c_double), P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -231,3 +236,21 @@ def ssl_localize_batch(ctx, descs, prec, p, stream=None):
 
 def ssl_ctx_use_graphs(ctx, enable: bool) -> None:
     _check("ssl_ctx_use_graphs", lib().ssl_ctx_use_graphs(ctx, int(bool(enable))))
+
+
+def ssl_ctx_set_jacobi_lanes(ctx, M: int, lanes: int) -> None:
+    _check("ssl_ctx_set_jacobi_lanes", lib().ssl_ctx_set_jacobi_lanes(ctx, M, lanes))
+
+
+def ssl_ctx_get_jacobi_lanes(ctx, M: int) -> int:
+    return lib().ssl_ctx_get_jacobi_lanes(ctx, M)
+
+
+def ssl_autotune_jacobi(ctx, R, noise, Ns: int, reps: int = 3, stream=None):
+    """Times the Jacobi variants of R's channel class; returns (best lanes, {lanes: ms})."""
+    F, M, _ = R.shape
+    best = ctypes.c_int(0)
+    ms = (ctypes.c_double * 3)()
+    _check("ssl_autotune_jacobi", lib().ssl_autotune_jacobi(ctx, _ptr(R), noise, F, M, Ns, reps,
+                                                            ctypes.byref(best), ms, _stream(stream)))
+    return best.value, {l: ms[i] for i, l in enumerate((4, 8, 16)) if ms[i] >= 0}

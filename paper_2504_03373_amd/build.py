@@ -15,7 +15,7 @@ SOURCES = ["abi.hip", "corr.hip", "noise.hip", "jacobi.hip", "steer.hip", "peaks
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+    "--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC",
     # packed FP32 instructions stay off on this hardware
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",

@@ -142,6 +142,8 @@ hipError_t timed(ssl_ctx ctx, int id, hipStream_t st, Fn &&launch)
     return e;
 }
 
+int jac_lanes(ssl_ctx ctx, int M) { return ctx->jac_lanes[jacobi_class_index(jacobi_class(M))]; }
+
 ssl_status check_common(int F, int M, int Ns)
 {
     if (F < 1 || F > 65535) {
@@ -479,7 +481,8 @@ ssl_status ssl_gsvd(ssl_ctx ctx, const ssl_c64 *R, ssl_noise K, int F, int M, in
                          [&] { return launch_whiten(K->Kinv, R, A, F, M, st); });
     if (e != hipSuccess) return hip_fail(e, "whiten launch");
     e = timed(ctx, SSL_K_JACOBI, st, [&] {
-        return launch_jacobi(A, K->status, F, M, Ns, max_sweeps, En, sigma, bin_status, conv, st);
+        return launch_jacobi(A, K->status, F, M, Ns, max_sweeps, jac_lanes(ctx, M), En, sigma,
+                             bin_status, conv, st);
     });
     return e == hipSuccess ? SSL_OK : hip_fail(e, "jacobi launch");
 }
@@ -598,8 +601,8 @@ ssl_status ssl_localize(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int M, int6
     e = timed(ctx, SSL_K_WHITEN, st, [&] { return launch_whiten(K->Kinv, R, A, F, M, st); });
     if (e != hipSuccess) return hip_fail(e, "whiten launch");
     e = timed(ctx, SSL_K_JACOBI, st, [&] {
-        return launch_jacobi(A, K->status, F, M, Ns, SSL_DEFAULT_SWEEPS, En, nullptr, stt,
-                             nullptr, st);
+        return launch_jacobi(A, K->status, F, M, Ns, SSL_DEFAULT_SWEEPS, jac_lanes(ctx, M), En,
+                             nullptr, stt, nullptr, st);
     });
     if (e != hipSuccess) return hip_fail(e, "jacobi launch");
     e = timed(ctx, SSL_K_STEER, st,
@@ -723,8 +726,10 @@ hipError_t enqueue_batch(ssl_ctx ctx, const Plan &P, const BlockDev *blk, const 
     }
     for (const Seg &s : P.jac) {
         e = timed(ctx, SSL_K_JACOBI, st, [&] {
-            return launch_jacobi_batch(blk, l_jac + s.start, s.count, s.cls, SSL_DEFAULT_SWEEPS,
-                                       ctx->counters + jacobi_queue(s.cls), s.extra, st);
+            return launch_jacobi_batch(blk, l_jac + s.start, s.count, s.cls,
+                                       ctx->jac_lanes[jacobi_class_index(s.cls)],
+                                       SSL_DEFAULT_SWEEPS, ctx->counters + jacobi_queue(s.cls),
+                                       s.extra, st);
         });
         if (e != hipSuccess) return e;
     }
@@ -742,6 +747,84 @@ hipError_t enqueue_batch(ssl_ctx ctx, const Plan &P, const BlockDev *blk, const 
 }  // namespace
 
 extern "C" {
+
+ssl_status ssl_ctx_set_jacobi_lanes(ssl_ctx ctx, int M, int lanes)
+{
+    if (!ctx || M < 1 || M > SSL_MAX_M || !jacobi_variant_ok(jacobi_class(M), lanes)) {
+        ssl_set_error("no Jacobi variant with %d lanes for M = %d", lanes, M);
+        return SSL_ERR_ARG;
+    }
+    ctx->jac_lanes[jacobi_class_index(jacobi_class(M))] = lanes;
+    return SSL_OK;
+}
+
+int ssl_ctx_get_jacobi_lanes(ssl_ctx ctx, int M)
+{
+    if (!ctx || M < 1 || M > SSL_MAX_M) return -1;
+    return jac_lanes(ctx, M);
+}
+
+ssl_status ssl_autotune_jacobi(ssl_ctx ctx, const ssl_c64 *R, ssl_noise K, int F, int M, int Ns,
+                               int reps, int *best_lanes, double *ms_per_variant, void *stream)
+{
+    if (!ctx || !R || !K || !best_lanes) {
+        ssl_set_error("ctx, R, K or best_lanes is NULL");
+        return SSL_ERR_ARG;
+    }
+    ssl_status s = check_common(F, M, Ns);
+    if (s != SSL_OK) return s;
+    if (K->F != F || K->M != M || !K->is_set) {
+        ssl_set_error("noise handle does not match (or was never set)");
+        return SSL_ERR_ARG;
+    }
+    if (reps < 1 || reps > 1000) {
+        ssl_set_error("reps = %d out of range [1, 1000]", reps);
+        return SSL_ERR_ARG;
+    }
+    DeviceGuard dg(ctx->device);
+    const size_t bA = align256((size_t)F * M * M * sizeof(ssl_c64));
+    const size_t bE = align256((size_t)F * (M - Ns) * M * sizeof(ssl_c64));
+    if ((s = ws_reserve(ctx, bA + bE)) != SSL_OK) return s;
+    ssl_c64 *A = static_cast<ssl_c64 *>(ctx->ws);
+    ssl_c64 *En = reinterpret_cast<ssl_c64 *>(static_cast<char *>(ctx->ws) + bA);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int cls = jacobi_class(M);
+    const int cand[3] = {4, 8, 16};
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    int best = -1;
+    double best_ms = 0.0;
+    for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+        if (ms_per_variant) ms_per_variant[i] = -1.0;
+        if (!jacobi_variant_ok(cls, cand[i])) continue;
+        double total = 0.0;
+        for (int r = 0; r <= reps && e == hipSuccess; ++r) {
+            e = launch_whiten(K->Kinv, R, A, F, M, st);          // A is consumed by each launch
+            if (e == hipSuccess) e = hipEventRecord(a, st);
+            if (e == hipSuccess)
+                e = launch_jacobi(A, K->status, F, M, Ns, SSL_DEFAULT_SWEEPS, cand[i], En,
+                                  nullptr, nullptr, nullptr, st);
+            if (e == hipSuccess) e = hipEventRecord(b, st);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+            if (r > 0) total += ms;                               // launch 0 is the warm-up
+        }
+        const double mean = total / reps;
+        if (ms_per_variant) ms_per_variant[i] = mean;
+        if (best < 0 || mean < best_ms) {
+            best = cand[i];
+            best_ms = mean;
+        }
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (e != hipSuccess) return hip_fail(e, "autotune");
+    ctx->jac_lanes[jacobi_class_index(cls)] = best;
+    *best_lanes = best;
+    return SSL_OK;
+}
 
 ssl_status ssl_ctx_use_graphs(ssl_ctx ctx, int enable)
 {

@@ -488,38 +488,64 @@ hipError_t launch_persistent(const BlockDev *blk, const int2 *items, int n_items
     return hipGetLastError();
 }
 
-}  // namespace
-
-int jacobi_threads(int cls)
+// Calls fn.template operator()<MP, G>() for the (class, lanes) variant; false if not compiled.
+template <class Fn>
+bool dispatch(int cls, int lanes, Fn &&fn)
 {
     switch (cls) {
-    case 8: return JacobiCfg<8, 8>::THREADS;
-    case 16: return JacobiCfg<16, 16>::THREADS;
-    case 32: return JacobiCfg<32, 16>::THREADS;
-    default: return JacobiCfg<64, 16>::THREADS;
+    case 8:
+        if (lanes == 4) return fn.template operator()<8, 4>(), true;
+        if (lanes == 8) return fn.template operator()<8, 8>(), true;
+        return false;
+    case 16:
+        if (lanes == 4) return fn.template operator()<16, 4>(), true;
+        if (lanes == 8) return fn.template operator()<16, 8>(), true;
+        if (lanes == 16) return fn.template operator()<16, 16>(), true;
+        return false;
+    case 32:
+        if (lanes == 8) return fn.template operator()<32, 8>(), true;
+        if (lanes == 16) return fn.template operator()<32, 16>(), true;
+        return false;
+    default:
+        if (lanes == 8) return fn.template operator()<64, 8>(), true;
+        if (lanes == 16) return fn.template operator()<64, 16>(), true;
+        return false;
     }
+}
+
+}  // namespace
+
+bool jacobi_variant_ok(int cls, int lanes)
+{
+    return dispatch(cls, lanes, [&]<int MP, int G>() {});
+}
+
+int jacobi_threads(int cls, int lanes)
+{
+    int t = 0;
+    dispatch(cls, lanes, [&]<int MP, int G>() { t = JacobiCfg<MP, G>::THREADS; });
+    return t;
 }
 
 hipError_t launch_jacobi(ssl_c64 *A, const int32_t *kstatus, int F, int M, int Ns, int max_sweeps,
-                         ssl_c64 *En, float *sigma, int32_t *bin_status, int32_t *conv,
+                         int lanes, ssl_c64 *En, float *sigma, int32_t *bin_status, int32_t *conv,
                          hipStream_t st)
 {
-    switch (jacobi_class(M)) {
-    case 8: return launch_cfg<8, 8>(A, kstatus, F, M, Ns, max_sweeps, En, sigma, bin_status, conv, st);
-    case 16: return launch_cfg<16, 16>(A, kstatus, F, M, Ns, max_sweeps, En, sigma, bin_status, conv, st);
-    case 32: return launch_cfg<32, 16>(A, kstatus, F, M, Ns, max_sweeps, En, sigma, bin_status, conv, st);
-    default: return launch_cfg<64, 16>(A, kstatus, F, M, Ns, max_sweeps, En, sigma, bin_status, conv, st);
-    }
+    hipError_t e = hipErrorInvalidValue;
+    dispatch(jacobi_class(M), lanes, [&]<int MP, int G>() {
+        e = launch_cfg<MP, G>(A, kstatus, F, M, Ns, max_sweeps, En, sigma, bin_status, conv, st);
+    });
+    return e;
 }
 
 hipError_t launch_jacobi_batch(const BlockDev *blk, const int2 *items, int n_items, int cls,
-                               int max_sweeps, unsigned int *queue, int grid, hipStream_t st)
+                               int lanes, int max_sweeps, unsigned int *queue, int grid,
+                               hipStream_t st)
 {
     if (n_items <= 0) return hipSuccess;
-    switch (cls) {
-    case 8: return launch_persistent<8, 8>(blk, items, n_items, max_sweeps, queue, grid, st);
-    case 16: return launch_persistent<16, 16>(blk, items, n_items, max_sweeps, queue, grid, st);
-    case 32: return launch_persistent<32, 16>(blk, items, n_items, max_sweeps, queue, grid, st);
-    default: return launch_persistent<64, 16>(blk, items, n_items, max_sweeps, queue, grid, st);
-    }
+    hipError_t e = hipErrorInvalidValue;
+    dispatch(cls, lanes, [&]<int MP, int G>() {
+        e = launch_persistent<MP, G>(blk, items, n_items, max_sweeps, queue, grid, st);
+    });
+    return e;
 }

@@ -53,6 +53,8 @@ struct ssl_ctx_s {
     };
     std::vector<GraphEntry> graphs;
     int cu_count = 0;
+    // Jacobi variant (lanes per column pair) per size class 8/16/32/64 channels
+    int jac_lanes[4] = {8, 16, 16, 16};
 };
 
 struct ssl_noise_s {
@@ -102,12 +104,14 @@ hipError_t launch_whiten_batch(const BlockDev *blk, const int2 *items, int n_ite
                                hipStream_t st);
 // Persistent: `grid` workgroups draw items from *queue (0 on entry, re-armed to 0 on exit).
 hipError_t launch_jacobi_batch(const BlockDev *blk, const int2 *items, int n_items, int cls,
-                               int max_sweeps, unsigned int *queue, int grid, hipStream_t st);
+                               int lanes, int max_sweeps, unsigned int *queue, int grid,
+                               hipStream_t st);
 hipError_t launch_steer_batch(const BlockDev *blk, const int2 *items, int n_items, int cls,
                               int max_dtiles, ssl_prec hprec, hipStream_t st);
 hipError_t launch_binsum_batch(const BlockDev *blk, int nblocks, int max_dchunks,
                                int max_fchunks, hipStream_t st);
-int jacobi_threads(int cls);
+int jacobi_threads(int cls, int lanes);
+inline int jacobi_class_index(int cls) { return cls == 8 ? 0 : cls == 16 ? 1 : cls == 32 ? 2 : 3; }
 int steer_rows_per_block();
 int binsum_threads();
 
@@ -123,9 +127,11 @@ hipError_t launch_noise_blend(ssl_c128 *K, const void *Khat, ssl_prec kprec, dou
 hipError_t launch_whiten(const ssl_c128 *Kinv, const ssl_c64 *R, ssl_c64 *A, int F, int M,
                          hipStream_t st);
 // A is library workspace and is overwritten (it parks the QR reflectors between phases).
+// lanes = lanes per column pair of the Jacobi variant (jacobi_variant_ok).
 hipError_t launch_jacobi(ssl_c64 *A, const int32_t *kstatus, int F, int M, int Ns,
-                         int max_sweeps, ssl_c64 *En, float *sigma, int32_t *bin_status,
-                         int32_t *conv, hipStream_t st);
+                         int max_sweeps, int lanes, ssl_c64 *En, float *sigma,
+                         int32_t *bin_status, int32_t *conv, hipStream_t st);
+bool jacobi_variant_ok(int cls, int lanes);
 hipError_t launch_steer(const void *H, ssl_prec hprec, const ssl_c64 *En, int F, int D, int M,
                         int Ns, int p, const int32_t *bin_status, float *P, hipStream_t st);
 hipError_t launch_binsum_peaks(const float *P, int F, int D, float *Pbar, float *part,

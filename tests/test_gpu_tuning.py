@@ -1,0 +1,117 @@
+"""Jacobi kernel variants (lanes per column pair) and the autotuner.
+
+Every variant meets the same parity bar against the oracle; the context's choice is applied to
+the single-block and batched entry points alike (bit-identical results); the autotuner returns an
+available variant, records it in the context and times every candidate.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import U32, projector, to_dev, to_host
+from test_gpu_parity import gsvd_case, set_noise
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = {8: (4, 8), 16: (4, 8, 16), 32: (8, 16), 60: (8, 16)}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    import paper_2504_03373_amd as S
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    S.lib()
+    return S
+
+
+@pytest.mark.parametrize("M", sorted(VARIANTS))
+def test_every_variant_meets_parity(S, M):
+    import torch
+    ctx = S.ssl_ctx_create(0, 0)
+    F, Ns = 13, 2
+    R, K = gsvd_case(M, F, Ns, seed=700 + M)
+    En_ref, sig_ref, st_ref, _ = oracle.gsvd(K, R, Ns)
+    n, _ = set_noise(S, ctx, K)
+    for lanes in VARIANTS[M]:
+        say(f"ssl_gsvd M={M} lanes={lanes}")
+        S.ssl_ctx_set_jacobi_lanes(ctx, M, lanes)
+        assert S.ssl_ctx_get_jacobi_lanes(ctx, M) == lanes
+        En = torch.zeros((F, M - Ns, M), dtype=torch.complex64, device="cuda:0")
+        sig = torch.zeros((F, M), dtype=torch.float32, device="cuda:0")
+        st = torch.zeros(F, dtype=torch.int32, device="cuda:0")
+        S.ssl_gsvd(ctx, to_dev(R.astype(np.complex64)), n, Ns, En, sig, st)
+        En, sig, st = to_host(En), to_host(sig), to_host(st)
+        assert np.all(st == 0)
+        for f in range(F):
+            nA = np.linalg.norm(np.linalg.solve(K[f], R[f]))
+            gap = sig_ref[f, Ns - 1] - sig_ref[f, Ns]
+            err = np.linalg.norm(projector(En[f].T.astype(np.complex128)) - projector(En_ref[f].T), 2)
+            assert err <= 16 * M * U32 * nA / gap
+            assert np.max(np.abs(sig[f] - sig_ref[f])) <= 8 * M * U32 * nA
+    S.ssl_noise_destroy(n)
+    S.ssl_ctx_destroy(ctx)
+
+
+def test_unavailable_variant_rejected(S):
+    ctx = S.ssl_ctx_create(0, 0)
+    with pytest.raises(S.SSLError):
+        S.ssl_ctx_set_jacobi_lanes(ctx, 60, 4)
+    with pytest.raises(S.SSLError):
+        S.ssl_ctx_set_jacobi_lanes(ctx, 8, 16)
+    assert S.ssl_ctx_get_jacobi_lanes(ctx, 60) == 16
+    S.ssl_ctx_destroy(ctx)
+
+
+def test_autotune_picks_and_applies(S):
+    ctx = S.ssl_ctx_create(0, 0)
+    F, M, Ns = 514, 60, 2
+    R, K = gsvd_case(M, F, Ns, seed=801)
+    n, _ = set_noise(S, ctx, K)
+    say("ssl_autotune_jacobi M=60 F=514")
+    best, ms = S.ssl_autotune_jacobi(ctx, to_dev(R.astype(np.complex64)), n, Ns, reps=2)
+    say(f"  best lanes {best}, ms {ms}")
+    assert best in VARIANTS[60] and set(ms) == set(VARIANTS[60])
+    assert ms[best] == min(ms.values())
+    assert S.ssl_ctx_get_jacobi_lanes(ctx, M) == best
+    S.ssl_noise_destroy(n)
+    S.ssl_ctx_destroy(ctx)
+
+
+def test_variant_applies_to_batch_and_single(S):
+    """With the non-default variant selected, batched and single-block outputs stay bit-identical."""
+    import torch
+    import synth
+    ctx = S.ssl_ctx_create(0, 0)
+    S.ssl_ctx_set_jacobi_lanes(ctx, 60, 8)
+    w = synth.workload_paper(n_blocks=4)
+    Xn = w.noise_frames()
+    Kd = torch.zeros((w.F, w.M, w.M), dtype=torch.complex128, device="cuda:0")
+    S.ssl_corr_accum(ctx, to_dev(Xn), 1.0 / Xn.shape[1], 0, S.SSL_FP64, Kd)
+    n = S.ssl_noise_create(ctx, w.F, w.M)
+    S.ssl_noise_set(n, Kd, S.SSL_FP64)
+    Hd = to_dev(w.steering_table())
+    Xs = [to_dev(w.block(b)[0]) for b in range(3)]
+    mk = lambda: (torch.zeros(w.Ns, dtype=torch.int32, device="cuda:0"),
+                  torch.zeros(w.Ns, dtype=torch.float32, device="cuda:0"),
+                  torch.zeros(w.D, dtype=torch.float32, device="cuda:0"))
+    single = []
+    for X in Xs:
+        pk, pv, pb = mk()
+        S.ssl_localize(ctx, X, n, Hd, S.SSL_FP32, 72, 19, w.Ns, 2, pk, pv, pb)
+        single.append((to_host(pk), to_host(pb)))
+    outs = [mk() for _ in Xs]
+    say("ssl_localize_batch with lanes=8")
+    S.ssl_localize_batch(ctx, [S.block_desc(X, n, Hd, 72, 19, w.Ns, o[0], o[1], o[2]) for X, o in zip(Xs, outs)],
+                         S.SSL_FP32, 2)
+    for (pk, pb), o in zip(single, outs):
+        assert np.array_equal(pk, to_host(o[0])) and np.array_equal(pb, to_host(o[2]))
+    S.ssl_noise_destroy(n)
+    S.ssl_ctx_destroy(ctx)
