@@ -59,6 +59,12 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one device copy of this size first (HBM counter calibration)")
+    ap.add_argument("--serve-seconds", type=float, default=2.0,
+                    help="duration of emitted traffic in the serving phase (0 = skip)")
+    ap.add_argument("--serve-streams", type=int, default=64)
+    ap.add_argument("--serve-period-ms", type=float, default=10.0, help="mean block period per stream")
+    ap.add_argument("--serve-budget-gb", type=float, default=4.0, help="HBM budget of in-flight work")
+    ap.add_argument("--k-update-every", type=int, default=1)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -216,9 +222,9 @@ def main() -> int:
         "graph_value": round(graph_value, 2),
         "per_block": {"value": round(per_block, 2), "unit": "blocks/s",
                       "path": "ssl_localize, one block per call"},
-        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
-                       "p99": round(float(np.percentile(lat, 99)), 4),
-                       "kind": f"device time of one {B}-block step"},
+        "step_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                    "p99": round(float(np.percentile(lat, 99)), 4),
+                    "kind": f"device time of one {B}-block step"},
         "dominant_kernel": dom,
         "kernels": kernels,
         "roofline": roofline,
@@ -227,6 +233,38 @@ def main() -> int:
         "status_ok": status_ok,
         "input_gen_s": round(gen_s, 2),
     }
+
+    if args.serve_seconds > 0:
+        from paper_2504_03373_amd.serving import GpuExecutor, Server
+        streams = synth.serving_streams(n_streams=args.serve_streams)
+        Hs = {}
+        for s in streams:
+            if s.M not in Hs:
+                h = torch.from_numpy(synth.steering_table(s.pos, s.grid, s.freqs)).to(dev)
+                if prec != S.SSL_FP32:
+                    h = torch.view_as_real(h).reshape(s.F, s.D, 2 * s.M).to(
+                        torch.bfloat16 if prec == S.SSL_BF16 else torch.float16).contiguous()
+                Hs[s.M] = h
+        budget = int(args.serve_budget_gb * (1 << 30))
+        ex = GpuExecutor(streams, Hs, prec=prec, alpha=0.95, k_update_every=args.k_update_every,
+                         hbm_budget_bytes=budget, lanes=2, pool=4)
+        srv = Server(ex, budget, max_batch=128)
+        srv.run(synth.poisson_arrivals(len(streams), 0.1, args.serve_period_ms * 1e-3, seed=7))
+        arrivals = synth.poisson_arrivals(len(streams), args.serve_seconds,
+                                          args.serve_period_ms * 1e-3)
+        sv = srv.run(arrivals)
+        ex.close()
+        mix = {m: sum(1 for s in streams if s.M == m) for m in sorted({s.M for s in streams})}
+        out["serving"] = {
+            "streams": len(streams), "streams_by_M": mix,
+            "offered_blocks_per_s": round(len(arrivals) / args.serve_seconds, 1),
+            "completed": sv["completed"], "blocks_per_s": round(sv["blocks_per_s"], 1),
+            "p50_ms": round(sv["p50_ms"], 3), "p99_ms": round(sv["p99_ms"], 3),
+            "max_ms": round(sv["max_ms"], 3), "mean_batch": round(sv["mean_batch"], 2),
+            "max_queue": sv["max_queue"], "k_update_every": args.k_update_every,
+            "hbm_budget_gb": args.serve_budget_gb, "emitted_seconds": args.serve_seconds}
+        out["latency_ms"] = {"p50": round(sv["p50_ms"], 3), "p99": round(sv["p99_ms"], 3),
+                             "kind": "served: emission to peaks on the host"}
 
     if not args.no_cpu:
         import oracle

@@ -76,7 +76,7 @@ size_t ssl_ctx_workspace_bytes(ssl_ctx ctx);
  * are host arrays of SSL_K_COUNT entries. */
 typedef enum {
     SSL_K_CORR = 0,     /* correlation accumulation (eq.2-3) */
-    SSL_K_NOISE = 1,    /* noise load / blend / FP64 Cholesky + inverse */
+    SSL_K_NOISE = 1,    /* noise load / blend / FP64 inversion */
     SSL_K_WHITEN = 2,   /* A = K^{-1} R (FP64) */
     SSL_K_JACOBI = 3,   /* one-sided Jacobi SVD + sort + E_n */
     SSL_K_STEER = 4,    /* H^H E_n projection and P (eq.5) */
@@ -111,8 +111,10 @@ ssl_status ssl_corr_accum(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int M, in
  * whitening product.  Owned by the library; destroy with ssl_noise_destroy. */
 ssl_status ssl_noise_create(ssl_ctx ctx, int F, int M, ssl_noise *out);
 /* Copies K ([F][M][M]; ssl_c128 if kprec == SSL_FP64, ssl_c64 if SSL_FP32) into the handle and
- * factors it in FP64: K = L L^H per bin, then K^{-1} = L^{-H} L^{-1}.  Per-bin result in
- * bin_status ([F] int32, may be NULL): SSL_BIN_OK or SSL_BIN_NOT_PD. */
+ * inverts it per bin in FP64 by Gauss-Jordan elimination (the paper's method for K^{-1}); without
+ * pivoting on a Hermitian positive definite K the elimination pivots are the Cholesky pivots
+ * d_k = L_kk^2, which give the positive-definiteness test.  Per-bin result in bin_status ([F]
+ * int32, may be NULL): SSL_BIN_OK or SSL_BIN_NOT_PD. */
 ssl_status ssl_noise_set(ssl_noise K, const void *Kin, ssl_prec kprec, int32_t *bin_status,
                          void *stream);
 /* Exponential averaging for streams whose noise field drifts:

@@ -2,125 +2,94 @@
 //
 // The paper inverts the preset noise correlation K by Gaussian elimination and then forms
 // A = K^{-1} R with a matrix product (Sec. III-B).  K is Hermitian positive definite and fixed per
-// stream, so here it is factored once per noise set with a complex Cholesky K = L L^H (the
-// pivots double as the positive-definiteness test), inverted as K^{-1} = L^{-H} L^{-1}, and kept
-// resident; each block then needs only the FP64 product A = K^{-1} R, rounded to complex64 for the
-// FP32 Jacobi SVD.
+// stream (or slowly updated), so here K^{-1} is computed once per noise set by in-place
+// Gauss-Jordan elimination in FP64 and kept resident; each block then needs only the FP64 product
+// A = K^{-1} R, rounded to complex64 for the FP32 Jacobi SVD.  Without pivoting on a Hermitian
+// positive definite matrix the elimination pivots are the Schur-complement diagonals, i.e. the
+// squared diagonal of the Cholesky factor, so they double as the positive-definiteness test.
 #include "ssl_internal.h"
 
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kFactorThreads = 512;
 constexpr double kPdRel = 9.094947017729282e-13;   // 2^-40: pivot floor relative to max_i K_ii
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b)
 {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
-// a * conj(b)
-__device__ __forceinline__ double2 cmulc(double2 a, double2 b)
-{
-    return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
-}
 
-// One workgroup per bin.  L (then L^{-1}) lives in LDS; both use MP x MP complex128 slots.
+// One workgroup per bin; the whole MP x MP complex128 matrix in LDS (64 KB at MP = 64).
+// Step k with pivot p = W_kk (real for Hermitian input):
+//   W_ij -= W_ik W_kj / p (i, j != k);  W_kj /= p;  W_ik = -W_ik / p;  W_kk = 1 / p.
+// After M steps W = K^{-1}.  A pivot p <= 2^-40 max_i K_ii (or non-finite) marks the bin NOT_PD.
 template <int MP>
-__global__ __launch_bounds__(kThreads) void noise_factor(const double2 *__restrict__ K,
-                                                         double2 *__restrict__ Kinv,
-                                                         int32_t *__restrict__ status, int M)
+__global__ __launch_bounds__(kFactorThreads) void noise_factor(const double2 *__restrict__ K,
+                                                               double2 *__restrict__ Kinv,
+                                                               int32_t *__restrict__ status,
+                                                               int M)
 {
-    __shared__ double2 L[MP * MP];
-    __shared__ double2 Y[MP * MP];
-    __shared__ int bad;
-    __shared__ double dmax_s;
+    __shared__ double2 W[MP * MP];
+    __shared__ double thr_s;
+    __shared__ int bad_s;
     const int f = blockIdx.x;
     const int tid = threadIdx.x;
     const double2 *Kf = K + (size_t)f * M * M;
     double2 *Wf = Kinv + (size_t)f * M * M;
 
-    for (int e = tid; e < M * M; e += kThreads) {
+    for (int e = tid; e < M * M; e += kFactorThreads) {
         const int i = e / M, j = e - i * M;
-        L[i * MP + j] = Kf[e];
-        Y[i * MP + j] = make_double2(0.0, 0.0);
+        W[i * MP + j] = Kf[e];
     }
-    if (tid == 0) bad = 0;
     __syncthreads();
     if (tid == 0) {
         double dm = 0.0;
-        for (int i = 0; i < M; ++i) dm = fmax(dm, L[i * MP + i].x);
-        dmax_s = dm;
-        if (!(dm > 0.0) || !isfinite(dm)) bad = 1;
+        bool fin = true;
+        for (int i = 0; i < M; ++i) {
+            const double d = W[i * MP + i].x;
+            fin = fin && isfinite(d);
+            dm = fmax(dm, d);
+        }
+        bad_s = (!(dm > 0.0) || !isfinite(dm) || !fin) ? 1 : 0;
+        thr_s = kPdRel * dm;
     }
     __syncthreads();
-    // right-looking Cholesky on the lower triangle
+    bool bad = bad_s != 0;
+    const double thr = thr_s;
     for (int k = 0; k < M && !bad; ++k) {
-        if (tid == 0) {
-            const double d = L[k * MP + k].x;
-            if (!isfinite(d) || d <= kPdRel * dmax_s) {
-                bad = 1;
+        const double p = W[k * MP + k].x;             // every thread reads the same pivot
+        if (!isfinite(p) || p <= thr) {
+            bad = true;
+            break;
+        }
+        const double ip = 1.0 / p;
+        for (int e = tid; e < M * M; e += kFactorThreads) {
+            const int i = e / M, j = e - i * M;
+            if (i == k || j == k) continue;
+            const double2 t = cmul(W[i * MP + k], W[k * MP + j]);
+            double2 w = W[i * MP + j];
+            w.x = fma(-t.x, ip, w.x);
+            w.y = fma(-t.y, ip, w.y);
+            W[i * MP + j] = w;
+        }
+        __syncthreads();
+        for (int e = tid; e < M; e += kFactorThreads) {
+            if (e == k) {
+                W[k * MP + k] = make_double2(ip, 0.0);
             } else {
-                L[k * MP + k] = make_double2(sqrt(d), 0.0);
+                const double2 r = W[k * MP + e], c = W[e * MP + k];
+                W[k * MP + e] = make_double2(r.x * ip, r.y * ip);
+                W[e * MP + k] = make_double2(-c.x * ip, -c.y * ip);
             }
         }
         __syncthreads();
-        if (bad) break;
-        const double inv = 1.0 / L[k * MP + k].x;
-        for (int i = k + 1 + tid; i < M; i += kThreads) {
-            double2 v = L[i * MP + k];
-            L[i * MP + k] = make_double2(v.x * inv, v.y * inv);
-        }
-        __syncthreads();
-        // trailing update of the lower triangle: L_ij -= L_ik conj(L_jk), k < j <= i
-        const int n = M - k - 1;
-        for (int e = tid; e < n * n; e += kThreads) {
-            const int i = k + 1 + e / n, j = k + 1 + e % n;
-            if (j > i) continue;
-            const double2 p = cmulc(L[i * MP + k], L[j * MP + k]);
-            double2 v = L[i * MP + j];
-            L[i * MP + j] = make_double2(v.x - p.x, v.y - p.y);
-        }
-        __syncthreads();
     }
-    if (bad) {
-        for (int e = tid; e < M * M; e += kThreads) Wf[e] = make_double2(0.0, 0.0);
-        if (tid == 0) status[f] = SSL_BIN_NOT_PD;
-        return;
+    for (int e = tid; e < M * M; e += kFactorThreads) {
+        const int i = e / M, j = e - i * M;
+        Wf[e] = bad ? make_double2(0.0, 0.0) : W[i * MP + j];
     }
-    // Y = L^{-1}: row by row, Y_ic = (delta_ic - sum_{c<=k<i} L_ik Y_kc) / L_ii, columns in parallel
-    for (int i = 0; i < M; ++i) {
-        const double linv = 1.0 / L[i * MP + i].x;
-        for (int c = tid; c <= i; c += kThreads) {
-            double2 s = make_double2(c == i ? 1.0 : 0.0, 0.0);
-            for (int k = c; k < i; ++k) {
-                const double2 p = cmul(L[i * MP + k], Y[k * MP + c]);
-                s.x -= p.x;
-                s.y -= p.y;
-            }
-            Y[i * MP + c] = make_double2(s.x * linv, s.y * linv);
-        }
-        __syncthreads();
-    }
-    // K^{-1} = Y^H Y: W_ij = sum_{k >= max(i,j)} conj(Y_ki) Y_kj; upper triangle computed once,
-    // the lower written as its conjugate (exactly Hermitian, real diagonal)
-    const int nent = M * (M + 1) / 2;
-    for (int e0 = tid; e0 < nent; e0 += kThreads) {
-        int e = e0, i = 0;
-        while (e >= M - i) { e -= M - i; ++i; }
-        const int j = i + e;
-        double2 s = make_double2(0.0, 0.0);
-        for (int k = j; k < M; ++k) {
-            const double2 p = cmulc(Y[k * MP + j], Y[k * MP + i]);   // Y_kj conj(Y_ki)
-            s.x += p.x;
-            s.y += p.y;
-        }
-        if (i == j) {
-            Wf[(size_t)i * M + i] = make_double2(s.x, 0.0);
-        } else {
-            Wf[(size_t)i * M + j] = s;
-            Wf[(size_t)j * M + i] = make_double2(s.x, -s.y);
-        }
-    }
-    if (tid == 0) status[f] = SSL_BIN_OK;
+    if (tid == 0) status[f] = bad ? SSL_BIN_NOT_PD : SSL_BIN_OK;
 }
 
 // K <- alpha K + (1 - alpha) Khat
@@ -238,6 +207,8 @@ __global__ __launch_bounds__(kThreads) void whiten_batch(const BlockDev *__restr
     whiten_bin<MP>(B.Kinv + o, B.R + o, B.A + o, B.M);
 }
 
+int grid_for(size_t n) { return (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096); }
+
 }  // namespace
 
 hipError_t launch_noise_factor(ssl_c128 *K, ssl_c128 *Kinv, int32_t *status, int F, int M,
@@ -246,11 +217,11 @@ hipError_t launch_noise_factor(ssl_c128 *K, ssl_c128 *Kinv, int32_t *status, int
     const double2 *Kp = reinterpret_cast<const double2 *>(K);
     double2 *Wp = reinterpret_cast<double2 *>(Kinv);
     if (M <= 16)
-        hipLaunchKernelGGL(noise_factor<16>, dim3(F), dim3(kThreads), 0, st, Kp, Wp, status, M);
+        hipLaunchKernelGGL(noise_factor<16>, dim3(F), dim3(kFactorThreads), 0, st, Kp, Wp, status, M);
     else if (M <= 32)
-        hipLaunchKernelGGL(noise_factor<32>, dim3(F), dim3(kThreads), 0, st, Kp, Wp, status, M);
+        hipLaunchKernelGGL(noise_factor<32>, dim3(F), dim3(kFactorThreads), 0, st, Kp, Wp, status, M);
     else
-        hipLaunchKernelGGL(noise_factor<64>, dim3(F), dim3(kThreads), 0, st, Kp, Wp, status, M);
+        hipLaunchKernelGGL(noise_factor<64>, dim3(F), dim3(kFactorThreads), 0, st, Kp, Wp, status, M);
     return hipGetLastError();
 }
 
@@ -258,12 +229,11 @@ hipError_t launch_noise_load(ssl_c128 *K, const void *Kin, ssl_prec kprec, int F
                              hipStream_t st)
 {
     const size_t n = (size_t)F * M * M;
-    const int blocks = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
     if (kprec == SSL_FP64)
-        hipLaunchKernelGGL(noise_load_c128, dim3(blocks), dim3(256), 0, st,
+        hipLaunchKernelGGL(noise_load_c128, dim3(grid_for(n)), dim3(256), 0, st,
                            reinterpret_cast<double2 *>(K), static_cast<const double2 *>(Kin), n);
     else
-        hipLaunchKernelGGL(noise_load_c64, dim3(blocks), dim3(256), 0, st,
+        hipLaunchKernelGGL(noise_load_c64, dim3(grid_for(n)), dim3(256), 0, st,
                            reinterpret_cast<double2 *>(K), static_cast<const float2 *>(Kin), n);
     return hipGetLastError();
 }
@@ -272,13 +242,12 @@ hipError_t launch_noise_blend(ssl_c128 *K, const void *Khat, ssl_prec kprec, dou
                               int M, hipStream_t st)
 {
     const size_t n = (size_t)F * M * M;
-    const int blocks = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
     if (kprec == SSL_FP64)
-        hipLaunchKernelGGL(noise_blend_c128, dim3(blocks), dim3(256), 0, st,
+        hipLaunchKernelGGL(noise_blend_c128, dim3(grid_for(n)), dim3(256), 0, st,
                            reinterpret_cast<double2 *>(K), static_cast<const double2 *>(Khat),
                            alpha, n);
     else
-        hipLaunchKernelGGL(noise_blend_c64, dim3(blocks), dim3(256), 0, st,
+        hipLaunchKernelGGL(noise_blend_c64, dim3(grid_for(n)), dim3(256), 0, st,
                            reinterpret_cast<double2 *>(K), static_cast<const float2 *>(Khat),
                            alpha, n);
     return hipGetLastError();

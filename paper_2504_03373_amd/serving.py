@@ -1,0 +1,261 @@
+"""Continuous-batching localization server for many microphone-array streams.
+
+Blocks arrive from array streams of different channel counts.  The scheduler admits them as
+lanes and HBM budget free up, packs every admitted block into the next batch on a free lane (a
+lane = a library context + a HIP stream, so a batch can be formed and started while another runs
+on the device), and records each block's latency from emission to results on the host.  Each
+stream's noise correlation K stays resident on the device and is updated by exponential averaging
+with the noise-only frames that accompany its blocks (K <- alpha K + (1 - alpha) K_hat, then a
+fresh FP64 inverse), the update of block n landing before the stream's block n + 1 runs.
+
+Rules: at most one block per stream is in flight (keeps per-stream order and the K update
+sequence exact); a lane's batch never needs more than its share of the HBM budget; requests wait
+in arrival order, skipping only blocks of streams that are still in flight.
+
+The executor interface (`lanes`, `cost_bytes`, `submit`, `poll`, `collect`) is what the scheduler
+needs; `GpuExecutor` implements it with the library's C ABI.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Callable, List, Sequence
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Request:
+    stream: int
+    seq: int
+    emit_t: float
+    submit_t: float = -1.0
+    done_t: float = -1.0
+    batch: int = -1
+    k_version: int = -1          # EMA updates applied to the stream's K before this block ran
+    peaks: np.ndarray = None
+    peak_val: np.ndarray = None
+
+
+class Server:
+    def __init__(self, executor, hbm_budget_bytes: int, max_batch: int = 64,
+                 clock: Callable[[], float] = time.perf_counter,
+                 sleep: Callable[[float], None] = time.sleep, poll_s: float = 50e-6):
+        self.ex = executor
+        self.lane_budget = hbm_budget_bytes // max(1, executor.lanes)
+        self.max_batch = max_batch
+        self.clock = clock
+        self.sleep = sleep
+        self.poll_s = poll_s
+
+    def run(self, arrivals: Sequence[tuple]) -> dict:
+        """arrivals: (emit time s, stream, seq), sorted by time.  Runs until every block is done."""
+        pending = collections.deque(Request(stream=s, seq=q, emit_t=t) for t, s, q in arrivals)
+        ready: List[Request] = []
+        busy_streams = set()
+        lanes = [None] * self.ex.lanes          # per lane: list of requests in flight
+        done: List[Request] = []
+        batches = 0
+        max_ready = 0
+        t0 = self.clock()
+        while pending or ready or any(lanes):
+            now = self.clock() - t0
+            while pending and pending[0].emit_t <= now:
+                ready.append(pending.popleft())
+            max_ready = max(max_ready, len(ready))
+            progressed = False
+            for li, reqs in enumerate(lanes):
+                if reqs and self.ex.poll(li):
+                    self.ex.collect(li)
+                    tdone = self.clock() - t0
+                    for r in reqs:
+                        r.done_t = tdone
+                        busy_streams.discard(r.stream)
+                    done.extend(reqs)
+                    lanes[li] = None
+                    progressed = True
+            for li in range(len(lanes)):
+                if lanes[li] is not None or not ready:
+                    continue
+                batch, cost, keep = [], 0, []
+                for r in ready:
+                    c = self.ex.cost_bytes(r.stream)
+                    if (len(batch) < self.max_batch and r.stream not in busy_streams
+                            and cost + c <= self.lane_budget):
+                        batch.append(r)
+                        busy_streams.add(r.stream)
+                        cost += c
+                    else:
+                        keep.append(r)
+                if not batch:
+                    if not any(lanes) and ready and all(self.ex.cost_bytes(r.stream) > self.lane_budget
+                                                        for r in ready):
+                        raise RuntimeError("a single block exceeds the per-lane HBM budget")
+                    break
+                ready = keep
+                tsub = self.clock() - t0
+                for r in batch:
+                    r.submit_t = tsub
+                    r.batch = batches
+                self.ex.submit(li, batch)
+                lanes[li] = batch
+                batches += 1
+                progressed = True
+            if not progressed:
+                nxt = pending[0].emit_t - (self.clock() - t0) if pending else self.poll_s
+                self.sleep(max(0.0, min(self.poll_s, nxt)))
+        return summarize(done, batches, max_ready)
+
+
+def summarize(done: List[Request], batches: int, max_ready: int) -> dict:
+    lat = np.array([r.done_t - r.emit_t for r in done]) * 1e3
+    if len(done) == 0:
+        return dict(completed=0)
+    span = max(r.done_t for r in done) - min(r.emit_t for r in done)
+    return dict(completed=len(done), blocks_per_s=len(done) / span if span > 0 else float("inf"),
+                p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                max_ms=float(lat.max()), batches=batches, mean_batch=len(done) / max(1, batches),
+                max_queue=max_ready, requests=done)
+
+
+# ------------------------------------------------------------------------------------------------
+class GpuExecutor:
+    """Executes batches with ssl_localize_batch on `lanes` (context, HIP stream) pairs; per-stream
+    noise handles, device input slots and pinned host pools of pre-generated blocks.
+
+    streams: objects with M, F, T, Ns, D, grid (n_az, n_el), `pos`, `freqs`, initial_noise_frames()
+    and block(seq) -> (X, noise-only frames); `pool` blocks per stream are generated up front and
+    reused cyclically (block seq uses pool entry seq % pool).
+    """
+
+    def __init__(self, streams, steering, prec=None, p: int = 2, alpha: float = 0.95,
+                 k_update_every: int = 1, hbm_budget_bytes: int = 4 << 30, lanes: int = 2,
+                 pool: int = 4, device: int = 0):
+        import torch
+
+        from . import (SSL_FP32, SSL_FP64, block_desc, ssl_corr_accum, ssl_ctx_create,
+                       ssl_noise_create, ssl_noise_set)
+        self.torch = torch
+        self.dev = f"cuda:{device}"
+        self.prec = SSL_FP32 if prec is None else prec
+        self.p = p
+        self.alpha = alpha
+        self.k_every = max(1, k_update_every)
+        self.lanes = lanes
+        self.streams = list(streams)
+        self.pool = pool
+        self._block_desc = block_desc
+        self._fp64 = SSL_FP64
+        from . import ssl_ctx_use_graphs
+        self.ctxs = [ssl_ctx_create(device, hbm_budget_bytes // lanes) for _ in range(lanes)]
+        for c in self.ctxs:
+            # every batch has a different composition: capture would never be replayed
+            ssl_ctx_use_graphs(c, False)
+        self.nctx = ssl_ctx_create(device, 0)
+        self.tstreams = [torch.cuda.Stream(device=self.dev) for _ in range(lanes)]
+        self.nstream = torch.cuda.Stream(device=self.dev)
+        self.noise_event = None
+        # steering tables per channel count (shared by streams of the same geometry)
+        self.H = {M: t for M, t in steering.items()}
+        self.noise, self.X_slot, self.Xn_slot, self.X_pool, self.Xn_pool = [], [], [], [], []
+        self.k_version = [0] * len(self.streams)
+        Mmax = max(s.M for s in self.streams)
+        Fmax = max(s.F for s in self.streams)
+        self.Khat = torch.zeros((Fmax * Mmax * Mmax,), dtype=torch.complex128, device=self.dev)
+        for s in self.streams:
+            Xn0 = torch.from_numpy(s.initial_noise_frames()).to(self.dev)
+            K0 = torch.zeros((s.F, s.M, s.M), dtype=torch.complex128, device=self.dev)
+            ssl_corr_accum(self.nctx, Xn0, 1.0 / Xn0.shape[1], 0, SSL_FP64, K0)
+            n = ssl_noise_create(self.nctx, s.F, s.M)
+            ssl_noise_set(n, K0, SSL_FP64)
+            self.noise.append(n)
+            xs, xns = [], []
+            for q in range(pool):
+                X, Xn = s.block(q)
+                xs.append(torch.from_numpy(X).pin_memory())
+                xns.append(torch.from_numpy(Xn).pin_memory())
+            self.X_pool.append(xs)
+            self.Xn_pool.append(xns)
+            self.X_slot.append(torch.empty((s.F, s.T, s.M), dtype=torch.complex64, device=self.dev))
+            self.Xn_slot.append(torch.empty((s.F, s.T, s.M), dtype=torch.complex64, device=self.dev))
+        torch.cuda.synchronize()
+        nmax = 4096
+        self.pk = [torch.zeros((nmax, 3), dtype=torch.int32, device=self.dev) for _ in range(lanes)]
+        self.pv = [torch.zeros((nmax, 3), dtype=torch.float32, device=self.dev) for _ in range(lanes)]
+        self.pk_h = [torch.zeros((nmax, 3), dtype=torch.int32).pin_memory() for _ in range(lanes)]
+        self.pv_h = [torch.zeros((nmax, 3), dtype=torch.float32).pin_memory() for _ in range(lanes)]
+        self.inflight = [None] * lanes
+
+    def cost_bytes(self, sid: int) -> int:
+        """Device bytes a block holds while in flight: its batch workspace slices (the same sizes
+        ssl_localize_batch reserves) plus its input slots."""
+        s = self.streams[sid]
+        a = lambda n: (n + 255) // 256 * 256
+        F, M, D, Nn = s.F, s.M, s.D, s.M - s.Ns
+        ws = (2 * a(F * M * M * 8) + a(F * Nn * M * 8) + a(F * D * 4) + a(-(-F // 16) * D * 4)
+              + a(F * 4) + a(D * 4))
+        return ws + 2 * F * s.T * M * 8
+
+    def submit(self, lane: int, reqs: List["Request"]) -> None:
+        from . import ssl_localize_batch
+        torch = self.torch
+        st = self.tstreams[lane]
+        descs = []
+        with torch.cuda.stream(st):
+            if self.noise_event is not None:
+                st.wait_event(self.noise_event)
+            for i, r in enumerate(reqs):
+                s = self.streams[r.stream]
+                self.X_slot[r.stream].copy_(self.X_pool[r.stream][r.seq % self.pool], non_blocking=True)
+                descs.append(self._block_desc(self.X_slot[r.stream], self.noise[r.stream], self.H[s.M],
+                                              s.grid.n_az, s.grid.n_el, s.Ns, self.pk[lane][i],
+                                              self.pv[lane][i]))
+                r.k_version = self.k_version[r.stream]
+            ssl_localize_batch(self.ctxs[lane], descs, self.prec, self.p, stream=st)
+            n = len(reqs)
+            self.pk_h[lane][:n].copy_(self.pk[lane][:n], non_blocking=True)
+            self.pv_h[lane][:n].copy_(self.pv[lane][:n], non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        self.inflight[lane] = (reqs, ev)
+
+    def poll(self, lane: int) -> bool:
+        return self.inflight[lane][1].query()
+
+    def collect(self, lane: int) -> None:
+        from . import ssl_corr_accum, ssl_noise_update
+        torch = self.torch
+        reqs, ev = self.inflight[lane]
+        ev.synchronize()
+        pk, pv = self.pk_h[lane].numpy(), self.pv_h[lane].numpy()
+        for i, r in enumerate(reqs):
+            ns = self.streams[r.stream].Ns
+            r.peaks = pk[i, :ns].copy()
+            r.peak_val = pv[i, :ns].copy()
+        # K EMA updates of this batch's streams, after the batch (which read the old K)
+        ups = [r for r in reqs if (r.seq + 1) % self.k_every == 0]
+        if ups:
+            with torch.cuda.stream(self.nstream):
+                self.nstream.wait_event(ev)
+                for r in ups:
+                    s = self.streams[r.stream]
+                    xn = self.Xn_slot[r.stream]
+                    xn.copy_(self.Xn_pool[r.stream][r.seq % self.pool], non_blocking=True)
+                    Kh = self.Khat[: s.F * s.M * s.M].view(s.F, s.M, s.M)
+                    ssl_corr_accum(self.nctx, xn, 1.0 / s.T, 0, self._fp64, Kh, stream=self.nstream)
+                    ssl_noise_update(self.noise[r.stream], Kh, self._fp64, self.alpha,
+                                     stream=self.nstream)
+                    self.k_version[r.stream] += 1
+                self.noise_event = torch.cuda.Event()
+                self.noise_event.record(self.nstream)
+        self.inflight[lane] = None
+
+    def close(self) -> None:
+        from . import ssl_ctx_destroy, ssl_noise_destroy
+        self.torch.cuda.synchronize()
+        for n in self.noise:
+            ssl_noise_destroy(n)
+        for c in self.ctxs:
+            ssl_ctx_destroy(c)
+        ssl_ctx_destroy(self.nctx)

@@ -236,6 +236,92 @@ def workload_paper(n_blocks: int = 1000, seed: int = 1002, M: int = 60, F: int =
                     max_src_el=80.0, seed=seed)
 
 
+@dataclasses.dataclass
+class ArrayStream:
+    """One simulated array stream for the serving workload: fixed geometry and noise field,
+    sources whose azimuths random-walk by +-2 degrees per block (off-grid), el fixed per source."""
+    sid: int
+    M: int
+    F: int
+    T: int
+    Ns: int
+    grid: DirectionGrid
+    pos: np.ndarray
+    freqs: np.ndarray
+    noise_u: list
+    p_noise: list
+    sigma_d2: float
+    snr_db: float
+    src_az0: list
+    src_el: list
+    seed: int
+
+    @property
+    def D(self) -> int:
+        return self.grid.D
+
+    def source_azimuths(self, seq: int) -> list:
+        """Azimuths (degrees) of the sources in block `seq` (random walk from the start angles)."""
+        rng = np.random.default_rng(np.random.SeedSequence(self.seed).spawn(3)[2])
+        steps = rng.choice([-2.0, 2.0], size=(seq + 1, self.Ns))
+        steps[0] = 0.0
+        return list((np.asarray(self.src_az0) + np.cumsum(steps, axis=0)[seq]) % 360.0)
+
+    def block(self, seq: int):
+        """(X [F][T][M], noise-only frames [F][T][M]) of block `seq`, both complex64."""
+        rng = np.random.default_rng(np.random.SeedSequence(self.seed).spawn(2)[1].spawn(seq + 1)[seq])
+        az = self.source_azimuths(seq)
+        src_u = [unit_vector(a, e) for a, e in zip(az, self.src_el)]
+        p_s = (self.sigma_d2 + sum(self.p_noise)) * 10.0 ** (self.snr_db / 10.0)
+        X = mix(rng, self.pos, self.freqs, self.T, src_u, [p_s] * self.Ns, self.noise_u,
+                self.p_noise, self.sigma_d2)
+        Xn = mix(rng, self.pos, self.freqs, self.T, [], [], self.noise_u, self.p_noise, self.sigma_d2)
+        return X, Xn
+
+    def initial_noise_frames(self) -> np.ndarray:
+        """4M noise-only frames for the stream's first K."""
+        rng = np.random.default_rng(np.random.SeedSequence(self.seed).spawn(1)[0])
+        return mix(rng, self.pos, self.freqs, 4 * self.M, [], [], self.noise_u, self.p_noise,
+                   self.sigma_d2)
+
+
+def serving_streams(n_streams: int = 64, seed: int = 1005, Ms=(8, 16, 60)):
+    """Array streams of the serving workload: M drawn uniformly from Ms (Ns = 2 for 60 mics,
+    1 otherwise), 257 bins, T = 50, 1368-direction grid, two directional noises + white noise,
+    SNR ~ U[0, 10] dB, sources starting at random azimuths (el 0-40 degrees)."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed))
+    out = []
+    for s in range(n_streams):
+        M = int(rng.choice(list(Ms)))
+        Ns = 2 if M == 60 else 1
+        out.append(ArrayStream(sid=s, M=M, F=257, T=50, Ns=Ns, grid=DirectionGrid(72, 19),
+                               pos=array_for(M), freqs=bin_freqs(257, 16000.0, 512),
+                               noise_u=[unit_vector(135.0, 10.0), unit_vector(290.0, 30.0)],
+                               p_noise=[1.0, 1.0], sigma_d2=1.0,
+                               snr_db=float(rng.uniform(0.0, 10.0)),
+                               src_az0=list(rng.uniform(0.0, 360.0, size=Ns)),
+                               src_el=list(rng.choice([0.0, 20.0, 40.0], size=Ns)),
+                               seed=seed * 1000 + s))
+    return out
+
+
+def poisson_arrivals(n_streams: int, duration_s: float, mean_period_s: float = 0.010,
+                     seed: int = 1006):
+    """(emit time, stream, seq) of every block emitted in [0, duration): per stream, exponential
+    inter-arrival times with the given mean (a Poisson process), sorted by time."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed))
+    ev = []
+    for s in range(n_streams):
+        t = float(rng.uniform(0.0, mean_period_s))
+        seq = 0
+        while t < duration_s:
+            ev.append((t, s, seq))
+            seq += 1
+            t += float(rng.exponential(mean_period_s))
+    ev.sort()
+    return ev
+
+
 def uneven_shapes(n_blocks: int, seed: int = 1004):
     """Shapes of an uneven batch: M in {8, 16, 32, 60}, 512- or 1024-point STFT (F = 257 / 513) and
     Ns in {1, 2, 3}, each uniform; returns a list of (M, F, Ns) tuples."""
