@@ -31,20 +31,20 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 
 
-def jacobi_flops(M: int, sweeps, rotations) -> float:
-    """Algorithmic real flops of the SVD kernel summed over bins.
-    QR preconditioner (Householder, trailing size n = M..1): each of the n - 1 remaining columns
-    costs w = v^H x (8n), x -= v (tau w) (8n) and its trailing norm (4n): 20 n (n - 1).
-    Jacobi: each pair visit forms |z_i|^2, |z_j|^2, z_i^H z_j (16 M); each applied rotation
-    rewrites two columns of Z and two of J (40 M); pair visits = sweeps * M(M-1)/2.
-    U = Q J: reflector n applied to the M columns of J, 16 n M."""
+def jacobi_flops(M: int, sweeps, rotations, rank) -> float:
+    """Algorithmic real flops of the SVD kernel summed over bins (rank r per bin).
+    QR preconditioner: step k = 0..r-1 has trailing size n = M - k; each of the n - 1 remaining
+    columns costs w = v^H x (8n), x -= v (tau w) (8n) and its trailing norm (4n): 20 n (n - 1).
+    Jacobi on the r leading columns of R^H: each pair visit forms |z_i|^2, |z_j|^2, z_i^H z_j
+    (16 M); each applied rotation rewrites two columns of Z and two of J (40 M); pair visits =
+    sweeps * r(r-1)/2.  U = Q J: reflector k applied to the M columns of J, 16 (M - k) M."""
     import numpy as np
-    sweeps = np.asarray(sweeps, dtype=np.float64)
-    rotations = np.asarray(rotations, dtype=np.float64)
-    n = np.arange(1, M + 1, dtype=np.float64)
-    per_bin_fixed = float(np.sum(20.0 * n * (n - 1)) + np.sum(16.0 * n * M))
-    visits = sweeps * M * (M - 1) / 2.0
-    return float(np.sum(visits * 16.0 * M + rotations * 40.0 * M) + per_bin_fixed * sweeps.size)
+    total = 0.0
+    for s, rot, r in zip(np.asarray(sweeps), np.asarray(rotations), np.asarray(rank)):
+        n = M - np.arange(int(r), dtype=np.float64)
+        total += float(np.sum(20.0 * n * (n - 1)) + np.sum(16.0 * n * M))
+        total += float(s) * r * (r - 1) / 2.0 * 16.0 * M + float(rot) * 40.0 * M
+    return total
 
 
 def main() -> int:
@@ -117,13 +117,13 @@ def main() -> int:
     # deterministic, so they are those of the timed launches.
     R = torch.zeros((F, M, M), dtype=torch.complex64, device=dev)
     En = torch.zeros((F, M - Ns, M), dtype=torch.complex64, device=dev)
-    conv = torch.zeros((F, 2), dtype=torch.int32, device=dev)
+    conv = torch.zeros((F, 3), dtype=torch.int32, device=dev)
     conv_all = []
     for b in range(B):
         S.ssl_corr_accum(ctx, Xs[b], 1.0 / T, 0, prec, R)
         S.ssl_gsvd(ctx, R, noise, Ns, En, None, None, conv, 0)
         conv_all.append(conv.cpu().numpy().copy())
-    flops_batch = float(sum(jacobi_flops(M, c[:, 0], c[:, 1]) for c in conv_all))
+    flops_batch = float(sum(jacobi_flops(M, c[:, 0], c[:, 1], c[:, 2]) for c in conv_all))
 
     pk = torch.zeros((B, Ns), dtype=torch.int32, device=dev)
     pv = torch.zeros((B, Ns), dtype=torch.float32, device=dev)
@@ -229,7 +229,8 @@ def main() -> int:
         "kernels": kernels,
         "roofline": roofline,
         "jacobi_sweeps": {"mean": round(float(np.mean([c[:, 0].mean() for c in conv_all])), 3),
-                          "max": int(max(c[:, 0].max() for c in conv_all))},
+                          "max": int(max(c[:, 0].max() for c in conv_all)),
+                          "mean_rank": round(float(np.mean([c[:, 2].mean() for c in conv_all])), 2)},
         "status_ok": status_ok,
         "input_gen_s": round(gen_s, 2),
     }

@@ -134,7 +134,10 @@ void ssl_noise_destroy(ssl_noise K);
  *   En[f] = U[:, Ns..M-1]   written column-major: [F][M-Ns][M] ssl_c64.
  * R: [F][M][M] ssl_c64 (e.g. from ssl_corr_accum).  K: a handle set for the same F and M.
  * sigma: [F][M] float or NULL.  bin_status: [F] int32 or NULL.
- * conv: [F][2] int32 or NULL -> (sweeps run, rotations applied) per bin.
+ * conv: [F][3] int32 or NULL -> (sweeps run, rotations applied, numerical rank) per bin.
+ * Numerical rank: the pivoted Householder QR that preconditions the Jacobi iteration stops at the
+ * first pivot norm <= M 2^-24 times the first; the trailing rows are treated as zero (their
+ * singular values are below the FP32 resolution of A), so only rank columns enter the sweeps.
  * max_sweeps: 0 selects the default (20).  Failed bins get En = 0 and sigma = 0. */
 ssl_status ssl_gsvd(ssl_ctx ctx, const ssl_c64 *R, ssl_noise K, int F, int M, int Ns, ssl_c64 *En,
                     float *sigma, int32_t *bin_status, int32_t *conv, int max_sweeps, void *stream);

@@ -15,8 +15,10 @@
 // GPU mapping (gfx950):
 //  * one workgroup per bin; two complex64 MP x MP column-major matrices in LDS (64 KB at MP = 64,
 //    two bins per CU): X1 holds A -> its QR -> J -> U, X2 holds Z -> the reflectors;
-//  * QR step k: one wave picks the pivot, one lane group forms the reflector, the groups apply it to
-//    the remaining columns and refresh their trailing norms;
+//  * QR step k (one barrier): every group reads the pivot (a 64-bit LDS max over norm/column keys
+//    posted by the previous step), forms the reflector itself, applies it to its remaining
+//    columns and posts their new trailing norms; columns are never moved;
+//  * U = Q J: each group takes its columns of J through all reflectors in registers;
 //  * parallel (round-robin) ordering: each sweep is M'-1 rounds of M'/2 disjoint column pairs
 //    (M' = M rounded up to even), one pair per group of G lanes, each lane owning MP/G rows;
 //  * alpha = |z_i|^2, beta = |z_j|^2 and gamma = z_i^H z_j are reduced across the G lanes with DPP
@@ -64,11 +66,12 @@ struct JacobiCfg {
     static constexpr int THREADS = ((NG * G + 63) / 64) * 64;
 };
 
-// Applies the reflector H = I - tau v v^H (v = rows k..M-1 of column k of V) to column c of X,
-// rows k..M-1, by one lane group; returns the group-summed |x_r|^2 over rows > k of the result.
+// Applies the reflector H = I - tau v v^H to column c of X, rows k..M-1, by one lane group:
+// v_k = vk, v_r = Vk[r] for k < r < M.  Returns the group-summed |x_r|^2 over rows > k of the
+// result (the column's trailing norm for the next step).
 template <int MP, int G>
-__device__ __forceinline__ float apply_reflector(const float2 *V, int k, float tau, float2 *X,
-                                                 int c, int M, int q)
+__device__ __forceinline__ float apply_reflector(const float2 *Vk, float2 vk, int k, float tau,
+                                                 float2 *X, int c, int M, int q)
 {
     constexpr int R = MP / G;
     float wr = 0.f, wi = 0.f;
@@ -76,8 +79,7 @@ __device__ __forceinline__ float apply_reflector(const float2 *V, int k, float t
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         const int r = q + G * j;
-        const bool in = r >= k && r < M;
-        v[j] = in ? V[k * MP + r] : make_float2(0.f, 0.f);
+        v[j] = (r == k) ? vk : ((r > k && r < M) ? Vk[r] : make_float2(0.f, 0.f));
         x[j] = X[c * MP + r];
         // conj(v) x
         wr = fmaf(v[j].x, x[j].x, fmaf(v[j].y, x[j].y, wr));
@@ -100,6 +102,13 @@ __device__ __forceinline__ float apply_reflector(const float2 *V, int k, float t
     return group_sum<G>(tn);
 }
 
+// Pivot key: larger squared norm first, then the lower column index (norms are >= 0, so the
+// float bits order like the values).
+__device__ __forceinline__ unsigned long long pivot_key(float nrm2, int c)
+{
+    return ((unsigned long long)__float_as_uint(nrm2) << 32) | (unsigned int)(0x7fffffff - c);
+}
+
 // One bin: Af = its A (row-major M x M, overwritten), kst = upstream status of the bin (noise
 // factorisation), Enf = [M-Ns][M] output, sigf = [M] or null, stf = status or null,
 // convf = (sweeps, rotations) or null.
@@ -115,19 +124,20 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
     constexpr int NG = C::NG;
     __shared__ float2 X1[MP * MP];      // column c at c*MP: A -> QR (R above, reflectors below) -> J -> U
     __shared__ float2 X2[MP * MP];      // Z = R^H during the sweeps, then the reflectors
-    __shared__ float2 diag[MP];         // diagonal of R
+    __shared__ float2 diag[MP];         // diagonal of R (step order)
+    __shared__ float2 vhead[MP];        // leading element v_k of reflector k
     __shared__ float tau[MP];
-    __shared__ float nu[MP];            // trailing column norms for pivoting
+    __shared__ int colmap[MP];          // step k's pivot: physical column colmap[k]
+    __shared__ int pos[MP];             // step at which physical column c was chosen (M: never)
     __shared__ float sig[MP];
     __shared__ int perm[MP];
+    __shared__ unsigned long long pkey[3];   // pivot keys of steps k, k+1 (k+2 being cleared)
     __shared__ int flag;                // upstream failure / non-finite input
     __shared__ float amax_s;
     __shared__ int rot_total;
-    __shared__ int piv_s;
+    __shared__ int rank_s;              // numerical rank found by the pivoted QR
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
     const int g = tid / G;              // lane group
     const int q = tid % G;              // lane in group
     const int Nn = M - Ns;
@@ -137,7 +147,10 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         flag = kst;
         amax_s = 0.0f;
         rot_total = 0;
+        rank_s = M;
+        pkey[0] = pkey[1] = pkey[2] = 0ull;
     }
+    if (tid < MP) pos[tid] = M;
     __syncthreads();
 
     // ---- load A column-major into X1 (padding zero) --------------------------------------------
@@ -175,6 +188,13 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         __syncthreads();
 
         // ---- 1. Householder QR with column pivoting: A P = Q R ----------------------------------
+        // Columns stay where they are; step k picks the unused column of largest trailing norm
+        // (rows k..M-1; ties: lower column), known from a 64-bit LDS max over (norm, column) keys
+        // that the previous step's update pass posts, so a step costs one barrier.  The reflector
+        // v = x - alpha e_k, alpha = -e^{i arg x_k}|x|, is formed redundantly by every group; its
+        // head v_k goes to vhead (x_k itself stays in place, R's diagonal is kept in diag).
+        // Once the pivot norm drops to M 2^-24 times the first one, the remaining rows of R are
+        // FP32 noise: the numerical rank is k.
         for (int c = g; c < M && g < NG; c += NG) {
             float s = 0.f;
 #pragma unroll
@@ -183,84 +203,65 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                 s = fmaf(v.x, v.x, fmaf(v.y, v.y, s));
             }
             s = group_sum<G>(s);
-            if (q == 0) nu[c] = s;
+            if (q == 0) atomicMax(&pkey[0], pivot_key(s, c));
         }
         __syncthreads();
+        int rk = M;
+        float thr = 0.0f;
+        unsigned long long used = 0ull;    // columns already chosen (M <= 64)
+        int kc = 0, kn = 1, kz = 2;        // pkey slots of steps k, k+1, k+2
         for (int k = 0; k < M; ++k) {
-            // (a) pivot: the remaining column of largest trailing norm (ties: lowest index)
-            if (wave == 0) {
-                float bv = (lane >= k && lane < M) ? nu[lane] : -1.0f;
-                int bi = lane;
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) {
-                    const float ov = __shfl_xor(bv, off);
-                    const int oi = __shfl_xor(bi, off);
-                    if (ov > bv || (ov == bv && oi < bi)) {
-                        bv = ov;
-                        bi = oi;
-                    }
-                }
-                if (lane == 0) piv_s = bi;
+            const unsigned long long key = pkey[kc];
+            const int p = 0x7fffffff - (int)(unsigned int)(key & 0xffffffffull);
+            const float nx = sqrtf(__uint_as_float((unsigned int)(key >> 32)));
+            if (nx <= thr) {               // uniform: every thread read the same key
+                rk = k;
+                break;
+            }
+            if (k == 0) thr = (float)M * 5.9604644775390625e-08f * nx;
+            const float2 xk = X1[p * MP + k];
+            const float axk = sqrtf(fmaf(xk.x, xk.x, xk.y * xk.y));
+            const float2 ph = axk > 0.f ? make_float2(xk.x / axk, xk.y / axk) : make_float2(1.f, 0.f);
+            const float tk = 1.0f / (nx * (nx + axk));
+            const float2 vk = make_float2(ph.x * (axk + nx), ph.y * (axk + nx));
+            if (tid == 0) {
+                diag[k] = make_float2(-ph.x * nx, -ph.y * nx);
+                vhead[k] = vk;
+                tau[k] = tk;
+                colmap[k] = p;
+                pos[p] = k;
+                pkey[kz] = 0ull;           // read by everyone in step k-1, posted in step k+1
+            }
+            used |= 1ull << p;
+            for (int c = g; c < M && g < NG; c += NG) {
+                if ((used >> c) & 1ull) continue;
+                const float tn = apply_reflector<MP, G>(X1 + p * MP, vk, k, tk, X1, c, M, q);
+                if (q == 0) atomicMax(&pkey[kn], pivot_key(tn, c));
             }
             __syncthreads();
-            const int p = piv_s;
-            if (p != k) {
-                for (int r = tid; r < M; r += NT) {
-                    const float2 t = X1[k * MP + r];
-                    X1[k * MP + r] = X1[p * MP + r];
-                    X1[p * MP + r] = t;
-                }
-                if (tid == 0) {
-                    const float t = nu[k];
-                    nu[k] = nu[p];
-                    nu[p] = t;
-                }
-                __syncthreads();
-            }
-            // (b) reflector for column k, rows k..M-1: v = x - alpha e_k, alpha = -e^{i arg x_k}|x|
-            if (g == 0) {
-                float s = 0.f;
-#pragma unroll
-                for (int j = 0; j < R; ++j) {
-                    const int r = q + G * j;
-                    if (r >= k && r < M) {
-                        const float2 v = X1[k * MP + r];
-                        s = fmaf(v.x, v.x, fmaf(v.y, v.y, s));
-                    }
-                }
-                s = group_sum<G>(s);
-                if (q == 0) {
-                    const float nx = sqrtf(s);
-                    const float2 xk = X1[k * MP + k];
-                    const float axk = sqrtf(fmaf(xk.x, xk.x, xk.y * xk.y));
-                    const float2 ph = axk > 0.f ? make_float2(xk.x / axk, xk.y / axk)
-                                                : make_float2(1.f, 0.f);
-                    diag[k] = make_float2(-ph.x * nx, -ph.y * nx);
-                    tau[k] = nx > 0.f ? 1.0f / (nx * (nx + axk)) : 0.0f;
-                    X1[k * MP + k] = make_float2(ph.x * (axk + nx), ph.y * (axk + nx));
-                }
-            }
-            __syncthreads();
-            // (c) apply to the remaining columns, refresh their trailing norms
-            const float tk = tau[k];
-            for (int c = k + 1 + g; c < M && g < NG; c += NG) {
-                const float tn = apply_reflector<MP, G>(X1, k, tk, X1, c, M, q);
-                if (q == 0) nu[c] = tn;
-            }
-            __syncthreads();
+            const int t = kc;
+            kc = kn;
+            kn = kz;
+            kz = t;
         }
 
         // ---- 2. park the reflectors in A's rows (workspace), Z = R^H into X2, J = I into X1 -----
+        // Only the leading rk rows of R are kept: Z's columns rk..M-1 are zero and take no part
+        // in the Jacobi iteration; the matching columns of U are Q's, spanning the null space.
+        // Z's rows follow the physical column order (a row permutation of R^H leaves the Gram
+        // matrix of its columns unchanged): Z[x][c] = conj(R[c][pos x]).
+        if (tid == 0) rank_s = rk;
         for (int e = tid; e < M * M; e += NT) {
             const int k = e / M, r = e - k * M;
-            if (r >= k) Af[e] = X1[k * MP + r];
+            if (r >= k && k < rk) Af[e] = (r == k) ? vhead[k] : X1[colmap[k] * MP + r];
         }
         for (int e = tid; e < MP * MP; e += NT) {
-            const int c = e / MP, r = e - c * MP;          // Z[r][c] = conj(R[c][r])
+            const int c = e / MP, x = e - c * MP;
             float2 z = make_float2(0.f, 0.f);
-            if (c < M && r < M) {
-                if (r > c) z = conj2(X1[r * MP + c]);
-                else if (r == c) z = conj2(diag[c]);
+            if (c < rk && x < M) {
+                const int px = pos[x];
+                if (px > c) z = conj2(X1[x * MP + c]);
+                else if (px == c) z = conj2(diag[c]);
             }
             X2[e] = z;
         }
@@ -274,7 +275,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         // ---- 3. one-sided Jacobi on Z, rotations accumulated in J -------------------------------
         float2 *Bs = X2;
         float2 *Js = X1;
-        const int Me = M + (M & 1);                  // players of the round-robin tournament
+        const int Me = rk + (rk & 1);                // players of the round-robin tournament
         const double tol = (double)M * 5.9604644775390625e-08;   // M * 2^-24
         const double tol2 = tol * tol;
         int my_rot = 0;
@@ -293,7 +294,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                         if (b < 0) b += Me - 1;
                     }
                     const int ci = min(a, b), cj = max(a, b);
-                    if (cj < M) {
+                    if (cj < rk) {
                         float2 bi[R], bj[R], ui[R], uj[R];
                         float al = 0.f, be = 0.f, gr = 0.f, gi = 0.f;
 #pragma unroll
@@ -396,16 +397,38 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         // ---- 5. U = Q J: reflectors back into X2, applied last to first ------------------------
         for (int e = tid; e < M * M; e += NT) {
             const int k = e / M, r = e - k * M;
-            if (r >= k) X2[k * MP + r] = Af[e];
+            if (r >= k && k < rk) X2[k * MP + r] = Af[e];
         }
         __syncthreads();
-        for (int k = M - 1; k >= 0; --k) {
-            const float tk = tau[k];
-            if (tk != 0.0f)
-                for (int c = g; c < M && g < NG; c += NG)
-                    (void)apply_reflector<MP, G>(X2, k, tk, X1, c, M, q);
-            __syncthreads();
+        // each group owns whole columns of J: it takes its column through every reflector in
+        // registers, no barrier between reflectors
+        for (int c = g; c < M && g < NG; c += NG) {
+            float2 x[R];
+#pragma unroll
+            for (int j = 0; j < R; ++j) x[j] = X1[c * MP + q + G * j];
+            for (int k = rk - 1; k >= 0; --k) {
+                const float tk = tau[k];
+                float2 v[R];
+                float wr = 0.f, wi = 0.f;
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    const int r = q + G * j;
+                    v[j] = (r >= k && r < M) ? X2[k * MP + r] : make_float2(0.f, 0.f);
+                    wr = fmaf(v[j].x, x[j].x, fmaf(v[j].y, x[j].y, wr));
+                    wi = fmaf(v[j].x, x[j].y, fmaf(-v[j].y, x[j].x, wi));
+                }
+                wr = group_sum<G>(wr) * tk;
+                wi = group_sum<G>(wi) * tk;
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    x[j].x = fmaf(-v[j].x, wr, fmaf(v[j].y, wi, x[j].x));
+                    x[j].y = fmaf(-v[j].x, wi, fmaf(-v[j].y, wr, x[j].y));
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < R; ++j) X1[c * MP + q + G * j] = x[j];
         }
+        __syncthreads();
     }
 
     // ---- outputs ------------------------------------------------------------------------------
@@ -422,6 +445,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         if (convf != nullptr) {
             convf[0] = sweeps;
             convf[1] = rot_total;
+            convf[2] = rank_s;
         }
     }
 }
@@ -436,7 +460,7 @@ __global__ __launch_bounds__((JacobiCfg<MP, G>::THREADS)) void jacobi_svd(
     const int f = blockIdx.x;
     jacobi_bin<MP, G>(A + (size_t)f * M * M, kstatus ? kstatus[f] : SSL_BIN_OK, M, Ns, max_sweeps,
                       En + (size_t)f * (M - Ns) * M, sigma ? sigma + (size_t)f * M : nullptr,
-                      bin_status ? bin_status + f : nullptr, conv ? conv + 2 * f : nullptr);
+                      bin_status ? bin_status + f : nullptr, conv ? conv + 3 * f : nullptr);
 }
 
 // Persistent: a fixed grid of workgroups draws (block, bin) items from a device counter until the

@@ -174,7 +174,7 @@ def run_gsvd(S, ctx, R64, K, Ns, max_sweeps=0):
     En = torch.zeros((F, M - Ns, M), dtype=torch.complex64, device="cuda:0")
     sig = torch.zeros((F, M), dtype=torch.float32, device="cuda:0")
     st = torch.zeros(F, dtype=torch.int32, device="cuda:0")
-    conv = torch.zeros((F, 2), dtype=torch.int32, device="cuda:0")
+    conv = torch.zeros((F, 3), dtype=torch.int32, device="cuda:0")
     S.ssl_gsvd(ctx, Rd, n, Ns, En, sig, st, conv, max_sweeps)
     out = dict(En=to_host(En), sigma=to_host(sig), status=to_host(st), conv=to_host(conv))
     S.ssl_noise_destroy(n)
@@ -198,6 +198,8 @@ def test_gsvd_parity(S, ctx, M, Ns):
     En_ref, sig_ref, st_ref, _ = oracle.gsvd(K, R, Ns)
     assert np.all(st_ref == 0) and np.all(g["status"] == 0), g["status"]
     assert np.all(g["conv"][:, 0] <= 20)
+    # R comes from T = 50 frames: rank min(M, 50), found by the pivoted QR
+    assert np.all(g["conv"][:, 2] == min(M, 50))
     errs = []
     for f in range(F):
         A = np.linalg.solve(K[f], R[f])
