@@ -33,17 +33,22 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3
 
 def jacobi_flops(M: int, sweeps, rotations, rank) -> float:
     """Algorithmic real flops of the SVD kernel summed over bins (rank r per bin).
-    QR preconditioner: step k = 0..r-1 has trailing size n = M - k; each of the n - 1 remaining
-    columns costs w = v^H x (8n), x -= v (tau w) (8n) and its trailing norm (4n): 20 n (n - 1).
-    Jacobi on the r leading columns of R^H: each pair visit forms |z_i|^2, |z_j|^2, z_i^H z_j
-    (16 M); each applied rotation rewrites two columns of Z and two of J (40 M); pair visits =
-    sweeps * r(r-1)/2.  U = Q J: reflector k applied to the M columns of J, 16 (M - k) M."""
+    Pivoted QR: step k = 0..r-1 has trailing size n = M - k; each of the n - 1 remaining columns
+    costs w = v^H x (8n), x -= v (tau w) (8n) and its trailing norm (4n): 20 n (n - 1).
+    Second QR of R^H (M x r, no pivoting): step k updates r - k - 1 columns of length M - k,
+    16 (M - k)(r - k - 1).  Jacobi on X (r x r): each pair visit forms |x_i|^2, |x_j|^2, x_i^H x_j
+    (16 r); each applied rotation rewrites two columns (20 r); pair visits = sweeps r(r-1)/2.
+    Normalisation of W: 6 r per column.  U = Q U_R: reflector k applied to the M columns,
+    16 (M - k) M."""
     import numpy as np
     total = 0.0
     for s, rot, r in zip(np.asarray(sweeps), np.asarray(rotations), np.asarray(rank)):
-        n = M - np.arange(int(r), dtype=np.float64)
-        total += float(np.sum(20.0 * n * (n - 1)) + np.sum(16.0 * n * M))
-        total += float(s) * r * (r - 1) / 2.0 * 16.0 * M + float(rot) * 40.0 * M
+        r = int(r)
+        k = np.arange(r, dtype=np.float64)
+        n = M - k
+        total += float(np.sum(20.0 * n * (n - 1)) + np.sum(16.0 * n * (r - k - 1))
+                       + np.sum(16.0 * n * M))
+        total += float(s) * r * (r - 1) / 2.0 * 16.0 * r + float(rot) * 20.0 * r + 6.0 * r * r
     return total
 
 

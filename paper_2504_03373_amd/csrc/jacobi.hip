@@ -1,33 +1,36 @@
 // GSVD step of arXiv 2504.03373 eq.4: SVD of A = K^{-1} R per frequency bin and the noise subspace
 // E_n = [e_{Ns+1} .. e_M] of its left singular vectors (the definition following eq.4).
 //
-// Method: one-sided (Hestenes) Jacobi -- the paper's "category 1" solver of Sec. III-B -- with a
-// Householder QR preconditioner (the paper's own building block, Sec. III-B category 2):
-//   1. A P = Q R         Householder QR with column pivoting (largest remaining column first);
-//   2. Z = R^H           one-sided Jacobi from the right, Z J = W with orthogonal columns, the
-//                        rotations accumulated in J (J = I initially);
-//   3. U = Q J           reflectors applied back to J.
-// Since R^H = W J^H, R = J W^H and A = Q R P^T = (Q J) W^H P^T: the columns of U = Q J are the left
-// singular vectors of A (exactly unitary even for zero singular values) and sigma_i = |w_i|.  The
-// Jacobi iteration works on the Gram matrix R R^H of the pivoted triangular factor, which is far
-// closer to diagonal than A A^H: about 7 sweeps instead of about 17 on the 60-channel workload.
+// Method: one-sided (Hestenes) Jacobi -- the paper's "category 1" solver of Sec. III-B -- with two
+// Householder QR preconditioners (the paper's own building block, Sec. III-B category 2):
+//   1. A P = Q R         Householder QR with column pivoting (largest remaining column first),
+//                        stopped at the numerical rank rk (R: rk x M);
+//   2. R^H = Q1 R1       Householder QR without pivoting (Q1 is never formed);
+//   3. X = R1^H          one-sided Jacobi from the right, X V = W with orthogonal columns;
+//   4. U = Q [W S^-1, 0; 0, I]   normalised columns, reflectors applied back.
+// Since R = R1^H Q1^H = X Q1^H, R's left singular vectors are X's, i.e. W S^-1 (S = diag |w_i|),
+// and A = Q R P^T gives U as above; sigma_i = |w_i|, the columns rk..M-1 of U are Q's and span the
+// numerical null space.  The Jacobi iteration works on X^H X = R1 R1^H, the Gram matrix of a
+// twice-triangularised pivoted factor, which is close to diagonal: about 6 sweeps on the
+// 60-channel workload (about 17 on A itself), and no rotation has to be accumulated.
 //
 // GPU mapping (gfx950):
 //  * one workgroup per bin; two complex64 MP x MP column-major matrices in LDS (64 KB at MP = 64,
-//    two bins per CU): X1 holds A -> its QR -> J -> U, X2 holds Z -> the reflectors;
-//  * QR step k (one barrier): every group reads the pivot (a 64-bit LDS max over norm/column keys
-//    posted by the previous step), forms the reflector itself, applies it to its remaining
-//    columns and posts their new trailing norms; columns are never moved;
-//  * U = Q J: each group takes its columns of J through all reflectors in registers;
-//  * parallel (round-robin) ordering: each sweep is M'-1 rounds of M'/2 disjoint column pairs
-//    (M' = M rounded up to even), one pair per group of G lanes, each lane owning MP/G rows;
-//  * alpha = |z_i|^2, beta = |z_j|^2 and gamma = z_i^H z_j are reduced across the G lanes with DPP
+//    two bins per CU): X1 holds A -> its QR -> X -> W -> U, X2 holds R^H -> R1 -> the reflectors;
+//  * pivoted QR step k (one barrier): every group reads the pivot (a 64-bit LDS max over
+//    norm/column keys posted by the previous step), forms the reflector itself, applies it to its
+//    remaining columns and posts their new trailing norms; columns are never moved;
+//  * parallel (round-robin) ordering: each sweep is rk'-1 rounds of rk'/2 disjoint column pairs
+//    (rk' = rk rounded up to even), one pair per group of G lanes, each lane owning MP/G rows;
+//  * alpha = |x_i|^2, beta = |x_j|^2 and gamma = x_i^H x_j are reduced across the G lanes with DPP
 //    butterflies (every lane ends with the same bits, so the rotation decision is uniform in the
 //    group);
-//  * convergence test in FP64: rotate iff |gamma|^2 > tol^2 alpha beta with tol = M 2^-24; a sweep
-//    without any rotation ends the solve (a fixed point: a converged bin is never changed again);
+//  * convergence test in FP64: rotate iff |gamma|^2 > tol^2 alpha beta with tol = 2 sqrt(M) 2^-24;
+//    a sweep without any rotation ends the solve (a fixed point: a converged bin is never changed
+//    again), and the columns of W S^-1 are then orthonormal to tol;
 //  * epilogue: sigma from the column norms, stable descending rank sort (ties: lower column
-//    first), U = Q J, E_n = sorted columns Ns..M-1 of U, written column-major per bin.
+//    first), U = Q U_R with each group taking its columns through all reflectors in registers,
+//    E_n = sorted columns Ns..M-1 of U, written column-major per bin.
 #include "ssl_internal.h"
 
 namespace {
@@ -78,6 +81,7 @@ __device__ __forceinline__ float apply_reflector(const float2 *Vk, float2 vk, in
     float2 x[R], v[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
+        if (G * (j + 1) <= k) continue;           // slot entirely above the reflector
         const int r = q + G * j;
         v[j] = (r == k) ? vk : ((r > k && r < M) ? Vk[r] : make_float2(0.f, 0.f));
         x[j] = X[c * MP + r];
@@ -90,6 +94,7 @@ __device__ __forceinline__ float apply_reflector(const float2 *Vk, float2 vk, in
     float tn = 0.f;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
+        if (G * (j + 1) <= k) continue;
         const int r = q + G * j;
         if (r >= k && r < M) {
             // x -= v * (tau w)
@@ -111,7 +116,7 @@ __device__ __forceinline__ unsigned long long pivot_key(float nrm2, int c)
 
 // One bin: Af = its A (row-major M x M, overwritten), kst = upstream status of the bin (noise
 // factorisation), Enf = [M-Ns][M] output, sigf = [M] or null, stf = status or null,
-// convf = (sweeps, rotations) or null.
+// convf = (sweeps, rotations, numerical rank) or null.
 template <int MP, int G>
 __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int M, int Ns,
                                            int max_sweeps, float2 *__restrict__ Enf,
@@ -122,8 +127,8 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
     constexpr int R = C::R;
     constexpr int NT = C::THREADS;
     constexpr int NG = C::NG;
-    __shared__ float2 X1[MP * MP];      // column c at c*MP: A -> QR (R above, reflectors below) -> J -> U
-    __shared__ float2 X2[MP * MP];      // Z = R^H during the sweeps, then the reflectors
+    __shared__ float2 X1[MP * MP];      // column c at c*MP: A -> QR (R above, reflectors below) -> X -> U
+    __shared__ float2 X2[MP * MP];      // R^H -> R1 (second QR), then the reflectors of Q
     __shared__ float2 diag[MP];         // diagonal of R (step order)
     __shared__ float2 vhead[MP];        // leading element v_k of reflector k
     __shared__ float tau[MP];
@@ -136,6 +141,9 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
     __shared__ float amax_s;
     __shared__ int rot_total;
     __shared__ int rank_s;              // numerical rank found by the pivoted QR
+    __shared__ float2 diag1[MP];        // diagonal of R1 (second QR)
+    __shared__ float nrm1[MP];          // trailing norm of the next column (second QR)
+    __shared__ int degen;               // a column of W vanished
 
     const int tid = threadIdx.x;
     const int g = tid / G;              // lane group
@@ -148,6 +156,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         amax_s = 0.0f;
         rot_total = 0;
         rank_s = M;
+        degen = 0;
         pkey[0] = pkey[1] = pkey[2] = 0ull;
     }
     if (tid < MP) pos[tid] = M;
@@ -221,8 +230,9 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
             if (k == 0) thr = (float)M * 5.9604644775390625e-08f * nx;
             const float2 xk = X1[p * MP + k];
             const float axk = sqrtf(fmaf(xk.x, xk.x, xk.y * xk.y));
-            const float2 ph = axk > 0.f ? make_float2(xk.x / axk, xk.y / axk) : make_float2(1.f, 0.f);
-            const float tk = 1.0f / (nx * (nx + axk));
+            const float rax = __builtin_amdgcn_rcpf(axk);
+            const float2 ph = axk > 0.f ? make_float2(xk.x * rax, xk.y * rax) : make_float2(1.f, 0.f);
+            const float tk = __builtin_amdgcn_rcpf(nx * (nx + axk));
             const float2 vk = make_float2(ph.x * (axk + nx), ph.y * (axk + nx));
             if (tid == 0) {
                 diag[k] = make_float2(-ph.x * nx, -ph.y * nx);
@@ -245,11 +255,11 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
             kz = t;
         }
 
-        // ---- 2. park the reflectors in A's rows (workspace), Z = R^H into X2, J = I into X1 -----
-        // Only the leading rk rows of R are kept: Z's columns rk..M-1 are zero and take no part
-        // in the Jacobi iteration; the matching columns of U are Q's, spanning the null space.
-        // Z's rows follow the physical column order (a row permutation of R^H leaves the Gram
-        // matrix of its columns unchanged): Z[x][c] = conj(R[c][pos x]).
+        // ---- 2. park the reflectors in A's rows (workspace), Z = R^H into X2 --------------------
+        // Only the leading rk rows of R are kept (R: rk x M); the columns rk..M-1 of U are Q's,
+        // spanning the null space.  Z's rows follow the physical column order (a row permutation
+        // of R^H changes neither the Gram matrix of its columns nor the triangular factor below):
+        // Z[x][c] = conj(R[c][pos x]).
         if (tid == 0) rank_s = rk;
         for (int e = tid; e < M * M; e += NT) {
             const int k = e / M, r = e - k * M;
@@ -266,17 +276,53 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
             X2[e] = z;
         }
         __syncthreads();
+
+        // ---- 3. Z = Q1 R1 (Householder, no pivoting; Q1 is not needed), X = R1^H into X1 ------
+        // R = R1^H Q1^H, so R's left singular vectors are X's; X's column Gram X^H X = R1 R1^H
+        // is closer still to diagonal than R R^H.  The trailing norm of the next column comes out
+        // of each update pass.
+        if (g == 0) {
+            float s = 0.f;
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const float2 v = X2[q + G * j];
+                s = fmaf(v.x, v.x, fmaf(v.y, v.y, s));
+            }
+            s = group_sum<G>(s);
+            if (q == 0) nrm1[0] = s;
+        }
+        __syncthreads();
+        for (int k = 0; k < rk; ++k) {
+            const float nx = sqrtf(nrm1[k]);
+            const float2 xk = X2[k * MP + k];
+            const float axk = sqrtf(fmaf(xk.x, xk.x, xk.y * xk.y));
+            const float rax = __builtin_amdgcn_rcpf(axk);
+            const float2 ph = axk > 0.f ? make_float2(xk.x * rax, xk.y * rax) : make_float2(1.f, 0.f);
+            const float tk = nx > 0.f ? __builtin_amdgcn_rcpf(nx * (nx + axk)) : 0.0f;
+            const float2 vk = make_float2(ph.x * (axk + nx), ph.y * (axk + nx));
+            if (tid == 0) diag1[k] = make_float2(-ph.x * nx, -ph.y * nx);
+            for (int c = k + 1 + g; c < rk && g < NG; c += NG) {
+                const float tn = apply_reflector<MP, G>(X2 + k * MP, vk, k, tk, X2, c, M, q);
+                if (c == k + 1 && q == 0) nrm1[c] = tn;
+            }
+            __syncthreads();
+        }
         for (int e = tid; e < MP * MP; e += NT) {
-            const int c = e / MP, r = e - c * MP;
-            X1[e] = make_float2((c == r && c < M) ? 1.f : 0.f, 0.f);
+            const int c = e / MP, i = e - c * MP;          // X[i][c] = conj(R1[c][i])
+            float2 z = make_float2(0.f, 0.f);
+            if (c < rk && i < rk) {
+                if (i > c) z = conj2(X2[i * MP + c]);
+                else if (i == c) z = conj2(diag1[c]);
+            }
+            X1[e] = z;
         }
         __syncthreads();
 
-        // ---- 3. one-sided Jacobi on Z, rotations accumulated in J -------------------------------
-        float2 *Bs = X2;
-        float2 *Js = X1;
+        // ---- 4. one-sided Jacobi on X: X V = W, columns orthogonalised in place ----------------
+        float2 *Bs = X1;
         const int Me = rk + (rk & 1);                // players of the round-robin tournament
-        const double tol = (double)M * 5.9604644775390625e-08;   // M * 2^-24
+        // rotate iff |cos| > 2 sqrt(M) 2^-24 (twice the usual FP32 one-sided Jacobi threshold)
+        const double tol = 2.0 * sqrt((double)M) * 5.9604644775390625e-08;
         const double tol2 = tol * tol;
         int my_rot = 0;
         for (int sw = 0; sw < max_sweeps; ++sw) {
@@ -295,15 +341,13 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                     }
                     const int ci = min(a, b), cj = max(a, b);
                     if (cj < rk) {
-                        float2 bi[R], bj[R], ui[R], uj[R];
+                        float2 bi[R], bj[R];
                         float al = 0.f, be = 0.f, gr = 0.f, gi = 0.f;
 #pragma unroll
                         for (int k = 0; k < R; ++k) {
                             const int r = q + G * k;
                             bi[k] = Bs[ci * MP + r];
                             bj[k] = Bs[cj * MP + r];
-                            ui[k] = Js[ci * MP + r];     // issued early: overlaps the reductions
-                            uj[k] = Js[cj * MP + r];
                             al = fmaf(bi[k].x, bi[k].x, fmaf(bi[k].y, bi[k].y, al));
                             be = fmaf(bj[k].x, bj[k].x, fmaf(bj[k].y, bj[k].y, be));
                             // conj(z_i) * z_j
@@ -330,8 +374,10 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                             const float rg = __builtin_amdgcn_rcpf(mx * sqrtf(fmaf(rt, rt, 1.0f)));
                             const float zeta = (be - al) * 0.5f * rg;
                             const float az = fabsf(zeta);
-                            float t = (az > 1e18f) ? 0.5f / az
-                                                   : 1.0f / (az + sqrtf(fmaf(az, az, 1.0f)));
+                            // (hardware reciprocals: c and s below come from the same t, so
+                            // the rotation is orthonormal whatever t's last-bit error)
+                            float t = (az > 1e18f) ? 0.5f * __builtin_amdgcn_rcpf(az)
+                                                   : __builtin_amdgcn_rcpf(az + sqrtf(fmaf(az, az, 1.0f)));
                             t = copysignf(t, zeta);
                             const float c = rsqrt_refined(fmaf(t, t, 1.0f));
                             const float s = c * t;
@@ -349,14 +395,6 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                                 nj.y = fmaf(c, y.y, fmaf(wr, x.y, -wi * x.x));
                                 Bs[ci * MP + r] = ni;
                                 Bs[cj * MP + r] = nj;
-                                x = ui[k];
-                                y = uj[k];
-                                ni.x = fmaf(c, x.x, -fmaf(wr, y.x, -wi * y.y));
-                                ni.y = fmaf(c, x.y, -fmaf(wr, y.y, wi * y.x));
-                                nj.x = fmaf(c, y.x, fmaf(wr, x.x, wi * x.y));
-                                nj.y = fmaf(c, y.y, fmaf(wr, x.y, -wi * x.x));
-                                Js[ci * MP + r] = ni;
-                                Js[cj * MP + r] = nj;
                             }
                             if (q == 0) ++my_rot;
                         }
@@ -372,19 +410,34 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         }
         if (my_rot) atomicAdd(&rot_total, my_rot);
 
-        // ---- 4. singular values sigma_c = |w_c| (scaled back), stable descending rank ----------
+        // ---- 5. sigma_c = |w_c| (scaled back); U_R = W Sigma^-1 extended by the identity on the
+        // null-space columns rk..M-1; stable descending rank of sigma ------------------------------
         for (int c = g; c < MP && g < NG; c += NG) {
+            float2 x[R];
             float s = 0.f;
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                const float2 v = Bs[c * MP + q + G * k];
-                s = fmaf(v.x, v.x, fmaf(v.y, v.y, s));
+                x[k] = Bs[c * MP + q + G * k];
+                s = fmaf(x[k].x, x[k].x, fmaf(x[k].y, x[k].y, s));
             }
             s = group_sum<G>(s);
+            if (c < rk) {
+                // X is nonsingular (rank rk), so a zero column means a numerical breakdown
+                const float inv = s > 0.f ? rsqrt_refined(s) : 0.0f;
+#pragma unroll
+                for (int k = 0; k < R; ++k)
+                    Bs[c * MP + q + G * k] = make_float2(x[k].x * inv, x[k].y * inv);
+                if (q == 0 && !(s > 0.f)) degen = 1;
+            } else {
+#pragma unroll
+                for (int k = 0; k < R; ++k)
+                    Bs[c * MP + q + G * k] = make_float2((q + G * k == c && c < M) ? 1.f : 0.f, 0.f);
+            }
             if (q == 0) sig[c] = (c < M) ? ldexpf(sqrtf(s), ex) : -1.0f;
         }
         for (int c = tid; c < MP; c += NT) perm[c] = c;
         __syncthreads();
+        if (degen) converged = false;
         for (int c = tid; c < M; c += NT) {
             const float sc_ = sig[c];
             int rank = 0;
@@ -394,13 +447,14 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
             }
             if (rank < M) perm[rank] = c;
         }
-        // ---- 5. U = Q J: reflectors back into X2, applied last to first ------------------------
-        for (int e = tid; e < M * M; e += NT) {
-            const int k = e / M, r = e - k * M;
-            if (r >= k && k < rk) X2[k * MP + r] = Af[e];
+        // ---- 6. U = Q U_R: reflectors back into X2, applied last to first ----------------------
+        // (stored with zeros outside rows k..M-1, so the loads below need no row test)
+        for (int e = tid; e < rk * MP; e += NT) {
+            const int k = e / MP, r = e - k * MP;
+            X2[e] = (r >= k && r < M) ? Af[k * M + r] : make_float2(0.f, 0.f);
         }
         __syncthreads();
-        // each group owns whole columns of J: it takes its column through every reflector in
+        // each group owns whole columns of U: it takes its column through every reflector in
         // registers, no barrier between reflectors
         for (int c = g; c < M && g < NG; c += NG) {
             float2 x[R];
@@ -412,8 +466,8 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                 float wr = 0.f, wi = 0.f;
 #pragma unroll
                 for (int j = 0; j < R; ++j) {
-                    const int r = q + G * j;
-                    v[j] = (r >= k && r < M) ? X2[k * MP + r] : make_float2(0.f, 0.f);
+                    if (G * (j + 1) <= k) continue;      // slot entirely above the reflector
+                    v[j] = X2[k * MP + q + G * j];
                     wr = fmaf(v[j].x, x[j].x, fmaf(v[j].y, x[j].y, wr));
                     wi = fmaf(v[j].x, x[j].y, fmaf(-v[j].y, x[j].x, wi));
                 }
@@ -421,6 +475,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                 wi = group_sum<G>(wi) * tk;
 #pragma unroll
                 for (int j = 0; j < R; ++j) {
+                    if (G * (j + 1) <= k) continue;
                     x[j].x = fmaf(-v[j].x, wr, fmaf(v[j].y, wi, x[j].x));
                     x[j].y = fmaf(-v[j].x, wi, fmaf(-v[j].y, wr, x[j].y));
                 }
