@@ -12,7 +12,9 @@ Timed regions (each bracketed by torch.cuda.synchronize()):
   * main: `--steps` batch steps with per-kernel HIP events on the launch stream -> `value` and
     the dominant kernel's roofline (algorithmic flops per launch / average launch duration);
   * graph: the same steps replayed from the captured HIP graph (no events) -> `graph_value`;
-  * per-block: ssl_localize one block at a time -> `per_block`.
+  * per-block: ssl_localize one block at a time -> `per_block`;
+  * host-to-device: the same steps with every block's X copied from pinned host memory, serial
+    and double-buffered on a side stream -> `h2d`.
 The FP64 CPU oracle is timed on a bounded sample of the same workload on this host's cores.
 Prints one JSON line.
 """
@@ -52,6 +54,73 @@ def jacobi_flops(M: int, sweeps, rotations, rank) -> float:
     return total
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jacobi_persistent_60ch_257bin_hbm_traffic.json")
+JACOBI_SRC = os.path.join(ROOT, "paper_2504_03373_amd", "csrc", "jacobi.hip")
+
+
+def _sha256(path: str) -> str:
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def traffic_bytes(batch: int):
+    """HBM bytes per Jacobi launch from the committed counter summary, or None when it is absent,
+    was taken at another batch size, or the kernel source has changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != _sha256(JACOBI_SRC) or t.get("blocks_per_launch") != batch:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def _pmc_rows(d: str, counter: str):
+    """(kernel name, value) per dispatch from a rocprofv3 --pmc csv output directory."""
+    import csv
+    import glob
+    rows = []
+    for fn in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(fn, newline="") as f:
+            for r in csv.DictReader(f):
+                if r.get("Counter_Name") == counter:
+                    rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    if not rows:
+        raise SystemExit(f"no {counter} rows under {d}")
+    return rows
+
+
+def pmc_summarize(fetch_dir: str, write_dir: str, calib_mb: int, batch: int) -> int:
+    """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of jacobi_persistent, each scaled by what the
+    same counter reads for the calibration kernel (calib_mb MiB read and written once)."""
+    import numpy as np
+    if calib_mb <= 0:
+        raise SystemExit("--calib-copy-mb is needed to scale the counters")
+    calib = calib_mb * (1 << 20)
+    out = {"kernel": "jacobi_persistent", "blocks_per_launch": batch,
+           "source_sha256": _sha256(JACOBI_SRC), "calibration_bytes": calib}
+    total = 0.0
+    for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = _pmc_rows(d, name)
+        cal = [v for k, v in rows if "neg" in k.lower()]
+        jac = [v for k, v in rows if "jacobi_persistent" in k]
+        if not cal or not jac:
+            raise SystemExit(f"{name}: calibration or Jacobi dispatches missing in {d}")
+        scale = calib / (max(cal) * 1024.0)
+        per_launch = float(np.median(jac)) * 1024.0 * scale
+        out[name.lower()] = {"kib_per_dispatch_median": float(np.median(jac)),
+                             "dispatches": len(jac), "calibration_kib": max(cal),
+                             "scale": scale, "bytes_per_launch": per_launch}
+        total += per_launch
+    out["bytes_per_launch"] = total
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,18 +129,26 @@ def main() -> int:
     ap.add_argument("--batch", type=int, default=32, help="blocks per step")
     ap.add_argument("--prec", choices=["fp32", "bf16", "fp16"], default="fp32")
     ap.add_argument("--per-block-steps", type=int, default=100)
-    ap.add_argument("--cpu-blocks", type=int, default=6, help="oracle sample size (blocks)")
+    ap.add_argument("--cpu-blocks", type=int, default=48, help="oracle sample size (blocks)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
-                    help="run one device copy of this size first (HBM counter calibration)")
+                    help="run one plain streaming kernel of this size first (HBM counter scale)")
+    ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="no GPU work: turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
+                         "this script with --calib-copy-mb into the traffic summary under profiles/")
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="duration of emitted traffic in the serving phase (0 = skip)")
     ap.add_argument("--serve-streams", type=int, default=64)
     ap.add_argument("--serve-period-ms", type=float, default=10.0, help="mean block period per stream")
+    ap.add_argument("--serve-light-period-ms", type=float, default=30.0,
+                    help="a second, lighter serving load (0 = skip)")
     ap.add_argument("--serve-budget-gb", type=float, default=4.0, help="HBM budget of in-flight work")
     ap.add_argument("--k-update-every", type=int, default=1)
     args = ap.parse_args()
 
+    if args.pmc_summarize:
+        return pmc_summarize(args.pmc_summarize[0], args.pmc_summarize[1], args.calib_copy_mb,
+                             args.batch)
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the localization path shards by stream/block with no "
               f"collective, so --gpus {args.gpus} is not run here", file=sys.stderr)
@@ -104,10 +181,13 @@ def main() -> int:
     gen_s = time.time() - t0
 
     if args.calib_copy_mb > 0:
+        # one plain streaming kernel of known traffic (reads and writes calib MiB once each): the
+        # scale of the HBM counters (FETCH_SIZE / WRITE_SIZE) in the same profiled run
         n = args.calib_copy_mb * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.cuda.synchronize()
+        torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
 
@@ -188,6 +268,47 @@ def main() -> int:
     torch.cuda.synchronize()
     per_block = args.per_block_steps / (time.perf_counter() - tb)
 
+    # ---- host-to-device inclusive region ------------------------------------------------------
+    # X of every block arrives from pinned host memory: (a) copy then compute on one stream;
+    # (b) double-buffered, the copy of step k+1 on a side stream under the compute of step k.
+    Xh = Xs.cpu().pin_memory()
+    Xs2 = torch.empty_like(Xs)
+    descs2 = [S.block_desc(Xs2[b], noise, H, w.grid.n_az, w.grid.n_el, Ns, pk[b], pv[b], Pbar[b],
+                           st[b]) for b in range(B)]
+    main_st = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    th = time.perf_counter()
+    for _ in range(args.steps):
+        Xs.copy_(Xh, non_blocking=True)
+        step()
+    torch.cuda.synchronize()
+    h2d_serial = args.steps * B / (time.perf_counter() - th)
+    cs = torch.cuda.Stream(device=dev)
+    bufs, bdescs = (Xs, Xs2), (descs, descs2)
+    copied = [torch.cuda.Event(), torch.cuda.Event()]
+    freed = [torch.cuda.Event(), torch.cuda.Event()]
+    for i in range(2):
+        S.ssl_localize_batch(ctx, bdescs[i], prec, 2)       # capture both buffer sets (not timed)
+    torch.cuda.synchronize()
+    th = time.perf_counter()
+    with torch.cuda.stream(cs):
+        bufs[0].copy_(Xh, non_blocking=True)
+        copied[0].record(cs)
+    for k in range(args.steps):
+        i = k & 1
+        if k + 1 < args.steps:
+            with torch.cuda.stream(cs):
+                if k >= 1:
+                    cs.wait_event(freed[1 - i])
+                bufs[1 - i].copy_(Xh, non_blocking=True)
+                copied[1 - i].record(cs)
+        main_st.wait_event(copied[i])
+        S.ssl_localize_batch(ctx, bdescs[i], prec, 2)
+        freed[i].record(main_st)
+    torch.cuda.synchronize()
+    h2d_overlap = args.steps * B / (time.perf_counter() - th)
+    del Xh, Xs2
+
     dom = max(ktimes, key=lambda k: ktimes[k][1])
     n_j, ms_j = ktimes["jacobi"]
     avg_j_ms = ms_j / max(n_j, 1)
@@ -199,7 +320,7 @@ def main() -> int:
         "peak": PEAK_FP32_VECTOR_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
-        "traffic": None,
+        "traffic": traffic_bytes(B),
         "avg_launch_ms": round(avg_j_ms, 4),
         "flops_per_launch": flops_batch,
         "bins_per_launch": B * F,
@@ -236,6 +357,10 @@ def main() -> int:
         "jacobi_sweeps": {"mean": round(float(np.mean([c[:, 0].mean() for c in conv_all])), 3),
                           "max": int(max(c[:, 0].max() for c in conv_all)),
                           "mean_rank": round(float(np.mean([c[:, 2].mean() for c in conv_all])), 2)},
+        "h2d": {"serial": round(h2d_serial, 2), "overlapped": round(h2d_overlap, 2),
+                "unit": "blocks/s", "bytes_per_block": F * T * M * 8,
+                "kind": "X from pinned host memory each step (copy then compute; copy of the "
+                        "next step on a side stream under the compute)"},
         "status_ok": status_ok,
         "input_gen_s": round(gen_s, 2),
     }
@@ -256,20 +381,24 @@ def main() -> int:
                          hbm_budget_bytes=budget, lanes=2, pool=4)
         srv = Server(ex, budget, max_batch=128)
         srv.run(synth.poisson_arrivals(len(streams), 0.1, args.serve_period_ms * 1e-3, seed=7))
-        arrivals = synth.poisson_arrivals(len(streams), args.serve_seconds,
-                                          args.serve_period_ms * 1e-3)
-        sv = srv.run(arrivals)
-        ex.close()
         mix = {m: sum(1 for s in streams if s.M == m) for m in sorted({s.M for s in streams})}
-        out["serving"] = {
-            "streams": len(streams), "streams_by_M": mix,
-            "offered_blocks_per_s": round(len(arrivals) / args.serve_seconds, 1),
-            "completed": sv["completed"], "blocks_per_s": round(sv["blocks_per_s"], 1),
-            "p50_ms": round(sv["p50_ms"], 3), "p99_ms": round(sv["p99_ms"], 3),
-            "max_ms": round(sv["max_ms"], 3), "mean_batch": round(sv["mean_batch"], 2),
-            "max_queue": sv["max_queue"], "k_update_every": args.k_update_every,
-            "hbm_budget_gb": args.serve_budget_gb, "emitted_seconds": args.serve_seconds}
-        out["latency_ms"] = {"p50": round(sv["p50_ms"], 3), "p99": round(sv["p99_ms"], 3),
+
+        def serve(period_ms: float) -> dict:
+            arrivals = synth.poisson_arrivals(len(streams), args.serve_seconds, period_ms * 1e-3)
+            sv = srv.run(arrivals)
+            return {"streams": len(streams), "streams_by_M": mix, "period_ms": period_ms,
+                    "offered_blocks_per_s": round(len(arrivals) / args.serve_seconds, 1),
+                    "completed": sv["completed"], "blocks_per_s": round(sv["blocks_per_s"], 1),
+                    "p50_ms": round(sv["p50_ms"], 3), "p99_ms": round(sv["p99_ms"], 3),
+                    "max_ms": round(sv["max_ms"], 3), "mean_batch": round(sv["mean_batch"], 2),
+                    "max_queue": sv["max_queue"], "k_update_every": args.k_update_every,
+                    "hbm_budget_gb": args.serve_budget_gb, "emitted_seconds": args.serve_seconds}
+
+        out["serving"] = serve(args.serve_period_ms)
+        if args.serve_light_period_ms > 0:
+            out["serving_light"] = serve(args.serve_light_period_ms)
+        ex.close()
+        out["latency_ms"] = {"p50": out["serving"]["p50_ms"], "p99": out["serving"]["p99_ms"],
                              "kind": "served: emission to peaks on the host"}
 
     if not args.no_cpu:

@@ -92,29 +92,21 @@ ssl_status ws_reserve(ssl_ctx ctx, size_t bytes)
     return s;
 }
 
-// Bin-sum scratch: [chunks][D] partials + a completion counter that starts (and is left) at 0.
+// Bin-sum scratch: [chunks][D] partials.
 ssl_status binsum_reserve(ssl_ctx ctx, int F, int D)
 {
     const size_t nch = (size_t)(F + SSL_BINSUM_CHUNK - 1) / SSL_BINSUM_CHUNK;
     const size_t need = nch * (size_t)D;
-    if (ctx->binsum_floats >= need && ctx->binsum_counter) return SSL_OK;
-    if (ctx->binsum_counter) {
-        dev_free(ctx, ctx->binsum_counter, ctx->binsum_floats * sizeof(float) + 256);
+    if (ctx->binsum_floats >= need && ctx->binsum_part) return SSL_OK;
+    if (ctx->binsum_part) {
+        dev_free(ctx, ctx->binsum_part, ctx->binsum_floats * sizeof(float));
         ctx->binsum_part = nullptr;
-        ctx->binsum_counter = nullptr;
         ctx->binsum_floats = 0;
     }
     void *p = nullptr;
-    const size_t bytes = need * sizeof(float) + 256;
-    ssl_status s = dev_alloc(ctx, &p, bytes, "bin-sum scratch");
+    ssl_status s = dev_alloc(ctx, &p, need * sizeof(float), "bin-sum scratch");
     if (s != SSL_OK) return s;
-    hipError_t e = hipMemset(p, 0, bytes);
-    if (e != hipSuccess) {
-        dev_free(ctx, p, bytes);
-        return hip_fail(e, "hipMemset");
-    }
-    ctx->binsum_counter = reinterpret_cast<unsigned int *>(p);
-    ctx->binsum_part = reinterpret_cast<float *>(static_cast<char *>(p) + 256);
+    ctx->binsum_part = static_cast<float *>(p);
     ctx->binsum_floats = need;
     return SSL_OK;
 }
@@ -256,8 +248,7 @@ void ssl_ctx_destroy(ssl_ctx ctx)
     dev_free(ctx, ctx->counters, ctx->n_counters * sizeof(unsigned int));
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     dev_free(ctx, ctx->ws, ctx->ws_bytes);
-    if (ctx->binsum_counter)
-        dev_free(ctx, ctx->binsum_counter, ctx->binsum_floats * sizeof(float) + 256);
+    if (ctx->binsum_part) dev_free(ctx, ctx->binsum_part, ctx->binsum_floats * sizeof(float));
     delete ctx;
 }
 
@@ -522,8 +513,8 @@ ssl_status ssl_music_spectrum(ssl_ctx ctx, const void *H, ssl_prec hprec, const 
     });
     if (e != hipSuccess) return hip_fail(e, "steer launch");
     e = timed(ctx, SSL_K_BINSUM, st, [&] {
-        return launch_binsum_peaks(Pw, F, D, Pbar, ctx->binsum_part, ctx->binsum_counter, D, 1, 1,
-                                   nullptr, nullptr, st);
+        return launch_binsum_peaks(Pw, F, D, Pbar, ctx->binsum_part, D, 1, 1, nullptr, nullptr,
+                                   st);
     });
     return e == hipSuccess ? SSL_OK : hip_fail(e, "bin-sum launch");
 }
@@ -609,8 +600,8 @@ ssl_status ssl_localize(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int M, int6
               [&] { return launch_steer(H, prec, En, F, D, M, Ns, p, stt, P, st); });
     if (e != hipSuccess) return hip_fail(e, "steer launch");
     e = timed(ctx, SSL_K_BINSUM, st, [&] {
-        return launch_binsum_peaks(P, F, D, Pb, ctx->binsum_part, ctx->binsum_counter, n_az,
-                                   n_el, Ns, peaks, peak_val, st);
+        return launch_binsum_peaks(P, F, D, Pb, ctx->binsum_part, n_az, n_el, Ns, peaks,
+                                   peak_val, st);
     });
     return e == hipSuccess ? SSL_OK : hip_fail(e, "bin-sum launch");
 }
@@ -625,7 +616,6 @@ namespace {
 constexpr int kJacobiQueues = 4;     // counters[0..3]: work queues of Jacobi classes 8/16/32/64
 
 int jacobi_queue(int cls) { return cls == 8 ? 0 : cls == 16 ? 1 : cls == 32 ? 2 : 3; }
-int jacobi_wg_per_cu(int cls) { return cls == 64 ? 2 : cls == 32 ? 4 : 8; }
 
 struct Seg {
     int cls, start, count, extra;
@@ -859,10 +849,11 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
     size_t ws_total = 0;
     int64_t n_items = 0;
     std::vector<int64_t> key;
-    key.reserve(3 + 6 * (size_t)nblocks);
+    key.reserve(7 + 6 * (size_t)nblocks);
     key.push_back(nblocks);
     key.push_back(prec);
     key.push_back(p);
+    for (int i = 0; i < 4; ++i) key.push_back(ctx->jac_lanes[i]);   // kernel variants captured
     for (int b = 0; b < nblocks; ++b) {
         const ssl_block_desc &d = descs[b];
         if ((s = check_common(d.F, d.M, d.Ns)) != SSL_OK ||
@@ -903,7 +894,7 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
     const size_t desc_bytes = align256(sizeof(BlockDev) * nblocks);
     const size_t list_bytes = sizeof(int2) * 4 * (size_t)n_items;
     if ((s = ws_reserve(ctx, ws_total)) != SSL_OK) return s;
-    if ((s = counters_reserve(ctx, kJacobiQueues + (size_t)nblocks)) != SSL_OK) return s;
+    if ((s = counters_reserve(ctx, kJacobiQueues)) != SSL_OK) return s;
     if ((s = bdesc_reserve(ctx, desc_bytes + list_bytes)) != SSL_OK) return s;
 
     // the previous call's staging copy must have completed before the buffer is rewritten
@@ -955,7 +946,6 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
         w += align256(F * sizeof(int32_t));
         B.Pbar = d.Pbar ? d.Pbar : reinterpret_cast<float *>(w);
         w += align256(D * sizeof(float));
-        B.counter = ctx->counters + kJacobiQueues + b;
         B.peaks = d.peaks;
         B.peak_val = d.peak_val;
         c_corr[b] = corr_class(d.M);
@@ -971,7 +961,8 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
     build_list(c_jac, Fs, hl + 2 * n_items, plan.jac);
     build_list(c_st, Fs, hl + 3 * n_items, plan.steer);
     for (Seg &sg : plan.jac)
-        sg.extra = std::min(sg.count, ctx->cu_count * jacobi_wg_per_cu(sg.cls));
+        sg.extra = std::min(sg.count, ctx->cu_count * jacobi_persistent_wg_per_cu(
+                                                         sg.cls, ctx->jac_lanes[jacobi_class_index(sg.cls)]));
     const int rows = steer_rows_per_block();
     for (Seg &sg : plan.steer) {
         int dt = 0;

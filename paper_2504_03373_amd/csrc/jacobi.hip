@@ -15,8 +15,9 @@
 // 60-channel workload (about 17 on A itself), and no rotation has to be accumulated.
 //
 // GPU mapping (gfx950):
-//  * one workgroup per bin; two complex64 MP x MP column-major matrices in LDS (64 KB at MP = 64,
-//    two bins per CU): X1 holds A -> its QR -> X -> W -> U, X2 holds R^H -> R1 -> the reflectors;
+//  * one workgroup per bin; one complex64 MP x MP column-major matrix in LDS (32 KB at MP = 64,
+//    four bins per CU) holds A -> its QR -> R^H -> R1 -> X -> W -> U in turn (the two
+//    transposes in place, each thread exchanging the pair of entries it owns);
 //  * pivoted QR step k (one barrier): every group reads the pivot (a 64-bit LDS max over
 //    norm/column keys posted by the previous step), forms the reflector itself, applies it to its
 //    remaining columns and posts their new trailing norms; columns are never moved;
@@ -32,6 +33,8 @@
 //    first), U = Q U_R with each group taking its columns through all reflectors in registers,
 //    E_n = sorted columns Ns..M-1 of U, written column-major per bin.
 #include "ssl_internal.h"
+
+#include <atomic>
 
 namespace {
 
@@ -67,23 +70,30 @@ struct JacobiCfg {
     static constexpr int R = MP / G;                       // rows per lane
     static constexpr int NG = MP / 2;                      // lane groups
     static constexpr int THREADS = ((NG * G + 63) / 64) * 64;
+    // register budget of the persistent variant: at MP = 64 the LDS admits 4 bins per CU; aim
+    // for 3 (16 lanes, <= 80 VGPRs) or 4 (8 lanes, <= 128) resident workgroups
+    static constexpr int WAVES_PER_EU = (MP == 64) ? (G == 16 ? 6 : 4) : 1;
 };
 
 // Applies the reflector H = I - tau v v^H to column c of X, rows k..M-1, by one lane group:
-// v_k = vk, v_r = Vk[r] for k < r < M.  Returns the group-summed |x_r|^2 over rows > k of the
-// result (the column's trailing norm for the next step).
+// v_k = vk, v_r = Vk[r] for r > k.  Rows >= M hold zeros in every column (so v_r = 0 there and
+// those rows stay zero), rows < k are left as they are (v_r = 0; rewritten unchanged).  Returns
+// the group-summed |x_r|^2 over rows > k of the result (the column's trailing norm for the next
+// step).
 template <int MP, int G>
 __device__ __forceinline__ float apply_reflector(const float2 *Vk, float2 vk, int k, float tau,
                                                  float2 *X, int c, int M, int q)
 {
     constexpr int R = MP / G;
+    (void)M;
     float wr = 0.f, wi = 0.f;
     float2 x[R], v[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         if (G * (j + 1) <= k) continue;           // slot entirely above the reflector
         const int r = q + G * j;
-        v[j] = (r == k) ? vk : ((r > k && r < M) ? Vk[r] : make_float2(0.f, 0.f));
+        const float2 raw = Vk[r];
+        v[j] = (r > k) ? raw : ((r == k) ? vk : make_float2(0.f, 0.f));
         x[j] = X[c * MP + r];
         // conj(v) x
         wr = fmaf(v[j].x, x[j].x, fmaf(v[j].y, x[j].y, wr));
@@ -96,13 +106,12 @@ __device__ __forceinline__ float apply_reflector(const float2 *Vk, float2 vk, in
     for (int j = 0; j < R; ++j) {
         if (G * (j + 1) <= k) continue;
         const int r = q + G * j;
-        if (r >= k && r < M) {
-            // x -= v * (tau w)
-            x[j].x = fmaf(-v[j].x, wr, fmaf(v[j].y, wi, x[j].x));
-            x[j].y = fmaf(-v[j].x, wi, fmaf(-v[j].y, wr, x[j].y));
-            X[c * MP + r] = x[j];
-            if (r > k) tn = fmaf(x[j].x, x[j].x, fmaf(x[j].y, x[j].y, tn));
-        }
+        // x -= v * (tau w)
+        x[j].x = fmaf(-v[j].x, wr, fmaf(v[j].y, wi, x[j].x));
+        x[j].y = fmaf(-v[j].x, wi, fmaf(-v[j].y, wr, x[j].y));
+        X[c * MP + r] = x[j];
+        const float n2 = fmaf(x[j].x, x[j].x, x[j].y * x[j].y);
+        tn += (r > k) ? n2 : 0.0f;
     }
     return group_sum<G>(tn);
 }
@@ -127,8 +136,9 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
     constexpr int R = C::R;
     constexpr int NT = C::THREADS;
     constexpr int NG = C::NG;
-    __shared__ float2 X1[MP * MP];      // column c at c*MP: A -> QR (R above, reflectors below) -> X -> U
-    __shared__ float2 X2[MP * MP];      // R^H -> R1 (second QR), then the reflectors of Q
+    // column c at c*MP: A -> QR (R above, reflectors below) -> Z = R^H -> R1 -> X = R1^H -> W ->
+    // U_R (-> registers while the reflectors of Q pass through) -> U
+    __shared__ float2 X[MP * MP];
     __shared__ float2 diag[MP];         // diagonal of R (step order)
     __shared__ float2 vhead[MP];        // leading element v_k of reflector k
     __shared__ float tau[MP];
@@ -162,7 +172,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
     if (tid < MP) pos[tid] = M;
     __syncthreads();
 
-    // ---- load A column-major into X1 (padding zero) --------------------------------------------
+    // ---- load A column-major into X (padding zero) ---------------------------------------------
     float amax = 0.0f;
     bool nonfinite = false;
     for (int e = tid; e < MP * MP; e += NT) {
@@ -173,7 +183,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
             if (!finite2(a)) nonfinite = true;
             amax = fmaxf(amax, fmaxf(fabsf(a.x), fabsf(a.y)));
         }
-        X1[c * MP + r] = a;
+        X[c * MP + r] = a;
     }
     const int nf_count = __syncthreads_count(nonfinite ? 1 : 0);
     if (!nonfinite && amax > 0.0f) atomicMax((int *)&amax_s, __float_as_int(amax));
@@ -191,8 +201,8 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         if (am > 0.0f) frexpf(am, &ex);
         const float sc = ldexpf(1.0f, -ex);
         for (int e = tid; e < MP * MP; e += NT) {
-            const float2 b = X1[e];
-            X1[e] = make_float2(b.x * sc, b.y * sc);
+            const float2 b = X[e];
+            X[e] = make_float2(b.x * sc, b.y * sc);
         }
         __syncthreads();
 
@@ -208,7 +218,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
             float s = 0.f;
 #pragma unroll
             for (int j = 0; j < R; ++j) {
-                const float2 v = X1[c * MP + q + G * j];
+                const float2 v = X[c * MP + q + G * j];
                 s = fmaf(v.x, v.x, fmaf(v.y, v.y, s));
             }
             s = group_sum<G>(s);
@@ -228,7 +238,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                 break;
             }
             if (k == 0) thr = (float)M * 5.9604644775390625e-08f * nx;
-            const float2 xk = X1[p * MP + k];
+            const float2 xk = X[p * MP + k];
             const float axk = sqrtf(fmaf(xk.x, xk.x, xk.y * xk.y));
             const float rax = __builtin_amdgcn_rcpf(axk);
             const float2 ph = axk > 0.f ? make_float2(xk.x * rax, xk.y * rax) : make_float2(1.f, 0.f);
@@ -245,7 +255,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
             used |= 1ull << p;
             for (int c = g; c < M && g < NG; c += NG) {
                 if ((used >> c) & 1ull) continue;
-                const float tn = apply_reflector<MP, G>(X1 + p * MP, vk, k, tk, X1, c, M, q);
+                const float tn = apply_reflector<MP, G>(X + p * MP, vk, k, tk, X, c, M, q);
                 if (q == 0) atomicMax(&pkey[kn], pivot_key(tn, c));
             }
             __syncthreads();
@@ -255,29 +265,39 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
             kz = t;
         }
 
-        // ---- 2. park the reflectors in A's rows (workspace), Z = R^H into X2 --------------------
+        // ---- 2. park the reflectors in A's rows (workspace); Z = R^H in place ------------------
         // Only the leading rk rows of R are kept (R: rk x M); the columns rk..M-1 of U are Q's,
         // spanning the null space.  Z's rows follow the physical column order (a row permutation
         // of R^H changes neither the Gram matrix of its columns nor the triangular factor below):
-        // Z[x][c] = conj(R[c][pos x]).
+        // Z[x][c] = conj(R[c][pos x]).  R[c][pos x] sits at (column x, row c), so Z is a masked
+        // conjugate transpose: each thread exchanges the pair (c, x), (x, c) it owns.
         if (tid == 0) rank_s = rk;
         for (int e = tid; e < M * M; e += NT) {
             const int k = e / M, r = e - k * M;
-            if (r >= k && k < rk) Af[e] = (r == k) ? vhead[k] : X1[colmap[k] * MP + r];
+            if (r >= k && k < rk) Af[e] = (r == k) ? vhead[k] : X[colmap[k] * MP + r];
         }
+        __syncthreads();
         for (int e = tid; e < MP * MP; e += NT) {
             const int c = e / MP, x = e - c * MP;
-            float2 z = make_float2(0.f, 0.f);
-            if (c < rk && x < M) {
+            if (c > x) continue;
+            const float2 o1 = X[x * MP + c], o2 = X[c * MP + x];
+            float2 n1 = make_float2(0.f, 0.f), n2 = make_float2(0.f, 0.f);
+            if (c < rk && x < M) {                       // Z[x][c]
                 const int px = pos[x];
-                if (px > c) z = conj2(X1[x * MP + c]);
-                else if (px == c) z = conj2(diag[c]);
+                if (px > c) n1 = conj2(o1);
+                else if (px == c) n1 = conj2(diag[c]);
             }
-            X2[e] = z;
+            if (x < rk && c < M) {                       // Z[c][x]
+                const int pc = pos[c];
+                if (pc > x) n2 = conj2(o2);
+                else if (pc == x) n2 = conj2(diag[x]);
+            }
+            X[c * MP + x] = n1;
+            X[x * MP + c] = n2;
         }
         __syncthreads();
 
-        // ---- 3. Z = Q1 R1 (Householder, no pivoting; Q1 is not needed), X = R1^H into X1 ------
+        // ---- 3. Z = Q1 R1 (Householder, no pivoting; Q1 is not needed), then X = R1^H --------
         // R = R1^H Q1^H, so R's left singular vectors are X's; X's column Gram X^H X = R1 R1^H
         // is closer still to diagonal than R R^H.  The trailing norm of the next column comes out
         // of each update pass.
@@ -285,7 +305,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
             float s = 0.f;
 #pragma unroll
             for (int j = 0; j < R; ++j) {
-                const float2 v = X2[q + G * j];
+                const float2 v = X[q + G * j];
                 s = fmaf(v.x, v.x, fmaf(v.y, v.y, s));
             }
             s = group_sum<G>(s);
@@ -294,7 +314,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         __syncthreads();
         for (int k = 0; k < rk; ++k) {
             const float nx = sqrtf(nrm1[k]);
-            const float2 xk = X2[k * MP + k];
+            const float2 xk = X[k * MP + k];
             const float axk = sqrtf(fmaf(xk.x, xk.x, xk.y * xk.y));
             const float rax = __builtin_amdgcn_rcpf(axk);
             const float2 ph = axk > 0.f ? make_float2(xk.x * rax, xk.y * rax) : make_float2(1.f, 0.f);
@@ -302,24 +322,29 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
             const float2 vk = make_float2(ph.x * (axk + nx), ph.y * (axk + nx));
             if (tid == 0) diag1[k] = make_float2(-ph.x * nx, -ph.y * nx);
             for (int c = k + 1 + g; c < rk && g < NG; c += NG) {
-                const float tn = apply_reflector<MP, G>(X2 + k * MP, vk, k, tk, X2, c, M, q);
+                const float tn = apply_reflector<MP, G>(X + k * MP, vk, k, tk, X, c, M, q);
                 if (c == k + 1 && q == 0) nrm1[c] = tn;
             }
             __syncthreads();
         }
+        // X[i][c] = conj(R1[c][i]), R1[c][i] at (column i, row c) for i > c: masked transpose
         for (int e = tid; e < MP * MP; e += NT) {
-            const int c = e / MP, i = e - c * MP;          // X[i][c] = conj(R1[c][i])
-            float2 z = make_float2(0.f, 0.f);
-            if (c < rk && i < rk) {
-                if (i > c) z = conj2(X2[i * MP + c]);
-                else if (i == c) z = conj2(diag1[c]);
+            const int c = e / MP, i = e - c * MP;
+            if (c > i) continue;
+            const float2 o1 = X[i * MP + c], o2 = X[c * MP + i];
+            float2 n1 = make_float2(0.f, 0.f), n2 = make_float2(0.f, 0.f);
+            if (i < rk) {
+                if (i > c) n1 = conj2(o1);               // X[i][c], below the diagonal
+                else n1 = conj2(diag1[c]);               // i == c
             }
-            X1[e] = z;
+            (void)o2;                                    // X[c][i] (c < i) is above: zero
+            X[c * MP + i] = n1;
+            if (c != i) X[i * MP + c] = n2;
         }
         __syncthreads();
 
         // ---- 4. one-sided Jacobi on X: X V = W, columns orthogonalised in place ----------------
-        float2 *Bs = X1;
+        float2 *Bs = X;
         const int Me = rk + (rk & 1);                // players of the round-robin tournament
         // rotate iff |cos| > 2 sqrt(M) 2^-24 (twice the usual FP32 one-sided Jacobi threshold)
         const double tol = 2.0 * sqrt((double)M) * 5.9604644775390625e-08;
@@ -447,43 +472,59 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
             }
             if (rank < M) perm[rank] = c;
         }
-        // ---- 6. U = Q U_R: reflectors back into X2, applied last to first ----------------------
-        // (stored with zeros outside rows k..M-1, so the loads below need no row test)
-        for (int e = tid; e < rk * MP; e += NT) {
-            const int k = e / MP, r = e - k * MP;
-            X2[e] = (r >= k && r < M) ? Af[k * M + r] : make_float2(0.f, 0.f);
-        }
-        __syncthreads();
-        // each group owns whole columns of U: it takes its column through every reflector in
-        // registers, no barrier between reflectors
-        for (int c = g; c < M && g < NG; c += NG) {
-            float2 x[R];
+        // ---- 6. U = Q U_R, reflectors applied last to first ----------------------------------
+        // U's columns move to registers (a group owns at most two: c = g, g + NG), the reflectors
+        // take the buffer (stored with zeros outside rows k..M-1, so their loads need no row
+        // test), and each group takes its columns through every reflector with no barrier.
+        {
+            const int c0 = g, c1 = g + NG;
+            const bool h0 = g < NG && c0 < M, h1 = g < NG && c1 < M;
+            float2 x0[R], x1[R];
 #pragma unroll
-            for (int j = 0; j < R; ++j) x[j] = X1[c * MP + q + G * j];
+            for (int j = 0; j < R; ++j) {
+                x0[j] = h0 ? X[c0 * MP + q + G * j] : make_float2(0.f, 0.f);
+                x1[j] = h1 ? X[c1 * MP + q + G * j] : make_float2(0.f, 0.f);
+            }
+            __syncthreads();
+            for (int e = tid; e < rk * MP; e += NT) {
+                const int k = e / MP, r = e - k * MP;
+                X[e] = (r >= k && r < M) ? Af[k * M + r] : make_float2(0.f, 0.f);
+            }
+            __syncthreads();
             for (int k = rk - 1; k >= 0; --k) {
                 const float tk = tau[k];
                 float2 v[R];
-                float wr = 0.f, wi = 0.f;
+                float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f;
 #pragma unroll
                 for (int j = 0; j < R; ++j) {
                     if (G * (j + 1) <= k) continue;      // slot entirely above the reflector
-                    v[j] = X2[k * MP + q + G * j];
-                    wr = fmaf(v[j].x, x[j].x, fmaf(v[j].y, x[j].y, wr));
-                    wi = fmaf(v[j].x, x[j].y, fmaf(-v[j].y, x[j].x, wi));
+                    v[j] = X[k * MP + q + G * j];
+                    ar = fmaf(v[j].x, x0[j].x, fmaf(v[j].y, x0[j].y, ar));
+                    ai = fmaf(v[j].x, x0[j].y, fmaf(-v[j].y, x0[j].x, ai));
+                    br = fmaf(v[j].x, x1[j].x, fmaf(v[j].y, x1[j].y, br));
+                    bi = fmaf(v[j].x, x1[j].y, fmaf(-v[j].y, x1[j].x, bi));
                 }
-                wr = group_sum<G>(wr) * tk;
-                wi = group_sum<G>(wi) * tk;
+                ar = group_sum<G>(ar) * tk;
+                ai = group_sum<G>(ai) * tk;
+                br = group_sum<G>(br) * tk;
+                bi = group_sum<G>(bi) * tk;
 #pragma unroll
                 for (int j = 0; j < R; ++j) {
                     if (G * (j + 1) <= k) continue;
-                    x[j].x = fmaf(-v[j].x, wr, fmaf(v[j].y, wi, x[j].x));
-                    x[j].y = fmaf(-v[j].x, wi, fmaf(-v[j].y, wr, x[j].y));
+                    x0[j].x = fmaf(-v[j].x, ar, fmaf(v[j].y, ai, x0[j].x));
+                    x0[j].y = fmaf(-v[j].x, ai, fmaf(-v[j].y, ar, x0[j].y));
+                    x1[j].x = fmaf(-v[j].x, br, fmaf(v[j].y, bi, x1[j].x));
+                    x1[j].y = fmaf(-v[j].x, bi, fmaf(-v[j].y, br, x1[j].y));
                 }
             }
+            __syncthreads();
 #pragma unroll
-            for (int j = 0; j < R; ++j) X1[c * MP + q + G * j] = x[j];
+            for (int j = 0; j < R; ++j) {
+                if (h0) X[c0 * MP + q + G * j] = x0[j];
+                if (h1) X[c1 * MP + q + G * j] = x1[j];
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 
     // ---- outputs ------------------------------------------------------------------------------
@@ -491,7 +532,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
     const int st = (flag != SSL_BIN_OK) ? flag : (converged ? SSL_BIN_OK : SSL_BIN_NO_CONV);
     for (int e = tid; e < Nn * M; e += NT) {
         const int c = e / M, r = e - c * M;
-        Enf[e] = ok ? X1[perm[Ns + c] * MP + r] : make_float2(0.f, 0.f);
+        Enf[e] = ok ? X[perm[Ns + c] * MP + r] : make_float2(0.f, 0.f);
     }
     if (sigf != nullptr)
         for (int k = tid; k < M; k += NT) sigf[k] = ok ? sig[perm[k]] : 0.0f;
@@ -523,7 +564,8 @@ __global__ __launch_bounds__((JacobiCfg<MP, G>::THREADS)) void jacobi_svd(
 // workgroup draws exactly one ticket >= n_items; the one drawing the last ticket re-arms the
 // counter to 0 for the next launch.
 template <int MP, int G>
-__global__ __launch_bounds__((JacobiCfg<MP, G>::THREADS)) void jacobi_persistent(
+__global__ __launch_bounds__((JacobiCfg<MP, G>::THREADS))
+__attribute__((amdgpu_waves_per_eu(JacobiCfg<MP, G>::WAVES_PER_EU))) void jacobi_persistent(
     const BlockDev *__restrict__ blk, const int2 *__restrict__ items, int n_items,
     int max_sweeps, unsigned int *__restrict__ queue)
 {
@@ -604,6 +646,24 @@ int jacobi_threads(int cls, int lanes)
     int t = 0;
     dispatch(cls, lanes, [&]<int MP, int G>() { t = JacobiCfg<MP, G>::THREADS; });
     return t;
+}
+
+int jacobi_persistent_wg_per_cu(int cls, int lanes)
+{
+    // resident workgroups per CU of the persistent variant (LDS and registers decide), cached
+    static std::atomic<int> cache[4][3];
+    const int ci = cls == 8 ? 0 : cls == 16 ? 1 : cls == 32 ? 2 : 3;
+    const int li = lanes == 4 ? 0 : lanes == 8 ? 1 : 2;
+    int n = cache[ci][li].load(std::memory_order_relaxed);
+    if (n > 0) return n;
+    dispatch(cls, lanes, [&]<int MP, int G>() {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, jacobi_persistent<MP, G>,
+                                                         JacobiCfg<MP, G>::THREADS, 0) != hipSuccess)
+            n = 0;
+    });
+    if (n <= 0) return 1;
+    cache[ci][li].store(n, std::memory_order_relaxed);
+    return n;
 }
 
 hipError_t launch_jacobi(ssl_c64 *A, const int32_t *kstatus, int F, int M, int Ns, int max_sweeps,

@@ -1,11 +1,10 @@
 // Bin integration (eq.6 of arXiv 2504.03373) and peak search (Sec. III-A, last paragraph).
 //
 // Pbar[d] = sum_f P[f, d].  Deterministic, atomics-free order: bins are summed in ascending order
-// inside fixed chunks of SSL_BINSUM_CHUNK bins (one thread per (direction, chunk)), then the chunk
-// partials in ascending chunk order.  The same launch finishes with the peak search: the last
-// workgroup to complete (a ticket on a device counter, released with a device-scope fence) sums
-// the partials and searches the peaks, then re-arms the counter for the next launch.  Nothing
-// ever waits on another workgroup.
+// inside fixed chunks of SSL_BINSUM_CHUNK bins (one thread per (direction, chunk), the whole chip
+// busy), then a second launch (one workgroup per block) sums the chunk partials in ascending chunk
+// order and searches the peaks.  The launch boundary makes the partials visible: no device-scope
+// fence per workgroup (each is an L2 write-back on this multi-XCD part) and no completion counter.
 //
 // Peak rule on the n_el x n_az grid (d = el * n_az + az): d is a local maximum when it beats each
 // of its 8 neighbours -- azimuth circular, elevation clamped -- where "beats" means a larger value,
@@ -15,7 +14,8 @@
 
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;         // partial sums
+constexpr int kFinal = 1024;          // final sum + peak search, one workgroup per block
 constexpr int kLdsPbar = 8192;        // Pbar staged in LDS when D <= this
 
 __device__ __forceinline__ bool beats(float va, int a, float vb, int b)
@@ -54,14 +54,14 @@ __device__ void search_peaks(const float *pb, int D, int n_az, int n_el, int Ns,
     const int tid = threadIdx.x;
     const bool use_cand = D <= kLdsPbar;
     if (use_cand) {
-        for (int d = tid; d < D; d += kThreads) cand[d] = is_local_max(pb, n_el, n_az, d) ? 1 : 0;
+        for (int d = tid; d < D; d += kFinal) cand[d] = is_local_max(pb, n_el, n_az, d) ? 1 : 0;
     }
     __syncthreads();
     for (int k = 0; k < Ns; ++k) {
         // each thread: best remaining candidate among its directions
         float bv = 0.f;
         int bi = -1;
-        for (int d = tid; d < D; d += kThreads) {
+        for (int d = tid; d < D; d += kFinal) {
             bool c = use_cand ? (cand[d] != 0) : is_local_max(pb, n_el, n_az, d);
             if (!c) continue;
             bool taken = false;
@@ -76,7 +76,7 @@ __device__ void search_peaks(const float *pb, int D, int n_az, int n_el, int Ns,
         red_v[tid] = bv;
         red_i[tid] = bi;
         __syncthreads();
-        for (int s = kThreads / 2; s > 0; s >>= 1) {
+        for (int s = kFinal / 2; s > 0; s >>= 1) {
             if (tid < s) {
                 const int oi = red_i[tid + s];
                 const float ov = red_v[tid + s];
@@ -96,103 +96,105 @@ __device__ void search_peaks(const float *pb, int D, int n_az, int n_el, int Ns,
     }
 }
 
-// Workgroup (dc, ch) of an ndc x nch grid over one block's [F][D] spectrum.
-__device__ __forceinline__ void binsum_peaks_body(
-    const float *__restrict__ P, int F, int D, float *__restrict__ Pbar, float *__restrict__ part,
-    unsigned int *__restrict__ counter, int n_az, int n_el, int Ns, int32_t *__restrict__ peaks,
-    float *__restrict__ peak_val, int dc, int ch, int ndc, int nch)
+// Partial sums: thread (dc, ch, tid) sums bins ch*CHUNK .. +CHUNK-1 of direction dc*kThreads+tid.
+__device__ __forceinline__ void binsum_part_body(const float *__restrict__ P, int F, int D,
+                                                 float *__restrict__ part, int dc, int ch)
+{
+    const int d = dc * kThreads + (int)threadIdx.x;
+    if (d >= D) return;
+    // all loads of the chunk in flight at once, then the sum in ascending bin order
+    // (absent bins of a short last chunk add an exact 0)
+    const int f0 = ch * SSL_BINSUM_CHUNK;
+    const int nf = min(F - f0, SSL_BINSUM_CHUNK);
+    float v[SSL_BINSUM_CHUNK];
+#pragma unroll
+    for (int i = 0; i < SSL_BINSUM_CHUNK; ++i)
+        v[i] = (i < nf) ? P[(size_t)(f0 + i) * D + d] : 0.0f;
+    float s = 0.f;
+#pragma unroll
+    for (int i = 0; i < SSL_BINSUM_CHUNK; ++i) s += v[i];
+    part[(size_t)ch * D + d] = s;
+}
+
+// Final sum over the nch chunk partials (ascending) and the peak search (peaks may be null).
+__device__ __forceinline__ void binsum_final_body(const float *__restrict__ part, int nch, int D,
+                                                  float *__restrict__ Pbar, int n_az, int n_el,
+                                                  int Ns, int32_t *__restrict__ peaks,
+                                                  float *__restrict__ peak_val)
 {
     __shared__ float pb_s[kLdsPbar];
     __shared__ unsigned char cand[kLdsPbar];
-    __shared__ float red_v[kThreads];
-    __shared__ int red_i[kThreads];
+    __shared__ float red_v[kFinal];
+    __shared__ int red_i[kFinal];
     __shared__ int chosen[SSL_MAX_M];
-    __shared__ int is_last;
     const int tid = threadIdx.x;
-    const int d = dc * kThreads + tid;
-    if (d < D) {
-        // all loads of the chunk in flight at once, then the sum in ascending bin order
-        // (absent bins of a short last chunk add an exact 0)
-        const int f0 = ch * SSL_BINSUM_CHUNK;
-        const int nf = min(F - f0, SSL_BINSUM_CHUNK);
-        float v[SSL_BINSUM_CHUNK];
-#pragma unroll
-        for (int i = 0; i < SSL_BINSUM_CHUNK; ++i)
-            v[i] = (i < nf) ? P[(size_t)(f0 + i) * D + d] : 0.0f;
-        float s = 0.f;
-#pragma unroll
-        for (int i = 0; i < SSL_BINSUM_CHUNK; ++i) s += v[i];
-        part[(size_t)ch * D + d] = s;
-    }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) {
-        const unsigned int ticket = atomicAdd(counter, 1u);
-        is_last = (ticket == (unsigned int)(ndc * nch) - 1u) ? 1 : 0;
-    }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
     const bool lds = D <= kLdsPbar;
-    for (int e = tid; e < D; e += kThreads) {
+    for (int e = tid; e < D; e += kFinal) {
         float s = 0.f;
         int c = 0;
         for (; c + 8 <= nch; c += 8) {
             float v[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
-                v[i] = __hip_atomic_load(&part[(size_t)(c + i) * D + e], __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
+            for (int i = 0; i < 8; ++i) v[i] = part[(size_t)(c + i) * D + e];
 #pragma unroll
             for (int i = 0; i < 8; ++i) s += v[i];
         }
-        for (; c < nch; ++c)
-            s += __hip_atomic_load(&part[(size_t)c * D + e], __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+        for (; c < nch; ++c) s += part[(size_t)c * D + e];
         Pbar[e] = s;
         if (lds) pb_s[e] = s;
     }
     __syncthreads();
-    if (tid == 0) *counter = 0u;     // re-arm for the next launch on this stream
     if (peaks != nullptr)
         search_peaks(lds ? pb_s : Pbar, D, n_az, n_el, Ns, peaks, peak_val, cand, red_v, red_i,
                      chosen);
 }
 
-__global__ __launch_bounds__(kThreads) void binsum_peaks(
-    const float *__restrict__ P, int F, int D, float *__restrict__ Pbar, float *__restrict__ part,
-    unsigned int *__restrict__ counter, int n_az, int n_el, int Ns, int32_t *__restrict__ peaks,
-    float *__restrict__ peak_val)
+__global__ __launch_bounds__(kThreads) void binsum_part(const float *__restrict__ P, int F, int D,
+                                                        float *__restrict__ part)
 {
-    binsum_peaks_body(P, F, D, Pbar, part, counter, n_az, n_el, Ns, peaks, peak_val, blockIdx.x,
-                      blockIdx.y, gridDim.x, gridDim.y);
+    binsum_part_body(P, F, D, part, blockIdx.x, blockIdx.y);
 }
 
-// Batch: grid z = block; workgroups outside a block's own (direction, bin) chunk grid leave at once
-// and never touch its counter.
-__global__ __launch_bounds__(kThreads) void binsum_peaks_batch(const BlockDev *__restrict__ blk)
+__global__ __launch_bounds__(kFinal) void binsum_final(const float *__restrict__ part, int nch,
+                                                       int D, float *__restrict__ Pbar, int n_az,
+                                                       int n_el, int Ns,
+                                                       int32_t *__restrict__ peaks,
+                                                       float *__restrict__ peak_val)
+{
+    binsum_final_body(part, nch, D, Pbar, n_az, n_el, Ns, peaks, peak_val);
+}
+
+// Batch: grid z (partials) or x (final) = block; workgroups outside a block's own (direction,
+// bin) chunk grid leave at once.
+__global__ __launch_bounds__(kThreads) void binsum_part_batch(const BlockDev *__restrict__ blk)
 {
     const BlockDev &B = blk[blockIdx.z];
     const int ndc = (B.D + kThreads - 1) / kThreads;
     const int nch = (B.F + SSL_BINSUM_CHUNK - 1) / SSL_BINSUM_CHUNK;
     if ((int)blockIdx.x >= ndc || (int)blockIdx.y >= nch) return;
-    binsum_peaks_body(B.P, B.F, B.D, B.Pbar, B.part, B.counter, B.n_az, B.n_el, B.Ns, B.peaks,
-                      B.peak_val, blockIdx.x, blockIdx.y, ndc, nch);
+    binsum_part_body(B.P, B.F, B.D, B.part, blockIdx.x, blockIdx.y);
 }
 
-__global__ __launch_bounds__(kThreads) void peaks_only(const float *__restrict__ Pbar, int D,
-                                                       int n_az, int n_el, int Ns,
-                                                       int32_t *__restrict__ peaks,
-                                                       float *__restrict__ peak_val)
+__global__ __launch_bounds__(kFinal) void binsum_final_batch(const BlockDev *__restrict__ blk)
+{
+    const BlockDev &B = blk[blockIdx.x];
+    const int nch = (B.F + SSL_BINSUM_CHUNK - 1) / SSL_BINSUM_CHUNK;
+    binsum_final_body(B.part, nch, B.D, B.Pbar, B.n_az, B.n_el, B.Ns, B.peaks, B.peak_val);
+}
+
+__global__ __launch_bounds__(kFinal) void peaks_only(const float *__restrict__ Pbar, int D,
+                                                     int n_az, int n_el, int Ns,
+                                                     int32_t *__restrict__ peaks,
+                                                     float *__restrict__ peak_val)
 {
     __shared__ float pb_s[kLdsPbar];
     __shared__ unsigned char cand[kLdsPbar];
-    __shared__ float red_v[kThreads];
-    __shared__ int red_i[kThreads];
+    __shared__ float red_v[kFinal];
+    __shared__ int red_i[kFinal];
     __shared__ int chosen[SSL_MAX_M];
     const bool lds = D <= kLdsPbar;
     if (lds)
-        for (int e = threadIdx.x; e < D; e += kThreads) pb_s[e] = Pbar[e];
+        for (int e = threadIdx.x; e < D; e += kFinal) pb_s[e] = Pbar[e];
     __syncthreads();
     search_peaks(lds ? pb_s : Pbar, D, n_az, n_el, Ns, peaks, peak_val, cand, red_v, red_i,
                  chosen);
@@ -201,13 +203,16 @@ __global__ __launch_bounds__(kThreads) void peaks_only(const float *__restrict__
 }  // namespace
 
 hipError_t launch_binsum_peaks(const float *P, int F, int D, float *Pbar, float *part,
-                               unsigned int *counter, int n_az, int n_el, int Ns, int32_t *peaks,
-                               float *peak_val, hipStream_t st)
+                               int n_az, int n_el, int Ns, int32_t *peaks, float *peak_val,
+                               hipStream_t st)
 {
     const int nch = (F + SSL_BINSUM_CHUNK - 1) / SSL_BINSUM_CHUNK;
-    const dim3 grid((D + kThreads - 1) / kThreads, nch);
-    hipLaunchKernelGGL(binsum_peaks, grid, dim3(kThreads), 0, st, P, F, D, Pbar, part, counter,
-                       n_az, n_el, Ns, peaks, peak_val);
+    hipLaunchKernelGGL(binsum_part, dim3((D + kThreads - 1) / kThreads, nch), dim3(kThreads), 0,
+                       st, P, F, D, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(binsum_final, dim3(1), dim3(kFinal), 0, st, part, nch, D, Pbar, n_az, n_el,
+                       Ns, peaks, peak_val);
     return hipGetLastError();
 }
 
@@ -217,15 +222,18 @@ hipError_t launch_binsum_batch(const BlockDev *blk, int nblocks, int max_dchunks
                                hipStream_t st)
 {
     if (nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(binsum_peaks_batch, dim3(max_dchunks, max_fchunks, nblocks),
+    hipLaunchKernelGGL(binsum_part_batch, dim3(max_dchunks, max_fchunks, nblocks),
                        dim3(kThreads), 0, st, blk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(binsum_final_batch, dim3(nblocks), dim3(kFinal), 0, st, blk);
     return hipGetLastError();
 }
 
 hipError_t launch_peaks(const float *Pbar, int n_az, int n_el, int Ns, int32_t *peaks,
                         float *peak_val, hipStream_t st)
 {
-    hipLaunchKernelGGL(peaks_only, dim3(1), dim3(kThreads), 0, st, Pbar, n_az * n_el, n_az, n_el,
+    hipLaunchKernelGGL(peaks_only, dim3(1), dim3(kFinal), 0, st, Pbar, n_az * n_el, n_az, n_el,
                        Ns, peaks, peak_val);
     return hipGetLastError();
 }

@@ -24,9 +24,8 @@ struct ssl_ctx_s {
     // workspace for ssl_localize / ssl_music_spectrum (grown on demand, never shrunk)
     void *ws;
     size_t ws_bytes;
-    // bin-sum scratch: partials [chunks][D] + one completion counter, zeroed at allocation
+    // bin-sum scratch: partials [chunks][D]
     float *binsum_part;
-    unsigned int *binsum_counter;
     size_t binsum_floats;
     // per-kernel event timing (ssl_ctx_timing)
     struct Timed {
@@ -81,7 +80,6 @@ struct BlockDev {
     const void *H;
     float2 *R, *A, *En;             // workspace slices
     float *P, *part;
-    unsigned int *counter;          // bin-sum completion counter (starts and ends at 0)
     int32_t *peaks, *status;        // caller outputs
     float *peak_val, *Pbar;
 };
@@ -132,10 +130,11 @@ hipError_t launch_jacobi(ssl_c64 *A, const int32_t *kstatus, int F, int M, int N
                          int max_sweeps, int lanes, ssl_c64 *En, float *sigma,
                          int32_t *bin_status, int32_t *conv, hipStream_t st);
 bool jacobi_variant_ok(int cls, int lanes);
+int jacobi_persistent_wg_per_cu(int cls, int lanes);
 hipError_t launch_steer(const void *H, ssl_prec hprec, const ssl_c64 *En, int F, int D, int M,
                         int Ns, int p, const int32_t *bin_status, float *P, hipStream_t st);
 hipError_t launch_binsum_peaks(const float *P, int F, int D, float *Pbar, float *part,
-                               unsigned int *counter, int n_az, int n_el, int Ns, int32_t *peaks,
-                               float *peak_val, hipStream_t st);
+                               int n_az, int n_el, int Ns, int32_t *peaks, float *peak_val,
+                               hipStream_t st);
 hipError_t launch_peaks(const float *Pbar, int n_az, int n_el, int Ns, int32_t *peaks,
                         float *peak_val, hipStream_t st);
