@@ -627,6 +627,13 @@ struct Plan {
     int nblocks = 0, n_items = 0, max_dc = 0, max_fc = 0;
 };
 
+// Device tail of the descriptor buffer after the four item lists: steering groups (first, count)
+// into a block-index list; a group = the blocks of one size class that share a steering table.
+struct GroupArrays {
+    const int2 *groups;
+    const int *gblocks;
+};
+
 ssl_status counters_reserve(ssl_ctx ctx, size_t n)
 {
     if (ctx->n_counters >= n) return SSL_OK;
@@ -698,7 +705,7 @@ void build_list(const std::vector<int> &cls_of_block, const std::vector<int> &F_
 }
 
 hipError_t enqueue_batch(ssl_ctx ctx, const Plan &P, const BlockDev *blk, const int2 *lists,
-                         ssl_prec prec, hipStream_t st)
+                         GroupArrays ga, ssl_prec prec, hipStream_t st)
 {
     const int2 *l_corr = lists, *l_wh = lists + P.n_items, *l_jac = lists + 2 * P.n_items,
                *l_st = lists + 3 * P.n_items;
@@ -725,7 +732,8 @@ hipError_t enqueue_batch(ssl_ctx ctx, const Plan &P, const BlockDev *blk, const 
     }
     for (const Seg &s : P.steer) {
         e = timed(ctx, SSL_K_STEER, st, [&] {
-            return launch_steer_batch(blk, l_st + s.start, s.count, s.cls, s.extra, prec, st);
+            return launch_steer_batch(blk, l_st + s.start, s.count, ga.groups, ga.gblocks, s.cls,
+                                      s.extra, prec, st);
         });
         if (e != hipSuccess) return e;
     }
@@ -892,7 +900,8 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
     DeviceGuard dg(ctx->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const size_t desc_bytes = align256(sizeof(BlockDev) * nblocks);
-    const size_t list_bytes = sizeof(int2) * 4 * (size_t)n_items;
+    const size_t list_bytes = sizeof(int2) * 4 * (size_t)n_items +
+                              (sizeof(int2) + sizeof(int)) * (size_t)nblocks;
     if ((s = ws_reserve(ctx, ws_total)) != SSL_OK) return s;
     if ((s = counters_reserve(ctx, kJacobiQueues)) != SSL_OK) return s;
     if ((s = bdesc_reserve(ctx, desc_bytes + list_bytes)) != SSL_OK) return s;
@@ -905,6 +914,7 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
     const BlockDev *db = static_cast<const BlockDev *>(ctx->bdesc_dev);
     const int2 *dl =
         reinterpret_cast<const int2 *>(static_cast<char *>(ctx->bdesc_dev) + desc_bytes);
+    const GroupArrays ga{dl + 4 * n_items, reinterpret_cast<const int *>(dl + 4 * n_items + nblocks)};
 
     Plan plan;
     plan.nblocks = nblocks;
@@ -959,7 +969,47 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
     build_list(c_corr, Fs, hl, plan.corr);
     build_list(c_wh, Fs, hl + n_items, plan.whiten);
     build_list(c_jac, Fs, hl + 2 * n_items, plan.jac);
-    build_list(c_st, Fs, hl + 3 * n_items, plan.steer);
+    {
+        // steering groups (first-appearance order), then (group, bin) items by ascending class
+        int2 *hg = hl + 4 * n_items;
+        int *hgb = reinterpret_cast<int *>(hg + nblocks);
+        std::vector<int> first;                       // first block of each group
+        std::vector<std::vector<int>> members;
+        for (int b = 0; b < nblocks; ++b) {
+            int g = 0;
+            for (; g < (int)first.size(); ++g) {
+                const BlockDev &A = hb[first[g]], &B = hb[b];
+                if (c_st[first[g]] == c_st[b] && A.H == B.H && A.F == B.F && A.D == B.D &&
+                    A.M == B.M)
+                    break;
+            }
+            if (g == (int)first.size()) {
+                first.push_back(b);
+                members.emplace_back();
+            }
+            members[g].push_back(b);
+            key.push_back(g);                         // the sharing pattern shapes the launch
+        }
+        int at = 0;
+        for (size_t g = 0; g < members.size(); ++g) {
+            hg[g] = make_int2(at, (int)members[g].size());
+            for (int b : members[g]) hgb[at++] = b;
+        }
+        std::vector<int> classes(c_st);
+        std::sort(classes.begin(), classes.end());
+        classes.erase(std::unique(classes.begin(), classes.end()), classes.end());
+        int2 *out = hl + 3 * n_items;
+        int pos = 0;
+        for (int c : classes) {
+            Seg sg{c, pos, 0, 0};
+            for (size_t g = 0; g < members.size(); ++g) {
+                if (c_st[first[g]] != c) continue;
+                for (int f = 0; f < hb[first[g]].F; ++f) out[pos++] = make_int2((int)g, f);
+            }
+            sg.count = pos - sg.start;
+            plan.steer.push_back(sg);
+        }
+    }
     for (Seg &sg : plan.jac)
         sg.extra = std::min(sg.count, ctx->cu_count * jacobi_persistent_wg_per_cu(
                                                          sg.cls, ctx->jac_lanes[jacobi_class_index(sg.cls)]));
@@ -977,7 +1027,7 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
     if (e != hipSuccess) return hip_fail(e, "descriptor copy");
 
     if (!ctx->use_graphs || ctx->timing) {
-        e = enqueue_batch(ctx, plan, db, dl, prec, st);
+        e = enqueue_batch(ctx, plan, db, dl, ga, prec, st);
         return e == hipSuccess ? SSL_OK : hip_fail(e, "batch launch");
     }
     hipGraphExec_t exec = nullptr;
@@ -993,7 +1043,7 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
         }
         e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-        hipError_t le = enqueue_batch(ctx, plan, db, dl, prec, ctx->cap_stream);
+        hipError_t le = enqueue_batch(ctx, plan, db, dl, ga, prec, ctx->cap_stream);
         hipGraph_t graph = nullptr;
         e = hipStreamEndCapture(ctx->cap_stream, &graph);
         if (le != hipSuccess) {

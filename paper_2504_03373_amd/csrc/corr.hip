@@ -29,43 +29,36 @@ __device__ __forceinline__ void tile_coords(int t, int NT, int &I, int &J)
     J = I + t;
 }
 
-// Write one 16x16 MFMA result tile.  Lane l, register r holds element (4*(l/16) + r, l%16).
-template <typename OutT>
-__device__ __forceinline__ void store_tile(OutT *Rf, int M, int I, int J, const floatx4 &re,
-                                           const floatx4 &im, float scale, int accumulate,
-                                           int lane)
+// The bin's result goes through LDS (row stride MP + 1 complex, no bank conflicts on the mirrored
+// writes) and leaves in coalesced rows.  Lane l, register r of a tile holds element
+// (4*(l/16) + r, l%16); the lower triangle is the conjugate of the same registers.
+__device__ __forceinline__ void tile_to_lds(float2 *Rs, int RS, int I, int J, const floatx4 &re,
+                                            const floatx4 &im, float scale, int lane)
 {
     const int j = 16 * J + (lane & 15);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = 16 * I + 4 * (lane >> 4) + r;
-        if (i >= M || j >= M) continue;
         if (I == J && i > j) continue;      // mirrored from the (j, i) lane
-        float vr = re[r] * scale;
-        float vi = (i == j) ? 0.0f : im[r] * scale;
-        OutT *p = Rf + (size_t)i * M + j;
-        OutT *q = Rf + (size_t)j * M + i;
+        const float vr = re[r] * scale;
+        const float vi = (i == j) ? 0.0f : im[r] * scale;
+        Rs[i * RS + j] = make_float2(vr, vi);
+        if (i != j) Rs[j * RS + i] = make_float2(vr, -vi);
+    }
+}
+
+__device__ __forceinline__ void lds_to_out(const float2 *Rs, int RS, int M, int accumulate,
+                                           float2 *__restrict__ Rf, int tid)
+{
+    for (int e = tid; e < M * M; e += kThreads) {
+        const int i = e / M, j = e - i * M;
+        float2 v = Rs[i * RS + j];
         if (accumulate) {
-            OutT a = *p;
-            a.x += vr;
-            a.y += vi;
-            *p = a;
-            if (i != j) {
-                OutT b = *q;
-                b.x += vr;
-                b.y -= vi;
-                *q = b;
-            }
-        } else {
-            OutT a;
-            a.x = vr;
-            a.y = vi;
-            *p = a;
-            if (i != j) {
-                a.y = -vi;
-                *q = a;
-            }
+            const float2 a = Rf[e];
+            v.x += a.x;
+            v.y += a.y;
         }
+        Rf[e] = v;
     }
 }
 
@@ -81,8 +74,10 @@ __device__ __forceinline__ void corr_f32_bin(const float2 *__restrict__ Xf, int 
     constexpr int NT = MP / 16;
     constexpr int NTILE = NT * (NT + 1) / 2;
     constexpr int TPW = (NTILE + 3) / 4;       // tiles per wave
-    __shared__ float Zr[kChunk * S];
-    __shared__ float Zi[kChunk * S];
+    constexpr int RS = MP + 1;
+    static_assert(2 * kChunk * S * 4 >= MP * RS * 8, "result staging exceeds the frame buffer");
+    __shared__ __attribute__((aligned(16))) float Z[2 * kChunk * S];
+    float *Zr = Z, *Zi = Z + kChunk * S;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -98,12 +93,21 @@ __device__ __forceinline__ void corr_f32_bin(const float2 *__restrict__ Xf, int 
     for (int t0 = 0; t0 < T; t0 += kChunk) {
         const int nf = min(kChunk, T - t0);
         __syncthreads();
-        for (int e = tid; e < kChunk * MP; e += kThreads) {
+        // every load of the chunk in flight before the first LDS store
+        constexpr int NIT = kChunk * MP / kThreads;
+        float2 v[NIT];
+#pragma unroll
+        for (int u = 0; u < NIT; ++u) {
+            const int e = tid + u * kThreads;
             const int tt = e / MP, m = e - tt * MP;
-            float2 v = make_float2(0.f, 0.f);
-            if (tt < nf && m < M) v = Xf[(size_t)(t0 + tt) * sT + m];
-            Zr[tt * S + m] = v.x;
-            Zi[tt * S + m] = v.y;
+            v[u] = (tt < nf && m < M) ? Xf[(size_t)(t0 + tt) * sT + m] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < NIT; ++u) {
+            const int e = tid + u * kThreads;
+            const int tt = e / MP, m = e - tt * MP;
+            Zr[tt * S + m] = v[u].x;
+            Zi[tt * S + m] = v[u].y;
         }
         __syncthreads();
         const int nsteps = (nf + 3) >> 2;
@@ -126,15 +130,19 @@ __device__ __forceinline__ void corr_f32_bin(const float2 *__restrict__ Xf, int 
             }
         }
     }
+    __syncthreads();                           // frames no longer needed: Z holds the result
+    float2 *Rs = reinterpret_cast<float2 *>(Z);
 #pragma unroll
     for (int q = 0; q < TPW; ++q) {
         const int tile = wave + 4 * q;
         if (tile < NTILE) {
             int I, J;
             tile_coords(tile, NT, I, J);
-            store_tile(Rf, M, I, J, acc_re[q], acc_im[q], scale, accumulate, lane);
+            tile_to_lds(Rs, RS, I, J, acc_re[q], acc_im[q], scale, lane);
         }
     }
+    __syncthreads();
+    lds_to_out(Rs, RS, M, accumulate, Rf, tid);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -167,9 +175,12 @@ __device__ __forceinline__ void corr_lp_bin(const float2 *__restrict__ Xf, int T
     constexpr int NT = MP / 16;
     constexpr int NTILE = NT * (NT + 1) / 2;
     constexpr int TPW = (NTILE + 3) / 4;
-    __shared__ __attribute__((aligned(16))) E Pr[MP * S];
-    __shared__ __attribute__((aligned(16))) E Pi[MP * S];
-    __shared__ __attribute__((aligned(16))) E Pn[MP * S];   // -Re, for the Im product
+    constexpr int RS = MP + 1;
+    constexpr int PLANES = 3 * MP * S * (int)sizeof(E), RESULT = MP * RS * 8;
+    __shared__ __attribute__((aligned(16))) float Z[(PLANES > RESULT ? PLANES : RESULT) / 4];
+    E *Pr = reinterpret_cast<E *>(Z);
+    E *Pi = Pr + MP * S;
+    E *Pn = Pi + MP * S;                                     // -Re, for the Im product
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -184,11 +195,20 @@ __device__ __forceinline__ void corr_lp_bin(const float2 *__restrict__ Xf, int T
     for (int t0 = 0; t0 < T; t0 += kChunk) {
         const int nf = min(kChunk, T - t0);
         __syncthreads();
-        for (int e = tid; e < kChunk * MP; e += kThreads) {
+        // every load of the chunk in flight before the first LDS store
+        constexpr int NIT = kChunk * MP / kThreads;
+        float2 v[NIT];
+#pragma unroll
+        for (int u = 0; u < NIT; ++u) {
+            const int e = tid + u * kThreads;
             const int tt = e / MP, m = e - tt * MP;
-            float2 v = make_float2(0.f, 0.f);
-            if (tt < nf && m < M) v = Xf[(size_t)(t0 + tt) * sT + m];
-            const E r = (E)v.x, im = (E)v.y;
+            v[u] = (tt < nf && m < M) ? Xf[(size_t)(t0 + tt) * sT + m] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < NIT; ++u) {
+            const int e = tid + u * kThreads;
+            const int tt = e / MP, m = e - tt * MP;
+            const E r = (E)v[u].x, im = (E)v[u].y;
             Pr[m * S + tt] = r;
             Pi[m * S + tt] = im;
             Pn[m * S + tt] = -r;
@@ -217,15 +237,19 @@ __device__ __forceinline__ void corr_lp_bin(const float2 *__restrict__ Xf, int T
             }
         }
     }
+    __syncthreads();                           // frames no longer needed: Z holds the result
+    float2 *Rs = reinterpret_cast<float2 *>(Z);
 #pragma unroll
     for (int q = 0; q < TPW; ++q) {
         const int tile = wave + 4 * q;
         if (tile < NTILE) {
             int I, J;
             tile_coords(tile, NT, I, J);
-            store_tile(Rf, M, I, J, acc_re[q], acc_im[q], scale, accumulate, lane);
+            tile_to_lds(Rs, RS, I, J, acc_re[q], acc_im[q], scale, lane);
         }
     }
+    __syncthreads();
+    lds_to_out(Rs, RS, M, accumulate, Rf, tid);
 }
 
 // ---------------------------------------------------------------------------------------------

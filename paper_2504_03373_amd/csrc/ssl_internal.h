@@ -91,8 +91,8 @@ inline int whiten_class(int M) { return M <= 16 ? 16 : M <= 32 ? 32 : 64; }
 inline int jacobi_class(int M) { return M <= 8 ? 8 : M <= 16 ? 16 : M <= 32 ? 32 : 64; }
 inline int steer_class(int M, int Ns)
 {
-    const int ncol = 2 * (M - Ns);
-    return ncol <= 16 ? 1 : ncol <= 32 ? 2 : ncol <= 64 ? 4 : 8;
+    const int nn = M - Ns;                 // noise vectors = B columns, 16 per column tile
+    return nn <= 16 ? 1 : nn <= 32 ? 2 : 4;
 }
 
 // Batched launchers.  `items` lists (block, bin) pairs whose blocks share the kernel's size class.
@@ -104,8 +104,9 @@ hipError_t launch_whiten_batch(const BlockDev *blk, const int2 *items, int n_ite
 hipError_t launch_jacobi_batch(const BlockDev *blk, const int2 *items, int n_items, int cls,
                                int lanes, int max_sweeps, unsigned int *queue, int grid,
                                hipStream_t st);
-hipError_t launch_steer_batch(const BlockDev *blk, const int2 *items, int n_items, int cls,
-                              int max_dtiles, ssl_prec hprec, hipStream_t st);
+hipError_t launch_steer_batch(const BlockDev *blk, const int2 *items, int n_items,
+                              const int2 *groups, const int *gblocks, int cls, int max_dtiles,
+                              ssl_prec hprec, hipStream_t st);
 hipError_t launch_binsum_batch(const BlockDev *blk, int nblocks, int max_dchunks,
                                int max_fchunks, hipStream_t st);
 int jacobi_threads(int cls, int lanes);

@@ -3,14 +3,19 @@
 //   den  = sum_c |G_dc|^p     (p = 2: the projector form; p = 1: the literal form of eq.5)
 //   P    = |H_d|^2 / max(den, FLT_MIN)
 //
-// Complex product as one real MFMA product.  Flatten H row d to 2M reals h = (Re H_d0, Im H_d0,
-// Re H_d1, ...) -- exactly its complex64 storage -- and give each noise vector e_c two real
-// columns, (Re e, Im e)-interleaved and (Im e, -Re e)-interleaved; then
-//   h . col(2c) = Re(H_d^H e_c),   h . col(2c+1) = Im(H_d^H e_c),
-// so G is a [D x 2M] . [2M x 2Nn] real product and |G_dc|^2 is the sum of squares of the two
-// adjacent outputs.  The B operand (E_n, <= 64 KB) is staged once per workgroup in LDS as
-// [column][k]; the A operand streams from HBM (the steering table is the dominant traffic).
-// Workgroup = 8 waves x 16 directions; a wave owns 16 rows x all 2Nn columns in accumulators.
+// Complex product as real MFMA products.  Flatten steering row d to 2M reals
+// h = (Re H_d0, Im H_d0, Re H_d1, ...) -- exactly its storage -- and let h' = (-Im H_d0, Re H_d0,
+// -Im H_d1, ...).  With the noise vector e_c flattened the same way (its complex64 storage),
+//   h . e_c = Re(H_d^H e_c),   h' . e_c = Im(H_d^H e_c),
+// so one B operand (E_n in its natural layout, <= 64 columns) serves two A operands, and
+// |G_dc|^2 = (h . e_c)^2 + (h' . e_c)^2 needs no cross-lane exchange.  h' is formed in registers
+// from h (a swap and a sign flip), so the steering table is read once.
+//
+// Workgroup = 8 waves x 16 directions of one bin; a wave keeps its 16-row strip of H (and h') in
+// registers and owns all Nn columns in accumulators.  Workgroups are mapped XCD by XCD so that
+// all direction tiles of a bin share one L2.  The batched kernel loops over every block
+// that shares the steering table: H is read once per (bin, direction tile) for all of them and
+// only E_n (staged in LDS) changes from block to block.
 #include "ssl_internal.h"
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -21,7 +26,6 @@ namespace {
 
 constexpr int kThreads = 512;            // 8 waves x 16 directions
 constexpr int kRowsPerBlock = 128;
-constexpr int kMaxColTiles = 8;          // 2 * Nn <= 126 -> 8 tiles of 16 columns
 
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v)
@@ -37,140 +41,6 @@ __device__ __forceinline__ float sum16(float v)
     return v;
 }
 
-// Shared epilogue.  acc[ct][r] = G-column (16 ct + l%16) of row (4 (l/16) + r) of this wave's
-// 16-row strip.  hn = partial |h|^2 of row l%16 over this lane's k-slice.
-template <int NCT>
-__device__ __forceinline__ void finish_rows(const floatx4 (&acc)[NCT], float hn, int p, int lane,
-                                            int wave, int d0, int D, bool bin_ok,
-                                            float *__restrict__ Pf, float *den_s, float *nrm_s)
-{
-    float part[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        float s = 0.f;
-#pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) {
-            const float v = acc[ct][r];
-            if (p == 2) {
-                s = fmaf(v, v, s);
-            } else {
-                const float w = dpp<0xB1>(v);                 // partner column (2c <-> 2c+1)
-                const float mag = sqrtf(fmaf(v, v, w * w));
-                s += (lane & 1) ? 0.f : mag;
-            }
-        }
-        part[r] = sum16(s);
-    }
-    // |h|^2: combine the 4 k-slices (lanes l, l^16, l^32, l^48)
-    hn += __shfl_xor(hn, 16);
-    hn += __shfl_xor(hn, 32);
-    if ((lane & 15) == 0) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) den_s[wave * 16 + 4 * (lane >> 4) + r] = part[r];
-    }
-    if (lane < 16) nrm_s[wave * 16 + lane] = hn;
-    __syncthreads();
-    if (lane < 16) {
-        const int d = d0 + wave * 16 + lane;
-        if (d < D) {
-            const float den = den_s[wave * 16 + lane];
-            Pf[d] = bin_ok ? nrm_s[wave * 16 + lane] / fmaxf(den, 1.17549435e-38f) : 0.0f;
-        }
-    }
-}
-
-// Stage E_n[f] as the real B operand: Bs[col * KS + k], col < 16*NCT, k < KP (zero padded).
-template <typename E>
-__device__ __forceinline__ void stage_b(const float2 *__restrict__ Enf, int M, int Nn, E *Bs,
-                                        int KS, int NCOL, int KP, int tid)
-{
-    for (int e = tid; e < (NCOL / 2) * (KP / 2); e += kThreads) {
-        const int col2 = e / (KP / 2);           // pair of columns (2c, 2c+1)
-        const int m = e - col2 * (KP / 2);       // k = 2m, 2m+1
-        float er = 0.f, ei = 0.f;
-        if (col2 < Nn && m < M) {
-            const float2 v = Enf[(size_t)col2 * M + m];
-            er = v.x;
-            ei = v.y;
-        }
-        Bs[(2 * col2) * KS + 2 * m] = (E)er;
-        Bs[(2 * col2) * KS + 2 * m + 1] = (E)ei;
-        Bs[(2 * col2 + 1) * KS + 2 * m] = (E)ei;
-        Bs[(2 * col2 + 1) * KS + 2 * m + 1] = (E)(-er);
-    }
-}
-
-// ---------------------------------------------------------------------------------------------
-// FP32: v_mfma_f32_16x16x4f32.  Lane l = (row i = l%16, slice s = l/16) reads the float4
-// h[16 kq + 4 s .. +3] of its row; MFMA step e (0..3) contracts k = 16 kq + 4 s + e, and the B
-// operand of the same k is the float4 Bs[col][16 kq + 4 s .. +3].
-// One workgroup tile: directions d0 .. d0 + kRowsPerBlock - 1 of one bin.  Hf = the bin's [D][2M]
-// table, Enf = its [Nn][M] noise subspace, Pf = its [D] output, ok = bin status is SSL_BIN_OK.
-template <int NCT>
-__device__ __forceinline__ void steer_f32_tile(const float *__restrict__ Hf,
-                                               const float2 *__restrict__ Enf, bool ok, int D,
-                                               int M, int Ns, int p, float *__restrict__ Pf,
-                                               int d0)
-{
-    constexpr int KS_MAX = 128 + 4;
-    __shared__ __attribute__((aligned(16))) float Bs[16 * NCT * KS_MAX];
-    __shared__ float den_s[kRowsPerBlock];
-    __shared__ float nrm_s[kRowsPerBlock];
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int Nn = M - Ns;
-    const int K2 = 2 * M;
-    const int KQ = (K2 + 15) / 16;
-    const int KP = 16 * KQ;
-    const int KS = KP + 4;
-    const int NCOL = 16 * NCT;
-    stage_b<float>(Enf, M, Nn, Bs, KS, NCOL, KP, tid);
-    __syncthreads();
-
-    const int row = d0 + wave * 16 + (lane & 15);
-    const int sl = lane >> 4;
-    const float *hrow = Hf + (size_t)(row < D ? row : 0) * K2;
-    // the wave's whole 16-row strip of H in registers first: every load in flight at once
-    constexpr int KQ_MAX = 8;
-    float4 a[KQ_MAX];
-    float hn = 0.f;
-#pragma unroll
-    for (int kq = 0; kq < KQ_MAX; ++kq) {
-        const int k0 = 16 * kq + 4 * sl;
-        float2 lo = make_float2(0.f, 0.f), hi = make_float2(0.f, 0.f);
-        if (kq < KQ && row < D) {
-            if (k0 < K2) lo = *(const float2 *)(hrow + k0);          // complex element k0/2
-            if (k0 + 2 < K2) hi = *(const float2 *)(hrow + k0 + 2);
-        }
-        a[kq] = make_float4(lo.x, lo.y, hi.x, hi.y);
-    }
-#pragma unroll
-    for (int kq = 0; kq < KQ_MAX; ++kq)
-        hn = fmaf(a[kq].x, a[kq].x, fmaf(a[kq].y, a[kq].y, fmaf(a[kq].z, a[kq].z, fmaf(a[kq].w, a[kq].w, hn))));
-    floatx4 acc[NCT];
-#pragma unroll
-    for (int ct = 0; ct < NCT; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kq = 0; kq < KQ_MAX; ++kq) {
-        if (kq < KQ) {
-            const int k0 = 16 * kq + 4 * sl;
-#pragma unroll
-            for (int ct = 0; ct < NCT; ++ct) {
-                const float4 b = *(const float4 *)&Bs[(16 * ct + (lane & 15)) * KS + k0];
-                acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kq].x, b.x, acc[ct], 0, 0, 0);
-                acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kq].y, b.y, acc[ct], 0, 0, 0);
-                acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kq].z, b.z, acc[ct], 0, 0, 0);
-                acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kq].w, b.w, acc[ct], 0, 0, 0);
-            }
-        }
-    }
-    finish_rows<NCT>(acc, hn, p, lane, wave, d0, D, ok, Pf, den_s, nrm_s);
-}
-
-// ---------------------------------------------------------------------------------------------
-// bf16 / fp16: v_mfma_f32_16x16x32_{bf16,f16}.  H is stored as interleaved 16-bit pairs; lane
-// (row i = l%16, slice s = l/16) reads 8 consecutive k = 32 ks + 8 s .. +7.
 template <typename E> struct LpMfma;
 template <> struct LpMfma<__bf16> {
     typedef bf16x8 vec;
@@ -187,136 +57,350 @@ template <> struct LpMfma<_Float16> {
     }
 };
 
-template <int NCT, typename E>
-__device__ __forceinline__ void steer_lp_tile(const E *__restrict__ Hf,
-                                              const float2 *__restrict__ Enf, bool ok, int D,
-                                              int M, int Ns, int p, float *__restrict__ Pf,
-                                              int d0)
+// Per-type layout constants.  FP32: v_mfma_f32_16x16x4f32, a k-chunk of 16 reals per kq, lane
+// slice s = l/16 holding reals 16 kq + 4 s .. +3 (four MFMA steps).  16-bit: 16x16x32, a k-chunk of
+// 32 reals, lane slice holding reals 32 kq + 8 s .. +7 (one MFMA step).
+template <typename E> struct SteerCfg {
+    static constexpr bool F32 = sizeof(E) == 4;
+    static constexpr int KC = F32 ? 16 : 32;          // reals per k-chunk
+    static constexpr int KQ_MAX = 128 / KC;           // 2M <= 128
+    static constexpr int PAD = F32 ? 4 : 8;           // LDS row padding (elements)
+    static constexpr int KS_MAX = 128 + PAD;
+};
+
+// A operands of one wave: rows d0 + 16 w .. +15 of the bin's table, h and h' per k-chunk.
+template <typename E> struct AStrip;
+template <> struct AStrip<float> {
+    float4 a[8];                                       // h' is derived per k-chunk in mma()
+};
+template <typename E> struct AStrip {
+    typename LpMfma<E>::vec a[4], b[4];                // h and h'
+};
+
+// (re, im) 16-bit pairs -> (-im, re): swap the halves, flip the sign bit of the new low half.
+template <typename V>
+__device__ __forceinline__ V twist(V a)
 {
-    typedef typename LpMfma<E>::vec vec;
-    constexpr int KS_MAX = 128 + 8;
-    __shared__ __attribute__((aligned(16))) E Bs[16 * NCT * KS_MAX];
+    uint32_t w[4];
+    __builtin_memcpy(w, &a, 16);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = __builtin_amdgcn_alignbit(w[i], w[i], 16) ^ 0x8000u;
+    return __builtin_bit_cast(V, w);
+}
+
+// Loads the strip and returns the partial |h|^2 of this lane's row slice.
+template <typename E>
+__device__ __forceinline__ float load_strip(const E *__restrict__ Hf, int D, int M, int row,
+                                            int sl, AStrip<E> &S)
+{
+    typedef SteerCfg<E> C;
+    const int K2 = 2 * M;
+    const int KQ = (K2 + C::KC - 1) / C::KC;
+    const E *hrow = Hf + (size_t)(row < D ? row : 0) * K2;
+    float hn = 0.f;
+    if constexpr (C::F32) {
+#pragma unroll
+        for (int kq = 0; kq < C::KQ_MAX; ++kq) {
+            const int k0 = 16 * kq + 4 * sl;
+            float2 lo = make_float2(0.f, 0.f), hi = make_float2(0.f, 0.f);
+            if (kq < KQ && row < D) {
+                if (k0 < K2) lo = *(const float2 *)(hrow + k0);          // complex element k0/2
+                if (k0 + 2 < K2) hi = *(const float2 *)(hrow + k0 + 2);
+            }
+            S.a[kq] = make_float4(lo.x, lo.y, hi.x, hi.y);
+            hn = fmaf(lo.x, lo.x, fmaf(lo.y, lo.y, fmaf(hi.x, hi.x, fmaf(hi.y, hi.y, hn))));
+        }
+    } else {
+        typedef typename LpMfma<E>::vec vec;
+#pragma unroll
+        for (int kq = 0; kq < C::KQ_MAX; ++kq) {
+            const int m0 = 16 * kq + 4 * sl;            // complex element of real 32 kq + 8 s
+            uint32_t w[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                w[i] = (kq < KQ && row < D && m0 + i < M)
+                           ? *(const uint32_t *)(hrow + 2 * (m0 + i)) : 0u;
+            S.a[kq] = __builtin_bit_cast(vec, w);
+            S.b[kq] = twist(S.a[kq]);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float fv = (float)S.a[kq][e];
+                hn = fmaf(fv, fv, hn);
+            }
+        }
+    }
+    return hn;
+}
+
+// E_n[f] as the B operand: Bs[c * KS + k] = real k of noise vector c (k < 2M), zero for c >= Nn
+// or k >= 2M up to the k-chunk padding KP.  Thread tid owns elements e = tid + u * kThreads of a
+// NCOL x 64 complex grid (column c = e / 64, element m = e % 64: shifts, no division); load_b puts
+// them in registers (all loads in flight at once), store_b writes those with m < KP / 2.
+template <int NCT> struct BStage {
+    static constexpr int NIT = 16 * NCT * 64 / kThreads;
+    float2 v[NIT];
+};
+
+template <int NCT>
+__device__ __forceinline__ void load_b(const float2 *__restrict__ Enf, int M, int Nn, int tid,
+                                       BStage<NCT> &st)
+{
+#pragma unroll
+    for (int u = 0; u < BStage<NCT>::NIT; ++u) {
+        const int e = tid + u * kThreads;
+        const int c = e >> 6, m = e & 63;
+        st.v[u] = (c < Nn && m < M) ? Enf[(size_t)c * M + m] : make_float2(0.f, 0.f);
+    }
+}
+
+template <int NCT, typename E>
+__device__ __forceinline__ void store_b(const BStage<NCT> &st, E *Bs, int KS, int KP, int tid)
+{
+#pragma unroll
+    for (int u = 0; u < BStage<NCT>::NIT; ++u) {
+        const int e = tid + u * kThreads;
+        const int c = e >> 6, m = e & 63;
+        if (2 * m >= KP) continue;
+        const float2 v = st.v[u];
+        if constexpr (sizeof(E) == 4) {
+            *(float2 *)&Bs[c * KS + 2 * m] = v;
+        } else {
+            E pr[2] = {(E)v.x, (E)v.y};
+            *(uint32_t *)&Bs[c * KS + 2 * m] = __builtin_bit_cast(uint32_t, pr);
+        }
+    }
+}
+
+// acc1/acc2[ct] += A(h / h') . B over the k-chunks.
+template <int NCT, typename E>
+__device__ __forceinline__ void mma(const AStrip<E> &S, const E *Bs, int KS, int KQ, int lane,
+                                    floatx4 (&acc1)[NCT], floatx4 (&acc2)[NCT])
+{
+    typedef SteerCfg<E> C;
+    const int sl = lane >> 4;
+    const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kq = 0; kq < C::KQ_MAX; ++kq) {
+        if (kq >= KQ) break;
+        if constexpr (C::F32) {
+            const int k0 = 16 * kq + 4 * sl;
+            const float4 a = S.a[kq];
+            const float4 a2 = make_float4(-a.y, a.x, -a.w, a.z);      // h'
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct) {
+                const float4 b = *(const float4 *)&Bs[(16 * ct + (lane & 15)) * KS + k0];
+                acc1[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, kq ? acc1[ct] : zero, 0, 0, 0);
+                acc2[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2.x, b.x, kq ? acc2[ct] : zero, 0, 0, 0);
+                acc1[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc1[ct], 0, 0, 0);
+                acc2[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2.y, b.y, acc2[ct], 0, 0, 0);
+                acc1[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc1[ct], 0, 0, 0);
+                acc2[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2.z, b.z, acc2[ct], 0, 0, 0);
+                acc1[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc1[ct], 0, 0, 0);
+                acc2[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2.w, b.w, acc2[ct], 0, 0, 0);
+            }
+        } else {
+            typedef typename LpMfma<E>::vec vec;
+            const int k0 = 32 * kq + 8 * sl;
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct) {
+                const vec b = *(const vec *)&Bs[(16 * ct + (lane & 15)) * KS + k0];
+                acc1[ct] = LpMfma<E>::run(S.a[kq], b, kq ? acc1[ct] : zero);
+                acc2[ct] = LpMfma<E>::run(S.b[kq], b, kq ? acc2[ct] : zero);
+            }
+            // keep the next k-chunk's operand loads from all being hoisted here (register cap)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// Epilogue.  acc[ct][r] = column 16 ct + l%16 of row 4 (l/16) + r of the wave's strip; den of a
+// row is the sum over columns (lanes of one 16-lane row group) of |G|^p.  nrm_s holds |h|^2 of
+// the workgroup's rows.
+template <int NCT>
+__device__ __forceinline__ void finish_rows(const floatx4 (&acc1)[NCT], const floatx4 (&acc2)[NCT],
+                                            int p, int lane, int wave, int d0, int D, bool bin_ok,
+                                            float *__restrict__ Pf, float *den_s,
+                                            const float *nrm_s)
+{
+    float part[4];
+    if (p == 2) {                          // uniform branch: no square roots on the p = 2 path
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float s = 0.f;
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct)
+                s = fmaf(acc1[ct][r], acc1[ct][r], fmaf(acc2[ct][r], acc2[ct][r], s));
+            part[r] = sum16(s);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float s = 0.f;
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct)
+                s += sqrtf(fmaf(acc1[ct][r], acc1[ct][r], acc2[ct][r] * acc2[ct][r]));
+            part[r] = sum16(s);
+        }
+    }
+    if ((lane & 15) == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) den_s[wave * 16 + 4 * (lane >> 4) + r] = part[r];
+    }
+    __syncthreads();
+    if (lane < 16) {
+        const int d = d0 + wave * 16 + lane;
+        if (d < D) {
+            const float den = den_s[wave * 16 + lane];
+            Pf[d] = bin_ok ? nrm_s[wave * 16 + lane] / fmaxf(den, 1.17549435e-38f) : 0.0f;
+        }
+    }
+}
+
+// One workgroup: directions d0 .. d0 + 127 of bin f for nb blocks sharing the table Hf (the bin's
+// [D][2M] rows).  blk(i) gives block i's (E_n of the bin, status ok, Ns, P row of the bin).
+template <int NCT, typename E, class BlockAt>
+__device__ __forceinline__ void steer_tile(const E *__restrict__ Hf, int D, int M, int p, int d0,
+                                           int nb, BlockAt &&blk)
+{
+    typedef SteerCfg<E> C;
+    __shared__ __attribute__((aligned(16))) E Bs[16 * NCT * C::KS_MAX];
     __shared__ float den_s[kRowsPerBlock];
     __shared__ float nrm_s[kRowsPerBlock];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int Nn = M - Ns;
     const int K2 = 2 * M;
-    const int KQ = (K2 + 31) / 32;
-    const int KP = 32 * KQ;
-    const int KS = KP + 8;
-    const int NCOL = 16 * NCT;
-    stage_b<E>(Enf, M, Nn, Bs, KS, NCOL, KP, tid);
-    __syncthreads();
+    const int KQ = (K2 + C::KC - 1) / C::KC;
+    const int KP = C::KC * KQ;
+    const int KS = KP + C::PAD;
 
-    const int row = d0 + wave * 16 + (lane & 15);
-    const int sl = lane >> 4;
-    const E *hrow = Hf + (size_t)(row < D ? row : 0) * K2;
-    // the strip in registers first; each complex element is one 32-bit (re, im) pair
-    constexpr int KQ_MAX = 4;
-    vec a[KQ_MAX];
-    float hn = 0.f;
-#pragma unroll
-    for (int kq = 0; kq < KQ_MAX; ++kq) {
-        const int m0 = 16 * kq + 4 * sl;                 // complex element of k0 = 32 kq + 8 s
-        uint32_t w[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            w[i] = (kq < KQ && row < D && m0 + i < M)
-                       ? *(const uint32_t *)(hrow + 2 * (m0 + i)) : 0u;
-        a[kq] = __builtin_bit_cast(vec, w);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const float fv = (float)a[kq][e];
-            hn = fmaf(fv, fv, hn);
+    AStrip<E> S;
+    float hn = load_strip<E>(Hf, D, M, d0 + wave * 16 + (lane & 15), lane >> 4, S);
+    // |h|^2: combine the 4 k-slices (lanes l, l^16, l^32, l^48)
+    hn += __shfl_xor(hn, 16);
+    hn += __shfl_xor(hn, 32);
+    if (lane < 16) nrm_s[wave * 16 + lane] = hn;
+
+    for (int i = 0; i < nb; ++i) {
+        const float2 *Enf;
+        bool ok;
+        int Ns;
+        float *Pf;
+        blk(i, Enf, ok, Ns, Pf);
+        // opaque copies of the thread indices: the operand addresses derived from them are
+        // recomputed per block instead of being hoisted out of the loop and held in registers
+        int tid_i = tid, lane_i = lane;
+        asm volatile("" : "+v"(tid_i), "+v"(lane_i));
+        {
+            BStage<NCT> st;                // every E_n load in flight before the LDS stores
+            load_b<NCT>(Enf, M, M - Ns, tid_i, st);
+            store_b<NCT, E>(st, Bs, KS, KP, tid_i);
         }
+        __syncthreads();                   // B staged (and the previous block's epilogue done)
+        floatx4 acc1[NCT], acc2[NCT];
+        mma<NCT, E>(S, Bs, KS, KQ, lane_i, acc1, acc2);
+        finish_rows<NCT>(acc1, acc2, p, lane, wave, d0, D, ok, Pf, den_s, nrm_s);
+        __syncthreads();                   // Bs and den_s free for the next block
     }
-    floatx4 acc[NCT];
-#pragma unroll
-    for (int ct = 0; ct < NCT; ++ct) acc[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kq = 0; kq < KQ_MAX; ++kq) {
-        if (kq < KQ) {
-            const int k0 = 32 * kq + 8 * sl;
-#pragma unroll
-            for (int ct = 0; ct < NCT; ++ct) {
-                const vec b = *(const vec *)&Bs[(16 * ct + (lane & 15)) * KS + k0];
-                acc[ct] = LpMfma<E>::run(a[kq], b, acc[ct]);
-            }
-        }
-    }
-    finish_rows<NCT>(acc, hn, p, lane, wave, d0, D, ok, Pf, den_s, nrm_s);
 }
 
-// E = float selects the FP32 tile, __bf16 / _Float16 the 16-bit tile.
-template <int NCT, typename E>
-__device__ __forceinline__ void steer_tile(const E *Hf, const float2 *Enf, bool ok, int D, int M,
-                                           int Ns, int p, float *Pf, int d0)
+// Workgroup -> (item, direction tile).  Workgroups are dealt to the 8 XCDs round-robin by linear
+// id, so workgroup w runs on XCD w % 8; giving XCD x the items x, x + 8, ... with all their tiles
+// back to back keeps every tile of an item (which all stage the same E_n) on one L2.
+constexpr int kXcds = 8;
+__host__ __device__ inline int xcd_grid(int n_items, int n_tiles)
 {
-    if constexpr (sizeof(E) == 4)
-        steer_f32_tile<NCT>(Hf, Enf, ok, D, M, Ns, p, Pf, d0);
-    else
-        steer_lp_tile<NCT, E>(Hf, Enf, ok, D, M, Ns, p, Pf, d0);
+    return kXcds * ((n_items + kXcds - 1) / kXcds) * n_tiles;
+}
+__device__ __forceinline__ bool xcd_item(int n_items, int n_tiles, int &item, int &tile)
+{
+    const int w = blockIdx.x;
+    const int slot = w / kXcds;
+    item = (slot / n_tiles) * kXcds + w % kXcds;
+    tile = slot % n_tiles;
+    return item < n_items;
 }
 
 template <int NCT, typename E>
-__global__ __launch_bounds__(kThreads) void steer_single(const E *__restrict__ H,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void steer_single(const E *__restrict__ H,
                                                          const float2 *__restrict__ En,
                                                          const int32_t *__restrict__ bin_status,
-                                                         int D, int M, int Ns, int p,
-                                                         float *__restrict__ P)
+                                                         int F, int D, int M, int Ns, int p,
+                                                         float *__restrict__ P, int n_tiles)
 {
-    const int f = blockIdx.y;
-    const bool ok = bin_status == nullptr || bin_status[f] == SSL_BIN_OK;
-    steer_tile<NCT, E>(H + (size_t)f * D * 2 * M, En + (size_t)f * (M - Ns) * M, ok, D, M, Ns, p,
-                       P + (size_t)f * D, blockIdx.x * kRowsPerBlock);
+    int f, tile;
+    if (!xcd_item(F, n_tiles, f, tile)) return;
+    steer_tile<NCT, E>(H + (size_t)f * D * 2 * M, D, M, p, tile * kRowsPerBlock, 1,
+                       [&](int, const float2 *&Enf, bool &ok, int &ns, float *&Pf) {
+                           Enf = En + (size_t)f * (M - Ns) * M;
+                           ok = bin_status == nullptr || bin_status[f] == SSL_BIN_OK;
+                           ns = Ns;
+                           Pf = P + (size_t)f * D;
+                       });
 }
 
+// Batched: item = (group, bin), groups[g] = (first, count) into gblocks, the blocks of one
+// steering table.
 template <int NCT, typename E>
-__global__ __launch_bounds__(kThreads) void steer_batch(const BlockDev *__restrict__ blk,
-                                                        const int2 *__restrict__ items)
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void steer_batch(const BlockDev *__restrict__ blk,
+                                                        const int2 *__restrict__ items,
+                                                        int n_items, int n_tiles,
+                                                        const int2 *__restrict__ groups,
+                                                        const int *__restrict__ gblocks)
 {
-    const int2 it = items[blockIdx.x];            // items on x: a batch may exceed 65535 of them
-    const BlockDev &B = blk[it.x];
-    const int d0 = blockIdx.y * kRowsPerBlock;
-    if (d0 >= B.D) return;
-    const int f = it.y, M = B.M, Ns = B.Ns, D = B.D;
-    const bool ok = B.status[f] == SSL_BIN_OK;
-    steer_tile<NCT, E>(static_cast<const E *>(B.H) + (size_t)f * D * 2 * M,
-                       B.En + (size_t)f * (M - Ns) * M, ok, D, M, Ns, B.p, B.P + (size_t)f * D,
-                       d0);
+    int ii, tile;
+    if (!xcd_item(n_items, n_tiles, ii, tile)) return;
+    const int2 it = items[ii];
+    const int2 gr = groups[it.x];
+    const BlockDev &B0 = blk[gblocks[gr.x]];
+    const int d0 = tile * kRowsPerBlock;
+    if (d0 >= B0.D) return;
+    const int f = it.y, M = B0.M, D = B0.D;
+    steer_tile<NCT, E>(static_cast<const E *>(B0.H) + (size_t)f * D * 2 * M, D, M, B0.p, d0, gr.y,
+                       [&](int i, const float2 *&Enf, bool &ok, int &ns, float *&Pf) {
+                           const BlockDev &B = blk[gblocks[gr.x + i]];
+                           Enf = B.En + (size_t)f * (M - B.Ns) * M;
+                           ok = B.status[f] == SSL_BIN_OK;
+                           ns = B.Ns;
+                           Pf = B.P + (size_t)f * D;
+                       });
 }
 
 template <int NCT>
 hipError_t launch_nct(const void *H, ssl_prec hprec, const ssl_c64 *En, int F, int D, int M,
                       int Ns, int p, const int32_t *bin_status, float *P, hipStream_t st)
 {
-    const dim3 grid((D + kRowsPerBlock - 1) / kRowsPerBlock, F);
+    const int nt = (D + kRowsPerBlock - 1) / kRowsPerBlock;
+    const dim3 grid(xcd_grid(F, nt));
     const float2 *Ep = reinterpret_cast<const float2 *>(En);
     if (hprec == SSL_FP32)
         hipLaunchKernelGGL((steer_single<NCT, float>), grid, dim3(kThreads), 0, st,
-                           static_cast<const float *>(H), Ep, bin_status, D, M, Ns, p, P);
+                           static_cast<const float *>(H), Ep, bin_status, F, D, M, Ns, p, P, nt);
     else if (hprec == SSL_BF16)
         hipLaunchKernelGGL((steer_single<NCT, __bf16>), grid, dim3(kThreads), 0, st,
-                           static_cast<const __bf16 *>(H), Ep, bin_status, D, M, Ns, p, P);
+                           static_cast<const __bf16 *>(H), Ep, bin_status, F, D, M, Ns, p, P, nt);
     else
         hipLaunchKernelGGL((steer_single<NCT, _Float16>), grid, dim3(kThreads), 0, st,
-                           static_cast<const _Float16 *>(H), Ep, bin_status, D, M, Ns, p, P);
+                           static_cast<const _Float16 *>(H), Ep, bin_status, F, D, M, Ns, p, P,
+                           nt);
     return hipGetLastError();
 }
 
 template <int NCT>
-hipError_t launch_nct_batch(const BlockDev *blk, const int2 *items, int n_items, int max_dtiles,
+hipError_t launch_nct_batch(const BlockDev *blk, const int2 *items, int n_items,
+                            const int2 *groups, const int *gblocks, int max_dtiles,
                             ssl_prec hprec, hipStream_t st)
 {
-    const dim3 grid(n_items, max_dtiles);
+    const dim3 grid(xcd_grid(n_items, max_dtiles));
     if (hprec == SSL_FP32)
-        hipLaunchKernelGGL((steer_batch<NCT, float>), grid, dim3(kThreads), 0, st, blk, items);
+        hipLaunchKernelGGL((steer_batch<NCT, float>), grid, dim3(kThreads), 0, st, blk, items,
+                           n_items, max_dtiles, groups, gblocks);
     else if (hprec == SSL_BF16)
-        hipLaunchKernelGGL((steer_batch<NCT, __bf16>), grid, dim3(kThreads), 0, st, blk, items);
+        hipLaunchKernelGGL((steer_batch<NCT, __bf16>), grid, dim3(kThreads), 0, st, blk, items,
+                           n_items, max_dtiles, groups, gblocks);
     else
-        hipLaunchKernelGGL((steer_batch<NCT, _Float16>), grid, dim3(kThreads), 0, st, blk, items);
+        hipLaunchKernelGGL((steer_batch<NCT, _Float16>), grid, dim3(kThreads), 0, st, blk,
+                           items, n_items, max_dtiles, groups, gblocks);
     return hipGetLastError();
 }
 
@@ -330,19 +414,19 @@ hipError_t launch_steer(const void *H, ssl_prec hprec, const ssl_c64 *En, int F,
     switch (steer_class(M, Ns)) {
     case 1: return launch_nct<1>(H, hprec, En, F, D, M, Ns, p, bin_status, P, st);
     case 2: return launch_nct<2>(H, hprec, En, F, D, M, Ns, p, bin_status, P, st);
-    case 4: return launch_nct<4>(H, hprec, En, F, D, M, Ns, p, bin_status, P, st);
-    default: return launch_nct<kMaxColTiles>(H, hprec, En, F, D, M, Ns, p, bin_status, P, st);
+    default: return launch_nct<4>(H, hprec, En, F, D, M, Ns, p, bin_status, P, st);
     }
 }
 
-hipError_t launch_steer_batch(const BlockDev *blk, const int2 *items, int n_items, int cls,
-                              int max_dtiles, ssl_prec hprec, hipStream_t st)
+hipError_t launch_steer_batch(const BlockDev *blk, const int2 *items, int n_items,
+                              const int2 *groups, const int *gblocks, int cls, int max_dtiles,
+                              ssl_prec hprec, hipStream_t st)
 {
     if (n_items <= 0) return hipSuccess;
     switch (cls) {
-    case 1: return launch_nct_batch<1>(blk, items, n_items, max_dtiles, hprec, st);
-    case 2: return launch_nct_batch<2>(blk, items, n_items, max_dtiles, hprec, st);
-    case 4: return launch_nct_batch<4>(blk, items, n_items, max_dtiles, hprec, st);
-    default: return launch_nct_batch<kMaxColTiles>(blk, items, n_items, max_dtiles, hprec, st);
+    case 1: return launch_nct_batch<1>(blk, items, n_items, groups, gblocks, max_dtiles, hprec, st);
+    case 2: return launch_nct_batch<2>(blk, items, n_items, groups, gblocks, max_dtiles, hprec, st);
+    default:
+        return launch_nct_batch<4>(blk, items, n_items, groups, gblocks, max_dtiles, hprec, st);
     }
 }

@@ -129,6 +129,27 @@ def test_batch_subset_and_reorder(env):
     assert same(run_batch(S, ctx, sub, outputs(sub)), ref)
 
 
+def test_batch_shared_tables(env):
+    """Blocks interleaved over two steering tables of one shape (one projection launch loops over
+    each table's blocks), then the same shapes with one table: bit-identical to single calls,
+    and the changed sharing pattern does not replay the first graph."""
+    S, ctx, blocks = env
+    b60 = [b for b in blocks if b["M"] == 60]
+    Hb = b60[0]["s"]["Hd"].clone()
+    mix = []
+    for i, tab in enumerate("ABAABA"):
+        b = dict(b60[i % len(b60)])
+        b["s"] = dict(b["s"], Hd=Hb) if tab == "B" else b["s"]
+        mix.append(b)
+    say("ssl_localize_batch 6 blocks over two shared tables (ABAABA)")
+    ref = run_single(S, ctx, mix)
+    assert same(run_batch(S, ctx, mix, outputs(mix)), ref)
+    assert same(run_batch(S, ctx, mix, outputs(mix)), ref)
+    one = [dict(b, s=b60[0]["s"]) if b["s"]["Hd"] is Hb else b for b in mix]
+    say("ssl_localize_batch same shapes, one table")
+    assert same(run_batch(S, ctx, one, outputs(one)), run_single(S, ctx, one))
+
+
 def test_batch_uneven_matches_oracle(env):
     S, ctx, blocks = env
     say("ssl_localize_batch uneven vs oracle")
