@@ -8,13 +8,18 @@ spectrum (eq.5), bin sum (eq.6) and peak search -- over one batch of `--batch` d
 ssl_localize_batch (all HIP kernels of the library).  Inputs (distinct seeded blocks, steering
 table, resident noise factor) are in HBM before any timed region starts.
 
-Timed regions (each bracketed by torch.cuda.synchronize()):
-  * main: `--steps` batch steps with per-kernel HIP events on the launch stream -> `value` and
-    the dominant kernel's roofline (algorithmic flops per launch / average launch duration);
+The headline path is mixed precision (`--prec`, default bf16: correlation and projection on
+16-bit MFMA inputs with FP32 accumulation, K^{-1}R in FP64, the Jacobi SVD in FP32); the plain
+FP32 path is measured in the same run, batched and one block per call, for comparison.
+
+Timed regions per precision (each bracketed by torch.cuda.synchronize()):
+  * main: `--steps` batch steps with per-kernel HIP events on the launch stream -> `value`, the
+    per-kernel rooflines (algorithmic bytes or flops per launch / average launch duration);
   * graph: the same steps replayed from the captured HIP graph (no events) -> `graph_value`;
   * per-block: ssl_localize one block at a time -> `per_block`;
-  * host-to-device: the same steps with every block's X copied from pinned host memory, serial
-    and double-buffered on a side stream -> `h2d`.
+  * host-to-device (headline precision): the same steps with every block's X copied from pinned
+    host memory, serial and double-buffered on a side stream -> `h2d`.
+Serving (headline precision): 64 array streams through paper_2504_03373_amd.serving.
 The FP64 CPU oracle is timed on a bounded sample of the same workload on this host's cores.
 Prints one JSON line.
 """
@@ -29,8 +34,11 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X FP32 vector peak: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed FP32) x 2.4 GHz
-PEAK_FP32_VECTOR_TFLOPS = 157.3
+# MI355X published peaks
+PEAK_FP32_VECTOR_TFLOPS = 157.3   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+PEAK_MFMA_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0}
 
 
 def jacobi_flops(M: int, sweeps, rotations, rank) -> float:
@@ -127,7 +135,10 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20, help="timed batch steps")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=32, help="blocks per step")
-    ap.add_argument("--prec", choices=["fp32", "bf16", "fp16"], default="fp32")
+    ap.add_argument("--prec", choices=["fp32", "bf16", "fp16"], default="bf16",
+                    help="MFMA input type of the headline path")
+    ap.add_argument("--no-fp32-compare", action="store_true",
+                    help="skip the FP32 comparison paths")
     ap.add_argument("--per-block-steps", type=int, default=100)
     ap.add_argument("--cpu-blocks", type=int, default=48, help="oracle sample size (blocks)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -165,18 +176,22 @@ def main() -> int:
         return 1
     dev = "cuda:0"
     S.lib()
-    prec = {"fp32": S.SSL_FP32, "bf16": S.SSL_BF16, "fp16": S.SSL_FP16}[args.prec]
+    PREC = {"fp32": S.SSL_FP32, "bf16": S.SSL_BF16, "fp16": S.SSL_FP16}
 
     w = synth.workload_paper(n_blocks=1000)
     F, T, M, Ns, D = w.F, w.T, w.M, w.Ns, w.D
     B = args.batch
     t0 = time.time()
     Xs = torch.stack([torch.from_numpy(w.block(b)[0]) for b in range(B)]).to(dev)
-    H = torch.from_numpy(w.steering_table()).to(dev)
-    if prec != S.SSL_FP32:
+    H32 = torch.from_numpy(w.steering_table()).to(dev)
+
+    def table(name):
+        if name == "fp32":
+            return H32
         # interleaved (re, im) 16-bit pairs, [F][D][2M]
-        H = torch.view_as_real(H).reshape(F, D, 2 * M).to(
-            torch.bfloat16 if prec == S.SSL_BF16 else torch.float16).contiguous()
+        return torch.view_as_real(H32).reshape(F, D, 2 * M).to(
+            torch.bfloat16 if name == "bf16" else torch.float16).contiguous()
+
     Xn = torch.from_numpy(w.noise_frames()).to(dev)
     gen_s = time.time() - t0
 
@@ -198,144 +213,165 @@ def main() -> int:
     kst = torch.zeros(F, dtype=torch.int32, device=dev)
     S.ssl_noise_set(noise, Kd, S.SSL_FP64, kst)
 
-    # Jacobi sweep / rotation counts for the flop model: same kernel variant, same inputs,
-    # deterministic, so they are those of the timed launches.
-    R = torch.zeros((F, M, M), dtype=torch.complex64, device=dev)
-    En = torch.zeros((F, M - Ns, M), dtype=torch.complex64, device=dev)
-    conv = torch.zeros((F, 3), dtype=torch.int32, device=dev)
-    conv_all = []
-    for b in range(B):
-        S.ssl_corr_accum(ctx, Xs[b], 1.0 / T, 0, prec, R)
-        S.ssl_gsvd(ctx, R, noise, Ns, En, None, None, conv, 0)
-        conv_all.append(conv.cpu().numpy().copy())
-    flops_batch = float(sum(jacobi_flops(M, c[:, 0], c[:, 1], c[:, 2]) for c in conv_all))
-
     pk = torch.zeros((B, Ns), dtype=torch.int32, device=dev)
     pv = torch.zeros((B, Ns), dtype=torch.float32, device=dev)
     Pbar = torch.zeros((B, D), dtype=torch.float32, device=dev)
     st = torch.zeros((B, F), dtype=torch.int32, device=dev)
-    descs = [S.block_desc(Xs[b], noise, H, w.grid.n_az, w.grid.n_el, Ns, pk[b], pv[b], Pbar[b],
-                          st[b]) for b in range(B)]
 
-    def step():
-        S.ssl_localize_batch(ctx, descs, prec, 2)
+    def measure(name: str, with_h2d: bool) -> dict:
+        prec = PREC[name]
+        H = table(name)
+        # Jacobi sweep / rotation counts for the flop model: same kernel variant, same inputs,
+        # deterministic, so they are those of the timed launches.
+        R = torch.zeros((F, M, M), dtype=torch.complex64, device=dev)
+        En = torch.zeros((F, M - Ns, M), dtype=torch.complex64, device=dev)
+        conv = torch.zeros((F, 3), dtype=torch.int32, device=dev)
+        conv_all = []
+        for b in range(B):
+            S.ssl_corr_accum(ctx, Xs[b], 1.0 / T, 0, prec, R)
+            S.ssl_gsvd(ctx, R, noise, Ns, En, None, None, conv, 0)
+            conv_all.append(conv.cpu().numpy().copy())
+        del R, En
+        jflops = float(sum(jacobi_flops(M, c[:, 0], c[:, 1], c[:, 2]) for c in conv_all))
+        descs = [S.block_desc(Xs[b], noise, H, w.grid.n_az, w.grid.n_el, Ns, pk[b], pv[b],
+                              Pbar[b], st[b]) for b in range(B)]
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
+        def step():
+            S.ssl_localize_batch(ctx, descs, prec, 2)
 
-    # ---- main timed region: per-kernel events on the launch stream --------------------------
-    S.ssl_ctx_timing_read(ctx, reset=True)
-    S.ssl_ctx_timing(ctx, True)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for k in range(args.steps):
-        ev[k][0].record()
-        step()
-        ev[k][1].record()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    S.ssl_ctx_timing(ctx, False)
-    ktimes = S.ssl_ctx_timing_read(ctx, reset=True)
-    lat = np.array([a.elapsed_time(b) for a, b in ev])
-    status_ok = bool((st.cpu().numpy() == 0).all())
-    value = args.steps * B / elapsed
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        # main timed region: per-kernel events on the launch stream
+        S.ssl_ctx_timing_read(ctx, reset=True)
+        S.ssl_ctx_timing(ctx, True)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for k in range(args.steps):
+            ev[k][0].record()
+            step()
+            ev[k][1].record()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        S.ssl_ctx_timing(ctx, False)
+        kt = S.ssl_ctx_timing_read(ctx, reset=True)
+        lat = np.array([a.elapsed_time(b) for a, b in ev])
+        status_ok = bool((st.cpu().numpy() == 0).all())
+        # graph replay region
+        step()                                   # capture (not timed)
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        graph_value = args.steps * B / (time.perf_counter() - tg)
+        # one block per call
+        pk1 = torch.zeros(Ns, dtype=torch.int32, device=dev)
+        pv1 = torch.zeros(Ns, dtype=torch.float32, device=dev)
+        pb1 = torch.zeros(D, dtype=torch.float32, device=dev)
+        st1 = torch.zeros(F, dtype=torch.int32, device=dev)
 
-    # ---- graph replay region ------------------------------------------------------------------
-    step()                                   # capture (not timed)
-    torch.cuda.synchronize()
-    tg = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    graph_value = args.steps * B / (time.perf_counter() - tg)
+        def one(k):
+            S.ssl_localize(ctx, Xs[k % B], noise, H, prec, w.grid.n_az, w.grid.n_el, Ns, 2, pk1,
+                           pv1, pb1, st1)
 
-    # ---- per-block region ---------------------------------------------------------------------
-    pk1 = torch.zeros(Ns, dtype=torch.int32, device=dev)
-    pv1 = torch.zeros(Ns, dtype=torch.float32, device=dev)
-    pb1 = torch.zeros(D, dtype=torch.float32, device=dev)
-    st1 = torch.zeros(F, dtype=torch.int32, device=dev)
-    for k in range(5):
-        S.ssl_localize(ctx, Xs[k % B], noise, H, prec, w.grid.n_az, w.grid.n_el, Ns, 2, pk1, pv1,
-                       pb1, st1)
-    torch.cuda.synchronize()
-    tb = time.perf_counter()
-    for k in range(args.per_block_steps):
-        S.ssl_localize(ctx, Xs[k % B], noise, H, prec, w.grid.n_az, w.grid.n_el, Ns, 2, pk1, pv1,
-                       pb1, st1)
-    torch.cuda.synchronize()
-    per_block = args.per_block_steps / (time.perf_counter() - tb)
+        for k in range(5):
+            one(k)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        for k in range(args.per_block_steps):
+            one(k)
+        torch.cuda.synchronize()
+        per_block = args.per_block_steps / (time.perf_counter() - tb)
 
-    # ---- host-to-device inclusive region ------------------------------------------------------
-    # X of every block arrives from pinned host memory: (a) copy then compute on one stream;
-    # (b) double-buffered, the copy of step k+1 on a side stream under the compute of step k.
-    Xh = Xs.cpu().pin_memory()
-    Xs2 = torch.empty_like(Xs)
-    descs2 = [S.block_desc(Xs2[b], noise, H, w.grid.n_az, w.grid.n_el, Ns, pk[b], pv[b], Pbar[b],
-                           st[b]) for b in range(B)]
-    main_st = torch.cuda.current_stream()
-    torch.cuda.synchronize()
-    th = time.perf_counter()
-    for _ in range(args.steps):
-        Xs.copy_(Xh, non_blocking=True)
-        step()
-    torch.cuda.synchronize()
-    h2d_serial = args.steps * B / (time.perf_counter() - th)
-    cs = torch.cuda.Stream(device=dev)
-    bufs, bdescs = (Xs, Xs2), (descs, descs2)
-    copied = [torch.cuda.Event(), torch.cuda.Event()]
-    freed = [torch.cuda.Event(), torch.cuda.Event()]
-    for i in range(2):
-        S.ssl_localize_batch(ctx, bdescs[i], prec, 2)       # capture both buffer sets (not timed)
-    torch.cuda.synchronize()
-    th = time.perf_counter()
-    with torch.cuda.stream(cs):
-        bufs[0].copy_(Xh, non_blocking=True)
-        copied[0].record(cs)
-    for k in range(args.steps):
-        i = k & 1
-        if k + 1 < args.steps:
+        avg = {k: ms / max(n, 1) for k, (n, ms) in kt.items() if n}
+        ms = lambda k: avg[k] * 1e-3
+        # algorithmic work per launch (B blocks): bytes or flops the method must move or compute
+        sH = 8 if name == "fp32" else 4
+        w_corr = B * (8.0 * F * T * M + 8.0 * F * M * M)
+        w_white = B * 8.0 * F * M ** 3
+        w_steer = B * 8.0 * F * D * M * (M - Ns)
+        w_bins = B * (4.0 * F * D + 4.0 * D)
+        rl = {
+            "corr": {"bound": "hbm", "unit": "GB/s", "bytes_per_launch": w_corr,
+                     "achieved": w_corr / ms("corr") / 1e9, "peak": PEAK_HBM_GBS},
+            "whiten": {"bound": "fp64", "unit": "TFLOP/s", "flops_per_launch": w_white,
+                       "achieved": w_white / ms("whiten") / 1e12, "peak": PEAK_FP64_TFLOPS},
+            "jacobi": {"bound": "alu", "unit": "TFLOP/s", "flops_per_launch": jflops,
+                       "achieved": jflops / ms("jacobi") / 1e12, "peak": PEAK_FP32_VECTOR_TFLOPS},
+            "steer": {"bound": "mfma", "unit": "TFLOP/s", "flops_per_launch": w_steer,
+                      "achieved": w_steer / ms("steer") / 1e12, "peak": PEAK_MFMA_TFLOPS[name],
+                      "table_bytes_per_element": sH},
+            "binsum": {"bound": "hbm", "unit": "GB/s", "bytes_per_launch": w_bins,
+                       "achieved": w_bins / ms("binsum") / 1e9, "peak": PEAK_HBM_GBS},
+        }
+        for v in rl.values():
+            v["frac"] = round(v["achieved"] / v["peak"], 4)
+            v["achieved"] = round(v["achieved"], 3)
+        out = {"value": args.steps * B / elapsed, "elapsed": elapsed, "graph_value": graph_value,
+               "per_block": per_block, "lat": lat, "kt": kt, "avg": avg, "rl": rl,
+               "jflops": jflops, "conv": conv_all, "status_ok": status_ok}
+        if with_h2d:
+            # X of every block from pinned host memory: (a) copy then compute on one stream;
+            # (b) double-buffered, the copy of step k+1 on a side stream under step k
+            Xh = Xs.cpu().pin_memory()
+            Xs2 = torch.empty_like(Xs)
+            descs2 = [S.block_desc(Xs2[b], noise, H, w.grid.n_az, w.grid.n_el, Ns, pk[b], pv[b],
+                                   Pbar[b], st[b]) for b in range(B)]
+            main_st = torch.cuda.current_stream()
+            torch.cuda.synchronize()
+            th = time.perf_counter()
+            for _ in range(args.steps):
+                Xs.copy_(Xh, non_blocking=True)
+                step()
+            torch.cuda.synchronize()
+            out["h2d_serial"] = args.steps * B / (time.perf_counter() - th)
+            cs = torch.cuda.Stream(device=dev)
+            bufs, bdescs = (Xs, Xs2), (descs, descs2)
+            copied = [torch.cuda.Event(), torch.cuda.Event()]
+            freed = [torch.cuda.Event(), torch.cuda.Event()]
+            for i in range(2):
+                S.ssl_localize_batch(ctx, bdescs[i], prec, 2)   # both captured (not timed)
+            torch.cuda.synchronize()
+            th = time.perf_counter()
             with torch.cuda.stream(cs):
-                if k >= 1:
-                    cs.wait_event(freed[1 - i])
-                bufs[1 - i].copy_(Xh, non_blocking=True)
-                copied[1 - i].record(cs)
-        main_st.wait_event(copied[i])
-        S.ssl_localize_batch(ctx, bdescs[i], prec, 2)
-        freed[i].record(main_st)
-    torch.cuda.synchronize()
-    h2d_overlap = args.steps * B / (time.perf_counter() - th)
-    del Xh, Xs2
+                bufs[0].copy_(Xh, non_blocking=True)
+                copied[0].record(cs)
+            for k in range(args.steps):
+                i = k & 1
+                if k + 1 < args.steps:
+                    with torch.cuda.stream(cs):
+                        if k >= 1:
+                            cs.wait_event(freed[1 - i])
+                        bufs[1 - i].copy_(Xh, non_blocking=True)
+                        copied[1 - i].record(cs)
+                main_st.wait_event(copied[i])
+                S.ssl_localize_batch(ctx, bdescs[i], prec, 2)
+                freed[i].record(main_st)
+            torch.cuda.synchronize()
+            out["h2d_overlap"] = args.steps * B / (time.perf_counter() - th)
+        return out
 
-    dom = max(ktimes, key=lambda k: ktimes[k][1])
-    n_j, ms_j = ktimes["jacobi"]
-    avg_j_ms = ms_j / max(n_j, 1)
-    achieved = flops_batch / (avg_j_ms * 1e-3) / 1e12
-    roofline = {
-        "kernel": "jacobi_persistent",
-        "bound": "alu",
-        "achieved": round(achieved, 3),
-        "peak": PEAK_FP32_VECTOR_TFLOPS,
-        "unit": "TFLOP/s",
-        "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
-        "traffic": traffic_bytes(B),
-        "avg_launch_ms": round(avg_j_ms, 4),
-        "flops_per_launch": flops_batch,
-        "bins_per_launch": B * F,
-    }
-    kernels = {k: {"launches": n, "avg_ms": round(ms / max(n, 1), 4)}
-               for k, (n, ms) in ktimes.items() if n}
+    main_r = measure(args.prec, with_h2d=True)
+    f32 = main_r if args.prec == "fp32" else (None if args.no_fp32_compare
+                                                else measure("fp32", with_h2d=False))
 
+    avg = main_r["avg"]
+    roofline = {"kernel": "jacobi_persistent", **{k: main_r["rl"]["jacobi"][k] for k in
+                                                   ("bound", "achieved", "peak", "unit", "frac")},
+                "traffic": traffic_bytes(B), "avg_launch_ms": round(avg["jacobi"], 4),
+                "flops_per_launch": main_r["jflops"], "bins_per_launch": B * F}
+    conv_all = main_r["conv"]
     out = {
         "metric": "GSVD-MUSIC blocks/s (60ch, 257 bins, 1368 dirs) + p50/p99 served latency",
-        "value": round(value, 2),
+        "value": round(main_r["value"], 2),
         "unit": "blocks/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1000.0 * elapsed / args.steps, 4),
+        "ms_per_step": round(1000.0 * main_r["elapsed"] / args.steps, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -344,49 +380,62 @@ def main() -> int:
         "config": {"workload": w.name, "M": M, "F": F, "T": T, "D": D, "Ns": Ns, "p": 2,
                    "blocks_per_step": B, "path": "ssl_localize_batch",
                    "mfma_inputs": args.prec, "whitening": "fp64",
-                   "svd": "fp32 one-sided Jacobi (QR-preconditioned)"},
-        "graph_value": round(graph_value, 2),
-        "per_block": {"value": round(per_block, 2), "unit": "blocks/s",
-                      "path": "ssl_localize, one block per call"},
-        "step_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
-                    "p99": round(float(np.percentile(lat, 99)), 4),
+                   "svd": "fp32 one-sided Jacobi (two-QR preconditioned)"},
+        "graph_value": round(main_r["graph_value"], 2),
+        "per_block": {"value": round(main_r["per_block"], 2), "unit": "blocks/s",
+                      "path": f"ssl_localize, one block per call, {args.prec}"},
+        "step_ms": {"p50": round(float(np.percentile(main_r["lat"], 50)), 4),
+                    "p99": round(float(np.percentile(main_r["lat"], 99)), 4),
                     "kind": f"device time of one {B}-block step"},
-        "dominant_kernel": dom,
-        "kernels": kernels,
+        "dominant_kernel": max(avg, key=lambda k: avg[k]),
+        "kernels": {k: {"launches": n, "avg_ms": round(ms / max(n, 1), 4)}
+                    for k, (n, ms) in main_r["kt"].items() if n},
         "roofline": roofline,
+        "kernel_rooflines": main_r["rl"],
         "jacobi_sweeps": {"mean": round(float(np.mean([c[:, 0].mean() for c in conv_all])), 3),
                           "max": int(max(c[:, 0].max() for c in conv_all)),
                           "mean_rank": round(float(np.mean([c[:, 2].mean() for c in conv_all])), 2)},
-        "h2d": {"serial": round(h2d_serial, 2), "overlapped": round(h2d_overlap, 2),
+        "h2d": {"serial": round(main_r["h2d_serial"], 2),
+                "overlapped": round(main_r["h2d_overlap"], 2),
                 "unit": "blocks/s", "bytes_per_block": F * T * M * 8,
                 "kind": "X from pinned host memory each step (copy then compute; copy of the "
                         "next step on a side stream under the compute)"},
-        "status_ok": status_ok,
+        "status_ok": main_r["status_ok"] and (f32 is None or f32["status_ok"]),
         "input_gen_s": round(gen_s, 2),
     }
+    if f32 is not None:
+        out["fp32"] = {"value": round(f32["value"], 2), "graph_value": round(f32["graph_value"], 2),
+                       "per_block": round(f32["per_block"], 2), "unit": "blocks/s",
+                       "ms_per_step": round(1000.0 * f32["elapsed"] / args.steps, 4),
+                       "kernels": {k: round(v, 4) for k, v in f32["avg"].items()},
+                       "steer_roofline": f32["rl"]["steer"], "corr_roofline": f32["rl"]["corr"],
+                       "kind": "plain FP32 path: batched, and one block per call"}
+        out["speedup_vs_fp32_per_block"] = round(main_r["value"] / f32["per_block"], 3)
 
     if args.serve_seconds > 0:
         from paper_2504_03373_amd.serving import GpuExecutor, Server
+        prec = PREC[args.prec]
         streams = synth.serving_streams(n_streams=args.serve_streams)
         Hs = {}
-        for s in streams:
-            if s.M not in Hs:
-                h = torch.from_numpy(synth.steering_table(s.pos, s.grid, s.freqs)).to(dev)
+        for s_ in streams:
+            if s_.M not in Hs:
+                h = torch.from_numpy(synth.steering_table(s_.pos, s_.grid, s_.freqs)).to(dev)
                 if prec != S.SSL_FP32:
-                    h = torch.view_as_real(h).reshape(s.F, s.D, 2 * s.M).to(
+                    h = torch.view_as_real(h).reshape(s_.F, s_.D, 2 * s_.M).to(
                         torch.bfloat16 if prec == S.SSL_BF16 else torch.float16).contiguous()
-                Hs[s.M] = h
+                Hs[s_.M] = h
         budget = int(args.serve_budget_gb * (1 << 30))
         ex = GpuExecutor(streams, Hs, prec=prec, alpha=0.95, k_update_every=args.k_update_every,
                          hbm_budget_bytes=budget, lanes=2, pool=4)
         srv = Server(ex, budget, max_batch=128)
         srv.run(synth.poisson_arrivals(len(streams), 0.1, args.serve_period_ms * 1e-3, seed=7))
-        mix = {m: sum(1 for s in streams if s.M == m) for m in sorted({s.M for s in streams})}
+        mix = {m: sum(1 for s_ in streams if s_.M == m) for m in sorted({s_.M for s_ in streams})}
 
         def serve(period_ms: float) -> dict:
             arrivals = synth.poisson_arrivals(len(streams), args.serve_seconds, period_ms * 1e-3)
             sv = srv.run(arrivals)
             return {"streams": len(streams), "streams_by_M": mix, "period_ms": period_ms,
+                    "prec": args.prec,
                     "offered_blocks_per_s": round(len(arrivals) / args.serve_seconds, 1),
                     "completed": sv["completed"], "blocks_per_s": round(sv["blocks_per_s"], 1),
                     "p50_ms": round(sv["p50_ms"], 3), "p99_ms": round(sv["p99_ms"], 3),
