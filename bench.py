@@ -139,6 +139,8 @@ def main() -> int:
                     help="MFMA input type of the headline path")
     ap.add_argument("--no-fp32-compare", action="store_true",
                     help="skip the FP32 comparison paths")
+    ap.add_argument("--no-h2d", action="store_true",
+                    help="skip the host-to-device region (its copies share the CUs)")
     ap.add_argument("--per-block-steps", type=int, default=100)
     ap.add_argument("--cpu-blocks", type=int, default=48, help="oracle sample size (blocks)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -354,7 +356,7 @@ def main() -> int:
             out["h2d_overlap"] = args.steps * B / (time.perf_counter() - th)
         return out
 
-    main_r = measure(args.prec, with_h2d=True)
+    main_r = measure(args.prec, with_h2d=not args.no_h2d)
     f32 = main_r if args.prec == "fp32" else (None if args.no_fp32_compare
                                                 else measure("fp32", with_h2d=False))
 
@@ -395,14 +397,15 @@ def main() -> int:
         "jacobi_sweeps": {"mean": round(float(np.mean([c[:, 0].mean() for c in conv_all])), 3),
                           "max": int(max(c[:, 0].max() for c in conv_all)),
                           "mean_rank": round(float(np.mean([c[:, 2].mean() for c in conv_all])), 2)},
-        "h2d": {"serial": round(main_r["h2d_serial"], 2),
-                "overlapped": round(main_r["h2d_overlap"], 2),
-                "unit": "blocks/s", "bytes_per_block": F * T * M * 8,
-                "kind": "X from pinned host memory each step (copy then compute; copy of the "
-                        "next step on a side stream under the compute)"},
         "status_ok": main_r["status_ok"] and (f32 is None or f32["status_ok"]),
         "input_gen_s": round(gen_s, 2),
     }
+    if "h2d_serial" in main_r:
+        out["h2d"] = {"serial": round(main_r["h2d_serial"], 2),
+                      "overlapped": round(main_r["h2d_overlap"], 2),
+                      "unit": "blocks/s", "bytes_per_block": F * T * M * 8,
+                      "kind": "X from pinned host memory each step (copy then compute; copy of "
+                              "the next step on a side stream under the compute)"}
     if f32 is not None:
         out["fp32"] = {"value": round(f32["value"], 2), "graph_value": round(f32["graph_value"], 2),
                        "per_block": round(f32["per_block"], 2), "unit": "blocks/s",

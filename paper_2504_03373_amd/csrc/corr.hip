@@ -265,23 +265,40 @@ __device__ __forceinline__ void corr_bin(const float2 *Xf, int T, int M, int64_t
         corr_lp_bin<MP, E>(Xf, T, M, sT, scale, accumulate, Rf);
 }
 
+// A resident grid of workgroups strides over the bins (a bin is a few microseconds of work: one
+// launch-time workgroup per bin spends as long being dispatched as computing).
 template <int MP, typename E>
-__global__ __launch_bounds__(kThreads) void corr_single(const float2 *__restrict__ X, int T, int M,
-                                                        int64_t sF, int64_t sT, float scale,
+__global__ __launch_bounds__(kThreads) void corr_single(const float2 *__restrict__ X, int F, int T,
+                                                        int M, int64_t sF, int64_t sT, float scale,
                                                         int accumulate, float2 *__restrict__ R)
 {
-    const int f = blockIdx.x;
-    corr_bin<MP, E>(X + (size_t)f * sF, T, M, sT, scale, accumulate, R + (size_t)f * M * M);
+    for (int f = blockIdx.x; f < F; f += gridDim.x)
+        corr_bin<MP, E>(X + (size_t)f * sF, T, M, sT, scale, accumulate, R + (size_t)f * M * M);
 }
 
 template <int MP, typename E>
 __global__ __launch_bounds__(kThreads) void corr_batch(const BlockDev *__restrict__ blk,
-                                                       const int2 *__restrict__ items)
+                                                       const int2 *__restrict__ items, int n_items)
 {
-    const int2 it = items[blockIdx.x];
-    const BlockDev &B = blk[it.x];
-    corr_bin<MP, E>(B.X + (size_t)it.y * B.sF, B.T, B.M, B.sT, B.scale, 0,
-                    B.R + (size_t)it.y * B.M * B.M);
+    for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+        const int2 it = items[i];
+        const BlockDev &B = blk[it.x];
+        corr_bin<MP, E>(B.X + (size_t)it.y * B.sF, B.T, B.M, B.sT, B.scale, 0,
+                        B.R + (size_t)it.y * B.M * B.M);
+    }
+}
+
+// Workgroups of `kernel` resident on the whole device at once, capped at n.
+template <typename K>
+int resident_grid(K kernel, int n)
+{
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kThreads, 0) != hipSuccess)
+        return n;
+    const int g = (cus > 0 ? cus : 1) * (per > 0 ? per : 1);
+    return n < g ? n : g;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -366,6 +383,16 @@ __global__ __launch_bounds__(kThreads) void corr_f64(const float2 *__restrict__ 
     }
 }
 
+template <int MP, typename E>
+hipError_t launch_mp_t(const float2 *Xp, int F, int T, int M, int64_t sF, int64_t sT, float scale,
+                       int accumulate, float2 *Rp, hipStream_t st)
+{
+    const int g = resident_grid(corr_single<MP, E>, F);
+    hipLaunchKernelGGL((corr_single<MP, E>), dim3(g), dim3(kThreads), 0, st, Xp, F, T, M, sF, sT,
+                       scale, accumulate, Rp);
+    return hipGetLastError();
+}
+
 template <int MP>
 hipError_t launch_mp(const ssl_c64 *X, int F, int T, int M, int64_t sF, int64_t sT, double scale,
                      int accumulate, ssl_prec prec, void *R, hipStream_t st)
@@ -373,14 +400,17 @@ hipError_t launch_mp(const ssl_c64 *X, int F, int T, int M, int64_t sF, int64_t 
     const float2 *Xp = reinterpret_cast<const float2 *>(X);
     float2 *Rp = reinterpret_cast<float2 *>(R);
     if (prec == SSL_FP32)
-        hipLaunchKernelGGL((corr_single<MP, float>), dim3(F), dim3(kThreads), 0, st, Xp, T, M, sF,
-                           sT, (float)scale, accumulate, Rp);
-    else if (prec == SSL_BF16)
-        hipLaunchKernelGGL((corr_single<MP, __bf16>), dim3(F), dim3(kThreads), 0, st, Xp, T, M,
-                           sF, sT, (float)scale, accumulate, Rp);
-    else
-        hipLaunchKernelGGL((corr_single<MP, _Float16>), dim3(F), dim3(kThreads), 0, st, Xp, T, M,
-                           sF, sT, (float)scale, accumulate, Rp);
+        return launch_mp_t<MP, float>(Xp, F, T, M, sF, sT, (float)scale, accumulate, Rp, st);
+    if (prec == SSL_BF16)
+        return launch_mp_t<MP, __bf16>(Xp, F, T, M, sF, sT, (float)scale, accumulate, Rp, st);
+    return launch_mp_t<MP, _Float16>(Xp, F, T, M, sF, sT, (float)scale, accumulate, Rp, st);
+}
+
+template <int MP, typename E>
+hipError_t launch_mp_batch_t(const BlockDev *blk, const int2 *items, int n, hipStream_t st)
+{
+    const int g = resident_grid(corr_batch<MP, E>, n);
+    hipLaunchKernelGGL((corr_batch<MP, E>), dim3(g), dim3(kThreads), 0, st, blk, items, n);
     return hipGetLastError();
 }
 
@@ -388,13 +418,9 @@ template <int MP>
 hipError_t launch_mp_batch(const BlockDev *blk, const int2 *items, int n, ssl_prec prec,
                            hipStream_t st)
 {
-    if (prec == SSL_FP32)
-        hipLaunchKernelGGL((corr_batch<MP, float>), dim3(n), dim3(kThreads), 0, st, blk, items);
-    else if (prec == SSL_BF16)
-        hipLaunchKernelGGL((corr_batch<MP, __bf16>), dim3(n), dim3(kThreads), 0, st, blk, items);
-    else
-        hipLaunchKernelGGL((corr_batch<MP, _Float16>), dim3(n), dim3(kThreads), 0, st, blk, items);
-    return hipGetLastError();
+    if (prec == SSL_FP32) return launch_mp_batch_t<MP, float>(blk, items, n, st);
+    if (prec == SSL_BF16) return launch_mp_batch_t<MP, __bf16>(blk, items, n, st);
+    return launch_mp_batch_t<MP, _Float16>(blk, items, n, st);
 }
 
 }  // namespace

@@ -144,6 +144,8 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
     __shared__ float tau[MP];
     __shared__ int colmap[MP];          // step k's pivot: physical column colmap[k]
     __shared__ int pos[MP];             // step at which physical column c was chosen (M: never)
+    __shared__ int clist[MP];           // unused columns of the pivoted QR, packed
+    __shared__ int cinv[MP];            // slot of column c in clist
     __shared__ float sig[MP];
     __shared__ int perm[MP];
     __shared__ unsigned long long pkey[3];   // pivot keys of steps k, k+1 (k+2 being cleared)
@@ -169,7 +171,11 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         degen = 0;
         pkey[0] = pkey[1] = pkey[2] = 0ull;
     }
-    if (tid < MP) pos[tid] = M;
+    if (tid < MP) {
+        pos[tid] = M;
+        clist[tid] = tid;
+        cinv[tid] = tid;
+    }
     __syncthreads();
 
     // ---- load A column-major into X (padding zero) ---------------------------------------------
@@ -213,7 +219,9 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         // v = x - alpha e_k, alpha = -e^{i arg x_k}|x|, is formed redundantly by every group; its
         // head v_k goes to vhead (x_k itself stays in place, R's diagonal is kept in diag).
         // Once the pivot norm drops to M 2^-24 times the first one, the remaining rows of R are
-        // FP32 noise: the numerical rank is k.
+        // FP32 noise: the numerical rank is k.  The unused columns are kept packed in clist
+        // (the pivot leaves by swapping in the last entry), so the update pass of step k occupies
+        // only ceil((M - k - 1) / groups-per-wave) waves' worth of groups.
         for (int c = g; c < M && g < NG; c += NG) {
             float s = 0.f;
 #pragma unroll
@@ -227,7 +235,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         __syncthreads();
         int rk = M;
         float thr = 0.0f;
-        unsigned long long used = 0ull;    // columns already chosen (M <= 64)
+        int nrem = M;                      // unused columns: clist[0 .. nrem)
         int kc = 0, kn = 1, kz = 2;        // pkey slots of steps k, k+1, k+2
         for (int k = 0; k < M; ++k) {
             const unsigned long long key = pkey[kc];
@@ -244,6 +252,12 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
             const float2 ph = axk > 0.f ? make_float2(xk.x * rax, xk.y * rax) : make_float2(1.f, 0.f);
             const float tk = __builtin_amdgcn_rcpf(nx * (nx + axk));
             const float2 vk = make_float2(ph.x * (axk + nx), ph.y * (axk + nx));
+            // p leaves the list: slot idx takes the last entry.  Every thread applies the swap
+            // virtually in this step (slot idx reads `last`), thread 0 writes it for the next;
+            // nothing else reads clist[idx] or cinv[last] in this step.
+            const int idx = cinv[p];
+            const int last = clist[nrem - 1];
+            --nrem;
             if (tid == 0) {
                 diag[k] = make_float2(-ph.x * nx, -ph.y * nx);
                 vhead[k] = vk;
@@ -251,10 +265,11 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                 colmap[k] = p;
                 pos[p] = k;
                 pkey[kz] = 0ull;           // read by everyone in step k-1, posted in step k+1
+                clist[idx] = last;
+                cinv[last] = idx;
             }
-            used |= 1ull << p;
-            for (int c = g; c < M && g < NG; c += NG) {
-                if ((used >> c) & 1ull) continue;
+            for (int sl = g; sl < nrem && g < NG; sl += NG) {
+                const int c = (sl == idx) ? last : clist[sl];
                 const float tn = apply_reflector<MP, G>(X + p * MP, vk, k, tk, X, c, M, q);
                 if (q == 0) atomicMax(&pkey[kn], pivot_key(tn, c));
             }

@@ -53,7 +53,7 @@ struct ssl_ctx_s {
     std::vector<GraphEntry> graphs;
     int cu_count = 0;
     // Jacobi variant (lanes per column pair) per size class 8/16/32/64 channels
-    int jac_lanes[4] = {8, 16, 16, 16};
+    int jac_lanes[4] = {8, 8, 8, 8};     // lanes per Jacobi column pair, classes 8/16/32/64
 };
 
 struct ssl_noise_s {

@@ -66,7 +66,7 @@ def test_unavailable_variant_rejected(S):
         S.ssl_ctx_set_jacobi_lanes(ctx, 60, 4)
     with pytest.raises(S.SSLError):
         S.ssl_ctx_set_jacobi_lanes(ctx, 8, 16)
-    assert S.ssl_ctx_get_jacobi_lanes(ctx, 60) == 16
+    assert S.ssl_ctx_get_jacobi_lanes(ctx, 60) == 8        # the default is untouched
     S.ssl_ctx_destroy(ctx)
 
 
@@ -90,7 +90,7 @@ def test_variant_applies_to_batch_and_single(S):
     import torch
     import synth
     ctx = S.ssl_ctx_create(0, 0)
-    S.ssl_ctx_set_jacobi_lanes(ctx, 60, 8)
+    S.ssl_ctx_set_jacobi_lanes(ctx, 60, 16)
     w = synth.workload_paper(n_blocks=4)
     Xn = w.noise_frames()
     Kd = torch.zeros((w.F, w.M, w.M), dtype=torch.complex128, device="cuda:0")
@@ -108,7 +108,7 @@ def test_variant_applies_to_batch_and_single(S):
         S.ssl_localize(ctx, X, n, Hd, S.SSL_FP32, 72, 19, w.Ns, 2, pk, pv, pb)
         single.append((to_host(pk), to_host(pb)))
     outs = [mk() for _ in Xs]
-    say("ssl_localize_batch with lanes=8")
+    say("ssl_localize_batch with lanes=16")
     S.ssl_localize_batch(ctx, [S.block_desc(X, n, Hd, 72, 19, w.Ns, o[0], o[1], o[2]) for X, o in zip(Xs, outs)],
                          S.SSL_FP32, 2)
     for (pk, pb), o in zip(single, outs):
