@@ -50,15 +50,17 @@ __device__ __forceinline__ void tile_to_lds(float2 *Rs, int RS, int I, int J, co
 __device__ __forceinline__ void lds_to_out(const float2 *Rs, int RS, int M, int accumulate,
                                            float2 *__restrict__ Rf, int tid)
 {
-    for (int e = tid; e < M * M; e += kThreads) {
-        const int i = e / M, j = e - i * M;
+    // row i by wave, column j by lane (M <= 64): coalesced rows, no index division
+    for (int i = tid >> 6; i < M; i += kThreads / 64) {
+        const int j = tid & 63;
+        if (j >= M) continue;
         float2 v = Rs[i * RS + j];
         if (accumulate) {
-            const float2 a = Rf[e];
+            const float2 a = Rf[(size_t)i * M + j];
             v.x += a.x;
             v.y += a.y;
         }
-        Rf[e] = v;
+        Rf[(size_t)i * M + j] = v;
     }
 }
 
@@ -302,12 +304,14 @@ int resident_grid(K kernel, int n)
 }
 
 // ---------------------------------------------------------------------------------------------
-// FP64 accumulation (noise correlation K): one thread per upper-triangle entry (i <= j).
-__global__ __launch_bounds__(kThreads) void corr_f64(const float2 *__restrict__ X, int T, int M,
+// FP64 accumulation (noise correlation K): one thread per upper-triangle entry (i <= j), 1024
+// threads so that each holds about two entries and a CU keeps 4 waves per SIMD busy.
+constexpr int kF64Threads = 1024;
+__global__ __launch_bounds__(kF64Threads) void corr_f64(const float2 *__restrict__ X, int T, int M,
                                                      int64_t sF, int64_t sT, double scale,
                                                      int accumulate, double2 *__restrict__ R)
 {
-    constexpr int MAXE = (SSL_MAX_M * (SSL_MAX_M + 1) / 2 + kThreads - 1) / kThreads;
+    constexpr int MAXE = (SSL_MAX_M * (SSL_MAX_M + 1) / 2 + kF64Threads - 1) / kF64Threads;
     __shared__ float2 Z[kChunk * SSL_MAX_M];
     const int f = blockIdx.x;
     const int tid = threadIdx.x;
@@ -318,7 +322,7 @@ __global__ __launch_bounds__(kThreads) void corr_f64(const float2 *__restrict__ 
     double accr[MAXE], acci[MAXE];
 #pragma unroll
     for (int q = 0; q < MAXE; ++q) {
-        int e = tid + q * kThreads;
+        int e = tid + q * kF64Threads;
         int i = 0;
         if (e < nent) {
             while (e >= M - i) { e -= M - i; ++i; }
@@ -334,9 +338,9 @@ __global__ __launch_bounds__(kThreads) void corr_f64(const float2 *__restrict__ 
     for (int t0 = 0; t0 < T; t0 += kChunk) {
         const int nf = min(kChunk, T - t0);
         __syncthreads();
-        for (int e = tid; e < nf * M; e += kThreads) {
-            const int tt = e / M, m = e - tt * M;
-            Z[tt * SSL_MAX_M + m] = Xf[(size_t)(t0 + tt) * sT + m];
+        for (int tt = tid >> 6; tt < nf; tt += kF64Threads / 64) {   // frame by wave, m by lane
+            const int m = tid & 63;
+            if (m < M) Z[tt * SSL_MAX_M + m] = Xf[(size_t)(t0 + tt) * sT + m];
         }
         __syncthreads();
 #pragma unroll
@@ -429,7 +433,7 @@ hipError_t launch_corr(const ssl_c64 *X, int F, int T, int M, int64_t sF, int64_
                        int accumulate, ssl_prec prec, void *R, hipStream_t st)
 {
     if (prec == SSL_FP64) {
-        hipLaunchKernelGGL(corr_f64, dim3(F), dim3(kThreads), 0, st,
+        hipLaunchKernelGGL(corr_f64, dim3(F), dim3(kF64Threads), 0, st,
                            reinterpret_cast<const float2 *>(X), T, M, sF, sT, scale, accumulate,
                            reinterpret_cast<double2 *>(R));
         return hipGetLastError();

@@ -287,9 +287,9 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         // Z[x][c] = conj(R[c][pos x]).  R[c][pos x] sits at (column x, row c), so Z is a masked
         // conjugate transpose: each thread exchanges the pair (c, x), (x, c) it owns.
         if (tid == 0) rank_s = rk;
-        for (int e = tid; e < M * M; e += NT) {
-            const int k = e / M, r = e - k * M;
-            if (r >= k && k < rk) Af[e] = (r == k) ? vhead[k] : X[colmap[k] * MP + r];
+        for (int e = tid; e < rk * MP; e += NT) {          // reflector k = e / MP, row e % MP
+            const int k = e / MP, r = e % MP;
+            if (r >= k && r < M) Af[k * M + r] = (r == k) ? vhead[k] : X[colmap[k] * MP + r];
         }
         __syncthreads();
         for (int e = tid; e < MP * MP; e += NT) {
@@ -545,9 +545,9 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
     // ---- outputs ------------------------------------------------------------------------------
     const bool ok = (flag == SSL_BIN_OK) && converged;
     const int st = (flag != SSL_BIN_OK) ? flag : (converged ? SSL_BIN_OK : SSL_BIN_NO_CONV);
-    for (int e = tid; e < Nn * M; e += NT) {
-        const int c = e / M, r = e - c * M;
-        Enf[e] = ok ? X[perm[Ns + c] * MP + r] : make_float2(0.f, 0.f);
+    for (int e = tid; e < Nn * MP; e += NT) {              // noise vector c = e / MP, row e % MP
+        const int c = e / MP, r = e % MP;
+        if (r < M) Enf[c * M + r] = ok ? X[perm[Ns + c] * MP + r] : make_float2(0.f, 0.f);
     }
     if (sigf != nullptr)
         for (int k = tid; k < M; k += NT) sigf[k] = ok ? sig[perm[k]] : 0.0f;

@@ -38,9 +38,9 @@ __global__ __launch_bounds__(kFactorThreads) void noise_factor(const double2 *__
     const double2 *Kf = K + (size_t)f * M * M;
     double2 *Wf = Kinv + (size_t)f * M * M;
 
-    for (int e = tid; e < M * M; e += kFactorThreads) {
-        const int i = e / M, j = e - i * M;
-        W[i * MP + j] = Kf[e];
+    for (int e = tid; e < M * MP; e += kFactorThreads) {
+        const int i = e / MP, j = e % MP;
+        if (j < M) W[i * MP + j] = Kf[i * M + j];
     }
     __syncthreads();
     if (tid == 0) {
@@ -64,9 +64,9 @@ __global__ __launch_bounds__(kFactorThreads) void noise_factor(const double2 *__
             break;
         }
         const double ip = 1.0 / p;
-        for (int e = tid; e < M * M; e += kFactorThreads) {
-            const int i = e / M, j = e - i * M;
-            if (i == k || j == k) continue;
+        for (int e = tid; e < MP * MP; e += kFactorThreads) {
+            const int i = e / MP, j = e % MP;             // MP is a power of two: shifts
+            if (i >= M || j >= M || i == k || j == k) continue;
             const double2 t = cmul(W[i * MP + k], W[k * MP + j]);
             double2 w = W[i * MP + j];
             w.x = fma(-t.x, ip, w.x);
@@ -85,9 +85,9 @@ __global__ __launch_bounds__(kFactorThreads) void noise_factor(const double2 *__
         }
         __syncthreads();
     }
-    for (int e = tid; e < M * M; e += kFactorThreads) {
-        const int i = e / M, j = e - i * M;
-        Wf[e] = bad ? make_double2(0.0, 0.0) : W[i * MP + j];
+    for (int e = tid; e < M * MP; e += kFactorThreads) {
+        const int i = e / MP, j = e % MP;
+        if (j < M) Wf[i * M + j] = bad ? make_double2(0.0, 0.0) : W[i * MP + j];
     }
     if (tid == 0) status[f] = bad ? SSL_BIN_NOT_PD : SSL_BIN_OK;
 }

@@ -131,7 +131,7 @@ class GpuExecutor:
 
     def __init__(self, streams, steering, prec=None, p: int = 2, alpha: float = 0.95,
                  k_update_every: int = 1, hbm_budget_bytes: int = 4 << 30, lanes: int = 2,
-                 pool: int = 4, device: int = 0):
+                 pool: int = 4, device: int = 0, noise_streams: int = 4):
         import torch
 
         from . import (SSL_FP32, SSL_FP64, block_desc, ssl_corr_accum, ssl_ctx_create,
@@ -154,15 +154,20 @@ class GpuExecutor:
             ssl_ctx_use_graphs(c, False)
         self.nctx = ssl_ctx_create(device, 0)
         self.tstreams = [torch.cuda.Stream(device=self.dev) for _ in range(lanes)]
-        self.nstream = torch.cuda.Stream(device=self.dev)
-        self.noise_event = None
+        # K updates go round-robin over a few streams (one update is a few hundred workgroups:
+        # alone it leaves most of the device idle); each array stream remembers the event of its
+        # last update, and a batch waits for those of its own streams only
+        self.nstreams = [torch.cuda.Stream(device=self.dev) for _ in range(max(1, noise_streams))]
+        self.next_ns = 0
+        self.k_event = [None] * len(self.streams)
         # steering tables per channel count (shared by streams of the same geometry)
         self.H = {M: t for M, t in steering.items()}
         self.noise, self.X_slot, self.Xn_slot, self.X_pool, self.Xn_pool = [], [], [], [], []
         self.k_version = [0] * len(self.streams)
         Mmax = max(s.M for s in self.streams)
         Fmax = max(s.F for s in self.streams)
-        self.Khat = torch.zeros((Fmax * Mmax * Mmax,), dtype=torch.complex128, device=self.dev)
+        self.Khat = [torch.zeros((Fmax * Mmax * Mmax,), dtype=torch.complex128, device=self.dev)
+                     for _ in self.nstreams]
         for s in self.streams:
             Xn0 = torch.from_numpy(s.initial_noise_frames()).to(self.dev)
             K0 = torch.zeros((s.F, s.M, s.M), dtype=torch.complex128, device=self.dev)
@@ -203,8 +208,12 @@ class GpuExecutor:
         st = self.tstreams[lane]
         descs = []
         with torch.cuda.stream(st):
-            if self.noise_event is not None:
-                st.wait_event(self.noise_event)
+            waited = set()
+            for r in reqs:
+                ev = self.k_event[r.stream]
+                if ev is not None and id(ev) not in waited:
+                    st.wait_event(ev)
+                    waited.add(id(ev))
             for i, r in enumerate(reqs):
                 s = self.streams[r.stream]
                 self.X_slot[r.stream].copy_(self.X_pool[r.stream][r.seq % self.pool], non_blocking=True)
@@ -234,21 +243,24 @@ class GpuExecutor:
             r.peaks = pk[i, :ns].copy()
             r.peak_val = pv[i, :ns].copy()
         # K EMA updates of this batch's streams, after the batch (which read the old K)
-        ups = [r for r in reqs if (r.seq + 1) % self.k_every == 0]
-        if ups:
-            with torch.cuda.stream(self.nstream):
-                self.nstream.wait_event(ev)
-                for r in ups:
-                    s = self.streams[r.stream]
-                    xn = self.Xn_slot[r.stream]
-                    xn.copy_(self.Xn_pool[r.stream][r.seq % self.pool], non_blocking=True)
-                    Kh = self.Khat[: s.F * s.M * s.M].view(s.F, s.M, s.M)
-                    ssl_corr_accum(self.nctx, xn, 1.0 / s.T, 0, self._fp64, Kh, stream=self.nstream)
-                    ssl_noise_update(self.noise[r.stream], Kh, self._fp64, self.alpha,
-                                     stream=self.nstream)
-                    self.k_version[r.stream] += 1
-                self.noise_event = torch.cuda.Event()
-                self.noise_event.record(self.nstream)
+        for r in reqs:
+            if (r.seq + 1) % self.k_every != 0:
+                continue
+            i = self.next_ns
+            self.next_ns = (i + 1) % len(self.nstreams)
+            ns = self.nstreams[i]
+            s = self.streams[r.stream]
+            with torch.cuda.stream(ns):
+                ns.wait_event(ev)                 # after the batch that read the old K
+                xn = self.Xn_slot[r.stream]
+                xn.copy_(self.Xn_pool[r.stream][r.seq % self.pool], non_blocking=True)
+                Kh = self.Khat[i][: s.F * s.M * s.M].view(s.F, s.M, s.M)
+                ssl_corr_accum(self.nctx, xn, 1.0 / s.T, 0, self._fp64, Kh, stream=ns)
+                ssl_noise_update(self.noise[r.stream], Kh, self._fp64, self.alpha, stream=ns)
+                done = torch.cuda.Event()
+                done.record(ns)
+            self.k_event[r.stream] = done
+            self.k_version[r.stream] += 1
         self.inflight[lane] = None
 
     def close(self) -> None:
