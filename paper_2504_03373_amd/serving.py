@@ -10,7 +10,8 @@ fresh FP64 inverse), the update of block n landing before the stream's block n +
 
 Rules: at most one block per stream is in flight (keeps per-stream order and the K update
 sequence exact); a lane's batch never needs more than its share of the HBM budget; requests wait
-in arrival order, skipping only blocks of streams that are still in flight.
+in arrival order, skipping only blocks of streams that are still in flight (kept as one FIFO per
+stream, so forming a batch costs O(streams), not O(queue)).
 
 The executor interface (`lanes`, `cost_bytes`, `submit`, `poll`, `collect`) is what the scheduler
 needs; `GpuExecutor` implements it with the library's C ABI.
@@ -52,18 +53,26 @@ class Server:
     def run(self, arrivals: Sequence[tuple]) -> dict:
         """arrivals: (emit time s, stream, seq), sorted by time.  Runs until every block is done."""
         pending = collections.deque(Request(stream=s, seq=q, emit_t=t) for t, s, q in arrivals)
-        ready: List[Request] = []
+        # ready blocks, one FIFO per stream: since a stream has at most one block in flight, the
+        # candidates of a batch are the heads of the idle streams, taken in emission order --
+        # the same order as scanning one arrival-ordered queue and skipping busy streams, at a
+        # cost of O(streams) per batch instead of O(queue)
+        queues = collections.defaultdict(collections.deque)
+        n_ready = 0
         busy_streams = set()
+        cost_of = {}
         lanes = [None] * self.ex.lanes          # per lane: list of requests in flight
         done: List[Request] = []
         batches = 0
         max_ready = 0
         t0 = self.clock()
-        while pending or ready or any(lanes):
+        while pending or n_ready or any(lanes):
             now = self.clock() - t0
             while pending and pending[0].emit_t <= now:
-                ready.append(pending.popleft())
-            max_ready = max(max_ready, len(ready))
+                r = pending.popleft()
+                queues[r.stream].append(r)
+                n_ready += 1
+            max_ready = max(max_ready, n_ready)
             progressed = False
             for li, reqs in enumerate(lanes):
                 if reqs and self.ex.poll(li):
@@ -76,24 +85,29 @@ class Server:
                     lanes[li] = None
                     progressed = True
             for li in range(len(lanes)):
-                if lanes[li] is not None or not ready:
+                if lanes[li] is not None or not n_ready:
                     continue
-                batch, cost, keep = [], 0, []
-                for r in ready:
-                    c = self.ex.cost_bytes(r.stream)
-                    if (len(batch) < self.max_batch and r.stream not in busy_streams
-                            and cost + c <= self.lane_budget):
+                heads = sorted((q[0] for sid, q in queues.items() if q and sid not in busy_streams),
+                               key=lambda r: (r.emit_t, r.stream, r.seq))
+                batch, cost = [], 0
+                for r in heads:
+                    if len(batch) >= self.max_batch:
+                        break
+                    if r.stream not in cost_of:
+                        cost_of[r.stream] = self.ex.cost_bytes(r.stream)
+                    c = cost_of[r.stream]
+                    if cost + c <= self.lane_budget:
                         batch.append(r)
-                        busy_streams.add(r.stream)
                         cost += c
-                    else:
-                        keep.append(r)
                 if not batch:
-                    if not any(lanes) and ready and all(self.ex.cost_bytes(r.stream) > self.lane_budget
-                                                        for r in ready):
+                    if not any(lanes) and heads and all(cost_of[r.stream] > self.lane_budget
+                                                        for r in heads):
                         raise RuntimeError("a single block exceeds the per-lane HBM budget")
                     break
-                ready = keep
+                for r in batch:
+                    queues[r.stream].popleft()
+                    busy_streams.add(r.stream)
+                n_ready -= len(batch)
                 tsub = self.clock() - t0
                 for r in batch:
                     r.submit_t = tsub
