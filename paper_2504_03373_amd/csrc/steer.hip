@@ -281,26 +281,39 @@ __device__ __forceinline__ void steer_tile(const E *__restrict__ Hf, int D, int 
     hn += __shfl_xor(hn, 32);
     if (lane < 16) nrm_s[wave * 16 + lane] = hn;
 
+    // software pipeline over the blocks: block i + 1's E_n loads are issued before block i's
+    // MFMAs and written to LDS right after them (Bs is free once every wave has its fragments);
+    // block i's epilogue then works on registers while the next B is in place
+    const float2 *Enf;
+    bool ok;
+    int Ns;
+    float *Pf;
+    blk(0, Enf, ok, Ns, Pf);
+    {
+        BStage<NCT> st;
+        load_b<NCT>(Enf, M, M - Ns, tid, st);
+        store_b<NCT, E>(st, Bs, KS, KP, tid);
+    }
+    __syncthreads();
     for (int i = 0; i < nb; ++i) {
-        const float2 *Enf;
-        bool ok;
-        int Ns;
-        float *Pf;
-        blk(i, Enf, ok, Ns, Pf);
         // opaque copies of the thread indices: the operand addresses derived from them are
         // recomputed per block instead of being hoisted out of the loop and held in registers
         int tid_i = tid, lane_i = lane;
         asm volatile("" : "+v"(tid_i), "+v"(lane_i));
-        {
-            BStage<NCT> st;                // every E_n load in flight before the LDS stores
+        const bool cur_ok = ok;
+        float *const cur_P = Pf;
+        const bool more = i + 1 < nb;
+        BStage<NCT> st;
+        if (more) {
+            blk(i + 1, Enf, ok, Ns, Pf);
             load_b<NCT>(Enf, M, M - Ns, tid_i, st);
-            store_b<NCT, E>(st, Bs, KS, KP, tid_i);
         }
-        __syncthreads();                   // B staged (and the previous block's epilogue done)
         floatx4 acc1[NCT], acc2[NCT];
         mma<NCT, E>(S, Bs, KS, KQ, lane_i, acc1, acc2);
-        finish_rows<NCT>(acc1, acc2, p, lane, wave, d0, D, ok, Pf, den_s, nrm_s);
-        __syncthreads();                   // Bs and den_s free for the next block
+        __syncthreads();                   // every wave has read Bs
+        if (more) store_b<NCT, E>(st, Bs, KS, KP, tid_i);
+        finish_rows<NCT>(acc1, acc2, p, lane, wave, d0, D, cur_ok, cur_P, den_s, nrm_s);
+        __syncthreads();                   // next B staged, den_s free
     }
 }
 
