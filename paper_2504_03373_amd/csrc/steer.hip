@@ -134,8 +134,9 @@ __device__ __forceinline__ float load_strip(const E *__restrict__ Hf, int D, int
 
 // E_n[f] as the B operand: Bs[c * KS + k] = real k of noise vector c (k < 2M), zero for c >= Nn
 // or k >= 2M up to the k-chunk padding KP.  Thread tid owns elements e = tid + u * kThreads of a
-// NCOL x 64 complex grid (column c = e / 64, element m = e % 64: shifts, no division); load_b puts
-// them in registers (all loads in flight at once), store_b writes those with m < KP / 2.
+// NCOL x 64 complex grid (column c = e / 64 = tid / 64 + 8u, element m = e % 64 = tid % 64);
+// load_b puts them in registers (all loads in flight at once), store_b writes those with
+// m < KP / 2.
 template <int NCT> struct BStage {
     static constexpr int NIT = 16 * NCT * 64 / kThreads;
     float2 v[NIT];
@@ -145,28 +146,29 @@ template <int NCT>
 __device__ __forceinline__ void load_b(const float2 *__restrict__ Enf, int M, int Nn, int tid,
                                        BStage<NCT> &st)
 {
+    // element u of this thread: column c0 + 8u, row m (fixed): one base address and a stride
+    const int c0 = tid >> 6, m = tid & 63;
+    const float2 *src = Enf + (size_t)c0 * M + m;
+    const bool mok = m < M;
 #pragma unroll
-    for (int u = 0; u < BStage<NCT>::NIT; ++u) {
-        const int e = tid + u * kThreads;
-        const int c = e >> 6, m = e & 63;
-        st.v[u] = (c < Nn && m < M) ? Enf[(size_t)c * M + m] : make_float2(0.f, 0.f);
-    }
+    for (int u = 0; u < BStage<NCT>::NIT; ++u)
+        st.v[u] = (mok && c0 + 8 * u < Nn) ? src[(size_t)u * 8 * M] : make_float2(0.f, 0.f);
 }
 
 template <int NCT, typename E>
 __device__ __forceinline__ void store_b(const BStage<NCT> &st, E *Bs, int KS, int KP, int tid)
 {
+    const int c0 = tid >> 6, m = tid & 63;
+    if (2 * m >= KP) return;
+    E *dst = Bs + c0 * KS + 2 * m;
 #pragma unroll
     for (int u = 0; u < BStage<NCT>::NIT; ++u) {
-        const int e = tid + u * kThreads;
-        const int c = e >> 6, m = e & 63;
-        if (2 * m >= KP) continue;
         const float2 v = st.v[u];
         if constexpr (sizeof(E) == 4) {
-            *(float2 *)&Bs[c * KS + 2 * m] = v;
+            *(float2 *)(dst + u * 8 * KS) = v;
         } else {
             E pr[2] = {(E)v.x, (E)v.y};
-            *(uint32_t *)&Bs[c * KS + 2 * m] = __builtin_bit_cast(uint32_t, pr);
+            *(uint32_t *)(dst + u * 8 * KS) = __builtin_bit_cast(uint32_t, pr);
         }
     }
 }
@@ -251,7 +253,9 @@ __device__ __forceinline__ void finish_rows(const floatx4 (&acc1)[NCT], const fl
         const int d = d0 + wave * 16 + lane;
         if (d < D) {
             const float den = den_s[wave * 16 + lane];
-            Pf[d] = bin_ok ? nrm_s[wave * 16 + lane] / fmaxf(den, 1.17549435e-38f) : 0.0f;
+            // hardware reciprocal (1 ulp): P is compared at 1e-4, den >= FLT_MIN
+            Pf[d] = bin_ok ? nrm_s[wave * 16 + lane] * __builtin_amdgcn_rcpf(fmaxf(den, 1.17549435e-38f))
+                           : 0.0f;
         }
     }
 }
