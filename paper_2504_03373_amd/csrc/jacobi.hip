@@ -385,6 +385,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                         float al = 0.f, be = 0.f, gr = 0.f, gi = 0.f;
 #pragma unroll
                         for (int k = 0; k < R; ++k) {
+                            if (G * k >= rk) break;     // rows >= rk of X are zero (uniform)
                             const int r = q + G * k;
                             bi[k] = Bs[ci * MP + r];
                             bj[k] = Bs[cj * MP + r];
@@ -426,6 +427,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                             const float wi = -s * gi * rg;
 #pragma unroll
                             for (int k = 0; k < R; ++k) {
+                                if (G * k >= rk) break;
                                 const int r = q + G * k;
                                 float2 x = bi[k], y = bj[k];
                                 float2 ni, nj;
