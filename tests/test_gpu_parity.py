@@ -216,6 +216,63 @@ def test_gsvd_parity(S, ctx, M, Ns):
     say(f"  projector error * gap / |A|: max {max(errs):.3g} (units of u: {max(errs) / U32:.1f})")
 
 
+@pytest.mark.parametrize("M,Ns,T", [(8, 7, 50), (60, 59, 130)])
+def test_gsvd_single_noise_vector(S, ctx, M, Ns, T):
+    """Ns = M - 1: E_n is one vector (full-rank R so that it is unique up to phase)."""
+    say(f"ssl_gsvd M={M} Ns={Ns} T={T} F=7")
+    F = 7
+    R, K = gsvd_case(M, F, Ns, seed=700 + M, T=T)
+    g = run_gsvd(S, ctx, R, K, Ns)
+    En_ref, sig_ref, st_ref, _ = oracle.gsvd(K, R, Ns)
+    assert np.all(g["status"] == 0) and np.all(g["conv"][:, 2] == M)
+    for f in range(F):
+        nA = np.linalg.norm(np.linalg.solve(K[f], R[f]))
+        gap = sig_ref[f, Ns - 1] - sig_ref[f, Ns]
+        err = np.linalg.norm(projector(g["En"][f].T.astype(np.complex128)) - projector(En_ref[f].T), 2)
+        assert err <= 16 * M * U32 * nA / gap, (f, err, gap)
+
+
+def test_gsvd_max_bins(S, ctx):
+    """F at its limit (65535 bins, M = 2): every bin converged; sampled bins against the oracle."""
+    say("ssl_gsvd F=65535 M=2 Ns=1")
+    F, M, Ns = 65535, 2, 1
+    R, K = gsvd_case(M, F, Ns, seed=65535, T=5)
+    g = run_gsvd(S, ctx, R, K, Ns)
+    assert np.all(g["status"] == 0)
+    pick = np.random.default_rng(1).choice(F, 200, replace=False)
+    En_ref, sig_ref, _, _ = oracle.gsvd(K[pick], R[pick], Ns)
+    for i, f in enumerate(pick):
+        nA = np.linalg.norm(np.linalg.solve(K[f], R[f]))
+        gap = sig_ref[i, 0] - sig_ref[i, 1]
+        err = np.linalg.norm(projector(g["En"][f].T.astype(np.complex128)) - projector(En_ref[i].T), 2)
+        assert err <= 16 * M * U32 * nA / gap + 1e-6, (f, err, gap)
+
+
+def test_empty_and_out_of_range_shapes(S, ctx):
+    """Empty inputs (F = 0, T = 0, an empty batch) and sizes past the limits are argument errors:
+    nothing is enqueued."""
+    import torch
+    say("empty / out-of-range shapes")
+    R = torch.zeros((1, 8, 8), dtype=torch.complex64, device="cuda:0")
+    X0 = torch.zeros((0, 5, 8), dtype=torch.complex64, device="cuda:0")
+    with pytest.raises(S.SSLError) as e:
+        S.ssl_corr_accum(ctx, X0, 1.0, 0, S.SSL_FP32, R[:0])            # F = 0
+    assert e.value.code == S.SSL_ERR_ARG
+    XT = torch.zeros((1, 0, 8), dtype=torch.complex64, device="cuda:0")
+    with pytest.raises(S.SSLError) as e:
+        S.ssl_corr_accum(ctx, XT, 1.0, 0, S.SSL_FP32, R)                # T = 0
+    assert e.value.code == S.SSL_ERR_ARG
+    with pytest.raises(S.SSLError) as e:
+        S.ssl_localize_batch(ctx, [], S.SSL_FP32, 2)                     # no blocks
+    assert e.value.code == S.SSL_ERR_ARG
+    with pytest.raises(S.SSLError) as e:
+        S.ssl_noise_create(ctx, 65536, 2)                                # F past 65535
+    assert e.value.code == S.SSL_ERR_ARG
+    with pytest.raises(S.SSLError) as e:
+        S.ssl_noise_create(ctx, 4, 65)                                   # M past 64
+    assert e.value.code == S.SSL_ERR_ARG
+
+
 def test_gsvd_status_paths(S, ctx):
     say("ssl_gsvd status paths M=8 F=6")
     F, M, Ns = 6, 8, 2
