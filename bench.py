@@ -144,6 +144,8 @@ def main() -> int:
     ap.add_argument("--per-block-steps", type=int, default=100)
     ap.add_argument("--cpu-blocks", type=int, default=48, help="oracle sample size (blocks)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default kernel variants (no Jacobi / projection autotuning)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one plain streaming kernel of this size first (HBM counter scale)")
     ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -220,6 +222,8 @@ def main() -> int:
     Pbar = torch.zeros((B, D), dtype=torch.float32, device=dev)
     st = torch.zeros((B, F), dtype=torch.int32, device=dev)
 
+    tuning = {}
+
     def measure(name: str, with_h2d: bool) -> dict:
         prec = PREC[name]
         H = table(name)
@@ -228,6 +232,19 @@ def main() -> int:
         R = torch.zeros((F, M, M), dtype=torch.complex64, device=dev)
         En = torch.zeros((F, M - Ns, M), dtype=torch.complex64, device=dev)
         conv = torch.zeros((F, 3), dtype=torch.int32, device=dev)
+        if not args.no_autotune:
+            S.ssl_corr_accum(ctx, Xs[0], 1.0 / T, 0, prec, R)
+            S.ssl_gsvd(ctx, R, noise, Ns, En, None, None, conv, 0)
+            # variants chosen on this workload, each timed in the batched form the step runs: the
+            # Jacobi lanes per column pair (once; the SVD is FP32 whatever the input precision)
+            # and the projection tile for this precision, B blocks sharing the steering table
+            if "jacobi_lanes" not in tuning:
+                lanes, jms = S.ssl_autotune_jacobi(ctx, R, noise, Ns, nblocks=B, reps=2)
+                tuning["jacobi_lanes"] = lanes
+                tuning["jacobi_ms"] = {str(k): round(v, 4) for k, v in jms.items()}
+            waves, sms = S.ssl_autotune_steer(ctx, H, prec, En, Ns, p=2, nblocks=B, reps=3)
+            tuning.setdefault("steer_waves", {})[name] = waves
+            tuning.setdefault("steer_ms", {})[name] = {str(k): round(v, 4) for k, v in sms.items()}
         conv_all = []
         for b in range(B):
             S.ssl_corr_accum(ctx, Xs[b], 1.0 / T, 0, prec, R)
@@ -399,6 +416,7 @@ def main() -> int:
                           "mean_rank": round(float(np.mean([c[:, 2].mean() for c in conv_all])), 2)},
         "status_ok": main_r["status_ok"] and (f32 is None or f32["status_ok"]),
         "input_gen_s": round(gen_s, 2),
+        "tuning": tuning or "defaults (--no-autotune)",
     }
     if "h2d_serial" in main_r:
         out["h2d"] = {"serial": round(main_r["h2d_serial"], 2),
@@ -428,8 +446,15 @@ def main() -> int:
                         torch.bfloat16 if prec == S.SSL_BF16 else torch.float16).contiguous()
                 Hs[s_.M] = h
         budget = int(args.serve_budget_gb * (1 << 30))
+        def configure(c):
+            # the variants tuned above for the 60-channel class carry over to the serving contexts
+            if "jacobi_lanes" in tuning:
+                S.ssl_ctx_set_jacobi_lanes(c, M, tuning["jacobi_lanes"])
+            if args.prec in tuning.get("steer_waves", {}):
+                S.ssl_ctx_set_steer_waves(c, M, Ns, prec, tuning["steer_waves"][args.prec])
+
         ex = GpuExecutor(streams, Hs, prec=prec, alpha=0.95, k_update_every=args.k_update_every,
-                         hbm_budget_bytes=budget, lanes=2, pool=4)
+                         hbm_budget_bytes=budget, lanes=2, pool=4, configure=configure)
         srv = Server(ex, budget, max_batch=128)
         srv.run(synth.poisson_arrivals(len(streams), 0.1, args.serve_period_ms * 1e-3, seed=7))
         mix = {m: sum(1 for s_ in streams if s_.M == m) for m in sorted({s_.M for s_ in streams})}

@@ -219,10 +219,37 @@ int ssl_ctx_get_jacobi_lanes(ssl_ctx ctx, int M);
 /* Autotuner: times every available Jacobi variant of M's class on the caller's problems -- the
  * whitened products K^{-1} R[f] of F bins -- `reps` launches each (after one untimed launch),
  * with HIP events on `stream`, keeps the fastest in the context and returns it in *best_lanes.
- * ms_per_variant ([3], host, or NULL) receives the mean milliseconds per launch for lanes = 4, 8,
- * 16 (-1 where unavailable).  R: [F][M][M] device, K set for F and M.  Synchronous. */
+ * nblocks = 1 times the one-launch-per-block kernel of ssl_gsvd / ssl_localize; nblocks > 1 (up
+ * to 65535) times the persistent kernel of ssl_localize_batch over nblocks copies of the F
+ * bins, whose best variant can differ (occupancy against load balance).  ms_per_variant ([3],
+ * host, or NULL) receives the mean milliseconds per launch for lanes = 4, 8, 16 (-1 where
+ * unavailable).  R: [F][M][M] device, K set for F and M.  Uses context workspace (nblocks * F
+ * bins of A and E_n).  Synchronous. */
 ssl_status ssl_autotune_jacobi(ssl_ctx ctx, const ssl_c64 *R, ssl_noise K, int F, int M, int Ns,
-                               int reps, int *best_lanes, double *ms_per_variant, void *stream);
+                               int nblocks, int reps, int *best_lanes, double *ms_per_variant,
+                               void *stream);
+
+/* Steering-projection (eq.5) tile shape per noise-subspace class (M - Ns <= 16, <= 32, <= 64) and
+ * steering-table precision (SSL_FP32, SSL_BF16, SSL_FP16): the number of 64-lane waves per
+ * workgroup, each wave owning 16 directions of one bin.  Available: 4, 8 or 16.  Default 8.  Every
+ * direction's value is computed by one wave in the same order whatever the tile, so the choice
+ * changes speed only: P and Pbar are bit-identical across variants.  Applied by every entry
+ * point of the context.  Returns SSL_ERR_ARG for an unavailable variant (get returns -1). */
+ssl_status ssl_ctx_set_steer_waves(ssl_ctx ctx, int M, int Ns, ssl_prec hprec, int waves);
+int ssl_ctx_get_steer_waves(ssl_ctx ctx, int M, int Ns, ssl_prec hprec);
+
+/* Autotuner for the projection tile: times the projection kernel for every available tile shape
+ * on the caller's problem -- H [F][D][M] in hprec and En [F][M][M - Ns] (both device) -- `reps`
+ * launches each (after one untimed launch) with HIP events on `stream`, keeps the fastest in the
+ * context and returns it in *best_waves.  nblocks = 1 times the single-block kernel of
+ * ssl_music_spectrum / ssl_localize; nblocks > 1 (up to 65535) times the batched kernel of
+ * ssl_localize_batch as it runs when nblocks blocks share the steering table (En repeated), the
+ * case whose best tile differs because H is read once for all of them.  ms_per_variant ([3],
+ * host, or NULL) receives the mean milliseconds per launch for 4, 8, 16 waves.  Uses context
+ * workspace (nblocks * F * D floats for P, plus descriptors).  Synchronous. */
+ssl_status ssl_autotune_steer(ssl_ctx ctx, const void *H, ssl_prec hprec, const ssl_c64 *En,
+                              int F, int D, int M, int Ns, int p, int nblocks, int reps,
+                              int *best_waves, double *ms_per_variant, void *stream);
 
 #ifdef __cplusplus
 }

@@ -27,6 +27,7 @@ EXPORTED = [
     "ssl_noise_destroy", "ssl_gsvd", "ssl_music_spectrum", "ssl_peaks", "ssl_localize",
     "ssl_ctx_timing", "ssl_ctx_timing_read", "ssl_localize_batch", "ssl_ctx_use_graphs",
     "ssl_ctx_set_jacobi_lanes", "ssl_ctx_get_jacobi_lanes", "ssl_autotune_jacobi",
+    "ssl_ctx_set_steer_waves", "ssl_ctx_get_steer_waves", "ssl_autotune_steer",
 ]
 
 
@@ -80,8 +81,12 @@ def lib() -> ctypes.CDLL:
         "ssl_ctx_use_graphs": (I, [P, I]),
         "ssl_ctx_set_jacobi_lanes": (I, [P, I, I]),
         "ssl_ctx_get_jacobi_lanes": (I, [P, I]),
-        "ssl_autotune_jacobi": (I, [P, P, P, I, I, I, I, ctypes.POINTER(I),
+        "ssl_autotune_jacobi": (I, [P, P, P, I, I, I, I, I, ctypes.POINTER(I),
                                     ctypes.POINTER(ctypes.c_double), P]),
+        "ssl_ctx_set_steer_waves": (I, [P, I, I, I, I]),
+        "ssl_ctx_get_steer_waves": (I, [P, I, I, I]),
+        "ssl_autotune_steer": (I, [P, P, I, P, I, I, I, I, I, I, I, ctypes.POINTER(I),
+                                   ctypes.POINTER(ctypes.c_double), P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -246,11 +251,34 @@ def ssl_ctx_get_jacobi_lanes(ctx, M: int) -> int:
     return lib().ssl_ctx_get_jacobi_lanes(ctx, M)
 
 
-def ssl_autotune_jacobi(ctx, R, noise, Ns: int, reps: int = 3, stream=None):
-    """Times the Jacobi variants of R's channel class; returns (best lanes, {lanes: ms})."""
+def ssl_autotune_jacobi(ctx, R, noise, Ns: int, nblocks: int = 1, reps: int = 3, stream=None):
+    """Times the Jacobi variants of R's channel class, one block per launch (nblocks = 1) or the
+    persistent batched kernel over nblocks blocks; returns (best lanes, {lanes: ms})."""
     F, M, _ = R.shape
     best = ctypes.c_int(0)
     ms = (ctypes.c_double * 3)()
-    _check("ssl_autotune_jacobi", lib().ssl_autotune_jacobi(ctx, _ptr(R), noise, F, M, Ns, reps,
+    _check("ssl_autotune_jacobi", lib().ssl_autotune_jacobi(ctx, _ptr(R), noise, F, M, Ns, nblocks, reps,
                                                             ctypes.byref(best), ms, _stream(stream)))
     return best.value, {l: ms[i] for i, l in enumerate((4, 8, 16)) if ms[i] >= 0}
+
+
+def ssl_ctx_set_steer_waves(ctx, M: int, Ns: int, hprec: int, waves: int) -> None:
+    _check("ssl_ctx_set_steer_waves", lib().ssl_ctx_set_steer_waves(ctx, M, Ns, hprec, waves))
+
+
+def ssl_ctx_get_steer_waves(ctx, M: int, Ns: int, hprec: int) -> int:
+    return lib().ssl_ctx_get_steer_waves(ctx, M, Ns, hprec)
+
+
+def ssl_autotune_steer(ctx, H, hprec, En, Ns: int, p: int = 2, nblocks: int = 1, reps: int = 3,
+                       stream=None):
+    """Times the projection tile shapes on (H, En), single-block (nblocks = 1) or batched over
+    nblocks blocks sharing H; returns (best waves, {waves: ms})."""
+    F, D = H.shape[0], H.shape[1]
+    M = En.shape[2]                                  # En: [F][M - Ns][M], a noise vector per row
+    best = ctypes.c_int(0)
+    ms = (ctypes.c_double * 3)()
+    _check("ssl_autotune_steer", lib().ssl_autotune_steer(ctx, _ptr(H), hprec, _ptr(En), F, D, M,
+                                                          Ns, p, nblocks, reps, ctypes.byref(best), ms,
+                                                          _stream(stream)))
+    return best.value, {w: ms[i] for i, w in enumerate((4, 8, 16))}

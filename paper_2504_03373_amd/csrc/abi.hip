@@ -135,6 +135,10 @@ hipError_t timed(ssl_ctx ctx, int id, hipStream_t st, Fn &&launch)
 }
 
 int jac_lanes(ssl_ctx ctx, int M) { return ctx->jac_lanes[jacobi_class_index(jacobi_class(M))]; }
+int st_waves(ssl_ctx ctx, int M, int Ns, ssl_prec prec)
+{
+    return ctx->steer_waves[steer_class_index(steer_class(M, Ns))][prec];
+}
 
 ssl_status check_common(int F, int M, int Ns)
 {
@@ -509,7 +513,8 @@ ssl_status ssl_music_spectrum(ssl_ctx ctx, const void *H, ssl_prec hprec, const 
     if ((s = binsum_reserve(ctx, F, D)) != SSL_OK) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e = timed(ctx, SSL_K_STEER, st, [&] {
-        return launch_steer(H, hprec, En, F, D, M, Ns, p, bin_status, Pw, st);
+        return launch_steer(H, hprec, En, F, D, M, Ns, p, bin_status, Pw,
+                            st_waves(ctx, M, Ns, hprec), st);
     });
     if (e != hipSuccess) return hip_fail(e, "steer launch");
     e = timed(ctx, SSL_K_BINSUM, st, [&] {
@@ -597,7 +602,10 @@ ssl_status ssl_localize(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int M, int6
     });
     if (e != hipSuccess) return hip_fail(e, "jacobi launch");
     e = timed(ctx, SSL_K_STEER, st,
-              [&] { return launch_steer(H, prec, En, F, D, M, Ns, p, stt, P, st); });
+              [&] {
+                  return launch_steer(H, prec, En, F, D, M, Ns, p, stt, P,
+                                      st_waves(ctx, M, Ns, prec), st);
+              });
     if (e != hipSuccess) return hip_fail(e, "steer launch");
     e = timed(ctx, SSL_K_BINSUM, st, [&] {
         return launch_binsum_peaks(P, F, D, Pb, ctx->binsum_part, n_az, n_el, Ns, peaks,
@@ -619,6 +627,7 @@ int jacobi_queue(int cls) { return cls == 8 ? 0 : cls == 16 ? 1 : cls == 32 ? 2 
 
 struct Seg {
     int cls, start, count, extra;
+    int waves = 0;                         // projection: waves per workgroup
 };
 
 // Launch plan of one batch shape: per kernel, contiguous runs of items sharing a size class.
@@ -733,7 +742,7 @@ hipError_t enqueue_batch(ssl_ctx ctx, const Plan &P, const BlockDev *blk, const 
     for (const Seg &s : P.steer) {
         e = timed(ctx, SSL_K_STEER, st, [&] {
             return launch_steer_batch(blk, l_st + s.start, s.count, ga.groups, ga.gblocks, s.cls,
-                                      s.extra, prec, st);
+                                      s.waves, s.extra, prec, st);
         });
         if (e != hipSuccess) return e;
     }
@@ -763,7 +772,8 @@ int ssl_ctx_get_jacobi_lanes(ssl_ctx ctx, int M)
 }
 
 ssl_status ssl_autotune_jacobi(ssl_ctx ctx, const ssl_c64 *R, ssl_noise K, int F, int M, int Ns,
-                               int reps, int *best_lanes, double *ms_per_variant, void *stream)
+                               int nblocks, int reps, int *best_lanes, double *ms_per_variant,
+                               void *stream)
 {
     if (!ctx || !R || !K || !best_lanes) {
         ssl_set_error("ctx, R, K or best_lanes is NULL");
@@ -779,17 +789,63 @@ ssl_status ssl_autotune_jacobi(ssl_ctx ctx, const ssl_c64 *R, ssl_noise K, int F
         ssl_set_error("reps = %d out of range [1, 1000]", reps);
         return SSL_ERR_ARG;
     }
+    if (nblocks < 1 || nblocks > 65535) {
+        ssl_set_error("nblocks = %d out of range [1, 65535]", nblocks);
+        return SSL_ERR_ARG;
+    }
     DeviceGuard dg(ctx->device);
-    const size_t bA = align256((size_t)F * M * M * sizeof(ssl_c64));
-    const size_t bE = align256((size_t)F * (M - Ns) * M * sizeof(ssl_c64));
-    if ((s = ws_reserve(ctx, bA + bE)) != SSL_OK) return s;
-    ssl_c64 *A = static_cast<ssl_c64 *>(ctx->ws);
-    ssl_c64 *En = reinterpret_cast<ssl_c64 *>(static_cast<char *>(ctx->ws) + bA);
+    // workspace: A and E_n per block, then (batched form) bin status, descriptors and items
+    const size_t nb = (size_t)nblocks;
+    const size_t perA = (size_t)F * M * M, perE = (size_t)F * (M - Ns) * M;
+    const size_t bA = align256(nb * perA * sizeof(ssl_c64));
+    const size_t bE = align256(nb * perE * sizeof(ssl_c64));
+    const size_t bS = align256(nb * F * sizeof(int32_t));
+    const size_t bB = align256(nb * sizeof(BlockDev));
+    const size_t bI = align256(nb * F * sizeof(int2));
+    if ((s = ws_reserve(ctx, bA + bE + bS + bB + bI)) != SSL_OK) return s;
+    if (nblocks > 1 && (s = counters_reserve(ctx, kJacobiQueues)) != SSL_OK) return s;
+    char *w = static_cast<char *>(ctx->ws);
+    ssl_c64 *A = reinterpret_cast<ssl_c64 *>(w);
+    ssl_c64 *En = reinterpret_cast<ssl_c64 *>(w + bA);
+    int32_t *dstat = reinterpret_cast<int32_t *>(w + bA + bE);
+    BlockDev *dblk = reinterpret_cast<BlockDev *>(w + bA + bE + bS);
+    int2 *ditems = reinterpret_cast<int2 *>(w + bA + bE + bS + bB);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int cls = jacobi_class(M);
+    hipError_t e = hipSuccess;
+    if (nblocks > 1) {
+        std::vector<BlockDev> hb(nb);
+        std::vector<int2> hi(nb * F);
+        for (size_t b = 0; b < nb; ++b) {
+            BlockDev &B = hb[b];
+            memset(&B, 0, sizeof(B));
+            B.F = F;
+            B.M = M;
+            B.Ns = Ns;
+            B.kstatus = K->status;
+            B.A = reinterpret_cast<float2 *>(A + b * perA);
+            B.En = reinterpret_cast<float2 *>(En + b * perE);
+            B.status = dstat + b * F;
+            for (int f = 0; f < F; ++f) hi[b * F + f] = make_int2((int)b, f);
+        }
+        e = hipMemcpyAsync(dblk, hb.data(), nb * sizeof(BlockDev), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ditems, hi.data(), nb * F * sizeof(int2), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);    // host staging goes out of scope
+        if (e != hipSuccess) return hip_fail(e, "autotune staging");
+    }
+    auto launch = [&](int lanes) {
+        if (nblocks == 1)
+            return launch_jacobi(A, K->status, F, M, Ns, SSL_DEFAULT_SWEEPS, lanes, En, nullptr,
+                                 nullptr, nullptr, st);
+        const int n_items = nblocks * F;
+        const int grid = std::min(n_items, ctx->cu_count * jacobi_persistent_wg_per_cu(cls, lanes));
+        return launch_jacobi_batch(dblk, ditems, n_items, cls, lanes, SSL_DEFAULT_SWEEPS,
+                                   ctx->counters + jacobi_queue(cls), grid, st);
+    };
     const int cand[3] = {4, 8, 16};
     hipEvent_t a = nullptr, b = nullptr;
-    hipError_t e = hipEventCreate(&a);
+    e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);
     int best = -1;
     double best_ms = 0.0;
@@ -798,11 +854,11 @@ ssl_status ssl_autotune_jacobi(ssl_ctx ctx, const ssl_c64 *R, ssl_noise K, int F
         if (!jacobi_variant_ok(cls, cand[i])) continue;
         double total = 0.0;
         for (int r = 0; r <= reps && e == hipSuccess; ++r) {
-            e = launch_whiten(K->Kinv, R, A, F, M, st);          // A is consumed by each launch
+            // A is consumed by each launch: whiten it again, outside the timed window
+            for (size_t bb = 0; bb < nb && e == hipSuccess; ++bb)
+                e = launch_whiten(K->Kinv, R, A + bb * perA, F, M, st);
             if (e == hipSuccess) e = hipEventRecord(a, st);
-            if (e == hipSuccess)
-                e = launch_jacobi(A, K->status, F, M, Ns, SSL_DEFAULT_SWEEPS, cand[i], En,
-                                  nullptr, nullptr, nullptr, st);
+            if (e == hipSuccess) e = launch(cand[i]);
             if (e == hipSuccess) e = hipEventRecord(b, st);
             if (e == hipSuccess) e = hipEventSynchronize(b);
             float ms = 0.f;
@@ -821,6 +877,147 @@ ssl_status ssl_autotune_jacobi(ssl_ctx ctx, const ssl_c64 *R, ssl_noise K, int F
     if (e != hipSuccess) return hip_fail(e, "autotune");
     ctx->jac_lanes[jacobi_class_index(cls)] = best;
     *best_lanes = best;
+    return SSL_OK;
+}
+
+ssl_status ssl_ctx_set_steer_waves(ssl_ctx ctx, int M, int Ns, ssl_prec hprec, int waves)
+{
+    if (!ctx || M < 1 || M > SSL_MAX_M || Ns < 1 || Ns >= M ||
+        (hprec != SSL_FP32 && hprec != SSL_BF16 && hprec != SSL_FP16) || !steer_waves_ok(waves)) {
+        ssl_set_error("no projection variant with %d waves for M = %d, Ns = %d, prec = %d", waves,
+                      M, Ns, (int)hprec);
+        return SSL_ERR_ARG;
+    }
+    ctx->steer_waves[steer_class_index(steer_class(M, Ns))][hprec] = waves;
+    return SSL_OK;
+}
+
+int ssl_ctx_get_steer_waves(ssl_ctx ctx, int M, int Ns, ssl_prec hprec)
+{
+    if (!ctx || M < 1 || M > SSL_MAX_M || Ns < 1 || Ns >= M ||
+        (hprec != SSL_FP32 && hprec != SSL_BF16 && hprec != SSL_FP16))
+        return -1;
+    return st_waves(ctx, M, Ns, hprec);
+}
+
+ssl_status ssl_autotune_steer(ssl_ctx ctx, const void *H, ssl_prec hprec, const ssl_c64 *En,
+                              int F, int D, int M, int Ns, int p, int nblocks, int reps,
+                              int *best_waves, double *ms_per_variant, void *stream)
+{
+    if (!ctx || !H || !En || !best_waves) {
+        ssl_set_error("ctx, H, En or best_waves is NULL");
+        return SSL_ERR_ARG;
+    }
+    ssl_status s = check_common(F, M, Ns);
+    if (s != SSL_OK) return s;
+    if (D < 1 || D > (1 << 24)) {
+        ssl_set_error("D = %d out of range", D);
+        return SSL_ERR_ARG;
+    }
+    if (p != 1 && p != 2) {
+        ssl_set_error("p = %d must be 1 or 2", p);
+        return SSL_ERR_ARG;
+    }
+    if (hprec != SSL_FP32 && hprec != SSL_BF16 && hprec != SSL_FP16) {
+        ssl_set_error("H precision must be SSL_FP32, SSL_BF16 or SSL_FP16");
+        return SSL_ERR_ARG;
+    }
+    if (reps < 1 || reps > 1000) {
+        ssl_set_error("reps = %d out of range [1, 1000]", reps);
+        return SSL_ERR_ARG;
+    }
+    if (nblocks < 1 || nblocks > 65535) {
+        ssl_set_error("nblocks = %d out of range [1, 65535]", nblocks);
+        return SSL_ERR_ARG;
+    }
+    DeviceGuard dg(ctx->device);
+    // workspace: P per block, then (batched form) the descriptors, the (group, bin) items, one
+    // group, its block list and an all-OK bin status
+    const size_t bP = align256((size_t)nblocks * F * D * sizeof(float));
+    const size_t bB = align256((size_t)nblocks * sizeof(BlockDev));
+    const size_t bI = align256((size_t)F * sizeof(int2));
+    const size_t bG = align256(sizeof(int2));
+    const size_t bL = align256((size_t)nblocks * sizeof(int));
+    const size_t bS = align256((size_t)F * sizeof(int32_t));
+    if ((s = ws_reserve(ctx, bP + bB + bI + bG + bL + bS)) != SSL_OK) return s;
+    char *w = static_cast<char *>(ctx->ws);
+    float *P = reinterpret_cast<float *>(w);
+    BlockDev *dblk = reinterpret_cast<BlockDev *>(w + bP);
+    int2 *ditems = reinterpret_cast<int2 *>(w + bP + bB);
+    int2 *dgroup = reinterpret_cast<int2 *>(w + bP + bB + bI);
+    int *dlist = reinterpret_cast<int *>(w + bP + bB + bI + bG);
+    int32_t *dstat = reinterpret_cast<int32_t *>(w + bP + bB + bI + bG + bL);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    const int cls = steer_class(M, Ns);
+    if (nblocks > 1) {
+        std::vector<BlockDev> hb(nblocks);
+        std::vector<int2> hi(F);
+        std::vector<int> hl(nblocks);
+        for (int b = 0; b < nblocks; ++b) {
+            BlockDev &B = hb[b];
+            memset(&B, 0, sizeof(B));
+            B.F = F;
+            B.M = M;
+            B.Ns = Ns;
+            B.D = D;
+            B.p = p;
+            B.hprec = hprec;
+            B.H = H;
+            B.En = const_cast<float2 *>(reinterpret_cast<const float2 *>(En));
+            B.P = P + (size_t)b * F * D;
+            B.status = dstat;
+            hl[b] = b;
+        }
+        for (int f = 0; f < F; ++f) hi[f] = make_int2(0, f);
+        const int2 grp = make_int2(0, nblocks);
+        e = hipMemcpyAsync(dblk, hb.data(), nblocks * sizeof(BlockDev), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ditems, hi.data(), F * sizeof(int2), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dgroup, &grp, sizeof(int2), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dlist, hl.data(), nblocks * sizeof(int), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemsetAsync(dstat, 0, F * sizeof(int32_t), st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);    // host staging goes out of scope
+        if (e != hipSuccess) return hip_fail(e, "autotune staging");
+    }
+    auto launch = [&](int waves) {
+        if (nblocks == 1)
+            return launch_steer(H, hprec, En, F, D, M, Ns, p, nullptr, P, waves, st);
+        const int rows = steer_rows_per_block(waves);
+        return launch_steer_batch(dblk, ditems, F, dgroup, dlist, cls, waves,
+                                  (D + rows - 1) / rows, hprec, st);
+    };
+    const int cand[3] = {4, 8, 16};
+    hipEvent_t a = nullptr, b = nullptr;
+    e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    int best = -1;
+    double best_ms = 0.0;
+    for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+        double total = 0.0;
+        for (int r = 0; r <= reps && e == hipSuccess; ++r) {
+            e = hipEventRecord(a, st);
+            if (e == hipSuccess) e = launch(cand[i]);
+            if (e == hipSuccess) e = hipEventRecord(b, st);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+            if (r > 0) total += ms;                               // launch 0 is the warm-up
+        }
+        const double mean = total / reps;
+        if (ms_per_variant) ms_per_variant[i] = mean;
+        if (best < 0 || mean < best_ms) {
+            best = cand[i];
+            best_ms = mean;
+        }
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (e != hipSuccess) return hip_fail(e, "autotune");
+    ctx->steer_waves[steer_class_index(cls)][hprec] = best;
+    *best_waves = best;
     return SSL_OK;
 }
 
@@ -857,11 +1054,12 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
     size_t ws_total = 0;
     int64_t n_items = 0;
     std::vector<int64_t> key;
-    key.reserve(7 + 6 * (size_t)nblocks);
+    key.reserve(10 + 6 * (size_t)nblocks);
     key.push_back(nblocks);
     key.push_back(prec);
     key.push_back(p);
     for (int i = 0; i < 4; ++i) key.push_back(ctx->jac_lanes[i]);   // kernel variants captured
+    for (int c = 0; c < 3; ++c) key.push_back(ctx->steer_waves[c][prec]);
     for (int b = 0; b < nblocks; ++b) {
         const ssl_block_desc &d = descs[b];
         if ((s = check_common(d.F, d.M, d.Ns)) != SSL_OK ||
@@ -1013,8 +1211,9 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
     for (Seg &sg : plan.jac)
         sg.extra = std::min(sg.count, ctx->cu_count * jacobi_persistent_wg_per_cu(
                                                          sg.cls, ctx->jac_lanes[jacobi_class_index(sg.cls)]));
-    const int rows = steer_rows_per_block();
     for (Seg &sg : plan.steer) {
+        sg.waves = ctx->steer_waves[steer_class_index(sg.cls)][prec];
+        const int rows = steer_rows_per_block(sg.waves);
         int dt = 0;
         for (int b = 0; b < nblocks; ++b)
             if (c_st[b] == sg.cls) dt = std::max(dt, (hb[b].D + rows - 1) / rows);

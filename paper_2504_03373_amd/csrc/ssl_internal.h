@@ -54,6 +54,8 @@ struct ssl_ctx_s {
     int cu_count = 0;
     // Jacobi variant (lanes per column pair) per size class 8/16/32/64 channels
     int jac_lanes[4] = {8, 8, 8, 8};     // lanes per Jacobi column pair, classes 8/16/32/64
+    // waves per projection workgroup, [steer class 1/2/4][SSL_FP32, SSL_BF16, SSL_FP16]
+    int steer_waves[3][3] = {{8, 8, 8}, {8, 8, 8}, {8, 8, 8}};
 };
 
 struct ssl_noise_s {
@@ -105,13 +107,15 @@ hipError_t launch_jacobi_batch(const BlockDev *blk, const int2 *items, int n_ite
                                int lanes, int max_sweeps, unsigned int *queue, int grid,
                                hipStream_t st);
 hipError_t launch_steer_batch(const BlockDev *blk, const int2 *items, int n_items,
-                              const int2 *groups, const int *gblocks, int cls, int max_dtiles,
-                              ssl_prec hprec, hipStream_t st);
+                              const int2 *groups, const int *gblocks, int cls, int waves,
+                              int max_dtiles, ssl_prec hprec, hipStream_t st);
 hipError_t launch_binsum_batch(const BlockDev *blk, int nblocks, int max_dchunks,
                                int max_fchunks, hipStream_t st);
 int jacobi_threads(int cls, int lanes);
 inline int jacobi_class_index(int cls) { return cls == 8 ? 0 : cls == 16 ? 1 : cls == 32 ? 2 : 3; }
-int steer_rows_per_block();
+inline int steer_class_index(int cls) { return cls == 1 ? 0 : cls == 2 ? 1 : 2; }
+bool steer_waves_ok(int waves);          // 4, 8 or 16 waves (16 directions each) per workgroup
+int steer_rows_per_block(int waves);
 int binsum_threads();
 
 // --- launchers (each returns hipSuccess or the launch error) ---
@@ -133,7 +137,8 @@ hipError_t launch_jacobi(ssl_c64 *A, const int32_t *kstatus, int F, int M, int N
 bool jacobi_variant_ok(int cls, int lanes);
 int jacobi_persistent_wg_per_cu(int cls, int lanes);
 hipError_t launch_steer(const void *H, ssl_prec hprec, const ssl_c64 *En, int F, int D, int M,
-                        int Ns, int p, const int32_t *bin_status, float *P, hipStream_t st);
+                        int Ns, int p, const int32_t *bin_status, float *P, int waves,
+                        hipStream_t st);
 hipError_t launch_binsum_peaks(const float *P, int F, int D, float *Pbar, float *part,
                                int n_az, int n_el, int Ns, int32_t *peaks, float *peak_val,
                                hipStream_t st);

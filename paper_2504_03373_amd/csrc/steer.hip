@@ -11,21 +11,21 @@
 // |G_dc|^2 = (h . e_c)^2 + (h' . e_c)^2 needs no cross-lane exchange.  h' is formed in registers
 // from h (a swap and a sign flip), so the steering table is read once.
 //
-// Workgroup = 8 waves x 16 directions of one bin; a wave keeps its 16-row strip of H (and h') in
-// registers and owns all Nn columns in accumulators.  Workgroups are mapped XCD by XCD so that
+// Workgroup = WV waves x 16 directions of one bin (WV = 4, 8 or 16, chosen per size class and
+// precision, 8 unless tuned); a wave keeps its 16-row strip of H (and h') in registers and owns
+// all Nn columns in accumulators.  Workgroups are mapped XCD by XCD so that
 // all direction tiles of a bin share one L2.  The batched kernel loops over every block
 // that shares the steering table: H is read once per (bin, direction tile) for all of them and
 // only E_n (staged in LDS) changes from block to block.
 #include "ssl_internal.h"
+
+#include <type_traits>
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
 namespace {
-
-constexpr int kThreads = 512;            // 8 waves x 16 directions
-constexpr int kRowsPerBlock = 128;
 
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v)
@@ -133,42 +133,42 @@ __device__ __forceinline__ float load_strip(const E *__restrict__ Hf, int D, int
 }
 
 // E_n[f] as the B operand: Bs[c * KS + k] = real k of noise vector c (k < 2M), zero for c >= Nn
-// or k >= 2M up to the k-chunk padding KP.  Thread tid owns elements e = tid + u * kThreads of a
-// NCOL x 64 complex grid (column c = e / 64 = tid / 64 + 8u, element m = e % 64 = tid % 64);
+// or k >= 2M up to the k-chunk padding KP.  Thread tid owns elements e = tid + 64 WV u of a
+// 16 NCT x 64 complex grid (column c = e / 64 = tid / 64 + WV u, element m = e % 64 = tid % 64);
 // load_b puts them in registers (all loads in flight at once), store_b writes those with
 // m < KP / 2.
-template <int NCT> struct BStage {
-    static constexpr int NIT = 16 * NCT * 64 / kThreads;
+template <int NCT, int WV> struct BStage {
+    static constexpr int NIT = 16 * NCT / WV;
     float2 v[NIT];
 };
 
-template <int NCT>
+template <int NCT, int WV>
 __device__ __forceinline__ void load_b(const float2 *__restrict__ Enf, int M, int Nn, int tid,
-                                       BStage<NCT> &st)
+                                       BStage<NCT, WV> &st)
 {
     // element u of this thread: column c0 + 8u, row m (fixed): one base address and a stride
     const int c0 = tid >> 6, m = tid & 63;
     const float2 *src = Enf + (size_t)c0 * M + m;
     const bool mok = m < M;
 #pragma unroll
-    for (int u = 0; u < BStage<NCT>::NIT; ++u)
-        st.v[u] = (mok && c0 + 8 * u < Nn) ? src[(size_t)u * 8 * M] : make_float2(0.f, 0.f);
+    for (int u = 0; u < BStage<NCT, WV>::NIT; ++u)
+        st.v[u] = (mok && c0 + WV * u < Nn) ? src[(size_t)u * WV * M] : make_float2(0.f, 0.f);
 }
 
-template <int NCT, typename E>
-__device__ __forceinline__ void store_b(const BStage<NCT> &st, E *Bs, int KS, int KP, int tid)
+template <int NCT, int WV, typename E>
+__device__ __forceinline__ void store_b(const BStage<NCT, WV> &st, E *Bs, int KS, int KP, int tid)
 {
     const int c0 = tid >> 6, m = tid & 63;
     if (2 * m >= KP) return;
     E *dst = Bs + c0 * KS + 2 * m;
 #pragma unroll
-    for (int u = 0; u < BStage<NCT>::NIT; ++u) {
+    for (int u = 0; u < BStage<NCT, WV>::NIT; ++u) {
         const float2 v = st.v[u];
         if constexpr (sizeof(E) == 4) {
-            *(float2 *)(dst + u * 8 * KS) = v;
+            *(float2 *)(dst + u * WV * KS) = v;
         } else {
             E pr[2] = {(E)v.x, (E)v.y};
-            *(uint32_t *)(dst + u * 8 * KS) = __builtin_bit_cast(uint32_t, pr);
+            *(uint32_t *)(dst + u * WV * KS) = __builtin_bit_cast(uint32_t, pr);
         }
     }
 }
@@ -260,16 +260,16 @@ __device__ __forceinline__ void finish_rows(const floatx4 (&acc1)[NCT], const fl
     }
 }
 
-// One workgroup: directions d0 .. d0 + 127 of bin f for nb blocks sharing the table Hf (the bin's
-// [D][2M] rows).  blk(i) gives block i's (E_n of the bin, status ok, Ns, P row of the bin).
-template <int NCT, typename E, class BlockAt>
+// One workgroup: directions d0 .. d0 + 16 WV - 1 of bin f for nb blocks sharing the table Hf (the
+// bin's [D][2M] rows).  blk(i) gives block i's (E_n of the bin, status ok, Ns, P row of the bin).
+template <int NCT, int WV, typename E, class BlockAt>
 __device__ __forceinline__ void steer_tile(const E *__restrict__ Hf, int D, int M, int p, int d0,
                                            int nb, BlockAt &&blk)
 {
     typedef SteerCfg<E> C;
     __shared__ __attribute__((aligned(16))) E Bs[16 * NCT * C::KS_MAX];
-    __shared__ float den_s[kRowsPerBlock];
-    __shared__ float nrm_s[kRowsPerBlock];
+    __shared__ float den_s[16 * WV];
+    __shared__ float nrm_s[16 * WV];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -294,9 +294,9 @@ __device__ __forceinline__ void steer_tile(const E *__restrict__ Hf, int D, int 
     float *Pf;
     blk(0, Enf, ok, Ns, Pf);
     {
-        BStage<NCT> st;
-        load_b<NCT>(Enf, M, M - Ns, tid, st);
-        store_b<NCT, E>(st, Bs, KS, KP, tid);
+        BStage<NCT, WV> st;
+        load_b<NCT, WV>(Enf, M, M - Ns, tid, st);
+        store_b<NCT, WV, E>(st, Bs, KS, KP, tid);
     }
     __syncthreads();
     for (int i = 0; i < nb; ++i) {
@@ -307,15 +307,15 @@ __device__ __forceinline__ void steer_tile(const E *__restrict__ Hf, int D, int 
         const bool cur_ok = ok;
         float *const cur_P = Pf;
         const bool more = i + 1 < nb;
-        BStage<NCT> st;
+        BStage<NCT, WV> st;
         if (more) {
             blk(i + 1, Enf, ok, Ns, Pf);
-            load_b<NCT>(Enf, M, M - Ns, tid_i, st);
+            load_b<NCT, WV>(Enf, M, M - Ns, tid_i, st);
         }
         floatx4 acc1[NCT], acc2[NCT];
         mma<NCT, E>(S, Bs, KS, KQ, lane_i, acc1, acc2);
         __syncthreads();                   // every wave has read Bs
-        if (more) store_b<NCT, E>(st, Bs, KS, KP, tid_i);
+        if (more) store_b<NCT, WV, E>(st, Bs, KS, KP, tid_i);
         finish_rows<NCT>(acc1, acc2, p, lane, wave, d0, D, cur_ok, cur_P, den_s, nrm_s);
         __syncthreads();                   // next B staged, den_s free
     }
@@ -338,8 +338,8 @@ __device__ __forceinline__ bool xcd_item(int n_items, int n_tiles, int &item, in
     return item < n_items;
 }
 
-template <int NCT, typename E>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void steer_single(const E *__restrict__ H,
+template <int NCT, typename E, int WV>
+__global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(4))) void steer_single(const E *__restrict__ H,
                                                          const float2 *__restrict__ En,
                                                          const int32_t *__restrict__ bin_status,
                                                          int F, int D, int M, int Ns, int p,
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
 {
     int f, tile;
     if (!xcd_item(F, n_tiles, f, tile)) return;
-    steer_tile<NCT, E>(H + (size_t)f * D * 2 * M, D, M, p, tile * kRowsPerBlock, 1,
+    steer_tile<NCT, WV, E>(H + (size_t)f * D * 2 * M, D, M, p, tile * 16 * WV, 1,
                        [&](int, const float2 *&Enf, bool &ok, int &ns, float *&Pf) {
                            Enf = En + (size_t)f * (M - Ns) * M;
                            ok = bin_status == nullptr || bin_status[f] == SSL_BIN_OK;
@@ -358,8 +358,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
 
 // Batched: item = (group, bin), groups[g] = (first, count) into gblocks, the blocks of one
 // steering table.
-template <int NCT, typename E>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void steer_batch(const BlockDev *__restrict__ blk,
+template <int NCT, typename E, int WV>
+__global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(4))) void steer_batch(const BlockDev *__restrict__ blk,
                                                         const int2 *__restrict__ items,
                                                         int n_items, int n_tiles,
                                                         const int2 *__restrict__ groups,
@@ -370,10 +370,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     const int2 it = items[ii];
     const int2 gr = groups[it.x];
     const BlockDev &B0 = blk[gblocks[gr.x]];
-    const int d0 = tile * kRowsPerBlock;
+    const int d0 = tile * 16 * WV;
     if (d0 >= B0.D) return;
     const int f = it.y, M = B0.M, D = B0.D;
-    steer_tile<NCT, E>(static_cast<const E *>(B0.H) + (size_t)f * D * 2 * M, D, M, B0.p, d0, gr.y,
+    steer_tile<NCT, WV, E>(static_cast<const E *>(B0.H) + (size_t)f * D * 2 * M, D, M, B0.p, d0, gr.y,
                        [&](int i, const float2 *&Enf, bool &ok, int &ns, float *&Pf) {
                            const BlockDev &B = blk[gblocks[gr.x + i]];
                            Enf = B.En + (size_t)f * (M - B.Ns) * M;
@@ -383,67 +383,56 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
                        });
 }
 
-template <int NCT>
-hipError_t launch_nct(const void *H, ssl_prec hprec, const ssl_c64 *En, int F, int D, int M,
-                      int Ns, int p, const int32_t *bin_status, float *P, hipStream_t st)
+// Calls fn(NCT, WV, (E *)nullptr) with the compile-time variant for (class, waves, precision).
+template <class Fn>
+hipError_t dispatch(int cls, int waves, ssl_prec prec, Fn &&fn)
 {
-    const int nt = (D + kRowsPerBlock - 1) / kRowsPerBlock;
-    const dim3 grid(xcd_grid(F, nt));
-    const float2 *Ep = reinterpret_cast<const float2 *>(En);
-    if (hprec == SSL_FP32)
-        hipLaunchKernelGGL((steer_single<NCT, float>), grid, dim3(kThreads), 0, st,
-                           static_cast<const float *>(H), Ep, bin_status, F, D, M, Ns, p, P, nt);
-    else if (hprec == SSL_BF16)
-        hipLaunchKernelGGL((steer_single<NCT, __bf16>), grid, dim3(kThreads), 0, st,
-                           static_cast<const __bf16 *>(H), Ep, bin_status, F, D, M, Ns, p, P, nt);
-    else
-        hipLaunchKernelGGL((steer_single<NCT, _Float16>), grid, dim3(kThreads), 0, st,
-                           static_cast<const _Float16 *>(H), Ep, bin_status, F, D, M, Ns, p, P,
-                           nt);
-    return hipGetLastError();
-}
-
-template <int NCT>
-hipError_t launch_nct_batch(const BlockDev *blk, const int2 *items, int n_items,
-                            const int2 *groups, const int *gblocks, int max_dtiles,
-                            ssl_prec hprec, hipStream_t st)
-{
-    const dim3 grid(xcd_grid(n_items, max_dtiles));
-    if (hprec == SSL_FP32)
-        hipLaunchKernelGGL((steer_batch<NCT, float>), grid, dim3(kThreads), 0, st, blk, items,
-                           n_items, max_dtiles, groups, gblocks);
-    else if (hprec == SSL_BF16)
-        hipLaunchKernelGGL((steer_batch<NCT, __bf16>), grid, dim3(kThreads), 0, st, blk, items,
-                           n_items, max_dtiles, groups, gblocks);
-    else
-        hipLaunchKernelGGL((steer_batch<NCT, _Float16>), grid, dim3(kThreads), 0, st, blk,
-                           items, n_items, max_dtiles, groups, gblocks);
-    return hipGetLastError();
+    auto by_type = [&](auto nct, auto wv) -> hipError_t {
+        if (prec == SSL_FP32) return fn(nct, wv, (float *)nullptr);
+        if (prec == SSL_BF16) return fn(nct, wv, (__bf16 *)nullptr);
+        return fn(nct, wv, (_Float16 *)nullptr);
+    };
+    auto by_waves = [&](auto nct) -> hipError_t {
+        if (waves == 4) return by_type(nct, std::integral_constant<int, 4>{});
+        if (waves == 16) return by_type(nct, std::integral_constant<int, 16>{});
+        return by_type(nct, std::integral_constant<int, 8>{});
+    };
+    if (cls == 1) return by_waves(std::integral_constant<int, 1>{});
+    if (cls == 2) return by_waves(std::integral_constant<int, 2>{});
+    return by_waves(std::integral_constant<int, 4>{});
 }
 
 }  // namespace
 
-int steer_rows_per_block() { return kRowsPerBlock; }
+bool steer_waves_ok(int waves) { return waves == 4 || waves == 8 || waves == 16; }
+int steer_rows_per_block(int waves) { return 16 * waves; }
 
 hipError_t launch_steer(const void *H, ssl_prec hprec, const ssl_c64 *En, int F, int D, int M,
-                        int Ns, int p, const int32_t *bin_status, float *P, hipStream_t st)
+                        int Ns, int p, const int32_t *bin_status, float *P, int waves,
+                        hipStream_t st)
 {
-    switch (steer_class(M, Ns)) {
-    case 1: return launch_nct<1>(H, hprec, En, F, D, M, Ns, p, bin_status, P, st);
-    case 2: return launch_nct<2>(H, hprec, En, F, D, M, Ns, p, bin_status, P, st);
-    default: return launch_nct<4>(H, hprec, En, F, D, M, Ns, p, bin_status, P, st);
-    }
+    const float2 *Ep = reinterpret_cast<const float2 *>(En);
+    return dispatch(steer_class(M, Ns), waves, hprec, [&](auto nct, auto wv, auto *tag) {
+        typedef std::remove_pointer_t<decltype(tag)> E;
+        constexpr int NCT = decltype(nct)::value, WV = decltype(wv)::value;
+        const int nt = (D + 16 * WV - 1) / (16 * WV);
+        hipLaunchKernelGGL((steer_single<NCT, E, WV>), dim3(xcd_grid(F, nt)), dim3(64 * WV), 0,
+                           st, static_cast<const E *>(H), Ep, bin_status, F, D, M, Ns, p, P, nt);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_steer_batch(const BlockDev *blk, const int2 *items, int n_items,
-                              const int2 *groups, const int *gblocks, int cls, int max_dtiles,
-                              ssl_prec hprec, hipStream_t st)
+                              const int2 *groups, const int *gblocks, int cls, int waves,
+                              int max_dtiles, ssl_prec hprec, hipStream_t st)
 {
     if (n_items <= 0) return hipSuccess;
-    switch (cls) {
-    case 1: return launch_nct_batch<1>(blk, items, n_items, groups, gblocks, max_dtiles, hprec, st);
-    case 2: return launch_nct_batch<2>(blk, items, n_items, groups, gblocks, max_dtiles, hprec, st);
-    default:
-        return launch_nct_batch<4>(blk, items, n_items, groups, gblocks, max_dtiles, hprec, st);
-    }
+    return dispatch(cls, waves, hprec, [&](auto nct, auto wv, auto *tag) {
+        typedef std::remove_pointer_t<decltype(tag)> E;
+        constexpr int NCT = decltype(nct)::value, WV = decltype(wv)::value;
+        hipLaunchKernelGGL((steer_batch<NCT, E, WV>), dim3(xcd_grid(n_items, max_dtiles)),
+                           dim3(64 * WV), 0, st, blk, items, n_items, max_dtiles, groups,
+                           gblocks);
+        return hipGetLastError();
+    });
 }

@@ -140,12 +140,13 @@ class GpuExecutor:
 
     streams: objects with M, F, T, Ns, D, grid (n_az, n_el), `pos`, `freqs`, initial_noise_frames()
     and block(seq) -> (X, noise-only frames); `pool` blocks per stream are generated up front and
-    reused cyclically (block seq uses pool entry seq % pool).
+    reused cyclically (block seq uses pool entry seq % pool).  `configure`, if given, is called
+    with each batch context after creation (to apply tuned kernel variants).
     """
 
     def __init__(self, streams, steering, prec=None, p: int = 2, alpha: float = 0.95,
                  k_update_every: int = 1, hbm_budget_bytes: int = 4 << 30, lanes: int = 2,
-                 pool: int = 4, device: int = 0, noise_streams: int = 4):
+                 pool: int = 4, device: int = 0, noise_streams: int = 4, configure=None):
         import torch
 
         from . import (SSL_FP32, SSL_FP64, block_desc, ssl_corr_accum, ssl_ctx_create,
@@ -166,6 +167,8 @@ class GpuExecutor:
         for c in self.ctxs:
             # every batch has a different composition: capture would never be replayed
             ssl_ctx_use_graphs(c, False)
+            if configure is not None:          # e.g. apply autotuned kernel variants
+                configure(c)
         self.nctx = ssl_ctx_create(device, 0)
         self.tstreams = [torch.cuda.Stream(device=self.dev) for _ in range(lanes)]
         # K updates go round-robin over a few streams (one update is a few hundred workgroups:

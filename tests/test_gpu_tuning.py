@@ -75,12 +75,16 @@ def test_autotune_picks_and_applies(S):
     F, M, Ns = 514, 60, 2
     R, K = gsvd_case(M, F, Ns, seed=801)
     n, _ = set_noise(S, ctx, K)
-    say("ssl_autotune_jacobi M=60 F=514")
-    best, ms = S.ssl_autotune_jacobi(ctx, to_dev(R.astype(np.complex64)), n, Ns, reps=2)
-    say(f"  best lanes {best}, ms {ms}")
-    assert best in VARIANTS[60] and set(ms) == set(VARIANTS[60])
-    assert ms[best] == min(ms.values())
-    assert S.ssl_ctx_get_jacobi_lanes(ctx, M) == best
+    Rd = to_dev(R.astype(np.complex64))
+    for nb in (1, 3):                      # one launch per block; persistent batched kernel
+        say(f"ssl_autotune_jacobi M=60 F=514 nblocks={nb}")
+        best, ms = S.ssl_autotune_jacobi(ctx, Rd, n, Ns, nblocks=nb, reps=2)
+        say(f"  best lanes {best}, ms {ms}")
+        assert best in VARIANTS[60] and set(ms) == set(VARIANTS[60])
+        assert ms[best] == min(ms.values())
+        assert S.ssl_ctx_get_jacobi_lanes(ctx, M) == best
+    with pytest.raises(S.SSLError):
+        S.ssl_autotune_jacobi(ctx, Rd, n, Ns, nblocks=0)
     S.ssl_noise_destroy(n)
     S.ssl_ctx_destroy(ctx)
 
