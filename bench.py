@@ -316,7 +316,8 @@ def main() -> int:
         rl = {
             "corr": {"bound": "hbm", "unit": "GB/s", "bytes_per_launch": w_corr,
                      "achieved": w_corr / ms("corr") / 1e9, "peak": PEAK_HBM_GBS},
-            "whiten": {"bound": "fp64", "unit": "TFLOP/s", "flops_per_launch": w_white,
+            "whiten": {"bound": "mfma", "mfma_dtype": "f64", "unit": "TFLOP/s",
+                       "flops_per_launch": w_white,
                        "achieved": w_white / ms("whiten") / 1e12, "peak": PEAK_FP64_TFLOPS},
             "jacobi": {"bound": "alu", "unit": "TFLOP/s", "flops_per_launch": jflops,
                        "achieved": jflops / ms("jacobi") / 1e12, "peak": PEAK_FP32_VECTOR_TFLOPS},

@@ -637,11 +637,38 @@ struct Plan {
 };
 
 // Device tail of the descriptor buffer after the four item lists: steering groups (first, count)
-// into a block-index list; a group = the blocks of one size class that share a steering table.
+// into a block-index list, a group = the blocks of one size class that share a steering table;
+// whitening chunks (first, count) into a second block-index list, a chunk = a run of blocks that
+// share a noise set.  Layout: groups int2[nblocks], chunks int2[nblocks], gblocks int[nblocks],
+// cblocks int[nblocks].
 struct GroupArrays {
     const int2 *groups;
     const int *gblocks;
+    const int2 *chunks;
+    const int *cblocks;
 };
+
+// Blocks per whitening workgroup for groups of sizes n[g] with F[g] bins on `slots` resident
+// workgroups: K^{-1} of a bin is loaded once per run, which costs about 0.3 of one block's
+// product, while longer runs mean fewer workgroups to fill the device.  Minimises
+// (rounds of the launch) x (0.3 + run length).
+int whiten_run_length(const std::vector<int> &n, const std::vector<int> &F, int slots)
+{
+    int maxn = 1;
+    for (int v : n) maxn = std::max(maxn, v);
+    int best_c = 1;
+    double best = 0.0;
+    for (int c = 1; c <= maxn; ++c) {
+        int64_t wg = 0;
+        for (size_t g = 0; g < n.size(); ++g) wg += (int64_t)((n[g] + c - 1) / c) * F[g];
+        const double cost = (double)((wg + slots - 1) / slots) * (0.3 + c);
+        if (c == 1 || cost < best) {
+            best = cost;
+            best_c = c;
+        }
+    }
+    return best_c;
+}
 
 ssl_status counters_reserve(ssl_ctx ctx, size_t n)
 {
@@ -726,8 +753,10 @@ hipError_t enqueue_batch(ssl_ctx ctx, const Plan &P, const BlockDev *blk, const 
         if (e != hipSuccess) return e;
     }
     for (const Seg &s : P.whiten) {
-        e = timed(ctx, SSL_K_WHITEN, st,
-                  [&] { return launch_whiten_batch(blk, l_wh + s.start, s.count, s.cls, st); });
+        e = timed(ctx, SSL_K_WHITEN, st, [&] {
+            return launch_whiten_batch(blk, l_wh + s.start, s.count, ga.chunks, ga.cblocks, s.cls,
+                                       st);
+        });
         if (e != hipSuccess) return e;
     }
     for (const Seg &s : P.jac) {
@@ -1099,7 +1128,7 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
     hipStream_t st = static_cast<hipStream_t>(stream);
     const size_t desc_bytes = align256(sizeof(BlockDev) * nblocks);
     const size_t list_bytes = sizeof(int2) * 4 * (size_t)n_items +
-                              (sizeof(int2) + sizeof(int)) * (size_t)nblocks;
+                              2 * (sizeof(int2) + sizeof(int)) * (size_t)nblocks;
     if ((s = ws_reserve(ctx, ws_total)) != SSL_OK) return s;
     if ((s = counters_reserve(ctx, kJacobiQueues)) != SSL_OK) return s;
     if ((s = bdesc_reserve(ctx, desc_bytes + list_bytes)) != SSL_OK) return s;
@@ -1112,7 +1141,9 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
     const BlockDev *db = static_cast<const BlockDev *>(ctx->bdesc_dev);
     const int2 *dl =
         reinterpret_cast<const int2 *>(static_cast<char *>(ctx->bdesc_dev) + desc_bytes);
-    const GroupArrays ga{dl + 4 * n_items, reinterpret_cast<const int *>(dl + 4 * n_items + nblocks)};
+    const int2 *dtail = dl + 4 * n_items;
+    const GroupArrays ga{dtail, reinterpret_cast<const int *>(dtail + 2 * nblocks), dtail + nblocks,
+                         reinterpret_cast<const int *>(dtail + 2 * nblocks) + nblocks};
 
     Plan plan;
     plan.nblocks = nblocks;
@@ -1165,12 +1196,62 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
         plan.max_fc = std::max(plan.max_fc, (int)nch);
     }
     build_list(c_corr, Fs, hl, plan.corr);
-    build_list(c_wh, Fs, hl + n_items, plan.whiten);
+    {
+        // whitening: blocks of one class sharing a noise set, cut into runs of near-equal length
+        // (whiten_run_length); items (chunk, bin), bin-major inside a group so that the runs of
+        // one bin (one K^{-1}) are dispatched together
+        int2 *hc = hl + 4 * n_items + nblocks;
+        int *hcb = reinterpret_cast<int *>(hl + 4 * n_items + 2 * nblocks) + nblocks;
+        std::vector<int> first;
+        std::vector<std::vector<int>> members;
+        for (int b = 0; b < nblocks; ++b) {
+            int g = 0;
+            for (; g < (int)first.size(); ++g)
+                if (c_wh[first[g]] == c_wh[b] && hb[first[g]].Kinv == hb[b].Kinv) break;
+            if (g == (int)first.size()) {
+                first.push_back(b);
+                members.emplace_back();
+            }
+            members[g].push_back(b);
+            key.push_back(g);                         // the sharing pattern shapes the launch
+        }
+        std::vector<int> classes(c_wh);
+        std::sort(classes.begin(), classes.end());
+        classes.erase(std::unique(classes.begin(), classes.end()), classes.end());
+        int2 *out = hl + n_items;
+        int pos = 0, nchunk = 0, at = 0;
+        for (int c : classes) {
+            Seg sg{c, pos, 0, 0};
+            std::vector<int> gs, gn, gf;
+            for (size_t g = 0; g < members.size(); ++g)
+                if (c_wh[first[g]] == c) {
+                    gs.push_back((int)g);
+                    gn.push_back((int)members[g].size());
+                    gf.push_back(hb[first[g]].F);
+                }
+            const int run = whiten_run_length(gn, gf, ctx->cu_count * whiten_wg_per_cu(c));
+            for (int g : gs) {
+                const std::vector<int> &mb = members[g];
+                const int n = (int)mb.size(), k = (n + run - 1) / run;
+                const int c0 = nchunk;
+                for (int r = 0, b0 = 0; r < k; ++r) {
+                    const int len = n / k + (r < n % k ? 1 : 0);
+                    hc[nchunk++] = make_int2(at, len);
+                    for (int i = 0; i < len; ++i) hcb[at++] = mb[b0 + i];
+                    b0 += len;
+                }
+                for (int f = 0; f < hb[first[g]].F; ++f)
+                    for (int r = 0; r < k; ++r) out[pos++] = make_int2(c0 + r, f);
+            }
+            sg.count = pos - sg.start;
+            plan.whiten.push_back(sg);
+        }
+    }
     build_list(c_jac, Fs, hl + 2 * n_items, plan.jac);
     {
         // steering groups (first-appearance order), then (group, bin) items by ascending class
         int2 *hg = hl + 4 * n_items;
-        int *hgb = reinterpret_cast<int *>(hg + nblocks);
+        int *hgb = reinterpret_cast<int *>(hg + 2 * nblocks);
         std::vector<int> first;                       // first block of each group
         std::vector<std::vector<int>> members;
         for (int b = 0; b < nblocks; ++b) {

@@ -9,9 +9,10 @@
 // squared diagonal of the Cholesky factor, so they double as the positive-definiteness test.
 #include "ssl_internal.h"
 
+#include <atomic>
+
 namespace {
 
-constexpr int kThreads = 256;
 constexpr int kFactorThreads = 512;
 constexpr double kPdRel = 9.094947017729282e-13;   // 2^-40: pivot floor relative to max_i K_ii
 
@@ -130,81 +131,151 @@ __global__ void noise_load_c64(double2 *__restrict__ K, const float2 *__restrict
     }
 }
 
-// A = K^{-1} R per bin in FP64.  One workgroup per bin, each thread a 4x4 register tile of A.
-// LDS: K^{-1} transposed (KT[k][i]) so a thread's 4 rows are contiguous, R upcast to FP64.
+// A = K^{-1} R per bin in FP64 on the matrix cores (v_mfma_f64_16x16x4f64: FP64 inputs, FP64
+// accumulation).  The complex product is split into real ones,
+//   Re A = Wr Rr + Wi (-Ri),   Im A = Wr Ri + Wi Rr,      W = K^{-1},
+// over k-steps of 4.  A workgroup takes one bin of a noise set for a run of blocks that share it:
+// NT = MP / 16 waves, wave w owning rows 16 w .. 16 w + 15 and all NT column tiles.  Its A
+// operands (W's rows, FP64) are loaded into registers once and reused for every block of the
+// run; each block's R (complex64) is staged in LDS -- the next block's R is loaded into
+// registers under the current block's products -- and read as B operands, widened to FP64.
+// Padding rows, columns and k-steps (beyond M) are zero on both operands and never stored.
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <int MP> struct WhCfg {
+    static constexpr int NT = MP / 16;          // row tiles = column tiles = waves
+    static constexpr int THREADS = 64 * NT;
+    static constexpr int KQ = MP / 4;           // k-steps at M = MP
+    static constexpr int RS = MP + 16;          // LDS row stride (complex64 elements)
+    static constexpr int NIT = MP * MP / THREADS;
+};
+
+// Thread t stages R elements (k0 + 4u, j), k0 = t / MP, j = t % MP, u < NIT (THREADS = 4 MP).
 template <int MP>
-__device__ __forceinline__ void whiten_bin(const double2 *__restrict__ Wf,
-                                           const float2 *__restrict__ Rf,
-                                           float2 *__restrict__ Af, int M)
+__device__ __forceinline__ void load_r(const float2 *__restrict__ Rf, int M, int tid,
+                                       float2 (&v)[WhCfg<MP>::NIT])
 {
-    static_assert(MP % 4 == 0 && (MP / 4) * (MP / 4) <= kThreads, "tile grid must fit");
-    __shared__ double2 KT[MP * MP];
-    __shared__ double2 Rs[MP * MP];
-    const int tid = threadIdx.x;
-    for (int e = tid; e < MP * MP; e += kThreads) {
-        const int i = e / MP, j = e - i * MP;
-        double2 w = make_double2(0.0, 0.0), r = make_double2(0.0, 0.0);
-        if (i < M && j < M) {
-            w = Wf[(size_t)i * M + j];
-            const float2 rv = Rf[(size_t)i * M + j];
-            r = make_double2((double)rv.x, (double)rv.y);
-        }
-        KT[j * MP + i] = w;
-        Rs[i * MP + j] = r;
+    const int k0 = tid / MP, j = tid % MP;
+    const float2 *src = Rf + (size_t)k0 * M + j;
+#pragma unroll
+    for (int u = 0; u < WhCfg<MP>::NIT; ++u)
+        v[u] = (j < M && k0 + 4 * u < M) ? src[(size_t)u * 4 * M] : make_float2(0.f, 0.f);
+}
+
+template <int MP>
+__device__ __forceinline__ void store_r(const float2 (&v)[WhCfg<MP>::NIT], float2 *Rs, int tid)
+{
+    const int k0 = tid / MP, j = tid % MP;
+#pragma unroll
+    for (int u = 0; u < WhCfg<MP>::NIT; ++u) Rs[(k0 + 4 * u) * WhCfg<MP>::RS + j] = v[u];
+}
+
+// One workgroup: bin `Wf` (K^{-1} of the bin, [M][M] FP64) for nb blocks; blk(i, Rf, Af) gives
+// block i's R and A of the bin.
+template <int MP, class BlockAt>
+__device__ __forceinline__ void whiten_run(const double2 *__restrict__ Wf, int M, int nb,
+                                           BlockAt &&blk)
+{
+    typedef WhCfg<MP> C;
+    __shared__ float2 Rs[MP * C::RS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int KQ = (M + 3) >> 2;
+    const int row = 16 * wave + (lane & 15);     // A-operand row of this lane
+    const int kl = lane >> 4;                    // k within a k-step (A and B operands)
+
+    double2 w[C::KQ];
+#pragma unroll
+    for (int q = 0; q < C::KQ; ++q) {
+        const int k = 4 * q + kl;
+        w[q] = (row < M && k < M) ? Wf[(size_t)row * M + k] : make_double2(0.0, 0.0);
+    }
+
+    const float2 *Rf;
+    float2 *Af;
+    blk(0, Rf, Af);
+    {
+        float2 v[C::NIT];
+        load_r<MP>(Rf, M, tid, v);
+        store_r<MP>(v, Rs, tid);
     }
     __syncthreads();
-    constexpr int NB = MP / 4;
-    if (tid >= NB * NB) return;
-    const int i0 = 4 * (tid / NB), j0 = 4 * (tid % NB);
-    if (i0 >= M || j0 >= M) return;
-    double2 acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = make_double2(0.0, 0.0);
-    for (int k = 0; k < M; ++k) {
-        double2 w[4], r[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) w[a] = KT[k * MP + i0 + a];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) r[b] = Rs[k * MP + j0 + b];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                acc[a][b].x = fma(w[a].x, r[b].x, acc[a][b].x);
-                acc[a][b].x = fma(-w[a].y, r[b].y, acc[a][b].x);
-                acc[a][b].y = fma(w[a].x, r[b].y, acc[a][b].y);
-                acc[a][b].y = fma(w[a].y, r[b].x, acc[a][b].y);
-            }
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int i = i0 + a, j = j0 + b;
-            if (i < M && j < M)
-                Af[(size_t)i * M + j] = make_float2((float)acc[a][b].x, (float)acc[a][b].y);
+    for (int i = 0; i < nb; ++i) {
+        float2 *const cur_A = Af;
+        const bool more = i + 1 < nb;
+        float2 v[C::NIT];
+        if (more) {
+            blk(i + 1, Rf, Af);
+            load_r<MP>(Rf, M, tid, v);
         }
+        doublex4 ar[C::NT], ai[C::NT];
+#pragma unroll
+        for (int ct = 0; ct < C::NT; ++ct) {
+            ar[ct] = doublex4{0.0, 0.0, 0.0, 0.0};
+            ai[ct] = doublex4{0.0, 0.0, 0.0, 0.0};
+        }
+#pragma unroll
+        for (int q = 0; q < C::KQ; ++q) {
+            if (q < KQ) {                        // uniform; w[] stays register-indexed
+                const float2 *rrow = Rs + (4 * q + kl) * C::RS + (lane & 15);
+#pragma unroll
+                for (int ct = 0; ct < C::NT; ++ct) {
+                    const float2 r = rrow[16 * ct];
+                    const double br = (double)r.x, bi = (double)r.y;
+                    ar[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(w[q].x, br, ar[ct], 0, 0, 0);
+                    ar[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(w[q].y, -bi, ar[ct], 0, 0, 0);
+                    ai[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(w[q].x, bi, ai[ct], 0, 0, 0);
+                    ai[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(w[q].y, br, ai[ct], 0, 0, 0);
+                }
+            }
+        }
+        // FP64 result layout: accumulator element e of lane l is row l / 16 + 4 e, column l % 16
+        // of the 16 x 16 tile (rows interleaved, unlike the FP32 16x16x4 layout)
+#pragma unroll
+        for (int ct = 0; ct < C::NT; ++ct) {
+            const int j = 16 * ct + (lane & 15);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = 16 * wave + kl + 4 * e;
+                if (r < M && j < M)
+                    cur_A[(size_t)r * M + j] = make_float2((float)ar[ct][e], (float)ai[ct][e]);
+            }
+        }
+        __syncthreads();                         // every wave has read Rs
+        if (more) store_r<MP>(v, Rs, tid);
+        __syncthreads();
+    }
 }
 
 template <int MP>
-__global__ __launch_bounds__(kThreads) void whiten(const double2 *__restrict__ Kinv,
-                                                   const float2 *__restrict__ R,
-                                                   float2 *__restrict__ A, int M)
+__global__ __launch_bounds__(WhCfg<MP>::THREADS) __attribute__((amdgpu_waves_per_eu(2))) void whiten(const double2 *__restrict__ Kinv,
+                                                              const float2 *__restrict__ R,
+                                                              float2 *__restrict__ A, int M)
 {
     const size_t o = (size_t)blockIdx.x * M * M;
-    whiten_bin<MP>(Kinv + o, R + o, A + o, M);
+    whiten_run<MP>(Kinv + o, M, 1, [&](int, const float2 *&Rf, float2 *&Af) {
+        Rf = R + o;
+        Af = A + o;
+    });
 }
 
+// Batched: item = (chunk, bin); chunks[c] = (first, count) into cblocks, a run of blocks that
+// share one noise set (the same K^{-1}).
 template <int MP>
-__global__ __launch_bounds__(kThreads) void whiten_batch(const BlockDev *__restrict__ blk,
-                                                         const int2 *__restrict__ items)
+__global__ __launch_bounds__(WhCfg<MP>::THREADS) __attribute__((amdgpu_waves_per_eu(2))) void whiten_batch(const BlockDev *__restrict__ blk,
+                                                                    const int2 *__restrict__ items,
+                                                                    const int2 *__restrict__ chunks,
+                                                                    const int *__restrict__ cblocks)
 {
     const int2 it = items[blockIdx.x];
-    const BlockDev &B = blk[it.x];
-    const size_t o = (size_t)it.y * B.M * B.M;
-    whiten_bin<MP>(B.Kinv + o, B.R + o, B.A + o, B.M);
+    const int2 ch = chunks[it.x];
+    const BlockDev &B0 = blk[cblocks[ch.x]];
+    const int M = B0.M;
+    const size_t o = (size_t)it.y * M * M;
+    whiten_run<MP>(B0.Kinv + o, M, ch.y, [&](int i, const float2 *&Rf, float2 *&Af) {
+        const BlockDev &B = blk[cblocks[ch.x + i]];
+        Rf = B.R + o;
+        Af = B.A + o;
+    });
 }
 
 int grid_for(size_t n) { return (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096); }
@@ -260,21 +331,55 @@ hipError_t launch_whiten(const ssl_c128 *Kinv, const ssl_c64 *R, ssl_c64 *A, int
     const float2 *Rp = reinterpret_cast<const float2 *>(R);
     float2 *Ap = reinterpret_cast<float2 *>(A);
     switch (whiten_class(M)) {
-    case 16: hipLaunchKernelGGL(whiten<16>, dim3(F), dim3(kThreads), 0, st, Wp, Rp, Ap, M); break;
-    case 32: hipLaunchKernelGGL(whiten<32>, dim3(F), dim3(kThreads), 0, st, Wp, Rp, Ap, M); break;
-    default: hipLaunchKernelGGL(whiten<64>, dim3(F), dim3(kThreads), 0, st, Wp, Rp, Ap, M); break;
+    case 16:
+        hipLaunchKernelGGL(whiten<16>, dim3(F), dim3(WhCfg<16>::THREADS), 0, st, Wp, Rp, Ap, M);
+        break;
+    case 32:
+        hipLaunchKernelGGL(whiten<32>, dim3(F), dim3(WhCfg<32>::THREADS), 0, st, Wp, Rp, Ap, M);
+        break;
+    default:
+        hipLaunchKernelGGL(whiten<64>, dim3(F), dim3(WhCfg<64>::THREADS), 0, st, Wp, Rp, Ap, M);
+        break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_whiten_batch(const BlockDev *blk, const int2 *items, int n_items, int cls,
-                               hipStream_t st)
+hipError_t launch_whiten_batch(const BlockDev *blk, const int2 *items, int n_items,
+                               const int2 *chunks, const int *cblocks, int cls, hipStream_t st)
 {
     if (n_items <= 0) return hipSuccess;
     switch (cls) {
-    case 16: hipLaunchKernelGGL(whiten_batch<16>, dim3(n_items), dim3(kThreads), 0, st, blk, items); break;
-    case 32: hipLaunchKernelGGL(whiten_batch<32>, dim3(n_items), dim3(kThreads), 0, st, blk, items); break;
-    default: hipLaunchKernelGGL(whiten_batch<64>, dim3(n_items), dim3(kThreads), 0, st, blk, items); break;
+    case 16:
+        hipLaunchKernelGGL(whiten_batch<16>, dim3(n_items), dim3(WhCfg<16>::THREADS), 0, st, blk,
+                           items, chunks, cblocks);
+        break;
+    case 32:
+        hipLaunchKernelGGL(whiten_batch<32>, dim3(n_items), dim3(WhCfg<32>::THREADS), 0, st, blk,
+                           items, chunks, cblocks);
+        break;
+    default:
+        hipLaunchKernelGGL(whiten_batch<64>, dim3(n_items), dim3(WhCfg<64>::THREADS), 0, st, blk,
+                           items, chunks, cblocks);
+        break;
     }
     return hipGetLastError();
+}
+
+int whiten_wg_per_cu(int cls)
+{
+    // resident workgroups per CU of the batched kernel (registers and LDS decide), cached
+    static std::atomic<int> cache[3];
+    const int i = cls == 16 ? 0 : cls == 32 ? 1 : 2;
+    int n = cache[i].load(std::memory_order_relaxed);
+    if (n > 0) return n;
+    hipError_t e;
+    if (cls == 16)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, whiten_batch<16>, WhCfg<16>::THREADS, 0);
+    else if (cls == 32)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, whiten_batch<32>, WhCfg<32>::THREADS, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, whiten_batch<64>, WhCfg<64>::THREADS, 0);
+    if (e != hipSuccess || n < 1) return 1;
+    cache[i].store(n, std::memory_order_relaxed);
+    return n;
 }

@@ -100,8 +100,11 @@ inline int steer_class(int M, int Ns)
 // Batched launchers.  `items` lists (block, bin) pairs whose blocks share the kernel's size class.
 hipError_t launch_corr_batch(const BlockDev *blk, const int2 *items, int n_items, int cls,
                              ssl_prec prec, hipStream_t st);
-hipError_t launch_whiten_batch(const BlockDev *blk, const int2 *items, int n_items, int cls,
-                               hipStream_t st);
+// Whitening items are (chunk, bin): chunks[c] = (first, count) into cblocks, a run of blocks that
+// share one noise set, whose K^{-1} the workgroup loads once.
+hipError_t launch_whiten_batch(const BlockDev *blk, const int2 *items, int n_items,
+                               const int2 *chunks, const int *cblocks, int cls, hipStream_t st);
+int whiten_wg_per_cu(int cls);
 // Persistent: `grid` workgroups draw items from *queue (0 on entry, re-armed to 0 on exit).
 hipError_t launch_jacobi_batch(const BlockDev *blk, const int2 *items, int n_items, int cls,
                                int lanes, int max_sweeps, unsigned int *queue, int grid,
