@@ -210,7 +210,7 @@ ssl_status ssl_ctx_use_graphs(ssl_ctx ctx, int enable);
 
 /* Jacobi SVD kernel variant per channel-count class (M <= 8, <= 16, <= 32, <= 64): the number of
  * lanes that cooperate on one column pair.  Available: 4 or 8 (M <= 8); 4, 8 or 16 (M <= 16);
- * 8 or 16 (M <= 32, M <= 64).  Default 8 in every class.  A context applies its current choice to
+ * 8 or 16 (M <= 32); 4, 8 or 16 (M <= 64).  Default 8 in every class.  A context applies its current choice to
  * every entry point, so batched and single-block results remain bit-identical; variants differ
  * from each other only by rounding.  Returns SSL_ERR_ARG for an unavailable variant. */
 ssl_status ssl_ctx_set_jacobi_lanes(ssl_ctx ctx, int M, int lanes);

@@ -72,7 +72,7 @@ struct JacobiCfg {
     static constexpr int THREADS = ((NG * G + 63) / 64) * 64;
     // register budget of the persistent variant: at MP = 64 the LDS admits 4 bins per CU; aim
     // for 3 (16 lanes, <= 80 VGPRs) or 4 (8 lanes, <= 128) resident workgroups
-    static constexpr int WAVES_PER_EU = (MP == 64) ? (G == 16 ? 6 : 4) : 1;
+    static constexpr int WAVES_PER_EU = (MP == 64) ? (G == 16 ? 6 : G == 8 ? 4 : 2) : 1;
 };
 
 // Applies the reflector H = I - tau v v^H to column c of X, rows k..M-1, by one lane group:
@@ -645,6 +645,7 @@ bool dispatch(int cls, int lanes, Fn &&fn)
         if (lanes == 16) return fn.template operator()<32, 16>(), true;
         return false;
     default:
+        if (lanes == 4) return fn.template operator()<64, 4>(), true;
         if (lanes == 8) return fn.template operator()<64, 8>(), true;
         if (lanes == 16) return fn.template operator()<64, 16>(), true;
         return false;
