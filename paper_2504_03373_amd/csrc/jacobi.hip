@@ -365,11 +365,24 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         const double tol = 2.0 * sqrt((double)M) * 5.9604644775390625e-08;
         const double tol2 = tol * tol;
         int my_rot = 0;
+        // A partly active wave costs as much as a full one.  When the Me/2 pairs of a round fill
+        // whole waves but one pair (Me/2 = 1 mod pairs-per-wave), that pair (group Me/2 - 1) is
+        // left out of every round: over the Me - 1 rounds the left-out pairs are (c - 1, c) for
+        // every c mod Me - 1, a single odd cycle, played after the regular rounds as the
+        // matchings {(0,1), (2,3), ..}, {(1,2), (3,4), ..} and {(Me-2, 0)}.  Every pair is still
+        // rotated once per sweep.
+        constexpr int kPairsPerWave = 64 / G;
+        const int P = Me / 2;
+        const bool defer = P > 1 && P % kPairsPerWave == 1;
+        const int Pr = defer ? P - 1 : P;
+        const int n_rounds = Me - 1 + (defer ? 3 : 0);
         for (int sw = 0; sw < max_sweeps; ++sw) {
             int rotated = 0;
-            for (int rd = 0; rd < Me - 1; ++rd) {
-                if (g < Me / 2) {
-                    int a, b;
+            for (int rd = 0; rd < n_rounds; ++rd) {
+                int a = 0, b = 0;
+                bool play;
+                if (rd < Me - 1) {
+                    play = g < Pr;
                     if (g == 0) {
                         a = Me - 1;
                         b = rd;
@@ -379,6 +392,16 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                         b = rd - g;
                         if (b < 0) b += Me - 1;
                     }
+                } else if (rd < Me + 1) {            // (2g + e, 2g + e + 1), e = 0, 1
+                    play = g < (Me - 2) / 2;
+                    a = 2 * g + (rd - (Me - 1));
+                    b = a + 1;
+                } else {
+                    play = g == 0;
+                    a = Me - 2;
+                    b = 0;
+                }
+                if (play) {
                     const int ci = min(a, b), cj = max(a, b);
                     if (cj < rk) {
                         float2 bi[R], bj[R];
