@@ -64,13 +64,38 @@ __device__ __forceinline__ void lds_to_out(const float2 *Rs, int RS, int M, int 
     }
 }
 
+// Frames t0 .. t0 + nf - 1 of a bin into registers, every load in flight at once; element
+// e = tid + u * kThreads of the kChunk x MP grid is frame e / MP, channel e % MP (zero beyond nf
+// frames or M channels).
+template <int MP> constexpr int kChunkRegs = kChunk * MP / kThreads;
+template <int MP>
+__device__ __forceinline__ void load_chunk(const float2 *__restrict__ Xf, int t0, int nf, int M,
+                                           int64_t sT, int tid, float2 (&v)[kChunkRegs<MP>])
+{
+    // opaque copy of the thread index: the addresses are recomputed at each call rather than
+    // hoisted out of the bin loop and held in registers
+    int t = tid;
+    asm volatile("" : "+v"(t));
+#pragma unroll
+    for (int u = 0; u < kChunkRegs<MP>; ++u) {
+        const int e = t + u * kThreads;
+        const int tt = e / MP, m = e - tt * MP;
+        v[u] = (tt < nf && m < M) ? Xf[(size_t)(t0 + tt) * sT + m] : make_float2(0.f, 0.f);
+    }
+}
+
 // ---------------------------------------------------------------------------------------------
+// Both bin kernels take the bin's first chunk already in registers (v) and call next(v) once
+// the last chunk is staged in LDS: the next bin's first chunk is then loaded while this bin's
+// products and result stores run.
+//
 // FP32 inputs, v_mfma_f32_16x16x4f32: per 4-frame step, A[i][k] = plane[t0+k][16I+i] from lane
 // i + 16k, B[k][j] = plane[t0+k][16J+j] from lane j + 16k.
-template <int MP>
+template <int MP, class Next>
 __device__ __forceinline__ void corr_f32_bin(const float2 *__restrict__ Xf, int T, int M,
                                              int64_t sT, float scale, int accumulate,
-                                             float2 *__restrict__ Rf)
+                                             float2 *__restrict__ Rf,
+                                             float2 (&v)[kChunkRegs<MP>], Next &&next)
 {
     constexpr int S = MP + 16;                 // row stride: 4 frame rows of a step hit other banks
     constexpr int NT = MP / 16;
@@ -94,16 +119,9 @@ __device__ __forceinline__ void corr_f32_bin(const float2 *__restrict__ Xf, int 
 
     for (int t0 = 0; t0 < T; t0 += kChunk) {
         const int nf = min(kChunk, T - t0);
+        if (t0 > 0) load_chunk<MP>(Xf, t0, nf, M, sT, tid, v);
         __syncthreads();
-        // every load of the chunk in flight before the first LDS store
-        constexpr int NIT = kChunk * MP / kThreads;
-        float2 v[NIT];
-#pragma unroll
-        for (int u = 0; u < NIT; ++u) {
-            const int e = tid + u * kThreads;
-            const int tt = e / MP, m = e - tt * MP;
-            v[u] = (tt < nf && m < M) ? Xf[(size_t)(t0 + tt) * sT + m] : make_float2(0.f, 0.f);
-        }
+        constexpr int NIT = kChunkRegs<MP>;
 #pragma unroll
         for (int u = 0; u < NIT; ++u) {
             const int e = tid + u * kThreads;
@@ -112,6 +130,7 @@ __device__ __forceinline__ void corr_f32_bin(const float2 *__restrict__ Xf, int 
             Zi[tt * S + m] = v[u].y;
         }
         __syncthreads();
+        if (t0 + kChunk >= T) next(v);
         const int nsteps = (nf + 3) >> 2;
 #pragma unroll
         for (int q = 0; q < TPW; ++q) {
@@ -167,10 +186,11 @@ template <> struct Mfma32<_Float16> {
     }
 };
 
-template <int MP, typename E>
+template <int MP, typename E, class Next>
 __device__ __forceinline__ void corr_lp_bin(const float2 *__restrict__ Xf, int T, int M,
                                             int64_t sT, float scale, int accumulate,
-                                            float2 *__restrict__ Rf)
+                                            float2 *__restrict__ Rf,
+                                            float2 (&v)[kChunkRegs<MP>], Next &&next)
 {
     typedef typename Mfma32<E>::vec vec;
     constexpr int S = kChunk + 8;              // elements per transposed row (16 B pad)
@@ -196,16 +216,9 @@ __device__ __forceinline__ void corr_lp_bin(const float2 *__restrict__ Xf, int T
     }
     for (int t0 = 0; t0 < T; t0 += kChunk) {
         const int nf = min(kChunk, T - t0);
+        if (t0 > 0) load_chunk<MP>(Xf, t0, nf, M, sT, tid, v);
         __syncthreads();
-        // every load of the chunk in flight before the first LDS store
-        constexpr int NIT = kChunk * MP / kThreads;
-        float2 v[NIT];
-#pragma unroll
-        for (int u = 0; u < NIT; ++u) {
-            const int e = tid + u * kThreads;
-            const int tt = e / MP, m = e - tt * MP;
-            v[u] = (tt < nf && m < M) ? Xf[(size_t)(t0 + tt) * sT + m] : make_float2(0.f, 0.f);
-        }
+        constexpr int NIT = kChunkRegs<MP>;
 #pragma unroll
         for (int u = 0; u < NIT; ++u) {
             const int e = tid + u * kThreads;
@@ -216,6 +229,7 @@ __device__ __forceinline__ void corr_lp_bin(const float2 *__restrict__ Xf, int T
             Pn[m * S + tt] = -r;
         }
         __syncthreads();
+        if (t0 + kChunk >= T) next(v);
         const int nsteps = (nf + 31) >> 5;
 #pragma unroll
         for (int q = 0; q < TPW; ++q) {
@@ -257,36 +271,58 @@ __device__ __forceinline__ void corr_lp_bin(const float2 *__restrict__ Xf, int T
 // ---------------------------------------------------------------------------------------------
 // Launch wrappers: one workgroup per bin, either bin f of one block or item (block, bin) of a batch.
 // E = float selects the FP32 kernel, __bf16 / _Float16 the 16-bit-input kernel.
-template <int MP, typename E>
+template <int MP, typename E, class Next>
 __device__ __forceinline__ void corr_bin(const float2 *Xf, int T, int M, int64_t sT, float scale,
-                                         int accumulate, float2 *Rf)
+                                         int accumulate, float2 *Rf, float2 (&v)[kChunkRegs<MP>],
+                                         Next &&next)
 {
     if constexpr (sizeof(E) == 4)
-        corr_f32_bin<MP>(Xf, T, M, sT, scale, accumulate, Rf);
+        corr_f32_bin<MP>(Xf, T, M, sT, scale, accumulate, Rf, v, next);
     else
-        corr_lp_bin<MP, E>(Xf, T, M, sT, scale, accumulate, Rf);
+        corr_lp_bin<MP, E>(Xf, T, M, sT, scale, accumulate, Rf, v, next);
 }
 
 // A resident grid of workgroups strides over the bins (a bin is a few microseconds of work: one
-// launch-time workgroup per bin spends as long being dispatched as computing).
+// launch-time workgroup per bin spends as long being dispatched as computing), loading each
+// bin's first chunk under the previous bin's products.
 template <int MP, typename E>
-__global__ __launch_bounds__(kThreads) void corr_single(const float2 *__restrict__ X, int F, int T,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void corr_single(const float2 *__restrict__ X, int F, int T,
                                                         int M, int64_t sF, int64_t sT, float scale,
                                                         int accumulate, float2 *__restrict__ R)
 {
-    for (int f = blockIdx.x; f < F; f += gridDim.x)
-        corr_bin<MP, E>(X + (size_t)f * sF, T, M, sT, scale, accumulate, R + (size_t)f * M * M);
+    const int tid = threadIdx.x;
+    const int nf0 = min(kChunk, T);
+    float2 v[kChunkRegs<MP>];
+    if (blockIdx.x < F) load_chunk<MP>(X + (size_t)blockIdx.x * sF, 0, nf0, M, sT, tid, v);
+    for (int f = blockIdx.x; f < F; f += gridDim.x) {
+        const int fn = f + gridDim.x;
+        corr_bin<MP, E>(X + (size_t)f * sF, T, M, sT, scale, accumulate, R + (size_t)f * M * M, v,
+                        [&](float2 (&w)[kChunkRegs<MP>]) {
+                            if (fn < F) load_chunk<MP>(X + (size_t)fn * sF, 0, nf0, M, sT, tid, w);
+                        });
+    }
 }
 
 template <int MP, typename E>
-__global__ __launch_bounds__(kThreads) void corr_batch(const BlockDev *__restrict__ blk,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void corr_batch(const BlockDev *__restrict__ blk,
                                                        const int2 *__restrict__ items, int n_items)
 {
+    const int tid = threadIdx.x;
+    auto first_chunk = [&](int i, float2 (&w)[kChunkRegs<MP>]) {
+        const int2 it = items[i];
+        const BlockDev &B = blk[it.x];
+        load_chunk<MP>(B.X + (size_t)it.y * B.sF, 0, min(kChunk, B.T), B.M, B.sT, tid, w);
+    };
+    float2 v[kChunkRegs<MP>];
+    if ((int)blockIdx.x < n_items) first_chunk(blockIdx.x, v);
     for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
         const int2 it = items[i];
         const BlockDev &B = blk[it.x];
+        const int in = i + gridDim.x;
         corr_bin<MP, E>(B.X + (size_t)it.y * B.sF, B.T, B.M, B.sT, B.scale, 0,
-                        B.R + (size_t)it.y * B.M * B.M);
+                        B.R + (size_t)it.y * B.M * B.M, v, [&](float2 (&w)[kChunkRegs<MP>]) {
+                            if (in < n_items) first_chunk(in, w);
+                        });
     }
 }
 
