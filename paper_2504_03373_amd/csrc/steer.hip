@@ -287,15 +287,20 @@ __device__ __forceinline__ void steer_tile(const E *__restrict__ Hf, int D, int 
 
     // software pipeline over the blocks: block i + 1's E_n loads are issued before block i's
     // MFMAs and written to LDS right after them (Bs is free once every wave has its fragments);
-    // block i's epilogue then works on registers while the next B is in place
-    const float2 *Enf;
-    bool ok;
-    int Ns;
-    float *Pf;
-    blk(0, Enf, ok, Ns, Pf);
+    // block i's epilogue then works on registers while the next B is in place.  The block
+    // descriptors (a chain of dependent reads) are fetched one block further ahead still.
+    struct Blk {
+        const float2 *En;
+        bool ok;
+        int Ns;
+        float *P;
+    };
+    Blk cur, nxt, nn;                  // blocks i, i + 1, i + 2 (unused entries stay unread)
+    blk(0, cur.En, cur.ok, cur.Ns, cur.P);
+    if (nb > 1) blk(1, nxt.En, nxt.ok, nxt.Ns, nxt.P);
     {
         BStage<NCT, WV> st;
-        load_b<NCT, WV>(Enf, M, M - Ns, tid, st);
+        load_b<NCT, WV>(cur.En, M, M - cur.Ns, tid, st);
         store_b<NCT, WV, E>(st, Bs, KS, KP, tid);
     }
     __syncthreads();
@@ -304,20 +309,18 @@ __device__ __forceinline__ void steer_tile(const E *__restrict__ Hf, int D, int 
         // recomputed per block instead of being hoisted out of the loop and held in registers
         int tid_i = tid, lane_i = lane;
         asm volatile("" : "+v"(tid_i), "+v"(lane_i));
-        const bool cur_ok = ok;
-        float *const cur_P = Pf;
         const bool more = i + 1 < nb;
+        if (i + 2 < nb) blk(i + 2, nn.En, nn.ok, nn.Ns, nn.P);
         BStage<NCT, WV> st;
-        if (more) {
-            blk(i + 1, Enf, ok, Ns, Pf);
-            load_b<NCT, WV>(Enf, M, M - Ns, tid_i, st);
-        }
+        if (more) load_b<NCT, WV>(nxt.En, M, M - nxt.Ns, tid_i, st);
         floatx4 acc1[NCT], acc2[NCT];
         mma<NCT, E>(S, Bs, KS, KQ, lane_i, acc1, acc2);
         __syncthreads();                   // every wave has read Bs
         if (more) store_b<NCT, WV, E>(st, Bs, KS, KP, tid_i);
-        finish_rows<NCT>(acc1, acc2, p, lane, wave, d0, D, cur_ok, cur_P, den_s, nrm_s);
+        finish_rows<NCT>(acc1, acc2, p, lane, wave, d0, D, cur.ok, cur.P, den_s, nrm_s);
         __syncthreads();                   // next B staged, den_s free
+        cur = nxt;
+        nxt = nn;
     }
 }
 
