@@ -221,7 +221,7 @@ __device__ __forceinline__ void mma(const AStrip<E> &S, const E *Bs, int KS, int
 template <int NCT>
 __device__ __forceinline__ void finish_rows(const floatx4 (&acc1)[NCT], const floatx4 (&acc2)[NCT],
                                             int p, int lane, int wave, int d0, int D, bool bin_ok,
-                                            float *__restrict__ Pf, float *den_s,
+                                            float *__restrict__ Pf,
                                             const float *nrm_s)
 {
     float part[4];
@@ -244,15 +244,13 @@ __device__ __forceinline__ void finish_rows(const floatx4 (&acc1)[NCT], const fl
             part[r] = sum16(s);
         }
     }
-    if ((lane & 15) == 0) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) den_s[wave * 16 + 4 * (lane >> 4) + r] = part[r];
-    }
-    __syncthreads();
+    // every lane of row group g = l / 16 holds den of rows 4 g + r in part[r]; lane j < 16 takes
+    // row j's from lane 16 (j / 4) + j % 4, which offers part[j % 4]
+    const float offer = (lane & 2) ? ((lane & 1) ? part[3] : part[2]) : ((lane & 1) ? part[1] : part[0]);
+    const float den = __shfl(offer, 16 * ((lane >> 2) & 3) + (lane & 3));
     if (lane < 16) {
         const int d = d0 + wave * 16 + lane;
         if (d < D) {
-            const float den = den_s[wave * 16 + lane];
             // hardware reciprocal (1 ulp): P is compared at 1e-4, den >= FLT_MIN
             Pf[d] = bin_ok ? nrm_s[wave * 16 + lane] * __builtin_amdgcn_rcpf(fmaxf(den, 1.17549435e-38f))
                            : 0.0f;
@@ -268,7 +266,6 @@ __device__ __forceinline__ void steer_tile(const E *__restrict__ Hf, int D, int 
 {
     typedef SteerCfg<E> C;
     __shared__ __attribute__((aligned(16))) E Bs[16 * NCT * C::KS_MAX];
-    __shared__ float den_s[16 * WV];
     __shared__ float nrm_s[16 * WV];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -317,8 +314,8 @@ __device__ __forceinline__ void steer_tile(const E *__restrict__ Hf, int D, int 
         mma<NCT, E>(S, Bs, KS, KQ, lane_i, acc1, acc2);
         __syncthreads();                   // every wave has read Bs
         if (more) store_b<NCT, WV, E>(st, Bs, KS, KP, tid_i);
-        finish_rows<NCT>(acc1, acc2, p, lane, wave, d0, D, cur.ok, cur.P, den_s, nrm_s);
-        __syncthreads();                   // next B staged, den_s free
+        finish_rows<NCT>(acc1, acc2, p, lane, wave, d0, D, cur.ok, cur.P, nrm_s);
+        __syncthreads();                   // next B staged
         cur = nxt;
         nxt = nn;
     }
