@@ -116,6 +116,54 @@ __device__ __forceinline__ float apply_reflector(const float2 *Vk, float2 vk, in
     return group_sum<G>(tn);
 }
 
+// The same reflector applied to two columns c0, c1 of X at once (one read of v, the two
+// dependency chains interleaved); the results for c1 are stored only if two.  tn0, tn1: their
+// trailing norms as in apply_reflector.
+template <int MP, int G>
+__device__ __forceinline__ void apply_reflector2(const float2 *Vk, float2 vk, int k, float tau,
+                                                 float2 *X, int c0, int c1, bool two, int q,
+                                                 float &tn0, float &tn1)
+{
+    constexpr int R = MP / G;
+    float wr0 = 0.f, wi0 = 0.f, wr1 = 0.f, wi1 = 0.f;
+    float2 x0[R], x1[R], v[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        if (G * (j + 1) <= k) continue;
+        const int r = q + G * j;
+        const float2 raw = Vk[r];
+        v[j] = (r > k) ? raw : ((r == k) ? vk : make_float2(0.f, 0.f));
+        x0[j] = X[c0 * MP + r];
+        x1[j] = X[c1 * MP + r];
+        wr0 = fmaf(v[j].x, x0[j].x, fmaf(v[j].y, x0[j].y, wr0));
+        wi0 = fmaf(v[j].x, x0[j].y, fmaf(-v[j].y, x0[j].x, wi0));
+        wr1 = fmaf(v[j].x, x1[j].x, fmaf(v[j].y, x1[j].y, wr1));
+        wi1 = fmaf(v[j].x, x1[j].y, fmaf(-v[j].y, x1[j].x, wi1));
+    }
+    wr0 = group_sum<G>(wr0) * tau;
+    wi0 = group_sum<G>(wi0) * tau;
+    wr1 = group_sum<G>(wr1) * tau;
+    wi1 = group_sum<G>(wi1) * tau;
+    float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        if (G * (j + 1) <= k) continue;
+        const int r = q + G * j;
+        x0[j].x = fmaf(-v[j].x, wr0, fmaf(v[j].y, wi0, x0[j].x));
+        x0[j].y = fmaf(-v[j].x, wi0, fmaf(-v[j].y, wr0, x0[j].y));
+        x1[j].x = fmaf(-v[j].x, wr1, fmaf(v[j].y, wi1, x1[j].x));
+        x1[j].y = fmaf(-v[j].x, wi1, fmaf(-v[j].y, wr1, x1[j].y));
+        X[c0 * MP + r] = x0[j];
+        if (two) X[c1 * MP + r] = x1[j];
+        const float n0 = fmaf(x0[j].x, x0[j].x, x0[j].y * x0[j].y);
+        const float n1 = fmaf(x1[j].x, x1[j].x, x1[j].y * x1[j].y);
+        s0 += (r > k) ? n0 : 0.0f;
+        s1 += (r > k) ? n1 : 0.0f;
+    }
+    tn0 = group_sum<G>(s0);
+    tn1 = group_sum<G>(s1);
+}
+
 // Pivot key: larger squared norm first, then the lower column index (norms are >= 0, so the
 // float bits order like the values).
 __device__ __forceinline__ unsigned long long pivot_key(float nrm2, int c)
@@ -268,10 +316,24 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                 clist[idx] = last;
                 cinv[last] = idx;
             }
-            for (int sl = g; sl < nrem && g < NG; sl += NG) {
-                const int c = (sl == idx) ? last : clist[sl];
-                const float tn = apply_reflector<MP, G>(X + p * MP, vk, k, tk, X, c, M, q);
-                if (q == 0) atomicMax(&pkey[kn], pivot_key(tn, c));
+            // slots g and g + NG (nrem <= 2 NG); a wave with any second slot takes the two-column
+            // path for all its groups
+            if (g < NG && g < nrem) {
+                const int c0 = (g == idx) ? last : clist[g];
+                const int s1 = g + NG;
+                const bool two = s1 < nrem;
+                if (__any(two)) {
+                    const int c1 = two ? ((s1 == idx) ? last : clist[s1]) : c0;
+                    float tn0, tn1;
+                    apply_reflector2<MP, G>(X + p * MP, vk, k, tk, X, c0, c1, two, q, tn0, tn1);
+                    if (q == 0) {
+                        atomicMax(&pkey[kn], pivot_key(tn0, c0));
+                        if (two) atomicMax(&pkey[kn], pivot_key(tn1, c1));
+                    }
+                } else {
+                    const float tn = apply_reflector<MP, G>(X + p * MP, vk, k, tk, X, c0, M, q);
+                    if (q == 0) atomicMax(&pkey[kn], pivot_key(tn, c0));
+                }
             }
             __syncthreads();
             const int t = kc;
@@ -336,9 +398,20 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
             const float tk = nx > 0.f ? __builtin_amdgcn_rcpf(nx * (nx + axk)) : 0.0f;
             const float2 vk = make_float2(ph.x * (axk + nx), ph.y * (axk + nx));
             if (tid == 0) diag1[k] = make_float2(-ph.x * nx, -ph.y * nx);
-            for (int c = k + 1 + g; c < rk && g < NG; c += NG) {
-                const float tn = apply_reflector<MP, G>(X + k * MP, vk, k, tk, X, c, M, q);
-                if (c == k + 1 && q == 0) nrm1[c] = tn;
+            // columns k + 1 + g and k + 1 + g + NG, as in the pivoted QR
+            const int c0 = k + 1 + g;
+            if (g < NG && c0 < rk) {
+                const int c1 = c0 + NG;
+                const bool two = c1 < rk;
+                if (__any(two)) {
+                    float tn0, tn1;
+                    apply_reflector2<MP, G>(X + k * MP, vk, k, tk, X, c0, two ? c1 : c0, two, q,
+                                            tn0, tn1);
+                    if (c0 == k + 1 && q == 0) nrm1[c0] = tn0;
+                } else {
+                    const float tn = apply_reflector<MP, G>(X + k * MP, vk, k, tk, X, c0, M, q);
+                    if (c0 == k + 1 && q == 0) nrm1[c0] = tn;
+                }
             }
             __syncthreads();
         }
