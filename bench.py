@@ -113,7 +113,11 @@ def pmc_summarize(fetch_dir: str, write_dir: str, calib_mb: int, batch: int) -> 
     for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = _pmc_rows(d, name)
         cal = [v for k, v in rows if "neg" in k.lower()]
-        jac = [v for k, v in rows if "jacobi_persistent" in k]
+        # the variant the timed steps ran: the most frequent one (the autotuner also launches the
+        # others a few times)
+        names = [k for k, _ in rows if "jacobi_persistent" in k]
+        top = max(set(names), key=names.count) if names else None
+        jac = [v for k, v in rows if k == top]
         if not cal or not jac:
             raise SystemExit(f"{name}: calibration or Jacobi dispatches missing in {d}")
         scale = calib / (max(cal) * 1024.0)
