@@ -8,8 +8,8 @@
 // 16x16 tiles of the upper block triangle (I <= J) of the MP x MP padded result; the lower
 // triangle is written as the conjugate of the same registers, so R is Hermitian to the bit.
 //
-// FP64 path (for the noise correlation K): same staging, one thread per upper-triangle entry,
-// FP64 fused multiply-adds in frame order.
+// FP64 path (for the noise correlation K): same staging and tiling on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64), FP64 products of the exactly widened frames, FP64 accumulation.
 #include "ssl_internal.h"
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -340,86 +340,100 @@ int resident_grid(K kernel, int n)
 }
 
 // ---------------------------------------------------------------------------------------------
-// FP64 accumulation (noise correlation K): one thread per upper-triangle entry (i <= j), 1024
-// threads so that each holds about two entries and a CU keeps 4 waves per SIMD busy.
-constexpr int kF64Threads = 1024;
-__global__ __launch_bounds__(kF64Threads) void corr_f64(const float2 *__restrict__ X, int T, int M,
+// FP64 accumulation (noise correlation K) on v_mfma_f64_16x16x4f64: the complex64 frames are
+// widened exactly to FP64 operands and the products accumulate in FP64.  With x = a + i b,
+//   Re K_ij += a_i a_j + b_i b_j,     Im K_ij += b_i a_j - a_i b_j
+// over k-steps of 4 frames: A[i][k] = x_{t+k}[16I + i] from lane i + 16k, B[k][j] = x_{t+k}[16J + j]
+// from lane j + 16k.  Each wave owns 16x16 tiles of the upper block triangle; the result goes
+// through LDS (the lower triangle as the conjugate of the same registers: K is Hermitian to the
+// bit, with a zero imaginary diagonal) and leaves in rows.  The FP64 result layout: element e of
+// lane l is row l/16 + 4e, column l%16 of the tile.
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <int MP>
+__global__ __launch_bounds__(kThreads) void corr_f64(const float2 *__restrict__ X, int T, int M,
                                                      int64_t sF, int64_t sT, double scale,
                                                      int accumulate, double2 *__restrict__ R)
 {
-    constexpr int MAXE = (SSL_MAX_M * (SSL_MAX_M + 1) / 2 + kF64Threads - 1) / kF64Threads;
-    __shared__ float2 Z[kChunk * SSL_MAX_M];
+    constexpr int NT = MP / 16;
+    constexpr int NTILE = NT * (NT + 1) / 2;
+    constexpr int TPW = (NTILE + 3) / 4;
+    constexpr int S = MP + 16;                 // frame row stride: the 4 rows of a step on other banks
+    constexpr int RS = MP + 1;                 // result row stride (complex128)
+    constexpr int ZB = kChunk * S * 8, RB = MP * RS * 16;
+    __shared__ __attribute__((aligned(16))) char buf[ZB > RB ? ZB : RB];
+    float2 *Z = reinterpret_cast<float2 *>(buf);
     const int f = blockIdx.x;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const float2 *Xf = X + (size_t)f * sF;
-    const int nent = M * (M + 1) / 2;
 
-    int ei[MAXE], ej[MAXE];
-    double accr[MAXE], acci[MAXE];
+    doublex4 acc_re[TPW], acc_im[TPW];
 #pragma unroll
-    for (int q = 0; q < MAXE; ++q) {
-        int e = tid + q * kF64Threads;
-        int i = 0;
-        if (e < nent) {
-            while (e >= M - i) { e -= M - i; ++i; }
-            ei[q] = i;
-            ej[q] = i + e;
-        } else {
-            ei[q] = -1;
-            ej[q] = -1;
-        }
-        accr[q] = 0.0;
-        acci[q] = 0.0;
+    for (int q = 0; q < TPW; ++q) {
+        acc_re[q] = doublex4{0.0, 0.0, 0.0, 0.0};
+        acc_im[q] = doublex4{0.0, 0.0, 0.0, 0.0};
     }
     for (int t0 = 0; t0 < T; t0 += kChunk) {
         const int nf = min(kChunk, T - t0);
         __syncthreads();
-        for (int tt = tid >> 6; tt < nf; tt += kF64Threads / 64) {   // frame by wave, m by lane
-            const int m = tid & 63;
-            if (m < M) Z[tt * SSL_MAX_M + m] = Xf[(size_t)(t0 + tt) * sT + m];
+        for (int e = tid; e < kChunk * MP; e += kThreads) {     // frame e / MP, channel e % MP
+            const int tt = e / MP, m = e % MP;
+            Z[tt * S + m] = (tt < nf && m < M) ? Xf[(size_t)(t0 + tt) * sT + m]
+                                               : make_float2(0.f, 0.f);
         }
         __syncthreads();
+        const int nsteps = (nf + 3) >> 2;
 #pragma unroll
-        for (int q = 0; q < MAXE; ++q) {
-            if (ei[q] < 0) continue;
-            const int i = ei[q], j = ej[q];
-            double sr = accr[q], si = acci[q];
-            for (int tt = 0; tt < nf; ++tt) {
-                const float2 a = Z[tt * SSL_MAX_M + i], b = Z[tt * SSL_MAX_M + j];
-                // x_i conj(x_j)
-                sr = fma((double)a.x, (double)b.x, sr);
-                sr = fma((double)a.y, (double)b.y, sr);
-                si = fma((double)a.y, (double)b.x, si);
-                si = fma(-(double)a.x, (double)b.y, si);
+        for (int q = 0; q < TPW; ++q) {
+            const int tile = wave + 4 * q;
+            if (tile < NTILE) {
+                int I, J;
+                tile_coords(tile, NT, I, J);
+                const int ca = 16 * I + (lane & 15), cb = 16 * J + (lane & 15);
+                for (int s = 0; s < nsteps; ++s) {
+                    const int row = (4 * s + (lane >> 4)) * S;
+                    const float2 a = Z[row + ca], b = Z[row + cb];
+                    const double ar = a.x, ai = a.y, br = b.x, bi = b.y;
+                    acc_re[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, acc_re[q], 0, 0, 0);
+                    acc_re[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, acc_re[q], 0, 0, 0);
+                    acc_im[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, acc_im[q], 0, 0, 0);
+                    acc_im[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ar, bi, acc_im[q], 0, 0, 0);
+                }
             }
-            accr[q] = sr;
-            acci[q] = si;
         }
     }
-    double2 *Rf = R + (size_t)f * M * M;
+    __syncthreads();                           // frames no longer needed: buf holds the result
+    double2 *Rs = reinterpret_cast<double2 *>(buf);
 #pragma unroll
-    for (int q = 0; q < MAXE; ++q) {
-        if (ei[q] < 0) continue;
-        const int i = ei[q], j = ej[q];
-        const double vr = accr[q] * scale;
-        const double vi = (i == j) ? 0.0 : acci[q] * scale;
-        double2 *p = Rf + (size_t)i * M + j;
-        double2 *pq = Rf + (size_t)j * M + i;
-        if (accumulate) {
-            double2 a = *p;
-            a.x += vr;
-            a.y += vi;
-            *p = a;
-            if (i != j) {
-                double2 b = *pq;
-                b.x += vr;
-                b.y -= vi;
-                *pq = b;
+    for (int q = 0; q < TPW; ++q) {
+        const int tile = wave + 4 * q;
+        if (tile < NTILE) {
+            int I, J;
+            tile_coords(tile, NT, I, J);
+            const int j = 16 * J + (lane & 15);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int i = 16 * I + (lane >> 4) + 4 * e;
+                if (I == J && i > j) continue;           // mirrored from the (j, i) lane
+                const double vr = acc_re[q][e] * scale;
+                const double vi = (i == j) ? 0.0 : acc_im[q][e] * scale;
+                Rs[i * RS + j] = make_double2(vr, vi);
+                if (i != j) Rs[j * RS + i] = make_double2(vr, -vi);
             }
-        } else {
-            *p = make_double2(vr, vi);
-            if (i != j) *pq = make_double2(vr, -vi);
         }
+    }
+    __syncthreads();
+    double2 *Rf = R + (size_t)f * M * M;
+    for (int i = wave; i < M; i += kThreads / 64) {              // row by wave, column by lane
+        const int j = lane;
+        if (j >= M) continue;
+        double2 v = Rs[i * RS + j];
+        if (accumulate) {
+            const double2 a = Rf[(size_t)i * M + j];
+            v.x += a.x;
+            v.y += a.y;
+        }
+        Rf[(size_t)i * M + j] = v;
     }
 }
 
@@ -469,9 +483,17 @@ hipError_t launch_corr(const ssl_c64 *X, int F, int T, int M, int64_t sF, int64_
                        int accumulate, ssl_prec prec, void *R, hipStream_t st)
 {
     if (prec == SSL_FP64) {
-        hipLaunchKernelGGL(corr_f64, dim3(F), dim3(kF64Threads), 0, st,
-                           reinterpret_cast<const float2 *>(X), T, M, sF, sT, scale, accumulate,
-                           reinterpret_cast<double2 *>(R));
+        const float2 *Xp = reinterpret_cast<const float2 *>(X);
+        double2 *Rp = reinterpret_cast<double2 *>(R);
+        if (M <= 16)
+            hipLaunchKernelGGL(corr_f64<16>, dim3(F), dim3(kThreads), 0, st, Xp, T, M, sF, sT,
+                               scale, accumulate, Rp);
+        else if (M <= 32)
+            hipLaunchKernelGGL(corr_f64<32>, dim3(F), dim3(kThreads), 0, st, Xp, T, M, sF, sT,
+                               scale, accumulate, Rp);
+        else
+            hipLaunchKernelGGL(corr_f64<64>, dim3(F), dim3(kThreads), 0, st, Xp, T, M, sF, sT,
+                               scale, accumulate, Rp);
         return hipGetLastError();
     }
     switch (corr_class(M)) {
