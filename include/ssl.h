@@ -121,6 +121,19 @@ ssl_status ssl_noise_set(ssl_noise K, const void *Kin, ssl_prec kprec, int32_t *
  *   K <- alpha * K + (1 - alpha) * Khat, then refactor (same outputs as ssl_noise_set). */
 ssl_status ssl_noise_update(ssl_noise K, const void *Khat, ssl_prec kprec, double alpha,
                             int32_t *bin_status, void *stream);
+/* Serving form of ssl_noise_update, for many streams in one call: for each i < n, handle i's K is
+ * blended with the FP64 correlation of its own noise-only frames Xn[i] ([F][T[i]][M] complex64,
+ * device, contiguous, F and M those of the handle) and refactored:
+ *   K <- alpha * K + (1 - alpha) * (1/T) sum_t x_t x_t^H.
+ * Bit-identical to ssl_corr_accum(ctx, Xn[i], F, T[i], M, T[i] M, M, 1.0 / T[i], 0, SSL_FP64,
+ * Khat) followed by ssl_noise_update(handle, Khat, SSL_FP64, alpha, NULL), handle by handle in
+ * array order on `stream` (a handle listed twice is updated twice).  K-hat lives in ctx's
+ * workspace (the largest F M^2 complex128 of the list), so calls on one ctx must not overlap on
+ * different streams.  Handles must be on ctx's device.  Each handle keeps its per-bin status
+ * (SSL_BIN_NOT_PD bins yield that status in ssl_gsvd). */
+ssl_status ssl_noise_update_frames(ssl_ctx ctx, int n, const ssl_noise *handles,
+                                   const ssl_c64 *const *Xn, const int *T, double alpha,
+                                   void *stream);
 /* Copies the current K (complex128 [F][M][M]) to K_out (device) for checkpointing. */
 ssl_status ssl_noise_get(ssl_noise K, ssl_c128 *K_out, void *stream);
 void ssl_noise_destroy(ssl_noise K);

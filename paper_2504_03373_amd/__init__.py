@@ -28,6 +28,7 @@ EXPORTED = [
     "ssl_ctx_timing", "ssl_ctx_timing_read", "ssl_localize_batch", "ssl_ctx_use_graphs",
     "ssl_ctx_set_jacobi_lanes", "ssl_ctx_get_jacobi_lanes", "ssl_autotune_jacobi",
     "ssl_ctx_set_steer_waves", "ssl_ctx_get_steer_waves", "ssl_autotune_steer",
+    "ssl_noise_update_frames",
 ]
 
 
@@ -84,6 +85,8 @@ def lib() -> ctypes.CDLL:
         "ssl_autotune_jacobi": (I, [P, P, P, I, I, I, I, I, ctypes.POINTER(I),
                                     ctypes.POINTER(ctypes.c_double), P]),
         "ssl_ctx_set_steer_waves": (I, [P, I, I, I, I]),
+        "ssl_noise_update_frames": (I, [P, I, ctypes.POINTER(P), ctypes.POINTER(P),
+                                        ctypes.POINTER(I), ctypes.c_double, P]),
         "ssl_ctx_get_steer_waves": (I, [P, I, I, I]),
         "ssl_autotune_steer": (I, [P, P, I, P, I, I, I, I, I, I, I, ctypes.POINTER(I),
                                    ctypes.POINTER(ctypes.c_double), P]),
@@ -178,6 +181,22 @@ def ssl_noise_set(noise, K, kprec, bin_status=None, stream=None):
 def ssl_noise_update(noise, Khat, kprec, alpha, bin_status=None, stream=None):
     _check("ssl_noise_update", lib().ssl_noise_update(noise, _ptr(Khat), kprec, float(alpha),
                                                       _ptr(bin_status), _stream(stream)))
+
+
+def ssl_noise_update_frames(ctx, noises, Xns, alpha, stream=None):
+    """Serving EMA update of many handles from their noise-only frames (each [F][T][M] complex64,
+    contiguous, on the device), one library call."""
+    n = len(noises)
+    if len(Xns) != n:
+        raise ValueError("one frame tensor per noise handle")
+    for X in Xns:
+        if not X.is_contiguous():
+            raise ValueError("noise frames must be contiguous")
+    hs = (ctypes.c_void_p * max(n, 1))(*noises)
+    xs = (ctypes.c_void_p * max(n, 1))(*[X.data_ptr() for X in Xns])
+    ts = (ctypes.c_int * max(n, 1))(*[int(X.shape[1]) for X in Xns])
+    _check("ssl_noise_update_frames", lib().ssl_noise_update_frames(ctx, n, hs, xs, ts, float(alpha),
+                                                                    _stream(stream)))
 
 
 def ssl_noise_get(noise, K_out, stream=None):

@@ -429,6 +429,63 @@ ssl_status ssl_noise_update(ssl_noise n, const void *Khat, ssl_prec kprec, doubl
     return noise_refactor(n, bin_status, st);
 }
 
+ssl_status ssl_noise_update_frames(ssl_ctx ctx, int n, const ssl_noise *handles,
+                                   const ssl_c64 *const *Xn, const int *T, double alpha,
+                                   void *stream)
+{
+    if (!ctx || n < 0 || (n > 0 && (!handles || !Xn || !T))) {
+        ssl_set_error("ctx, handles, Xn or T is NULL (or n < 0)");
+        return SSL_ERR_ARG;
+    }
+    if (!(alpha >= 0.0 && alpha <= 1.0)) {
+        ssl_set_error("alpha = %g must lie in [0, 1]", alpha);
+        return SSL_ERR_ARG;
+    }
+    size_t most = 0;
+    for (int i = 0; i < n; ++i) {
+        const ssl_noise h = handles[i];
+        if (!h || !Xn[i]) {
+            ssl_set_error("entry %d: noise handle or frames are NULL", i);
+            return SSL_ERR_ARG;
+        }
+        if (!h->is_set) {
+            ssl_set_error("entry %d: noise handle was never set", i);
+            return SSL_ERR_STATE;
+        }
+        if (h->ctx->device != ctx->device) {
+            ssl_set_error("entry %d: noise handle lives on device %d, ctx on %d", i,
+                          h->ctx->device, ctx->device);
+            return SSL_ERR_ARG;
+        }
+        if (T[i] < 1) {
+            ssl_set_error("entry %d: T = %d must be >= 1", i, T[i]);
+            return SSL_ERR_ARG;
+        }
+        most = std::max(most, (size_t)h->F * h->M * h->M * sizeof(ssl_c128));
+    }
+    if (n == 0) return SSL_OK;
+    DeviceGuard dg(ctx->device);
+    ssl_status s = ws_reserve(ctx, align256(most));
+    if (s != SSL_OK) return s;
+    ssl_c128 *Khat = static_cast<ssl_c128 *>(ctx->ws);      // reused in stream order
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    for (int i = 0; i < n; ++i) {
+        const ssl_noise h = handles[i];
+        const int F = h->F, M = h->M;
+        hipError_t e = timed(ctx, SSL_K_CORR, st, [&] {
+            return launch_corr(Xn[i], F, T[i], M, (int64_t)T[i] * M, M, 1.0 / T[i], 0, SSL_FP64,
+                               Khat, st);
+        });
+        if (e != hipSuccess) return hip_fail(e, "noise correlation launch");
+        e = timed(h->ctx, SSL_K_NOISE, st, [&] {
+            return launch_noise_blend(h->K, Khat, SSL_FP64, alpha, F, M, st);
+        });
+        if (e != hipSuccess) return hip_fail(e, "noise blend launch");
+        if ((s = noise_refactor(h, nullptr, st)) != SSL_OK) return s;
+    }
+    return SSL_OK;
+}
+
 ssl_status ssl_noise_get(ssl_noise n, ssl_c128 *K_out, void *stream)
 {
     if (!n || !K_out) {

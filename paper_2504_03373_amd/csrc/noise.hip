@@ -13,7 +13,6 @@
 
 namespace {
 
-constexpr int kFactorThreads = 512;
 constexpr double kPdRel = 9.094947017729282e-13;   // 2^-40: pivot floor relative to max_i K_ii
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b)
@@ -21,34 +20,47 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b)
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// One workgroup per bin; the whole MP x MP complex128 matrix in LDS (64 KB at MP = 64).
-// Step k with pivot p = W_kk (real for Hermitian input):
+// One workgroup per bin, the MP x MP complex128 matrix in registers: thread t owns column
+// j = t % MP of rows t / MP + (MP / 8) u, u < 8.  Step k with pivot p = W_kk (real for Hermitian
+// input):
 //   W_ij -= W_ik W_kj / p (i, j != k);  W_kj /= p;  W_ik = -W_ik / p;  W_kk = 1 / p.
-// After M steps W = K^{-1}.  A pivot p <= 2^-40 max_i K_ii (or non-finite) marks the bin NOT_PD.
+// Only the pivot row and column travel, through two LDS buffers alternating by step: the owners
+// post row and column k + 1 after their update, so a step costs one barrier.  After M steps
+// W = K^{-1}.  A pivot p <= 2^-40 max_i K_ii (or non-finite) marks the bin NOT_PD.
+template <int MP> constexpr int kFactorThreads = MP * MP / 8;
+
 template <int MP>
-__global__ __launch_bounds__(kFactorThreads) void noise_factor(const double2 *__restrict__ K,
-                                                               double2 *__restrict__ Kinv,
-                                                               int32_t *__restrict__ status,
-                                                               int M)
+__global__ __launch_bounds__(kFactorThreads<MP>) void noise_factor(const double2 *__restrict__ K,
+                                                                    double2 *__restrict__ Kinv,
+                                                                    int32_t *__restrict__ status,
+                                                                    int M)
 {
-    __shared__ double2 W[MP * MP];
+    constexpr int RG = MP / 8;                     // row groups: rows of thread t are t / MP + RG u
+    __shared__ double2 colb[2][MP], rowb[2][MP];
+    __shared__ double diag_s[MP];
     __shared__ double thr_s;
     __shared__ int bad_s;
     const int f = blockIdx.x;
-    const int tid = threadIdx.x;
+    const int t = threadIdx.x;
+    const int j = t % MP, i0 = t / MP;
     const double2 *Kf = K + (size_t)f * M * M;
     double2 *Wf = Kinv + (size_t)f * M * M;
 
-    for (int e = tid; e < M * MP; e += kFactorThreads) {
-        const int i = e / MP, j = e % MP;
-        if (j < M) W[i * MP + j] = Kf[i * M + j];
+    double2 w[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int i = i0 + RG * u;
+        w[u] = (i < M && j < M) ? Kf[(size_t)i * M + j] : make_double2(0.0, 0.0);
+        if (i == j) diag_s[i] = w[u].x;
+        if (j == 0) colb[0][i] = w[u];
+        if (i == 0) rowb[0][j] = w[u];
     }
     __syncthreads();
-    if (tid == 0) {
+    if (t == 0) {
         double dm = 0.0;
         bool fin = true;
         for (int i = 0; i < M; ++i) {
-            const double d = W[i * MP + i].x;
+            const double d = diag_s[i];
             fin = fin && isfinite(d);
             dm = fmax(dm, d);
         }
@@ -59,38 +71,46 @@ __global__ __launch_bounds__(kFactorThreads) void noise_factor(const double2 *__
     bool bad = bad_s != 0;
     const double thr = thr_s;
     for (int k = 0; k < M && !bad; ++k) {
-        const double p = W[k * MP + k].x;             // every thread reads the same pivot
+        const int b = k & 1;
+        const double p = rowb[b][k].x;                // every thread reads the same pivot
         if (!isfinite(p) || p <= thr) {
             bad = true;
             break;
         }
         const double ip = 1.0 / p;
-        for (int e = tid; e < MP * MP; e += kFactorThreads) {
-            const int i = e / MP, j = e % MP;             // MP is a power of two: shifts
-            if (i >= M || j >= M || i == k || j == k) continue;
-            const double2 t = cmul(W[i * MP + k], W[k * MP + j]);
-            double2 w = W[i * MP + j];
-            w.x = fma(-t.x, ip, w.x);
-            w.y = fma(-t.y, ip, w.y);
-            W[i * MP + j] = w;
-        }
-        __syncthreads();
-        for (int e = tid; e < M; e += kFactorThreads) {
-            if (e == k) {
-                W[k * MP + k] = make_double2(ip, 0.0);
+        const double2 wkj = rowb[b][j];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + RG * u;
+            if (i >= M || j >= M) continue;
+            if (i == k && j == k) {
+                w[u] = make_double2(ip, 0.0);
+            } else if (i == k) {
+                w[u] = make_double2(w[u].x * ip, w[u].y * ip);
+            } else if (j == k) {
+                w[u] = make_double2(-w[u].x * ip, -w[u].y * ip);
             } else {
-                const double2 r = W[k * MP + e], c = W[e * MP + k];
-                W[k * MP + e] = make_double2(r.x * ip, r.y * ip);
-                W[e * MP + k] = make_double2(-c.x * ip, -c.y * ip);
+                const double2 tt = cmul(colb[b][i], wkj);
+                w[u].x = fma(-tt.x, ip, w[u].x);
+                w[u].y = fma(-tt.y, ip, w[u].y);
+            }
+        }
+        if (k + 1 < M) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = i0 + RG * u;
+                if (j == k + 1) colb[b ^ 1][i] = w[u];
+                if (i == k + 1) rowb[b ^ 1][j] = w[u];
             }
         }
         __syncthreads();
     }
-    for (int e = tid; e < M * MP; e += kFactorThreads) {
-        const int i = e / MP, j = e % MP;
-        if (j < M) Wf[i * M + j] = bad ? make_double2(0.0, 0.0) : W[i * MP + j];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int i = i0 + RG * u;
+        if (i < M && j < M) Wf[(size_t)i * M + j] = bad ? make_double2(0.0, 0.0) : w[u];
     }
-    if (tid == 0) status[f] = bad ? SSL_BIN_NOT_PD : SSL_BIN_OK;
+    if (t == 0) status[f] = bad ? SSL_BIN_NOT_PD : SSL_BIN_OK;
 }
 
 // K <- alpha K + (1 - alpha) Khat
@@ -288,11 +308,14 @@ hipError_t launch_noise_factor(ssl_c128 *K, ssl_c128 *Kinv, int32_t *status, int
     const double2 *Kp = reinterpret_cast<const double2 *>(K);
     double2 *Wp = reinterpret_cast<double2 *>(Kinv);
     if (M <= 16)
-        hipLaunchKernelGGL(noise_factor<16>, dim3(F), dim3(kFactorThreads), 0, st, Kp, Wp, status, M);
+        hipLaunchKernelGGL(noise_factor<16>, dim3(F), dim3(kFactorThreads<16>), 0, st, Kp, Wp,
+                           status, M);
     else if (M <= 32)
-        hipLaunchKernelGGL(noise_factor<32>, dim3(F), dim3(kFactorThreads), 0, st, Kp, Wp, status, M);
+        hipLaunchKernelGGL(noise_factor<32>, dim3(F), dim3(kFactorThreads<32>), 0, st, Kp, Wp,
+                           status, M);
     else
-        hipLaunchKernelGGL(noise_factor<64>, dim3(F), dim3(kFactorThreads), 0, st, Kp, Wp, status, M);
+        hipLaunchKernelGGL(noise_factor<64>, dim3(F), dim3(kFactorThreads<64>), 0, st, Kp, Wp,
+                           status, M);
     return hipGetLastError();
 }
 

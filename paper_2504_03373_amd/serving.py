@@ -181,10 +181,9 @@ class GpuExecutor:
         self.H = {M: t for M, t in steering.items()}
         self.noise, self.X_slot, self.Xn_slot, self.X_pool, self.Xn_pool = [], [], [], [], []
         self.k_version = [0] * len(self.streams)
-        Mmax = max(s.M for s in self.streams)
-        Fmax = max(s.F for s in self.streams)
-        self.Khat = [torch.zeros((Fmax * Mmax * Mmax,), dtype=torch.complex128, device=self.dev)
-                     for _ in self.nstreams]
+        # one library context per noise stream: an update call keeps K-hat in its context's
+        # workspace, and calls on different streams may overlap
+        self.uctx = [ssl_ctx_create(device, 0) for _ in self.nstreams]
         for s in self.streams:
             Xn0 = torch.from_numpy(s.initial_noise_frames()).to(self.dev)
             K0 = torch.zeros((s.F, s.M, s.M), dtype=torch.complex128, device=self.dev)
@@ -250,7 +249,7 @@ class GpuExecutor:
         return self.inflight[lane][1].query()
 
     def collect(self, lane: int) -> None:
-        from . import ssl_corr_accum, ssl_noise_update
+        from . import ssl_noise_update_frames
         torch = self.torch
         reqs, ev = self.inflight[lane]
         ev.synchronize()
@@ -259,25 +258,30 @@ class GpuExecutor:
             ns = self.streams[r.stream].Ns
             r.peaks = pk[i, :ns].copy()
             r.peak_val = pv[i, :ns].copy()
-        # K EMA updates of this batch's streams, after the batch (which read the old K)
-        for r in reqs:
-            if (r.seq + 1) % self.k_every != 0:
-                continue
+        # K EMA updates of this batch's streams, after the batch (which read the old K): split
+        # over the noise streams, one library call each, so that a stream's next block waits for
+        # a short chain of updates only
+        ups = [r for r in reqs if (r.seq + 1) % self.k_every == 0]
+        nq = len(self.nstreams)
+        per = -(-len(ups) // nq) if ups else 0
+        for c0 in range(0, len(ups), max(per, 1)):
+            part = ups[c0:c0 + per]
             i = self.next_ns
-            self.next_ns = (i + 1) % len(self.nstreams)
+            self.next_ns = (i + 1) % nq
             ns = self.nstreams[i]
-            s = self.streams[r.stream]
             with torch.cuda.stream(ns):
                 ns.wait_event(ev)                 # after the batch that read the old K
-                xn = self.Xn_slot[r.stream]
-                xn.copy_(self.Xn_pool[r.stream][r.seq % self.pool], non_blocking=True)
-                Kh = self.Khat[i][: s.F * s.M * s.M].view(s.F, s.M, s.M)
-                ssl_corr_accum(self.nctx, xn, 1.0 / s.T, 0, self._fp64, Kh, stream=ns)
-                ssl_noise_update(self.noise[r.stream], Kh, self._fp64, self.alpha, stream=ns)
+                for r in part:
+                    self.Xn_slot[r.stream].copy_(self.Xn_pool[r.stream][r.seq % self.pool],
+                                                 non_blocking=True)
+                ssl_noise_update_frames(self.uctx[i], [self.noise[r.stream] for r in part],
+                                        [self.Xn_slot[r.stream] for r in part], self.alpha,
+                                        stream=ns)
                 done = torch.cuda.Event()
                 done.record(ns)
-            self.k_event[r.stream] = done
-            self.k_version[r.stream] += 1
+            for r in part:
+                self.k_event[r.stream] = done
+                self.k_version[r.stream] += 1
         self.inflight[lane] = None
 
     def close(self) -> None:
@@ -285,6 +289,6 @@ class GpuExecutor:
         self.torch.cuda.synchronize()
         for n in self.noise:
             ssl_noise_destroy(n)
-        for c in self.ctxs:
+        for c in self.ctxs + self.uctx:
             ssl_ctx_destroy(c)
         ssl_ctx_destroy(self.nctx)

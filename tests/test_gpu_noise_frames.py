@@ -1,0 +1,90 @@
+"""ssl_noise_update_frames: the serving form of the EMA noise update, many handles in one call.
+
+It must leave every handle exactly as the two-call form does (FP64 correlation of the noise-only
+frames into a scratch K-hat, then ssl_noise_update), in array order, including a handle listed
+twice; the inverse is checked through ssl_gsvd outputs on the updated handles.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_util import to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    import paper_2504_03373_amd as S
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    S.lib()
+    return S
+
+
+def crandn(rng, *shape):
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex64)
+
+
+def make_handle(S, ctx, X0):
+    import torch
+    F, T, M = X0.shape
+    K0 = torch.zeros((F, M, M), dtype=torch.complex128, device="cuda:0")
+    S.ssl_corr_accum(ctx, to_dev(X0), 1.0 / T, 0, S.SSL_FP64, K0)
+    n = S.ssl_noise_create(ctx, F, M)
+    S.ssl_noise_set(n, K0, S.SSL_FP64)
+    return n
+
+
+def test_update_frames_matches_two_call_form(S):
+    import torch
+    rng = np.random.default_rng(1234)
+    shapes = [(9, 40, 8), (5, 50, 16), (7, 50, 60)]
+    ctx = S.ssl_ctx_create(0, 0)
+    uctx = S.ssl_ctx_create(0, 0)
+    base = [crandn(rng, F, T, M) for F, T, M in shapes]
+    ref = [make_handle(S, ctx, X0) for X0 in base]
+    got = [make_handle(S, ctx, X0) for X0 in base]
+    # two rounds of frames; handle 1 listed twice in the second round
+    rounds = [[0, 1, 2], [1, 2, 1]]
+    for rd, order in enumerate(rounds):
+        frames = [to_dev(crandn(rng, *shapes[i])) for i in order]
+        say(f"round {rd}: two-call form, handles {order}")
+        for i, Xn in zip(order, frames):
+            F, T, M = shapes[i]
+            Kh = torch.zeros((F, M, M), dtype=torch.complex128, device="cuda:0")
+            S.ssl_corr_accum(ctx, Xn, 1.0 / T, 0, S.SSL_FP64, Kh)
+            S.ssl_noise_update(ref[i], Kh, S.SSL_FP64, 0.95)
+        say(f"round {rd}: ssl_noise_update_frames, handles {order}")
+        S.ssl_noise_update_frames(uctx, [got[i] for i in order], frames, 0.95)
+    for i, (F, T, M) in enumerate(shapes):
+        Ka = torch.zeros((F, M, M), dtype=torch.complex128, device="cuda:0")
+        Kb = torch.zeros_like(Ka)
+        S.ssl_noise_get(ref[i], Ka)
+        S.ssl_noise_get(got[i], Kb)
+        assert np.array_equal(to_host(Ka), to_host(Kb)), i
+        # the inverse, through the whitened SVD of one R
+        Ns = 1
+        R = torch.zeros((F, M, M), dtype=torch.complex64, device="cuda:0")
+        S.ssl_corr_accum(ctx, to_dev(crandn(rng, F, T, M)), 1.0 / T, 0, S.SSL_FP32, R)
+        out = []
+        for h in (ref[i], got[i]):
+            En = torch.zeros((F, M - Ns, M), dtype=torch.complex64, device="cuda:0")
+            st = torch.zeros(F, dtype=torch.int32, device="cuda:0")
+            S.ssl_gsvd(ctx, R, h, Ns, En, None, st, None, 0)
+            out.append((to_host(En), to_host(st)))
+        assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1]), i
+    # argument errors leave the handles untouched
+    with pytest.raises(S.SSLError):
+        S.ssl_noise_update_frames(uctx, [got[0]], [to_dev(crandn(rng, *shapes[0]))], 1.5)
+    S.ssl_noise_update_frames(uctx, [], [], 0.95)
+    for h in ref + got:
+        S.ssl_noise_destroy(h)
+    S.ssl_ctx_destroy(uctx)
+    S.ssl_ctx_destroy(ctx)
