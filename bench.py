@@ -162,6 +162,8 @@ def main() -> int:
     ap.add_argument("--serve-light-period-ms", type=float, default=30.0,
                     help="a second, lighter serving load (0 = skip)")
     ap.add_argument("--serve-budget-gb", type=float, default=4.0, help="HBM budget of in-flight work")
+    ap.add_argument("--serve-lanes", type=int, default=2,
+                    help="batches in flight at once (library context + HIP stream each)")
     ap.add_argument("--k-update-every", type=int, default=1)
     args = ap.parse_args()
 
@@ -459,7 +461,8 @@ def main() -> int:
                 S.ssl_ctx_set_steer_waves(c, M, Ns, prec, tuning["steer_waves"][args.prec])
 
         ex = GpuExecutor(streams, Hs, prec=prec, alpha=0.95, k_update_every=args.k_update_every,
-                         hbm_budget_bytes=budget, lanes=2, pool=4, configure=configure)
+                         hbm_budget_bytes=budget, lanes=args.serve_lanes, pool=4,
+                         configure=configure)
         srv = Server(ex, budget, max_batch=128)
         srv.run(synth.poisson_arrivals(len(streams), 0.1, args.serve_period_ms * 1e-3, seed=7))
         mix = {m: sum(1 for s_ in streams if s_.M == m) for m in sorted({s_.M for s_ in streams})}
@@ -474,7 +477,10 @@ def main() -> int:
                     "p50_ms": round(sv["p50_ms"], 3), "p99_ms": round(sv["p99_ms"], 3),
                     "max_ms": round(sv["max_ms"], 3), "mean_batch": round(sv["mean_batch"], 2),
                     "max_queue": sv["max_queue"], "k_update_every": args.k_update_every,
-                    "hbm_budget_gb": args.serve_budget_gb, "emitted_seconds": args.serve_seconds}
+                    "hbm_budget_gb": args.serve_budget_gb, "emitted_seconds": args.serve_seconds,
+                    "lanes": args.serve_lanes,
+                    "host_s": {k: round(sv[k], 3) for k in ("loop_s", "submit_s", "collect_s",
+                                                            "sleep_s")}}
 
         out["serving"] = serve(args.serve_period_ms)
         if args.serve_light_period_ms > 0:

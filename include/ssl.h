@@ -125,12 +125,13 @@ ssl_status ssl_noise_update(ssl_noise K, const void *Khat, ssl_prec kprec, doubl
  * blended with the FP64 correlation of its own noise-only frames Xn[i] ([F][T[i]][M] complex64,
  * device, contiguous, F and M those of the handle) and refactored:
  *   K <- alpha * K + (1 - alpha) * (1/T) sum_t x_t x_t^H.
- * Bit-identical to ssl_corr_accum(ctx, Xn[i], F, T[i], M, T[i] M, M, 1.0 / T[i], 0, SSL_FP64,
- * Khat) followed by ssl_noise_update(handle, Khat, SSL_FP64, alpha, NULL), handle by handle in
- * array order on `stream` (a handle listed twice is updated twice).  K-hat lives in ctx's
- * workspace (the largest F M^2 complex128 of the list), so calls on one ctx must not overlap on
- * different streams.  Handles must be on ctx's device.  Each handle keeps its per-bin status
- * (SSL_BIN_NOT_PD bins yield that status in ssl_gsvd). */
+ * Bit-identical, handle by handle, to ssl_corr_accum(ctx, Xn[i], F, T[i], M, T[i] M, M,
+ * 1.0 / T[i], 0, SSL_FP64, Khat) followed by ssl_noise_update(handle, Khat, SSL_FP64, alpha,
+ * NULL); a handle listed twice is updated twice, in list order.  All the bins of all the handles
+ * run in one correlation-and-blend launch and one inverse launch per channel-count class (M <= 16,
+ * <= 32, <= 64), on `stream`.  The descriptors go through ctx's batch staging buffers, so calls on
+ * one ctx must be issued on one stream (or not overlap).  Handles must be on ctx's device.  Each
+ * handle keeps its per-bin status (SSL_BIN_NOT_PD bins yield that status in ssl_gsvd). */
 ssl_status ssl_noise_update_frames(ssl_ctx ctx, int n, const ssl_noise *handles,
                                    const ssl_c64 *const *Xn, const int *T, double alpha,
                                    void *stream);

@@ -429,63 +429,6 @@ ssl_status ssl_noise_update(ssl_noise n, const void *Khat, ssl_prec kprec, doubl
     return noise_refactor(n, bin_status, st);
 }
 
-ssl_status ssl_noise_update_frames(ssl_ctx ctx, int n, const ssl_noise *handles,
-                                   const ssl_c64 *const *Xn, const int *T, double alpha,
-                                   void *stream)
-{
-    if (!ctx || n < 0 || (n > 0 && (!handles || !Xn || !T))) {
-        ssl_set_error("ctx, handles, Xn or T is NULL (or n < 0)");
-        return SSL_ERR_ARG;
-    }
-    if (!(alpha >= 0.0 && alpha <= 1.0)) {
-        ssl_set_error("alpha = %g must lie in [0, 1]", alpha);
-        return SSL_ERR_ARG;
-    }
-    size_t most = 0;
-    for (int i = 0; i < n; ++i) {
-        const ssl_noise h = handles[i];
-        if (!h || !Xn[i]) {
-            ssl_set_error("entry %d: noise handle or frames are NULL", i);
-            return SSL_ERR_ARG;
-        }
-        if (!h->is_set) {
-            ssl_set_error("entry %d: noise handle was never set", i);
-            return SSL_ERR_STATE;
-        }
-        if (h->ctx->device != ctx->device) {
-            ssl_set_error("entry %d: noise handle lives on device %d, ctx on %d", i,
-                          h->ctx->device, ctx->device);
-            return SSL_ERR_ARG;
-        }
-        if (T[i] < 1) {
-            ssl_set_error("entry %d: T = %d must be >= 1", i, T[i]);
-            return SSL_ERR_ARG;
-        }
-        most = std::max(most, (size_t)h->F * h->M * h->M * sizeof(ssl_c128));
-    }
-    if (n == 0) return SSL_OK;
-    DeviceGuard dg(ctx->device);
-    ssl_status s = ws_reserve(ctx, align256(most));
-    if (s != SSL_OK) return s;
-    ssl_c128 *Khat = static_cast<ssl_c128 *>(ctx->ws);      // reused in stream order
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    for (int i = 0; i < n; ++i) {
-        const ssl_noise h = handles[i];
-        const int F = h->F, M = h->M;
-        hipError_t e = timed(ctx, SSL_K_CORR, st, [&] {
-            return launch_corr(Xn[i], F, T[i], M, (int64_t)T[i] * M, M, 1.0 / T[i], 0, SSL_FP64,
-                               Khat, st);
-        });
-        if (e != hipSuccess) return hip_fail(e, "noise correlation launch");
-        e = timed(h->ctx, SSL_K_NOISE, st, [&] {
-            return launch_noise_blend(h->K, Khat, SSL_FP64, alpha, F, M, st);
-        });
-        if (e != hipSuccess) return hip_fail(e, "noise blend launch");
-        if ((s = noise_refactor(h, nullptr, st)) != SSL_OK) return s;
-    }
-    return SSL_OK;
-}
-
 ssl_status ssl_noise_get(ssl_noise n, ssl_c128 *K_out, void *stream)
 {
     if (!n || !K_out) {
@@ -1396,6 +1339,107 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
     }
     e = hipGraphLaunch(exec, st);
     return e == hipSuccess ? SSL_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+ssl_status ssl_noise_update_frames(ssl_ctx ctx, int n, const ssl_noise *handles,
+                                   const ssl_c64 *const *Xn, const int *T, double alpha,
+                                   void *stream)
+{
+    if (!ctx || n < 0 || (n > 0 && (!handles || !Xn || !T))) {
+        ssl_set_error("ctx, handles, Xn or T is NULL (or n < 0)");
+        return SSL_ERR_ARG;
+    }
+    if (!(alpha >= 0.0 && alpha <= 1.0)) {
+        ssl_set_error("alpha = %g must lie in [0, 1]", alpha);
+        return SSL_ERR_ARG;
+    }
+    // a handle listed r times is updated in rounds 0 .. r - 1 (in list order); the handles of one
+    // round are distinct, so each round is one batched launch pair per size class
+    std::vector<int> round(n);
+    int n_rounds = 0;
+    int64_t n_items = 0;
+    for (int i = 0; i < n; ++i) {
+        const ssl_noise h = handles[i];
+        if (!h || !Xn[i]) {
+            ssl_set_error("entry %d: noise handle or frames are NULL", i);
+            return SSL_ERR_ARG;
+        }
+        if (!h->is_set) {
+            ssl_set_error("entry %d: noise handle was never set", i);
+            return SSL_ERR_STATE;
+        }
+        if (h->ctx->device != ctx->device) {
+            ssl_set_error("entry %d: noise handle lives on device %d, ctx on %d", i,
+                          h->ctx->device, ctx->device);
+            return SSL_ERR_ARG;
+        }
+        if (T[i] < 1) {
+            ssl_set_error("entry %d: T = %d must be >= 1", i, T[i]);
+            return SSL_ERR_ARG;
+        }
+        int r = 0;
+        for (int k = 0; k < i; ++k) r += handles[k] == h;
+        round[i] = r;
+        n_rounds = std::max(n_rounds, r + 1);
+        n_items += h->F;
+    }
+    if (n == 0) return SSL_OK;
+    if (n_items > (int64_t)1 << 30) {
+        ssl_set_error("too many bins");
+        return SSL_ERR_ARG;
+    }
+    DeviceGuard dg(ctx->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // staging: descriptors [n], then the items of (round, class) segments
+    const size_t desc_bytes = align256(sizeof(NoiseUpdDev) * n);
+    const size_t item_bytes = sizeof(int2) * (size_t)n_items;
+    ssl_status s = bdesc_reserve(ctx, desc_bytes + item_bytes);
+    if (s != SSL_OK) return s;
+    hipError_t e = hipEventSynchronize(ctx->bdesc_ev);   // the previous staging copy is done
+    if (e != hipSuccess) return hip_fail(e, "staging event");
+    NoiseUpdDev *hd = static_cast<NoiseUpdDev *>(ctx->bdesc_host);
+    int2 *hi = reinterpret_cast<int2 *>(static_cast<char *>(ctx->bdesc_host) + desc_bytes);
+    for (int i = 0; i < n; ++i) {
+        const ssl_noise h = handles[i];
+        hd[i] = NoiseUpdDev{reinterpret_cast<const float2 *>(Xn[i]), h->F, T[i], h->M,
+                            reinterpret_cast<double2 *>(h->K), reinterpret_cast<double2 *>(h->Kinv),
+                            h->status};
+    }
+    struct Seg {
+        int cls, start, count;
+    };
+    std::vector<std::vector<Seg>> segs(n_rounds);
+    int pos = 0;
+    for (int r = 0; r < n_rounds; ++r)
+        for (int c : {16, 32, 64}) {
+            Seg sg{c, pos, 0};
+            for (int i = 0; i < n; ++i)
+                if (round[i] == r && noise_class(handles[i]->M) == c)
+                    for (int f = 0; f < handles[i]->F; ++f) hi[pos++] = make_int2(i, f);
+            sg.count = pos - sg.start;
+            if (sg.count) segs[r].push_back(sg);
+        }
+    e = hipMemcpyAsync(ctx->bdesc_dev, ctx->bdesc_host, desc_bytes + item_bytes,
+                       hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipEventRecord(ctx->bdesc_ev, st);
+    if (e != hipSuccess) return hip_fail(e, "descriptor copy");
+    const NoiseUpdDev *dd = static_cast<const NoiseUpdDev *>(ctx->bdesc_dev);
+    const int2 *di = reinterpret_cast<const int2 *>(static_cast<char *>(ctx->bdesc_dev) + desc_bytes);
+    for (int r = 0; r < n_rounds; ++r) {
+        for (const Seg &sg : segs[r]) {
+            e = timed(ctx, SSL_K_CORR, st, [&] {
+                return launch_noise_corr_blend(dd, di + sg.start, sg.count, sg.cls, alpha, st);
+            });
+            if (e != hipSuccess) return hip_fail(e, "noise correlation launch");
+        }
+        for (const Seg &sg : segs[r]) {
+            e = timed(ctx, SSL_K_NOISE, st, [&] {
+                return launch_noise_factor_batch(dd, di + sg.start, sg.count, sg.cls, st);
+            });
+            if (e != hipSuccess) return hip_fail(e, "noise factor launch");
+        }
+    }
+    return SSL_OK;
 }
 
 }  // extern "C"

@@ -350,10 +350,14 @@ int resident_grid(K kernel, int n)
 // lane l is row l/16 + 4e, column l%16 of the tile.
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
+// mode 0: R = scale S;  1: R += scale S;  2: R = alpha R + (1 - alpha) (scale S), S = sum_t x x^H
+// (the blend of the EMA noise update, in the same arithmetic as noise_blend_c128).
+constexpr int kStore = 0, kAccumulate = 1, kBlend = 2;
+
 template <int MP>
-__global__ __launch_bounds__(kThreads) void corr_f64(const float2 *__restrict__ X, int T, int M,
-                                                     int64_t sF, int64_t sT, double scale,
-                                                     int accumulate, double2 *__restrict__ R)
+__device__ __forceinline__ void corr_f64_bin(const float2 *__restrict__ Xf, int T, int M,
+                                             int64_t sT, double scale, int mode, double alpha,
+                                             double2 *__restrict__ Rf)
 {
     constexpr int NT = MP / 16;
     constexpr int NTILE = NT * (NT + 1) / 2;
@@ -363,9 +367,7 @@ __global__ __launch_bounds__(kThreads) void corr_f64(const float2 *__restrict__ 
     constexpr int ZB = kChunk * S * 8, RB = MP * RS * 16;
     __shared__ __attribute__((aligned(16))) char buf[ZB > RB ? ZB : RB];
     float2 *Z = reinterpret_cast<float2 *>(buf);
-    const int f = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const float2 *Xf = X + (size_t)f * sF;
 
     doublex4 acc_re[TPW], acc_im[TPW];
 #pragma unroll
@@ -423,18 +425,44 @@ __global__ __launch_bounds__(kThreads) void corr_f64(const float2 *__restrict__ 
         }
     }
     __syncthreads();
-    double2 *Rf = R + (size_t)f * M * M;
     for (int i = wave; i < M; i += kThreads / 64) {              // row by wave, column by lane
         const int j = lane;
         if (j >= M) continue;
         double2 v = Rs[i * RS + j];
-        if (accumulate) {
+        if (mode == kAccumulate) {
             const double2 a = Rf[(size_t)i * M + j];
             v.x += a.x;
             v.y += a.y;
+        } else if (mode == kBlend) {
+            const double2 a = Rf[(size_t)i * M + j];
+            v = make_double2(fma(alpha, a.x, (1.0 - alpha) * v.x),
+                             fma(alpha, a.y, (1.0 - alpha) * v.y));
         }
         Rf[(size_t)i * M + j] = v;
     }
+}
+
+template <int MP>
+__global__ __launch_bounds__(kThreads) void corr_f64(const float2 *__restrict__ X, int T, int M,
+                                                     int64_t sF, int64_t sT, double scale,
+                                                     int accumulate, double2 *__restrict__ R)
+{
+    const int f = blockIdx.x;
+    corr_f64_bin<MP>(X + (size_t)f * sF, T, M, sT, scale, accumulate ? kAccumulate : kStore, 0.0,
+                     R + (size_t)f * M * M);
+}
+
+// Item (handle, bin): K[f] <- alpha K[f] + (1 - alpha) (1/T) sum_t x x^H of the handle's frames.
+template <int MP>
+__global__ __launch_bounds__(kThreads) void noise_corr_blend(const NoiseUpdDev *__restrict__ h,
+                                                             const int2 *__restrict__ items,
+                                                             double alpha)
+{
+    const int2 it = items[blockIdx.x];
+    const NoiseUpdDev &H = h[it.x];
+    const int M = H.M, T = H.T, f = it.y;
+    corr_f64_bin<MP>(H.X + (size_t)f * T * M, T, M, M, 1.0 / T, kBlend, alpha,
+                     H.K + (size_t)f * M * M);
 }
 
 template <int MP, typename E>
@@ -502,6 +530,22 @@ hipError_t launch_corr(const ssl_c64 *X, int F, int T, int M, int64_t sF, int64_
     case 48: return launch_mp<48>(X, F, T, M, sF, sT, scale, accumulate, prec, R, st);
     default: return launch_mp<64>(X, F, T, M, sF, sT, scale, accumulate, prec, R, st);
     }
+}
+
+hipError_t launch_noise_corr_blend(const NoiseUpdDev *h, const int2 *items, int n_items, int cls,
+                                   double alpha, hipStream_t st)
+{
+    if (n_items <= 0) return hipSuccess;
+    if (cls == 16)
+        hipLaunchKernelGGL(noise_corr_blend<16>, dim3(n_items), dim3(kThreads), 0, st, h, items,
+                           alpha);
+    else if (cls == 32)
+        hipLaunchKernelGGL(noise_corr_blend<32>, dim3(n_items), dim3(kThreads), 0, st, h, items,
+                           alpha);
+    else
+        hipLaunchKernelGGL(noise_corr_blend<64>, dim3(n_items), dim3(kThreads), 0, st, h, items,
+                           alpha);
+    return hipGetLastError();
 }
 
 hipError_t launch_corr_batch(const BlockDev *blk, const int2 *items, int n_items, int cls,

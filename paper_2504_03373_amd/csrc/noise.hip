@@ -30,21 +30,17 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b)
 template <int MP> constexpr int kFactorThreads = MP * MP / 8;
 
 template <int MP>
-__global__ __launch_bounds__(kFactorThreads<MP>) void noise_factor(const double2 *__restrict__ K,
-                                                                    double2 *__restrict__ Kinv,
-                                                                    int32_t *__restrict__ status,
-                                                                    int M)
+__device__ __forceinline__ void noise_factor_bin(const double2 *__restrict__ Kf,
+                                                 double2 *__restrict__ Wf,
+                                                 int32_t *__restrict__ stf, int M)
 {
     constexpr int RG = MP / 8;                     // row groups: rows of thread t are t / MP + RG u
     __shared__ double2 colb[2][MP], rowb[2][MP];
     __shared__ double diag_s[MP];
     __shared__ double thr_s;
     __shared__ int bad_s;
-    const int f = blockIdx.x;
     const int t = threadIdx.x;
     const int j = t % MP, i0 = t / MP;
-    const double2 *Kf = K + (size_t)f * M * M;
-    double2 *Wf = Kinv + (size_t)f * M * M;
 
     double2 w[8];
 #pragma unroll
@@ -110,7 +106,28 @@ __global__ __launch_bounds__(kFactorThreads<MP>) void noise_factor(const double2
         const int i = i0 + RG * u;
         if (i < M && j < M) Wf[(size_t)i * M + j] = bad ? make_double2(0.0, 0.0) : w[u];
     }
-    if (t == 0) status[f] = bad ? SSL_BIN_NOT_PD : SSL_BIN_OK;
+    if (t == 0) *stf = bad ? SSL_BIN_NOT_PD : SSL_BIN_OK;
+}
+
+template <int MP>
+__global__ __launch_bounds__(kFactorThreads<MP>) void noise_factor(const double2 *__restrict__ K,
+                                                                    double2 *__restrict__ Kinv,
+                                                                    int32_t *__restrict__ status,
+                                                                    int M)
+{
+    const int f = blockIdx.x;
+    noise_factor_bin<MP>(K + (size_t)f * M * M, Kinv + (size_t)f * M * M, status + f, M);
+}
+
+// Item (handle, bin) of a batched noise update.
+template <int MP>
+__global__ __launch_bounds__(kFactorThreads<MP>) void noise_factor_batch(
+    const NoiseUpdDev *__restrict__ h, const int2 *__restrict__ items)
+{
+    const int2 it = items[blockIdx.x];
+    const NoiseUpdDev &H = h[it.x];
+    const int M = H.M, f = it.y;
+    noise_factor_bin<MP>(H.K + (size_t)f * M * M, H.Kinv + (size_t)f * M * M, H.status + f, M);
 }
 
 // K <- alpha K + (1 - alpha) Khat
@@ -120,7 +137,7 @@ __global__ void noise_blend_c128(double2 *__restrict__ K, const double2 *__restr
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
          e += (size_t)gridDim.x * blockDim.x) {
         const double2 a = K[e], b = Kh[e];
-        K[e] = make_double2(alpha * a.x + (1.0 - alpha) * b.x, alpha * a.y + (1.0 - alpha) * b.y);
+        K[e] = make_double2(fma(alpha, a.x, (1.0 - alpha) * b.x), fma(alpha, a.y, (1.0 - alpha) * b.y));
     }
 }
 __global__ void noise_blend_c64(double2 *__restrict__ K, const float2 *__restrict__ Kh,
@@ -130,8 +147,8 @@ __global__ void noise_blend_c64(double2 *__restrict__ K, const float2 *__restric
          e += (size_t)gridDim.x * blockDim.x) {
         const double2 a = K[e];
         const float2 b = Kh[e];
-        K[e] = make_double2(alpha * a.x + (1.0 - alpha) * (double)b.x,
-                            alpha * a.y + (1.0 - alpha) * (double)b.y);
+        K[e] = make_double2(fma(alpha, a.x, (1.0 - alpha) * (double)b.x),
+                            fma(alpha, a.y, (1.0 - alpha) * (double)b.y));
     }
 }
 
@@ -316,6 +333,22 @@ hipError_t launch_noise_factor(ssl_c128 *K, ssl_c128 *Kinv, int32_t *status, int
     else
         hipLaunchKernelGGL(noise_factor<64>, dim3(F), dim3(kFactorThreads<64>), 0, st, Kp, Wp,
                            status, M);
+    return hipGetLastError();
+}
+
+hipError_t launch_noise_factor_batch(const NoiseUpdDev *h, const int2 *items, int n_items,
+                                     int cls, hipStream_t st)
+{
+    if (n_items <= 0) return hipSuccess;
+    if (cls == 16)
+        hipLaunchKernelGGL(noise_factor_batch<16>, dim3(n_items), dim3(kFactorThreads<16>), 0, st,
+                           h, items);
+    else if (cls == 32)
+        hipLaunchKernelGGL(noise_factor_batch<32>, dim3(n_items), dim3(kFactorThreads<32>), 0, st,
+                           h, items);
+    else
+        hipLaunchKernelGGL(noise_factor_batch<64>, dim3(n_items), dim3(kFactorThreads<64>), 0, st,
+                           h, items);
     return hipGetLastError();
 }
 

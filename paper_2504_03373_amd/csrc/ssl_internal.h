@@ -86,6 +86,15 @@ struct BlockDev {
     float *peak_val, *Pbar;
 };
 
+// Device view of one noise-handle update of ssl_noise_update_frames: the handle's noise-only
+// frames [F][T][M] (contiguous), its K, K^{-1} and per-bin status.
+struct NoiseUpdDev {
+    const float2 *X;
+    int F, T, M;
+    double2 *K, *Kinv;
+    int32_t *status;
+};
+
 // Size classes shared by the single-block and batched launches, so that a bin is computed by the
 // same kernel variant whichever entry point schedules it.
 inline int corr_class(int M) { return M <= 16 ? 16 : M <= 32 ? 32 : M <= 48 ? 48 : 64; }
@@ -132,6 +141,14 @@ hipError_t launch_noise_blend(ssl_c128 *K, const void *Khat, ssl_prec kprec, dou
                               int F, int M, hipStream_t st);
 hipError_t launch_whiten(const ssl_c128 *Kinv, const ssl_c64 *R, ssl_c64 *A, int F, int M,
                          hipStream_t st);
+// Batched EMA noise update, items (handle, bin) of one size class (16 / 32 / 64 channels):
+// K <- alpha K + (1 - alpha) (1/T) sum_t x x^H (FP64 MFMA correlation, blend fused), then the
+// Gauss-Jordan inverse of the updated K.  Both launches read the same items.
+hipError_t launch_noise_corr_blend(const NoiseUpdDev *h, const int2 *items, int n_items, int cls,
+                                   double alpha, hipStream_t st);
+hipError_t launch_noise_factor_batch(const NoiseUpdDev *h, const int2 *items, int n_items,
+                                     int cls, hipStream_t st);
+inline int noise_class(int M) { return M <= 16 ? 16 : M <= 32 ? 32 : 64; }
 // A is library workspace and is overwritten (it parks the QR reflectors between phases).
 // lanes = lanes per column pair of the Jacobi variant (jacobi_variant_ok).
 hipError_t launch_jacobi(ssl_c64 *A, const int32_t *kstatus, int F, int M, int Ns,

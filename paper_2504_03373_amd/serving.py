@@ -65,6 +65,7 @@ class Server:
         done: List[Request] = []
         batches = 0
         max_ready = 0
+        host = dict(submit_s=0.0, collect_s=0.0, sleep_s=0.0)   # where the loop's time goes
         t0 = self.clock()
         while pending or n_ready or any(lanes):
             now = self.clock() - t0
@@ -76,7 +77,9 @@ class Server:
             progressed = False
             for li, reqs in enumerate(lanes):
                 if reqs and self.ex.poll(li):
+                    tc = self.clock()
                     self.ex.collect(li)
+                    host["collect_s"] += self.clock() - tc
                     tdone = self.clock() - t0
                     for r in reqs:
                         r.done_t = tdone
@@ -113,13 +116,18 @@ class Server:
                     r.submit_t = tsub
                     r.batch = batches
                 self.ex.submit(li, batch)
+                host["submit_s"] += self.clock() - t0 - tsub
                 lanes[li] = batch
                 batches += 1
                 progressed = True
             if not progressed:
                 nxt = pending[0].emit_t - (self.clock() - t0) if pending else self.poll_s
+                ts = self.clock()
                 self.sleep(max(0.0, min(self.poll_s, nxt)))
-        return summarize(done, batches, max_ready)
+                host["sleep_s"] += self.clock() - ts
+        out = summarize(done, batches, max_ready)
+        out.update(host, loop_s=self.clock() - t0)
+        return out
 
 
 def summarize(done: List[Request], batches: int, max_ready: int) -> dict:
@@ -258,16 +266,14 @@ class GpuExecutor:
             ns = self.streams[r.stream].Ns
             r.peaks = pk[i, :ns].copy()
             r.peak_val = pv[i, :ns].copy()
-        # K EMA updates of this batch's streams, after the batch (which read the old K): split
-        # over the noise streams, one library call each, so that a stream's next block waits for
-        # a short chain of updates only
+        # K EMA updates of this batch's streams, after the batch (which read the old K): one
+        # library call (all their bins in one launch pair per channel class) on the next noise
+        # stream
         ups = [r for r in reqs if (r.seq + 1) % self.k_every == 0]
-        nq = len(self.nstreams)
-        per = -(-len(ups) // nq) if ups else 0
-        for c0 in range(0, len(ups), max(per, 1)):
-            part = ups[c0:c0 + per]
+        if ups:
+            part = ups
             i = self.next_ns
-            self.next_ns = (i + 1) % nq
+            self.next_ns = (i + 1) % len(self.nstreams)
             ns = self.nstreams[i]
             with torch.cuda.stream(ns):
                 ns.wait_event(ev)                 # after the batch that read the old K
