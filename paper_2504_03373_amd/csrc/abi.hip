@@ -7,7 +7,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <new>
+#include <tuple>
 
 #include "ssl_internal.h"
 
@@ -1204,11 +1206,12 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
         int *hcb = reinterpret_cast<int *>(hl + 4 * n_items + 2 * nblocks) + nblocks;
         std::vector<int> first;
         std::vector<std::vector<int>> members;
+        std::map<std::tuple<int, const void *>, int> group_of;
         for (int b = 0; b < nblocks; ++b) {
-            int g = 0;
-            for (; g < (int)first.size(); ++g)
-                if (c_wh[first[g]] == c_wh[b] && hb[first[g]].Kinv == hb[b].Kinv) break;
-            if (g == (int)first.size()) {
+            const auto ins = group_of.emplace(std::make_tuple(c_wh[b], (const void *)hb[b].Kinv),
+                                              (int)first.size());
+            const int g = ins.first->second;
+            if (ins.second) {
                 first.push_back(b);
                 members.emplace_back();
             }
@@ -1254,15 +1257,13 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
         int *hgb = reinterpret_cast<int *>(hg + 2 * nblocks);
         std::vector<int> first;                       // first block of each group
         std::vector<std::vector<int>> members;
+        std::map<std::tuple<int, const void *, int, int, int>, int> group_of;
         for (int b = 0; b < nblocks; ++b) {
-            int g = 0;
-            for (; g < (int)first.size(); ++g) {
-                const BlockDev &A = hb[first[g]], &B = hb[b];
-                if (c_st[first[g]] == c_st[b] && A.H == B.H && A.F == B.F && A.D == B.D &&
-                    A.M == B.M)
-                    break;
-            }
-            if (g == (int)first.size()) {
+            const BlockDev &B = hb[b];
+            const auto ins = group_of.emplace(std::make_tuple(c_st[b], B.H, B.F, B.D, B.M),
+                                              (int)first.size());
+            const int g = ins.first->second;
+            if (ins.second) {
                 first.push_back(b);
                 members.emplace_back();
             }
@@ -1356,6 +1357,7 @@ ssl_status ssl_noise_update_frames(ssl_ctx ctx, int n, const ssl_noise *handles,
     // a handle listed r times is updated in rounds 0 .. r - 1 (in list order); the handles of one
     // round are distinct, so each round is one batched launch pair per size class
     std::vector<int> round(n);
+    std::map<ssl_noise, int> seen;
     int n_rounds = 0;
     int64_t n_items = 0;
     for (int i = 0; i < n; ++i) {
@@ -1377,8 +1379,7 @@ ssl_status ssl_noise_update_frames(ssl_ctx ctx, int n, const ssl_noise *handles,
             ssl_set_error("entry %d: T = %d must be >= 1", i, T[i]);
             return SSL_ERR_ARG;
         }
-        int r = 0;
-        for (int k = 0; k < i; ++k) r += handles[k] == h;
+        const int r = seen[h]++;
         round[i] = r;
         n_rounds = std::max(n_rounds, r + 1);
         n_items += h->F;

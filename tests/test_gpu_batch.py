@@ -178,3 +178,23 @@ def test_batch_argument_errors(env):
     assert e.value.code == S.SSL_ERR_ARG and "block 0" in str(e.value)
     with pytest.raises(S.SSLError):
         S.ssl_localize_batch(ctx, [], S.SSL_FP32, 2)
+
+
+def test_batch_mixed_frame_counts(env):
+    """Blocks of one size class with different T (one frame chunk, two chunks, a strided view) in
+    one batch: each bin's first frame chunk is loaded under the previous bin's products, whatever
+    the previous block's T; results bit-identical to single calls."""
+    import torch
+    S, ctx, blocks = env
+    b60 = [b for b in blocks if b["M"] == 60][:2]
+    X0, X1 = b60[0]["Xd"], b60[1]["Xd"]
+    variants = [X0[:, :20].contiguous(),                 # T = 20
+                torch.cat([X0, X1], dim=1).contiguous(),  # T = 100: two 64-frame chunks
+                X1,                                       # T = 50
+                torch.cat([X1, X0], dim=1)[:, ::2],       # T = 50, frame stride 2M
+                X0[:, :1].contiguous()]                   # T = 1
+    mixed = [dict(b60[i % 2], Xd=v) for i, v in enumerate(variants)]
+    say("ssl_localize_batch, one class, T = 20 / 100 / 50 / 50 (strided) / 1")
+    ref = run_single(S, ctx, mixed)
+    assert same(run_batch(S, ctx, mixed, outputs(mixed)), ref)
+    assert same(run_batch(S, ctx, mixed[::-1], outputs(mixed[::-1])), ref[::-1])
