@@ -377,11 +377,13 @@ __device__ __forceinline__ void corr_f64_bin(const float2 *__restrict__ Xf, int 
     }
     for (int t0 = 0; t0 < T; t0 += kChunk) {
         const int nf = min(kChunk, T - t0);
+        float2 v[kChunkRegs<MP>];
+        load_chunk<MP>(Xf, t0, nf, M, sT, tid, v);               // every load in flight
         __syncthreads();
-        for (int e = tid; e < kChunk * MP; e += kThreads) {     // frame e / MP, channel e % MP
-            const int tt = e / MP, m = e % MP;
-            Z[tt * S + m] = (tt < nf && m < M) ? Xf[(size_t)(t0 + tt) * sT + m]
-                                               : make_float2(0.f, 0.f);
+#pragma unroll
+        for (int u = 0; u < kChunkRegs<MP>; ++u) {               // frame e / MP, channel e % MP
+            const int e = tid + u * kThreads;
+            Z[(e / MP) * S + e % MP] = v[u];
         }
         __syncthreads();
         const int nsteps = (nf + 3) >> 2;

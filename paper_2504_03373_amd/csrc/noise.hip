@@ -44,9 +44,13 @@ __device__ __forceinline__ void noise_factor_bin(const double2 *__restrict__ Kf,
 
     double2 w[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 8; ++u) {                      // every load in flight first
         const int i = i0 + RG * u;
         w[u] = (i < M && j < M) ? Kf[(size_t)i * M + j] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int i = i0 + RG * u;
         if (i == j) diag_s[i] = w[u].x;
         if (j == 0) colb[0][i] = w[u];
         if (i == 0) rowb[0][j] = w[u];
@@ -75,20 +79,22 @@ __device__ __forceinline__ void noise_factor_bin(const double2 *__restrict__ Kf,
         }
         const double ip = 1.0 / p;
         const double2 wkj = rowb[b][j];
+        double2 wik[8];                                // every pivot-column read in flight first
+#pragma unroll
+        for (int u = 0; u < 8; ++u) wik[u] = colb[b][i0 + RG * u];
+        // row i is the same for every lane of a wave (uniform branch); column j == k is one lane
+        // (a select).  Padding rows and columns hold zeros and stay zero: their w_kj / w_ik are 0.
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int i = i0 + RG * u;
-            if (i >= M || j >= M) continue;
-            if (i == k && j == k) {
-                w[u] = make_double2(ip, 0.0);
-            } else if (i == k) {
-                w[u] = make_double2(w[u].x * ip, w[u].y * ip);
-            } else if (j == k) {
-                w[u] = make_double2(-w[u].x * ip, -w[u].y * ip);
+            if (i == k) {
+                const double2 row = make_double2(w[u].x * ip, w[u].y * ip);
+                w[u] = (j == k) ? make_double2(ip, 0.0) : row;
             } else {
-                const double2 tt = cmul(colb[b][i], wkj);
-                w[u].x = fma(-tt.x, ip, w[u].x);
-                w[u].y = fma(-tt.y, ip, w[u].y);
+                const double2 tt = cmul(wik[u], wkj);
+                const double2 gen = make_double2(fma(-tt.x, ip, w[u].x), fma(-tt.y, ip, w[u].y));
+                const double2 col = make_double2(-w[u].x * ip, -w[u].y * ip);
+                w[u] = (j == k) ? col : gen;
             }
         }
         if (k + 1 < M) {
