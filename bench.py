@@ -138,7 +138,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20, help="timed batch steps")
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--batch", type=int, default=32, help="blocks per step")
+    ap.add_argument("--batch", type=int, default=128, help="blocks per step")
     ap.add_argument("--prec", choices=["fp32", "bf16", "fp16"], default="bf16",
                     help="MFMA input type of the headline path")
     ap.add_argument("--no-fp32-compare", action="store_true",
