@@ -13,8 +13,9 @@ sequence exact); a lane's batch never needs more than its share of the HBM budge
 in arrival order, skipping only blocks of streams that are still in flight (kept as one FIFO per
 stream, so forming a batch costs O(streams), not O(queue)).
 
-The executor interface (`lanes`, `cost_bytes`, `submit`, `poll`, `collect`) is what the scheduler
-needs; `GpuExecutor` implements it with the library's C ABI.
+The executor interface (`lanes`, `cost_bytes`, `submit`, `poll`, `collect`, and optionally
+`arrive`, told of each block as it is emitted) is what the scheduler needs; `GpuExecutor`
+implements it with the library's C ABI.
 """
 from __future__ import annotations
 
@@ -66,6 +67,7 @@ class Server:
         batches = 0
         max_ready = 0
         host = dict(submit_s=0.0, collect_s=0.0, sleep_s=0.0)   # where the loop's time goes
+        arrive = getattr(self.ex, "arrive", None)
         t0 = self.clock()
         while pending or n_ready or any(lanes):
             now = self.clock() - t0
@@ -73,6 +75,8 @@ class Server:
                 r = pending.popleft()
                 queues[r.stream].append(r)
                 n_ready += 1
+                if arrive is not None:
+                    arrive(r)
             max_ready = max(max_ready, n_ready)
             progressed = False
             for li, reqs in enumerate(lanes):
@@ -150,11 +154,18 @@ class GpuExecutor:
     and block(seq) -> (X, noise-only frames); `pool` blocks per stream are generated up front and
     reused cyclically (block seq uses pool entry seq % pool).  `configure`, if given, is called
     with each batch context after creation (to apply tuned kernel variants).
+
+    Input staging: each stream owns `slots` device slots (frames X and noise-only frames).  A
+    block is uploaded from pinned host memory on a copy stream as soon as it is emitted and a slot
+    is free, so uploads overlap the batches on the device; a batch then only waits for its blocks'
+    copy events.  A slot frees when its block's K update (or, without one, its batch) has run; a
+    block still unstaged when its batch is formed is uploaded on the lane stream.
     """
 
     def __init__(self, streams, steering, prec=None, p: int = 2, alpha: float = 0.95,
                  k_update_every: int = 1, hbm_budget_bytes: int = 4 << 30, lanes: int = 2,
-                 pool: int = 4, device: int = 0, noise_streams: int = 4, configure=None):
+                 pool: int = 4, device: int = 0, noise_streams: int = 4, configure=None,
+                 slots: int = 3):
         import torch
 
         from . import (SSL_FP32, SSL_FP64, block_desc, ssl_corr_accum, ssl_ctx_create,
@@ -206,9 +217,20 @@ class GpuExecutor:
                 xns.append(torch.from_numpy(Xn).pin_memory())
             self.X_pool.append(xs)
             self.Xn_pool.append(xns)
-            self.X_slot.append(torch.empty((s.F, s.T, s.M), dtype=torch.complex64, device=self.dev))
-            self.Xn_slot.append(torch.empty((s.F, s.T, s.M), dtype=torch.complex64, device=self.dev))
+            self.X_slot.append([torch.empty((s.F, s.T, s.M), dtype=torch.complex64, device=self.dev)
+                                for _ in range(slots)])
+            self.Xn_slot.append([torch.empty((s.F, s.T, s.M), dtype=torch.complex64, device=self.dev)
+                                 for _ in range(slots)])
         torch.cuda.synchronize()
+        # staging state per stream: slot owners (request staged into it, until collected), the
+        # event after which a released slot may be overwritten, blocks waiting for a slot
+        self.cstream = torch.cuda.Stream(device=self.dev)
+        self.nslot = slots
+        self.slot_owner = [[None] * slots for _ in self.streams]
+        self.slot_free = [[None] * slots for _ in self.streams]
+        self.waiting = [collections.deque() for _ in self.streams]
+        self.to_pump = set()
+        self.staged = {}                     # (stream, seq) -> (slot, copy event)
         nmax = 4096
         self.pk = [torch.zeros((nmax, 3), dtype=torch.int32, device=self.dev) for _ in range(lanes)]
         self.pv = [torch.zeros((nmax, 3), dtype=torch.float32, device=self.dev) for _ in range(lanes)]
@@ -226,6 +248,43 @@ class GpuExecutor:
               + a(F * 4) + a(D * 4))
         return ws + 2 * F * s.T * M * 8
 
+    def _stage(self, r: "Request", k: int, st) -> None:
+        """Upload block r into slot k of its stream on HIP stream st."""
+        torch = self.torch
+        sid = r.stream
+        self.slot_owner[sid][k] = r
+        with torch.cuda.stream(st):
+            if self.slot_free[sid][k] is not None:
+                st.wait_event(self.slot_free[sid][k])
+            self.slot_free[sid][k] = None
+            self.X_slot[sid][k].copy_(self.X_pool[sid][r.seq % self.pool], non_blocking=True)
+            self.Xn_slot[sid][k].copy_(self.Xn_pool[sid][r.seq % self.pool], non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        self.staged[(sid, r.seq)] = (k, ev)
+
+    def _free_slot(self, sid: int, ready_only: bool):
+        for k in range(self.nslot):
+            if self.slot_owner[sid][k] is None:
+                ev = self.slot_free[sid][k]
+                if not ready_only or ev is None or ev.query():
+                    return k
+        return None
+
+    def _pump(self, sid: int) -> None:
+        q = self.waiting[sid]
+        while q:
+            k = self._free_slot(sid, ready_only=True)
+            if k is None:
+                self.to_pump.add(sid)
+                return
+            self._stage(q.popleft(), k, self.cstream)
+        self.to_pump.discard(sid)
+
+    def arrive(self, r: "Request") -> None:
+        self.waiting[r.stream].append(r)
+        self._pump(r.stream)
+
     def submit(self, lane: int, reqs: List["Request"]) -> None:
         from . import ssl_localize_batch
         torch = self.torch
@@ -234,16 +293,26 @@ class GpuExecutor:
         with torch.cuda.stream(st):
             waited = set()
             for r in reqs:
+                if (r.stream, r.seq) not in self.staged:
+                    # not uploaded yet (no slot was free, or the scheduler was not told): it is the
+                    # oldest block of its stream not yet run, so every slot is released
+                    q = self.waiting[r.stream]
+                    if q and q[0] is r:
+                        q.popleft()
+                    k = self._free_slot(r.stream, ready_only=True)
+                    self._stage(r, self._free_slot(r.stream, ready_only=False) if k is None else k, st)
+                k, cev = self.staged[(r.stream, r.seq)]
+                st.wait_event(cev)
                 ev = self.k_event[r.stream]
                 if ev is not None and id(ev) not in waited:
                     st.wait_event(ev)
                     waited.add(id(ev))
             for i, r in enumerate(reqs):
                 s = self.streams[r.stream]
-                self.X_slot[r.stream].copy_(self.X_pool[r.stream][r.seq % self.pool], non_blocking=True)
-                descs.append(self._block_desc(self.X_slot[r.stream], self.noise[r.stream], self.H[s.M],
-                                              s.grid.n_az, s.grid.n_el, s.Ns, self.pk[lane][i],
-                                              self.pv[lane][i]))
+                k = self.staged[(r.stream, r.seq)][0]
+                descs.append(self._block_desc(self.X_slot[r.stream][k], self.noise[r.stream],
+                                              self.H[s.M], s.grid.n_az, s.grid.n_el, s.Ns,
+                                              self.pk[lane][i], self.pv[lane][i]))
                 r.k_version = self.k_version[r.stream]
             ssl_localize_batch(self.ctxs[lane], descs, self.prec, self.p, stream=st)
             n = len(reqs)
@@ -254,6 +323,8 @@ class GpuExecutor:
         self.inflight[lane] = (reqs, ev)
 
     def poll(self, lane: int) -> bool:
+        for sid in list(self.to_pump):
+            self._pump(sid)
         return self.inflight[lane][1].query()
 
     def collect(self, lane: int) -> None:
@@ -270,6 +341,8 @@ class GpuExecutor:
         # library call (all their bins in one launch pair per channel class) on the next noise
         # stream
         ups = [r for r in reqs if (r.seq + 1) % self.k_every == 0]
+        slot = {r.stream: self.staged.pop((r.stream, r.seq))[0] for r in reqs}
+        done = None
         if ups:
             part = ups
             i = self.next_ns
@@ -277,17 +350,21 @@ class GpuExecutor:
             ns = self.nstreams[i]
             with torch.cuda.stream(ns):
                 ns.wait_event(ev)                 # after the batch that read the old K
-                for r in part:
-                    self.Xn_slot[r.stream].copy_(self.Xn_pool[r.stream][r.seq % self.pool],
-                                                 non_blocking=True)
                 ssl_noise_update_frames(self.uctx[i], [self.noise[r.stream] for r in part],
-                                        [self.Xn_slot[r.stream] for r in part], self.alpha,
-                                        stream=ns)
+                                        [self.Xn_slot[r.stream][slot[r.stream]] for r in part],
+                                        self.alpha, stream=ns)
                 done = torch.cuda.Event()
                 done.record(ns)
             for r in part:
                 self.k_event[r.stream] = done
                 self.k_version[r.stream] += 1
+        upd = {r.stream for r in ups}
+        for r in reqs:                            # release the slots, reusable after their readers
+            k = slot[r.stream]
+            self.slot_owner[r.stream][k] = None
+            self.slot_free[r.stream][k] = done if r.stream in upd else ev
+            if self.waiting[r.stream]:
+                self.to_pump.add(r.stream)
         self.inflight[lane] = None
 
     def close(self) -> None:
