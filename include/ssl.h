@@ -135,6 +135,19 @@ ssl_status ssl_noise_update(ssl_noise K, const void *Khat, ssl_prec kprec, doubl
 ssl_status ssl_noise_update_frames(ssl_ctx ctx, int n, const ssl_noise *handles,
                                    const ssl_c64 *const *Xn, const int *T, double alpha,
                                    void *stream);
+/* ssl_noise_update_frames with a separate source per entry: for each i < n,
+ *   dst[i].K <- alpha * src[i].K + (1 - alpha) * (1/T[i]) sum_t x_t x_t^H   (frames Xn[i]),
+ * then dst[i]'s FP64 inverse and per-bin status are recomputed from the new K; src[i] is only
+ * read (src[i] == dst[i] is the in-place update, bit-identical to ssl_noise_update_frames).  It
+ * lets a stream keep two handles and blend into the one no batch is reading, so the update of
+ * block n can run beside block n + 1 (which reads the other handle).  src[i] must be set (or be
+ * the destination of an earlier entry) and have dst[i]'s F and M; dst[i] need not be set before.  Entries take effect in list order (an entry
+ * that reads or writes a matrix an earlier entry writes, or writes one it reads, runs after it).
+ * Errors (SSL_ERR_ARG / SSL_ERR_STATE, nothing launched): NULL arrays or entries, a source never
+ * set, mismatched shapes or devices, T < 1, alpha outside [0, 1]. */
+ssl_status ssl_noise_update_frames_from(ssl_ctx ctx, int n, const ssl_noise *dst,
+                                        const ssl_noise *src, const ssl_c64 *const *Xn,
+                                        const int *T, double alpha, void *stream);
 /* Copies the current K (complex128 [F][M][M]) to K_out (device) for checkpointing. */
 ssl_status ssl_noise_get(ssl_noise K, ssl_c128 *K_out, void *stream);
 void ssl_noise_destroy(ssl_noise K);

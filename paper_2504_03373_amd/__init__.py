@@ -29,6 +29,7 @@ EXPORTED = [
     "ssl_ctx_set_jacobi_lanes", "ssl_ctx_get_jacobi_lanes", "ssl_autotune_jacobi",
     "ssl_ctx_set_steer_waves", "ssl_ctx_get_steer_waves", "ssl_autotune_steer",
     "ssl_noise_update_frames",
+    "ssl_noise_update_frames_from",
 ]
 
 
@@ -87,6 +88,9 @@ def lib() -> ctypes.CDLL:
         "ssl_ctx_set_steer_waves": (I, [P, I, I, I, I]),
         "ssl_noise_update_frames": (I, [P, I, ctypes.POINTER(P), ctypes.POINTER(P),
                                         ctypes.POINTER(I), ctypes.c_double, P]),
+        "ssl_noise_update_frames_from": (I, [P, I, ctypes.POINTER(P), ctypes.POINTER(P),
+                                             ctypes.POINTER(P), ctypes.POINTER(I),
+                                             ctypes.c_double, P]),
         "ssl_ctx_get_steer_waves": (I, [P, I, I, I]),
         "ssl_autotune_steer": (I, [P, P, I, P, I, I, I, I, I, I, I, ctypes.POINTER(I),
                                    ctypes.POINTER(ctypes.c_double), P]),
@@ -183,20 +187,37 @@ def ssl_noise_update(noise, Khat, kprec, alpha, bin_status=None, stream=None):
                                                       _ptr(bin_status), _stream(stream)))
 
 
-def ssl_noise_update_frames(ctx, noises, Xns, alpha, stream=None):
-    """Serving EMA update of many handles from their noise-only frames (each [F][T][M] complex64,
-    contiguous, on the device), one library call."""
-    n = len(noises)
+def _frames_args(Xns, n):
     if len(Xns) != n:
         raise ValueError("one frame tensor per noise handle")
     for X in Xns:
         if not X.is_contiguous():
             raise ValueError("noise frames must be contiguous")
-    hs = (ctypes.c_void_p * max(n, 1))(*noises)
     xs = (ctypes.c_void_p * max(n, 1))(*[X.data_ptr() for X in Xns])
     ts = (ctypes.c_int * max(n, 1))(*[int(X.shape[1]) for X in Xns])
+    return xs, ts
+
+
+def ssl_noise_update_frames(ctx, noises, Xns, alpha, stream=None):
+    """Serving EMA update of many handles from their noise-only frames (each [F][T][M] complex64,
+    contiguous, on the device), one library call."""
+    n = len(noises)
+    xs, ts = _frames_args(Xns, n)
+    hs = (ctypes.c_void_p * max(n, 1))(*noises)
     _check("ssl_noise_update_frames", lib().ssl_noise_update_frames(ctx, n, hs, xs, ts, float(alpha),
                                                                     _stream(stream)))
+
+
+def ssl_noise_update_frames_from(ctx, dst, src, Xns, alpha, stream=None):
+    """As ssl_noise_update_frames, blending from src[i]'s K into dst[i]."""
+    n = len(dst)
+    if len(src) != n:
+        raise ValueError("one source handle per destination")
+    xs, ts = _frames_args(Xns, n)
+    hd = (ctypes.c_void_p * max(n, 1))(*dst)
+    hs = (ctypes.c_void_p * max(n, 1))(*src)
+    _check("ssl_noise_update_frames_from",
+           lib().ssl_noise_update_frames_from(ctx, n, hd, hs, xs, ts, float(alpha), _stream(stream)))
 
 
 def ssl_noise_get(noise, K_out, stream=None):

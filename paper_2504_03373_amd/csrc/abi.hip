@@ -1342,45 +1342,58 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
     return e == hipSuccess ? SSL_OK : hip_fail(e, "hipGraphLaunch");
 }
 
-ssl_status ssl_noise_update_frames(ssl_ctx ctx, int n, const ssl_noise *handles,
-                                   const ssl_c64 *const *Xn, const int *T, double alpha,
-                                   void *stream)
+ssl_status ssl_noise_update_frames_from(ssl_ctx ctx, int n, const ssl_noise *dst,
+                                        const ssl_noise *src, const ssl_c64 *const *Xn,
+                                        const int *T, double alpha, void *stream)
 {
-    if (!ctx || n < 0 || (n > 0 && (!handles || !Xn || !T))) {
-        ssl_set_error("ctx, handles, Xn or T is NULL (or n < 0)");
+    if (!ctx || n < 0 || (n > 0 && (!dst || !src || !Xn || !T))) {
+        ssl_set_error("ctx, dst, src, Xn or T is NULL (or n < 0)");
         return SSL_ERR_ARG;
     }
     if (!(alpha >= 0.0 && alpha <= 1.0)) {
         ssl_set_error("alpha = %g must lie in [0, 1]", alpha);
         return SSL_ERR_ARG;
     }
-    // a handle listed r times is updated in rounds 0 .. r - 1 (in list order); the handles of one
-    // round are distinct, so each round is one batched launch pair per size class
+    // entries run in list order: entry i goes to the round after the last one that wrote its
+    // source or its destination, or read its destination; the entries of one round touch
+    // disjoint matrices (apart from an update in place), so each round is one batched launch pair
+    // per size class
     std::vector<int> round(n);
-    std::map<ssl_noise, int> seen;
+    std::map<ssl_noise, int> last_w, last_r;
+    auto last = [](const std::map<ssl_noise, int> &m, ssl_noise h) {
+        auto it = m.find(h);
+        return it == m.end() ? -1 : it->second;
+    };
     int n_rounds = 0;
     int64_t n_items = 0;
     for (int i = 0; i < n; ++i) {
-        const ssl_noise h = handles[i];
-        if (!h || !Xn[i]) {
+        const ssl_noise h = dst[i], hs = src[i];
+        if (!h || !hs || !Xn[i]) {
             ssl_set_error("entry %d: noise handle or frames are NULL", i);
             return SSL_ERR_ARG;
         }
-        if (!h->is_set) {
-            ssl_set_error("entry %d: noise handle was never set", i);
+        if (!hs->is_set && !last_w.count(hs)) {          // nor written by an earlier entry
+            ssl_set_error("entry %d: source noise handle was never set", i);
             return SSL_ERR_STATE;
         }
-        if (h->ctx->device != ctx->device) {
-            ssl_set_error("entry %d: noise handle lives on device %d, ctx on %d", i,
-                          h->ctx->device, ctx->device);
+        if (h->ctx->device != ctx->device || hs->ctx->device != ctx->device) {
+            ssl_set_error("entry %d: noise handles live on devices %d / %d, ctx on %d", i,
+                          h->ctx->device, hs->ctx->device, ctx->device);
+            return SSL_ERR_ARG;
+        }
+        if (hs->F != h->F || hs->M != h->M) {
+            ssl_set_error("entry %d: source handle is %d x %d x %d, destination %d x %d x %d", i,
+                          hs->F, hs->M, hs->M, h->F, h->M, h->M);
             return SSL_ERR_ARG;
         }
         if (T[i] < 1) {
             ssl_set_error("entry %d: T = %d must be >= 1", i, T[i]);
             return SSL_ERR_ARG;
         }
-        const int r = seen[h]++;
+        const int r = 1 + std::max({last(last_w, hs), last(last_w, h), last(last_r, h)});
         round[i] = r;
+        last_w[h] = r;
+        last_r[hs] = std::max(last(last_r, hs), r);
         n_rounds = std::max(n_rounds, r + 1);
         n_items += h->F;
     }
@@ -1401,8 +1414,9 @@ ssl_status ssl_noise_update_frames(ssl_ctx ctx, int n, const ssl_noise *handles,
     NoiseUpdDev *hd = static_cast<NoiseUpdDev *>(ctx->bdesc_host);
     int2 *hi = reinterpret_cast<int2 *>(static_cast<char *>(ctx->bdesc_host) + desc_bytes);
     for (int i = 0; i < n; ++i) {
-        const ssl_noise h = handles[i];
+        const ssl_noise h = dst[i];
         hd[i] = NoiseUpdDev{reinterpret_cast<const float2 *>(Xn[i]), h->F, T[i], h->M,
+                            reinterpret_cast<const double2 *>(src[i]->K),
                             reinterpret_cast<double2 *>(h->K), reinterpret_cast<double2 *>(h->Kinv),
                             h->status};
     }
@@ -1415,8 +1429,8 @@ ssl_status ssl_noise_update_frames(ssl_ctx ctx, int n, const ssl_noise *handles,
         for (int c : {16, 32, 64}) {
             Seg sg{c, pos, 0};
             for (int i = 0; i < n; ++i)
-                if (round[i] == r && noise_class(handles[i]->M) == c)
-                    for (int f = 0; f < handles[i]->F; ++f) hi[pos++] = make_int2(i, f);
+                if (round[i] == r && noise_class(dst[i]->M) == c)
+                    for (int f = 0; f < dst[i]->F; ++f) hi[pos++] = make_int2(i, f);
             sg.count = pos - sg.start;
             if (sg.count) segs[r].push_back(sg);
         }
@@ -1440,7 +1454,15 @@ ssl_status ssl_noise_update_frames(ssl_ctx ctx, int n, const ssl_noise *handles,
             if (e != hipSuccess) return hip_fail(e, "noise factor launch");
         }
     }
+    for (int i = 0; i < n; ++i) dst[i]->is_set = true;
     return SSL_OK;
+}
+
+ssl_status ssl_noise_update_frames(ssl_ctx ctx, int n, const ssl_noise *handles,
+                                   const ssl_c64 *const *Xn, const int *T, double alpha,
+                                   void *stream)
+{
+    return ssl_noise_update_frames_from(ctx, n, handles, handles, Xn, T, alpha, stream);
 }
 
 }  // extern "C"

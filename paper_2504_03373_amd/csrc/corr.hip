@@ -350,14 +350,15 @@ int resident_grid(K kernel, int n)
 // lane l is row l/16 + 4e, column l%16 of the tile.
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-// mode 0: R = scale S;  1: R += scale S;  2: R = alpha R + (1 - alpha) (scale S), S = sum_t x x^H
-// (the blend of the EMA noise update, in the same arithmetic as noise_blend_c128).
+// mode 0: R = scale S;  1: R = R0 + scale S;  2: R = alpha R0 + (1 - alpha) (scale S),
+// S = sum_t x x^H (the blend of the EMA noise update, in the same arithmetic as
+// noise_blend_c128).  R0 is read from R0f: Rf itself, or another matrix of the same shape.
 constexpr int kStore = 0, kAccumulate = 1, kBlend = 2;
 
 template <int MP>
 __device__ __forceinline__ void corr_f64_bin(const float2 *__restrict__ Xf, int T, int M,
                                              int64_t sT, double scale, int mode, double alpha,
-                                             double2 *__restrict__ Rf)
+                                             const double2 *R0f, double2 *Rf)
 {
     constexpr int NT = MP / 16;
     constexpr int NTILE = NT * (NT + 1) / 2;
@@ -432,11 +433,11 @@ __device__ __forceinline__ void corr_f64_bin(const float2 *__restrict__ Xf, int 
         if (j >= M) continue;
         double2 v = Rs[i * RS + j];
         if (mode == kAccumulate) {
-            const double2 a = Rf[(size_t)i * M + j];
+            const double2 a = R0f[(size_t)i * M + j];
             v.x += a.x;
             v.y += a.y;
         } else if (mode == kBlend) {
-            const double2 a = Rf[(size_t)i * M + j];
+            const double2 a = R0f[(size_t)i * M + j];
             v = make_double2(fma(alpha, a.x, (1.0 - alpha) * v.x),
                              fma(alpha, a.y, (1.0 - alpha) * v.y));
         }
@@ -450,11 +451,12 @@ __global__ __launch_bounds__(kThreads) void corr_f64(const float2 *__restrict__ 
                                                      int accumulate, double2 *__restrict__ R)
 {
     const int f = blockIdx.x;
+    double2 *Rf = R + (size_t)f * M * M;
     corr_f64_bin<MP>(X + (size_t)f * sF, T, M, sT, scale, accumulate ? kAccumulate : kStore, 0.0,
-                     R + (size_t)f * M * M);
+                     Rf, Rf);
 }
 
-// Item (handle, bin): K[f] <- alpha K[f] + (1 - alpha) (1/T) sum_t x x^H of the handle's frames.
+// Item (handle, bin): K[f] <- alpha Ks[f] + (1 - alpha) (1/T) sum_t x x^H of the handle's frames.
 template <int MP>
 __global__ __launch_bounds__(kThreads) void noise_corr_blend(const NoiseUpdDev *__restrict__ h,
                                                              const int2 *__restrict__ items,
@@ -464,7 +466,7 @@ __global__ __launch_bounds__(kThreads) void noise_corr_blend(const NoiseUpdDev *
     const NoiseUpdDev &H = h[it.x];
     const int M = H.M, T = H.T, f = it.y;
     corr_f64_bin<MP>(H.X + (size_t)f * T * M, T, M, M, 1.0 / T, kBlend, alpha,
-                     H.K + (size_t)f * M * M);
+                     H.Ks + (size_t)f * M * M, H.K + (size_t)f * M * M);
 }
 
 template <int MP, typename E>

@@ -86,11 +86,13 @@ struct BlockDev {
     float *peak_val, *Pbar;
 };
 
-// Device view of one noise-handle update of ssl_noise_update_frames: the handle's noise-only
-// frames [F][T][M] (contiguous), its K, K^{-1} and per-bin status.
+// Device view of one noise-handle update of ssl_noise_update_frames(_from): the noise-only
+// frames [F][T][M] (contiguous), the source K read by the blend (Ks; the destination K itself for
+// an update in place), and the destination's K, K^{-1} and per-bin status.
 struct NoiseUpdDev {
     const float2 *X;
     int F, T, M;
+    const double2 *Ks;
     double2 *K, *Kinv;
     int32_t *status;
 };

@@ -6,16 +6,21 @@ lane = a library context + a HIP stream, so a batch can be formed and started wh
 on the device), and records each block's latency from emission to results on the host.  Each
 stream's noise correlation K stays resident on the device and is updated by exponential averaging
 with the noise-only frames that accompany its blocks (K <- alpha K + (1 - alpha) K_hat, then a
-fresh FP64 inverse), the update of block n landing before the stream's block n + 1 runs.
+fresh FP64 inverse).  With a lag of L blocks (k_lag), block n runs on the K that includes the
+noise of blocks <= n - 1 - L: at L = 0 the update of block n lands before block n + 1 runs; at
+L = 1 (the default) it runs beside block n + 1, which reads the stream's other K handle, so the
+update is off the stream's round trip.
 
-Rules: at most one block per stream is in flight (keeps per-stream order and the K update
-sequence exact); a lane's batch never needs more than its share of the HBM budget; requests wait
-in arrival order, skipping only blocks of streams that are still in flight (kept as one FIFO per
-stream, so forming a batch costs O(streams), not O(queue)).
+Rules: at most `stream_depth` blocks per stream are in flight (an executor attribute, 1 if
+absent; the GPU executor allows 1 + k_lag, the most for which the K versions the blocks read are
+never being written), and a stream's blocks are submitted in order; a lane's batch never needs more
+than its share of the HBM budget; requests wait in arrival order, skipping only blocks of streams
+at their in-flight limit (kept as one FIFO per stream, so forming a batch costs O(streams), not
+O(queue)).
 
 The executor interface (`lanes`, `cost_bytes`, `submit`, `poll`, `collect`, and optionally
-`arrive`, told of each block as it is emitted) is what the scheduler needs; `GpuExecutor`
-implements it with the library's C ABI.
+`arrive`, told of each block as it is emitted, and `stream_depth`) is what the scheduler needs;
+`GpuExecutor` implements it with the library's C ABI.
 """
 from __future__ import annotations
 
@@ -54,13 +59,14 @@ class Server:
     def run(self, arrivals: Sequence[tuple]) -> dict:
         """arrivals: (emit time s, stream, seq), sorted by time.  Runs until every block is done."""
         pending = collections.deque(Request(stream=s, seq=q, emit_t=t) for t, s, q in arrivals)
-        # ready blocks, one FIFO per stream: since a stream has at most one block in flight, the
-        # candidates of a batch are the heads of the idle streams, taken in emission order --
-        # the same order as scanning one arrival-ordered queue and skipping busy streams, at a
-        # cost of O(streams) per batch instead of O(queue)
+        # ready blocks, one FIFO per stream: the candidates of a batch are the heads of the
+        # streams below their in-flight limit, taken in emission order -- the same order as
+        # scanning one arrival-ordered queue and skipping streams at the limit, at a cost of
+        # O(streams) per batch instead of O(queue)
         queues = collections.defaultdict(collections.deque)
         n_ready = 0
-        busy_streams = set()
+        depth = max(1, int(getattr(self.ex, "stream_depth", 1)))
+        in_flight = collections.Counter()
         cost_of = {}
         lanes = [None] * self.ex.lanes          # per lane: list of requests in flight
         done: List[Request] = []
@@ -87,14 +93,14 @@ class Server:
                     tdone = self.clock() - t0
                     for r in reqs:
                         r.done_t = tdone
-                        busy_streams.discard(r.stream)
+                        in_flight[r.stream] -= 1
                     done.extend(reqs)
                     lanes[li] = None
                     progressed = True
             for li in range(len(lanes)):
                 if lanes[li] is not None or not n_ready:
                     continue
-                heads = sorted((q[0] for sid, q in queues.items() if q and sid not in busy_streams),
+                heads = sorted((q[0] for sid, q in queues.items() if q and in_flight[sid] < depth),
                                key=lambda r: (r.emit_t, r.stream, r.seq))
                 batch, cost = [], 0
                 for r in heads:
@@ -113,7 +119,7 @@ class Server:
                     break
                 for r in batch:
                     queues[r.stream].popleft()
-                    busy_streams.add(r.stream)
+                    in_flight[r.stream] += 1
                 n_ready -= len(batch)
                 tsub = self.clock() - t0
                 for r in batch:
@@ -165,11 +171,15 @@ class GpuExecutor:
     def __init__(self, streams, steering, prec=None, p: int = 2, alpha: float = 0.95,
                  k_update_every: int = 1, hbm_budget_bytes: int = 4 << 30, lanes: int = 2,
                  pool: int = 4, device: int = 0, noise_streams: int = 4, configure=None,
-                 slots: int = 3):
+                 slots: int = 4, k_lag: int = 1):
         import torch
 
         from . import (SSL_FP32, SSL_FP64, block_desc, ssl_corr_accum, ssl_ctx_create,
                        ssl_noise_create, ssl_noise_set)
+        if k_lag not in (0, 1):
+            raise ValueError("k_lag must be 0 or 1")
+        if slots < 2 + k_lag:
+            raise ValueError("need slots >= 2 + k_lag (blocks in flight plus one staged)")
         self.torch = torch
         self.dev = f"cuda:{device}"
         self.prec = SSL_FP32 if prec is None else prec
@@ -191,15 +201,20 @@ class GpuExecutor:
         self.nctx = ssl_ctx_create(device, 0)
         self.tstreams = [torch.cuda.Stream(device=self.dev) for _ in range(lanes)]
         # K updates go round-robin over a few streams (one update is a few hundred workgroups:
-        # alone it leaves most of the device idle); each array stream remembers the event of its
-        # last update, and a batch waits for those of its own streams only
+        # alone it leaves most of the device idle); a batch waits only for the updates that
+        # produced the K versions its blocks read
         self.nstreams = [torch.cuda.Stream(device=self.dev) for _ in range(max(1, noise_streams))]
         self.next_ns = 0
-        self.k_event = [None] * len(self.streams)
         # steering tables per channel count (shared by streams of the same geometry)
         self.H = {M: t for M, t in steering.items()}
         self.noise, self.X_slot, self.Xn_slot, self.X_pool, self.Xn_pool = [], [], [], [], []
+        # K versions: version v (v updates applied) lives in handle v % 2 of the stream; an
+        # update reads version v and writes v + 1 into the other handle.  k_version = updates
+        # launched, k_done[v % 2] = event completing version v (None: already complete)
+        self.k_lag = k_lag
+        self.stream_depth = 1 + k_lag
         self.k_version = [0] * len(self.streams)
+        self.k_done = [[None, None] for _ in self.streams]
         # one library context per noise stream: an update call keeps K-hat in its context's
         # workspace, and calls on different streams may overlap
         self.uctx = [ssl_ctx_create(device, 0) for _ in self.nstreams]
@@ -207,9 +222,12 @@ class GpuExecutor:
             Xn0 = torch.from_numpy(s.initial_noise_frames()).to(self.dev)
             K0 = torch.zeros((s.F, s.M, s.M), dtype=torch.complex128, device=self.dev)
             ssl_corr_accum(self.nctx, Xn0, 1.0 / Xn0.shape[1], 0, SSL_FP64, K0)
-            n = ssl_noise_create(self.nctx, s.F, s.M)
-            ssl_noise_set(n, K0, SSL_FP64)
-            self.noise.append(n)
+            pair = []
+            for _ in range(2):
+                n = ssl_noise_create(self.nctx, s.F, s.M)
+                ssl_noise_set(n, K0, SSL_FP64)
+                pair.append(n)
+            self.noise.append(pair)
             xs, xns = [], []
             for q in range(pool):
                 X, Xn = s.block(q)
@@ -295,7 +313,8 @@ class GpuExecutor:
             for r in reqs:
                 if (r.stream, r.seq) not in self.staged:
                     # not uploaded yet (no slot was free, or the scheduler was not told): it is the
-                    # oldest block of its stream not yet run, so every slot is released
+                    # oldest block of its stream not yet submitted, so only the stream's blocks in
+                    # flight (fewer than stream_depth <= slots) own slots; the others are released
                     q = self.waiting[r.stream]
                     if q and q[0] is r:
                         q.popleft()
@@ -303,24 +322,59 @@ class GpuExecutor:
                     self._stage(r, self._free_slot(r.stream, ready_only=False) if k is None else k, st)
                 k, cev = self.staged[(r.stream, r.seq)]
                 st.wait_event(cev)
-                ev = self.k_event[r.stream]
+                r.k_version = max(0, self.k_version[r.stream] - self.k_lag)
+                ev = self.k_done[r.stream][r.k_version % 2]
                 if ev is not None and id(ev) not in waited:
                     st.wait_event(ev)
                     waited.add(id(ev))
             for i, r in enumerate(reqs):
                 s = self.streams[r.stream]
                 k = self.staged[(r.stream, r.seq)][0]
-                descs.append(self._block_desc(self.X_slot[r.stream][k], self.noise[r.stream],
+                descs.append(self._block_desc(self.X_slot[r.stream][k],
+                                              self.noise[r.stream][r.k_version % 2],
                                               self.H[s.M], s.grid.n_az, s.grid.n_el, s.Ns,
                                               self.pk[lane][i], self.pv[lane][i]))
-                r.k_version = self.k_version[r.stream]
             ssl_localize_batch(self.ctxs[lane], descs, self.prec, self.p, stream=st)
             n = len(reqs)
             self.pk_h[lane][:n].copy_(self.pk[lane][:n], non_blocking=True)
             self.pv_h[lane][:n].copy_(self.pv[lane][:n], non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(st)
-        self.inflight[lane] = (reqs, ev)
+        self.inflight[lane] = (reqs, ev, self._launch_updates(reqs, ev))
+
+    def _launch_updates(self, reqs: List["Request"], ev):
+        """K EMA updates of the blocks of a batch, queued behind it (the batch may read the handle
+        they write, and it waited for their frames' upload): one library call on the next noise
+        stream, all their bins in one launch pair per channel class.  Returns the completion event
+        (None if no block of the batch updates K)."""
+        from . import ssl_noise_update_frames_from
+        torch = self.torch
+        ups = [r for r in reqs if (r.seq + 1) % self.k_every == 0]
+        if not ups:
+            return None
+        i = self.next_ns
+        self.next_ns = (i + 1) % len(self.nstreams)
+        ns = self.nstreams[i]
+        with torch.cuda.stream(ns):
+            ns.wait_event(ev)
+            waited = set()
+            for r in ups:                         # version v must be complete before v + 1
+                pev = self.k_done[r.stream][self.k_version[r.stream] % 2]
+                if pev is not None and id(pev) not in waited:
+                    ns.wait_event(pev)
+                    waited.add(id(pev))
+            v = [self.k_version[r.stream] for r in ups]
+            ssl_noise_update_frames_from(
+                self.uctx[i], [self.noise[r.stream][(vv + 1) % 2] for r, vv in zip(ups, v)],
+                [self.noise[r.stream][vv % 2] for r, vv in zip(ups, v)],
+                [self.Xn_slot[r.stream][self.staged[(r.stream, r.seq)][0]] for r in ups],
+                self.alpha, stream=ns)
+            done = torch.cuda.Event()
+            done.record(ns)
+        for r in ups:
+            self.k_version[r.stream] += 1
+            self.k_done[r.stream][self.k_version[r.stream] % 2] = done
+        return done
 
     def poll(self, lane: int) -> bool:
         for sid in list(self.to_pump):
@@ -328,41 +382,17 @@ class GpuExecutor:
         return self.inflight[lane][1].query()
 
     def collect(self, lane: int) -> None:
-        from . import ssl_noise_update_frames
-        torch = self.torch
-        reqs, ev = self.inflight[lane]
+        reqs, ev, done = self.inflight[lane]
         ev.synchronize()
         pk, pv = self.pk_h[lane].numpy(), self.pv_h[lane].numpy()
         for i, r in enumerate(reqs):
             ns = self.streams[r.stream].Ns
             r.peaks = pk[i, :ns].copy()
             r.peak_val = pv[i, :ns].copy()
-        # K EMA updates of this batch's streams, after the batch (which read the old K): one
-        # library call (all their bins in one launch pair per channel class) on the next noise
-        # stream
-        ups = [r for r in reqs if (r.seq + 1) % self.k_every == 0]
-        slot = {r.stream: self.staged.pop((r.stream, r.seq))[0] for r in reqs}
-        done = None
-        if ups:
-            part = ups
-            i = self.next_ns
-            self.next_ns = (i + 1) % len(self.nstreams)
-            ns = self.nstreams[i]
-            with torch.cuda.stream(ns):
-                ns.wait_event(ev)                 # after the batch that read the old K
-                ssl_noise_update_frames(self.uctx[i], [self.noise[r.stream] for r in part],
-                                        [self.Xn_slot[r.stream][slot[r.stream]] for r in part],
-                                        self.alpha, stream=ns)
-                done = torch.cuda.Event()
-                done.record(ns)
-            for r in part:
-                self.k_event[r.stream] = done
-                self.k_version[r.stream] += 1
-        upd = {r.stream for r in ups}
         for r in reqs:                            # release the slots, reusable after their readers
-            k = slot[r.stream]
+            k = self.staged.pop((r.stream, r.seq))[0]
             self.slot_owner[r.stream][k] = None
-            self.slot_free[r.stream][k] = done if r.stream in upd else ev
+            self.slot_free[r.stream][k] = done if (r.seq + 1) % self.k_every == 0 else ev
             if self.waiting[r.stream]:
                 self.to_pump.add(r.stream)
         self.inflight[lane] = None
@@ -370,8 +400,9 @@ class GpuExecutor:
     def close(self) -> None:
         from . import ssl_ctx_destroy, ssl_noise_destroy
         self.torch.cuda.synchronize()
-        for n in self.noise:
-            ssl_noise_destroy(n)
+        for pair in self.noise:
+            for n in pair:
+                ssl_noise_destroy(n)
         for c in self.ctxs + self.uctx:
             ssl_ctx_destroy(c)
         ssl_ctx_destroy(self.nctx)

@@ -88,3 +88,59 @@ def test_update_frames_matches_two_call_form(S):
         S.ssl_noise_destroy(h)
     S.ssl_ctx_destroy(uctx)
     S.ssl_ctx_destroy(ctx)
+
+
+def test_update_frames_from_ping_pong(S):
+    """Blending from a source handle into another: the chain A -> B -> A equals the in-place chain
+    on C, the source stays untouched, and both entries in one call run in list order."""
+    import torch
+    rng = np.random.default_rng(4321)
+    F, T, M = 7, 50, 60
+    ctx = S.ssl_ctx_create(0, 0)
+    X0 = crandn(rng, F, T, M)
+    A, C, C2 = (make_handle(S, ctx, X0) for _ in range(3))
+    A2 = make_handle(S, ctx, X0)
+    B, B2 = S.ssl_noise_create(ctx, F, M), S.ssl_noise_create(ctx, F, M)
+    X1, X2 = to_dev(crandn(rng, F, T, M)), to_dev(crandn(rng, F, T, M))
+
+    def K_of(h):
+        K = torch.zeros((F, M, M), dtype=torch.complex128, device="cuda:0")
+        S.ssl_noise_get(h, K)
+        return to_host(K)
+
+    K0 = K_of(A)
+    say("ssl_noise_update_frames_from: A -> B, then in place on C")
+    S.ssl_noise_update_frames_from(ctx, [B], [A], [X1], 0.95)
+    S.ssl_noise_update_frames(ctx, [C], [X1], 0.95)
+    assert np.array_equal(K_of(A), K0)
+    assert np.array_equal(K_of(B), K_of(C))
+    say("B -> A, then in place on C")
+    S.ssl_noise_update_frames_from(ctx, [A], [B], [X2], 0.95)
+    S.ssl_noise_update_frames(ctx, [C], [X2], 0.95)
+    assert np.array_equal(K_of(A), K_of(C))
+    say("both entries in one call")
+    S.ssl_noise_update_frames_from(ctx, [B2, A2], [A2, B2], [X1, X2], 0.95)
+    S.ssl_noise_update_frames(ctx, [C2, C2], [X1, X2], 0.95)
+    assert np.array_equal(K_of(A2), K_of(C2))
+    # the inverse, through the whitened SVD of one R
+    R = torch.zeros((F, M, M), dtype=torch.complex64, device="cuda:0")
+    S.ssl_corr_accum(ctx, to_dev(crandn(rng, F, T, M)), 1.0 / T, 0, S.SSL_FP32, R)
+    out = []
+    for h in (A, C, A2):
+        En = torch.zeros((F, M - 2, M), dtype=torch.complex64, device="cuda:0")
+        st = torch.zeros(F, dtype=torch.int32, device="cuda:0")
+        S.ssl_gsvd(ctx, R, h, 2, En, None, st, None, 0)
+        out.append((to_host(En), to_host(st)))
+    for o in out[1:]:
+        assert np.array_equal(out[0][0], o[0]) and np.array_equal(out[0][1], o[1])
+    # errors: unset source, shape mismatch; nothing is launched
+    U = S.ssl_noise_create(ctx, F, M)
+    with pytest.raises(S.SSLError):
+        S.ssl_noise_update_frames_from(ctx, [A], [U], [X1], 0.95)
+    W = S.ssl_noise_create(ctx, F, 16)
+    with pytest.raises(S.SSLError):
+        S.ssl_noise_update_frames_from(ctx, [W], [A], [X1], 0.95)
+    assert np.array_equal(K_of(A), K_of(C))
+    for h in (A, B, C, A2, B2, C2, U, W):
+        S.ssl_noise_destroy(h)
+    S.ssl_ctx_destroy(ctx)

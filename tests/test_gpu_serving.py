@@ -25,15 +25,20 @@ def steering_tables(streams, torch):
     return out
 
 
-def test_served_equals_alone():
+@pytest.mark.parametrize("k_lag", [0, 1])
+def test_served_equals_alone(k_lag):
+    """Each served block equals ssl_localize on the K version it was served with: version v is
+    K0 blended with the noise frames of the stream's first v blocks, one plain in-place
+    ssl_noise_update per block; with a lag of L, block n reads version max(0, n - L)."""
     import torch
     import paper_2504_03373_amd as S
     from paper_2504_03373_amd.serving import GpuExecutor, Server
     S.lib()
     streams = synth.serving_streams(n_streams=6, seed=77)
-    say("streams M:", [s.M for s in streams])
+    say("streams M:", [s.M for s in streams], "k_lag", k_lag)
     H = steering_tables(streams, torch)
-    ex = GpuExecutor(streams, H, alpha=0.95, k_update_every=1, hbm_budget_bytes=2 << 30, lanes=2, pool=3)
+    ex = GpuExecutor(streams, H, alpha=0.95, k_update_every=1, hbm_budget_bytes=2 << 30, lanes=2,
+                     pool=3, k_lag=k_lag)
     arrivals = synth.poisson_arrivals(len(streams), 0.25, 0.010, seed=78)
     say(f"serving {len(arrivals)} blocks")
     st = Server(ex, 2 << 30, max_batch=64).run(arrivals)
@@ -55,19 +60,30 @@ def test_served_equals_alone():
         S.ssl_corr_accum(ctx, Xn0, 1.0 / Xn0.shape[1], 0, S.SSL_FP64, K0)
         n = S.ssl_noise_create(ctx, s.F, s.M)
         S.ssl_noise_set(n, K0, S.SSL_FP64)
+        versions = [n]                      # handle of K version v
         Kh = torch.zeros((s.F, s.M, s.M), dtype=torch.complex128, device="cuda:0")
+        Kc = torch.zeros_like(Kh)
         pool = [s.block(q) for q in range(3)]
-        updates = 0
         for r in reqs:
             X, Xn = pool[r.seq % 3]
+            assert r.k_version == max(0, r.seq - k_lag), (sid, r.seq, r.k_version)
             pk = torch.zeros(s.Ns, dtype=torch.int32, device="cuda:0")
             pv = torch.zeros(s.Ns, dtype=torch.float32, device="cuda:0")
-            S.ssl_localize(ctx, to_dev(X), n, H[s.M], S.SSL_FP32, s.grid.n_az, s.grid.n_el, s.Ns, 2, pk, pv)
-            assert r.k_version == updates
+            S.ssl_localize(ctx, to_dev(X), versions[r.k_version], H[s.M], S.SSL_FP32,
+                           s.grid.n_az, s.grid.n_el, s.Ns, 2, pk, pv)
             assert np.array_equal(to_host(pk), r.peaks), (sid, r.seq)
             assert np.array_equal(to_host(pv), r.peak_val), (sid, r.seq)
+            # next version: a fresh handle holding the latest K, updated in place
+            S.ssl_noise_get(versions[-1], Kc)
+            nv = S.ssl_noise_create(ctx, s.F, s.M)
+            S.ssl_noise_set(nv, Kc, S.SSL_FP64)
             S.ssl_corr_accum(ctx, to_dev(Xn), 1.0 / s.T, 0, S.SSL_FP64, Kh)
-            S.ssl_noise_update(n, Kh, S.SSL_FP64, 0.95)
-            updates += 1
-        S.ssl_noise_destroy(n)
+            S.ssl_noise_update(nv, Kh, S.SSL_FP64, 0.95)
+            versions.append(nv)
+            if len(versions) > 3:               # keep the versions a later block can read
+                S.ssl_noise_destroy(versions[-4])
+                versions[-4] = None
+        for h in versions:
+            if h is not None:
+                S.ssl_noise_destroy(h)
     S.ssl_ctx_destroy(ctx)

@@ -1,6 +1,6 @@
 """Serving scheduler on the CPU: a fake executor with a latency model and a simulated clock.
 
-Checks admission by HBM budget, at most one block per stream in flight, per-stream order,
+Checks admission by HBM budget, the per-stream in-flight limit, per-stream order,
 continuous batching (a batch starts on a free lane while another runs), latency bookkeeping and the
 oversize-block error.  No GPU and no HIP library involved.
 """
@@ -25,20 +25,29 @@ class FakeClock:
 class FakeExecutor:
     """Batch of n blocks takes a + b * n seconds; records what the scheduler asked for."""
 
-    def __init__(self, clock, costs, lanes=2, a=2e-3, b=1e-4):
+    def __init__(self, clock, costs, lanes=2, a=2e-3, b=1e-4, depth=1):
         self.clock, self.costs, self.lanes, self.a, self.b = clock, costs, lanes, a, b
         self.inflight = [None] * lanes
         self.log = []
         self.max_bytes = 0
+        self.max_depth = 0
+        if depth != 1:
+            self.stream_depth = depth
 
     def cost_bytes(self, sid):
         return self.costs[sid]
 
     def submit(self, lane, reqs):
         assert self.inflight[lane] is None
-        busy = {r.stream for x in self.inflight if x for r in x[0]}
-        assert not busy & {r.stream for r in reqs}, "stream already in flight"
         assert len({r.stream for r in reqs}) == len(reqs)
+        n = {}
+        for x in self.inflight:
+            for r in (x[0] if x else []):
+                n[r.stream] = n.get(r.stream, 0) + 1
+        for r in reqs:
+            n[r.stream] = n.get(r.stream, 0) + 1
+        self.max_depth = max([self.max_depth] + list(n.values()))
+        assert self.max_depth <= getattr(self, "stream_depth", 1), "too many blocks of a stream in flight"
         self.inflight[lane] = (reqs, self.clock() + self.a + self.b * len(reqs))
         self.log.append((self.clock(), lane, [(r.stream, r.seq) for r in reqs]))
         used = sum(self.costs[r.stream] for x in self.inflight if x for r in x[0])
@@ -53,9 +62,9 @@ class FakeExecutor:
         self.inflight[lane] = None
 
 
-def run(arrivals, costs, budget, lanes=2, max_batch=64, a=2e-3, b=1e-4):
+def run(arrivals, costs, budget, lanes=2, max_batch=64, a=2e-3, b=1e-4, depth=1):
     clk = FakeClock()
-    ex = FakeExecutor(clk, costs, lanes, a, b)
+    ex = FakeExecutor(clk, costs, lanes, a, b, depth)
     srv = Server(ex, budget, max_batch=max_batch, clock=clk, sleep=clk.sleep, poll_s=1e-4)
     return srv.run(arrivals), ex
 
@@ -118,3 +127,21 @@ def test_max_batch_cap():
     st, ex = run(arr, [1] * 40, budget=1 << 20, max_batch=8)
     assert all(len(items) <= 8 for _, _, items in ex.log)
     assert st["completed"] == 40
+
+
+def test_stream_depth_two():
+    """With two blocks per stream allowed in flight, a backlogged stream gets its next block into
+    the other lane while the first runs; submission order per stream is kept."""
+    arr = [(0.0, s, k) for s in range(4) for k in range(6)]
+    arr.sort()
+    st, ex = run(arr, [1] * 4, budget=1 << 20, lanes=2, depth=2)
+    assert st["completed"] == len(arr)
+    assert ex.max_depth == 2
+    order = {}
+    for _, _, items in ex.log:
+        for s, q in items:
+            assert q == order.get(s, -1) + 1, "per-stream order broken"
+            order[s] = q
+    st1, ex1 = run(arr, [1] * 4, budget=1 << 20, lanes=2, depth=1)
+    assert ex1.max_depth == 1
+    assert max(r.done_t for r in st["requests"]) < max(r.done_t for r in st1["requests"])
