@@ -170,7 +170,7 @@ class GpuExecutor:
 
     def __init__(self, streams, steering, prec=None, p: int = 2, alpha: float = 0.95,
                  k_update_every: int = 1, hbm_budget_bytes: int = 4 << 30, lanes: int = 2,
-                 pool: int = 4, device: int = 0, noise_streams: int = 4, configure=None,
+                 pool: int = 4, device: int = 0, update_contexts: int = 4, configure=None,
                  slots: int = 4, k_lag: int = 1):
         import torch
 
@@ -200,24 +200,28 @@ class GpuExecutor:
                 configure(c)
         self.nctx = ssl_ctx_create(device, 0)
         self.tstreams = [torch.cuda.Stream(device=self.dev) for _ in range(lanes)]
-        # K updates go round-robin over a few streams (one update is a few hundred workgroups:
-        # alone it leaves most of the device idle); a batch waits only for the updates that
-        # produced the K versions its blocks read
-        self.nstreams = [torch.cuda.Stream(device=self.dev) for _ in range(max(1, noise_streams))]
-        self.next_ns = 0
+        # K updates run on one stream of their own, in submission order (so version v of a
+        # stream is complete before v + 1 starts, with no waits between updates); a batch waits
+        # only for the updates that produced the K versions its blocks read.  Few streams on
+        # purpose: HIP maps streams onto a handful of hardware queues, and a stream's wait on
+        # another parked at the head of a shared queue holds back everything behind it.
+        self.ustream = torch.cuda.Stream(device=self.dev)
         # steering tables per channel count (shared by streams of the same geometry)
         self.H = {M: t for M, t in steering.items()}
         self.noise, self.X_slot, self.Xn_slot, self.X_pool, self.Xn_pool = [], [], [], [], []
         # K versions: version v (v updates applied) lives in handle v % 2 of the stream; an
         # update reads version v and writes v + 1 into the other handle.  k_version = updates
-        # launched, k_done[v % 2] = event completing version v (None: already complete)
+        # launched, k_done[v % 2] = (event completing version v, update call number), None for
+        # the initial version
         self.k_lag = k_lag
         self.stream_depth = 1 + k_lag
         self.k_version = [0] * len(self.streams)
         self.k_done = [[None, None] for _ in self.streams]
-        # one library context per noise stream: an update call keeps K-hat in its context's
-        # workspace, and calls on different streams may overlap
-        self.uctx = [ssl_ctx_create(device, 0) for _ in self.nstreams]
+        self.n_updates = 0
+        # update calls go round-robin over a few library contexts: a call waits (on the host) for
+        # its context's previous descriptor upload, which sits behind that call's batch
+        self.uctx = [ssl_ctx_create(device, 0) for _ in range(max(1, update_contexts))]
+        self.next_uctx = 0
         for s in self.streams:
             Xn0 = torch.from_numpy(s.initial_noise_frames()).to(self.dev)
             K0 = torch.zeros((s.F, s.M, s.M), dtype=torch.complex128, device=self.dev)
@@ -248,7 +252,8 @@ class GpuExecutor:
         self.slot_free = [[None] * slots for _ in self.streams]
         self.waiting = [collections.deque() for _ in self.streams]
         self.to_pump = set()
-        self.staged = {}                     # (stream, seq) -> (slot, copy event)
+        self.staged = {}          # (stream, seq) -> (slot, copy event or None, staging number)
+        self.n_staged = 0
         nmax = 4096
         self.pk = [torch.zeros((nmax, 3), dtype=torch.int32, device=self.dev) for _ in range(lanes)]
         self.pv = [torch.zeros((nmax, 3), dtype=torch.float32, device=self.dev) for _ in range(lanes)]
@@ -272,14 +277,19 @@ class GpuExecutor:
         sid = r.stream
         self.slot_owner[sid][k] = r
         with torch.cuda.stream(st):
-            if self.slot_free[sid][k] is not None:
-                st.wait_event(self.slot_free[sid][k])
+            fev = self.slot_free[sid][k]
+            if fev is not None and not fev.query():
+                st.wait_event(fev)
             self.slot_free[sid][k] = None
             self.X_slot[sid][k].copy_(self.X_pool[sid][r.seq % self.pool], non_blocking=True)
             self.Xn_slot[sid][k].copy_(self.Xn_pool[sid][r.seq % self.pool], non_blocking=True)
-            ev = torch.cuda.Event()
-            ev.record(st)
-        self.staged[(sid, r.seq)] = (k, ev)
+            ev, num = None, -1                    # staged on the lane stream: no wait
+            if st is self.cstream:               # copies complete in staging order
+                ev = torch.cuda.Event()
+                ev.record(st)
+                self.n_staged += 1
+                num = self.n_staged
+        self.staged[(sid, r.seq)] = (k, ev, num)
 
     def _free_slot(self, sid: int, ready_only: bool):
         for k in range(self.nslot):
@@ -309,7 +319,7 @@ class GpuExecutor:
         st = self.tstreams[lane]
         descs = []
         with torch.cuda.stream(st):
-            waited = set()
+            last_update = None                    # updates complete in call order
             for r in reqs:
                 if (r.stream, r.seq) not in self.staged:
                     # not uploaded yet (no slot was free, or the scheduler was not told): it is the
@@ -320,13 +330,16 @@ class GpuExecutor:
                         q.popleft()
                     k = self._free_slot(r.stream, ready_only=True)
                     self._stage(r, self._free_slot(r.stream, ready_only=False) if k is None else k, st)
-                k, cev = self.staged[(r.stream, r.seq)]
-                st.wait_event(cev)
                 r.k_version = max(0, self.k_version[r.stream] - self.k_lag)
-                ev = self.k_done[r.stream][r.k_version % 2]
-                if ev is not None and id(ev) not in waited:
-                    st.wait_event(ev)
-                    waited.add(id(ev))
+                kd = self.k_done[r.stream][r.k_version % 2]
+                if kd is not None and (last_update is None or kd[1] > last_update[1]):
+                    last_update = kd
+            # the copy stream runs in staging order: its last copy among the batch's covers all
+            cev = max((self.staged[(r.stream, r.seq)] for r in reqs), key=lambda t: t[2])
+            if cev[1] is not None:
+                st.wait_event(cev[1])
+            if last_update is not None:
+                st.wait_event(last_update[0])
             for i, r in enumerate(reqs):
                 s = self.streams[r.stream]
                 k = self.staged[(r.stream, r.seq)][0]
@@ -344,7 +357,7 @@ class GpuExecutor:
 
     def _launch_updates(self, reqs: List["Request"], ev):
         """K EMA updates of the blocks of a batch, queued behind it (the batch may read the handle
-        they write, and it waited for their frames' upload): one library call on the next noise
+        they write, and it waited for their frames' upload): one library call on the update
         stream, all their bins in one launch pair per channel class.  Returns the completion event
         (None if no block of the batch updates K)."""
         from . import ssl_noise_update_frames_from
@@ -352,17 +365,11 @@ class GpuExecutor:
         ups = [r for r in reqs if (r.seq + 1) % self.k_every == 0]
         if not ups:
             return None
-        i = self.next_ns
-        self.next_ns = (i + 1) % len(self.nstreams)
-        ns = self.nstreams[i]
+        i = self.next_uctx
+        self.next_uctx = (i + 1) % len(self.uctx)
+        ns = self.ustream
         with torch.cuda.stream(ns):
             ns.wait_event(ev)
-            waited = set()
-            for r in ups:                         # version v must be complete before v + 1
-                pev = self.k_done[r.stream][self.k_version[r.stream] % 2]
-                if pev is not None and id(pev) not in waited:
-                    ns.wait_event(pev)
-                    waited.add(id(pev))
             v = [self.k_version[r.stream] for r in ups]
             ssl_noise_update_frames_from(
                 self.uctx[i], [self.noise[r.stream][(vv + 1) % 2] for r, vv in zip(ups, v)],
@@ -371,9 +378,10 @@ class GpuExecutor:
                 self.alpha, stream=ns)
             done = torch.cuda.Event()
             done.record(ns)
+        self.n_updates += 1
         for r in ups:
             self.k_version[r.stream] += 1
-            self.k_done[r.stream][self.k_version[r.stream] % 2] = done
+            self.k_done[r.stream][self.k_version[r.stream] % 2] = (done, self.n_updates)
         return done
 
     def poll(self, lane: int) -> bool:
