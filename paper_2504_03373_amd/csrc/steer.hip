@@ -265,7 +265,8 @@ __device__ __forceinline__ void steer_tile(const E *__restrict__ Hf, int D, int 
                                            int nb, BlockAt &&blk)
 {
     typedef SteerCfg<E> C;
-    __shared__ __attribute__((aligned(16))) E Bs[16 * NCT * C::KS_MAX];
+    constexpr int BSZ = 16 * NCT * C::KS_MAX;
+    __shared__ __attribute__((aligned(16))) E Bbuf[2 * BSZ];   // two B stages, alternating by block
     __shared__ float nrm_s[16 * WV];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -283,9 +284,12 @@ __device__ __forceinline__ void steer_tile(const E *__restrict__ Hf, int D, int 
     if (lane < 16) nrm_s[wave * 16 + lane] = hn;
 
     // software pipeline over the blocks: block i + 1's E_n loads are issued before block i's
-    // MFMAs and written to LDS right after them (Bs is free once every wave has its fragments);
-    // block i's epilogue then works on registers while the next B is in place.  The block
-    // descriptors (a chain of dependent reads) are fetched one block further ahead still.
+    // MFMAs and written to the other LDS stage right after them, then block i's epilogue runs on
+    // registers.  One barrier per block: the stage written for block i + 1 was last read by block
+    // i - 1's MFMAs, which every wave finished before the previous barrier, so waves need not
+    // wait for each other between their MFMAs and their stores, and one wave's stores and
+    // epilogue overlap another's MFMAs.  The block descriptors (a chain of dependent reads) are
+    // fetched one block further ahead still.
     struct Blk {
         const float2 *En;
         bool ok;
@@ -298,7 +302,7 @@ __device__ __forceinline__ void steer_tile(const E *__restrict__ Hf, int D, int 
     {
         BStage<NCT, WV> st;
         load_b<NCT, WV>(cur.En, M, M - cur.Ns, tid, st);
-        store_b<NCT, WV, E>(st, Bs, KS, KP, tid);
+        store_b<NCT, WV, E>(st, Bbuf, KS, KP, tid);
     }
     __syncthreads();
     for (int i = 0; i < nb; ++i) {
@@ -307,15 +311,15 @@ __device__ __forceinline__ void steer_tile(const E *__restrict__ Hf, int D, int 
         int tid_i = tid, lane_i = lane;
         asm volatile("" : "+v"(tid_i), "+v"(lane_i));
         const bool more = i + 1 < nb;
+        E *Bs = Bbuf + (i & 1) * BSZ;
         if (i + 2 < nb) blk(i + 2, nn.En, nn.ok, nn.Ns, nn.P);
         BStage<NCT, WV> st;
         if (more) load_b<NCT, WV>(nxt.En, M, M - nxt.Ns, tid_i, st);
         floatx4 acc1[NCT], acc2[NCT];
         mma<NCT, E>(S, Bs, KS, KQ, lane_i, acc1, acc2);
-        __syncthreads();                   // every wave has read Bs
-        if (more) store_b<NCT, WV, E>(st, Bs, KS, KP, tid_i);
+        if (more) store_b<NCT, WV, E>(st, Bbuf + ((i + 1) & 1) * BSZ, KS, KP, tid_i);
         finish_rows<NCT>(acc1, acc2, p, lane, wave, d0, D, cur.ok, cur.P, nrm_s);
-        __syncthreads();                   // next B staged
+        __syncthreads();                   // next B staged; this B free for block i + 2
         cur = nxt;
         nxt = nn;
     }
