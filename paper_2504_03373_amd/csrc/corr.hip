@@ -56,11 +56,11 @@ __device__ __forceinline__ void lds_to_out(const float2 *Rs, int RS, int M, int 
         if (j >= M) continue;
         float2 v = Rs[i * RS + j];
         if (accumulate) {
-            const float2 a = Rf[(size_t)i * M + j];
+            const float2 a = gload(Rf + (size_t)i * M + j);
             v.x += a.x;
             v.y += a.y;
         }
-        Rf[(size_t)i * M + j] = v;
+        gstore(Rf + (size_t)i * M + j, v);
     }
 }
 
@@ -80,7 +80,7 @@ __device__ __forceinline__ void load_chunk(const float2 *__restrict__ Xf, int t0
     for (int u = 0; u < kChunkRegs<MP>; ++u) {
         const int e = t + u * kThreads;
         const int tt = e / MP, m = e - tt * MP;
-        v[u] = (tt < nf && m < M) ? Xf[(size_t)(t0 + tt) * sT + m] : make_float2(0.f, 0.f);
+        v[u] = (tt < nf && m < M) ? gload(Xf + (size_t)(t0 + tt) * sT + m) : make_float2(0.f, 0.f);
     }
 }
 
@@ -433,15 +433,15 @@ __device__ __forceinline__ void corr_f64_bin(const float2 *__restrict__ Xf, int 
         if (j >= M) continue;
         double2 v = Rs[i * RS + j];
         if (mode == kAccumulate) {
-            const double2 a = R0f[(size_t)i * M + j];
+            const double2 a = gload(R0f + (size_t)i * M + j);
             v.x += a.x;
             v.y += a.y;
         } else if (mode == kBlend) {
-            const double2 a = R0f[(size_t)i * M + j];
+            const double2 a = gload(R0f + (size_t)i * M + j);
             v = make_double2(fma(alpha, a.x, (1.0 - alpha) * v.x),
                              fma(alpha, a.y, (1.0 - alpha) * v.y));
         }
-        Rf[(size_t)i * M + j] = v;
+        gstore(Rf + (size_t)i * M + j, v);
     }
 }
 

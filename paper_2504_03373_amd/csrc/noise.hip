@@ -46,7 +46,7 @@ __device__ __forceinline__ void noise_factor_bin(const double2 *__restrict__ Kf,
 #pragma unroll
     for (int u = 0; u < 8; ++u) {                      // every load in flight first
         const int i = i0 + RG * u;
-        w[u] = (i < M && j < M) ? Kf[(size_t)i * M + j] : make_double2(0.0, 0.0);
+        w[u] = (i < M && j < M) ? gload(Kf + (size_t)i * M + j) : make_double2(0.0, 0.0);
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -110,9 +110,9 @@ __device__ __forceinline__ void noise_factor_bin(const double2 *__restrict__ Kf,
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
         const int i = i0 + RG * u;
-        if (i < M && j < M) Wf[(size_t)i * M + j] = bad ? make_double2(0.0, 0.0) : w[u];
+        if (i < M && j < M) gstore(Wf + (size_t)i * M + j, bad ? make_double2(0.0, 0.0) : w[u]);
     }
-    if (t == 0) *stf = bad ? SSL_BIN_NOT_PD : SSL_BIN_OK;
+    if (t == 0) gstore(stf, (int32_t)(bad ? SSL_BIN_NOT_PD : SSL_BIN_OK));
 }
 
 template <int MP>
@@ -202,7 +202,7 @@ __device__ __forceinline__ void load_r(const float2 *__restrict__ Rf, int M, int
     const float2 *src = Rf + (size_t)k0 * M + j;
 #pragma unroll
     for (int u = 0; u < WhCfg<MP>::NIT; ++u)
-        v[u] = (j < M && k0 + 4 * u < M) ? src[(size_t)u * 4 * M] : make_float2(0.f, 0.f);
+        v[u] = (j < M && k0 + 4 * u < M) ? gload(src + (size_t)u * 4 * M) : make_float2(0.f, 0.f);
 }
 
 template <int MP>
@@ -230,7 +230,7 @@ __device__ __forceinline__ void whiten_run(const double2 *__restrict__ Wf, int M
 #pragma unroll
     for (int q = 0; q < C::KQ; ++q) {
         const int k = 4 * q + kl;
-        w[q] = (row < M && k < M) ? Wf[(size_t)row * M + k] : make_double2(0.0, 0.0);
+        w[q] = (row < M && k < M) ? gload(Wf + (size_t)row * M + k) : make_double2(0.0, 0.0);
     }
 
     const float2 *Rf;
@@ -280,7 +280,7 @@ __device__ __forceinline__ void whiten_run(const double2 *__restrict__ Wf, int M
             for (int e = 0; e < 4; ++e) {
                 const int r = 16 * wave + kl + 4 * e;
                 if (r < M && j < M)
-                    cur_A[(size_t)r * M + j] = make_float2((float)ar[ct][e], (float)ai[ct][e]);
+                    gstore(cur_A + (size_t)r * M + j, make_float2((float)ar[ct][e], (float)ai[ct][e]));
             }
         }
         __syncthreads();                         // every wave has read Rs

@@ -97,6 +97,27 @@ struct NoiseUpdDev {
     int32_t *status;
 };
 
+// Device pointers read from descriptors are generic: loads through them compile to FLAT
+// instructions, which count against the LDS counter as well, so a wait for an LDS read would also
+// wait for every such load in flight.  gload / gstore access one element through a global-memory
+// pointer (global_load / global_store, counted by the vector-memory counter only).
+template <int N> struct GWord;
+template <> struct GWord<4> { typedef unsigned int type; };
+template <> struct GWord<8> { typedef unsigned long long type; };
+template <> struct GWord<16> { typedef unsigned int type __attribute__((ext_vector_type(4))); };
+template <typename T>
+__device__ __forceinline__ T gload(const T *p)
+{
+    typedef typename GWord<sizeof(T)>::type W;
+    return __builtin_bit_cast(T, *(const __attribute__((address_space(1))) W *)p);
+}
+template <typename T>
+__device__ __forceinline__ void gstore(T *p, T v)
+{
+    typedef typename GWord<sizeof(T)>::type W;
+    *(__attribute__((address_space(1))) W *)p = __builtin_bit_cast(W, v);
+}
+
 // Size classes shared by the single-block and batched launches, so that a bin is computed by the
 // same kernel variant whichever entry point schedules it.
 inline int corr_class(int M) { return M <= 16 ? 16 : M <= 32 ? 32 : M <= 48 ? 48 : 64; }

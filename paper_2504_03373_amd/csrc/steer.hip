@@ -104,8 +104,8 @@ __device__ __forceinline__ float load_strip(const E *__restrict__ Hf, int D, int
             const int k0 = 16 * kq + 4 * sl;
             float2 lo = make_float2(0.f, 0.f), hi = make_float2(0.f, 0.f);
             if (kq < KQ && row < D) {
-                if (k0 < K2) lo = *(const float2 *)(hrow + k0);          // complex element k0/2
-                if (k0 + 2 < K2) hi = *(const float2 *)(hrow + k0 + 2);
+                if (k0 < K2) lo = gload((const float2 *)(hrow + k0));    // complex element k0/2
+                if (k0 + 2 < K2) hi = gload((const float2 *)(hrow + k0 + 2));
             }
             S.a[kq] = make_float4(lo.x, lo.y, hi.x, hi.y);
             hn = fmaf(lo.x, lo.x, fmaf(lo.y, lo.y, fmaf(hi.x, hi.x, fmaf(hi.y, hi.y, hn))));
@@ -119,7 +119,7 @@ __device__ __forceinline__ float load_strip(const E *__restrict__ Hf, int D, int
 #pragma unroll
             for (int i = 0; i < 4; ++i)
                 w[i] = (kq < KQ && row < D && m0 + i < M)
-                           ? *(const uint32_t *)(hrow + 2 * (m0 + i)) : 0u;
+                           ? gload((const uint32_t *)(hrow + 2 * (m0 + i))) : 0u;
             S.a[kq] = __builtin_bit_cast(vec, w);
             S.b[kq] = twist(S.a[kq]);
 #pragma unroll
@@ -152,7 +152,7 @@ __device__ __forceinline__ void load_b(const float2 *__restrict__ Enf, int M, in
     const bool mok = m < M;
 #pragma unroll
     for (int u = 0; u < BStage<NCT, WV>::NIT; ++u)
-        st.v[u] = (mok && c0 + WV * u < Nn) ? src[(size_t)u * WV * M] : make_float2(0.f, 0.f);
+        st.v[u] = (mok && c0 + WV * u < Nn) ? gload(src + (size_t)u * WV * M) : make_float2(0.f, 0.f);
 }
 
 template <int NCT, int WV, typename E>
@@ -252,8 +252,9 @@ __device__ __forceinline__ void finish_rows(const floatx4 (&acc1)[NCT], const fl
         const int d = d0 + wave * 16 + lane;
         if (d < D) {
             // hardware reciprocal (1 ulp): P is compared at 1e-4, den >= FLT_MIN
-            Pf[d] = bin_ok ? nrm_s[wave * 16 + lane] * __builtin_amdgcn_rcpf(fmaxf(den, 1.17549435e-38f))
-                           : 0.0f;
+            gstore(Pf + d, bin_ok ? nrm_s[wave * 16 + lane] *
+                                        __builtin_amdgcn_rcpf(fmaxf(den, 1.17549435e-38f))
+                                  : 0.0f);
         }
     }
 }
@@ -381,7 +382,7 @@ __global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(4))) vo
                        [&](int i, const float2 *&Enf, bool &ok, int &ns, float *&Pf) {
                            const BlockDev &B = blk[gblocks[gr.x + i]];
                            Enf = B.En + (size_t)f * (M - B.Ns) * M;
-                           ok = B.status[f] == SSL_BIN_OK;
+                           ok = gload(B.status + f) == SSL_BIN_OK;
                            ns = B.Ns;
                            Pf = B.P + (size_t)f * D;
                        });
