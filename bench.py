@@ -197,6 +197,87 @@ def serving_phase(args, variants: dict) -> dict:
     return out
 
 
+def uneven_phase(args) -> dict:
+    """The uneven batch: `--uneven-blocks` blocks with M in {8, 16, 32, 60}, F in {257, 513} and
+    Ns in {1, 2, 3} (uniform, seeded), all in one ssl_localize_batch call per step (persistent
+    Jacobi launch, graph replay after the first call), every block its own device copy of X.
+    Kernel variants are autotuned per channel class on this mix (F = 257, Ns = 2 blocks)."""
+    import torch
+
+    import paper_2504_03373_amd as S
+    import synth
+    dev = "cuda:0"
+    PREC = {"fp32": S.SSL_FP32, "bf16": S.SSL_BF16, "fp16": S.SSL_FP16}
+    prec = PREC[args.prec]
+    shapes = synth.uneven_shapes(args.uneven_blocks)
+    ctx = S.ssl_ctx_create(0, 0)
+    geo, pool = {}, {}
+    t0 = time.time()
+    for M, F, Ns in sorted(set(shapes)):
+        if (M, F) not in geo:
+            w = synth.workload_paper(n_blocks=2, seed=3000 + 10 * M + F, M=M, F=F)
+            Xn = torch.from_numpy(w.noise_frames()).to(dev)
+            K = torch.zeros((F, M, M), dtype=torch.complex128, device=dev)
+            S.ssl_corr_accum(ctx, Xn, 1.0 / Xn.shape[1], 0, S.SSL_FP64, K)
+            n = S.ssl_noise_create(ctx, F, M)
+            S.ssl_noise_set(n, K, S.SSL_FP64)
+            H = torch.from_numpy(w.steering_table()).to(dev)
+            if prec != S.SSL_FP32:
+                H = torch.view_as_real(H).reshape(F, w.D, 2 * M).to(
+                    torch.bfloat16 if prec == S.SSL_BF16 else torch.float16).contiguous()
+            geo[(M, F)] = dict(noise=n, H=H, D=w.D, grid=w.grid)
+        wk = synth.workload_paper(n_blocks=2, seed=3100 + 10 * M + F + Ns, M=M, F=F, Ns=Ns)
+        pool[(M, F, Ns)] = [wk.block(q)[0] for q in range(2)]
+    gen_s = time.time() - t0
+    tuned = {}
+    if not args.no_autotune:
+        for M in (8, 16, 32, 60):
+            g = geo.get((M, 257))
+            if g is None or (M, 257, 2) not in pool:
+                continue
+            X = torch.from_numpy(pool[(M, 257, 2)][0]).to(dev)
+            R = torch.zeros((257, M, M), dtype=torch.complex64, device=dev)
+            En = torch.zeros((257, M - 2, M), dtype=torch.complex64, device=dev)
+            S.ssl_corr_accum(ctx, X, 1.0 / X.shape[1], 0, prec, R)
+            S.ssl_gsvd(ctx, R, g["noise"], 2, En, None, None, None, 0)
+            lanes, _ = S.ssl_autotune_jacobi(ctx, R, g["noise"], 2, nblocks=32, reps=2)
+            waves, _ = S.ssl_autotune_steer(ctx, g["H"], prec, En, 2, p=2, nblocks=32, reps=2)
+            tuned[str(M)] = {"jacobi_lanes": lanes, "steer_waves": waves}
+    descs, outs = [], []
+    for i, (M, F, Ns) in enumerate(shapes):
+        g = geo[(M, F)]
+        X = torch.from_numpy(pool[(M, F, Ns)][i % 2]).to(dev)
+        o = (torch.zeros(Ns, dtype=torch.int32, device=dev),
+             torch.zeros(Ns, dtype=torch.float32, device=dev),
+             torch.zeros(g["D"], dtype=torch.float32, device=dev),
+             torch.zeros(F, dtype=torch.int32, device=dev), X)
+        outs.append(o)
+        descs.append(S.block_desc(X, g["noise"], g["H"], g["grid"].n_az, g["grid"].n_el, Ns,
+                                  o[0], o[1], o[2], o[3]))
+    for _ in range(2):                       # the first call captures the graph
+        S.ssl_localize_batch(ctx, descs, prec, 2)
+    torch.cuda.synchronize()
+    tt = time.perf_counter()
+    for _ in range(args.uneven_steps):
+        S.ssl_localize_batch(ctx, descs, prec, 2)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - tt
+    bins = sum(F for _, F, _ in shapes)
+    ok = all(bool((o[3] == S.SSL_BIN_OK).all()) for o in outs)
+    for g in geo.values():
+        S.ssl_noise_destroy(g["noise"])
+    S.ssl_ctx_destroy(ctx)
+    mix = {f"M{m}": sum(1 for s_ in shapes if s_[0] == m) for m in (8, 16, 32, 60)}
+    return {"blocks": len(shapes), "bins": bins, "value": round(len(shapes) * args.uneven_steps / el, 1),
+            "unit": "blocks/s", "bins_per_s": round(bins * args.uneven_steps / el, 1),
+            "ms_per_step": round(1e3 * el / args.uneven_steps, 3), "steps": args.uneven_steps,
+            "prec": args.prec, "blocks_by_M": mix,
+            "blocks_F513": sum(1 for s_ in shapes if s_[1] == 513),
+            "tuned": tuned or "defaults", "status_ok": ok, "input_gen_s": round(gen_s, 2),
+            "kind": "one ssl_localize_batch per step over all blocks (persistent Jacobi, graph "
+                    "replay), M in {8,16,32,60}, F in {257,513}, Ns in {1,2,3}"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -231,6 +312,9 @@ def main() -> int:
     ap.add_argument("--k-update-every", type=int, default=1)
     ap.add_argument("--k-lag", type=int, default=1, choices=[0, 1],
                     help="serving: block n reads the K of blocks <= n - 1 - k_lag")
+    ap.add_argument("--uneven-blocks", type=int, default=512,
+                    help="blocks of the uneven-shape batch (0 = skip)")
+    ap.add_argument("--uneven-steps", type=int, default=5)
     ap.add_argument("--serve-inproc", action="store_true",
                     help="run the serving phase in this process instead of a fresh child")
     ap.add_argument("--serve-child", metavar="VARIANTS_JSON", default=None,
@@ -508,6 +592,8 @@ def main() -> int:
         "input_gen_s": round(gen_s, 2),
         "tuning": tuning or "defaults (--no-autotune)",
     }
+    if args.uneven_blocks > 0:
+        out["uneven"] = uneven_phase(args)
     if "h2d_serial" in main_r:
         out["h2d"] = {"serial": round(main_r["h2d_serial"], 2),
                       "overlapped": round(main_r["h2d_overlap"], 2),
