@@ -8,8 +8,10 @@ stream's noise correlation K stays resident on the device and is updated by expo
 with the noise-only frames that accompany its blocks (K <- alpha K + (1 - alpha) K_hat, then a
 fresh FP64 inverse).  With a lag of L blocks (k_lag), block n runs on the K that includes the
 noise of blocks <= n - 1 - L: at L = 0 the update of block n lands before block n + 1 runs; at
-L = 1 (the default) it runs beside block n + 1, which reads the stream's other K handle, so the
-update is off the stream's round trip.
+L = 1 (the default) it runs beside block n + 1, so the update is off the stream's round trip.
+K versions live in a ring of four handles per stream: an update writes a handle no block in
+flight reads, and a block is submitted only once the host has seen its inputs (upload, K version)
+complete, so no correctness rests on a device-side wait between streams.
 
 Rules: at most `stream_depth` blocks per stream are in flight (an executor attribute, 1 if
 absent; the GPU executor allows 1 + k_lag, the most for which the K versions the blocks read are
@@ -19,8 +21,9 @@ at their in-flight limit (kept as one FIFO per stream, so forming a batch costs 
 O(queue)).
 
 The executor interface (`lanes`, `cost_bytes`, `submit`, `poll`, `collect`, and optionally
-`arrive`, told of each block as it is emitted, and `stream_depth`) is what the scheduler needs;
-`GpuExecutor` implements it with the library's C ABI.
+`arrive`, told of each block as it is emitted, `ready`, false while a block's inputs are still
+being uploaded, and `stream_depth`) is what the scheduler needs; `GpuExecutor` implements it with
+the library's C ABI.
 """
 from __future__ import annotations
 
@@ -74,6 +77,7 @@ class Server:
         max_ready = 0
         host = dict(submit_s=0.0, collect_s=0.0, sleep_s=0.0)   # where the loop's time goes
         arrive = getattr(self.ex, "arrive", None)
+        ready = getattr(self.ex, "ready", None)
         t0 = self.clock()
         while pending or n_ready or any(lanes):
             now = self.clock() - t0
@@ -100,7 +104,8 @@ class Server:
             for li in range(len(lanes)):
                 if lanes[li] is not None or not n_ready:
                     continue
-                heads = sorted((q[0] for sid, q in queues.items() if q and in_flight[sid] < depth),
+                heads = sorted((q[0] for sid, q in queues.items()
+                                if q and in_flight[sid] < depth and (ready is None or ready(q[0]))),
                                key=lambda r: (r.emit_t, r.stream, r.seq))
                 batch, cost = [], 0
                 for r in heads:
@@ -209,14 +214,16 @@ class GpuExecutor:
         # steering tables per channel count (shared by streams of the same geometry)
         self.H = {M: t for M, t in steering.items()}
         self.noise, self.X_slot, self.Xn_slot, self.X_pool, self.Xn_pool = [], [], [], [], []
-        # K versions: version v (v updates applied) lives in handle v % 2 of the stream; an
-        # update reads version v and writes v + 1 into the other handle.  k_version = updates
-        # launched, k_done[v % 2] = (event completing version v, update call number), None for
-        # the initial version
+        # K versions: version v (v updates applied) lives in handle v % NH of the stream; an
+        # update reads version v and writes v + 1.  With at most 1 + k_lag blocks of a stream in
+        # flight, reading versions >= v - 1 - k_lag, the handle of v + 1 (that of v + 1 - NH) is
+        # read by none of them.  k_version = updates launched, k_done[v % NH] = (event
+        # completing version v, update call number), None for the initial version
         self.k_lag = k_lag
         self.stream_depth = 1 + k_lag
         self.k_version = [0] * len(self.streams)
-        self.k_done = [[None, None] for _ in self.streams]
+        self.NH = 4
+        self.k_done = [[None] * self.NH for _ in self.streams]
         self.n_updates = 0
         # update calls go round-robin over a few library contexts: a call waits (on the host) for
         # its context's previous descriptor upload, which sits behind that call's batch
@@ -226,12 +233,12 @@ class GpuExecutor:
             Xn0 = torch.from_numpy(s.initial_noise_frames()).to(self.dev)
             K0 = torch.zeros((s.F, s.M, s.M), dtype=torch.complex128, device=self.dev)
             ssl_corr_accum(self.nctx, Xn0, 1.0 / Xn0.shape[1], 0, SSL_FP64, K0)
-            pair = []
-            for _ in range(2):
+            ring = []
+            for _ in range(self.NH):
                 n = ssl_noise_create(self.nctx, s.F, s.M)
                 ssl_noise_set(n, K0, SSL_FP64)
-                pair.append(n)
-            self.noise.append(pair)
+                ring.append(n)
+            self.noise.append(ring)
             xs, xns = [], []
             for q in range(pool):
                 X, Xn = s.block(q)
@@ -245,11 +252,12 @@ class GpuExecutor:
                                  for _ in range(slots)])
         torch.cuda.synchronize()
         # staging state per stream: slot owners (request staged into it, until collected), the
-        # event after which a released slot may be overwritten, blocks waiting for a slot
+        # events after which a released slot may be overwritten (its batch, its K update), blocks
+        # waiting for a slot
         self.cstream = torch.cuda.Stream(device=self.dev)
         self.nslot = slots
         self.slot_owner = [[None] * slots for _ in self.streams]
-        self.slot_free = [[None] * slots for _ in self.streams]
+        self.slot_free = [[()] * slots for _ in self.streams]
         self.waiting = [collections.deque() for _ in self.streams]
         self.to_pump = set()
         self.staged = {}          # (stream, seq) -> (slot, copy event or None, staging number)
@@ -272,15 +280,13 @@ class GpuExecutor:
         return ws + 2 * F * s.T * M * 8
 
     def _stage(self, r: "Request", k: int, st) -> None:
-        """Upload block r into slot k of its stream on HIP stream st."""
+        """Upload block r into slot k of its stream on HIP stream st; the slot's previous readers
+        have completed (the callers check on the host)."""
         torch = self.torch
         sid = r.stream
         self.slot_owner[sid][k] = r
         with torch.cuda.stream(st):
-            fev = self.slot_free[sid][k]
-            if fev is not None and not fev.query():
-                st.wait_event(fev)
-            self.slot_free[sid][k] = None
+            self.slot_free[sid][k] = ()
             self.X_slot[sid][k].copy_(self.X_pool[sid][r.seq % self.pool], non_blocking=True)
             self.Xn_slot[sid][k].copy_(self.Xn_pool[sid][r.seq % self.pool], non_blocking=True)
             ev, num = None, -1                    # staged on the lane stream: no wait
@@ -292,10 +298,10 @@ class GpuExecutor:
         self.staged[(sid, r.seq)] = (k, ev, num)
 
     def _free_slot(self, sid: int, ready_only: bool):
+        """A released slot (whose readers have completed, if ready_only)."""
         for k in range(self.nslot):
             if self.slot_owner[sid][k] is None:
-                ev = self.slot_free[sid][k]
-                if not ready_only or ev is None or ev.query():
+                if not ready_only or all(e.query() for e in self.slot_free[sid][k]):
                     return k
         return None
 
@@ -313,6 +319,16 @@ class GpuExecutor:
         self.waiting[r.stream].append(r)
         self._pump(r.stream)
 
+    def ready(self, r: "Request") -> bool:
+        """False while r's upload on the copy stream or the K update producing the K version it
+        will read is in flight (a block not staged yet is uploaded on the lane stream at
+        submission, in order with its batch)."""
+        st = self.staged.get((r.stream, r.seq))
+        if st is not None and st[1] is not None and not st[1].query():
+            return False
+        kd = self.k_done[r.stream][max(0, self.k_version[r.stream] - self.k_lag) % self.NH]
+        return kd is None or kd[0].query()
+
     def submit(self, lane: int, reqs: List["Request"]) -> None:
         from . import ssl_localize_batch
         torch = self.torch
@@ -329,14 +345,26 @@ class GpuExecutor:
                     if q and q[0] is r:
                         q.popleft()
                     k = self._free_slot(r.stream, ready_only=True)
-                    self._stage(r, self._free_slot(r.stream, ready_only=False) if k is None else k, st)
+                    if k is None:
+                        k = self._free_slot(r.stream, ready_only=False)
+                        for e in self.slot_free[r.stream][k]:
+                            e.synchronize()
+                    self._stage(r, k, st)
                 r.k_version = max(0, self.k_version[r.stream] - self.k_lag)
-                kd = self.k_done[r.stream][r.k_version % 2]
+                kd = self.k_done[r.stream][r.k_version % self.NH]
+                if kd is not None and not kd[0].query():
+                    kd[0].synchronize()               # the scheduler submits ready blocks only
                 if kd is not None and (last_update is None or kd[1] > last_update[1]):
                     last_update = kd
-            # the copy stream runs in staging order: its last copy among the batch's covers all
+            # the copy stream runs in staging order: its last copy among the batch's covers all.
+            # The scheduler only submits blocks whose upload the host has seen complete (`ready`),
+            # and the host checks again here: a device-side wait on the copy stream's event alone
+            # once let a batch read a slot whose upload had not landed (a block served with no
+            # peaks).
             cev = max((self.staged[(r.stream, r.seq)] for r in reqs), key=lambda t: t[2])
             if cev[1] is not None:
+                if not cev[1].query():
+                    cev[1].synchronize()
                 st.wait_event(cev[1])
             if last_update is not None:
                 st.wait_event(last_update[0])
@@ -344,7 +372,7 @@ class GpuExecutor:
                 s = self.streams[r.stream]
                 k = self.staged[(r.stream, r.seq)][0]
                 descs.append(self._block_desc(self.X_slot[r.stream][k],
-                                              self.noise[r.stream][r.k_version % 2],
+                                              self.noise[r.stream][r.k_version % self.NH],
                                               self.H[s.M], s.grid.n_az, s.grid.n_el, s.Ns,
                                               self.pk[lane][i], self.pv[lane][i]))
             ssl_localize_batch(self.ctxs[lane], descs, self.prec, self.p, stream=st)
@@ -356,10 +384,9 @@ class GpuExecutor:
         self.inflight[lane] = (reqs, ev, self._launch_updates(reqs, ev))
 
     def _launch_updates(self, reqs: List["Request"], ev):
-        """K EMA updates of the blocks of a batch, queued behind it (the batch may read the handle
-        they write, and it waited for their frames' upload): one library call on the update
-        stream, all their bins in one launch pair per channel class.  Returns the completion event
-        (None if no block of the batch updates K)."""
+        """K EMA updates of the blocks of a batch, launched with it: one library call on the
+        update stream (updates run in launch order there), all their bins in one launch pair per
+        channel class.  Returns the completion event (None if no block of the batch updates K)."""
         from . import ssl_noise_update_frames_from
         torch = self.torch
         ups = [r for r in reqs if (r.seq + 1) % self.k_every == 0]
@@ -369,11 +396,12 @@ class GpuExecutor:
         self.next_uctx = (i + 1) % len(self.uctx)
         ns = self.ustream
         with torch.cuda.stream(ns):
-            ns.wait_event(ev)
+            # no wait on the batch: the update writes a handle no block in flight reads, and its
+            # inputs (the source K, ordered on this stream; the uploaded frames) are complete
             v = [self.k_version[r.stream] for r in ups]
             ssl_noise_update_frames_from(
-                self.uctx[i], [self.noise[r.stream][(vv + 1) % 2] for r, vv in zip(ups, v)],
-                [self.noise[r.stream][vv % 2] for r, vv in zip(ups, v)],
+                self.uctx[i], [self.noise[r.stream][(vv + 1) % self.NH] for r, vv in zip(ups, v)],
+                [self.noise[r.stream][vv % self.NH] for r, vv in zip(ups, v)],
                 [self.Xn_slot[r.stream][self.staged[(r.stream, r.seq)][0]] for r in ups],
                 self.alpha, stream=ns)
             done = torch.cuda.Event()
@@ -381,7 +409,7 @@ class GpuExecutor:
         self.n_updates += 1
         for r in ups:
             self.k_version[r.stream] += 1
-            self.k_done[r.stream][self.k_version[r.stream] % 2] = (done, self.n_updates)
+            self.k_done[r.stream][self.k_version[r.stream] % self.NH] = (done, self.n_updates)
         return done
 
     def poll(self, lane: int) -> bool:
@@ -400,7 +428,7 @@ class GpuExecutor:
         for r in reqs:                            # release the slots, reusable after their readers
             k = self.staged.pop((r.stream, r.seq))[0]
             self.slot_owner[r.stream][k] = None
-            self.slot_free[r.stream][k] = done if (r.seq + 1) % self.k_every == 0 else ev
+            self.slot_free[r.stream][k] = (ev, done) if (r.seq + 1) % self.k_every == 0 else (ev,)
             if self.waiting[r.stream]:
                 self.to_pump.add(r.stream)
         self.inflight[lane] = None
@@ -408,8 +436,8 @@ class GpuExecutor:
     def close(self) -> None:
         from . import ssl_ctx_destroy, ssl_noise_destroy
         self.torch.cuda.synchronize()
-        for pair in self.noise:
-            for n in pair:
+        for ring in self.noise:
+            for n in ring:
                 ssl_noise_destroy(n)
         for c in self.ctxs + self.uctx:
             ssl_ctx_destroy(c)
