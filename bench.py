@@ -192,6 +192,29 @@ def serving_phase(args, variants: dict) -> dict:
     if args.serve_light_period_ms > 0:
         out["serving_light"] = serve(args.serve_light_period_ms)
     ex.close()
+    if args.serve_fp32_seconds > 0:
+        # the plain FP32 path served one block per call (one lane, batches of one block), same
+        # streams and load, a shorter emission window: its capacity is far below the load
+        H32 = {}
+        for s_ in streams:
+            if s_.M not in H32:
+                H32[s_.M] = torch.from_numpy(synth.steering_table(s_.pos, s_.grid, s_.freqs)).to(dev)
+        ex1 = GpuExecutor(streams, H32, prec=S.SSL_FP32, alpha=0.95,
+                          k_update_every=args.k_update_every, hbm_budget_bytes=budget, lanes=1,
+                          pool=4, k_lag=args.k_lag)
+        srv1 = Server(ex1, budget, max_batch=1)
+        srv1.run(synth.poisson_arrivals(len(streams), 0.05, args.serve_period_ms * 1e-3, seed=7))
+        arrivals = synth.poisson_arrivals(len(streams), args.serve_fp32_seconds,
+                                          args.serve_period_ms * 1e-3)
+        sv = srv1.run(arrivals)
+        ex1.close()
+        out["serving_fp32_per_block"] = {
+            "period_ms": args.serve_period_ms, "prec": "fp32", "lanes": 1, "max_batch": 1,
+            "offered_blocks_per_s": round(len(arrivals) / args.serve_fp32_seconds, 1),
+            "completed": sv["completed"], "blocks_per_s": round(sv["blocks_per_s"], 1),
+            "p50_ms": round(sv["p50_ms"], 3), "p99_ms": round(sv["p99_ms"], 3),
+            "emitted_seconds": args.serve_fp32_seconds,
+            "kind": "same streams and load; FP32 MFMA inputs, one block per batch on one lane"}
     out["latency_ms"] = {"p50": out["serving"]["p50_ms"], "p99": out["serving"]["p99_ms"],
                          "kind": "served: emission to peaks on the host"}
     return out
@@ -315,6 +338,8 @@ def main() -> int:
     ap.add_argument("--uneven-blocks", type=int, default=512,
                     help="blocks of the uneven-shape batch (0 = skip)")
     ap.add_argument("--uneven-steps", type=int, default=5)
+    ap.add_argument("--serve-fp32-seconds", type=float, default=1.0,
+                    help="emission window of the FP32 one-block-per-call serving comparison (0 = skip)")
     ap.add_argument("--serve-inproc", action="store_true",
                     help="run the serving phase in this process instead of a fresh child")
     ap.add_argument("--serve-child", metavar="VARIANTS_JSON", default=None,
