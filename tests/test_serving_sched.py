@@ -145,3 +145,29 @@ def test_stream_depth_two():
     st1, ex1 = run(arr, [1] * 4, budget=1 << 20, lanes=2, depth=1)
     assert ex1.max_depth == 1
     assert max(r.done_t for r in st["requests"]) < max(r.done_t for r in st1["requests"])
+
+
+def test_ready_hook_delays_blocks():
+    """A block the executor reports not ready (inputs still uploading) stays out of batches until
+    it is; everything completes, per-stream order holds, and no block runs before it is ready."""
+    clk = FakeClock()
+    ex = FakeExecutor(clk, [1] * 8, lanes=2, a=1e-3, b=1e-4)
+    upload_s = 2e-3
+    ex.ready = lambda r: clk() >= r.emit_t + upload_s
+    seen = []
+    orig = ex.submit
+
+    def submit(lane, reqs):
+        for r in reqs:
+            seen.append(clk() - r.emit_t)
+        orig(lane, reqs)
+    ex.submit = submit
+    arr = synth.poisson_arrivals(8, 0.05, 0.005, seed=5)
+    st = Server(ex, 1 << 20, max_batch=16, clock=clk, sleep=clk.sleep, poll_s=1e-4).run(arr)
+    assert st["completed"] == len(arr)
+    assert min(seen) >= upload_s - 1e-12
+    order = {}
+    for _, _, items in ex.log:
+        for s, q in items:
+            assert q == order.get(s, -1) + 1
+            order[s] = q
