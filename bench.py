@@ -645,11 +645,15 @@ def main() -> int:
             import subprocess
             cmd = [sys.executable, os.path.abspath(__file__)] + sys.argv[1:] + [
                 "--serve-child", json.dumps(variants)]
-            res = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=600)
-            if res.returncode != 0:
-                print(f"serving child failed with status {res.returncode}", file=sys.stderr)
-                return res.returncode or 1
-            sv = json.loads(res.stdout.strip().splitlines()[-1])
+            try:
+                res = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=600)
+                if res.returncode != 0:
+                    raise RuntimeError(f"serving process exited with status {res.returncode}")
+                sv = json.loads(res.stdout.strip().splitlines()[-1])
+            except (RuntimeError, ValueError, IndexError, subprocess.TimeoutExpired) as exc:
+                # the throughput results above stand; the line says why serving is missing
+                print(f"serving phase failed: {exc}", file=sys.stderr)
+                sv = {"serving_error": str(exc)}
         out.update(sv)
 
     if not args.no_cpu:
