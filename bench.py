@@ -8,9 +8,10 @@ spectrum (eq.5), bin sum (eq.6) and peak search -- over one batch of `--batch` d
 ssl_localize_batch (all HIP kernels of the library).  Inputs (distinct seeded blocks, steering
 table, resident noise factor) are in HBM before any timed region starts.
 
-The headline path is mixed precision (`--prec`, default bf16: correlation and projection on
-16-bit MFMA inputs with FP32 accumulation, K^{-1}R in FP64, the Jacobi SVD in FP32); the plain
-FP32 path is measured in the same run, batched and one block per call, for comparison.
+The headline path (`--prec`, default fp32) is the paper's arithmetic: correlation and projection
+on FP32 MFMA, K^{-1}R in FP64, the Jacobi SVD in FP32.  The mixed-precision paths (bf16 and fp16
+MFMA inputs with FP32 accumulation, the rest unchanged) are measured in the same run as secondary
+keys, batched and one block per call.
 
 Timed regions per precision (each bracketed by torch.cuda.synchronize()):
   * main: `--steps` batch steps with per-kernel HIP events on the launch stream -> `value`, the
@@ -19,8 +20,10 @@ Timed regions per precision (each bracketed by torch.cuda.synchronize()):
   * per-block: ssl_localize one block at a time -> `per_block`;
   * host-to-device (headline precision): the same steps with every block's X copied from pinned
     host memory, serial and double-buffered on a side stream -> `h2d`.
-Serving (headline precision): 64 array streams through paper_2504_03373_amd.serving.
-The FP64 CPU oracle is timed on a bounded sample of the same workload on this host's cores.
+Serving: 64 array streams through paper_2504_03373_amd.serving, batched at the headline precision
+(its p50/p99 are `latency_ms`) and at bf16, and the FP32 path one block per call for comparison.
+The FP64 CPU oracle is timed on a bounded sample of the same workload on this host's cores, and
+the headline step's results for those blocks are compared with it (`cpu_baseline.parity`).
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -36,6 +39,7 @@ sys.path.insert(0, ROOT)
 
 # MI355X published peaks
 PEAK_FP32_VECTOR_TFLOPS = 157.3   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
+PEAK_FP32_UNPACKED_TFLOPS = 78.6  # the same without packed FP32, which this build leaves off
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 PEAK_MFMA_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0}
@@ -134,9 +138,10 @@ def pmc_summarize(fetch_dir: str, write_dir: str, calib_mb: int, batch: int) -> 
 
 
 def serving_phase(args, variants: dict) -> dict:
-    """Serving: `--serve-streams` array streams through paper_2504_03373_amd.serving at the
-    configured load (and the light one), with the kernel variants tuned for the 60-channel class
-    (`variants`) applied to the serving contexts."""
+    """Serving: `--serve-streams` array streams through paper_2504_03373_amd.serving, batched at
+    the headline precision (the configured load and the light one) and at bf16 (the configured
+    load), then the FP32 path one block per call; the kernel variants tuned for the 60-channel
+    class (`variants`) are applied to the serving contexts."""
     import torch
 
     import paper_2504_03373_amd as S
@@ -145,63 +150,73 @@ def serving_phase(args, variants: dict) -> dict:
     dev = "cuda:0"
     S.lib()
     PREC = {"fp32": S.SSL_FP32, "bf16": S.SSL_BF16, "fp16": S.SSL_FP16}
-    prec = PREC[args.prec]
     streams = synth.serving_streams(n_streams=args.serve_streams)
-    Hs = {}
+    H32 = {}
     for s_ in streams:
-        if s_.M not in Hs:
-            h = torch.from_numpy(synth.steering_table(s_.pos, s_.grid, s_.freqs)).to(dev)
-            if prec != S.SSL_FP32:
-                h = torch.view_as_real(h).reshape(s_.F, s_.D, 2 * s_.M).to(
-                    torch.bfloat16 if prec == S.SSL_BF16 else torch.float16).contiguous()
-            Hs[s_.M] = h
+        if s_.M not in H32:
+            H32[s_.M] = torch.from_numpy(synth.steering_table(s_.pos, s_.grid, s_.freqs)).to(dev)
+
+    def tables(prec):
+        if prec == S.SSL_FP32:
+            return H32
+        dt = torch.bfloat16 if prec == S.SSL_BF16 else torch.float16
+        return {M: torch.view_as_real(h).reshape(h.shape[0], h.shape[1], 2 * M).to(dt).contiguous()
+                for M, h in H32.items()}
+
     budget = int(args.serve_budget_gb * (1 << 30))
     M, Ns = variants["M"], variants["Ns"]
-
-    def configure(c):
-        if variants.get("jacobi_lanes"):
-            S.ssl_ctx_set_jacobi_lanes(c, M, variants["jacobi_lanes"])
-        if variants.get("steer_waves"):
-            S.ssl_ctx_set_steer_waves(c, M, Ns, prec, variants["steer_waves"])
-
-    ex = GpuExecutor(streams, Hs, prec=prec, alpha=0.95, k_update_every=args.k_update_every,
-                     hbm_budget_bytes=budget, lanes=args.serve_lanes, pool=4,
-                     configure=configure, k_lag=args.k_lag)
-    srv = Server(ex, budget, max_batch=128)
-    srv.run(synth.poisson_arrivals(len(streams), 0.1, args.serve_period_ms * 1e-3, seed=7))
     mix = {m: sum(1 for s_ in streams if s_.M == m) for m in sorted({s_.M for s_ in streams})}
 
-    def serve(period_ms: float) -> dict:
-        arrivals = synth.poisson_arrivals(len(streams), args.serve_seconds, period_ms * 1e-3)
+    def executor(pname, lanes=None):
+        prec = PREC[pname]
+
+        def configure(c):
+            if variants.get("jacobi_lanes"):
+                S.ssl_ctx_set_jacobi_lanes(c, M, variants["jacobi_lanes"])
+            w_ = (variants.get("steer_waves") or {}).get(pname)
+            if w_:
+                S.ssl_ctx_set_steer_waves(c, M, Ns, prec, w_)
+
+        return GpuExecutor(streams, tables(prec), prec=prec, alpha=0.95,
+                           k_update_every=args.k_update_every, hbm_budget_bytes=budget,
+                           lanes=args.serve_lanes if lanes is None else lanes, pool=4,
+                           configure=configure, k_lag=args.k_lag)
+
+    def serve(srv, ex, pname, period_ms: float, seconds: float) -> dict:
+        arrivals = synth.poisson_arrivals(len(streams), seconds, period_ms * 1e-3)
         sv = srv.run(arrivals)
         return {"streams": len(streams), "streams_by_M": mix, "period_ms": period_ms,
-                "prec": args.prec,
-                "offered_blocks_per_s": round(len(arrivals) / args.serve_seconds, 1),
+                "prec": pname, "offered_blocks_per_s": round(len(arrivals) / seconds, 1),
                 "completed": sv["completed"], "blocks_per_s": round(sv["blocks_per_s"], 1),
                 "p50_ms": round(sv["p50_ms"], 3), "p99_ms": round(sv["p99_ms"], 3),
                 "max_ms": round(sv["max_ms"], 3), "mean_batch": round(sv["mean_batch"], 2),
                 "max_queue": sv["max_queue"], "k_update_every": args.k_update_every,
                 "k_lag": args.k_lag, "stream_depth": ex.stream_depth,
-                "hbm_budget_gb": args.serve_budget_gb, "emitted_seconds": args.serve_seconds,
-                "lanes": args.serve_lanes, "process": "in-process" if args.serve_inproc else
+                "hbm_budget_gb": args.serve_budget_gb, "emitted_seconds": seconds,
+                "lanes": ex.lanes, "process": "in-process" if args.serve_inproc else
                 "child process",
                 "host_s": {k: round(sv[k], 3) for k in ("loop_s", "submit_s", "collect_s",
                                                         "sleep_s")}}
 
-    out = {"serving": serve(args.serve_period_ms)}
-    if args.serve_light_period_ms > 0:
-        out["serving_light"] = serve(args.serve_light_period_ms)
-    ex.close()
+    out = {}
+    legs = [(args.prec, "serving", True)]
+    if args.serve_mixed and args.serve_mixed != args.prec:
+        legs.append((args.serve_mixed, f"serving_{args.serve_mixed}", False))
+    for pname, key, headline in legs:
+        ex = executor(pname)
+        srv = Server(ex, budget, max_batch=128)
+        srv.run(synth.poisson_arrivals(len(streams), 0.1, args.serve_period_ms * 1e-3, seed=7))
+        out[key] = serve(srv, ex, pname, args.serve_period_ms, args.serve_seconds)
+        if headline and args.serve_light_period_ms > 0:
+            out["serving_light"] = serve(srv, ex, pname, args.serve_light_period_ms,
+                                         args.serve_seconds)
+        ex.close()
+        del ex, srv
+        torch.cuda.synchronize()
     if args.serve_fp32_seconds > 0:
         # the plain FP32 path served one block per call (one lane, batches of one block), same
         # streams and load, a shorter emission window: its capacity is far below the load
-        H32 = {}
-        for s_ in streams:
-            if s_.M not in H32:
-                H32[s_.M] = torch.from_numpy(synth.steering_table(s_.pos, s_.grid, s_.freqs)).to(dev)
-        ex1 = GpuExecutor(streams, H32, prec=S.SSL_FP32, alpha=0.95,
-                          k_update_every=args.k_update_every, hbm_budget_bytes=budget, lanes=1,
-                          pool=4, k_lag=args.k_lag)
+        ex1 = executor("fp32", lanes=1)
         srv1 = Server(ex1, budget, max_batch=1)
         srv1.run(synth.poisson_arrivals(len(streams), 0.05, args.serve_period_ms * 1e-3, seed=7))
         arrivals = synth.poisson_arrivals(len(streams), args.serve_fp32_seconds,
@@ -216,7 +231,7 @@ def serving_phase(args, variants: dict) -> dict:
             "emitted_seconds": args.serve_fp32_seconds,
             "kind": "same streams and load; FP32 MFMA inputs, one block per batch on one lane"}
     out["latency_ms"] = {"p50": out["serving"]["p50_ms"], "p99": out["serving"]["p99_ms"],
-                         "kind": "served: emission to peaks on the host"}
+                         "prec": args.prec, "kind": "served, batched: emission to peaks on the host"}
     return out
 
 
@@ -307,10 +322,11 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20, help="timed batch steps")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=128, help="blocks per step")
-    ap.add_argument("--prec", choices=["fp32", "bf16", "fp16"], default="bf16",
+    ap.add_argument("--prec", choices=["fp32", "bf16", "fp16"], default="fp32",
                     help="MFMA input type of the headline path")
-    ap.add_argument("--no-fp32-compare", action="store_true",
-                    help="skip the FP32 comparison paths")
+    ap.add_argument("--compare", default="bf16,fp16",
+                    help="comma-separated secondary MFMA input types measured in the same run "
+                         "('' = none)")
     ap.add_argument("--no-h2d", action="store_true",
                     help="skip the host-to-device region (its copies share the CUs)")
     ap.add_argument("--per-block-steps", type=int, default=100)
@@ -338,6 +354,8 @@ def main() -> int:
     ap.add_argument("--uneven-blocks", type=int, default=512,
                     help="blocks of the uneven-shape batch (0 = skip)")
     ap.add_argument("--uneven-steps", type=int, default=5)
+    ap.add_argument("--serve-mixed", default="bf16",
+                    help="a second batched serving leg at this MFMA input type ('' = skip)")
     ap.add_argument("--serve-fp32-seconds", type=float, default=1.0,
                     help="emission window of the FP32 one-block-per-call serving comparison (0 = skip)")
     ap.add_argument("--serve-inproc", action="store_true",
@@ -417,17 +435,17 @@ def main() -> int:
 
     tuning = {}
 
-    def measure(name: str, with_h2d: bool) -> dict:
+    def measure(name: str, with_h2d: bool, conv: bool = True) -> dict:
         prec = PREC[name]
         H = table(name)
         # Jacobi sweep / rotation counts for the flop model: same kernel variant, same inputs,
         # deterministic, so they are those of the timed launches.
         R = torch.zeros((F, M, M), dtype=torch.complex64, device=dev)
         En = torch.zeros((F, M - Ns, M), dtype=torch.complex64, device=dev)
-        conv = torch.zeros((F, 3), dtype=torch.int32, device=dev)
+        conv_t = torch.zeros((F, 3), dtype=torch.int32, device=dev)
         if not args.no_autotune:
             S.ssl_corr_accum(ctx, Xs[0], 1.0 / T, 0, prec, R)
-            S.ssl_gsvd(ctx, R, noise, Ns, En, None, None, conv, 0)
+            S.ssl_gsvd(ctx, R, noise, Ns, En, None, None, conv_t, 0)
             # variants chosen on this workload, each timed in the batched form the step runs: the
             # Jacobi lanes per column pair (once; the SVD is FP32 whatever the input precision)
             # and the projection tile for this precision, B blocks sharing the steering table
@@ -439,10 +457,10 @@ def main() -> int:
             tuning.setdefault("steer_waves", {})[name] = waves
             tuning.setdefault("steer_ms", {})[name] = {str(k): round(v, 4) for k, v in sms.items()}
         conv_all = []
-        for b in range(B):
+        for b in range(B if conv else 0):
             S.ssl_corr_accum(ctx, Xs[b], 1.0 / T, 0, prec, R)
-            S.ssl_gsvd(ctx, R, noise, Ns, En, None, None, conv, 0)
-            conv_all.append(conv.cpu().numpy().copy())
+            S.ssl_gsvd(ctx, R, noise, Ns, En, None, None, conv_t, 0)
+            conv_all.append(conv_t.cpu().numpy().copy())
         del R, En
         jflops = float(sum(jacobi_flops(M, c[:, 0], c[:, 1], c[:, 2]) for c in conv_all))
         descs = [S.block_desc(Xs[b], noise, H, w.grid.n_az, w.grid.n_el, Ns, pk[b], pv[b],
@@ -573,12 +591,16 @@ def main() -> int:
         return out
 
     main_r = measure(args.prec, with_h2d=not args.no_h2d)
-    f32 = main_r if args.prec == "fp32" else (None if args.no_fp32_compare
-                                                else measure("fp32", with_h2d=False))
+    # the headline step's outputs, kept for the comparison with the oracle below
+    head_pk, head_pv, head_pbar = pk.cpu().numpy(), pv.cpu().numpy(), Pbar.cpu().numpy()
+    compare = [c for c in args.compare.split(",") if c and c != args.prec]
+    sec = {c: measure(c, with_h2d=False, conv=False) for c in compare}
+    f32 = main_r if args.prec == "fp32" else sec.get("fp32")
 
     avg = main_r["avg"]
     roofline = {"kernel": "jacobi_persistent", **{k: main_r["rl"]["jacobi"][k] for k in
                                                    ("bound", "achieved", "peak", "unit", "frac")},
+                "frac_unpacked": round(main_r["rl"]["jacobi"]["achieved"] / PEAK_FP32_UNPACKED_TFLOPS, 4),
                 "traffic": traffic_bytes(B), "avg_launch_ms": round(avg["jacobi"], 4),
                 "flops_per_launch": main_r["jflops"], "bins_per_launch": B * F}
     conv_all = main_r["conv"]
@@ -613,7 +635,7 @@ def main() -> int:
         "jacobi_sweeps": {"mean": round(float(np.mean([c[:, 0].mean() for c in conv_all])), 3),
                           "max": int(max(c[:, 0].max() for c in conv_all)),
                           "mean_rank": round(float(np.mean([c[:, 2].mean() for c in conv_all])), 2)},
-        "status_ok": main_r["status_ok"] and (f32 is None or f32["status_ok"]),
+        "status_ok": main_r["status_ok"] and all(r["status_ok"] for r in sec.values()),
         "input_gen_s": round(gen_s, 2),
         "tuning": tuning or "defaults (--no-autotune)",
     }
@@ -625,18 +647,22 @@ def main() -> int:
                       "unit": "blocks/s", "bytes_per_block": F * T * M * 8,
                       "kind": "X from pinned host memory each step (copy then compute; copy of "
                               "the next step on a side stream under the compute)"}
+    for c, r in sec.items():
+        out[c] = {"value": round(r["value"], 2), "graph_value": round(r["graph_value"], 2),
+                  "per_block": round(r["per_block"], 2), "unit": "blocks/s",
+                  "ms_per_step": round(1000.0 * r["elapsed"] / args.steps, 4),
+                  "kernels": {k: round(v, 4) for k, v in r["avg"].items()},
+                  "steer_roofline": r["rl"]["steer"], "corr_roofline": r["rl"]["corr"],
+                  "kind": f"{c} MFMA inputs for the correlation and the projection (FP32 "
+                          f"accumulation), FP64 whitening, FP32 Jacobi: batched, and one block "
+                          f"per call"}
     if f32 is not None:
-        out["fp32"] = {"value": round(f32["value"], 2), "graph_value": round(f32["graph_value"], 2),
-                       "per_block": round(f32["per_block"], 2), "unit": "blocks/s",
-                       "ms_per_step": round(1000.0 * f32["elapsed"] / args.steps, 4),
-                       "kernels": {k: round(v, 4) for k, v in f32["avg"].items()},
-                       "steer_roofline": f32["rl"]["steer"], "corr_roofline": f32["rl"]["corr"],
-                       "kind": "plain FP32 path: batched, and one block per call"}
-        out["speedup_vs_fp32_per_block"] = round(main_r["value"] / f32["per_block"], 3)
+        best = max([main_r] + list(sec.values()), key=lambda r: r["value"])
+        out["speedup_vs_fp32_per_block"] = round(best["value"] / f32["per_block"], 3)
 
     if args.serve_seconds > 0:
         variants = {"M": M, "Ns": Ns, "jacobi_lanes": tuning.get("jacobi_lanes"),
-                    "steer_waves": tuning.get("steer_waves", {}).get(args.prec)}
+                    "steer_waves": tuning.get("steer_waves", {})}
         if args.serve_inproc:
             sv = serving_phase(args, variants)
         else:
@@ -661,16 +687,24 @@ def main() -> int:
         cores = len(os.sched_getaffinity(0))
         Kh = oracle.noise_corr(Xn.cpu().numpy())
         Hh = w.steering_table()
-        nb = max(1, args.cpu_blocks)
+        nb = max(1, min(args.cpu_blocks, B))
         blocks = [w.block(b)[0] for b in range(nb)]
         tc = time.perf_counter()
-        for X in blocks:
-            oracle.localize(X, Kh, Hh, w.grid.n_az, w.grid.n_el, Ns, nthreads=cores)
+        refs = [oracle.localize(X, Kh, Hh, w.grid.n_az, w.grid.n_el, Ns, nthreads=cores)
+                for X in blocks]
         cpu_s = time.perf_counter() - tc
+        rel = [float(np.max(np.abs(head_pbar[b].astype(np.float64) - r["Pbar"]) / r["Pbar"]))
+               for b, r in enumerate(refs)]
         out["cpu_baseline"] = {"value": round(nb / cpu_s, 4), "unit": "blocks/s", "cores": cores,
                                "kind": "oracle",
                                "sample": f"{nb} blocks of the same 60ch/257-bin/1368-dir workload, "
-                                         f"FP64 oracle end to end, threads over bins, {cpu_s:.1f} s"}
+                                         f"FP64 oracle end to end, threads over bins, {cpu_s:.1f} s",
+                               "parity": {"blocks": nb, "prec": args.prec,
+                                          "pbar_rel_max": float(f"{max(rel):.3g}"),
+                                          "peaks_equal": sum(bool(np.array_equal(head_pk[b], r["peaks"]))
+                                                             for b, r in enumerate(refs)),
+                                          "kind": "the headline step's Pbar and peaks of these "
+                                                  "blocks against the oracle's"}}
 
     S.ssl_noise_destroy(noise)
     S.ssl_ctx_destroy(ctx)

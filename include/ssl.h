@@ -156,7 +156,8 @@ void ssl_noise_destroy(ssl_noise K);
 
 /* For every bin f: A = K^{-1} R (FP64 product with the handle's inverse, rounded to complex64),
  * then the SVD A = U Sigma V^H by one-sided Jacobi in FP32 with the whole M x M problem resident in
- * LDS (convergence test in FP64: |b_i^H b_j| <= M 2^-24 |b_i||b_j| for every pair of a sweep),
+ * LDS (a pair is rotated iff |b_i^H b_j| > 2 sqrt(M) 2^-24 |b_i||b_j|, the inner products
+ * accumulated in FP32 and the comparison made in FP64; a sweep without a rotation ends the solve),
  * singular values sorted descending (ties: lower column first), and
  *   En[f] = U[:, Ns..M-1]   written column-major: [F][M-Ns][M] ssl_c64.
  * R: [F][M][M] ssl_c64 (e.g. from ssl_corr_accum).  K: a handle set for the same F and M.

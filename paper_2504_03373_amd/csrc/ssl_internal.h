@@ -63,7 +63,7 @@ struct ssl_noise_s {
     int F, M;
     bool is_set;
     ssl_c128 *K;       // [F][M][M] current noise correlation
-    ssl_c128 *Kinv;    // [F][M][M] FP64 inverse from the Cholesky factor
+    ssl_c128 *Kinv;    // [F][M][M] FP64 inverse by Gauss-Jordan elimination
     int32_t *status;   // [F] SSL_BIN_OK / SSL_BIN_NOT_PD
 };
 

@@ -10,8 +10,12 @@ fresh FP64 inverse).  With a lag of L blocks (k_lag), block n runs on the K that
 noise of blocks <= n - 1 - L: at L = 0 the update of block n lands before block n + 1 runs; at
 L = 1 (the default) it runs beside block n + 1, so the update is off the stream's round trip.
 K versions live in a ring of four handles per stream: an update writes a handle no block in
-flight reads, and a block is submitted only once the host has seen its inputs (upload, K version)
-complete, so no correctness rests on a device-side wait between streams.
+flight reads.  Every dependency between HIP streams is a device-side wait on the producer's event:
+a batch waits for the uploads of its blocks and for the updates producing the K versions they
+read, an update waits for the upload of the noise-only frames it reads (whichever stream carried
+it), and a slot is overwritten only after its previous batch and update (on the host, or by a
+device wait when the upload rides on the lane stream).  The host-side readiness checks
+(`ready`) are scheduling policy only: they keep a batch from queueing behind work in flight.
 
 Rules: at most `stream_depth` blocks per stream are in flight (an executor attribute, 1 if
 absent; the GPU executor allows 1 + k_lag, the most for which the K versions the blocks read are
@@ -46,6 +50,7 @@ class Request:
     k_version: int = -1          # EMA updates applied to the stream's K before this block ran
     peaks: np.ndarray = None
     peak_val: np.ndarray = None
+    Pbar: np.ndarray = None      # eq.6 spectrum of the block (only with GpuExecutor(keep_pbar=True))
 
 
 class Server:
@@ -170,13 +175,16 @@ class GpuExecutor:
     block is uploaded from pinned host memory on a copy stream as soon as it is emitted and a slot
     is free, so uploads overlap the batches on the device; a batch then only waits for its blocks'
     copy events.  A slot frees when its block's K update (or, without one, its batch) has run; a
-    block still unstaged when its batch is formed is uploaded on the lane stream.
+    block still unstaged when its batch is formed is uploaded on the lane stream, after a device
+    wait for the slot's previous readers.  `stage_at_arrival=False` uploads every block that way
+    (a test of that path).  `keep_pbar=True` also copies each block's Pbar back to the host.
     """
 
     def __init__(self, streams, steering, prec=None, p: int = 2, alpha: float = 0.95,
                  k_update_every: int = 1, hbm_budget_bytes: int = 4 << 30, lanes: int = 2,
                  pool: int = 4, device: int = 0, update_contexts: int = 4, configure=None,
-                 slots: int = 4, k_lag: int = 1):
+                 slots: int = 4, k_lag: int = 1, stage_at_arrival: bool = True,
+                 keep_pbar: bool = False):
         import torch
 
         from . import (SSL_FP32, SSL_FP64, block_desc, ssl_corr_accum, ssl_ctx_create,
@@ -267,6 +275,14 @@ class GpuExecutor:
         self.pv = [torch.zeros((nmax, 3), dtype=torch.float32, device=self.dev) for _ in range(lanes)]
         self.pk_h = [torch.zeros((nmax, 3), dtype=torch.int32).pin_memory() for _ in range(lanes)]
         self.pv_h = [torch.zeros((nmax, 3), dtype=torch.float32).pin_memory() for _ in range(lanes)]
+        self.stage_at_arrival = stage_at_arrival
+        self.keep_pbar = keep_pbar
+        if keep_pbar:
+            nb, dmax = 512, max(s.D for s in self.streams)
+            self.pb = [torch.zeros((nb, dmax), dtype=torch.float32, device=self.dev)
+                       for _ in range(lanes)]
+            self.pb_h = [torch.zeros((nb, dmax), dtype=torch.float32).pin_memory()
+                         for _ in range(lanes)]
         self.inflight = [None] * lanes
 
     def cost_bytes(self, sid: int) -> int:
@@ -280,19 +296,24 @@ class GpuExecutor:
         return ws + 2 * F * s.T * M * 8
 
     def _stage(self, r: "Request", k: int, st) -> None:
-        """Upload block r into slot k of its stream on HIP stream st; the slot's previous readers
-        have completed (the callers check on the host)."""
+        """Upload block r into slot k of its stream on HIP stream st.  On the copy stream the
+        caller has seen the slot's previous readers complete; on a lane stream the copy waits for
+        them on the device.  Records the upload's completion event: (slot, event, staging number
+        on the copy stream or -1 on a lane stream)."""
         torch = self.torch
         sid = r.stream
         self.slot_owner[sid][k] = r
         with torch.cuda.stream(st):
+            if st is not self.cstream:
+                for e in self.slot_free[sid][k]:
+                    st.wait_event(e)
             self.slot_free[sid][k] = ()
             self.X_slot[sid][k].copy_(self.X_pool[sid][r.seq % self.pool], non_blocking=True)
             self.Xn_slot[sid][k].copy_(self.Xn_pool[sid][r.seq % self.pool], non_blocking=True)
-            ev, num = None, -1                    # staged on the lane stream: no wait
+            ev = torch.cuda.Event()
+            ev.record(st)
+            num = -1
             if st is self.cstream:               # copies complete in staging order
-                ev = torch.cuda.Event()
-                ev.record(st)
                 self.n_staged += 1
                 num = self.n_staged
         self.staged[(sid, r.seq)] = (k, ev, num)
@@ -316,15 +337,18 @@ class GpuExecutor:
         self.to_pump.discard(sid)
 
     def arrive(self, r: "Request") -> None:
+        if not self.stage_at_arrival:
+            return
         self.waiting[r.stream].append(r)
         self._pump(r.stream)
 
     def ready(self, r: "Request") -> bool:
-        """False while r's upload on the copy stream or the K update producing the K version it
-        will read is in flight (a block not staged yet is uploaded on the lane stream at
-        submission, in order with its batch)."""
+        """Scheduling policy, not ordering: false while r's upload on the copy stream or the K
+        update producing the K version it will read is in flight, so that a batch is not queued
+        behind them (a block not staged yet is uploaded on the lane stream at submission, in
+        order with its batch)."""
         st = self.staged.get((r.stream, r.seq))
-        if st is not None and st[1] is not None and not st[1].query():
+        if st is not None and st[2] >= 0 and not st[1].query():
             return False
         kd = self.k_done[r.stream][max(0, self.k_version[r.stream] - self.k_lag) % self.NH]
         return kd is None or kd[0].query()
@@ -333,6 +357,8 @@ class GpuExecutor:
         from . import ssl_localize_batch
         torch = self.torch
         st = self.tstreams[lane]
+        if self.keep_pbar and len(reqs) > self.pb[lane].shape[0]:
+            raise ValueError(f"keep_pbar holds at most {self.pb[lane].shape[0]} blocks per batch")
         descs = []
         with torch.cuda.stream(st):
             last_update = None                    # updates complete in call order
@@ -341,44 +367,41 @@ class GpuExecutor:
                     # not uploaded yet (no slot was free, or the scheduler was not told): it is the
                     # oldest block of its stream not yet submitted, so only the stream's blocks in
                     # flight (fewer than stream_depth <= slots) own slots; the others are released
+                    # and their last readers are waited for on the device (_stage)
                     q = self.waiting[r.stream]
                     if q and q[0] is r:
                         q.popleft()
                     k = self._free_slot(r.stream, ready_only=True)
                     if k is None:
                         k = self._free_slot(r.stream, ready_only=False)
-                        for e in self.slot_free[r.stream][k]:
-                            e.synchronize()
                     self._stage(r, k, st)
                 r.k_version = max(0, self.k_version[r.stream] - self.k_lag)
                 kd = self.k_done[r.stream][r.k_version % self.NH]
-                if kd is not None and not kd[0].query():
-                    kd[0].synchronize()               # the scheduler submits ready blocks only
                 if kd is not None and (last_update is None or kd[1] > last_update[1]):
                     last_update = kd
-            # the copy stream runs in staging order: its last copy among the batch's covers all.
-            # The scheduler only submits blocks whose upload the host has seen complete (`ready`),
-            # and the host checks again here: a device-side wait on the copy stream's event alone
-            # once let a batch read a slot whose upload had not landed (a block served with no
-            # peaks).
-            cev = max((self.staged[(r.stream, r.seq)] for r in reqs), key=lambda t: t[2])
-            if cev[1] is not None:
-                if not cev[1].query():
-                    cev[1].synchronize()
-                st.wait_event(cev[1])
+            # device-side waits for every producer on another stream: the copy stream runs in
+            # staging order, so its last upload among the batch's blocks covers all of them; the
+            # update stream runs in call order, so the latest K version read covers the others
+            cp = [self.staged[(r.stream, r.seq)] for r in reqs]
+            cp = [t for t in cp if t[2] >= 0]
+            if cp:
+                st.wait_event(max(cp, key=lambda t: t[2])[1])
             if last_update is not None:
                 st.wait_event(last_update[0])
             for i, r in enumerate(reqs):
                 s = self.streams[r.stream]
                 k = self.staged[(r.stream, r.seq)][0]
+                pb = self.pb[lane][i] if self.keep_pbar else None
                 descs.append(self._block_desc(self.X_slot[r.stream][k],
                                               self.noise[r.stream][r.k_version % self.NH],
                                               self.H[s.M], s.grid.n_az, s.grid.n_el, s.Ns,
-                                              self.pk[lane][i], self.pv[lane][i]))
+                                              self.pk[lane][i], self.pv[lane][i], pb))
             ssl_localize_batch(self.ctxs[lane], descs, self.prec, self.p, stream=st)
             n = len(reqs)
             self.pk_h[lane][:n].copy_(self.pk[lane][:n], non_blocking=True)
             self.pv_h[lane][:n].copy_(self.pv[lane][:n], non_blocking=True)
+            if self.keep_pbar:
+                self.pb_h[lane][:n].copy_(self.pb[lane][:n], non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(st)
         self.inflight[lane] = (reqs, ev, self._launch_updates(reqs, ev))
@@ -396,8 +419,17 @@ class GpuExecutor:
         self.next_uctx = (i + 1) % len(self.uctx)
         ns = self.ustream
         with torch.cuda.stream(ns):
-            # no wait on the batch: the update writes a handle no block in flight reads, and its
-            # inputs (the source K, ordered on this stream; the uploaded frames) are complete
+            # no wait on the batch: the update writes a handle no block in flight reads.  Its
+            # inputs: the source K version, produced earlier on this stream; the noise-only frames,
+            # whose upload it waits for on the device (the copy stream's last one among these
+            # blocks covers the others there; every upload that rode on a lane stream separately)
+            stg = [self.staged[(r.stream, r.seq)] for r in ups]
+            cp = [t for t in stg if t[2] >= 0]
+            if cp:
+                ns.wait_event(max(cp, key=lambda t: t[2])[1])
+            for t in stg:
+                if t[2] < 0:
+                    ns.wait_event(t[1])
             v = [self.k_version[r.stream] for r in ups]
             ssl_noise_update_frames_from(
                 self.uctx[i], [self.noise[r.stream][(vv + 1) % self.NH] for r, vv in zip(ups, v)],
@@ -425,6 +457,8 @@ class GpuExecutor:
             ns = self.streams[r.stream].Ns
             r.peaks = pk[i, :ns].copy()
             r.peak_val = pv[i, :ns].copy()
+            if self.keep_pbar:
+                r.Pbar = self.pb_h[lane][i, :self.streams[r.stream].D].numpy().copy()
         for r in reqs:                            # release the slots, reusable after their readers
             k = self.staged.pop((r.stream, r.seq))[0]
             self.slot_owner[r.stream][k] = None

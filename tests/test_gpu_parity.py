@@ -12,7 +12,7 @@ import pytest
 import oracle
 import synth
 from conftest import crandn, random_pd
-from gpu_util import U32, corr_bound, peaks_ambiguous, projector, to_dev, to_host
+from gpu_util import U32, corr_bound, peak_ambiguity, projector, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -124,7 +124,7 @@ def test_corr_low_precision(S, ctx, prec):
 
 
 # ------------------------------------------------------------------------------------------------
-# A2: noise handle (FP64 Cholesky)
+# A2: noise handle (FP64 Gauss-Jordan inverse; its pivots are the Cholesky pivots of the PD test)
 # ------------------------------------------------------------------------------------------------
 def test_noise_set_get_and_not_pd(S, ctx):
     import torch
@@ -245,7 +245,7 @@ def test_gsvd_max_bins(S, ctx):
         nA = np.linalg.norm(np.linalg.solve(K[f], R[f]))
         gap = sig_ref[i, 0] - sig_ref[i, 1]
         err = np.linalg.norm(projector(g["En"][f].T.astype(np.complex128)) - projector(En_ref[i].T), 2)
-        assert err <= 16 * M * U32 * nA / gap + 1e-6, (f, err, gap)
+        assert err <= 16 * M * U32 * nA / gap, (f, err, gap)
 
 
 def test_empty_and_out_of_range_shapes(S, ctx):
@@ -395,11 +395,17 @@ def noise_from_frames(S, ctx, w):
     return n, oracle.noise_corr(Xn)
 
 
-def check_block(o_gpu, o_ref, w, rtol):
+def check_block(o_gpu, o_ref, w, Ns=None):
+    """Pbar relative error against the oracle, and the peak comparison.  A peak decision can
+    differ between two correct evaluations only where the reference values are within twice the
+    evaluation's own error of each other: the near-tie radius is this block's measured maximum
+    relative Pbar error, so outside the reasons listed the returned peaks must be identical."""
+    Ns = w.Ns if Ns is None else Ns
     rel = np.abs(o_gpu["Pbar"].astype(np.float64) - o_ref["Pbar"]) / o_ref["Pbar"]
-    amb = peaks_ambiguous(o_ref["Pbar"], w.grid.n_el, w.grid.n_az, w.Ns, rtol)
+    rel = float(rel.max())
+    amb = peak_ambiguity(o_ref["Pbar"], w.grid.n_el, w.grid.n_az, Ns, max(rel, 1e-7))
     same = np.array_equal(o_gpu["peaks"], o_ref["peaks"])
-    return float(rel.max()), same, amb
+    return rel, same, amb
 
 
 @pytest.mark.parametrize("blocks", [range(10)])
@@ -416,34 +422,41 @@ def test_localize_small_workload(S, ctx, blocks):
         g = localize_gpu(S, ctx, w, X, n, Hd)
         r = oracle.localize(X, K, H, w.grid.n_az, w.grid.n_el, w.Ns, nthreads=8)
         assert np.all(g["status"] == 0) and np.all(r["status"] == 0)
-        rel, same, amb = check_block(g, r, w, 1e-4)
+        rel, same, amb = check_block(g, r, w)
         worst = max(worst, rel)
         assert rel <= 1e-4, (b, rel)
-        assert same or amb, (b, g["peaks"], r["peaks"])
+        assert not amb, (b, amb)
+        assert same, (b, g["peaks"], r["peaks"])
         assert g["peaks"][0] == dirs[0]
     say(f"  max Pbar relative error {worst:.3g}")
     S.ssl_noise_destroy(n)
 
 
 def test_localize_paper_workload(S, ctx):
-    """60-mic, 257-bin, 1368-direction blocks at full size: peaks bit-exact, Pbar within 1e-4."""
+    """60-mic, 257-bin, 1368-direction blocks at full size (the paper-scale workload, eight seeded
+    blocks): Pbar within 1e-4 of the FP64 oracle, no near-tie within the measured error, and the
+    returned peaks identical."""
     w = synth.workload_paper(n_blocks=1000)
     n, K = noise_from_frames(S, ctx, w)
     H = w.steering_table()
     Hd = to_dev(H)
     worst = 0.0
-    for b in (0, 1):
+    for b in range(8):
         say(f"ssl_localize 60ch block {b}")
         X, dirs, snr = w.block(b)
         g = localize_gpu(S, ctx, w, X, n, Hd)
         r = oracle.localize(X, K, H, w.grid.n_az, w.grid.n_el, w.Ns, nthreads=16)
         assert np.array_equal(g["status"], r["status"])
-        rel, same, amb = check_block(g, r, w, 1e-4)
+        rel, same, amb = check_block(g, r, w)
         worst = max(worst, rel)
         say(f"  block {b}: snr {snr:.1f} dB, rel {rel:.3g}, peaks gpu {g['peaks']} ref {r['peaks']} "
-            f"src {dirs} ambiguous {amb}")
+            f"src {dirs} near-ties {amb}")
         assert rel <= 1e-4
-        assert same or amb
+        assert not amb
+        assert same
+        # the peak values are Pbar at the peaks: within the same bound
+        assert np.all(np.abs(g["peak_val"] - r["peak_val"]) <= 1e-4 * r["peak_val"])
+    say(f"  max Pbar relative error over 8 blocks {worst:.3g}")
     S.ssl_noise_destroy(n)
 
 

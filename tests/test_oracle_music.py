@@ -103,6 +103,75 @@ def test_spectrum_matches_library_evaluation(orc):
         assert np.max(np.abs(P2[f] - num / den) / P2[f]) <= 1e-12
 
 
+def test_p1_single_noise_vector_reduces_to_projector_form(orc):
+    """p = 1 (eq.5 as printed) pinned where the noise subspace is one vector, unique up to phase:
+    with M - Ns = 1, |H^H e| = sqrt(H^H Pi H), so P_1 = |H|^2 / sqrt(H^H Pi H) exactly, Pi being
+    the projector onto the null vector that LAPACK's SVD gives for a rank-(M-1) matrix.  A dropped
+    conjugate, a missing absolute value or a p = 2 square would fail it."""
+    rng = np.random.default_rng(28)
+    F, D, M = 3, 13, 6
+    Ns = M - 1
+    H = crandn(rng, F, D, M).astype(np.complex64)
+    Hd = H.astype(np.complex128)
+    En, want = [], []
+    for f in range(F):
+        B = crandn(rng, M - 1, M)                          # rank M - 1: null space of dim 1
+        e = np.linalg.svd(B)[2][-1].conj()                 # B e = 0, |e| = 1
+        assert np.linalg.norm(B @ e) <= 1e-13 * np.linalg.norm(B)
+        e = e * np.exp(1j * rng.uniform(0, 2 * np.pi))      # arbitrary phase
+        En.append(e[None, :])
+        Pi = np.outer(e, e.conj())
+        num = np.sum(np.abs(Hd[f]) ** 2, axis=1)
+        quad = np.einsum("dm,mn,dn->d", Hd[f].conj(), Pi, Hd[f]).real
+        want.append(num / np.sqrt(quad))
+    En = np.stack(En)
+    P1, Pbar1 = orc.spectrum(H, En, Ns, p=1)
+    P2, _ = orc.spectrum(H, En, Ns, p=2)
+    want = np.stack(want)
+    assert np.max(np.abs(P1 - want) / want) <= 1e-13
+    num = np.sum(np.abs(Hd) ** 2, axis=2)
+    assert np.max(np.abs(P1 - np.sqrt(num * P2)) / P1) <= 1e-13     # P_1 = sqrt(|h|^2 P_2)
+    assert np.max(np.abs(Pbar1 - want.sum(0)) / Pbar1) <= 1e-14
+
+
+def test_p1_standard_basis_noise_vectors(orc):
+    """p = 1 with coordinate vectors as the noise basis: sum_i |H^H e_i| = sum_{m in N} |H_m|
+    (closed form); the result is unchanged by a phase on each noise vector and by their order,
+    the two freedoms of an SVD with distinct singular values."""
+    rng = np.random.default_rng(29)
+    F, D, M, Ns = 2, 7, 5, 2
+    H = crandn(rng, F, D, M).astype(np.complex64)
+    Hd = H.astype(np.complex128)
+    I = np.eye(M, dtype=np.complex128)
+    En = np.stack([I[:, [4, 1, 3]].T for _ in range(F)])       # noise channels {1, 3, 4}
+    P1, _ = orc.spectrum(H, En, Ns, p=1)
+    num = np.sum(np.abs(Hd) ** 2, axis=2)
+    den = np.abs(Hd[..., 1]) + np.abs(Hd[..., 3]) + np.abs(Hd[..., 4])
+    assert np.max(np.abs(P1 - num / den) / P1) <= 1e-14
+    ph = np.exp(1j * rng.uniform(0, 2 * np.pi, (F, M - Ns)))
+    En2 = (En * ph[..., None])[:, ::-1]
+    P1b, _ = orc.spectrum(H, np.ascontiguousarray(En2), Ns, p=1)
+    assert np.max(np.abs(P1b - P1) / P1) <= 1e-14
+
+
+def test_p1_planted_source_is_unbounded(orc):
+    """Noise-free planted sources with K = I: H_s^H e_i = 0 for every noise vector, so the p = 1
+    spectrum is unbounded at the sources as well (the floor DBL_MIN in the denominator)."""
+    M, Ns = 8, 2
+    grid = synth.DirectionGrid(72, 1)
+    src = [12, 50]
+    Hs, freqs, pos = _planted(M, Ns, [5.0 * d for d in src])
+    F = freqs.shape[0]
+    R = np.einsum("fsm,fsn->fmn", Hs, Hs.conj())
+    K = np.broadcast_to(np.eye(M, dtype=np.complex128), (F, M, M)).copy()
+    En, _, st, _ = orc.gsvd(K, R, Ns)
+    H = synth.steering(pos, grid.unit_vectors(), freqs).astype(np.complex64)
+    P1, Pbar1 = orc.spectrum(H, En, Ns, p=1)
+    pk, _ = orc.peaks(Pbar1, 1, 72, Ns)
+    assert sorted(pk.tolist()) == src
+    assert Pbar1[src].min() > 1e6 * np.delete(Pbar1, src).max()
+
+
 def test_failed_bins_contribute_zero(orc):
     rng = np.random.default_rng(23)
     F, D, M, Ns = 4, 5, 4, 1
