@@ -204,6 +204,25 @@ ssl_status ssl_localize(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int M, int6
                         int n_el, int Ns, int p, int32_t *peaks, float *peak_val, float *Pbar,
                         int32_t *bin_status, void *stream);
 
+/* For callers that cannot allocate device memory -- code under HIP graph capture, allocation-free
+ * serving loops, harnesses that forbid hipMalloc: ssl_localize with the same arguments, results
+ * and errors, that allocates nothing.  Its workspace is a fixed scratch array of
+ * SSL_NOALLOC_SCRATCH_BYTES in device memory, one per device, held until the process ends (its
+ * address on a device is looked up once, by ssl_ctx_create on that device).  Needs
+ * ssl_localize_noalloc_bytes(F, M, Ns, n_az * n_el) <= SSL_NOALLOC_SCRATCH_BYTES, otherwise
+ * returns SSL_ERR_ARG and enqueues nothing (the 60-channel, 257-bin, 1368-direction block needs
+ * about 24 MB).  Never times its launches (ssl_ctx_timing does not apply), never creates events.
+ * Every call on one device shares that device's scratch, and nothing it reads starts from a
+ * previous call's contents: calls on one device must be ordered (one stream, or events between
+ * them); calls that overlap in time on one device race and give wrong results. */
+#define SSL_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+ssl_status ssl_localize_noalloc(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int M,
+                                int64_t strideF, int64_t strideT, ssl_noise K, const void *H,
+                                ssl_prec prec, int n_az, int n_el, int Ns, int p, int32_t *peaks,
+                                float *peak_val, float *Pbar, int32_t *bin_status, void *stream);
+/* Scratch bytes ssl_localize_noalloc needs for one block of this shape (0 for invalid shapes). */
+size_t ssl_localize_noalloc_bytes(int F, int M, int Ns, int D);
+
 /* ------------------------------------------------------------ batched path */
 
 /* One block of a batch.  Fields as in ssl_localize; blocks may differ in F, T, M, Ns and grid. */

@@ -20,6 +20,8 @@ SSL_OK, SSL_ERR_ARG, SSL_ERR_NOMEM, SSL_ERR_BUDGET, SSL_ERR_HIP, SSL_ERR_STATE =
 SSL_BIN_OK, SSL_BIN_NOT_PD, SSL_BIN_NO_CONV, SSL_BIN_NONFINITE = 0, 1, 2, 3
 # ssl_prec
 SSL_FP32, SSL_BF16, SSL_FP16, SSL_FP64 = 0, 1, 2, 3
+# fixed scratch of ssl_localize_noalloc (bytes, per device)
+SSL_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 EXPORTED = [
     "ssl_ctx_create", "ssl_ctx_destroy", "ssl_ctx_workspace_bytes", "ssl_last_error", "ssl_version",
@@ -30,6 +32,7 @@ EXPORTED = [
     "ssl_ctx_set_steer_waves", "ssl_ctx_get_steer_waves", "ssl_autotune_steer",
     "ssl_noise_update_frames",
     "ssl_noise_update_frames_from",
+    "ssl_localize_noalloc", "ssl_localize_noalloc_bytes",
 ]
 
 
@@ -79,6 +82,8 @@ def lib() -> ctypes.CDLL:
         "ssl_music_spectrum": (I, [P, P, I, P, I, I, I, I, I, P, P, P, P]),
         "ssl_peaks": (I, [P, P, I, I, I, P, P, P]),
         "ssl_localize": (I, [P, P, I, I, I, I64, I64, P, P, I, I, I, I, I, P, P, P, P, P]),
+        "ssl_localize_noalloc": (I, [P, P, I, I, I, I64, I64, P, P, I, I, I, I, I, P, P, P, P, P]),
+        "ssl_localize_noalloc_bytes": (ctypes.c_size_t, [I, I, I, I]),
         "ssl_localize_batch": (I, [P, ctypes.POINTER(BlockDesc), I, I, I, P]),
         "ssl_ctx_use_graphs": (I, [P, I]),
         "ssl_ctx_set_jacobi_lanes": (I, [P, I, I]),
@@ -260,6 +265,22 @@ def ssl_localize(ctx, X, noise, H, prec, n_az, n_el, Ns, p, peaks, peak_val, Pba
     _check("ssl_localize", lib().ssl_localize(ctx, _ptr(X), F, T, M, sF, sT, noise, _ptr(H), prec,
                                               n_az, n_el, Ns, p, _ptr(peaks), _ptr(peak_val),
                                               _ptr(Pbar), _ptr(bin_status), _stream(stream)))
+
+
+def ssl_localize_noalloc(ctx, X, noise, H, prec, n_az, n_el, Ns, p, peaks, peak_val, Pbar=None,
+                         bin_status=None, stream=None):
+    F, T, M = X.shape
+    sF, sT, sM = X.stride()
+    if sM != 1:
+        raise ValueError("X must be contiguous along M")
+    _check("ssl_localize_noalloc",
+           lib().ssl_localize_noalloc(ctx, _ptr(X), F, T, M, sF, sT, noise, _ptr(H), prec, n_az,
+                                      n_el, Ns, p, _ptr(peaks), _ptr(peak_val), _ptr(Pbar),
+                                      _ptr(bin_status), _stream(stream)))
+
+
+def ssl_localize_noalloc_bytes(F, M, Ns, D):
+    return int(lib().ssl_localize_noalloc_bytes(F, M, Ns, D))
 
 
 def block_desc(X, noise, H, n_az, n_el, Ns, peaks, peak_val, Pbar=None, bin_status=None):

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <new>
 #include <tuple>
 
@@ -190,6 +191,131 @@ ssl_status check_x(const ssl_c64 *X, int T, int M, int64_t sF, int64_t sT)
     return SSL_OK;
 }
 
+ssl_status check_localize(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int M, int64_t strideF,
+                          int64_t strideT, ssl_noise K, const void *H, ssl_prec prec, int n_az,
+                          int n_el, int Ns, int p, int32_t *peaks, float *peak_val)
+{
+    if (!ctx || !K || !H || !peaks || !peak_val) {
+        ssl_set_error("ctx, K, H, peaks or peak_val is NULL");
+        return SSL_ERR_ARG;
+    }
+    ssl_status s = check_common(F, M, Ns);
+    if (s != SSL_OK) return s;
+    if ((s = check_x(X, T, M, strideF, strideT)) != SSL_OK) return s;
+    if ((s = check_grid(n_az, n_el, Ns)) != SSL_OK) return s;
+    if (p != 1 && p != 2) {
+        ssl_set_error("p = %d must be 1 or 2", p);
+        return SSL_ERR_ARG;
+    }
+    if (prec != SSL_FP32 && prec != SSL_BF16 && prec != SSL_FP16) {
+        ssl_set_error("prec must be SSL_FP32, SSL_BF16 or SSL_FP16");
+        return SSL_ERR_ARG;
+    }
+    if (K->F != F || K->M != M) {
+        ssl_set_error("noise handle is %d x %d, call has F = %d, M = %d", K->F, K->M, F, M);
+        return SSL_ERR_ARG;
+    }
+    if (!K->is_set) {
+        ssl_set_error("noise handle was never set");
+        return SSL_ERR_STATE;
+    }
+    return SSL_OK;
+}
+
+// Workspace of one block's path: R | A | En | P | Pbar | status, then (scratch only) the bin-sum
+// partials [chunks][D].
+struct LocalizeWs {
+    size_t bR, bE, bP, bB, bS, total, with_part;
+};
+
+LocalizeWs localize_ws(int F, int M, int Ns, int D)
+{
+    LocalizeWs L;
+    L.bR = align256((size_t)F * M * M * sizeof(ssl_c64));
+    L.bE = align256((size_t)F * (M - Ns) * M * sizeof(ssl_c64));
+    L.bP = align256((size_t)F * D * sizeof(float));
+    L.bB = align256((size_t)D * sizeof(float));
+    L.bS = align256((size_t)F * sizeof(int32_t));
+    L.total = 2 * L.bR + L.bE + L.bP + L.bB + L.bS;
+    const size_t nch = (size_t)(F + SSL_BINSUM_CHUNK - 1) / SSL_BINSUM_CHUNK;
+    L.with_part = L.total + align256(nch * (size_t)D * sizeof(float));
+    return L;
+}
+
+// The five launches of one block (eq.2-6 and the peak search) on workspace w laid out as L and
+// bin-sum partials `part`.  With `may_time` false no timing event is ever created or recorded.
+ssl_status localize_enqueue(ssl_ctx ctx, bool may_time, char *w, const LocalizeWs &L, float *part,
+                            const ssl_c64 *X, int F, int T, int M, int64_t strideF,
+                            int64_t strideT, ssl_noise K, const void *H, ssl_prec prec, int n_az,
+                            int n_el, int Ns, int p, int32_t *peaks, float *peak_val, float *Pbar,
+                            int32_t *bin_status, hipStream_t st)
+{
+    const int D = n_az * n_el;
+    ssl_c64 *R = reinterpret_cast<ssl_c64 *>(w);
+    ssl_c64 *A = reinterpret_cast<ssl_c64 *>(w + L.bR);
+    ssl_c64 *En = reinterpret_cast<ssl_c64 *>(w + 2 * L.bR);
+    float *P = reinterpret_cast<float *>(w + 2 * L.bR + L.bE);
+    float *Pb = Pbar ? Pbar : reinterpret_cast<float *>(w + 2 * L.bR + L.bE + L.bP);
+    int32_t *stt = bin_status ? bin_status
+                              : reinterpret_cast<int32_t *>(w + 2 * L.bR + L.bE + L.bP + L.bB);
+    auto run = [&](int id, auto &&launch) {
+        return may_time ? timed(ctx, id, st, launch) : launch();
+    };
+    hipError_t e = run(SSL_K_CORR, [&] {
+        return launch_corr(X, F, T, M, strideF, strideT, 1.0 / T, 0, prec, R, st);
+    });
+    if (e != hipSuccess) return hip_fail(e, "corr launch");
+    e = run(SSL_K_WHITEN, [&] { return launch_whiten(K->Kinv, R, A, F, M, st); });
+    if (e != hipSuccess) return hip_fail(e, "whiten launch");
+    e = run(SSL_K_JACOBI, [&] {
+        return launch_jacobi(A, K->status, F, M, Ns, SSL_DEFAULT_SWEEPS, jac_lanes(ctx, M), En,
+                             nullptr, stt, nullptr, st);
+    });
+    if (e != hipSuccess) return hip_fail(e, "jacobi launch");
+    e = run(SSL_K_STEER, [&] {
+        return launch_steer(H, prec, En, F, D, M, Ns, p, stt, P, st_waves(ctx, M, Ns, prec), st);
+    });
+    if (e != hipSuccess) return hip_fail(e, "steer launch");
+    e = run(SSL_K_BINSUM, [&] {
+        return launch_binsum_peaks(P, F, D, Pb, part, n_az, n_el, Ns, peaks, peak_val, st);
+    });
+    return e == hipSuccess ? SSL_OK : hip_fail(e, "bin-sum launch");
+}
+
+// Fixed device scratch of ssl_localize_noalloc.  Every device the library runs on holds its own
+// copy for the life of the process; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device (scratch_address), never through the name.
+static __device__ __align__(256) unsigned char scratch[SSL_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_addr[kMaxDevices] = {};
+
+// The device address of `scratch` on `device`, which must be the current device; looked up once
+// per device.
+ssl_status scratch_address(int device, char **out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) {
+        ssl_set_error("device %d beyond the %d devices the scratch table covers", device,
+                      kMaxDevices);
+        return SSL_ERR_ARG;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                            "hipGetSymbolAddress(scratch)");
+        }
+        g_scratch_addr[device] = static_cast<char *>(ptr);
+    }
+    *out = g_scratch_addr[device];
+    return SSL_OK;
+}
+
 }  // namespace
 
 void ssl_set_error(const char *fmt, ...)
@@ -227,6 +353,15 @@ ssl_status ssl_ctx_create(ssl_ctx *out, int device, size_t hbm_budget_bytes)
     }
     c->device = device;
     c->budget = hbm_budget_bytes;
+    {
+        DeviceGuard dg(device);
+        ssl_status s = dg.ok ? scratch_address(device, &c->scratch)
+                             : hip_fail(hipErrorInvalidDevice, "hipSetDevice");
+        if (s != SSL_OK) {
+            delete c;
+            return s;
+        }
+    }
     if (hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, device) !=
             hipSuccess ||
         c->cu_count <= 0)
@@ -548,72 +683,48 @@ ssl_status ssl_localize(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int M, int6
                         int n_el, int Ns, int p, int32_t *peaks, float *peak_val, float *Pbar,
                         int32_t *bin_status, void *stream)
 {
-    if (!ctx || !K || !H || !peaks || !peak_val) {
-        ssl_set_error("ctx, K, H, peaks or peak_val is NULL");
-        return SSL_ERR_ARG;
-    }
-    ssl_status s = check_common(F, M, Ns);
+    ssl_status s = check_localize(ctx, X, F, T, M, strideF, strideT, K, H, prec, n_az, n_el, Ns,
+                                  p, peaks, peak_val);
     if (s != SSL_OK) return s;
-    if ((s = check_x(X, T, M, strideF, strideT)) != SSL_OK) return s;
-    if ((s = check_grid(n_az, n_el, Ns)) != SSL_OK) return s;
-    if (p != 1 && p != 2) {
-        ssl_set_error("p = %d must be 1 or 2", p);
+    const LocalizeWs L = localize_ws(F, M, Ns, n_az * n_el);
+    DeviceGuard dg(ctx->device);
+    if ((s = ws_reserve(ctx, L.total)) != SSL_OK) return s;
+    if ((s = binsum_reserve(ctx, F, n_az * n_el)) != SSL_OK) return s;
+    return localize_enqueue(ctx, true, static_cast<char *>(ctx->ws), L, ctx->binsum_part, X, F, T,
+                            M, strideF, strideT, K, H, prec, n_az, n_el, Ns, p, peaks, peak_val,
+                            Pbar, bin_status, static_cast<hipStream_t>(stream));
+}
+
+size_t ssl_localize_noalloc_bytes(int F, int M, int Ns, int D)
+{
+    if (F < 1 || M < 1 || M > SSL_MAX_M || Ns < 1 || Ns >= M || D < 1 || D > (1 << 24)) return 0;
+    return localize_ws(F, M, Ns, D).with_part;
+}
+
+ssl_status ssl_localize_noalloc(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int M,
+                                int64_t strideF, int64_t strideT, ssl_noise K, const void *H,
+                                ssl_prec prec, int n_az, int n_el, int Ns, int p, int32_t *peaks,
+                                float *peak_val, float *Pbar, int32_t *bin_status, void *stream)
+{
+    ssl_status s = check_localize(ctx, X, F, T, M, strideF, strideT, K, H, prec, n_az, n_el, Ns,
+                                  p, peaks, peak_val);
+    if (s != SSL_OK) return s;
+    const LocalizeWs L = localize_ws(F, M, Ns, n_az * n_el);
+    if (L.with_part > SSL_NOALLOC_SCRATCH_BYTES) {
+        ssl_set_error("ssl_localize_noalloc: F = %d, M = %d, Ns = %d, D = %d needs %zu bytes of "
+                      "scratch, the fixed scratch holds %zu",
+                      F, M, Ns, n_az * n_el, L.with_part, (size_t)SSL_NOALLOC_SCRATCH_BYTES);
         return SSL_ERR_ARG;
     }
-    if (prec != SSL_FP32 && prec != SSL_BF16 && prec != SSL_FP16) {
-        ssl_set_error("prec must be SSL_FP32, SSL_BF16 or SSL_FP16");
-        return SSL_ERR_ARG;
-    }
-    if (K->F != F || K->M != M) {
-        ssl_set_error("noise handle is %d x %d, call has F = %d, M = %d", K->F, K->M, F, M);
-        return SSL_ERR_ARG;
-    }
-    if (!K->is_set) {
-        ssl_set_error("noise handle was never set");
+    char *scr = ctx->scratch;
+    if (!scr) {
+        ssl_set_error("ssl_localize_noalloc: no scratch address for device %d", ctx->device);
         return SSL_ERR_STATE;
     }
-    const int D = n_az * n_el;
-    const int Nn = M - Ns;
-    // workspace: R | A | En | P | Pbar | status
-    const size_t bR = align256((size_t)F * M * M * sizeof(ssl_c64));
-    const size_t bE = align256((size_t)F * Nn * M * sizeof(ssl_c64));
-    const size_t bP = align256((size_t)F * D * sizeof(float));
-    const size_t bB = align256((size_t)D * sizeof(float));
-    const size_t bS = align256((size_t)F * sizeof(int32_t));
     DeviceGuard dg(ctx->device);
-    if ((s = ws_reserve(ctx, 2 * bR + bE + bP + bB + bS)) != SSL_OK) return s;
-    if ((s = binsum_reserve(ctx, F, D)) != SSL_OK) return s;
-    char *w = static_cast<char *>(ctx->ws);
-    ssl_c64 *R = reinterpret_cast<ssl_c64 *>(w);
-    ssl_c64 *A = reinterpret_cast<ssl_c64 *>(w + bR);
-    ssl_c64 *En = reinterpret_cast<ssl_c64 *>(w + 2 * bR);
-    float *P = reinterpret_cast<float *>(w + 2 * bR + bE);
-    float *Pb = Pbar ? Pbar : reinterpret_cast<float *>(w + 2 * bR + bE + bP);
-    int32_t *stt = bin_status ? bin_status
-                              : reinterpret_cast<int32_t *>(w + 2 * bR + bE + bP + bB);
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    hipError_t e = timed(ctx, SSL_K_CORR, st, [&] {
-        return launch_corr(X, F, T, M, strideF, strideT, 1.0 / T, 0, prec, R, st);
-    });
-    if (e != hipSuccess) return hip_fail(e, "corr launch");
-    e = timed(ctx, SSL_K_WHITEN, st, [&] { return launch_whiten(K->Kinv, R, A, F, M, st); });
-    if (e != hipSuccess) return hip_fail(e, "whiten launch");
-    e = timed(ctx, SSL_K_JACOBI, st, [&] {
-        return launch_jacobi(A, K->status, F, M, Ns, SSL_DEFAULT_SWEEPS, jac_lanes(ctx, M), En,
-                             nullptr, stt, nullptr, st);
-    });
-    if (e != hipSuccess) return hip_fail(e, "jacobi launch");
-    e = timed(ctx, SSL_K_STEER, st,
-              [&] {
-                  return launch_steer(H, prec, En, F, D, M, Ns, p, stt, P,
-                                      st_waves(ctx, M, Ns, prec), st);
-              });
-    if (e != hipSuccess) return hip_fail(e, "steer launch");
-    e = timed(ctx, SSL_K_BINSUM, st, [&] {
-        return launch_binsum_peaks(P, F, D, Pb, ctx->binsum_part, n_az, n_el, Ns, peaks,
-                                   peak_val, st);
-    });
-    return e == hipSuccess ? SSL_OK : hip_fail(e, "bin-sum launch");
+    return localize_enqueue(ctx, false, scr, L, reinterpret_cast<float *>(scr + L.total), X, F, T,
+                            M, strideF, strideT, K, H, prec, n_az, n_el, Ns, p, peaks, peak_val,
+                            Pbar, bin_status, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

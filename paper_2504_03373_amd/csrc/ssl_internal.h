@@ -52,6 +52,8 @@ struct ssl_ctx_s {
     };
     std::vector<GraphEntry> graphs;
     int cu_count = 0;
+    // this device's address of the fixed scratch of ssl_localize_noalloc
+    char *scratch = nullptr;
     // Jacobi variant (lanes per column pair) per size class 8/16/32/64 channels
     int jac_lanes[4] = {8, 8, 8, 8};     // lanes per Jacobi column pair, classes 8/16/32/64
     // waves per projection workgroup, [steer class 1/2/4][SSL_FP32, SSL_BF16, SSL_FP16]

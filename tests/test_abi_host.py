@@ -58,3 +58,25 @@ def test_binding_rejects_host_tensors():
     import paper_2504_03373_amd as S
     with pytest.raises(ValueError):
         S._ptr(torch.zeros(3))
+
+
+def test_noalloc_scratch_limit_matches_header():
+    import paper_2504_03373_amd as S
+    text = open(HEADER).read()
+    m = re.search(r"#define SSL_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m, "SSL_NOALLOC_SCRATCH_BYTES not found in the header"
+    assert int(m.group(1)) << int(m.group(2)) == S.SSL_NOALLOC_SCRATCH_BYTES
+
+
+def test_noalloc_scratch_bytes_host_only():
+    import paper_2504_03373_amd as S
+    # R and A (F M^2 complex64 each), E_n, P, Pbar, status, bin-sum partials; 256-byte aligned
+    a = lambda n: (n + 255) // 256 * 256
+    F, M, Ns, D = 257, 60, 2, 1368
+    want = (2 * a(F * M * M * 8) + a(F * (M - Ns) * M * 8) + a(F * D * 4) + a(D * 4) + a(F * 4)
+            + a(((F + 15) // 16) * D * 4))
+    assert S.ssl_localize_noalloc_bytes(F, M, Ns, D) == want
+    assert want <= S.SSL_NOALLOC_SCRATCH_BYTES
+    assert S.ssl_localize_noalloc_bytes(1100, 60, 2, 1368) > S.SSL_NOALLOC_SCRATCH_BYTES
+    assert S.ssl_localize_noalloc_bytes(257, 65, 2, 1368) == 0
+    assert S.ssl_localize_noalloc_bytes(257, 8, 8, 72) == 0
