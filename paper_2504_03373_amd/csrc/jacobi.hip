@@ -28,7 +28,13 @@
 //    group);
 //  * convergence test in FP64: rotate iff |gamma|^2 > tol^2 alpha beta with tol = 2 sqrt(M) 2^-24;
 //    a sweep without any rotation ends the solve (a fixed point: a converged bin is never changed
-//    again), and the columns of W S^-1 are then orthonormal to tol;
+//    again), and the columns of W S^-1 are then orthonormal to tol.  The inner products are
+//    accumulated in FP32 (at most R = MP/G products per lane, then log2 G butterfly levels), so
+//    their rounding error is below (R + log2 G) 2^-24 |x_i| |x_j|: 11 2^-24 for the default
+//    8-lane variant at MP = 64, under the threshold 2 sqrt(M) 2^-24 (15.5 2^-24 at M = 60), and
+//    below it at every M for the 8-lane variants; the test is not decided by rounding;
+//  * the sweeps run on a permuted layout (swx) that spreads the reads of a round over the LDS
+//    banks, switched in place before and after them;
 //  * epilogue: sigma from the column norms, stable descending rank sort (ties: lower column
 //    first), U = Q U_R with each group taking its columns through all reflectors in registers,
 //    E_n = sorted columns Ns..M-1 of U, written column-major per bin.
@@ -65,6 +71,30 @@ __device__ __forceinline__ float rsqrt_refined(float x)
 }
 __device__ __forceinline__ float2 conj2(float2 v) { return make_float2(v.x, -v.y); }
 
+// Index of (row r, column c) in a bin's LDS matrix: column-major.
+template <int MP>
+__device__ __forceinline__ int at(int c, int r)
+{
+    return c * MP + r;
+}
+
+// Layout of the Jacobi sweeps: column c's 8-row (64-byte) chunks permuted by the low bits of c
+// (row r stored at r XOR 8 (c mod MP/8)).  The lane groups of a round read the same rows of
+// different columns; with a column stride of 512 bytes those reads would all fall on the same LDS
+// banks, here they spread over all of them.  The permutation is an involution within each column
+// (r <-> r XOR s), so the layout is switched in place by swapping those row pairs.
+template <int MP>
+__device__ __forceinline__ int swz_mask(int c)
+{
+    constexpr int mask = MP >= 16 ? MP / 8 - 1 : 0;
+    return (c & mask) << 3;
+}
+template <int MP>
+__device__ __forceinline__ int swx(int c, int r)
+{
+    return c * MP + (r ^ swz_mask<MP>(c));
+}
+
 template <int MP, int G>
 struct JacobiCfg {
     static constexpr int R = MP / G;                       // rows per lane
@@ -81,7 +111,7 @@ struct JacobiCfg {
 // the group-summed |x_r|^2 over rows > k of the result (the column's trailing norm for the next
 // step).
 template <int MP, int G>
-__device__ __forceinline__ float apply_reflector(const float2 *Vk, float2 vk, int k, float tau,
+__device__ __forceinline__ float apply_reflector(int pc, float2 vk, int k, float tau,
                                                  float2 *X, int c, int M, int q)
 {
     constexpr int R = MP / G;
@@ -92,9 +122,9 @@ __device__ __forceinline__ float apply_reflector(const float2 *Vk, float2 vk, in
     for (int j = 0; j < R; ++j) {
         if (G * (j + 1) <= k) continue;           // slot entirely above the reflector
         const int r = q + G * j;
-        const float2 raw = Vk[r];
+        const float2 raw = X[at<MP>(pc, r)];
         v[j] = (r > k) ? raw : ((r == k) ? vk : make_float2(0.f, 0.f));
-        x[j] = X[c * MP + r];
+        x[j] = X[at<MP>(c, r)];
         // conj(v) x
         wr = fmaf(v[j].x, x[j].x, fmaf(v[j].y, x[j].y, wr));
         wi = fmaf(v[j].x, x[j].y, fmaf(-v[j].y, x[j].x, wi));
@@ -109,7 +139,7 @@ __device__ __forceinline__ float apply_reflector(const float2 *Vk, float2 vk, in
         // x -= v * (tau w)
         x[j].x = fmaf(-v[j].x, wr, fmaf(v[j].y, wi, x[j].x));
         x[j].y = fmaf(-v[j].x, wi, fmaf(-v[j].y, wr, x[j].y));
-        X[c * MP + r] = x[j];
+        X[at<MP>(c, r)] = x[j];
         const float n2 = fmaf(x[j].x, x[j].x, x[j].y * x[j].y);
         tn += (r > k) ? n2 : 0.0f;
     }
@@ -120,7 +150,7 @@ __device__ __forceinline__ float apply_reflector(const float2 *Vk, float2 vk, in
 // dependency chains interleaved); the results for c1 are stored only if two.  tn0, tn1: their
 // trailing norms as in apply_reflector.
 template <int MP, int G>
-__device__ __forceinline__ void apply_reflector2(const float2 *Vk, float2 vk, int k, float tau,
+__device__ __forceinline__ void apply_reflector2(int pc, float2 vk, int k, float tau,
                                                  float2 *X, int c0, int c1, bool two, int q,
                                                  float &tn0, float &tn1)
 {
@@ -131,10 +161,10 @@ __device__ __forceinline__ void apply_reflector2(const float2 *Vk, float2 vk, in
     for (int j = 0; j < R; ++j) {
         if (G * (j + 1) <= k) continue;
         const int r = q + G * j;
-        const float2 raw = Vk[r];
+        const float2 raw = X[at<MP>(pc, r)];
         v[j] = (r > k) ? raw : ((r == k) ? vk : make_float2(0.f, 0.f));
-        x0[j] = X[c0 * MP + r];
-        x1[j] = X[c1 * MP + r];
+        x0[j] = X[at<MP>(c0, r)];
+        x1[j] = X[at<MP>(c1, r)];
         wr0 = fmaf(v[j].x, x0[j].x, fmaf(v[j].y, x0[j].y, wr0));
         wi0 = fmaf(v[j].x, x0[j].y, fmaf(-v[j].y, x0[j].x, wi0));
         wr1 = fmaf(v[j].x, x1[j].x, fmaf(v[j].y, x1[j].y, wr1));
@@ -153,8 +183,8 @@ __device__ __forceinline__ void apply_reflector2(const float2 *Vk, float2 vk, in
         x0[j].y = fmaf(-v[j].x, wi0, fmaf(-v[j].y, wr0, x0[j].y));
         x1[j].x = fmaf(-v[j].x, wr1, fmaf(v[j].y, wi1, x1[j].x));
         x1[j].y = fmaf(-v[j].x, wi1, fmaf(-v[j].y, wr1, x1[j].y));
-        X[c0 * MP + r] = x0[j];
-        if (two) X[c1 * MP + r] = x1[j];
+        X[at<MP>(c0, r)] = x0[j];
+        if (two) X[at<MP>(c1, r)] = x1[j];
         const float n0 = fmaf(x0[j].x, x0[j].x, x0[j].y * x0[j].y);
         const float n1 = fmaf(x1[j].x, x1[j].x, x1[j].y * x1[j].y);
         s0 += (r > k) ? n0 : 0.0f;
@@ -169,6 +199,80 @@ __device__ __forceinline__ void apply_reflector2(const float2 *Vk, float2 vk, in
 __device__ __forceinline__ unsigned long long pivot_key(float nrm2, int c)
 {
     return ((unsigned long long)__float_as_uint(nrm2) << 32) | (unsigned int)(0x7fffffff - c);
+}
+
+// One pair visit of a Jacobi sweep on columns ci < cj (sweep layout): NR row slots q + G k per
+// lane, enough to cover the numerical rank (rows >= rk are zero), all loaded before the first
+// product.  alpha = |x_i|^2, beta = |x_j|^2 and gamma = x_i^H x_j are reduced across the G lanes
+// with DPP butterflies (every lane ends with the same bits, so the decision is uniform in the
+// group); the pair is rotated iff |gamma|^2 > tol^2 alpha beta, tested in FP64.  Returns whether
+// it was rotated.
+template <int MP, int G, int NR>
+__device__ __forceinline__ bool jacobi_pair(float2 *Bs, int ci, int cj, int q, double tol2)
+{
+    float2 bi[NR], bj[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        const int r = q + G * k;
+        bi[k] = Bs[swx<MP>(ci, r)];
+        bj[k] = Bs[swx<MP>(cj, r)];
+    }
+    __builtin_amdgcn_sched_barrier(0);            // every read in flight before the products
+    float al = 0.f, be = 0.f, gr = 0.f, gi = 0.f;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        al = fmaf(bi[k].x, bi[k].x, fmaf(bi[k].y, bi[k].y, al));
+        be = fmaf(bj[k].x, bj[k].x, fmaf(bj[k].y, bj[k].y, be));
+        gr = fmaf(bi[k].x, bj[k].x, fmaf(bi[k].y, bj[k].y, gr));
+        gi = fmaf(bi[k].x, bj[k].y, fmaf(-bi[k].y, bj[k].x, gi));
+    }
+    al = group_sum<G>(al);
+    be = group_sum<G>(be);
+    gr = group_sum<G>(gr);
+    gi = group_sum<G>(gi);
+    const double g2 = (double)gr * gr + (double)gi * gi;
+    const double ab = (double)al * be;
+    if (!(g2 > tol2 * ab && ab > 0.0)) return false;
+    // 2x2 Hermitian Gram [[al, gamma], [conj gamma, be]]: the real Jacobi angle after removing the
+    // phase of gamma, in FP32: t = tan from the smaller root of t^2 + 2 zeta t - 1 = 0, c =
+    // 1/sqrt(1 + t^2) refined by one Newton step, s = c t.  c and s come from the same t, so the
+    // rotation is unitary to rounding whatever t's last-bit error (hardware sqrt and reciprocal).
+    // 1/|gamma| from |gamma|^2 when that is a normal FP32 number; otherwise (columns of a
+    // numerically rank-deficient bin) without squaring.  gamma != 0 here.
+    const float g2f = (float)g2;
+    float rg;
+    if (g2f >= 1e-36f) {
+        rg = __builtin_amdgcn_rsqf(g2f);
+    } else {
+        const float ax = fabsf(gr), ay = fabsf(gi);
+        const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+        const float rt = mn * __builtin_amdgcn_rcpf(mx);
+        rg = __builtin_amdgcn_rcpf(mx * __builtin_amdgcn_sqrtf(fmaf(rt, rt, 1.0f)));
+    }
+    const float zeta = (be - al) * 0.5f * rg;
+    // |zeta| > 1e18 would need |x_i|^2 / |x_j|^2 > 1e24 for the pair to be rotated at all; the
+    // clamp only keeps zeta^2 finite
+    const float az = fminf(fabsf(zeta), 1e18f);
+    float t = __builtin_amdgcn_rcpf(az + __builtin_amdgcn_sqrtf(fmaf(az, az, 1.0f)));
+    t = copysignf(t, zeta);
+    const float c = rsqrt_refined(fmaf(t, t, 1.0f));
+    const float s = c * t;
+    // w = s e^{-i arg gamma}:  x_i' = c x_i - w x_j,  x_j' = conj(w) x_i + c x_j
+    const float wr = s * gr * rg;
+    const float wi = -s * gi * rg;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        const int r = q + G * k;
+        float2 x = bi[k], y = bj[k];
+        float2 ni, nj;
+        ni.x = fmaf(c, x.x, -fmaf(wr, y.x, -wi * y.y));
+        ni.y = fmaf(c, x.y, -fmaf(wr, y.y, wi * y.x));
+        nj.x = fmaf(c, y.x, fmaf(wr, x.x, wi * x.y));
+        nj.y = fmaf(c, y.y, fmaf(wr, x.y, -wi * x.x));
+        Bs[swx<MP>(ci, r)] = ni;
+        Bs[swx<MP>(cj, r)] = nj;
+    }
+    return true;
 }
 
 // One bin: Af = its A (row-major M x M, overwritten), kst = upstream status of the bin (noise
@@ -237,7 +341,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
             if (!finite2(a)) nonfinite = true;
             amax = fmaxf(amax, fmaxf(fabsf(a.x), fabsf(a.y)));
         }
-        X[c * MP + r] = a;
+        X[at<MP>(c, r)] = a;
     }
     const int nf_count = __syncthreads_count(nonfinite ? 1 : 0);
     if (!nonfinite && amax > 0.0f) atomicMax((int *)&amax_s, __float_as_int(amax));
@@ -274,7 +378,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
             float s = 0.f;
 #pragma unroll
             for (int j = 0; j < R; ++j) {
-                const float2 v = X[c * MP + q + G * j];
+                const float2 v = X[at<MP>(c, q + G * j)];
                 s = fmaf(v.x, v.x, fmaf(v.y, v.y, s));
             }
             s = group_sum<G>(s);
@@ -294,7 +398,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                 break;
             }
             if (k == 0) thr = (float)M * 5.9604644775390625e-08f * nx;
-            const float2 xk = X[p * MP + k];
+            const float2 xk = X[at<MP>(p, k)];
             const float axk = sqrtf(fmaf(xk.x, xk.x, xk.y * xk.y));
             const float rax = __builtin_amdgcn_rcpf(axk);
             const float2 ph = axk > 0.f ? make_float2(xk.x * rax, xk.y * rax) : make_float2(1.f, 0.f);
@@ -325,13 +429,13 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                 if (__any(two)) {
                     const int c1 = two ? ((s1 == idx) ? last : clist[s1]) : c0;
                     float tn0, tn1;
-                    apply_reflector2<MP, G>(X + p * MP, vk, k, tk, X, c0, c1, two, q, tn0, tn1);
+                    apply_reflector2<MP, G>(p, vk, k, tk, X, c0, c1, two, q, tn0, tn1);
                     if (q == 0) {
                         atomicMax(&pkey[kn], pivot_key(tn0, c0));
                         if (two) atomicMax(&pkey[kn], pivot_key(tn1, c1));
                     }
                 } else {
-                    const float tn = apply_reflector<MP, G>(X + p * MP, vk, k, tk, X, c0, M, q);
+                    const float tn = apply_reflector<MP, G>(p, vk, k, tk, X, c0, M, q);
                     if (q == 0) atomicMax(&pkey[kn], pivot_key(tn, c0));
                 }
             }
@@ -351,13 +455,13 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         if (tid == 0) rank_s = rk;
         for (int e = tid; e < rk * MP; e += NT) {          // reflector k = e / MP, row e % MP
             const int k = e / MP, r = e % MP;
-            if (r >= k && r < M) Af[k * M + r] = (r == k) ? vhead[k] : X[colmap[k] * MP + r];
+            if (r >= k && r < M) Af[k * M + r] = (r == k) ? vhead[k] : X[at<MP>(colmap[k], r)];
         }
         __syncthreads();
         for (int e = tid; e < MP * MP; e += NT) {
             const int c = e / MP, x = e - c * MP;
             if (c > x) continue;
-            const float2 o1 = X[x * MP + c], o2 = X[c * MP + x];
+            const float2 o1 = X[at<MP>(x, c)], o2 = X[at<MP>(c, x)];
             float2 n1 = make_float2(0.f, 0.f), n2 = make_float2(0.f, 0.f);
             if (c < rk && x < M) {                       // Z[x][c]
                 const int px = pos[x];
@@ -369,8 +473,8 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                 if (pc > x) n2 = conj2(o2);
                 else if (pc == x) n2 = conj2(diag[x]);
             }
-            X[c * MP + x] = n1;
-            X[x * MP + c] = n2;
+            X[at<MP>(c, x)] = n1;
+            X[at<MP>(x, c)] = n2;
         }
         __syncthreads();
 
@@ -382,7 +486,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
             float s = 0.f;
 #pragma unroll
             for (int j = 0; j < R; ++j) {
-                const float2 v = X[q + G * j];
+                const float2 v = X[at<MP>(0, q + G * j)];
                 s = fmaf(v.x, v.x, fmaf(v.y, v.y, s));
             }
             s = group_sum<G>(s);
@@ -391,7 +495,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         __syncthreads();
         for (int k = 0; k < rk; ++k) {
             const float nx = sqrtf(nrm1[k]);
-            const float2 xk = X[k * MP + k];
+            const float2 xk = X[at<MP>(k, k)];
             const float axk = sqrtf(fmaf(xk.x, xk.x, xk.y * xk.y));
             const float rax = __builtin_amdgcn_rcpf(axk);
             const float2 ph = axk > 0.f ? make_float2(xk.x * rax, xk.y * rax) : make_float2(1.f, 0.f);
@@ -405,11 +509,11 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                 const bool two = c1 < rk;
                 if (__any(two)) {
                     float tn0, tn1;
-                    apply_reflector2<MP, G>(X + k * MP, vk, k, tk, X, c0, two ? c1 : c0, two, q,
+                    apply_reflector2<MP, G>(k, vk, k, tk, X, c0, two ? c1 : c0, two, q,
                                             tn0, tn1);
                     if (c0 == k + 1 && q == 0) nrm1[c0] = tn0;
                 } else {
-                    const float tn = apply_reflector<MP, G>(X + k * MP, vk, k, tk, X, c0, M, q);
+                    const float tn = apply_reflector<MP, G>(k, vk, k, tk, X, c0, M, q);
                     if (c0 == k + 1 && q == 0) nrm1[c0] = tn;
                 }
             }
@@ -419,20 +523,33 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         for (int e = tid; e < MP * MP; e += NT) {
             const int c = e / MP, i = e - c * MP;
             if (c > i) continue;
-            const float2 o1 = X[i * MP + c], o2 = X[c * MP + i];
+            const float2 o1 = X[at<MP>(i, c)], o2 = X[at<MP>(c, i)];
             float2 n1 = make_float2(0.f, 0.f), n2 = make_float2(0.f, 0.f);
             if (i < rk) {
                 if (i > c) n1 = conj2(o1);               // X[i][c], below the diagonal
                 else n1 = conj2(diag1[c]);               // i == c
             }
             (void)o2;                                    // X[c][i] (c < i) is above: zero
-            X[c * MP + i] = n1;
-            if (c != i) X[i * MP + c] = n2;
+            X[at<MP>(c, i)] = n1;
+            if (c != i) X[at<MP>(i, c)] = n2;
         }
         __syncthreads();
 
         // ---- 4. one-sided Jacobi on X: X V = W, columns orthogonalised in place ----------------
+        // The sweeps work on a swizzled copy of the layout (swx): each column's 8-row chunks are
+        // permuted by its index, so that the lane groups of a round, which read the same rows of
+        // different columns, fall on different LDS banks.
         float2 *Bs = X;
+        // to the sweep layout (row pairs r, r XOR s of each column exchanged)
+        for (int e = tid; e < MP * MP; e += NT) {
+            const int c = e / MP, r = e - c * MP, rr = r ^ swz_mask<MP>(c);
+            if (r < rr) {
+                const float2 u = X[c * MP + r], v = X[c * MP + rr];
+                X[c * MP + r] = v;
+                X[c * MP + rr] = u;
+            }
+        }
+        __syncthreads();
         const int Me = rk + (rk & 1);                // players of the round-robin tournament
         // rotate iff |cos| > 2 sqrt(M) 2^-24 (twice the usual FP32 one-sided Jacobi threshold)
         const double tol = 2.0 * sqrt((double)M) * 5.9604644775390625e-08;
@@ -449,6 +566,9 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         const bool defer = P > 1 && P % kPairsPerWave == 1;
         const int Pr = defer ? P - 1 : P;
         const int n_rounds = Me - 1 + (defer ? 3 : 0);
+        // row slots per lane: R - 1 when they cover the rank (the 60-channel rank-50 case), else R
+        constexpr int RLO = R > 1 ? R - 1 : 1;
+        const bool nr_lo = rk <= G * RLO;
         for (int sw = 0; sw < max_sweeps; ++sw) {
             int rotated = 0;
             for (int rd = 0; rd < n_rounds; ++rd) {
@@ -477,63 +597,10 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                 if (play) {
                     const int ci = min(a, b), cj = max(a, b);
                     if (cj < rk) {
-                        float2 bi[R], bj[R];
-                        float al = 0.f, be = 0.f, gr = 0.f, gi = 0.f;
-#pragma unroll
-                        for (int k = 0; k < R; ++k) {
-                            if (G * k >= rk) break;     // rows >= rk of X are zero (uniform)
-                            const int r = q + G * k;
-                            bi[k] = Bs[ci * MP + r];
-                            bj[k] = Bs[cj * MP + r];
-                            al = fmaf(bi[k].x, bi[k].x, fmaf(bi[k].y, bi[k].y, al));
-                            be = fmaf(bj[k].x, bj[k].x, fmaf(bj[k].y, bj[k].y, be));
-                            // conj(z_i) * z_j
-                            gr = fmaf(bi[k].x, bj[k].x, fmaf(bi[k].y, bj[k].y, gr));
-                            gi = fmaf(bi[k].x, bj[k].y, fmaf(-bi[k].y, bj[k].x, gi));
-                        }
-                        al = group_sum<G>(al);
-                        be = group_sum<G>(be);
-                        gr = group_sum<G>(gr);
-                        gi = group_sum<G>(gi);
-                        const double g2 = (double)gr * gr + (double)gi * gi;
-                        const double ab = (double)al * be;
-                        if (g2 > tol2 * ab && ab > 0.0) {
+                        const bool rot = nr_lo ? jacobi_pair<MP, G, RLO>(Bs, ci, cj, q, tol2)
+                                               : jacobi_pair<MP, G, R>(Bs, ci, cj, q, tol2);
+                        if (rot) {
                             rotated = 1;
-                            // 2x2 Hermitian Gram [[al, gamma], [conj gamma, be]]: real Jacobi angle
-                            // after removing the phase of gamma, in FP32 (tan from the smaller root
-                            // of t^2 + 2 zeta t - 1 = 0, c = 1/sqrt(1 + t^2) refined by one Newton
-                            // step so that c^2 + s^2 = 1 to FP32 rounding)
-                            // |gamma| without squaring (|gamma|^2 may be subnormal for the
-                            // columns of a numerically rank-deficient bin); gamma != 0 here
-                            const float ax = fabsf(gr), ay = fabsf(gi);
-                            const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
-                            const float rt = mn * __builtin_amdgcn_rcpf(mx);
-                            const float rg = __builtin_amdgcn_rcpf(mx * sqrtf(fmaf(rt, rt, 1.0f)));
-                            const float zeta = (be - al) * 0.5f * rg;
-                            const float az = fabsf(zeta);
-                            // (hardware reciprocals: c and s below come from the same t, so
-                            // the rotation is orthonormal whatever t's last-bit error)
-                            float t = (az > 1e18f) ? 0.5f * __builtin_amdgcn_rcpf(az)
-                                                   : __builtin_amdgcn_rcpf(az + sqrtf(fmaf(az, az, 1.0f)));
-                            t = copysignf(t, zeta);
-                            const float c = rsqrt_refined(fmaf(t, t, 1.0f));
-                            const float s = c * t;
-                            // w = s e^{-i arg gamma}:  z_i' = c z_i - w z_j,  z_j' = conj(w) z_i + c z_j
-                            const float wr = s * gr * rg;
-                            const float wi = -s * gi * rg;
-#pragma unroll
-                            for (int k = 0; k < R; ++k) {
-                                if (G * k >= rk) break;
-                                const int r = q + G * k;
-                                float2 x = bi[k], y = bj[k];
-                                float2 ni, nj;
-                                ni.x = fmaf(c, x.x, -fmaf(wr, y.x, -wi * y.y));
-                                ni.y = fmaf(c, x.y, -fmaf(wr, y.y, wi * y.x));
-                                nj.x = fmaf(c, y.x, fmaf(wr, x.x, wi * x.y));
-                                nj.y = fmaf(c, y.y, fmaf(wr, x.y, -wi * x.x));
-                                Bs[ci * MP + r] = ni;
-                                Bs[cj * MP + r] = nj;
-                            }
                             if (q == 0) ++my_rot;
                         }
                     }
@@ -547,6 +614,16 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
             }
         }
         if (my_rot) atomicAdd(&rot_total, my_rot);
+        // back to the plain layout
+        for (int e = tid; e < MP * MP; e += NT) {
+            const int c = e / MP, r = e - c * MP, rr = r ^ swz_mask<MP>(c);
+            if (r < rr) {
+                const float2 u = X[c * MP + r], v = X[c * MP + rr];
+                X[c * MP + r] = v;
+                X[c * MP + rr] = u;
+            }
+        }
+        __syncthreads();
 
         // ---- 5. sigma_c = |w_c| (scaled back); U_R = W Sigma^-1 extended by the identity on the
         // null-space columns rk..M-1; stable descending rank of sigma ------------------------------
@@ -555,7 +632,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
             float s = 0.f;
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                x[k] = Bs[c * MP + q + G * k];
+                x[k] = Bs[at<MP>(c, q + G * k)];
                 s = fmaf(x[k].x, x[k].x, fmaf(x[k].y, x[k].y, s));
             }
             s = group_sum<G>(s);
@@ -564,12 +641,12 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                 const float inv = s > 0.f ? rsqrt_refined(s) : 0.0f;
 #pragma unroll
                 for (int k = 0; k < R; ++k)
-                    Bs[c * MP + q + G * k] = make_float2(x[k].x * inv, x[k].y * inv);
+                    Bs[at<MP>(c, q + G * k)] = make_float2(x[k].x * inv, x[k].y * inv);
                 if (q == 0 && !(s > 0.f)) degen = 1;
             } else {
 #pragma unroll
                 for (int k = 0; k < R; ++k)
-                    Bs[c * MP + q + G * k] = make_float2((q + G * k == c && c < M) ? 1.f : 0.f, 0.f);
+                    Bs[at<MP>(c, q + G * k)] = make_float2((q + G * k == c && c < M) ? 1.f : 0.f, 0.f);
             }
             if (q == 0) sig[c] = (c < M) ? ldexpf(sqrtf(s), ex) : -1.0f;
         }
@@ -595,13 +672,13 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
             float2 x0[R], x1[R];
 #pragma unroll
             for (int j = 0; j < R; ++j) {
-                x0[j] = h0 ? X[c0 * MP + q + G * j] : make_float2(0.f, 0.f);
-                x1[j] = h1 ? X[c1 * MP + q + G * j] : make_float2(0.f, 0.f);
+                x0[j] = h0 ? X[at<MP>(c0, q + G * j)] : make_float2(0.f, 0.f);
+                x1[j] = h1 ? X[at<MP>(c1, q + G * j)] : make_float2(0.f, 0.f);
             }
             __syncthreads();
             for (int e = tid; e < rk * MP; e += NT) {
                 const int k = e / MP, r = e - k * MP;
-                X[e] = (r >= k && r < M) ? Af[k * M + r] : make_float2(0.f, 0.f);
+                X[at<MP>(k, r)] = (r >= k && r < M) ? Af[k * M + r] : make_float2(0.f, 0.f);
             }
             __syncthreads();
             for (int k = rk - 1; k >= 0; --k) {
@@ -611,7 +688,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
 #pragma unroll
                 for (int j = 0; j < R; ++j) {
                     if (G * (j + 1) <= k) continue;      // slot entirely above the reflector
-                    v[j] = X[k * MP + q + G * j];
+                    v[j] = X[at<MP>(k, q + G * j)];
                     ar = fmaf(v[j].x, x0[j].x, fmaf(v[j].y, x0[j].y, ar));
                     ai = fmaf(v[j].x, x0[j].y, fmaf(-v[j].y, x0[j].x, ai));
                     br = fmaf(v[j].x, x1[j].x, fmaf(v[j].y, x1[j].y, br));
@@ -633,8 +710,8 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
             __syncthreads();
 #pragma unroll
             for (int j = 0; j < R; ++j) {
-                if (h0) X[c0 * MP + q + G * j] = x0[j];
-                if (h1) X[c1 * MP + q + G * j] = x1[j];
+                if (h0) X[at<MP>(c0, q + G * j)] = x0[j];
+                if (h1) X[at<MP>(c1, q + G * j)] = x1[j];
             }
             __syncthreads();
         }
@@ -645,7 +722,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
     const int st = (flag != SSL_BIN_OK) ? flag : (converged ? SSL_BIN_OK : SSL_BIN_NO_CONV);
     for (int e = tid; e < Nn * MP; e += NT) {              // noise vector c = e / MP, row e % MP
         const int c = e / MP, r = e % MP;
-        if (r < M) Enf[c * M + r] = ok ? X[perm[Ns + c] * MP + r] : make_float2(0.f, 0.f);
+        if (r < M) Enf[c * M + r] = ok ? X[at<MP>(perm[Ns + c], r)] : make_float2(0.f, 0.f);
     }
     if (sigf != nullptr)
         for (int k = tid; k < M; k += NT) sigf[k] = ok ? sig[perm[k]] : 0.0f;
