@@ -160,7 +160,10 @@ void ssl_noise_destroy(ssl_noise K);
  * accumulated in FP32 and the comparison made in FP64; a sweep without a rotation ends the solve),
  * singular values sorted descending (ties: lower column first), and
  *   En[f] = U[:, Ns..M-1]   written column-major: [F][M-Ns][M] ssl_c64.
- * R: [F][M][M] ssl_c64 (e.g. from ssl_corr_accum).  K: a handle set for the same F and M.
+ * R: [F][M][M] ssl_c64 (e.g. from ssl_corr_accum).  K: a handle set for the same F and M, or
+ * NULL for SEVD-MUSIC (the standard-eigenvalue baseline the paper compares against, Sec. II):
+ * no whitening, the same SVD of R itself -- R is Hermitian positive semi-definite, so its left
+ * singular vectors are its eigenvectors and its singular values its eigenvalues.
  * sigma: [F][M] float or NULL.  bin_status: [F] int32 or NULL.
  * conv: [F][3] int32 or NULL -> (sweeps run, rotations applied, numerical rank) per bin.
  * Numerical rank: the pivoted Householder QR that preconditions the Jacobi iteration stops at the
@@ -198,6 +201,7 @@ ssl_status ssl_peaks(ssl_ctx ctx, const float *Pbar, int n_az, int n_el, int Ns,
  * Pbar (eq.6), peaks.  X as in ssl_corr_accum; H as in ssl_music_spectrum with D = n_az*n_el;
  * prec selects the MFMA input type of the correlation and the projection (SSL_FP32, SSL_BF16 or
  * SSL_FP16; H must be stored in that type).  Pbar ([D]) and bin_status ([F]) may be NULL.
+ * K NULL selects SEVD-MUSIC (E_n from R itself, as in ssl_gsvd).
  * Uses the context's workspace (allocated on first use within the HBM budget). */
 ssl_status ssl_localize(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int M, int64_t strideF,
                         int64_t strideT, ssl_noise K, const void *H, ssl_prec prec, int n_az,
@@ -230,7 +234,7 @@ typedef struct {
     const ssl_c64 *X;          /* [F][T][M], M contiguous, strides in elements */
     int64_t strideF, strideT;
     int F, T, M, Ns;
-    ssl_noise K;               /* noise handle set for this F and M */
+    ssl_noise K;               /* noise handle set for this F and M, or NULL: SEVD-MUSIC */
     const void *H;             /* [F][D][M] steering table in the batch's prec, D = n_az*n_el */
     int n_az, n_el;
     int32_t *peaks;            /* [Ns] out */

@@ -191,12 +191,27 @@ ssl_status check_x(const ssl_c64 *X, int T, int M, int64_t sF, int64_t sT)
     return SSL_OK;
 }
 
+// A noise handle for F bins of M channels that has been set, or NULL (SEVD-MUSIC: no whitening).
+ssl_status check_noise(ssl_noise K, int F, int M)
+{
+    if (!K) return SSL_OK;
+    if (K->F != F || K->M != M) {
+        ssl_set_error("noise handle is %d x %d, call has F = %d, M = %d", K->F, K->M, F, M);
+        return SSL_ERR_ARG;
+    }
+    if (!K->is_set) {
+        ssl_set_error("noise handle was never set");
+        return SSL_ERR_STATE;
+    }
+    return SSL_OK;
+}
+
 ssl_status check_localize(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int M, int64_t strideF,
                           int64_t strideT, ssl_noise K, const void *H, ssl_prec prec, int n_az,
                           int n_el, int Ns, int p, int32_t *peaks, float *peak_val)
 {
-    if (!ctx || !K || !H || !peaks || !peak_val) {
-        ssl_set_error("ctx, K, H, peaks or peak_val is NULL");
+    if (!ctx || !H || !peaks || !peak_val) {
+        ssl_set_error("ctx, H, peaks or peak_val is NULL");
         return SSL_ERR_ARG;
     }
     ssl_status s = check_common(F, M, Ns);
@@ -211,15 +226,7 @@ ssl_status check_localize(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int M, in
         ssl_set_error("prec must be SSL_FP32, SSL_BF16 or SSL_FP16");
         return SSL_ERR_ARG;
     }
-    if (K->F != F || K->M != M) {
-        ssl_set_error("noise handle is %d x %d, call has F = %d, M = %d", K->F, K->M, F, M);
-        return SSL_ERR_ARG;
-    }
-    if (!K->is_set) {
-        ssl_set_error("noise handle was never set");
-        return SSL_ERR_STATE;
-    }
-    return SSL_OK;
+    return check_noise(K, F, M);
 }
 
 // Workspace of one block's path: R | A | En | P | Pbar | status, then (scratch only) the bin-sum
@@ -265,11 +272,15 @@ ssl_status localize_enqueue(ssl_ctx ctx, bool may_time, char *w, const LocalizeW
         return launch_corr(X, F, T, M, strideF, strideT, 1.0 / T, 0, prec, R, st);
     });
     if (e != hipSuccess) return hip_fail(e, "corr launch");
-    e = run(SSL_K_WHITEN, [&] { return launch_whiten(K->Kinv, R, A, F, M, st); });
-    if (e != hipSuccess) return hip_fail(e, "whiten launch");
+    if (K) {
+        e = run(SSL_K_WHITEN, [&] { return launch_whiten(K->Kinv, R, A, F, M, st); });
+        if (e != hipSuccess) return hip_fail(e, "whiten launch");
+    } else {
+        A = R;                                   // SEVD-MUSIC: the decomposition of R itself
+    }
     e = run(SSL_K_JACOBI, [&] {
-        return launch_jacobi(A, K->status, F, M, Ns, SSL_DEFAULT_SWEEPS, jac_lanes(ctx, M), En,
-                             nullptr, stt, nullptr, st);
+        return launch_jacobi(A, K ? K->status : nullptr, F, M, Ns, SSL_DEFAULT_SWEEPS,
+                             jac_lanes(ctx, M), En, nullptr, stt, nullptr, st);
     });
     if (e != hipSuccess) return hip_fail(e, "jacobi launch");
     e = run(SSL_K_STEER, [&] {
@@ -586,20 +597,13 @@ ssl_status ssl_gsvd(ssl_ctx ctx, const ssl_c64 *R, ssl_noise K, int F, int M, in
                     float *sigma, int32_t *bin_status, int32_t *conv, int max_sweeps,
                     void *stream)
 {
-    if (!ctx || !R || !K || !En) {
-        ssl_set_error("ctx, R, K or En is NULL");
+    if (!ctx || !R || !En) {
+        ssl_set_error("ctx, R or En is NULL");
         return SSL_ERR_ARG;
     }
     ssl_status s = check_common(F, M, Ns);
     if (s != SSL_OK) return s;
-    if (K->F != F || K->M != M) {
-        ssl_set_error("noise handle is %d x %d, call has F = %d, M = %d", K->F, K->M, F, M);
-        return SSL_ERR_ARG;
-    }
-    if (!K->is_set) {
-        ssl_set_error("noise handle was never set");
-        return SSL_ERR_STATE;
-    }
+    if ((s = check_noise(K, F, M)) != SSL_OK) return s;
     if (max_sweeps < 0 || max_sweeps > 1000) {
         ssl_set_error("max_sweeps = %d out of range [0, 1000]", max_sweeps);
         return SSL_ERR_ARG;
@@ -609,12 +613,18 @@ ssl_status ssl_gsvd(ssl_ctx ctx, const ssl_c64 *R, ssl_noise K, int F, int M, in
     if ((s = ws_reserve(ctx, align256((size_t)F * M * M * sizeof(ssl_c64)))) != SSL_OK) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
     ssl_c64 *A = static_cast<ssl_c64 *>(ctx->ws);
-    hipError_t e = timed(ctx, SSL_K_WHITEN, st,
-                         [&] { return launch_whiten(K->Kinv, R, A, F, M, st); });
-    if (e != hipSuccess) return hip_fail(e, "whiten launch");
+    hipError_t e;
+    if (K) {
+        e = timed(ctx, SSL_K_WHITEN, st, [&] { return launch_whiten(K->Kinv, R, A, F, M, st); });
+        if (e != hipSuccess) return hip_fail(e, "whiten launch");
+    } else {                                     // SEVD-MUSIC: the kernel overwrites its input
+        e = hipMemcpyAsync(A, R, (size_t)F * M * M * sizeof(ssl_c64), hipMemcpyDeviceToDevice,
+                           st);
+        if (e != hipSuccess) return hip_fail(e, "copy of R");
+    }
     e = timed(ctx, SSL_K_JACOBI, st, [&] {
-        return launch_jacobi(A, K->status, F, M, Ns, max_sweeps, jac_lanes(ctx, M), En, sigma,
-                             bin_status, conv, st);
+        return launch_jacobi(A, K ? K->status : nullptr, F, M, Ns, max_sweeps, jac_lanes(ctx, M),
+                             En, sigma, bin_status, conv, st);
     });
     return e == hipSuccess ? SSL_OK : hip_fail(e, "jacobi launch");
 }
@@ -1212,14 +1222,15 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
             ssl_set_error("%s", msg);
             return s;
         }
-        if (!d.K || !d.H || !d.peaks || !d.peak_val) {
-            ssl_set_error("block %d: K, H, peaks or peak_val is NULL", b);
+        if (!d.H || !d.peaks || !d.peak_val) {
+            ssl_set_error("block %d: H, peaks or peak_val is NULL", b);
             return SSL_ERR_ARG;
         }
-        if (d.K->F != d.F || d.K->M != d.M || !d.K->is_set) {
+        if (d.K && (d.K->F != d.F || d.K->M != d.M || !d.K->is_set)) {
             ssl_set_error("block %d: noise handle does not match (or was never set)", b);
             return SSL_ERR_ARG;
         }
+        key.push_back(d.K ? 1 : 0);
         const size_t F = d.F, M = d.M, D = (size_t)d.n_az * d.n_el, Nn = d.M - d.Ns;
         const size_t nch = (F + SSL_BINSUM_CHUNK - 1) / SSL_BINSUM_CHUNK;
         ws_total += 2 * align256(F * M * M * sizeof(ssl_c64)) + align256(F * Nn * M * sizeof(ssl_c64)) +
@@ -1281,12 +1292,12 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
         B.p = p;
         B.scale = (float)(1.0 / d.T);
         B.hprec = prec;
-        B.Kinv = reinterpret_cast<const double2 *>(d.K->Kinv);
-        B.kstatus = d.K->status;
+        B.Kinv = d.K ? reinterpret_cast<const double2 *>(d.K->Kinv) : nullptr;
+        B.kstatus = d.K ? d.K->status : nullptr;
         B.H = d.H;
         B.R = reinterpret_cast<float2 *>(w);
         w += align256(F * M * M * sizeof(ssl_c64));
-        B.A = reinterpret_cast<float2 *>(w);
+        B.A = d.K ? reinterpret_cast<float2 *>(w) : B.R;   // SEVD-MUSIC: Jacobi on R
         w += align256(F * M * M * sizeof(ssl_c64));
         B.En = reinterpret_cast<float2 *>(w);
         w += align256(F * Nn * M * sizeof(ssl_c64));
@@ -1319,6 +1330,10 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
         std::vector<std::vector<int>> members;
         std::map<std::tuple<int, const void *>, int> group_of;
         for (int b = 0; b < nblocks; ++b) {
+            if (!hb[b].Kinv) {                        // SEVD-MUSIC block: no whitening
+                key.push_back(-1);
+                continue;
+            }
             const auto ins = group_of.emplace(std::make_tuple(c_wh[b], (const void *)hb[b].Kinv),
                                               (int)first.size());
             const int g = ins.first->second;
@@ -1329,7 +1344,9 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
             members[g].push_back(b);
             key.push_back(g);                         // the sharing pattern shapes the launch
         }
-        std::vector<int> classes(c_wh);
+        std::vector<int> classes;
+        for (int b = 0; b < nblocks; ++b)
+            if (hb[b].Kinv) classes.push_back(c_wh[b]);
         std::sort(classes.begin(), classes.end());
         classes.erase(std::unique(classes.begin(), classes.end()), classes.end());
         int2 *out = hl + n_items;
