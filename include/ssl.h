@@ -91,6 +91,20 @@ const char *ssl_last_error(void);
 /* Library version as major*10000 + minor*100 + patch. */
 int ssl_version(void);
 
+/* ------------------------------------------------------------ STFT (eq.1) */
+
+/* eq.1: the short-time Fourier transform of every channel of M-channel PCM,
+ *   X_m(w, t) = sum_{n < nfft} win[n] x_m[t*hop + n] exp(-2 pi i w n / nfft),  w = 0 .. nfft/2,
+ * for the complete frames t = 0 .. T-1 (frame t covers samples t*hop .. t*hop + nfft - 1; no
+ * padding, no normalisation).  pcm: [n_samples][M] float32, channel-interleaved (device).
+ * window: [nfft] float32 (device), or NULL for the periodic Hann window sin^2(pi n / nfft).
+ * X: [nfft/2 + 1][T][M] complex64 (device), the layout ssl_corr_accum and ssl_localize read
+ * (strideF = T*M, strideT = M).  nfft a power of two in [16, 4096]; 1 <= M <= 4096; hop >= 1;
+ * 1 <= T <= 65535 with (T-1)*hop + nfft <= n_samples.  FP32 radix-2 FFT.  Timed (ssl_ctx_timing)
+ * under SSL_K_CORR. */
+ssl_status ssl_stft(ssl_ctx ctx, const float *pcm, int64_t n_samples, int M, int nfft, int hop,
+                    int T, const float *window, ssl_c64 *X, void *stream);
+
 /* ------------------------------------------------------- correlation (eq.2-3) */
 
 /* AddCorrelation + NormalizeCorrelation (eq.2, eq.3):

@@ -53,6 +53,8 @@ def lib():
         P = ctypes.c_void_p
         i32, i64, f64 = ctypes.c_int, ctypes.c_int64, ctypes.c_double
         L.orc_corr.argtypes = [P, i32, i32, i32, i64, i64, f64, P]
+        L.orc_hann.argtypes = [i32, P]
+        L.orc_stft.argtypes = [P, i32, i32, i32, P, i32, P]
         L.orc_cholesky.argtypes = [P, i32, P]
         L.orc_cholesky.restype = i32
         L.orc_chol_solve.argtypes = [P, P, i32, P]
@@ -81,6 +83,26 @@ def _c128(a) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------
+def hann(N: int) -> np.ndarray:
+    """Periodic Hann window 1/2 - 1/2 cos(2 pi n / N) (the default STFT window)."""
+    w = np.empty(N, np.float64)
+    lib().orc_hann(N, _ptr(w))
+    return w
+
+
+def stft(pcm: np.ndarray, nfft: int, hop: int, T: int, window=None) -> np.ndarray:
+    """eq.1: X [nfft/2 + 1][T][M] complex128 of pcm [n_samples][M] float32, frames t*hop .. t*hop +
+    nfft - 1 (t < T), window (float, [nfft]) or the periodic Hann window."""
+    pcm = np.ascontiguousarray(pcm, dtype=np.float32)
+    n, M = pcm.shape
+    if (T - 1) * hop + nfft > n:
+        raise ValueError("not enough samples for T frames")
+    win = hann(nfft) if window is None else np.ascontiguousarray(window, dtype=np.float64)
+    X = np.empty((nfft // 2 + 1, T, M), np.complex128)
+    lib().orc_stft(_ptr(pcm), M, nfft, hop, _ptr(win), T, _ptr(X))
+    return X
+
+
 def corr(X: np.ndarray, scale: float | None = None) -> np.ndarray:
     """eq.2-3: R[f] = scale * sum_t X[f,t,:] X[f,t,:]^H for X [F][T][M] complex64 (any strides
     along F and T with M contiguous).  scale defaults to 1/T."""

@@ -10,6 +10,9 @@
  * parallelism.
  *
  * Steps and the passages they follow:
+ *   orc_stft         eq.1: the frequency-domain input X(w, f) of every channel,
+ *                    X_m(w, f) = sum_n win[n] x_m[f*hop + n] e^{-2 pi i w n / N}
+ *                    (the direct DFT sum; orc_hann gives the default window)
  *   orc_corr         eq.2 and eq.3 (AddCorrelation + NormalizeCorrelation):
  *                    R = scale * sum_t x_t x_t^H
  *   orc_chol_solve   Sec. III-B: A = K^{-1} R.  K = L L^H (Cholesky, also the
@@ -48,7 +51,45 @@
 
 typedef double complex cplx;
 
+static const double kPi = 3.14159265358979323846;
+
 enum { ORC_OK = 0, ORC_NOT_PD = 1, ORC_NO_CONV = 2, ORC_NONFINITE = 3 };
+
+/* ------------------------------------------------------------------------ */
+/* eq.1: short-time Fourier transform                                         */
+/* ------------------------------------------------------------------------ */
+/* Periodic Hann window of length N (the reading taken for the unspecified window):
+ * win[n] = 1/2 - 1/2 cos(2 pi n / N). */
+void orc_hann(int N, double *win)
+{
+    for (int n = 0; n < N; ++n) win[n] = 0.5 - 0.5 * cos(2.0 * kPi * (double)n / (double)N);
+}
+
+/* pcm [n_samples][M] float (channel-interleaved); frame f covers samples f*hop .. f*hop + N - 1.
+ * X [N/2 + 1][T][M] complex128: X[w][f][m] = sum_{n<N} win[n] pcm[f*hop + n][m] e^{-2 pi i w n/N},
+ * summed over n in ascending order; the phase w*n/N is reduced modulo 1 exactly in integers and
+ * e^{-2 pi i k / N} taken from a table of the N values (OpenMP over bins). */
+void orc_stft(const float *pcm, int M, int N, int hop, const double *win, int T, cplx *X)
+{
+    const int F = N / 2 + 1;
+    cplx *tw = malloc(sizeof(cplx) * (size_t)N);
+    for (int k = 0; k < N; ++k) {
+        const double ph = -2.0 * kPi * (double)k / (double)N;
+        tw[k] = cos(ph) + I * sin(ph);
+    }
+#pragma omp parallel for schedule(dynamic)
+    for (int w = 0; w < F; ++w)
+        for (int f = 0; f < T; ++f)
+            for (int m = 0; m < M; ++m) {
+                cplx acc = 0.0;
+                for (int n = 0; n < N; ++n) {
+                    const double x = win[n] * (double)pcm[((size_t)f * hop + n) * M + m];
+                    acc += x * tw[((long long)w * n) % N];
+                }
+                X[((size_t)w * T + f) * M + m] = acc;
+            }
+    free(tw);
+}
 
 /* ------------------------------------------------------------------------ */
 /* eq.2 + eq.3                                                               */

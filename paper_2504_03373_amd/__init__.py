@@ -32,7 +32,7 @@ EXPORTED = [
     "ssl_ctx_set_steer_waves", "ssl_ctx_get_steer_waves", "ssl_autotune_steer",
     "ssl_noise_update_frames",
     "ssl_noise_update_frames_from",
-    "ssl_localize_noalloc", "ssl_localize_noalloc_bytes",
+    "ssl_localize_noalloc", "ssl_localize_noalloc_bytes", "ssl_stft",
 ]
 
 
@@ -83,6 +83,7 @@ def lib() -> ctypes.CDLL:
         "ssl_peaks": (I, [P, P, I, I, I, P, P, P]),
         "ssl_localize": (I, [P, P, I, I, I, I64, I64, P, P, I, I, I, I, I, P, P, P, P, P]),
         "ssl_localize_noalloc": (I, [P, P, I, I, I, I64, I64, P, P, I, I, I, I, I, P, P, P, P, P]),
+        "ssl_stft": (I, [P, P, I64, I, I, I, I, P, P, P]),
         "ssl_localize_noalloc_bytes": (ctypes.c_size_t, [I, I, I, I]),
         "ssl_localize_batch": (I, [P, ctypes.POINTER(BlockDesc), I, I, I, P]),
         "ssl_ctx_use_graphs": (I, [P, I]),
@@ -165,6 +166,18 @@ def ssl_ctx_destroy(ctx: int) -> None:
 
 def ssl_ctx_workspace_bytes(ctx: int) -> int:
     return lib().ssl_ctx_workspace_bytes(ctx)
+
+
+def ssl_stft(ctx, pcm, nfft, hop, T, X, window=None, stream=None):
+    """eq.1.  pcm: float32 device tensor [n_samples][M] (contiguous); X: complex64 device tensor
+    [nfft/2 + 1][T][M]; window: float32 device tensor [nfft] or None (periodic Hann)."""
+    if pcm.dim() != 2 or not pcm.is_contiguous():
+        raise ValueError("pcm must be a contiguous [n_samples][M] tensor")
+    n, M = pcm.shape
+    if tuple(X.shape) != (nfft // 2 + 1, T, M) or not X.is_contiguous():
+        raise ValueError(f"X must be a contiguous [{nfft // 2 + 1}][{T}][{M}] tensor")
+    _check("ssl_stft", lib().ssl_stft(ctx, _ptr(pcm), n, M, nfft, hop, T, _ptr(window), _ptr(X),
+                                      _stream(stream)))
 
 
 def ssl_corr_accum(ctx, X, scale, accumulate, prec, R, stream=None, F=None, T=None, M=None):

@@ -445,6 +445,34 @@ ssl_status ssl_ctx_timing_read(ssl_ctx ctx, int64_t *launches, double *total_ms,
     return s;
 }
 
+ssl_status ssl_stft(ssl_ctx ctx, const float *pcm, int64_t n_samples, int M, int nfft, int hop,
+                    int T, const float *window, ssl_c64 *X, void *stream)
+{
+    if (!ctx || !pcm || !X) {
+        ssl_set_error("ctx, pcm or X is NULL");
+        return SSL_ERR_ARG;
+    }
+    if (nfft < 16 || nfft > 4096 || (nfft & (nfft - 1)) != 0) {
+        ssl_set_error("nfft = %d must be a power of two in [16, 4096]", nfft);
+        return SSL_ERR_ARG;
+    }
+    if (M < 1 || M > 4096 || hop < 1 || T < 1 || T > 65535) {
+        ssl_set_error("M = %d, hop = %d, T = %d out of range", M, hop, T);
+        return SSL_ERR_ARG;
+    }
+    if ((int64_t)(T - 1) * hop + nfft > n_samples) {
+        ssl_set_error("T = %d frames of %d samples at hop %d need %lld samples, pcm has %lld", T,
+                      nfft, hop, (long long)((int64_t)(T - 1) * hop + nfft),
+                      (long long)n_samples);
+        return SSL_ERR_ARG;
+    }
+    DeviceGuard dg(ctx->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = timed(ctx, SSL_K_CORR, st,
+                         [&] { return launch_stft(pcm, M, nfft, hop, window, T, X, st); });
+    return e == hipSuccess ? SSL_OK : hip_fail(e, "stft launch");
+}
+
 ssl_status ssl_corr_accum(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int M, int64_t strideF,
                           int64_t strideT, double scale, int accumulate, ssl_prec prec, void *R,
                           void *stream)

@@ -156,6 +156,9 @@ int steer_rows_per_block(int waves);
 int binsum_threads();
 
 // --- launchers (each returns hipSuccess or the launch error) ---
+// eq.1: pcm [n_samples][M] float -> X [nfft/2 + 1][T][M]; nfft a power of two in [16, 4096]
+hipError_t launch_stft(const float *pcm, int M, int nfft, int hop, const float *win, int T,
+                       ssl_c64 *X, hipStream_t st);
 hipError_t launch_corr(const ssl_c64 *X, int F, int T, int M, int64_t sF, int64_t sT, double scale,
                        int accumulate, ssl_prec prec, void *R, hipStream_t st);
 hipError_t launch_noise_factor(ssl_c128 *K, ssl_c128 *Kinv, int32_t *status, int F, int M,

@@ -137,6 +137,55 @@ def mix(rng: np.random.Generator, pos, freqs, n_frames: int,
     return np.ascontiguousarray(X.astype(np.complex64))
 
 
+def pcm_scene(rng: np.random.Generator, pos, fs: float, n_samples: int,
+              src_u: Sequence[np.ndarray], p_src: Sequence[float],
+              noise_u: Sequence[np.ndarray], p_noise: Sequence[float],
+              sigma_d2: float) -> np.ndarray:
+    """Time-domain multichannel PCM [n_samples][M] float32 (channel-interleaved): plane-wave
+    sources and directional noises, each a white Gaussian signal of power p reaching microphone m
+    (u . p_m) / c seconds early -- applied as a phase exp(+j 2 pi f (u . p_m) / c) on its
+    circular spectrum, the free-field convention of the steering table -- plus white noise of
+    power sigma_d2 per channel."""
+    M = pos.shape[0]
+    freqs = np.fft.rfftfreq(n_samples, 1.0 / fs)
+    x = math.sqrt(sigma_d2) * rng.standard_normal((n_samples, M)) if sigma_d2 > 0 \
+        else np.zeros((n_samples, M))
+    for u, p in list(zip(src_u, p_src)) + list(zip(noise_u, p_noise)):
+        sig = math.sqrt(p) * rng.standard_normal(n_samples)
+        S = np.fft.rfft(sig)
+        adv = (np.asarray(u) @ pos.T) / C_SOUND                          # [M] seconds early
+        Sm = S[:, None] * np.exp(2j * np.pi * freqs[:, None] * adv[None, :])
+        x += np.fft.irfft(Sm, n=n_samples, axis=0)
+    return np.ascontiguousarray(x.astype(np.float32))
+
+
+def pcm_workload(M: int = 8, seed: int = 1006, nfft: int = 512, hop: int = 160, T: int = 50,
+                 n_blocks: int = 4):
+    """Time-domain version of the 8-mic (M = 8) or 60-mic workload for the STFT front end:
+    blocks of T frames of nfft samples at hop `hop` (16 kHz), sources on the direction grid.
+    Returns (workload, pcm_block(b) -> (pcm, dirs), noise_pcm) where noise_pcm holds 4M frames of
+    the noise field alone (for K)."""
+    w = workload_small(n_blocks=n_blocks, seed=seed) if M == 8 else \
+        workload_paper(n_blocks=n_blocks, seed=seed, M=M)
+    fs = 16000.0
+    n = (T - 1) * hop + nfft
+    n_noise = (max(4 * M, 50) - 1) * hop + nfft
+
+    def pcm_block(b: int):
+        rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(3)[2].spawn(b + 1)[b])
+        dirs = w._source_dirs(rng)
+        ref = w.sigma_d2 if w.white_ref else w.sigma_d2 + sum(w.p_noise)
+        p_s = ref * 10.0 ** (float(rng.uniform(*w.snr_db_range)) / 10.0)
+        az, el = w.grid.angles_deg()
+        src_u = [unit_vector(az[d], el[d]) for d in dirs]
+        return pcm_scene(rng, w.pos, fs, n, src_u, [p_s] * w.Ns, w.noise_u, w.p_noise,
+                         w.sigma_d2), dirs
+
+    rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(3)[0])
+    noise = pcm_scene(rng, w.pos, fs, n_noise, [], [], w.noise_u, w.p_noise, w.sigma_d2)
+    return w, pcm_block, noise
+
+
 # ----------------------------------------------------------------------------
 # workloads
 # ----------------------------------------------------------------------------
