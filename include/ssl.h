@@ -209,6 +209,38 @@ ssl_status ssl_music_spectrum(ssl_ctx ctx, const void *H, ssl_prec hprec, const 
 ssl_status ssl_peaks(ssl_ctx ctx, const float *Pbar, int n_az, int n_el, int Ns, int32_t *peaks,
                      float *peak_val, void *stream);
 
+/* ------------------------------------------- transfer-function tables (eq.5) */
+
+/* Shape of a transfer-function table file: M channels, F bins of an nfft-point STFT at fs, a
+ * regular n_el x n_az direction grid (azimuth az0 + k az_step, elevation el0 + l el_step degrees,
+ * flat index d = l n_az + k) -- the layout of H in ssl_music_spectrum. */
+typedef struct {
+    int M, F, n_az, n_el, nfft;
+    float fs, az0_deg, az_step_deg, el0_deg, el_step_deg;
+} ssl_tf_info;
+
+/* File layout (little-endian): 8-byte magic "SSLTF\0\0\1"; uint32 M, F, n_az, n_el, nfft; float32
+ * fs, az0_deg, az_step_deg, el0_deg, el_step_deg; 16 zero bytes (64-byte header); float64
+ * pos[M][3] (microphone positions, m); complex64 H[F][D][M].  Host only (no GPU work):
+ * ssl_tf_write stores a table held in host memory; ssl_tf_info_read reads the header and, if pos
+ * (host, [M][3]) is not NULL, the positions.  SSL_ERR_ARG for unreadable, malformed or truncated
+ * files. */
+ssl_status ssl_tf_write(const char *path, const ssl_tf_info *info, const double *pos,
+                        const ssl_c64 *H);
+ssl_status ssl_tf_info_read(const char *path, ssl_tf_info *info, double *pos);
+
+/* Loads the table of a file into device memory H in the steering-table layout of `prec`:
+ * SSL_FP32 -> [F][D][M] complex64; SSL_BF16 / SSL_FP16 -> [F][D][2M] interleaved (re, im) 16-bit
+ * pairs, rounded to nearest even.  The file is streamed through pinned host memory in slabs of
+ * whole bins (at most 16 MB each, allocated for the call) and converted on the device.  The call
+ * synchronises `stream` and returns when H is complete. */
+ssl_status ssl_tf_load(ssl_ctx ctx, const char *path, ssl_prec prec, void *H, void *stream);
+
+/* Converts a complex64 steering table H [F][D][M] (device) into the 16-bit layout Hout
+ * [F][D][2M] (device) of prec = SSL_BF16 or SSL_FP16, rounding to nearest even. */
+ssl_status ssl_steering_convert(ssl_ctx ctx, const ssl_c64 *H, int F, int D, int M, ssl_prec prec,
+                                void *Hout, void *stream);
+
 /* ----------------------------------------------------------- whole path */
 
 /* One block end to end: R = (1/T) sum X X^H (eq.2-3), A = K^{-1} R and E_n (eq.4), P (eq.5),

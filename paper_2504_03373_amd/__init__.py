@@ -33,6 +33,7 @@ EXPORTED = [
     "ssl_noise_update_frames",
     "ssl_noise_update_frames_from",
     "ssl_localize_noalloc", "ssl_localize_noalloc_bytes", "ssl_stft",
+    "ssl_tf_write", "ssl_tf_info_read", "ssl_tf_load", "ssl_steering_convert",
 ]
 
 
@@ -44,6 +45,14 @@ class BlockDesc(ctypes.Structure):
                 ("n_el", ctypes.c_int), ("peaks", ctypes.c_void_p), ("peak_val", ctypes.c_void_p),
                 ("Pbar", ctypes.c_void_p), ("bin_status", ctypes.c_void_p)]
 KERNELS = ["corr", "noise", "whiten", "jacobi", "steer", "binsum"]
+
+
+class TfInfo(ctypes.Structure):
+    """ssl_tf_info."""
+    _fields_ = [("M", ctypes.c_int), ("F", ctypes.c_int), ("n_az", ctypes.c_int),
+                ("n_el", ctypes.c_int), ("nfft", ctypes.c_int), ("fs", ctypes.c_float),
+                ("az0_deg", ctypes.c_float), ("az_step_deg", ctypes.c_float),
+                ("el0_deg", ctypes.c_float), ("el_step_deg", ctypes.c_float)]
 
 
 class SSLError(RuntimeError):
@@ -84,6 +93,10 @@ def lib() -> ctypes.CDLL:
         "ssl_localize": (I, [P, P, I, I, I, I64, I64, P, P, I, I, I, I, I, P, P, P, P, P]),
         "ssl_localize_noalloc": (I, [P, P, I, I, I, I64, I64, P, P, I, I, I, I, I, P, P, P, P, P]),
         "ssl_stft": (I, [P, P, I64, I, I, I, I, P, P, P]),
+        "ssl_tf_write": (I, [ctypes.c_char_p, ctypes.POINTER(TfInfo), P, P]),
+        "ssl_tf_info_read": (I, [ctypes.c_char_p, ctypes.POINTER(TfInfo), P]),
+        "ssl_tf_load": (I, [P, ctypes.c_char_p, I, P, P]),
+        "ssl_steering_convert": (I, [P, P, I, I, I, I, P, P]),
         "ssl_localize_noalloc_bytes": (ctypes.c_size_t, [I, I, I, I]),
         "ssl_localize_batch": (I, [P, ctypes.POINTER(BlockDesc), I, I, I, P]),
         "ssl_ctx_use_graphs": (I, [P, I]),
@@ -166,6 +179,41 @@ def ssl_ctx_destroy(ctx: int) -> None:
 
 def ssl_ctx_workspace_bytes(ctx: int) -> int:
     return lib().ssl_ctx_workspace_bytes(ctx)
+
+
+def ssl_tf_write(path, info: "TfInfo", pos, H) -> None:
+    """Host: writes a table file.  pos: float64 numpy [M][3]; H: complex64 numpy [F][D][M]."""
+    import numpy as np
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    H = np.ascontiguousarray(H, dtype=np.complex64)
+    if pos.shape != (info.M, 3) or H.shape != (info.F, info.n_az * info.n_el, info.M):
+        raise ValueError("pos / H shapes do not match info")
+    _check("ssl_tf_write", lib().ssl_tf_write(os.fsencode(path), ctypes.byref(info),
+                                              pos.ctypes.data_as(ctypes.c_void_p),
+                                              H.ctypes.data_as(ctypes.c_void_p)))
+
+
+def ssl_tf_info_read(path):
+    """Host: returns (TfInfo, pos float64 numpy [M][3])."""
+    import numpy as np
+    info = TfInfo()
+    _check("ssl_tf_info_read", lib().ssl_tf_info_read(os.fsencode(path), ctypes.byref(info), None))
+    pos = np.zeros((info.M, 3), np.float64)
+    _check("ssl_tf_info_read", lib().ssl_tf_info_read(os.fsencode(path), ctypes.byref(info),
+                                                      pos.ctypes.data_as(ctypes.c_void_p)))
+    return info, pos
+
+
+def ssl_tf_load(ctx, path, prec, H, stream=None):
+    """Loads a table file into the device tensor H ([F][D][M] complex64 for SSL_FP32, [F][D][2M]
+    bfloat16 / float16 otherwise)."""
+    _check("ssl_tf_load", lib().ssl_tf_load(ctx, os.fsencode(path), prec, _ptr(H), _stream(stream)))
+
+
+def ssl_steering_convert(ctx, H, prec, Hout, stream=None):
+    F, D, M = H.shape
+    _check("ssl_steering_convert", lib().ssl_steering_convert(ctx, _ptr(H), F, D, M, prec, _ptr(Hout),
+                                                              _stream(stream)))
 
 
 def ssl_stft(ctx, pcm, nfft, hop, T, X, window=None, stream=None):
