@@ -316,6 +316,54 @@ def uneven_phase(args) -> dict:
                     "replay), M in {8,16,32,60}, F in {257,513}, Ns in {1,2,3}"}
 
 
+def streaming_phase(args, S, ctx, w, noise, H32, Xs) -> dict:
+    """One 60-channel stream localized at frame rate (eq.3: the window of the T frames ending at
+    each new frame): per frame, push the frame (rank-2 FP64 update of the window sum) and run the
+    whole method on the window, FP32 path; warm-started Jacobi (from the previous frame's singular
+    vectors) and cold solves, device time per frame with events on the launch stream."""
+    import numpy as np
+    import torch
+    dev = "cuda:0"
+    F, T, M, Ns, D = w.F, w.T, w.M, w.Ns, w.D
+    frames = torch.cat([Xs[0], Xs[1]], dim=1).contiguous()          # [F][2T][M]
+    n = min(args.stream_frames, frames.shape[1] - T)
+    pk = torch.zeros(Ns, dtype=torch.int32, device=dev)
+    pv = torch.zeros(Ns, dtype=torch.float32, device=dev)
+    bst = torch.zeros(F, dtype=torch.int32, device=dev)
+    conv = torch.zeros((F, 3), dtype=torch.int32, device=dev)
+    res = {"M": M, "F": F, "T": T, "D": D, "frames": n, "prec": "fp32",
+           "kind": "one stream, one frame per step: push (rank-2 FP64 window update) + "
+                   "localization of the window; device time per frame"}
+    for warm in (1, 0):
+        s = S.ssl_sliding_create(ctx, F, M, T)
+        S.ssl_sliding_push(s, frames[:, :T, :])
+        S.ssl_sliding_localize(s, noise, H32, S.SSL_FP32, w.grid.n_az, w.grid.n_el, Ns, 2, 0, pk,
+                               pv, None, bst, conv)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(n)]
+        sweeps = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(n):
+            ev[k][0].record()
+            S.ssl_sliding_push(s, frames[:, T + k:T + k + 1, :])
+            S.ssl_sliding_localize(s, noise, H32, S.SSL_FP32, w.grid.n_az, w.grid.n_el, Ns, 2,
+                                   warm, pk, pv, None, bst, conv)
+            ev[k][1].record()
+            sweeps.append(conv[:, 0].clone())
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        lat = np.array([a.elapsed_time(b) for a, b in ev])
+        ok = bool((bst.cpu().numpy() == 0).all())
+        sw = float(torch.stack(sweeps).float().mean().item())
+        res["warm" if warm else "cold"] = {
+            "frames_per_s": round(n / wall, 1), "p50_ms": round(float(np.percentile(lat, 50)), 4),
+            "p99_ms": round(float(np.percentile(lat, 99)), 4), "mean_sweeps": round(sw, 3),
+            "status_ok": ok}
+        S.ssl_sliding_destroy(s)
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -354,6 +402,8 @@ def main() -> int:
     ap.add_argument("--uneven-blocks", type=int, default=512,
                     help="blocks of the uneven-shape batch (0 = skip)")
     ap.add_argument("--uneven-steps", type=int, default=5)
+    ap.add_argument("--stream-frames", type=int, default=50,
+                    help="frame-rate localizations of one 60-channel stream (eq.3 window), 0 = skip")
     ap.add_argument("--serve-mixed", default="bf16",
                     help="a second batched serving leg at this MFMA input type ('' = skip)")
     ap.add_argument("--serve-fp32-seconds", type=float, default=1.0,
@@ -641,6 +691,8 @@ def main() -> int:
     }
     if args.uneven_blocks > 0:
         out["uneven"] = uneven_phase(args)
+    if args.stream_frames > 0:
+        out["streaming"] = streaming_phase(args, S, ctx, w, noise, H32, Xs)
     if "h2d_serial" in main_r:
         out["h2d"] = {"serial": round(main_r["h2d_serial"], 2),
                       "overlapped": round(main_r["h2d_overlap"], 2),

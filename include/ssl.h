@@ -41,6 +41,7 @@ typedef struct { double re, im; } ssl_c128;
 
 typedef struct ssl_ctx_s *ssl_ctx;      /* library-owned: device, workspace (HBM budget) */
 typedef struct ssl_noise_s *ssl_noise;  /* library-owned: one stream's K and its FP64 factor */
+typedef struct ssl_sliding_s *ssl_sliding;  /* library-owned: a frame stream's eq.3 window */
 
 typedef enum {
     SSL_OK = 0,
@@ -272,6 +273,44 @@ ssl_status ssl_localize_noalloc(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int
                                 float *peak_val, float *Pbar, int32_t *bin_status, void *stream);
 /* Scratch bytes ssl_localize_noalloc needs for one block of this shape (0 for invalid shapes). */
 size_t ssl_localize_noalloc_bytes(int F, int M, int Ns, int D);
+
+/* ------------------------------------------------- frame stream (eq.3 window) */
+
+/* Localization at frame rate, eq.3 as printed: R(w, f) = (1/T) sum_{i=-T+1}^{0} x(w, f+i)
+ * x(w, f+i)^H over the T frames ending at the latest frame f, maintained as frames arrive (the
+ * stream processing the paper leaves to future work, Sec. VI).  The state keeps the last T frames
+ * of every bin, their outer-product sum S in FP64 (each pushed frame x adds x x^H and removes the
+ * o o^H of the frame o it displaces, a rank-2 update; S is recomputed exactly from the stored
+ * frames each time T more frames have passed) and the singular vectors of the last solve.
+ * create: F <= 65535 bins, 1 <= M <= 64 channels, 1 <= T <= 65535; allocates 8FTM + 24FM^2 bytes
+ * from ctx (within its HBM budget).  destroy synchronises the device. */
+ssl_status ssl_sliding_create(ssl_ctx ctx, int F, int M, int T, ssl_sliding *out);
+void ssl_sliding_destroy(ssl_sliding s);
+/* Appends n frames X [F][n][M] (complex64, device; element strides strideF, strideT, M
+ * contiguous), oldest first. */
+ssl_status ssl_sliding_push(ssl_sliding s, const ssl_c64 *X, int n, int64_t strideF,
+                            int64_t strideT, void *stream);
+/* Frames pushed so far (-1 for NULL). */
+int64_t ssl_sliding_frames(ssl_sliding s);
+/* The current window's R = S / T, [F][M][M] complex128 (device). */
+ssl_status ssl_sliding_corr(ssl_sliding s, ssl_c128 *R, void *stream);
+/* The whole method on the current window (as ssl_localize from R on; R rounded to complex64 from
+ * the FP64 window sum; prec selects the projection's input type; K NULL: SEVD-MUSIC).
+ * warm = 0: the cold solve of ssl_gsvd.  warm != 0 and a previous solve on this state: a
+ * warm-started Jacobi -- Y = A^H U0 with U0 the previous window's sorted left singular vectors,
+ * one-sided Jacobi on Y accumulating its rotations into U0 -- which needs a few sweeps when the
+ * window moved by a few frames and the spectrum is well separated (same rotation rule and
+ * tolerance as the cold solve; the result matches the cold solve's to within the parity bounds,
+ * not bit for bit).  A warm solve is used only within T frames of the last cold solve, which
+ * re-anchors the singular vectors (rounding in U = U0 V accumulates over warm solves).  Either
+ * way the sorted singular vectors are kept for the next call.  Needs at least T pushed frames
+ * (SSL_ERR_STATE).
+ * conv: [F][3] int32 or NULL (sweeps, rotations, rank as in ssl_gsvd; M for a warm solve).
+ * Uses the context's workspace; calls on one ctx must be ordered on one stream. */
+ssl_status ssl_sliding_localize(ssl_sliding s, ssl_noise K, const void *H, ssl_prec prec,
+                                int n_az, int n_el, int Ns, int p, int warm, int32_t *peaks,
+                                float *peak_val, float *Pbar, int32_t *bin_status, int32_t *conv,
+                                void *stream);
 
 /* ------------------------------------------------------------ batched path */
 

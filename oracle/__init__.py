@@ -231,6 +231,27 @@ def localize(X: np.ndarray, K: np.ndarray, H: np.ndarray, n_az: int, n_el: int, 
     return out
 
 
+def sliding_corr(X: np.ndarray, T: int, f: int) -> np.ndarray:
+    """eq.3 as printed: R(w, f) = (1/T) sum_{i = -T+1}^{0} x(w, f + i) x(w, f + i)^H, the
+    correlation of the T frames ending at frame f of a frame sequence X [F][n_frames][M]
+    (complex64); needs T - 1 <= f < n_frames."""
+    if f < T - 1 or f >= X.shape[1]:
+        raise ValueError("frame f has fewer than T frames before it, or is past the sequence")
+    return corr(X[:, f - T + 1:f + 1, :], 1.0 / T)
+
+
+def localize_frame(X: np.ndarray, T: int, f: int, K, H: np.ndarray, n_az: int, n_el: int,
+                   Ns: int, p: int = 2, nthreads: int = 1):
+    """The localization of frame f of a frame sequence: eq.3's window of the T frames ending at f,
+    then the whole method on it (K None: SEVD-MUSIC, K = I)."""
+    if f < T - 1 or f >= X.shape[1]:
+        raise ValueError("frame f has fewer than T frames before it, or is past the sequence")
+    W = X[:, f - T + 1:f + 1, :]
+    if K is None:
+        K = np.broadcast_to(np.eye(X.shape[2], dtype=np.complex128), (X.shape[0],) + (X.shape[2],) * 2)
+    return localize(W, K, H, n_az, n_el, Ns, p=p, nthreads=nthreads)
+
+
 def noise_corr(Xn: np.ndarray) -> np.ndarray:
     """K estimated from noise-only frames with the eq.2-3 definition (scale 1/N)."""
     return corr(Xn)

@@ -34,6 +34,8 @@ EXPORTED = [
     "ssl_noise_update_frames_from",
     "ssl_localize_noalloc", "ssl_localize_noalloc_bytes", "ssl_stft",
     "ssl_tf_write", "ssl_tf_info_read", "ssl_tf_load", "ssl_steering_convert",
+    "ssl_sliding_create", "ssl_sliding_destroy", "ssl_sliding_push", "ssl_sliding_frames",
+    "ssl_sliding_corr", "ssl_sliding_localize",
 ]
 
 
@@ -93,6 +95,12 @@ def lib() -> ctypes.CDLL:
         "ssl_localize": (I, [P, P, I, I, I, I64, I64, P, P, I, I, I, I, I, P, P, P, P, P]),
         "ssl_localize_noalloc": (I, [P, P, I, I, I, I64, I64, P, P, I, I, I, I, I, P, P, P, P, P]),
         "ssl_stft": (I, [P, P, I64, I, I, I, I, P, P, P]),
+        "ssl_sliding_create": (I, [P, I, I, I, ctypes.POINTER(P)]),
+        "ssl_sliding_destroy": (None, [P]),
+        "ssl_sliding_push": (I, [P, P, I, I64, I64, P]),
+        "ssl_sliding_frames": (I64, [P]),
+        "ssl_sliding_corr": (I, [P, P, P]),
+        "ssl_sliding_localize": (I, [P, P, P, I, I, I, I, I, I, P, P, P, P, P, P]),
         "ssl_tf_write": (I, [ctypes.c_char_p, ctypes.POINTER(TfInfo), P, P]),
         "ssl_tf_info_read": (I, [ctypes.c_char_p, ctypes.POINTER(TfInfo), P]),
         "ssl_tf_load": (I, [P, ctypes.c_char_p, I, P, P]),
@@ -214,6 +222,41 @@ def ssl_steering_convert(ctx, H, prec, Hout, stream=None):
     F, D, M = H.shape
     _check("ssl_steering_convert", lib().ssl_steering_convert(ctx, _ptr(H), F, D, M, prec, _ptr(Hout),
                                                               _stream(stream)))
+
+
+def ssl_sliding_create(ctx, F: int, M: int, T: int) -> int:
+    out = ctypes.c_void_p()
+    _check("ssl_sliding_create", lib().ssl_sliding_create(ctx, F, M, T, ctypes.byref(out)))
+    return out.value
+
+
+def ssl_sliding_destroy(s) -> None:
+    lib().ssl_sliding_destroy(s)
+
+
+def ssl_sliding_push(s, X, stream=None):
+    """Appends the frames of X: complex64 device tensor [F][n][M] (M contiguous)."""
+    F, n, M = X.shape
+    sF, sT, sM = X.stride()
+    if sM != 1:
+        raise ValueError("X must be contiguous along M")
+    _check("ssl_sliding_push", lib().ssl_sliding_push(s, _ptr(X), n, sF, sT, _stream(stream)))
+
+
+def ssl_sliding_frames(s) -> int:
+    return int(lib().ssl_sliding_frames(s))
+
+
+def ssl_sliding_corr(s, R, stream=None):
+    _check("ssl_sliding_corr", lib().ssl_sliding_corr(s, _ptr(R), _stream(stream)))
+
+
+def ssl_sliding_localize(s, noise, H, prec, n_az, n_el, Ns, p, warm, peaks, peak_val, Pbar=None,
+                         bin_status=None, conv=None, stream=None):
+    _check("ssl_sliding_localize",
+           lib().ssl_sliding_localize(s, noise, _ptr(H), prec, n_az, n_el, Ns, p, int(warm),
+                                      _ptr(peaks), _ptr(peak_val), _ptr(Pbar), _ptr(bin_status),
+                                      _ptr(conv), _stream(stream)))
 
 
 def ssl_stft(ctx, pcm, nfft, hop, T, X, window=None, stream=None):

@@ -765,6 +765,185 @@ ssl_status ssl_localize_noalloc(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int
                             Pbar, bin_status, static_cast<hipStream_t>(stream));
 }
 
+ssl_status ssl_sliding_create(ssl_ctx ctx, int F, int M, int T, ssl_sliding *out)
+{
+    if (!ctx || !out) {
+        ssl_set_error("ctx or out is NULL");
+        return SSL_ERR_ARG;
+    }
+    *out = nullptr;
+    if (F < 1 || F > 65535 || M < 1 || M > SSL_MAX_M || T < 1 || T > 65535) {
+        ssl_set_error("F = %d, M = %d, T = %d out of range", F, M, T);
+        return SSL_ERR_ARG;
+    }
+    ssl_sliding s = new (std::nothrow) ssl_sliding_s();
+    if (!s) {
+        ssl_set_error("out of host memory");
+        return SSL_ERR_NOMEM;
+    }
+    s->ctx = ctx;
+    s->F = F;
+    s->M = M;
+    s->T = T;
+    DeviceGuard dg(ctx->device);
+    const size_t bRing = (size_t)F * T * M * sizeof(ssl_c64),
+                 bS = (size_t)F * M * M * sizeof(ssl_c128), bU = (size_t)F * M * M * sizeof(ssl_c64);
+    ssl_status st = dev_alloc(ctx, (void **)&s->ring, bRing, "frame ring");
+    if (st == SSL_OK) st = dev_alloc(ctx, (void **)&s->S, bS, "sliding correlation");
+    if (st == SSL_OK) st = dev_alloc(ctx, (void **)&s->U, bU, "singular vectors");
+    if (st == SSL_OK) {
+        s->bytes = bRing + bS + bU;
+        const hipError_t e = hipMemset(s->S, 0, bS);
+        if (e != hipSuccess) st = hip_fail(e, "hipMemset");
+    }
+    if (st != SSL_OK) {
+        dev_free(ctx, s->ring, s->ring ? bRing : 0);
+        dev_free(ctx, s->S, s->S ? bS : 0);
+        dev_free(ctx, s->U, s->U ? bU : 0);
+        delete s;
+        return st;
+    }
+    *out = s;
+    return SSL_OK;
+}
+
+void ssl_sliding_destroy(ssl_sliding s)
+{
+    if (!s) return;
+    DeviceGuard dg(s->ctx->device);
+    (void)hipDeviceSynchronize();
+    dev_free(s->ctx, s->ring, (size_t)s->F * s->T * s->M * sizeof(ssl_c64));
+    dev_free(s->ctx, s->S, (size_t)s->F * s->M * s->M * sizeof(ssl_c128));
+    dev_free(s->ctx, s->U, (size_t)s->F * s->M * s->M * sizeof(ssl_c64));
+    delete s;
+}
+
+int64_t ssl_sliding_frames(ssl_sliding s) { return s ? s->pushed : -1; }
+
+ssl_status ssl_sliding_push(ssl_sliding s, const ssl_c64 *X, int n, int64_t strideF,
+                            int64_t strideT, void *stream)
+{
+    if (!s || !X) {
+        ssl_set_error("stream state or X is NULL");
+        return SSL_ERR_ARG;
+    }
+    if (n < 1 || n > 65535 || strideT < s->M || strideF < 0) {
+        ssl_set_error("n = %d, strides (%lld, %lld) invalid for M = %d", n, (long long)strideF,
+                      (long long)strideT, s->M);
+        return SSL_ERR_ARG;
+    }
+    DeviceGuard dg(s->ctx->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = timed(s->ctx, SSL_K_CORR, st, [&] {
+        return launch_sliding_push(X, n, strideF, strideT, s->F, s->M, s->T, s->pushed, s->ring,
+                                   s->S, st);
+    });
+    if (e != hipSuccess) return hip_fail(e, "sliding push launch");
+    s->pushed += n;
+    s->since_refresh += n;
+    if (s->pushed >= s->T && s->since_refresh >= s->T) {
+        // exact recomputation of S from the ring (FP64), so that update rounding never builds up
+        e = timed(s->ctx, SSL_K_CORR, st, [&] {
+            return launch_corr(s->ring, s->F, s->T, s->M, (int64_t)s->T * s->M, s->M, 1.0, 0,
+                               SSL_FP64, s->S, st);
+        });
+        if (e != hipSuccess) return hip_fail(e, "sliding refresh launch");
+        s->since_refresh = 0;
+    }
+    return SSL_OK;
+}
+
+ssl_status ssl_sliding_corr(ssl_sliding s, ssl_c128 *R, void *stream)
+{
+    if (!s || !R) {
+        ssl_set_error("stream state or R is NULL");
+        return SSL_ERR_ARG;
+    }
+    DeviceGuard dg(s->ctx->device);
+    const hipError_t e = launch_sliding_scale(s->S, (int64_t)s->F * s->M * s->M, 1.0 / s->T, R,
+                                              true, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SSL_OK : hip_fail(e, "sliding scale launch");
+}
+
+ssl_status ssl_sliding_localize(ssl_sliding s, ssl_noise K, const void *H, ssl_prec prec,
+                                int n_az, int n_el, int Ns, int p, int warm, int32_t *peaks,
+                                float *peak_val, float *Pbar, int32_t *bin_status, int32_t *conv,
+                                void *stream)
+{
+    if (!s || !H || !peaks || !peak_val) {
+        ssl_set_error("stream state, H, peaks or peak_val is NULL");
+        return SSL_ERR_ARG;
+    }
+    const int F = s->F, M = s->M;
+    ssl_status st_ = check_common(F, M, Ns);
+    if (st_ != SSL_OK) return st_;
+    if ((st_ = check_grid(n_az, n_el, Ns)) != SSL_OK) return st_;
+    if ((st_ = check_noise(K, F, M)) != SSL_OK) return st_;
+    if (p != 1 && p != 2) {
+        ssl_set_error("p = %d must be 1 or 2", p);
+        return SSL_ERR_ARG;
+    }
+    if (prec != SSL_FP32 && prec != SSL_BF16 && prec != SSL_FP16) {
+        ssl_set_error("prec must be SSL_FP32, SSL_BF16 or SSL_FP16");
+        return SSL_ERR_ARG;
+    }
+    if (s->pushed < s->T) {
+        ssl_set_error("%lld frames pushed, the window needs T = %d", (long long)s->pushed, s->T);
+        return SSL_ERR_STATE;
+    }
+    ssl_ctx ctx = s->ctx;
+    const int D = n_az * n_el;
+    const LocalizeWs L = localize_ws(F, M, Ns, D);
+    DeviceGuard dg(ctx->device);
+    if ((st_ = ws_reserve(ctx, L.total)) != SSL_OK) return st_;
+    if ((st_ = binsum_reserve(ctx, F, D)) != SSL_OK) return st_;
+    char *w = static_cast<char *>(ctx->ws);
+    ssl_c64 *R = reinterpret_cast<ssl_c64 *>(w);
+    ssl_c64 *A = reinterpret_cast<ssl_c64 *>(w + L.bR);
+    ssl_c64 *En = reinterpret_cast<ssl_c64 *>(w + 2 * L.bR);
+    float *P = reinterpret_cast<float *>(w + 2 * L.bR + L.bE);
+    float *Pb = Pbar ? Pbar : reinterpret_cast<float *>(w + 2 * L.bR + L.bE + L.bP);
+    int32_t *stt = bin_status ? bin_status
+                              : reinterpret_cast<int32_t *>(w + 2 * L.bR + L.bE + L.bP + L.bB);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = timed(ctx, SSL_K_CORR, st, [&] {
+        return launch_sliding_scale(s->S, (int64_t)F * M * M, 1.0 / s->T, R, false, st);
+    });
+    if (e != hipSuccess) return hip_fail(e, "sliding scale launch");
+    if (K) {
+        e = timed(ctx, SSL_K_WHITEN, st, [&] { return launch_whiten(K->Kinv, R, A, F, M, st); });
+        if (e != hipSuccess) return hip_fail(e, "whiten launch");
+    } else {
+        A = R;
+    }
+    const int32_t *kst = K ? K->status : nullptr;
+    if (warm && s->have_U && s->pushed - s->cold_at < s->T) {
+        e = timed(ctx, SSL_K_JACOBI, st, [&] {
+            return launch_jacobi_warm(A, kst, F, M, Ns, SSL_DEFAULT_SWEEPS, s->U, En, stt, conv,
+                                      st);
+        });
+    } else {
+        e = timed(ctx, SSL_K_JACOBI, st, [&] {
+            return launch_jacobi(A, kst, F, M, Ns, SSL_DEFAULT_SWEEPS, jac_lanes(ctx, M), En,
+                                 nullptr, stt, conv, st, s->U);
+        });
+        if (e == hipSuccess) {
+            s->have_U = true;
+            s->cold_at = s->pushed;
+        }
+    }
+    if (e != hipSuccess) return hip_fail(e, "jacobi launch");
+    e = timed(ctx, SSL_K_STEER, st, [&] {
+        return launch_steer(H, prec, En, F, D, M, Ns, p, stt, P, st_waves(ctx, M, Ns, prec), st);
+    });
+    if (e != hipSuccess) return hip_fail(e, "steer launch");
+    e = timed(ctx, SSL_K_BINSUM, st, [&] {
+        return launch_binsum_peaks(P, F, D, Pb, ctx->binsum_part, n_az, n_el, Ns, peaks, peak_val,
+                                   st);
+    });
+    return e == hipSuccess ? SSL_OK : hip_fail(e, "bin-sum launch");
+}
+
 }  // extern "C"
 
 // ------------------------------------------------------------------------------------------------

@@ -282,7 +282,8 @@ template <int MP, int G>
 __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int M, int Ns,
                                            int max_sweeps, float2 *__restrict__ Enf,
                                            float *__restrict__ sigf, int32_t *__restrict__ stf,
-                                           int32_t *__restrict__ convf)
+                                           int32_t *__restrict__ convf,
+                                           float2 *__restrict__ Uf = nullptr)
 {
     typedef JacobiCfg<MP, G> C;
     constexpr int R = C::R;
@@ -726,6 +727,12 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
     }
     if (sigf != nullptr)
         for (int k = tid; k < M; k += NT) sigf[k] = ok ? sig[perm[k]] : 0.0f;
+    if (Uf != nullptr)                                     // all M sorted columns (identity if failed)
+        for (int e = tid; e < M * MP; e += NT) {
+            const int c = e / MP, r = e % MP;
+            if (r < M)
+                Uf[c * M + r] = ok ? X[at<MP>(perm[c], r)] : make_float2(r == c ? 1.f : 0.f, 0.f);
+        }
     if (tid == 0) {
         if (stf != nullptr) *stf = st;
         if (convf != nullptr) {
@@ -741,12 +748,13 @@ template <int MP, int G>
 __global__ __launch_bounds__((JacobiCfg<MP, G>::THREADS)) void jacobi_svd(
     float2 *__restrict__ A, const int32_t *__restrict__ kstatus, int M, int Ns, int max_sweeps,
     float2 *__restrict__ En, float *__restrict__ sigma, int32_t *__restrict__ bin_status,
-    int32_t *__restrict__ conv)
+    int32_t *__restrict__ conv, float2 *__restrict__ U)
 {
     const int f = blockIdx.x;
     jacobi_bin<MP, G>(A + (size_t)f * M * M, kstatus ? kstatus[f] : SSL_BIN_OK, M, Ns, max_sweeps,
                       En + (size_t)f * (M - Ns) * M, sigma ? sigma + (size_t)f * M : nullptr,
-                      bin_status ? bin_status + f : nullptr, conv ? conv + 3 * f : nullptr);
+                      bin_status ? bin_status + f : nullptr, conv ? conv + 3 * f : nullptr,
+                      U ? U + (size_t)f * M * M : nullptr);
 }
 
 // Persistent: a fixed grid of workgroups draws (block, bin) items from a device counter until the
@@ -779,14 +787,264 @@ __attribute__((amdgpu_waves_per_eu(JacobiCfg<MP, G>::WAVES_PER_EU))) void jacobi
     }
 }
 
+// Warm-started solve for a stream of windows whose A changes little from one call to the next
+// (the sliding correlation of eq.3, one frame in and one out): U0 = the previous solve's sorted
+// left singular vectors.  Y = A^H U0 has nearly orthogonal columns when U0 is close to A's left
+// singular vectors; one-sided Jacobi on Y from the right, Y V = Z with orthogonal columns,
+// applying the same rotations to U = U0 V, gives A^H U = Z: U's columns are left singular vectors
+// of A with sigma_k = |z_k|.  A few sweeps replace the two preconditioning QRs and the cold
+// sweeps.  No rank truncation: columns of Y in A's null space are rounding-level and are only
+// rotated among themselves or by negligible angles, so they stay inside the noise subspace.
+// LDS: Y and U, both MP x MP complex64 column-major (64 KB at MP = 64).  Same pair test and
+// rotation as the cold sweeps (jacobi_pair), on both matrices.
+template <int MP, int G, int NR>
+__device__ __forceinline__ bool warm_pair(float2 *Ys, float2 *Us, int ci, int cj, int q,
+                                          double tol2)
+{
+    float2 bi[NR], bj[NR], ui[NR], uj[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        const int r = q + G * k;
+        bi[k] = Ys[at<MP>(ci, r)];
+        bj[k] = Ys[at<MP>(cj, r)];
+        ui[k] = Us[at<MP>(ci, r)];
+        uj[k] = Us[at<MP>(cj, r)];
+    }
+    __builtin_amdgcn_sched_barrier(0);            // every read in flight before the products
+    float al = 0.f, be = 0.f, gr = 0.f, gi = 0.f;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        al = fmaf(bi[k].x, bi[k].x, fmaf(bi[k].y, bi[k].y, al));
+        be = fmaf(bj[k].x, bj[k].x, fmaf(bj[k].y, bj[k].y, be));
+        gr = fmaf(bi[k].x, bj[k].x, fmaf(bi[k].y, bj[k].y, gr));
+        gi = fmaf(bi[k].x, bj[k].y, fmaf(-bi[k].y, bj[k].x, gi));
+    }
+    al = group_sum<G>(al);
+    be = group_sum<G>(be);
+    gr = group_sum<G>(gr);
+    gi = group_sum<G>(gi);
+    const double g2 = (double)gr * gr + (double)gi * gi;
+    const double ab = (double)al * be;
+    if (!(g2 > tol2 * ab && ab > 0.0)) return false;
+    const float g2f = (float)g2;
+    float rg;
+    if (g2f >= 1e-36f) {
+        rg = __builtin_amdgcn_rsqf(g2f);
+    } else {
+        const float ax = fabsf(gr), ay = fabsf(gi);
+        const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+        const float rt = mn * __builtin_amdgcn_rcpf(mx);
+        rg = __builtin_amdgcn_rcpf(mx * __builtin_amdgcn_sqrtf(fmaf(rt, rt, 1.0f)));
+    }
+    const float zeta = (be - al) * 0.5f * rg;
+    const float az = fminf(fabsf(zeta), 1e18f);
+    float t = __builtin_amdgcn_rcpf(az + __builtin_amdgcn_sqrtf(fmaf(az, az, 1.0f)));
+    t = copysignf(t, zeta);
+    const float c = rsqrt_refined(fmaf(t, t, 1.0f));
+    const float s = c * t;
+    const float wr = s * gr * rg;
+    const float wi = -s * gi * rg;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        const int r = q + G * k;
+        float2 x = bi[k], y = bj[k];
+        Ys[at<MP>(ci, r)] = make_float2(fmaf(c, x.x, -fmaf(wr, y.x, -wi * y.y)),
+                                        fmaf(c, x.y, -fmaf(wr, y.y, wi * y.x)));
+        Ys[at<MP>(cj, r)] = make_float2(fmaf(c, y.x, fmaf(wr, x.x, wi * x.y)),
+                                        fmaf(c, y.y, fmaf(wr, x.y, -wi * x.x)));
+        x = ui[k];
+        y = uj[k];
+        Us[at<MP>(ci, r)] = make_float2(fmaf(c, x.x, -fmaf(wr, y.x, -wi * y.y)),
+                                        fmaf(c, x.y, -fmaf(wr, y.y, wi * y.x)));
+        Us[at<MP>(cj, r)] = make_float2(fmaf(c, y.x, fmaf(wr, x.x, wi * x.y)),
+                                        fmaf(c, y.y, fmaf(wr, x.y, -wi * x.x)));
+    }
+    return true;
+}
+
+template <int MP, int G>
+__global__ __launch_bounds__((JacobiCfg<MP, G>::THREADS)) void jacobi_warm(
+    const float2 *__restrict__ Aall, const int32_t *__restrict__ kstatus, int M, int Ns,
+    int max_sweeps, float2 *__restrict__ Uall, float2 *__restrict__ Enall,
+    int32_t *__restrict__ status, int32_t *__restrict__ conv)
+{
+    typedef JacobiCfg<MP, G> C;
+    constexpr int R = C::R;
+    constexpr int NT = C::THREADS;
+    constexpr int NG = C::NG;
+    static_assert((MP / 4) * (MP / 4) <= NT, "one 4 x 4 tile of Y per thread");
+    __shared__ float2 Ys[MP * MP];      // A (column-major), then Y = A^H U0, then Z
+    __shared__ float2 Us[MP * MP];      // U0, then U = U0 V
+    __shared__ float sig[MP];
+    __shared__ int perm[MP];
+    __shared__ int flag;
+    __shared__ float amax_s;
+    __shared__ int rot_total;
+
+    const int f = blockIdx.x;
+    const float2 *Af = Aall + (size_t)f * M * M;
+    float2 *Uf = Uall + (size_t)f * M * M;
+    float2 *Enf = Enall + (size_t)f * (M - Ns) * M;
+    const int tid = threadIdx.x;
+    const int g = tid / G;
+    const int q = tid % G;
+    const int Nn = M - Ns;
+
+    if (tid == 0) {
+        flag = kstatus ? kstatus[f] : SSL_BIN_OK;
+        amax_s = 0.0f;
+        rot_total = 0;
+    }
+    // A column-major (entry (i, j) at column j, row i) and U0; zero padding
+    float amax = 0.0f;
+    bool nonfinite = false;
+    for (int e = tid; e < MP * MP; e += NT) {
+        const int i = e / MP, j = e - i * MP;           // read row-major A: coalesced
+        float2 a = make_float2(0.f, 0.f);
+        if (i < M && j < M) {
+            a = Af[(size_t)i * M + j];
+            if (!finite2(a)) nonfinite = true;
+            amax = fmaxf(amax, fmaxf(fabsf(a.x), fabsf(a.y)));
+        }
+        Ys[at<MP>(j, i)] = a;
+        const int c = e / MP, r = e - c * MP;           // U0 column-major: coalesced
+        Us[at<MP>(c, r)] = (c < M && r < M) ? Uf[(size_t)c * M + r] : make_float2(0.f, 0.f);
+    }
+    const int nf_count = __syncthreads_count(nonfinite ? 1 : 0);
+    if (!nonfinite && amax > 0.0f) atomicMax((int *)&amax_s, __float_as_int(amax));
+    __syncthreads();
+    if (tid == 0 && nf_count > 0 && flag == SSL_BIN_OK) flag = SSL_BIN_NONFINITE;
+    __syncthreads();
+
+    int sweeps = 0;
+    bool converged = false;
+    if (flag == SSL_BIN_OK) {
+        // Y = 2^-ex A^H U0 (the power of two keeps every Gram entry far from FP32 overflow); one
+        // 4 x 4 tile of Y per thread, kept in registers until every thread has read A
+        int ex = 0;
+        if (amax_s > 0.0f) frexpf(amax_s, &ex);
+        const float sc = ldexpf(1.0f, -ex);
+        constexpr int TB = MP / 4;
+        const int ti = tid / TB, tk = tid - ti * TB;   // rows 4 ti.., columns 4 tk..
+        float2 acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = make_float2(0.f, 0.f);
+        if (tid < TB * TB) {
+            for (int j = 0; j < M; ++j) {
+                float2 av[4], uv[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) av[a] = Ys[at<MP>(4 * ti + a, j)];   // A[j][i]
+#pragma unroll
+                for (int b = 0; b < 4; ++b) uv[b] = Us[at<MP>(4 * tk + b, j)];   // U0[j][k]
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {     // conj(A[j][i]) U0[j][k]
+                        acc[a][b].x = fmaf(av[a].x, uv[b].x, fmaf(av[a].y, uv[b].y, acc[a][b].x));
+                        acc[a][b].y = fmaf(av[a].x, uv[b].y, fmaf(-av[a].y, uv[b].x, acc[a][b].y));
+                    }
+            }
+        }
+        __syncthreads();
+        if (tid < TB * TB) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    Ys[at<MP>(4 * tk + b, 4 * ti + a)] =
+                        make_float2(acc[a][b].x * sc, acc[a][b].y * sc);
+        }
+        __syncthreads();
+
+        const int Me = M + (M & 1);
+        const double tol = 2.0 * sqrt((double)M) * 5.9604644775390625e-08;
+        const double tol2 = tol * tol;
+        const int P = Me / 2;
+        int my_rot = 0;
+        for (int sw = 0; sw < max_sweeps; ++sw) {
+            int rotated = 0;
+            for (int rd = 0; rd < Me - 1; ++rd) {
+                if (g < P && g < NG) {
+                    int a, b;
+                    if (g == 0) {
+                        a = Me - 1;
+                        b = rd;
+                    } else {
+                        a = rd + g;
+                        if (a >= Me - 1) a -= Me - 1;
+                        b = rd - g;
+                        if (b < 0) b += Me - 1;
+                    }
+                    const int ci = min(a, b), cj = max(a, b);
+                    if (cj < M && warm_pair<MP, G, R>(Ys, Us, ci, cj, q, tol2)) {
+                        rotated = 1;
+                        if (q == 0) ++my_rot;
+                    }
+                }
+                __syncthreads();
+            }
+            ++sweeps;
+            if (__syncthreads_count(rotated) == 0) {
+                converged = true;
+                break;
+            }
+        }
+        if (my_rot) atomicAdd(&rot_total, my_rot);
+        // sigma_c = |z_c| and the stable descending rank (ties: lower column first)
+        for (int c = g; c < M && g < NG; c += NG) {
+            float s2 = 0.f;
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const float2 v = Ys[at<MP>(c, q + G * k)];
+                s2 = fmaf(v.x, v.x, fmaf(v.y, v.y, s2));
+            }
+            s2 = group_sum<G>(s2);
+            if (q == 0) sig[c] = sqrtf(s2);
+        }
+        __syncthreads();
+        for (int c = tid; c < M; c += NT) {
+            const float sc_ = sig[c];
+            int rank = 0;
+            for (int k = 0; k < M; ++k) {
+                const float sk = sig[k];
+                rank += (sk > sc_ || (sk == sc_ && k < c)) ? 1 : 0;
+            }
+            perm[rank] = c;
+        }
+        __syncthreads();
+    }
+    const bool ok = (flag == SSL_BIN_OK) && converged;
+    const int st = (flag != SSL_BIN_OK) ? flag : (converged ? SSL_BIN_OK : SSL_BIN_NO_CONV);
+    for (int e = tid; e < Nn * MP; e += NT) {
+        const int c = e / MP, r = e % MP;
+        if (r < M) Enf[c * M + r] = ok ? Us[at<MP>(perm[Ns + c], r)] : make_float2(0.f, 0.f);
+    }
+    for (int e = tid; e < M * MP; e += NT) {          // next start: sorted U (identity if failed)
+        const int c = e / MP, r = e % MP;
+        if (r < M)
+            Uf[c * M + r] = ok ? Us[at<MP>(perm[c], r)] : make_float2(r == c ? 1.f : 0.f, 0.f);
+    }
+    if (tid == 0) {
+        if (status) status[f] = st;
+        if (conv) {
+            conv[3 * f] = sweeps;
+            conv[3 * f + 1] = rot_total;
+            conv[3 * f + 2] = M;
+        }
+    }
+}
+
 template <int MP, int G>
 hipError_t launch_cfg(ssl_c64 *A, const int32_t *kstatus, int F, int M, int Ns, int max_sweeps,
-                      ssl_c64 *En, float *sigma, int32_t *bin_status, int32_t *conv,
+                      ssl_c64 *En, float *sigma, int32_t *bin_status, int32_t *conv, ssl_c64 *U,
                       hipStream_t st)
 {
     hipLaunchKernelGGL((jacobi_svd<MP, G>), dim3(F), dim3(JacobiCfg<MP, G>::THREADS), 0, st,
                        reinterpret_cast<float2 *>(A), kstatus, M, Ns, max_sweeps,
-                       reinterpret_cast<float2 *>(En), sigma, bin_status, conv);
+                       reinterpret_cast<float2 *>(En), sigma, bin_status, conv,
+                       reinterpret_cast<float2 *>(U));
     return hipGetLastError();
 }
 
@@ -859,13 +1117,41 @@ int jacobi_persistent_wg_per_cu(int cls, int lanes)
 
 hipError_t launch_jacobi(ssl_c64 *A, const int32_t *kstatus, int F, int M, int Ns, int max_sweeps,
                          int lanes, ssl_c64 *En, float *sigma, int32_t *bin_status, int32_t *conv,
-                         hipStream_t st)
+                         hipStream_t st, ssl_c64 *U)
 {
     hipError_t e = hipErrorInvalidValue;
     dispatch(jacobi_class(M), lanes, [&]<int MP, int G>() {
-        e = launch_cfg<MP, G>(A, kstatus, F, M, Ns, max_sweeps, En, sigma, bin_status, conv, st);
+        e = launch_cfg<MP, G>(A, kstatus, F, M, Ns, max_sweeps, En, sigma, bin_status, conv, U,
+                              st);
     });
     return e;
+}
+
+hipError_t launch_jacobi_warm(const ssl_c64 *A, const int32_t *kstatus, int F, int M, int Ns,
+                              int max_sweeps, ssl_c64 *U, ssl_c64 *En, int32_t *bin_status,
+                              int32_t *conv, hipStream_t st)
+{
+    const float2 *a = reinterpret_cast<const float2 *>(A);
+    float2 *u = reinterpret_cast<float2 *>(U), *en = reinterpret_cast<float2 *>(En);
+    switch (jacobi_class(M)) {
+    case 8:
+        hipLaunchKernelGGL((jacobi_warm<8, 8>), dim3(F), dim3(JacobiCfg<8, 8>::THREADS), 0, st, a,
+                           kstatus, M, Ns, max_sweeps, u, en, bin_status, conv);
+        break;
+    case 16:
+        hipLaunchKernelGGL((jacobi_warm<16, 8>), dim3(F), dim3(JacobiCfg<16, 8>::THREADS), 0, st,
+                           a, kstatus, M, Ns, max_sweeps, u, en, bin_status, conv);
+        break;
+    case 32:
+        hipLaunchKernelGGL((jacobi_warm<32, 8>), dim3(F), dim3(JacobiCfg<32, 8>::THREADS), 0, st,
+                           a, kstatus, M, Ns, max_sweeps, u, en, bin_status, conv);
+        break;
+    default:
+        hipLaunchKernelGGL((jacobi_warm<64, 8>), dim3(F), dim3(JacobiCfg<64, 8>::THREADS), 0, st,
+                           a, kstatus, M, Ns, max_sweeps, u, en, bin_status, conv);
+        break;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_jacobi_batch(const BlockDev *blk, const int2 *items, int n_items, int cls,

@@ -69,6 +69,22 @@ struct ssl_noise_s {
     int32_t *status;   // [F] SSL_BIN_OK / SSL_BIN_NOT_PD
 };
 
+// Frame stream of eq.3 (ssl_sliding_*): the ring of the last T frames of every bin, the FP64 sum
+// S of their outer products, and the sorted left singular vectors of the last solve (the start
+// of a warm-started one).
+struct ssl_sliding_s {
+    ssl_ctx ctx;
+    int F, M, T;
+    int64_t pushed = 0;          // frames pushed so far
+    int64_t since_refresh = 0;   // frames pushed since S was last recomputed from the ring
+    ssl_c64 *ring = nullptr;     // [F][T][M]; frame k in slot k mod T
+    ssl_c128 *S = nullptr;       // [F][M][M]
+    ssl_c64 *U = nullptr;        // [F][M][M] column-major per bin
+    bool have_U = false;
+    int64_t cold_at = 0;         // frames pushed at the last cold solve
+    size_t bytes = 0;
+};
+
 void ssl_set_error(const char *fmt, ...);
 
 // Device view of one block of a batch: caller pointers, shapes and the block's slices of the
@@ -156,6 +172,12 @@ int steer_rows_per_block(int waves);
 int binsum_threads();
 
 // --- launchers (each returns hipSuccess or the launch error) ---
+// eq.3 frame stream: S += sum over the n new frames of x x^H - o o^H (o: the frame each displaces
+// from the ring, zero while fewer than T frames were pushed), ring updated; R = S * inv_t
+hipError_t launch_sliding_push(const ssl_c64 *X, int n, int64_t sF, int64_t sT, int F, int M,
+                               int T, int64_t pushed, ssl_c64 *ring, ssl_c128 *S, hipStream_t st);
+hipError_t launch_sliding_scale(const ssl_c128 *S, int64_t n, double inv_t, void *R, bool fp64,
+                                hipStream_t st);
 // eq.1: pcm [n_samples][M] float -> X [nfft/2 + 1][T][M]; nfft a power of two in [16, 4096]
 hipError_t launch_stft(const float *pcm, int M, int nfft, int hop, const float *win, int T,
                        ssl_c64 *X, hipStream_t st);
@@ -179,9 +201,17 @@ hipError_t launch_noise_factor_batch(const NoiseUpdDev *h, const int2 *items, in
 inline int noise_class(int M) { return M <= 16 ? 16 : M <= 32 ? 32 : 64; }
 // A is library workspace and is overwritten (it parks the QR reflectors between phases).
 // lanes = lanes per column pair of the Jacobi variant (jacobi_variant_ok).
+// U (optional): all M sorted left singular vectors, [F][M][M] column-major per bin (identity for
+// a failed bin) -- the start of a warm-started solve (launch_jacobi_warm).
 hipError_t launch_jacobi(ssl_c64 *A, const int32_t *kstatus, int F, int M, int Ns,
                          int max_sweeps, int lanes, ssl_c64 *En, float *sigma,
-                         int32_t *bin_status, int32_t *conv, hipStream_t st);
+                         int32_t *bin_status, int32_t *conv, hipStream_t st,
+                         ssl_c64 *U = nullptr);
+// Warm-started solve: U [F][M][M] (column-major per bin) holds a unitary start on entry (the
+// previous solve's sorted singular vectors) and this solve's on exit; A is read only.
+hipError_t launch_jacobi_warm(const ssl_c64 *A, const int32_t *kstatus, int F, int M, int Ns,
+                              int max_sweeps, ssl_c64 *U, ssl_c64 *En, int32_t *bin_status,
+                              int32_t *conv, hipStream_t st);
 bool jacobi_variant_ok(int cls, int lanes);
 int jacobi_persistent_wg_per_cu(int cls, int lanes);
 hipError_t launch_steer(const void *H, ssl_prec hprec, const ssl_c64 *En, int F, int D, int M,

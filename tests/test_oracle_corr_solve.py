@@ -134,3 +134,24 @@ def test_not_pd_detection(orc):
     Kn = np.eye(M, dtype=np.complex128)
     Kn[2, 2] = np.nan
     assert orc.solve(Kn, np.eye(M))[0] == orc.NOT_PD
+
+
+def test_sliding_corr_definition_and_rank2_recurrence(orc):
+    """eq.3's window: the direct sum over the T frames ending at f (einsum), and, on Gaussian-integer
+    frames where FP64 is exact, R(f + 1) - R(f) = (x_{f+1} x_{f+1}^H - x_{f-T+1} x_{f-T+1}^H) / T
+    exactly -- the rank-2 update a streaming implementation applies per frame."""
+    rng = np.random.default_rng(41)
+    F, N, M, T = 3, 20, 5, 8
+    X = (rng.integers(-3, 4, (F, N, M)) + 1j * rng.integers(-3, 4, (F, N, M))).astype(np.complex64)
+    x = X.astype(np.complex128)
+    for f in range(T - 1, N):
+        R = orc.sliding_corr(X, T, f)
+        W = x[:, f - T + 1:f + 1]
+        assert np.allclose(R, np.einsum("fti,ftj->fij", W, W.conj()) / T, rtol=0, atol=1e-13)
+    for f in range(T - 1, N - 1):
+        d = (orc.sliding_corr(X, T, f + 1) - orc.sliding_corr(X, T, f)) * T
+        new, old = x[:, f + 1], x[:, f - T + 1]
+        want = np.einsum("fi,fj->fij", new, new.conj()) - np.einsum("fi,fj->fij", old, old.conj())
+        assert np.array_equal(np.round(d, 9), want)
+    with pytest.raises(ValueError):
+        orc.sliding_corr(X, T, T - 2)
