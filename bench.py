@@ -316,6 +316,41 @@ def uneven_phase(args) -> dict:
                     "replay), M in {8,16,32,60}, F in {257,513}, Ns in {1,2,3}"}
 
 
+def bidiag_phase(args, S, ctx, w, noise, H32, Xs) -> dict:
+    """The same FP32 batch step with the paper's own SVD (Householder bidiagonalisation + implicit
+    QR) in place of the Jacobi backend: blocks/s and the SVD kernel's average time."""
+    import torch
+    dev = "cuda:0"
+    B, F, Ns, D = Xs.shape[0], w.F, w.Ns, w.D
+    pk = torch.zeros((B, Ns), dtype=torch.int32, device=dev)
+    pv = torch.zeros((B, Ns), dtype=torch.float32, device=dev)
+    pb = torch.zeros((B, D), dtype=torch.float32, device=dev)
+    st = torch.zeros((B, F), dtype=torch.int32, device=dev)
+    descs = [S.block_desc(Xs[b], noise, H32, w.grid.n_az, w.grid.n_el, Ns, pk[b], pv[b], pb[b],
+                          st[b]) for b in range(B)]
+    S.ssl_ctx_set_svd(ctx, S.SSL_SVD_BIDIAG_QR)
+    try:
+        S.ssl_localize_batch(ctx, descs, S.SSL_FP32, 2)
+        torch.cuda.synchronize()
+        S.ssl_ctx_timing_read(ctx, reset=True)
+        S.ssl_ctx_timing(ctx, True)
+        t0 = time.perf_counter()
+        for _ in range(args.bidiag_steps):
+            S.ssl_localize_batch(ctx, descs, S.SSL_FP32, 2)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        S.ssl_ctx_timing(ctx, False)
+        kt = S.ssl_ctx_timing_read(ctx, reset=True)
+    finally:
+        S.ssl_ctx_set_svd(ctx, S.SSL_SVD_JACOBI)
+    n, ms = kt["jacobi"]
+    return {"value": round(args.bidiag_steps * B / el, 2), "unit": "blocks/s", "prec": "fp32",
+            "svd_avg_ms": round(ms / max(n, 1), 4), "blocks_per_step": B,
+            "status_ok": bool((st.cpu() == 0).all()),
+            "kind": "FP32 batch step with the Householder-bidiagonalisation + implicit-QR SVD "
+                    "(one workgroup per bin, per-event timing)"}
+
+
 def streaming_phase(args, S, ctx, w, noise, H32, Xs) -> dict:
     """One 60-channel stream localized at frame rate (eq.3: the window of the T frames ending at
     each new frame): per frame, push the frame (rank-2 FP64 update of the window sum) and run the
@@ -402,6 +437,8 @@ def main() -> int:
     ap.add_argument("--uneven-blocks", type=int, default=512,
                     help="blocks of the uneven-shape batch (0 = skip)")
     ap.add_argument("--uneven-steps", type=int, default=5)
+    ap.add_argument("--bidiag-steps", type=int, default=3,
+                    help="batch steps timed with the bidiagonal-QR SVD backend, 0 = skip")
     ap.add_argument("--stream-frames", type=int, default=50,
                     help="frame-rate localizations of one 60-channel stream (eq.3 window), 0 = skip")
     ap.add_argument("--serve-mixed", default="bf16",
@@ -693,6 +730,8 @@ def main() -> int:
         out["uneven"] = uneven_phase(args)
     if args.stream_frames > 0:
         out["streaming"] = streaming_phase(args, S, ctx, w, noise, H32, Xs)
+    if args.bidiag_steps > 0:
+        out["svd_bidiag_qr"] = bidiag_phase(args, S, ctx, w, noise, H32, Xs)
     if "h2d_serial" in main_r:
         out["h2d"] = {"serial": round(main_r["h2d_serial"], 2),
                       "overlapped": round(main_r["h2d_overlap"], 2),

@@ -338,6 +338,24 @@ typedef struct {
 ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblocks,
                               ssl_prec prec, int p, void *stream);
 
+/* SVD backend of every entry point of the context (ssl_gsvd, ssl_localize, ssl_localize_noalloc,
+ * ssl_localize_batch, cold solves of ssl_sliding_localize):
+ *   SSL_SVD_JACOBI (default)  one-sided Jacobi preconditioned by two Householder QRs (the paper's
+ *                             Sec. III-B category 1), FP32;
+ *   SSL_SVD_BIDIAG_QR         the paper's own method (Sec. III-B category 2, its steps SVD1..SVD6):
+ *                             Householder bidiagonalisation, phase transform to a real
+ *                             non-negative bidiagonal, tolerance M 2^-24 max_k (|d_k| + |e_k|),
+ *                             implicit-shift QR iterations (Golub-Kahan steps, Wilkinson shift) on
+ *                             it with the left rotations accumulated, sort, back-transformation;
+ *                             FP32, at most 40 M QR steps (SSL_BIN_NO_CONV beyond), ssl_gsvd's
+ *                             max_sweeps is not used and conv reports (QR steps, zero-diagonal
+ *                             chases, M).  No warm start in ssl_sliding_localize.
+ * The two agree to within the parity bounds (rounding differs), so results are bit-identical
+ * between entry points for one backend only.  Changing it drops captured batch graphs' reuse. */
+typedef enum { SSL_SVD_JACOBI = 0, SSL_SVD_BIDIAG_QR = 1 } ssl_svd;
+ssl_status ssl_ctx_set_svd(ssl_ctx ctx, ssl_svd method);
+int ssl_ctx_get_svd(ssl_ctx ctx);
+
 /* Graph replay for ssl_localize_batch (default on).  With timing enabled (ssl_ctx_timing) batches
  * always run as individually timed launches. */
 ssl_status ssl_ctx_use_graphs(ssl_ctx ctx, int enable);

@@ -20,6 +20,8 @@ SSL_OK, SSL_ERR_ARG, SSL_ERR_NOMEM, SSL_ERR_BUDGET, SSL_ERR_HIP, SSL_ERR_STATE =
 SSL_BIN_OK, SSL_BIN_NOT_PD, SSL_BIN_NO_CONV, SSL_BIN_NONFINITE = 0, 1, 2, 3
 # ssl_prec
 SSL_FP32, SSL_BF16, SSL_FP16, SSL_FP64 = 0, 1, 2, 3
+# ssl_svd
+SSL_SVD_JACOBI, SSL_SVD_BIDIAG_QR = 0, 1
 # fixed scratch of ssl_localize_noalloc (bytes, per device)
 SSL_NOALLOC_SCRATCH_BYTES = 64 << 20
 
@@ -35,7 +37,7 @@ EXPORTED = [
     "ssl_localize_noalloc", "ssl_localize_noalloc_bytes", "ssl_stft",
     "ssl_tf_write", "ssl_tf_info_read", "ssl_tf_load", "ssl_steering_convert",
     "ssl_sliding_create", "ssl_sliding_destroy", "ssl_sliding_push", "ssl_sliding_frames",
-    "ssl_sliding_corr", "ssl_sliding_localize",
+    "ssl_sliding_corr", "ssl_sliding_localize", "ssl_ctx_set_svd", "ssl_ctx_get_svd",
 ]
 
 
@@ -95,6 +97,8 @@ def lib() -> ctypes.CDLL:
         "ssl_localize": (I, [P, P, I, I, I, I64, I64, P, P, I, I, I, I, I, P, P, P, P, P]),
         "ssl_localize_noalloc": (I, [P, P, I, I, I, I64, I64, P, P, I, I, I, I, I, P, P, P, P, P]),
         "ssl_stft": (I, [P, P, I64, I, I, I, I, P, P, P]),
+        "ssl_ctx_set_svd": (I, [P, I]),
+        "ssl_ctx_get_svd": (I, [P]),
         "ssl_sliding_create": (I, [P, I, I, I, ctypes.POINTER(P)]),
         "ssl_sliding_destroy": (None, [P]),
         "ssl_sliding_push": (I, [P, P, I, I64, I64, P]),
@@ -222,6 +226,14 @@ def ssl_steering_convert(ctx, H, prec, Hout, stream=None):
     F, D, M = H.shape
     _check("ssl_steering_convert", lib().ssl_steering_convert(ctx, _ptr(H), F, D, M, prec, _ptr(Hout),
                                                               _stream(stream)))
+
+
+def ssl_ctx_set_svd(ctx, method: int) -> None:
+    _check("ssl_ctx_set_svd", lib().ssl_ctx_set_svd(ctx, method))
+
+
+def ssl_ctx_get_svd(ctx) -> int:
+    return int(lib().ssl_ctx_get_svd(ctx))
 
 
 def ssl_sliding_create(ctx, F: int, M: int, T: int) -> int:

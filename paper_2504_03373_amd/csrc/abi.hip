@@ -138,6 +138,21 @@ hipError_t timed(ssl_ctx ctx, int id, hipStream_t st, Fn &&launch)
 }
 
 int jac_lanes(ssl_ctx ctx, int M) { return ctx->jac_lanes[jacobi_class_index(jacobi_class(M))]; }
+
+// QR steps allowed to the bidiagonal solve: about 2 per singular value suffice in practice
+int gk_max_steps(int M) { return 40 * M; }
+
+// The SVD of the context's backend for F bins of A (the Jacobi kernel overwrites A, the
+// bidiagonal one reads it only); U (Jacobi only) receives all sorted singular vectors.
+hipError_t launch_svd(ssl_ctx ctx, ssl_c64 *A, const int32_t *kst, int F, int M, int Ns,
+                      int max_sweeps, ssl_c64 *En, float *sigma, int32_t *stt, int32_t *conv,
+                      hipStream_t st, ssl_c64 *U = nullptr)
+{
+    if (ctx->svd == SSL_SVD_BIDIAG_QR)
+        return launch_gk_svd(A, kst, F, M, Ns, gk_max_steps(M), En, sigma, stt, conv, st);
+    return launch_jacobi(A, kst, F, M, Ns, max_sweeps, jac_lanes(ctx, M), En, sigma, stt, conv, st,
+                         U);
+}
 int st_waves(ssl_ctx ctx, int M, int Ns, ssl_prec prec)
 {
     return ctx->steer_waves[steer_class_index(steer_class(M, Ns))][prec];
@@ -279,8 +294,8 @@ ssl_status localize_enqueue(ssl_ctx ctx, bool may_time, char *w, const LocalizeW
         A = R;                                   // SEVD-MUSIC: the decomposition of R itself
     }
     e = run(SSL_K_JACOBI, [&] {
-        return launch_jacobi(A, K ? K->status : nullptr, F, M, Ns, SSL_DEFAULT_SWEEPS,
-                             jac_lanes(ctx, M), En, nullptr, stt, nullptr, st);
+        return launch_svd(ctx, A, K ? K->status : nullptr, F, M, Ns, SSL_DEFAULT_SWEEPS, En,
+                          nullptr, stt, nullptr, st);
     });
     if (e != hipSuccess) return hip_fail(e, "jacobi launch");
     e = run(SSL_K_STEER, [&] {
@@ -651,8 +666,8 @@ ssl_status ssl_gsvd(ssl_ctx ctx, const ssl_c64 *R, ssl_noise K, int F, int M, in
         if (e != hipSuccess) return hip_fail(e, "copy of R");
     }
     e = timed(ctx, SSL_K_JACOBI, st, [&] {
-        return launch_jacobi(A, K ? K->status : nullptr, F, M, Ns, max_sweeps, jac_lanes(ctx, M),
-                             En, sigma, bin_status, conv, st);
+        return launch_svd(ctx, A, K ? K->status : nullptr, F, M, Ns, max_sweeps, En, sigma,
+                          bin_status, conv, st);
     });
     return e == hipSuccess ? SSL_OK : hip_fail(e, "jacobi launch");
 }
@@ -924,10 +939,10 @@ ssl_status ssl_sliding_localize(ssl_sliding s, ssl_noise K, const void *H, ssl_p
         });
     } else {
         e = timed(ctx, SSL_K_JACOBI, st, [&] {
-            return launch_jacobi(A, kst, F, M, Ns, SSL_DEFAULT_SWEEPS, jac_lanes(ctx, M), En,
-                                 nullptr, stt, conv, st, s->U);
+            return launch_svd(ctx, A, kst, F, M, Ns, SSL_DEFAULT_SWEEPS, En, nullptr, stt, conv,
+                              st, s->U);
         });
-        if (e == hipSuccess) {
+        if (e == hipSuccess && ctx->svd == SSL_SVD_JACOBI) {     // the Jacobi solve wrote U
             s->have_U = true;
             s->cold_at = s->pushed;
         }
@@ -1091,6 +1106,9 @@ hipError_t enqueue_batch(ssl_ctx ctx, const Plan &P, const BlockDev *blk, const 
     }
     for (const Seg &s : P.jac) {
         e = timed(ctx, SSL_K_JACOBI, st, [&] {
+            if (ctx->svd == SSL_SVD_BIDIAG_QR)
+                return launch_gk_svd_batch(blk, l_jac + s.start, s.count, s.cls,
+                                           gk_max_steps(s.cls), st);
             return launch_jacobi_batch(blk, l_jac + s.start, s.count, s.cls,
                                        ctx->jac_lanes[jacobi_class_index(s.cls)],
                                        SSL_DEFAULT_SWEEPS, ctx->counters + jacobi_queue(s.cls),
@@ -1380,6 +1398,22 @@ ssl_status ssl_autotune_steer(ssl_ctx ctx, const void *H, ssl_prec hprec, const 
     return SSL_OK;
 }
 
+ssl_status ssl_ctx_set_svd(ssl_ctx ctx, ssl_svd method)
+{
+    if (!ctx) {
+        ssl_set_error("ctx is NULL");
+        return SSL_ERR_ARG;
+    }
+    if (method != SSL_SVD_JACOBI && method != SSL_SVD_BIDIAG_QR) {
+        ssl_set_error("unknown SVD method %d", (int)method);
+        return SSL_ERR_ARG;
+    }
+    ctx->svd = method;
+    return SSL_OK;
+}
+
+int ssl_ctx_get_svd(ssl_ctx ctx) { return ctx ? ctx->svd : -1; }
+
 ssl_status ssl_ctx_use_graphs(ssl_ctx ctx, int enable)
 {
     if (!ctx) {
@@ -1418,6 +1452,7 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
     key.push_back(prec);
     key.push_back(p);
     for (int i = 0; i < 4; ++i) key.push_back(ctx->jac_lanes[i]);   // kernel variants captured
+    key.push_back(ctx->svd);
     for (int c = 0; c < 3; ++c) key.push_back(ctx->steer_waves[c][prec]);
     for (int b = 0; b < nblocks; ++b) {
         const ssl_block_desc &d = descs[b];

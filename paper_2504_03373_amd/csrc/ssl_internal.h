@@ -54,6 +54,8 @@ struct ssl_ctx_s {
     int cu_count = 0;
     // this device's address of the fixed scratch of ssl_localize_noalloc
     char *scratch = nullptr;
+    // SVD backend of every entry point (ssl_ctx_set_svd)
+    int svd = SSL_SVD_JACOBI;
     // Jacobi variant (lanes per column pair) per size class 8/16/32/64 channels
     int jac_lanes[4] = {8, 8, 8, 8};     // lanes per Jacobi column pair, classes 8/16/32/64
     // waves per projection workgroup, [steer class 1/2/4][SSL_FP32, SSL_BF16, SSL_FP16]
@@ -213,6 +215,13 @@ hipError_t launch_jacobi_warm(const ssl_c64 *A, const int32_t *kstatus, int F, i
                               int max_sweeps, ssl_c64 *U, ssl_c64 *En, int32_t *bin_status,
                               int32_t *conv, hipStream_t st);
 bool jacobi_variant_ok(int cls, int lanes);
+// The paper's SVD (Householder bidiagonalisation, phase transform, implicit-shift QR, sort,
+// back-transformation): A is read only; conv = (QR steps, zero-diagonal chases, M) per bin.
+hipError_t launch_gk_svd(const ssl_c64 *A, const int32_t *kstatus, int F, int M, int Ns,
+                         int max_steps, ssl_c64 *En, float *sigma, int32_t *bin_status,
+                         int32_t *conv, hipStream_t st);
+hipError_t launch_gk_svd_batch(const BlockDev *blk, const int2 *items, int n_items, int cls,
+                               int max_steps, hipStream_t st);
 int jacobi_persistent_wg_per_cu(int cls, int lanes);
 hipError_t launch_steer(const void *H, ssl_prec hprec, const ssl_c64 *En, int F, int D, int M,
                         int Ns, int p, const int32_t *bin_status, float *P, int waves,
