@@ -70,6 +70,11 @@ def lib():
         L.orc_peaks.restype = i32
         L.orc_localize.argtypes = [P, i32, i32, i32, i64, i64, P, P, i32, i32, i32, i32,
                                    f64, i32, i32, P, P, P, P, P]
+        L.orc_localize_m.argtypes = [P, i32, i32, i32, i64, i64, P, P, i32, i32, i32, i32,
+                                     f64, i32, i32, i32, P, P, P, P, P]
+        L.orc_inv_sqrt.argtypes = [P, i32, f64, i32, P]
+        L.orc_inv_sqrt.restype = i32
+        L.orc_gevd.argtypes = [P, P, i32, i32, i32, f64, i32, i32, P, P, P]
         _lib = L
     return _lib
 
@@ -204,10 +209,35 @@ def peaks(Pbar: np.ndarray, n_el: int, n_az: int, Ns: int):
     return pk, vals
 
 
+def inv_sqrt(K: np.ndarray, tol: float | None = None, max_sweeps: int = DEFAULT_MAX_SWEEPS):
+    """K^{-1/2} (Hermitian inverse square root) of one bin's K.  Returns (status, W)."""
+    K = _c128(K)
+    M = K.shape[0]
+    W = np.zeros((M, M), np.complex128)
+    st = lib().orc_inv_sqrt(_ptr(K), M, default_tol(M) if tol is None else tol, max_sweeps, _ptr(W))
+    return st, W
+
+
+def gevd(K: np.ndarray, R: np.ndarray, Ns: int, tol: float | None = None,
+         max_sweeps: int = DEFAULT_MAX_SWEEPS, nthreads: int = 1):
+    """GEVD-MUSIC per bin: the generalized eigenvectors R e = lambda K e of the M - Ns smallest
+    lambda (K-orthonormal), via K^{-1/2} R K^{-1/2}; returns (En [F][M-Ns][M], sigma = the
+    generalized eigenvalues descending, status)."""
+    K, R = _c128(K), _c128(R)
+    F, M, _ = R.shape
+    En = np.zeros((F, M - Ns, M), np.complex128)
+    sig = np.zeros((F, M), np.float64)
+    st = np.zeros(F, np.int32)
+    lib().orc_gevd(_ptr(K), _ptr(R), F, M, Ns, default_tol(M) if tol is None else tol, max_sweeps,
+                   nthreads, _ptr(En), _ptr(sig), _ptr(st))
+    return En, sig, st
+
+
 def localize(X: np.ndarray, K: np.ndarray, H: np.ndarray, n_az: int, n_el: int, Ns: int,
              p: int = 2, tol: float | None = None, max_sweeps: int = DEFAULT_MAX_SWEEPS,
-             nthreads: int = 1, want_P: bool = False):
-    """One block end to end.  Returns dict(peaks, peak_val, Pbar, status[, P])."""
+             nthreads: int = 1, want_P: bool = False, gevd: bool = False):
+    """One block end to end (GSVD-MUSIC, or GEVD-MUSIC with gevd=True).  Returns dict(peaks,
+    peak_val, Pbar, status[, P])."""
     if X.dtype != np.complex64:
         raise TypeError("X must be complex64")
     if X.strides[2] != 8:
@@ -221,10 +251,10 @@ def localize(X: np.ndarray, K: np.ndarray, H: np.ndarray, n_az: int, n_el: int, 
     Pbar = np.zeros(D, np.float64)
     st = np.zeros(F, np.int32)
     P = np.zeros((F, D), np.float64) if want_P else None
-    lib().orc_localize(_ptr(X), F, T, M, X.strides[0] // 8, X.strides[1] // 8, _ptr(K), _ptr(H),
-                       n_az, n_el, Ns, p, default_tol(M) if tol is None else tol, max_sweeps,
-                       nthreads, _ptr(pk), _ptr(pv), _ptr(Pbar), _ptr(st),
-                       _ptr(P) if want_P else None)
+    lib().orc_localize_m(_ptr(X), F, T, M, X.strides[0] // 8, X.strides[1] // 8, _ptr(K),
+                         _ptr(H), n_az, n_el, Ns, p, default_tol(M) if tol is None else tol,
+                         max_sweeps, nthreads, int(bool(gevd)), _ptr(pk), _ptr(pv), _ptr(Pbar),
+                         _ptr(st), _ptr(P) if want_P else None)
     out = dict(peaks=pk, peak_val=pv, Pbar=Pbar, status=st)
     if want_P:
         out["P"] = P

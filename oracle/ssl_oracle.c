@@ -24,6 +24,12 @@
  *                    singular vectors reordered with them (ties: lower index first).
  *   orc_gsvd         eq.4 + the definition of E_n after eq.4: E_n = columns
  *                    Ns..M-1 of the sorted left singular vectors of K^{-1} R.
+ *   orc_inv_sqrt,    GEVD-MUSIC, the generalized-eigenvalue alternative (Sec. II): the noise
+ *   orc_gevd         vectors are the generalized eigenvectors R e = lambda K e of the M - Ns
+ *                    smallest lambda, computed as e = K^{-1/2} y from the eigenvectors y of
+ *                    K^{-1/2} R K^{-1/2} (K^{-1/2} the Hermitian inverse square root of K, from
+ *                    K = U diag(s) U^H by the Jacobi SVD of K, which for a Hermitian positive
+ *                    definite K is its eigen-decomposition); the e are K-orthonormal.
  *   orc_spectrum     eq.5 (CalcAveragePower) and eq.6 (sum over bins).
  *   orc_peaks        Sec. III-A, last paragraph: the preset number of peaks of
  *                    P-bar over the direction grid.
@@ -310,6 +316,88 @@ void orc_gsvd(const cplx *K, const cplx *R, int F, int M, int Ns, double tol, in
     }
 }
 
+/* W = K^{-1/2} = U diag(s^{-1/2}) U^H for Hermitian positive definite K (the Cholesky test decides
+ * positive definiteness, as for the GSVD path).  Returns ORC_OK, ORC_NOT_PD or ORC_NO_CONV. */
+int orc_inv_sqrt(const cplx *K, int M, double tol, int max_sweeps, cplx *W)
+{
+    cplx *L = malloc(sizeof(cplx) * M * M);
+    int st = orc_cholesky(K, M, L);
+    free(L);
+    if (st != ORC_OK) return st;
+    cplx *U = malloc(sizeof(cplx) * M * M);
+    double *sg = malloc(sizeof(double) * M);
+    int sw = 0;
+    st = orc_jacobi_svd(K, M, tol, max_sweeps, U, NULL, sg, &sw);
+    if (st == ORC_OK)
+        for (int i = 0; i < M; ++i)
+            for (int j = 0; j < M; ++j) {
+                cplx acc = 0.0;
+                for (int k = 0; k < M; ++k)
+                    acc += U[i * M + k] * (1.0 / sqrt(sg[k])) * conj(U[j * M + k]);
+                W[i * M + j] = acc;
+            }
+    free(U);
+    free(sg);
+    return st;
+}
+
+/* GEVD-MUSIC noise vectors per bin: C = W R W (W = K^{-1/2}), its singular vectors Y (C is
+ * Hermitian positive semi-definite: its eigenvectors) sorted descending, E_n = W Y[:, Ns..M-1]:
+ * the generalized eigenvectors of (R, K) of the M - Ns smallest generalized eigenvalues. */
+void orc_gevd(const cplx *K, const cplx *R, int F, int M, int Ns, double tol, int max_sweeps,
+              int nthreads, cplx *En, double *sigma, int *status)
+{
+    const int Nn = M - Ns;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1)
+    for (int f = 0; f < F; ++f) {
+        const cplx *Kf = K + (size_t)f * M * M;
+        const cplx *Rf = R + (size_t)f * M * M;
+        cplx *W = malloc(sizeof(cplx) * M * M);
+        cplx *T = malloc(sizeof(cplx) * M * M);
+        cplx *C = malloc(sizeof(cplx) * M * M);
+        cplx *U = malloc(sizeof(cplx) * M * M);
+        double *sg = malloc(sizeof(double) * M);
+        int st, sw = 0;
+        if (!all_finite(Rf, (size_t)M * M) || !all_finite(Kf, (size_t)M * M)) {
+            st = ORC_NONFINITE;
+        } else {
+            st = orc_inv_sqrt(Kf, M, tol, max_sweeps, W);
+            if (st == ORC_OK) {
+                for (int i = 0; i < M; ++i)               /* T = W R */
+                    for (int j = 0; j < M; ++j) {
+                        cplx acc = 0.0;
+                        for (int k = 0; k < M; ++k) acc += W[i * M + k] * Rf[k * M + j];
+                        T[i * M + j] = acc;
+                    }
+                for (int i = 0; i < M; ++i)               /* C = T W */
+                    for (int j = 0; j < M; ++j) {
+                        cplx acc = 0.0;
+                        for (int k = 0; k < M; ++k) acc += T[i * M + k] * W[k * M + j];
+                        C[i * M + j] = acc;
+                    }
+                st = orc_jacobi_svd(C, M, tol, max_sweeps, U, NULL, sg, &sw);
+                if (st == ORC_OK) orc_sort_desc(M, sg, U, NULL, NULL);
+            }
+        }
+        cplx *Enf = En + (size_t)f * Nn * M;
+        for (int c = 0; c < Nn; ++c)
+            for (int r = 0; r < M; ++r) {
+                cplx acc = 0.0;
+                if (st == ORC_OK)
+                    for (int k = 0; k < M; ++k) acc += W[r * M + k] * U[k * M + (Ns + c)];
+                Enf[c * M + r] = acc;
+            }
+        if (sigma)
+            for (int k = 0; k < M; ++k) sigma[(size_t)f * M + k] = (st == ORC_OK) ? sg[k] : 0.0;
+        status[f] = st;
+        free(W);
+        free(T);
+        free(C);
+        free(U);
+        free(sg);
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* eq.5 and eq.6                                                             */
 /* ------------------------------------------------------------------------ */
@@ -404,17 +492,35 @@ int orc_peaks(const double *Pbar, int n_el, int n_az, int Ns, int *peaks, double
 /* ------------------------------------------------------------------------ */
 /* one block end to end: R from X, A = K^{-1}R, SVD, E_n, spectrum, peaks     */
 /* ------------------------------------------------------------------------ */
+void orc_localize_m(const float complex *X, int F, int T, int M, int64_t strideF,
+                    int64_t strideT, const cplx *K, const float complex *H, int n_az, int n_el,
+                    int Ns, int p, double tol, int max_sweeps, int nthreads, int gevd,
+                    int *peaks, double *peak_val, double *Pbar, int *status, double *P_out);
+
 void orc_localize(const float complex *X, int F, int T, int M, int64_t strideF, int64_t strideT,
                   const cplx *K, const float complex *H, int n_az, int n_el, int Ns, int p,
                   double tol, int max_sweeps, int nthreads,
                   int *peaks, double *peak_val, double *Pbar, int *status, double *P_out)
+{
+    orc_localize_m(X, F, T, M, strideF, strideT, K, H, n_az, n_el, Ns, p, tol, max_sweeps,
+                   nthreads, 0, peaks, peak_val, Pbar, status, P_out);
+}
+
+/* as orc_localize; gevd != 0 takes the noise subspace from orc_gevd instead of orc_gsvd */
+void orc_localize_m(const float complex *X, int F, int T, int M, int64_t strideF,
+                    int64_t strideT, const cplx *K, const float complex *H, int n_az, int n_el,
+                    int Ns, int p, double tol, int max_sweeps, int nthreads, int gevd,
+                    int *peaks, double *peak_val, double *Pbar, int *status, double *P_out)
 {
     const int D = n_az * n_el;
     cplx *R = malloc(sizeof(cplx) * (size_t)F * M * M);
     cplx *En = malloc(sizeof(cplx) * (size_t)F * (M - Ns) * M);
     double *P = P_out ? P_out : malloc(sizeof(double) * (size_t)F * D);
     orc_corr(X, F, T, M, strideF, strideT, 1.0 / T, R);
-    orc_gsvd(K, R, F, M, Ns, tol, max_sweeps, nthreads, En, NULL, status, NULL);
+    if (gevd)
+        orc_gevd(K, R, F, M, Ns, tol, max_sweeps, nthreads, En, NULL, status);
+    else
+        orc_gsvd(K, R, F, M, Ns, tol, max_sweeps, nthreads, En, NULL, status, NULL);
     orc_spectrum(H, En, status, F, D, M, Ns, p, nthreads, P, Pbar);
     orc_peaks(Pbar, n_el, n_az, Ns, peaks, peak_val);
     if (!P_out) free(P);
