@@ -316,39 +316,76 @@ def uneven_phase(args) -> dict:
                     "replay), M in {8,16,32,60}, F in {257,513}, Ns in {1,2,3}"}
 
 
-def bidiag_phase(args, S, ctx, w, noise, H32, Xs) -> dict:
-    """The same FP32 batch step with the paper's own SVD (Householder bidiagonalisation + implicit
-    QR) in place of the Jacobi backend: blocks/s and the SVD kernel's average time."""
+def _timed_batch_steps(S, ctx, w, noise, H32, Xs, steps: int):
+    """FP32 batch steps over the bench's blocks: one untimed call (captures the launch sequence),
+    then `steps` timed ones; returns (seconds, per-kernel (launches, ms), statuses all OK)."""
     import torch
     dev = "cuda:0"
     B, F, Ns, D = Xs.shape[0], w.F, w.Ns, w.D
     pk = torch.zeros((B, Ns), dtype=torch.int32, device=dev)
     pv = torch.zeros((B, Ns), dtype=torch.float32, device=dev)
     pb = torch.zeros((B, D), dtype=torch.float32, device=dev)
-    st = torch.zeros((B, F), dtype=torch.int32, device=dev)
+    st = torch.full((B, F), -7, dtype=torch.int32, device=dev)
     descs = [S.block_desc(Xs[b], noise, H32, w.grid.n_az, w.grid.n_el, Ns, pk[b], pv[b], pb[b],
                           st[b]) for b in range(B)]
+    S.ssl_localize_batch(ctx, descs, S.SSL_FP32, 2)
+    torch.cuda.synchronize()
+    S.ssl_ctx_timing_read(ctx, reset=True)
+    S.ssl_ctx_timing(ctx, True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        S.ssl_localize_batch(ctx, descs, S.SSL_FP32, 2)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    S.ssl_ctx_timing(ctx, False)
+    kt = S.ssl_ctx_timing_read(ctx, reset=True)
+    return el, kt, bool((st.cpu() == 0).all())
+
+
+def bidiag_phase(args, S, ctx, w, noise, H32, Xs) -> dict:
+    """The same FP32 batch step with the paper's own SVD (Householder bidiagonalisation + implicit
+    QR) in place of the Jacobi backend: blocks/s and the SVD kernel's average time."""
+    B = Xs.shape[0]
     S.ssl_ctx_set_svd(ctx, S.SSL_SVD_BIDIAG_QR)
     try:
-        S.ssl_localize_batch(ctx, descs, S.SSL_FP32, 2)
-        torch.cuda.synchronize()
-        S.ssl_ctx_timing_read(ctx, reset=True)
-        S.ssl_ctx_timing(ctx, True)
-        t0 = time.perf_counter()
-        for _ in range(args.bidiag_steps):
-            S.ssl_localize_batch(ctx, descs, S.SSL_FP32, 2)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        S.ssl_ctx_timing(ctx, False)
-        kt = S.ssl_ctx_timing_read(ctx, reset=True)
+        el, kt, ok = _timed_batch_steps(S, ctx, w, noise, H32, Xs, args.bidiag_steps)
     finally:
         S.ssl_ctx_set_svd(ctx, S.SSL_SVD_JACOBI)
     n, ms = kt["jacobi"]
     return {"value": round(args.bidiag_steps * B / el, 2), "unit": "blocks/s", "prec": "fp32",
-            "svd_avg_ms": round(ms / max(n, 1), 4), "blocks_per_step": B,
-            "status_ok": bool((st.cpu() == 0).all()),
+            "svd_avg_ms": round(ms / max(n, 1), 4), "blocks_per_step": B, "status_ok": ok,
             "kind": "FP32 batch step with the Householder-bidiagonalisation + implicit-QR SVD "
                     "(one workgroup per bin, per-event timing)"}
+
+
+def gevd_phase(args, S, ctx, w, Kd, H32, Xs) -> dict:
+    """The same FP32 batch step in GEVD-MUSIC mode (C = K^{-1/2} R K^{-1/2} in FP64, the Jacobi SVD
+    of C, E_n = K^{-1/2} Y_n): blocks/s, the two FP64 products' and the SVD's average times, and
+    the one-off K^{-1/2} time of the noise handle."""
+    import torch
+    B, F, M = Xs.shape[0], w.F, w.M
+    noise = S.ssl_noise_create(ctx, F, M)
+    S.ssl_noise_set(noise, Kd, S.SSL_FP64)
+    torch.cuda.synchronize()
+    S.ssl_ctx_timing_read(ctx, reset=True)
+    S.ssl_ctx_timing(ctx, True)
+    S.ssl_noise_enable_gevd(noise)
+    torch.cuda.synchronize()
+    S.ssl_ctx_timing(ctx, False)
+    isq_n, isq_ms = S.ssl_ctx_timing_read(ctx, reset=True)["noise"]
+    S.ssl_ctx_set_subspace(ctx, S.SSL_SUBSPACE_GEVD)
+    try:
+        el, kt, ok = _timed_batch_steps(S, ctx, w, noise, H32, Xs, args.gevd_steps)
+    finally:
+        S.ssl_ctx_set_subspace(ctx, S.SSL_SUBSPACE_GSVD)
+        S.ssl_noise_destroy(noise)
+    avg = lambda k: round(kt[k][1] / max(kt[k][0], 1), 4)
+    return {"value": round(args.gevd_steps * B / el, 2), "unit": "blocks/s", "prec": "fp32",
+            "gevd_products_ms_per_step": round(kt["whiten"][1] / args.gevd_steps, 4),
+            "svd_avg_ms": avg("jacobi"),
+            "noise_isqrt_ms": round(isq_ms, 4), "blocks_per_step": B, "status_ok": ok,
+            "kind": "FP32 batch step in GEVD-MUSIC mode (FP64 K^{-1/2} R K^{-1/2} and K^{-1/2} Y_n "
+                    "products, one workgroup per bin; per-event timing)"}
 
 
 def streaming_phase(args, S, ctx, w, noise, H32, Xs) -> dict:
@@ -439,6 +476,8 @@ def main() -> int:
     ap.add_argument("--uneven-steps", type=int, default=5)
     ap.add_argument("--bidiag-steps", type=int, default=3,
                     help="batch steps timed with the bidiagonal-QR SVD backend, 0 = skip")
+    ap.add_argument("--gevd-steps", type=int, default=5,
+                    help="batch steps timed in GEVD-MUSIC mode, 0 = skip")
     ap.add_argument("--stream-frames", type=int, default=50,
                     help="frame-rate localizations of one 60-channel stream (eq.3 window), 0 = skip")
     ap.add_argument("--serve-mixed", default="bf16",
@@ -732,6 +771,8 @@ def main() -> int:
         out["streaming"] = streaming_phase(args, S, ctx, w, noise, H32, Xs)
     if args.bidiag_steps > 0:
         out["svd_bidiag_qr"] = bidiag_phase(args, S, ctx, w, noise, H32, Xs)
+    if args.gevd_steps > 0:
+        out["gevd_music"] = gevd_phase(args, S, ctx, w, Kd, H32, Xs)
     if "h2d_serial" in main_r:
         out["h2d"] = {"serial": round(main_r["h2d_serial"], 2),
                       "overlapped": round(main_r["h2d_overlap"], 2),

@@ -165,6 +165,13 @@ ssl_status ssl_noise_update_frames_from(ssl_ctx ctx, int n, const ssl_noise *dst
                                         const int *T, double alpha, void *stream);
 /* Copies the current K (complex128 [F][M][M]) to K_out (device) for checkpointing. */
 ssl_status ssl_noise_get(ssl_noise K, ssl_c128 *K_out, void *stream);
+/* Prepares the handle for GEVD-MUSIC: allocates 16 F M^2 bytes (within the HBM budget) for
+ * K^{-1/2}, computes it if K is set (FP64 one-sided Jacobi eigen-decomposition of K, rotate iff
+ * |z_i^H z_j| > M 2^-53 |z_i||z_j|, at most 40 sweeps), and from then on recomputes it with every
+ * ssl_noise_set / ssl_noise_update / ssl_noise_update_frames(_from) of the handle.  A bin whose K
+ * is not positive definite, or whose decomposition does not converge, gets SSL_BIN_NOT_PD /
+ * SSL_BIN_NO_CONV in the handle's status. */
+ssl_status ssl_noise_enable_gevd(ssl_noise K, void *stream);
 void ssl_noise_destroy(ssl_noise K);
 
 /* --------------------------------------------------------------- GSVD (eq.4) */
@@ -353,6 +360,21 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
  * The two agree to within the parity bounds (rounding differs), so results are bit-identical
  * between entry points for one backend only.  Changing it drops captured batch graphs' reuse. */
 typedef enum { SSL_SVD_JACOBI = 0, SSL_SVD_BIDIAG_QR = 1 } ssl_svd;
+
+/* Subspace method of every entry point of the context for calls that pass a noise handle (a NULL
+ * handle is SEVD-MUSIC whatever this setting):
+ *   SSL_SUBSPACE_GSVD (default)  eq.4: left singular vectors of K^{-1} R;
+ *   SSL_SUBSPACE_GEVD            GEVD-MUSIC, the generalized-eigenvalue alternative the paper
+ *                                names (Sec. II): the noise vectors are the generalized
+ *                                eigenvectors R e = lambda K e of the M - Ns smallest lambda,
+ *                                computed as e = K^{-1/2} y from the eigenvectors y of
+ *                                C = K^{-1/2} R K^{-1/2} (FP64 products, C rounded to complex64
+ *                                for the context's SVD backend, e mapped back in FP64); they are
+ *                                K-orthonormal.  Every noise handle used must have had
+ *                                ssl_noise_enable_gevd called (SSL_ERR_STATE otherwise). */
+typedef enum { SSL_SUBSPACE_GSVD = 0, SSL_SUBSPACE_GEVD = 1 } ssl_subspace;
+ssl_status ssl_ctx_set_subspace(ssl_ctx ctx, ssl_subspace method);
+int ssl_ctx_get_subspace(ssl_ctx ctx);
 ssl_status ssl_ctx_set_svd(ssl_ctx ctx, ssl_svd method);
 int ssl_ctx_get_svd(ssl_ctx ctx);
 

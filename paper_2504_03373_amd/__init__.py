@@ -22,6 +22,8 @@ SSL_BIN_OK, SSL_BIN_NOT_PD, SSL_BIN_NO_CONV, SSL_BIN_NONFINITE = 0, 1, 2, 3
 SSL_FP32, SSL_BF16, SSL_FP16, SSL_FP64 = 0, 1, 2, 3
 # ssl_svd
 SSL_SVD_JACOBI, SSL_SVD_BIDIAG_QR = 0, 1
+# ssl_subspace
+SSL_SUBSPACE_GSVD, SSL_SUBSPACE_GEVD = 0, 1
 # fixed scratch of ssl_localize_noalloc (bytes, per device)
 SSL_NOALLOC_SCRATCH_BYTES = 64 << 20
 
@@ -38,6 +40,7 @@ EXPORTED = [
     "ssl_tf_write", "ssl_tf_info_read", "ssl_tf_load", "ssl_steering_convert",
     "ssl_sliding_create", "ssl_sliding_destroy", "ssl_sliding_push", "ssl_sliding_frames",
     "ssl_sliding_corr", "ssl_sliding_localize", "ssl_ctx_set_svd", "ssl_ctx_get_svd",
+    "ssl_ctx_set_subspace", "ssl_ctx_get_subspace", "ssl_noise_enable_gevd",
 ]
 
 
@@ -99,6 +102,9 @@ def lib() -> ctypes.CDLL:
         "ssl_stft": (I, [P, P, I64, I, I, I, I, P, P, P]),
         "ssl_ctx_set_svd": (I, [P, I]),
         "ssl_ctx_get_svd": (I, [P]),
+        "ssl_ctx_set_subspace": (I, [P, I]),
+        "ssl_ctx_get_subspace": (I, [P]),
+        "ssl_noise_enable_gevd": (I, [P, P]),
         "ssl_sliding_create": (I, [P, I, I, I, ctypes.POINTER(P)]),
         "ssl_sliding_destroy": (None, [P]),
         "ssl_sliding_push": (I, [P, P, I, I64, I64, P]),
@@ -234,6 +240,18 @@ def ssl_ctx_set_svd(ctx, method: int) -> None:
 
 def ssl_ctx_get_svd(ctx) -> int:
     return int(lib().ssl_ctx_get_svd(ctx))
+
+
+def ssl_ctx_set_subspace(ctx, method: int) -> None:
+    _check("ssl_ctx_set_subspace", lib().ssl_ctx_set_subspace(ctx, method))
+
+
+def ssl_ctx_get_subspace(ctx) -> int:
+    return int(lib().ssl_ctx_get_subspace(ctx))
+
+
+def ssl_noise_enable_gevd(noise, stream=None) -> None:
+    _check("ssl_noise_enable_gevd", lib().ssl_noise_enable_gevd(noise, _stream(stream)))
 
 
 def ssl_sliding_create(ctx, F: int, M: int, T: int) -> int:

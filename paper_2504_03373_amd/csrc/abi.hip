@@ -221,6 +221,17 @@ ssl_status check_noise(ssl_noise K, int F, int M)
     return SSL_OK;
 }
 
+// GEVD-MUSIC needs the handle's K^{-1/2} (ssl_noise_enable_gevd)
+bool use_gevd(ssl_ctx ctx, ssl_noise K) { return K && ctx->subspace == SSL_SUBSPACE_GEVD; }
+ssl_status check_gevd(ssl_ctx ctx, ssl_noise K)
+{
+    if (use_gevd(ctx, K) && !K->gevd) {
+        ssl_set_error("GEVD-MUSIC selected but ssl_noise_enable_gevd was not called on the handle");
+        return SSL_ERR_STATE;
+    }
+    return SSL_OK;
+}
+
 ssl_status check_localize(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int M, int64_t strideF,
                           int64_t strideT, ssl_noise K, const void *H, ssl_prec prec, int n_az,
                           int n_el, int Ns, int p, int32_t *peaks, float *peak_val)
@@ -241,7 +252,8 @@ ssl_status check_localize(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int M, in
         ssl_set_error("prec must be SSL_FP32, SSL_BF16 or SSL_FP16");
         return SSL_ERR_ARG;
     }
-    return check_noise(K, F, M);
+    ssl_status s2 = check_noise(K, F, M);
+    return s2 != SSL_OK ? s2 : check_gevd(ctx, K);
 }
 
 // Workspace of one block's path: R | A | En | P | Pbar | status, then (scratch only) the bin-sum
@@ -287,7 +299,11 @@ ssl_status localize_enqueue(ssl_ctx ctx, bool may_time, char *w, const LocalizeW
         return launch_corr(X, F, T, M, strideF, strideT, 1.0 / T, 0, prec, R, st);
     });
     if (e != hipSuccess) return hip_fail(e, "corr launch");
-    if (K) {
+    const bool gevd = use_gevd(ctx, K);
+    if (gevd) {
+        e = run(SSL_K_WHITEN, [&] { return launch_gevd_whiten(K->Kisq, R, A, F, M, st); });
+        if (e != hipSuccess) return hip_fail(e, "GEVD whitening launch");
+    } else if (K) {
         e = run(SSL_K_WHITEN, [&] { return launch_whiten(K->Kinv, R, A, F, M, st); });
         if (e != hipSuccess) return hip_fail(e, "whiten launch");
     } else {
@@ -298,6 +314,10 @@ ssl_status localize_enqueue(ssl_ctx ctx, bool may_time, char *w, const LocalizeW
                           nullptr, stt, nullptr, st);
     });
     if (e != hipSuccess) return hip_fail(e, "jacobi launch");
+    if (gevd) {
+        e = run(SSL_K_WHITEN, [&] { return launch_gevd_back(K->Kisq, En, F, M, Ns, st); });
+        if (e != hipSuccess) return hip_fail(e, "GEVD back-transformation launch");
+    }
     e = run(SSL_K_STEER, [&] {
         return launch_steer(H, prec, En, F, D, M, Ns, p, stt, P, st_waves(ctx, M, Ns, prec), st);
     });
@@ -554,6 +574,7 @@ void ssl_noise_destroy(ssl_noise n)
     const size_t mat = (size_t)n->F * n->M * n->M * sizeof(ssl_c128);
     dev_free(n->ctx, n->K, mat);
     dev_free(n->ctx, n->Kinv, mat);
+    if (n->Kisq) dev_free(n->ctx, n->Kisq, mat);
     dev_free(n->ctx, n->status, align256((size_t)n->F * sizeof(int32_t)));
     delete n;
 }
@@ -564,6 +585,12 @@ static ssl_status noise_refactor(ssl_noise n, int32_t *bin_status, hipStream_t s
         return launch_noise_factor(n->K, n->Kinv, n->status, n->F, n->M, st);
     });
     if (e != hipSuccess) return hip_fail(e, "noise factor launch");
+    if (n->gevd) {
+        e = timed(n->ctx, SSL_K_NOISE, st, [&] {
+            return launch_noise_isqrt(n->K, n->status, n->F, n->M, n->Kisq, n->status, st);
+        });
+        if (e != hipSuccess) return hip_fail(e, "K^-1/2 launch");
+    }
     if (bin_status) {
         e = hipMemcpyAsync(bin_status, n->status, (size_t)n->F * sizeof(int32_t),
                            hipMemcpyDeviceToDevice, st);
@@ -636,6 +663,45 @@ ssl_status ssl_noise_get(ssl_noise n, ssl_c128 *K_out, void *stream)
     return e == hipSuccess ? SSL_OK : hip_fail(e, "noise get");
 }
 
+ssl_status ssl_noise_enable_gevd(ssl_noise n, void *stream)
+{
+    if (!n) {
+        ssl_set_error("noise handle is NULL");
+        return SSL_ERR_ARG;
+    }
+    DeviceGuard dg(n->ctx->device);
+    if (!n->Kisq) {
+        void *w = nullptr;
+        ssl_status s = dev_alloc(n->ctx, &w, (size_t)n->F * n->M * n->M * sizeof(ssl_c128),
+                                 "noise K^-1/2");
+        if (s != SSL_OK) return s;
+        n->Kisq = static_cast<ssl_c128 *>(w);
+    }
+    n->gevd = true;
+    if (!n->is_set) return SSL_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const hipError_t e = timed(n->ctx, SSL_K_NOISE, st, [&] {
+        return launch_noise_isqrt(n->K, n->status, n->F, n->M, n->Kisq, n->status, st);
+    });
+    return e == hipSuccess ? SSL_OK : hip_fail(e, "K^-1/2 launch");
+}
+
+ssl_status ssl_ctx_set_subspace(ssl_ctx ctx, ssl_subspace method)
+{
+    if (!ctx) {
+        ssl_set_error("ctx is NULL");
+        return SSL_ERR_ARG;
+    }
+    if (method != SSL_SUBSPACE_GSVD && method != SSL_SUBSPACE_GEVD) {
+        ssl_set_error("unknown subspace method %d", (int)method);
+        return SSL_ERR_ARG;
+    }
+    ctx->subspace = method;
+    return SSL_OK;
+}
+
+int ssl_ctx_get_subspace(ssl_ctx ctx) { return ctx ? ctx->subspace : -1; }
+
 ssl_status ssl_gsvd(ssl_ctx ctx, const ssl_c64 *R, ssl_noise K, int F, int M, int Ns, ssl_c64 *En,
                     float *sigma, int32_t *bin_status, int32_t *conv, int max_sweeps,
                     void *stream)
@@ -647,6 +713,7 @@ ssl_status ssl_gsvd(ssl_ctx ctx, const ssl_c64 *R, ssl_noise K, int F, int M, in
     ssl_status s = check_common(F, M, Ns);
     if (s != SSL_OK) return s;
     if ((s = check_noise(K, F, M)) != SSL_OK) return s;
+    if ((s = check_gevd(ctx, K)) != SSL_OK) return s;
     if (max_sweeps < 0 || max_sweeps > 1000) {
         ssl_set_error("max_sweeps = %d out of range [0, 1000]", max_sweeps);
         return SSL_ERR_ARG;
@@ -657,7 +724,12 @@ ssl_status ssl_gsvd(ssl_ctx ctx, const ssl_c64 *R, ssl_noise K, int F, int M, in
     hipStream_t st = static_cast<hipStream_t>(stream);
     ssl_c64 *A = static_cast<ssl_c64 *>(ctx->ws);
     hipError_t e;
-    if (K) {
+    const bool gevd = use_gevd(ctx, K);
+    if (gevd) {
+        e = timed(ctx, SSL_K_WHITEN, st,
+                  [&] { return launch_gevd_whiten(K->Kisq, R, A, F, M, st); });
+        if (e != hipSuccess) return hip_fail(e, "GEVD whitening launch");
+    } else if (K) {
         e = timed(ctx, SSL_K_WHITEN, st, [&] { return launch_whiten(K->Kinv, R, A, F, M, st); });
         if (e != hipSuccess) return hip_fail(e, "whiten launch");
     } else {                                     // SEVD-MUSIC: the kernel overwrites its input
@@ -669,7 +741,12 @@ ssl_status ssl_gsvd(ssl_ctx ctx, const ssl_c64 *R, ssl_noise K, int F, int M, in
         return launch_svd(ctx, A, K ? K->status : nullptr, F, M, Ns, max_sweeps, En, sigma,
                           bin_status, conv, st);
     });
-    return e == hipSuccess ? SSL_OK : hip_fail(e, "jacobi launch");
+    if (e != hipSuccess) return hip_fail(e, "jacobi launch");
+    if (gevd) {
+        e = timed(ctx, SSL_K_WHITEN, st, [&] { return launch_gevd_back(K->Kisq, En, F, M, Ns, st); });
+        if (e != hipSuccess) return hip_fail(e, "GEVD back-transformation launch");
+    }
+    return SSL_OK;
 }
 
 ssl_status ssl_music_spectrum(ssl_ctx ctx, const void *H, ssl_prec hprec, const ssl_c64 *En, int F,
@@ -894,6 +971,7 @@ ssl_status ssl_sliding_localize(ssl_sliding s, ssl_noise K, const void *H, ssl_p
     if (st_ != SSL_OK) return st_;
     if ((st_ = check_grid(n_az, n_el, Ns)) != SSL_OK) return st_;
     if ((st_ = check_noise(K, F, M)) != SSL_OK) return st_;
+    if ((st_ = check_gevd(s->ctx, K)) != SSL_OK) return st_;
     if (p != 1 && p != 2) {
         ssl_set_error("p = %d must be 1 or 2", p);
         return SSL_ERR_ARG;
@@ -925,7 +1003,12 @@ ssl_status ssl_sliding_localize(ssl_sliding s, ssl_noise K, const void *H, ssl_p
         return launch_sliding_scale(s->S, (int64_t)F * M * M, 1.0 / s->T, R, false, st);
     });
     if (e != hipSuccess) return hip_fail(e, "sliding scale launch");
-    if (K) {
+    const bool gevd = use_gevd(ctx, K);
+    if (gevd) {
+        e = timed(ctx, SSL_K_WHITEN, st,
+                  [&] { return launch_gevd_whiten(K->Kisq, R, A, F, M, st); });
+        if (e != hipSuccess) return hip_fail(e, "GEVD whitening launch");
+    } else if (K) {
         e = timed(ctx, SSL_K_WHITEN, st, [&] { return launch_whiten(K->Kinv, R, A, F, M, st); });
         if (e != hipSuccess) return hip_fail(e, "whiten launch");
     } else {
@@ -948,6 +1031,10 @@ ssl_status ssl_sliding_localize(ssl_sliding s, ssl_noise K, const void *H, ssl_p
         }
     }
     if (e != hipSuccess) return hip_fail(e, "jacobi launch");
+    if (gevd) {
+        e = timed(ctx, SSL_K_WHITEN, st, [&] { return launch_gevd_back(K->Kisq, En, F, M, Ns, st); });
+        if (e != hipSuccess) return hip_fail(e, "GEVD back-transformation launch");
+    }
     e = timed(ctx, SSL_K_STEER, st, [&] {
         return launch_steer(H, prec, En, F, D, M, Ns, p, stt, P, st_waves(ctx, M, Ns, prec), st);
     });
@@ -979,6 +1066,7 @@ struct Seg {
 struct Plan {
     std::vector<Seg> corr, whiten, jac, steer;
     int nblocks = 0, n_items = 0, max_dc = 0, max_fc = 0;
+    std::vector<Seg> gevd;                 // (block, bin) items of GEVD-MUSIC blocks, by class
 };
 
 // Device tail of the descriptor buffer after the four item lists: steering groups (first, count)
@@ -1086,7 +1174,7 @@ void build_list(const std::vector<int> &cls_of_block, const std::vector<int> &F_
 }
 
 hipError_t enqueue_batch(ssl_ctx ctx, const Plan &P, const BlockDev *blk, const int2 *lists,
-                         GroupArrays ga, ssl_prec prec, hipStream_t st)
+                         GroupArrays ga, const int2 *l_gevd, ssl_prec prec, hipStream_t st)
 {
     const int2 *l_corr = lists, *l_wh = lists + P.n_items, *l_jac = lists + 2 * P.n_items,
                *l_st = lists + 3 * P.n_items;
@@ -1104,6 +1192,12 @@ hipError_t enqueue_batch(ssl_ctx ctx, const Plan &P, const BlockDev *blk, const 
         });
         if (e != hipSuccess) return e;
     }
+    for (const Seg &s : P.gevd) {
+        e = timed(ctx, SSL_K_WHITEN, st, [&] {
+            return launch_gevd_whiten_batch(blk, l_gevd + s.start, s.count, s.cls, st);
+        });
+        if (e != hipSuccess) return e;
+    }
     for (const Seg &s : P.jac) {
         e = timed(ctx, SSL_K_JACOBI, st, [&] {
             if (ctx->svd == SSL_SVD_BIDIAG_QR)
@@ -1113,6 +1207,12 @@ hipError_t enqueue_batch(ssl_ctx ctx, const Plan &P, const BlockDev *blk, const 
                                        ctx->jac_lanes[jacobi_class_index(s.cls)],
                                        SSL_DEFAULT_SWEEPS, ctx->counters + jacobi_queue(s.cls),
                                        s.extra, st);
+        });
+        if (e != hipSuccess) return e;
+    }
+    for (const Seg &s : P.gevd) {
+        e = timed(ctx, SSL_K_WHITEN, st, [&] {
+            return launch_gevd_back_batch(blk, l_gevd + s.start, s.count, s.cls, st);
         });
         if (e != hipSuccess) return e;
     }
@@ -1472,7 +1572,13 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
             ssl_set_error("block %d: noise handle does not match (or was never set)", b);
             return SSL_ERR_ARG;
         }
-        key.push_back(d.K ? 1 : 0);
+        if ((s = check_gevd(ctx, d.K)) != SSL_OK) {
+            char msg[512];
+            snprintf(msg, sizeof(msg), "block %d: %s", b, ssl_last_error());
+            ssl_set_error("%s", msg);
+            return s;
+        }
+        key.push_back(d.K ? (use_gevd(ctx, d.K) ? 2 : 1) : 0);
         const size_t F = d.F, M = d.M, D = (size_t)d.n_az * d.n_el, Nn = d.M - d.Ns;
         const size_t nch = (F + SSL_BINSUM_CHUNK - 1) / SSL_BINSUM_CHUNK;
         ws_total += 2 * align256(F * M * M * sizeof(ssl_c64)) + align256(F * Nn * M * sizeof(ssl_c64)) +
@@ -1493,8 +1599,9 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
     DeviceGuard dg(ctx->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const size_t desc_bytes = align256(sizeof(BlockDev) * nblocks);
-    const size_t list_bytes = sizeof(int2) * 4 * (size_t)n_items +
-                              2 * (sizeof(int2) + sizeof(int)) * (size_t)nblocks;
+    // four item lists, the group / chunk tail, then the GEVD items
+    const size_t tail_bytes = 2 * (sizeof(int2) + sizeof(int)) * (size_t)nblocks;
+    const size_t list_bytes = sizeof(int2) * 5 * (size_t)n_items + tail_bytes;
     if ((s = ws_reserve(ctx, ws_total)) != SSL_OK) return s;
     if ((s = counters_reserve(ctx, kJacobiQueues)) != SSL_OK) return s;
     if ((s = bdesc_reserve(ctx, desc_bytes + list_bytes)) != SSL_OK) return s;
@@ -1510,6 +1617,9 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
     const int2 *dtail = dl + 4 * n_items;
     const GroupArrays ga{dtail, reinterpret_cast<const int *>(dtail + 2 * nblocks), dtail + nblocks,
                          reinterpret_cast<const int *>(dtail + 2 * nblocks) + nblocks};
+    const int2 *dgevd = reinterpret_cast<const int2 *>(reinterpret_cast<const char *>(dtail) +
+                                                       tail_bytes);
+    int2 *hgevd = reinterpret_cast<int2 *>(reinterpret_cast<char *>(hl + 4 * n_items) + tail_bytes);
 
     Plan plan;
     plan.nblocks = nblocks;
@@ -1535,6 +1645,7 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
         B.scale = (float)(1.0 / d.T);
         B.hprec = prec;
         B.Kinv = d.K ? reinterpret_cast<const double2 *>(d.K->Kinv) : nullptr;
+        B.Kisq = use_gevd(ctx, d.K) ? reinterpret_cast<const double2 *>(d.K->Kisq) : nullptr;
         B.kstatus = d.K ? d.K->status : nullptr;
         B.H = d.H;
         B.R = reinterpret_cast<float2 *>(w);
@@ -1562,6 +1673,14 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
         plan.max_fc = std::max(plan.max_fc, (int)nch);
     }
     build_list(c_corr, Fs, hl, plan.corr);
+    for (int cls : {16, 32, 64}) {                    // GEVD products: (block, bin) by class
+        Seg sg{cls, 0, 0, 0};
+        sg.start = plan.gevd.empty() ? 0 : plan.gevd.back().start + plan.gevd.back().count;
+        for (int b = 0; b < nblocks; ++b)
+            if (hb[b].Kisq && c_wh[b] == cls)
+                for (int f = 0; f < hb[b].F; ++f) hgevd[sg.start + sg.count++] = make_int2(b, f);
+        if (sg.count) plan.gevd.push_back(sg);
+    }
     {
         // whitening: blocks of one class sharing a noise set, cut into runs of near-equal length
         // (whiten_run_length); items (chunk, bin), bin-major inside a group so that the runs of
@@ -1572,7 +1691,7 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
         std::vector<std::vector<int>> members;
         std::map<std::tuple<int, const void *>, int> group_of;
         for (int b = 0; b < nblocks; ++b) {
-            if (!hb[b].Kinv) {                        // SEVD-MUSIC block: no whitening
+            if (!hb[b].Kinv || hb[b].Kisq) {          // SEVD / GEVD block: not whitened here
                 key.push_back(-1);
                 continue;
             }
@@ -1588,7 +1707,7 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
         }
         std::vector<int> classes;
         for (int b = 0; b < nblocks; ++b)
-            if (hb[b].Kinv) classes.push_back(c_wh[b]);
+            if (hb[b].Kinv && !hb[b].Kisq) classes.push_back(c_wh[b]);
         std::sort(classes.begin(), classes.end());
         classes.erase(std::unique(classes.begin(), classes.end()), classes.end());
         int2 *out = hl + n_items;
@@ -1678,7 +1797,7 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
     if (e != hipSuccess) return hip_fail(e, "descriptor copy");
 
     if (!ctx->use_graphs || ctx->timing) {
-        e = enqueue_batch(ctx, plan, db, dl, ga, prec, st);
+        e = enqueue_batch(ctx, plan, db, dl, ga, dgevd, prec, st);
         return e == hipSuccess ? SSL_OK : hip_fail(e, "batch launch");
     }
     hipGraphExec_t exec = nullptr;
@@ -1694,7 +1813,7 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
         }
         e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-        hipError_t le = enqueue_batch(ctx, plan, db, dl, ga, prec, ctx->cap_stream);
+        hipError_t le = enqueue_batch(ctx, plan, db, dl, ga, dgevd, prec, ctx->cap_stream);
         hipGraph_t graph = nullptr;
         e = hipStreamEndCapture(ctx->cap_stream, &graph);
         if (le != hipSuccess) {
@@ -1824,7 +1943,18 @@ ssl_status ssl_noise_update_frames_from(ssl_ctx ctx, int n, const ssl_noise *dst
             if (e != hipSuccess) return hip_fail(e, "noise factor launch");
         }
     }
-    for (int i = 0; i < n; ++i) dst[i]->is_set = true;
+    for (int i = 0; i < n; ++i) {
+        ssl_noise h = dst[i];
+        h->is_set = true;
+        bool first = true;                           // a handle listed twice: once suffices
+        for (int j = i + 1; j < n; ++j) first = first && dst[j] != h;
+        if (h->gevd && first) {
+            e = timed(ctx, SSL_K_NOISE, st, [&] {
+                return launch_noise_isqrt(h->K, h->status, h->F, h->M, h->Kisq, h->status, st);
+            });
+            if (e != hipSuccess) return hip_fail(e, "K^-1/2 launch");
+        }
+    }
     return SSL_OK;
 }
 

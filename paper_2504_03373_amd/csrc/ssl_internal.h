@@ -56,6 +56,8 @@ struct ssl_ctx_s {
     char *scratch = nullptr;
     // SVD backend of every entry point (ssl_ctx_set_svd)
     int svd = SSL_SVD_JACOBI;
+    // subspace method for calls with a noise handle (ssl_ctx_set_subspace)
+    int subspace = SSL_SUBSPACE_GSVD;
     // Jacobi variant (lanes per column pair) per size class 8/16/32/64 channels
     int jac_lanes[4] = {8, 8, 8, 8};     // lanes per Jacobi column pair, classes 8/16/32/64
     // waves per projection workgroup, [steer class 1/2/4][SSL_FP32, SSL_BF16, SSL_FP16]
@@ -69,6 +71,9 @@ struct ssl_noise_s {
     ssl_c128 *K;       // [F][M][M] current noise correlation
     ssl_c128 *Kinv;    // [F][M][M] FP64 inverse by Gauss-Jordan elimination
     int32_t *status;   // [F] SSL_BIN_OK / SSL_BIN_NOT_PD
+    // GEVD-MUSIC (ssl_noise_enable_gevd): K^{-1/2}, recomputed with every refactor once enabled
+    ssl_c128 *Kisq = nullptr;
+    bool gevd = false;
 };
 
 // Frame stream of eq.3 (ssl_sliding_*): the ring of the last T frames of every bin, the FP64 sum
@@ -98,6 +103,7 @@ struct BlockDev {
     float scale;                    // (float)(1/T), the same value the single-block path uses
     int hprec;                      // ssl_prec of H
     const double2 *Kinv;            // noise handle: FP64 inverse, per-bin status
+    const double2 *Kisq;            // K^{-1/2} when the block runs GEVD-MUSIC, else null
     const int32_t *kstatus;
     const void *H;
     float2 *R, *A, *En;             // workspace slices
@@ -174,6 +180,17 @@ int steer_rows_per_block(int waves);
 int binsum_threads();
 
 // --- launchers (each returns hipSuccess or the launch error) ---
+// GEVD-MUSIC: W = K^{-1/2} per bin (FP64 Jacobi eigen-decomposition of K; wstatus may alias
+// kstatus), C = W R W, and E_n <- W E_n; batched forms over (block, bin) items
+hipError_t launch_noise_isqrt(const ssl_c128 *K, const int32_t *kstatus, int F, int M,
+                              ssl_c128 *W, int32_t *wstatus, hipStream_t st);
+hipError_t launch_gevd_whiten(const ssl_c128 *W, const ssl_c64 *R, ssl_c64 *C, int F, int M,
+                              hipStream_t st);
+hipError_t launch_gevd_back(const ssl_c128 *W, ssl_c64 *En, int F, int M, int Ns, hipStream_t st);
+hipError_t launch_gevd_whiten_batch(const BlockDev *blk, const int2 *items, int n_items, int cls,
+                                    hipStream_t st);
+hipError_t launch_gevd_back_batch(const BlockDev *blk, const int2 *items, int n_items, int cls,
+                                  hipStream_t st);
 // eq.3 frame stream: S += sum over the n new frames of x x^H - o o^H (o: the frame each displaces
 // from the ring, zero while fewer than T frames were pushed), ring updated; R = S * inv_t
 hipError_t launch_sliding_push(const ssl_c64 *X, int n, int64_t sF, int64_t sT, int F, int M,
