@@ -32,14 +32,6 @@ __device__ __forceinline__ float dpp(float v)
 {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
-__device__ __forceinline__ float sum16(float v)
-{
-    v += dpp<0xB1>(v);
-    v += dpp<0x4E>(v);
-    v += dpp<0x141>(v);
-    v += dpp<0x140>(v);
-    return v;
-}
 
 template <typename E> struct LpMfma;
 template <> struct LpMfma<__bf16> {
@@ -64,7 +56,10 @@ template <typename E> struct SteerCfg {
     static constexpr bool F32 = sizeof(E) == 4;
     static constexpr int KC = F32 ? 16 : 32;          // reals per k-chunk
     static constexpr int KQ_MAX = 128 / KC;           // 2M <= 128
-    static constexpr int PAD = F32 ? 4 : 8;           // LDS row padding (elements)
+    // B row stride KS_MAX (compile-time, so every LDS offset is an immediate): 128 reals plus 32
+    // bytes, 8 banks mod 64, so the 16-byte B fragments of the 32 lanes of a half wave (16 rows x
+    // 2 k-slices) fall on distinct banks (counted: no LDS bank conflicts)
+    static constexpr int PAD = F32 ? 8 : 16;
     static constexpr int KS_MAX = 128 + PAD;
 };
 
@@ -133,7 +128,7 @@ __device__ __forceinline__ float load_strip(const E *__restrict__ Hf, int D, int
 }
 
 // E_n[f] as the B operand: Bs[c * KS + k] = real k of noise vector c (k < 2M), zero for c >= Nn
-// or k >= 2M up to the k-chunk padding KP.  Thread tid owns elements e = tid + 64 WV u of a
+// or k >= 2M up to the k-chunk padding KP (KS = KS_MAX).  Thread tid owns elements e = tid + 64 WV u of a
 // 16 NCT x 64 complex grid (column c = e / 64 = tid / 64 + WV u, element m = e % 64 = tid % 64);
 // load_b puts them in registers (all loads in flight at once), store_b writes those with
 // m < KP / 2.
@@ -216,8 +211,11 @@ __device__ __forceinline__ void mma(const AStrip<E> &S, const E *Bs, int KS, int
 }
 
 // Epilogue.  acc[ct][r] = column 16 ct + l%16 of row 4 (l/16) + r of the wave's strip; den of a
-// row is the sum over columns (lanes of one 16-lane row group) of |G|^p.  nrm_s holds |h|^2 of
-// the workgroup's rows.
+// row is the sum over columns (the 16 lanes of a row group) of |G|^p.  The four row sums of a
+// lane are reduced and scattered at once: a mirror exchange across the 16 lanes leaves rows
+// {0, 1} on lanes c < 8 and {2, 3} on the others, a half mirror leaves one row per lane (row
+// c / 4), and two quad exchanges complete the sums, so lane c of row group g ends with den of row
+// 4 g + c / 4.  nrm_s holds |h|^2 of the workgroup's rows.
 template <int NCT>
 __device__ __forceinline__ void finish_rows(const floatx4 (&acc1)[NCT], const floatx4 (&acc2)[NCT],
                                             int p, int lane, int wave, int d0, int D, bool bin_ok,
@@ -232,7 +230,7 @@ __device__ __forceinline__ void finish_rows(const floatx4 (&acc1)[NCT], const fl
 #pragma unroll
             for (int ct = 0; ct < NCT; ++ct)
                 s = fmaf(acc1[ct][r], acc1[ct][r], fmaf(acc2[ct][r], acc2[ct][r], s));
-            part[r] = sum16(s);
+            part[r] = s;
         }
     } else {
 #pragma unroll
@@ -241,19 +239,22 @@ __device__ __forceinline__ void finish_rows(const floatx4 (&acc1)[NCT], const fl
 #pragma unroll
             for (int ct = 0; ct < NCT; ++ct)
                 s += sqrtf(fmaf(acc1[ct][r], acc1[ct][r], acc2[ct][r] * acc2[ct][r]));
-            part[r] = sum16(s);
+            part[r] = s;
         }
     }
-    // every lane of row group g = l / 16 holds den of rows 4 g + r in part[r]; lane j < 16 takes
-    // row j's from lane 16 (j / 4) + j % 4, which offers part[j % 4]
-    const float offer = (lane & 2) ? ((lane & 1) ? part[3] : part[2]) : ((lane & 1) ? part[1] : part[0]);
-    const float den = __shfl(offer, 16 * ((lane >> 2) & 3) + (lane & 3));
-    if (lane < 16) {
-        const int d = d0 + wave * 16 + lane;
+    const int c = lane & 15;
+    const bool lo = c < 8, lo2 = (c & 7) < 4;
+    const float a0 = (lo ? part[0] : part[2]) + dpp<0x140>(lo ? part[2] : part[0]);   // row_mirror
+    const float a1 = (lo ? part[1] : part[3]) + dpp<0x140>(lo ? part[3] : part[1]);
+    float den = (lo2 ? a0 : a1) + dpp<0x141>(lo2 ? a1 : a0);                        // row_half_mirror
+    den += dpp<0xB1>(den);
+    den += dpp<0x4E>(den);
+    if ((c & 3) == 0) {
+        const int row = wave * 16 + 4 * (lane >> 4) + (c >> 2);
+        const int d = d0 + row;
         if (d < D) {
             // hardware reciprocal (1 ulp): P is compared at 1e-4, den >= FLT_MIN
-            gstore(Pf + d, bin_ok ? nrm_s[wave * 16 + lane] *
-                                        __builtin_amdgcn_rcpf(fmaxf(den, 1.17549435e-38f))
+            gstore(Pf + d, bin_ok ? nrm_s[row] * __builtin_amdgcn_rcpf(fmaxf(den, 1.17549435e-38f))
                                   : 0.0f);
         }
     }
@@ -275,7 +276,7 @@ __device__ __forceinline__ void steer_tile(const E *__restrict__ Hf, int D, int 
     const int K2 = 2 * M;
     const int KQ = (K2 + C::KC - 1) / C::KC;
     const int KP = C::KC * KQ;
-    const int KS = KP + C::PAD;
+    constexpr int KS = C::KS_MAX;
 
     AStrip<E> S;
     float hn = load_strip<E>(Hf, D, M, d0 + wave * 16 + (lane & 15), lane >> 4, S);
