@@ -45,7 +45,7 @@ PEAK_HBM_GBS = 8000.0
 PEAK_MFMA_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0}
 
 
-def jacobi_flops(M: int, sweeps, rotations, rank) -> float:
+def jacobi_flops(M: int, sweeps, rotations, rank, Ns: int = 0, sub: bool = False) -> float:
     """Algorithmic real flops of the SVD kernel summed over bins (rank r per bin).
     Pivoted QR: step k = 0..r-1 has trailing size n = M - k; each of the n - 1 remaining columns
     costs w = v^H x (8n), x -= v (tau w) (8n) and its trailing norm (4n): 20 n (n - 1).
@@ -53,7 +53,11 @@ def jacobi_flops(M: int, sweeps, rotations, rank) -> float:
     16 (M - k)(r - k - 1).  Jacobi on X (r x r): each pair visit forms |x_i|^2, |x_j|^2, x_i^H x_j
     (16 r); each applied rotation rewrites two columns (20 r); pair visits = sweeps r(r-1)/2.
     Normalisation of W: 6 r per column.  U = Q U_R: reflector k applied to the M columns,
-    16 (M - k) M."""
+    16 (M - k) M.
+    sub: the solve stopped at the noise subspace (p = 2 localization): the first sweep visits
+    every pair, each later one the Ns (r - Ns) + Ns (Ns - 1) / 2 pairs with a member in the signal
+    set (a bin that fell back to full sweeps is counted the same way, which undercounts it); the
+    r - Ns complement vectors each pass Ns reflectors (16 r), and W is not normalised."""
     import numpy as np
     total = 0.0
     for s, rot, r in zip(np.asarray(sweeps), np.asarray(rotations), np.asarray(rank)):
@@ -62,7 +66,12 @@ def jacobi_flops(M: int, sweeps, rotations, rank) -> float:
         n = M - k
         total += float(np.sum(20.0 * n * (n - 1)) + np.sum(16.0 * n * (r - k - 1))
                        + np.sum(16.0 * n * M))
-        total += float(s) * r * (r - 1) / 2.0 * 16.0 * r + float(rot) * 20.0 * r + 6.0 * r * r
+        if sub and r > Ns:
+            visits = min(float(s), 1.0) * r * (r - 1) / 2.0 + \
+                max(float(s) - 1.0, 0.0) * (Ns * (r - Ns) + Ns * (Ns - 1) / 2.0)
+            total += visits * 16.0 * r + float(rot) * 20.0 * r + (r - Ns) * Ns * 16.0 * r
+        else:
+            total += float(s) * r * (r - 1) / 2.0 * 16.0 * r + float(rot) * 20.0 * r + 6.0 * r * r
     return total
 
 
@@ -582,13 +591,17 @@ def main() -> int:
             waves, sms = S.ssl_autotune_steer(ctx, H, prec, En, Ns, p=2, nblocks=B, reps=3)
             tuning.setdefault("steer_waves", {})[name] = waves
             tuning.setdefault("steer_ms", {})[name] = {str(k): round(v, 4) for k, v in sms.items()}
+        # ssl_gsvd without sigma under SSL_STOP_ALSO_GSVD runs the Jacobi solve exactly as the
+        # p = 2 localization does (stopped at the noise subspace)
         conv_all = []
+        S.ssl_ctx_set_stop(ctx, S.SSL_STOP_ALSO_GSVD)
         for b in range(B if conv else 0):
             S.ssl_corr_accum(ctx, Xs[b], 1.0 / T, 0, prec, R)
             S.ssl_gsvd(ctx, R, noise, Ns, En, None, None, conv_t, 0)
             conv_all.append(conv_t.cpu().numpy().copy())
+        S.ssl_ctx_set_stop(ctx, S.SSL_STOP_LOCALIZE)
         del R, En
-        jflops = float(sum(jacobi_flops(M, c[:, 0], c[:, 1], c[:, 2]) for c in conv_all))
+        jflops = float(sum(jacobi_flops(M, c[:, 0], c[:, 1], c[:, 2], Ns, True) for c in conv_all))
         descs = [S.block_desc(Xs[b], noise, H, w.grid.n_az, w.grid.n_el, Ns, pk[b], pv[b],
                               Pbar[b], st[b]) for b in range(B)]
 
@@ -746,7 +759,8 @@ def main() -> int:
         "config": {"workload": w.name, "M": M, "F": F, "T": T, "D": D, "Ns": Ns, "p": 2,
                    "blocks_per_step": B, "path": "ssl_localize_batch",
                    "mfma_inputs": args.prec, "whitening": "fp64",
-                   "svd": "fp32 one-sided Jacobi (two-QR preconditioned)"},
+                   "svd": "fp32 one-sided Jacobi (two-QR preconditioned), stopped at the noise "
+                          "subspace"},
         "graph_value": round(main_r["graph_value"], 2),
         "per_block": {"value": round(main_r["per_block"], 2), "unit": "blocks/s",
                       "path": f"ssl_localize, one block per call, {args.prec}"},

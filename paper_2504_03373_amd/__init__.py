@@ -24,6 +24,8 @@ SSL_FP32, SSL_BF16, SSL_FP16, SSL_FP64 = 0, 1, 2, 3
 SSL_SVD_JACOBI, SSL_SVD_BIDIAG_QR = 0, 1
 # ssl_subspace
 SSL_SUBSPACE_GSVD, SSL_SUBSPACE_GEVD = 0, 1
+# ssl_stop
+SSL_STOP_NEVER, SSL_STOP_BATCH, SSL_STOP_LOCALIZE, SSL_STOP_ALSO_GSVD = 0, 1, 2, 3
 # fixed scratch of ssl_localize_noalloc (bytes, per device)
 SSL_NOALLOC_SCRATCH_BYTES = 64 << 20
 
@@ -41,6 +43,7 @@ EXPORTED = [
     "ssl_sliding_create", "ssl_sliding_destroy", "ssl_sliding_push", "ssl_sliding_frames",
     "ssl_sliding_corr", "ssl_sliding_localize", "ssl_ctx_set_svd", "ssl_ctx_get_svd",
     "ssl_ctx_set_subspace", "ssl_ctx_get_subspace", "ssl_noise_enable_gevd",
+    "ssl_ctx_set_stop", "ssl_ctx_get_stop",
 ]
 
 
@@ -105,6 +108,8 @@ def lib() -> ctypes.CDLL:
         "ssl_ctx_set_subspace": (I, [P, I]),
         "ssl_ctx_get_subspace": (I, [P]),
         "ssl_noise_enable_gevd": (I, [P, P]),
+        "ssl_ctx_set_stop": (I, [P, I]),
+        "ssl_ctx_get_stop": (I, [P]),
         "ssl_sliding_create": (I, [P, I, I, I, ctypes.POINTER(P)]),
         "ssl_sliding_destroy": (None, [P]),
         "ssl_sliding_push": (I, [P, P, I, I64, I64, P]),
@@ -248,6 +253,14 @@ def ssl_ctx_set_subspace(ctx, method: int) -> None:
 
 def ssl_ctx_get_subspace(ctx) -> int:
     return int(lib().ssl_ctx_get_subspace(ctx))
+
+
+def ssl_ctx_set_stop(ctx, mode: int) -> None:
+    _check("ssl_ctx_set_stop", lib().ssl_ctx_set_stop(ctx, mode))
+
+
+def ssl_ctx_get_stop(ctx) -> int:
+    return int(lib().ssl_ctx_get_stop(ctx))
 
 
 def ssl_noise_enable_gevd(noise, stream=None) -> None:

@@ -146,12 +146,20 @@ int gk_max_steps(int M) { return 40 * M; }
 // bidiagonal one reads it only); U (Jacobi only) receives all sorted singular vectors.
 hipError_t launch_svd(ssl_ctx ctx, ssl_c64 *A, const int32_t *kst, int F, int M, int Ns,
                       int max_sweeps, ssl_c64 *En, float *sigma, int32_t *stt, int32_t *conv,
-                      hipStream_t st, ssl_c64 *U = nullptr)
+                      hipStream_t st, ssl_c64 *U = nullptr, int sub_full = -1)
 {
     if (ctx->svd == SSL_SVD_BIDIAG_QR)
         return launch_gk_svd(A, kst, F, M, Ns, gk_max_steps(M), En, sigma, stt, conv, st);
     return launch_jacobi(A, kst, F, M, Ns, max_sweeps, jac_lanes(ctx, M), En, sigma, stt, conv, st,
-                         U);
+                         U, sub_full);
+}
+// Whether a localization path stops the Jacobi solve at the noise subspace (p = 2: eq.5 reads only
+// its projector): the batched path from SSL_STOP_BATCH on, the one-block paths from
+// SSL_STOP_LOCALIZE on.
+int sub_full_for(ssl_ctx ctx, int p, bool batched)
+{
+    const int need = batched ? SSL_STOP_BATCH : SSL_STOP_LOCALIZE;
+    return p == 2 && ctx->sub_stop >= need ? kSubFullSweeps : -1;
 }
 int st_waves(ssl_ctx ctx, int M, int Ns, ssl_prec prec)
 {
@@ -311,7 +319,7 @@ ssl_status localize_enqueue(ssl_ctx ctx, bool may_time, char *w, const LocalizeW
     }
     e = run(SSL_K_JACOBI, [&] {
         return launch_svd(ctx, A, K ? K->status : nullptr, F, M, Ns, SSL_DEFAULT_SWEEPS, En,
-                          nullptr, stt, nullptr, st);
+                          nullptr, stt, nullptr, st, nullptr, sub_full_for(ctx, p, false));
     });
     if (e != hipSuccess) return hip_fail(e, "jacobi launch");
     if (gevd) {
@@ -739,7 +747,8 @@ ssl_status ssl_gsvd(ssl_ctx ctx, const ssl_c64 *R, ssl_noise K, int F, int M, in
     }
     e = timed(ctx, SSL_K_JACOBI, st, [&] {
         return launch_svd(ctx, A, K ? K->status : nullptr, F, M, Ns, max_sweeps, En, sigma,
-                          bin_status, conv, st);
+                          bin_status, conv, st, nullptr,
+                          ctx->sub_stop == SSL_STOP_ALSO_GSVD && !sigma ? kSubFullSweeps : -1);
     });
     if (e != hipSuccess) return hip_fail(e, "jacobi launch");
     if (gevd) {
@@ -1206,7 +1215,7 @@ hipError_t enqueue_batch(ssl_ctx ctx, const Plan &P, const BlockDev *blk, const 
             return launch_jacobi_batch(blk, l_jac + s.start, s.count, s.cls,
                                        ctx->jac_lanes[jacobi_class_index(s.cls)],
                                        SSL_DEFAULT_SWEEPS, ctx->counters + jacobi_queue(s.cls),
-                                       s.extra, st);
+                                       s.extra, st, sub_full_for(ctx, 2, true));
         });
         if (e != hipSuccess) return e;
     }
@@ -1299,6 +1308,7 @@ ssl_status ssl_autotune_jacobi(ssl_ctx ctx, const ssl_c64 *R, ssl_noise K, int F
             B.F = F;
             B.M = M;
             B.Ns = Ns;
+            B.p = 2;                                   // timed as the p = 2 localization runs
             B.kstatus = K->status;
             B.A = reinterpret_cast<float2 *>(A + b * perA);
             B.En = reinterpret_cast<float2 *>(En + b * perE);
@@ -1314,11 +1324,12 @@ ssl_status ssl_autotune_jacobi(ssl_ctx ctx, const ssl_c64 *R, ssl_noise K, int F
     auto launch = [&](int lanes) {
         if (nblocks == 1)
             return launch_jacobi(A, K->status, F, M, Ns, SSL_DEFAULT_SWEEPS, lanes, En, nullptr,
-                                 nullptr, nullptr, st);
+                                 nullptr, nullptr, st, nullptr, sub_full_for(ctx, 2, false));
         const int n_items = nblocks * F;
         const int grid = std::min(n_items, ctx->cu_count * jacobi_persistent_wg_per_cu(cls, lanes));
         return launch_jacobi_batch(dblk, ditems, n_items, cls, lanes, SSL_DEFAULT_SWEEPS,
-                                   ctx->counters + jacobi_queue(cls), grid, st);
+                                   ctx->counters + jacobi_queue(cls), grid, st,
+                                   sub_full_for(ctx, 2, true));
     };
     const int cand[3] = {4, 8, 16};
     hipEvent_t a = nullptr, b = nullptr;
@@ -1514,6 +1525,22 @@ ssl_status ssl_ctx_set_svd(ssl_ctx ctx, ssl_svd method)
 
 int ssl_ctx_get_svd(ssl_ctx ctx) { return ctx ? ctx->svd : -1; }
 
+ssl_status ssl_ctx_set_stop(ssl_ctx ctx, ssl_stop mode)
+{
+    if (!ctx) {
+        ssl_set_error("ctx is NULL");
+        return SSL_ERR_ARG;
+    }
+    if (mode < SSL_STOP_NEVER || mode > SSL_STOP_ALSO_GSVD) {
+        ssl_set_error("unknown stop mode %d", (int)mode);
+        return SSL_ERR_ARG;
+    }
+    ctx->sub_stop = mode;
+    return SSL_OK;
+}
+
+int ssl_ctx_get_stop(ssl_ctx ctx) { return ctx ? ctx->sub_stop : -1; }
+
 ssl_status ssl_ctx_use_graphs(ssl_ctx ctx, int enable)
 {
     if (!ctx) {
@@ -1553,6 +1580,7 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
     key.push_back(p);
     for (int i = 0; i < 4; ++i) key.push_back(ctx->jac_lanes[i]);   // kernel variants captured
     key.push_back(ctx->svd);
+    key.push_back(ctx->sub_stop);
     for (int c = 0; c < 3; ++c) key.push_back(ctx->steer_waves[c][prec]);
     for (int b = 0; b < nblocks; ++b) {
         const ssl_block_desc &d = descs[b];

@@ -14,6 +14,16 @@
 // twice-triangularised pivoted factor, which is close to diagonal: about 6 sweeps on the
 // 60-channel workload (about 17 on A itself), and no rotation has to be accumulated.
 //
+// Stopping at the noise subspace (sub_full >= 0, the p = 2 localization): eq.5 with p = 2 reads
+// only E_n E_n^H.  After sub_full full sweeps the Ns columns of largest norm form the signal set S
+// and only the pairs with a member in S are visited (the larger result kept in S) until such a
+// sweep changes nothing; if then min_S |x|^2 exceeds the sum of |x|^2 over the other columns (a
+// bound on their largest squared singular value), X_S spans the Ns dominant singular vectors and
+// E_n is built as the orthogonal complement of X_S (Householder vectors of X_S) instead of from
+// the rotations that would still run inside the noise cluster.  On the 60-channel workload the
+// projector has converged after 1 full and about 2 such sweeps, against about 6 full sweeps for
+// the singular vectors; the noise vectors then are not singular vectors (sigma is not produced).
+//
 // GPU mapping (gfx950):
 //  * one workgroup per bin; one complex64 MP x MP column-major matrix in LDS (32 KB at MP = 64,
 //    four bins per CU) holds A -> its QR -> R^H -> R1 -> X -> W -> U in turn (the two
@@ -275,15 +285,172 @@ __device__ __forceinline__ bool jacobi_pair(float2 *Bs, int ci, int cj, int q, d
     return true;
 }
 
+// Subspace phase limits: signal sets of at most kSubMaxNs columns, at most kSubMaxSweeps sweeps
+// over their pairs before the solve returns to full sweeps.
+constexpr int kSubMaxNs = 8;
+constexpr int kSubMaxSweeps = 4;
+
+// |x_c|^2 of the columns c < rk (sweep layout) into nrm[c], one lane group per column.
+template <int MP, int G>
+__device__ __forceinline__ void sub_norms(const float2 *Bs, int rk, int g, int q, float *nrm)
+{
+    constexpr int R = MP / G, NG = MP / 2;
+    for (int c = g; c < rk && g < NG; c += NG) {
+        float s = 0.f;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const float2 v = Bs[swx<MP>(c, q + G * k)];
+            s = fmaf(v.x, v.x, fmaf(v.y, v.y, s));
+        }
+        s = group_sum<G>(s);
+        if (q == 0) nrm[c] = s;
+    }
+}
+
+// Whether a subspace-phase sweep would change nothing: every pair with a member in S tested at
+// once (no rotation in between, so a sweep over them in any order would see the same columns),
+// a lane group per pair.  A signal / noise pair fails if it would be rotated (the jacobi_pair
+// test, same sums: rows >= rk are zero) or exchanged (noise column longer); a signal / signal
+// pair if it would be rotated.  slist = S's columns, nlist = the others (< rk).  Uniform result.
+template <int MP, int G>
+__device__ __forceinline__ bool sub_settled(const float2 *Bs, const int *slist, const int *nlist,
+                                            int Ns, int rk, int g, int q, double tol2)
+{
+    constexpr int R = MP / G, NG = MP / 2;
+    const int nn = rk - Ns, ncross = Ns * nn, npairs = ncross + Ns * (Ns - 1) / 2;
+    int bad = 0;
+    for (int p = g; p < npairs && g < NG; p += NG) {
+        int ci, cj;
+        if (p < ncross) {
+            ci = slist[p / nn];
+            cj = nlist[p % nn];
+        } else {                                     // (a, b), a < b < Ns, enumerated by b
+            int t = p - ncross, b = 1;
+            while (t >= b) {
+                t -= b;
+                ++b;
+            }
+            ci = slist[t];
+            cj = slist[b];
+        }
+        float al = 0.f, be = 0.f, gr = 0.f, gi = 0.f;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int r = q + G * k;
+            const float2 x = Bs[swx<MP>(ci, r)], y = Bs[swx<MP>(cj, r)];
+            al = fmaf(x.x, x.x, fmaf(x.y, x.y, al));
+            be = fmaf(y.x, y.x, fmaf(y.y, y.y, be));
+            gr = fmaf(x.x, y.x, fmaf(x.y, y.y, gr));
+            gi = fmaf(x.x, y.y, fmaf(-x.y, y.x, gi));
+        }
+        al = group_sum<G>(al);
+        be = group_sum<G>(be);
+        gr = group_sum<G>(gr);
+        gi = group_sum<G>(gi);
+        const double g2 = (double)gr * gr + (double)gi * gi;
+        const double ab = (double)al * be;
+        if ((g2 > tol2 * ab && ab > 0.0) || (p < ncross && be > al)) bad = 1;
+    }
+    return __syncthreads_count(bad) == 0;
+}
+
+// A pair visit of the subspace phase: column cs of the signal set S, column cn outside it.  The
+// pair is rotated as in jacobi_pair, and the result of larger norm is kept in the signal slot:
+// the minimal rotation keeps the order of the two norms (|x_s'|^2 = alpha - t |gamma|,
+// |x_n'|^2 = beta + t |gamma|, t of the sign of beta - alpha), so the two results trade places
+// iff beta > alpha; an orthogonal pair with beta > alpha is exchanged.  |X_S|_F^2 never
+// decreases.  Returns whether the columns changed.
+template <int MP, int G, int NR>
+__device__ __forceinline__ bool jacobi_pair_sorted(float2 *Bs, int cs, int cn, int q, double tol2)
+{
+    float2 bi[NR], bj[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        const int r = q + G * k;
+        bi[k] = Bs[swx<MP>(cs, r)];
+        bj[k] = Bs[swx<MP>(cn, r)];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    float al = 0.f, be = 0.f, gr = 0.f, gi = 0.f;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        al = fmaf(bi[k].x, bi[k].x, fmaf(bi[k].y, bi[k].y, al));
+        be = fmaf(bj[k].x, bj[k].x, fmaf(bj[k].y, bj[k].y, be));
+        gr = fmaf(bi[k].x, bj[k].x, fmaf(bi[k].y, bj[k].y, gr));
+        gi = fmaf(bi[k].x, bj[k].y, fmaf(-bi[k].y, bj[k].x, gi));
+    }
+    al = group_sum<G>(al);
+    be = group_sum<G>(be);
+    gr = group_sum<G>(gr);
+    gi = group_sum<G>(gi);
+    const bool swap = be > al;
+    const double g2 = (double)gr * gr + (double)gi * gi;
+    const double ab = (double)al * be;
+    if (!(g2 > tol2 * ab && ab > 0.0)) {
+        if (!swap) return false;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const int r = q + G * k;
+            Bs[swx<MP>(cs, r)] = bj[k];
+            Bs[swx<MP>(cn, r)] = bi[k];
+        }
+        return true;
+    }
+    const float g2f = (float)g2;
+    float rg;
+    if (g2f >= 1e-36f) {
+        rg = __builtin_amdgcn_rsqf(g2f);
+    } else {
+        const float ax = fabsf(gr), ay = fabsf(gi);
+        const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+        const float rt = mn * __builtin_amdgcn_rcpf(mx);
+        rg = __builtin_amdgcn_rcpf(mx * __builtin_amdgcn_sqrtf(fmaf(rt, rt, 1.0f)));
+    }
+    const float zeta = (be - al) * 0.5f * rg;
+    const float az = fminf(fabsf(zeta), 1e18f);
+    float t = __builtin_amdgcn_rcpf(az + __builtin_amdgcn_sqrtf(fmaf(az, az, 1.0f)));
+    t = copysignf(t, zeta);
+    const float c = rsqrt_refined(fmaf(t, t, 1.0f));
+    const float sn = c * t;
+    const float wr = sn * gr * rg;
+    const float wi = -sn * gi * rg;
+    const int ds = swap ? cn : cs, dn = swap ? cs : cn;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        const int r = q + G * k;
+        float2 x = bi[k], y = bj[k];
+        float2 ni, nj;
+        ni.x = fmaf(c, x.x, -fmaf(wr, y.x, -wi * y.y));
+        ni.y = fmaf(c, x.y, -fmaf(wr, y.y, wi * y.x));
+        nj.x = fmaf(c, y.x, fmaf(wr, x.x, wi * x.y));
+        nj.y = fmaf(c, y.y, fmaf(wr, x.y, -wi * x.x));
+        Bs[swx<MP>(ds, r)] = ni;
+        Bs[swx<MP>(dn, r)] = nj;
+    }
+    return true;
+}
+
+// Sum over the 64 lanes of a wave; every lane gets the same bits.
+__device__ __forceinline__ float wave_sum(float v)
+{
+    v = group_sum<16>(v);
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    return v;
+}
+
 // One bin: Af = its A (row-major M x M, overwritten), kst = upstream status of the bin (noise
 // factorisation), Enf = [M-Ns][M] output, sigf = [M] or null, stf = status or null,
-// convf = (sweeps, rotations, numerical rank) or null.
+// convf = (sweeps, rotations, numerical rank) or null.  sub_full >= 0 (only with sigf and Uf
+// null, 1 <= Ns <= kSubMaxNs) asks for the noise subspace alone: E_n is then an orthonormal basis
+// of the span of the M - Ns smallest left singular vectors (what eq.5 with p = 2 depends on), not
+// the singular vectors themselves; see the subspace phase below.
 template <int MP, int G>
 __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int M, int Ns,
                                            int max_sweeps, float2 *__restrict__ Enf,
                                            float *__restrict__ sigf, int32_t *__restrict__ stf,
                                            int32_t *__restrict__ convf,
-                                           float2 *__restrict__ Uf = nullptr)
+                                           float2 *__restrict__ Uf = nullptr, int sub_full = -1)
 {
     typedef JacobiCfg<MP, G> C;
     constexpr int R = C::R;
@@ -352,6 +519,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
 
     int sweeps = 0;
     bool converged = false;
+    bool sub_done = false;              // stopped by the subspace phase
     int ex = 0;
     if (flag == SSL_BIN_OK) {
         // scale by a power of two so that max |A_ij| lies in [0.5, 1): exact, keeps every Gram
@@ -570,49 +738,148 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         // row slots per lane: R - 1 when they cover the rank (the 60-channel rank-50 case), else R
         constexpr int RLO = R > 1 ? R - 1 : 1;
         const bool nr_lo = rk <= G * RLO;
+        // Subspace phase (sub_full >= 0): after sub_full full sweeps, S = the Ns columns of
+        // largest norm; then only the pairs with a member in S are visited (jacobi_pair_sorted
+        // for a signal / noise pair, so that S keeps the larger results), until such a sweep
+        // changes nothing: X_S is then orthogonal to the other columns and within itself to the
+        // rotation tolerance, and X's singular values split into those of X_S and of the rest.
+        // X_S spans the Ns dominant left singular vectors when min_S |x|^2 > sum of |x|^2 over
+        // the rest (that sum bounds the square of the largest singular value of the rest),
+        // checked on the column norms; the noise subspace is then the orthogonal complement of
+        // X_S, and the rotations inside it that the full solve would still make change nothing
+        // eq.5 with p = 2 reads.  A failed check, or kSubMaxSweeps subspace sweeps without
+        // convergence, returns to full sweeps (the full solve); so does a bin whose weakest
+        // signal column holds less than the other columns' energy at the switch.
+        const bool sub = sub_full >= 0 && sigf == nullptr && Uf == nullptr && Ns >= 1 &&
+                         Ns <= kSubMaxNs && Ns < rk;
+        int phase = 0;                               // 0 full, 1 subspace, 2 full after a fallback
+        int sub_sweeps = 0;
+        unsigned long long smask = 0ull;
         for (int sw = 0; sw < max_sweeps; ++sw) {
-            int rotated = 0;
-            for (int rd = 0; rd < n_rounds; ++rd) {
-                int a = 0, b = 0;
-                bool play;
-                if (rd < Me - 1) {
-                    play = g < Pr;
-                    if (g == 0) {
-                        a = Me - 1;
-                        b = rd;
-                    } else {                         // (rd +- g) mod (Me - 1), 0 < g < Me/2
-                        a = rd + g;
-                        if (a >= Me - 1) a -= Me - 1;
-                        b = rd - g;
-                        if (b < 0) b += Me - 1;
+            if (sub && phase == 0 && sw == sub_full) {
+                sub_norms<MP, G>(Bs, rk, g, q, nrm1);
+                __syncthreads();
+                if (tid == 0) {
+                    unsigned long long m = 0ull;
+                    float tot = 0.0f;
+                    for (int c = 0; c < rk; ++c) tot += nrm1[c];
+                    for (int k = 0; k < Ns; ++k) {
+                        int best = -1;
+                        float bv = -1.0f;
+                        for (int c = 0; c < rk; ++c)
+                            if (!((m >> c) & 1ull) && (best < 0 || nrm1[c] > bv)) {
+                                bv = nrm1[c];
+                                best = c;
+                            }
+                        m |= 1ull << best;              // rk > Ns: a column is always left
                     }
-                } else if (rd < Me + 1) {            // (2g + e, 2g + e + 1), e = 0, 1
-                    play = g < (Me - 2) / 2;
-                    a = 2 * g + (rd - (Me - 1));
-                    b = a + 1;
-                } else {
-                    play = g == 0;
-                    a = Me - 2;
-                    b = 0;
-                }
-                if (play) {
-                    const int ci = min(a, b), cj = max(a, b);
-                    if (cj < rk) {
-                        const bool rot = nr_lo ? jacobi_pair<MP, G, RLO>(Bs, ci, cj, q, tol2)
-                                               : jacobi_pair<MP, G, R>(Bs, ci, cj, q, tol2);
-                        if (rot) {
-                            rotated = 1;
-                            if (q == 0) ++my_rot;
+                    // a bin whose weakest signal column holds less than the rest's energy
+                    // will hardly pass the dominance check: it stays with full sweeps (this
+                    // decides speed only, not the result's accuracy)
+                    float mins = 3.4e38f, sums = 0.0f;
+                    for (int c = 0; c < rk; ++c)
+                        if ((m >> c) & 1ull) {
+                            mins = fminf(mins, nrm1[c]);
+                            sums += nrm1[c];
                         }
+                    pkey[0] = (mins > tot - sums) ? m : 0ull;
+                    int ks = 0, kn = 0;              // S and the other columns, ascending
+                    for (int c = 0; c < rk; ++c) {
+                        if ((m >> c) & 1ull) cinv[ks++] = c;
+                        else clist[kn++] = c;
                     }
                 }
                 __syncthreads();
+                smask = pkey[0];
+                phase = smask ? 1 : 2;
             }
-            ++sweeps;
-            if (__syncthreads_count(rotated) == 0) {
+            // a subspace sweep that would change nothing is replaced by one parallel test
+            bool settled = false;
+            if (phase == 1) {
+                settled = sub_settled<MP, G>(Bs, cinv, clist, Ns, rk, g, q, tol2);
+                if (!settled && sub_sweeps >= kSubMaxSweeps) phase = 2;
+            }
+            if (!settled) {
+                int rotated = 0;
+                for (int rd = 0; rd < n_rounds; ++rd) {
+                    int a = 0, b = 0;
+                    bool play;
+                    if (rd < Me - 1) {
+                        play = g < Pr;
+                        if (g == 0) {
+                            a = Me - 1;
+                            b = rd;
+                        } else {                         // (rd +- g) mod (Me - 1), 0 < g < Me/2
+                            a = rd + g;
+                            if (a >= Me - 1) a -= Me - 1;
+                            b = rd - g;
+                            if (b < 0) b += Me - 1;
+                        }
+                    } else if (rd < Me + 1) {            // (2g + e, 2g + e + 1), e = 0, 1
+                        play = g < (Me - 2) / 2;
+                        a = 2 * g + (rd - (Me - 1));
+                        b = a + 1;
+                    } else {
+                        play = g == 0;
+                        a = Me - 2;
+                        b = 0;
+                    }
+                    if (play) {
+                        const int ci = min(a, b), cj = max(a, b);
+                        if (cj < rk) {
+                            bool rot = false;
+                            if (phase == 1) {
+                                const bool si = (smask >> ci) & 1ull, sj = (smask >> cj) & 1ull;
+                                if (si != sj) {
+                                    const int cs = si ? ci : cj, cn = si ? cj : ci;
+                                    rot = nr_lo ? jacobi_pair_sorted<MP, G, RLO>(Bs, cs, cn, q, tol2)
+                                                : jacobi_pair_sorted<MP, G, R>(Bs, cs, cn, q, tol2);
+                                } else if (si) {
+                                    rot = nr_lo ? jacobi_pair<MP, G, RLO>(Bs, ci, cj, q, tol2)
+                                                : jacobi_pair<MP, G, R>(Bs, ci, cj, q, tol2);
+                                }
+                            } else {
+                                rot = nr_lo ? jacobi_pair<MP, G, RLO>(Bs, ci, cj, q, tol2)
+                                            : jacobi_pair<MP, G, R>(Bs, ci, cj, q, tol2);
+                            }
+                            if (rot) {
+                                rotated = 1;
+                                if (q == 0) ++my_rot;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+                ++sweeps;
+                const bool none = __syncthreads_count(rotated) == 0;
+                if (phase != 1) {
+                    if (none) {
+                        converged = true;
+                        break;
+                    }
+                    continue;
+                }
+                ++sub_sweeps;
+                if (!none) continue;
+            }
+            // the split has converged: dominance check on the column norms (fixed-order sum)
+            sub_norms<MP, G>(Bs, rk, g, q, nrm1);
+            __syncthreads();
+            if (tid == 0) {
+                float mins = 3.4e38f, sumn = 0.0f;
+                for (int c = 0; c < rk; ++c) {
+                    if ((smask >> c) & 1ull) mins = fminf(mins, nrm1[c]);
+                    else sumn += nrm1[c];
+                }
+                pkey[1] = mins > sumn ? 1ull : 0ull;
+            }
+            __syncthreads();
+            if (pkey[1] != 0ull) {
                 converged = true;
+                sub_done = true;
                 break;
             }
+            phase = 2;
         }
         if (my_rot) atomicAdd(&rot_total, my_rot);
         // back to the plain layout
@@ -626,42 +893,144 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         }
         __syncthreads();
 
-        // ---- 5. sigma_c = |w_c| (scaled back); U_R = W Sigma^-1 extended by the identity on the
-        // null-space columns rk..M-1; stable descending rank of sigma ------------------------------
-        for (int c = g; c < MP && g < NG; c += NG) {
-            float2 x[R];
-            float s = 0.f;
+        if (!sub_done) {
+            // ---- 5. sigma_c = |w_c| (scaled back); U_R = W Sigma^-1 extended by the identity on the
+            // null-space columns rk..M-1; stable descending rank of sigma ------------------------------
+            for (int c = g; c < MP && g < NG; c += NG) {
+                float2 x[R];
+                float s = 0.f;
 #pragma unroll
-            for (int k = 0; k < R; ++k) {
-                x[k] = Bs[at<MP>(c, q + G * k)];
-                s = fmaf(x[k].x, x[k].x, fmaf(x[k].y, x[k].y, s));
-            }
-            s = group_sum<G>(s);
-            if (c < rk) {
-                // X is nonsingular (rank rk), so a zero column means a numerical breakdown
-                const float inv = s > 0.f ? rsqrt_refined(s) : 0.0f;
+                for (int k = 0; k < R; ++k) {
+                    x[k] = Bs[at<MP>(c, q + G * k)];
+                    s = fmaf(x[k].x, x[k].x, fmaf(x[k].y, x[k].y, s));
+                }
+                s = group_sum<G>(s);
+                if (c < rk) {
+                    // X is nonsingular (rank rk), so a zero column means a numerical breakdown
+                    const float inv = s > 0.f ? rsqrt_refined(s) : 0.0f;
 #pragma unroll
-                for (int k = 0; k < R; ++k)
-                    Bs[at<MP>(c, q + G * k)] = make_float2(x[k].x * inv, x[k].y * inv);
-                if (q == 0 && !(s > 0.f)) degen = 1;
-            } else {
+                    for (int k = 0; k < R; ++k)
+                        Bs[at<MP>(c, q + G * k)] = make_float2(x[k].x * inv, x[k].y * inv);
+                    if (q == 0 && !(s > 0.f)) degen = 1;
+                } else {
 #pragma unroll
-                for (int k = 0; k < R; ++k)
-                    Bs[at<MP>(c, q + G * k)] = make_float2((q + G * k == c && c < M) ? 1.f : 0.f, 0.f);
+                    for (int k = 0; k < R; ++k)
+                        Bs[at<MP>(c, q + G * k)] = make_float2((q + G * k == c && c < M) ? 1.f : 0.f, 0.f);
+                }
+                if (q == 0) sig[c] = (c < M) ? ldexpf(sqrtf(s), ex) : -1.0f;
             }
-            if (q == 0) sig[c] = (c < M) ? ldexpf(sqrtf(s), ex) : -1.0f;
-        }
-        for (int c = tid; c < MP; c += NT) perm[c] = c;
-        __syncthreads();
-        if (degen) converged = false;
-        for (int c = tid; c < M; c += NT) {
-            const float sc_ = sig[c];
-            int rank = 0;
-            for (int k = 0; k < M; ++k) {
-                const float sk = sig[k];
-                rank += (sk > sc_ || (sk == sc_ && k < c)) ? 1 : 0;
+            for (int c = tid; c < MP; c += NT) perm[c] = c;
+            __syncthreads();
+            if (degen) converged = false;
+            for (int c = tid; c < M; c += NT) {
+                const float sc_ = sig[c];
+                int rank = 0;
+                for (int k = 0; k < M; ++k) {
+                    const float sk = sig[k];
+                    rank += (sk > sc_ || (sk == sc_ && k < c)) ? 1 : 0;
+                }
+                if (rank < M) perm[rank] = c;
             }
-            if (rank < M) perm[rank] = c;
+        } else {
+            // ---- 5'. noise subspace: the orthogonal complement of X_S -------------------------
+            // Householder QR of the Ns columns of S (wave 0, one row per lane; S in ascending
+            // column order, listed in cinv): reflector k (rows k..rk-1) is stored in S's k-th
+            // slot and its tau in diag1[k].x.  Every other column c < rk takes the complement
+            // vector H_0 .. H_{Ns-1} e_kc (kc = Ns + its position among the non-S columns), an
+            // orthonormal basis of the complement of span X_S; columns rk.. stay the identity
+            // (null space).  The S slots are not used further (E_n excludes them).
+            if (tid < 64) {
+                const int r = tid;
+                float2 col[kSubMaxNs];
+                int sl[kSubMaxNs];
+#pragma unroll
+                for (int j = 0; j < kSubMaxNs; ++j) sl[j] = 0;
+                {
+                    int k = 0;
+                    for (int c = 0; c < rk; ++c)
+                        if ((smask >> c) & 1ull) {
+#pragma unroll
+                            for (int j = 0; j < kSubMaxNs; ++j)
+                                if (j == k) sl[j] = c;
+                            ++k;
+                        }
+                }
+#pragma unroll
+                for (int k = 0; k < kSubMaxNs; ++k)
+                    col[k] = (k < Ns && r < MP) ? Bs[at<MP>(sl[k], r)] : make_float2(0.f, 0.f);
+#pragma unroll
+                for (int k = 0; k < kSubMaxNs; ++k) {
+                    if (k >= Ns) break;
+                    const float2 x = col[k];
+                    const float a2 = wave_sum((r >= k && r < rk) ? fmaf(x.x, x.x, x.y * x.y) : 0.f);
+                    const float xr = __shfl(x.x, k), xi = __shfl(x.y, k);
+                    const float nx = sqrtf(a2);
+                    const float axk = sqrtf(fmaf(xr, xr, xi * xi));
+                    const float rax = axk > 0.f ? __builtin_amdgcn_rcpf(axk) : 0.f;
+                    const float2 ph = axk > 0.f ? make_float2(xr * rax, xi * rax) : make_float2(1.f, 0.f);
+                    const float tk = nx > 0.f ? __builtin_amdgcn_rcpf(nx * (nx + axk)) : 0.0f;
+                    const float2 vk = make_float2(ph.x * (axk + nx), ph.y * (axk + nx));
+                    const float2 v = (r > k && r < rk) ? x : ((r == k) ? vk : make_float2(0.f, 0.f));
+                    if (r < MP) Bs[at<MP>(sl[k], r)] = v;
+                    if (r == 0) {
+                        diag1[k] = make_float2(tk, 0.f);
+                        cinv[k] = sl[k];
+                    }
+#pragma unroll
+                    for (int j = 0; j < kSubMaxNs; ++j) {
+                        if (j <= k || j >= Ns) continue;
+                        const float2 y = col[j];
+                        float wr = wave_sum(fmaf(v.x, y.x, v.y * y.y));       // conj(v) y
+                        float wi = wave_sum(fmaf(v.x, y.y, -v.y * y.x));
+                        wr *= tk;
+                        wi *= tk;
+                        col[j] = make_float2(y.x - fmaf(v.x, wr, -v.y * wi),
+                                             y.y - fmaf(v.x, wi, v.y * wr));
+                    }
+                }
+            }
+            __syncthreads();
+            for (int c = g; c < MP && g < NG; c += NG) {
+                if (c < rk && ((smask >> c) & 1ull)) continue;
+                float2 z[R];
+                if (c < rk) {
+                    const int kc = Ns + c - __popcll(smask & ((1ull << c) - 1ull));
+#pragma unroll
+                    for (int j = 0; j < R; ++j)
+                        z[j] = make_float2(q + G * j == kc ? 1.f : 0.f, 0.f);
+                    for (int k = Ns - 1; k >= 0; --k) {
+                        const int sc = cinv[k];
+                        const float tk = diag1[k].x;
+                        float2 v[R];
+                        float wr = 0.f, wi = 0.f;
+#pragma unroll
+                        for (int j = 0; j < R; ++j) {
+                            v[j] = Bs[at<MP>(sc, q + G * j)];
+                            wr = fmaf(v[j].x, z[j].x, fmaf(v[j].y, z[j].y, wr));
+                            wi = fmaf(v[j].x, z[j].y, fmaf(-v[j].y, z[j].x, wi));
+                        }
+                        wr = group_sum<G>(wr) * tk;
+                        wi = group_sum<G>(wi) * tk;
+#pragma unroll
+                        for (int j = 0; j < R; ++j) {
+                            z[j].x = fmaf(-v[j].x, wr, fmaf(v[j].y, wi, z[j].x));
+                            z[j].y = fmaf(-v[j].x, wi, fmaf(-v[j].y, wr, z[j].y));
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < R; ++j)
+                        z[j] = make_float2((q + G * j == c && c < M) ? 1.f : 0.f, 0.f);
+                }
+#pragma unroll
+                for (int j = 0; j < R; ++j) Bs[at<MP>(c, q + G * j)] = z[j];
+            }
+            for (int c = tid; c < M; c += NT) {
+                const int below = __popcll(smask & ((1ull << c) - 1ull));
+                if (c < rk && ((smask >> c) & 1ull)) perm[below] = c;
+                else perm[Ns + c - below] = c;
+            }
+            __syncthreads();
         }
         // ---- 6. U = Q U_R, reflectors applied last to first ----------------------------------
         // U's columns move to registers (a group owns at most two: c = g, g + NG), the reflectors
@@ -748,13 +1117,13 @@ template <int MP, int G>
 __global__ __launch_bounds__((JacobiCfg<MP, G>::THREADS)) void jacobi_svd(
     float2 *__restrict__ A, const int32_t *__restrict__ kstatus, int M, int Ns, int max_sweeps,
     float2 *__restrict__ En, float *__restrict__ sigma, int32_t *__restrict__ bin_status,
-    int32_t *__restrict__ conv, float2 *__restrict__ U)
+    int32_t *__restrict__ conv, float2 *__restrict__ U, int sub_full)
 {
     const int f = blockIdx.x;
     jacobi_bin<MP, G>(A + (size_t)f * M * M, kstatus ? kstatus[f] : SSL_BIN_OK, M, Ns, max_sweeps,
                       En + (size_t)f * (M - Ns) * M, sigma ? sigma + (size_t)f * M : nullptr,
                       bin_status ? bin_status + f : nullptr, conv ? conv + 3 * f : nullptr,
-                      U ? U + (size_t)f * M * M : nullptr);
+                      U ? U + (size_t)f * M * M : nullptr, sub_full);
 }
 
 // Persistent: a fixed grid of workgroups draws (block, bin) items from a device counter until the
@@ -765,7 +1134,7 @@ template <int MP, int G>
 __global__ __launch_bounds__((JacobiCfg<MP, G>::THREADS))
 __attribute__((amdgpu_waves_per_eu(JacobiCfg<MP, G>::WAVES_PER_EU))) void jacobi_persistent(
     const BlockDev *__restrict__ blk, const int2 *__restrict__ items, int n_items,
-    int max_sweeps, unsigned int *__restrict__ queue)
+    int max_sweeps, unsigned int *__restrict__ queue, int sub_full)
 {
     __shared__ int item_s;
     for (;;) {
@@ -783,7 +1152,7 @@ __attribute__((amdgpu_waves_per_eu(JacobiCfg<MP, G>::WAVES_PER_EU))) void jacobi
         const int f = w.y, M = B.M, Ns = B.Ns;
         jacobi_bin<MP, G>(B.A + (size_t)f * M * M, B.kstatus ? B.kstatus[f] : SSL_BIN_OK, M, Ns,
                           max_sweeps, B.En + (size_t)f * (M - Ns) * M, nullptr, B.status + f,
-                          nullptr);
+                          nullptr, nullptr, B.p == 2 ? sub_full : -1);
     }
 }
 
@@ -1039,21 +1408,21 @@ __global__ __launch_bounds__((JacobiCfg<MP, G>::THREADS)) void jacobi_warm(
 template <int MP, int G>
 hipError_t launch_cfg(ssl_c64 *A, const int32_t *kstatus, int F, int M, int Ns, int max_sweeps,
                       ssl_c64 *En, float *sigma, int32_t *bin_status, int32_t *conv, ssl_c64 *U,
-                      hipStream_t st)
+                      int sub_full, hipStream_t st)
 {
     hipLaunchKernelGGL((jacobi_svd<MP, G>), dim3(F), dim3(JacobiCfg<MP, G>::THREADS), 0, st,
                        reinterpret_cast<float2 *>(A), kstatus, M, Ns, max_sweeps,
                        reinterpret_cast<float2 *>(En), sigma, bin_status, conv,
-                       reinterpret_cast<float2 *>(U));
+                       reinterpret_cast<float2 *>(U), sub_full);
     return hipGetLastError();
 }
 
 template <int MP, int G>
 hipError_t launch_persistent(const BlockDev *blk, const int2 *items, int n_items, int max_sweeps,
-                             unsigned int *queue, int grid, hipStream_t st)
+                             unsigned int *queue, int grid, int sub_full, hipStream_t st)
 {
     hipLaunchKernelGGL((jacobi_persistent<MP, G>), dim3(grid), dim3(JacobiCfg<MP, G>::THREADS), 0,
-                       st, blk, items, n_items, max_sweeps, queue);
+                       st, blk, items, n_items, max_sweeps, queue, sub_full);
     return hipGetLastError();
 }
 
@@ -1117,12 +1486,12 @@ int jacobi_persistent_wg_per_cu(int cls, int lanes)
 
 hipError_t launch_jacobi(ssl_c64 *A, const int32_t *kstatus, int F, int M, int Ns, int max_sweeps,
                          int lanes, ssl_c64 *En, float *sigma, int32_t *bin_status, int32_t *conv,
-                         hipStream_t st, ssl_c64 *U)
+                         hipStream_t st, ssl_c64 *U, int sub_full)
 {
     hipError_t e = hipErrorInvalidValue;
     dispatch(jacobi_class(M), lanes, [&]<int MP, int G>() {
         e = launch_cfg<MP, G>(A, kstatus, F, M, Ns, max_sweeps, En, sigma, bin_status, conv, U,
-                              st);
+                              sub_full, st);
     });
     return e;
 }
@@ -1156,12 +1525,12 @@ hipError_t launch_jacobi_warm(const ssl_c64 *A, const int32_t *kstatus, int F, i
 
 hipError_t launch_jacobi_batch(const BlockDev *blk, const int2 *items, int n_items, int cls,
                                int lanes, int max_sweeps, unsigned int *queue, int grid,
-                               hipStream_t st)
+                               hipStream_t st, int sub_full)
 {
     if (n_items <= 0) return hipSuccess;
     hipError_t e = hipErrorInvalidValue;
     dispatch(cls, lanes, [&]<int MP, int G>() {
-        e = launch_persistent<MP, G>(blk, items, n_items, max_sweeps, queue, grid, st);
+        e = launch_persistent<MP, G>(blk, items, n_items, max_sweeps, queue, grid, sub_full, st);
     });
     return e;
 }

@@ -58,6 +58,7 @@ struct ssl_ctx_s {
     int svd = SSL_SVD_JACOBI;
     // subspace method for calls with a noise handle (ssl_ctx_set_subspace)
     int subspace = SSL_SUBSPACE_GSVD;
+    int sub_stop = SSL_STOP_LOCALIZE;   // ssl_stop: where the Jacobi solve may stop at the subspace
     // Jacobi variant (lanes per column pair) per size class 8/16/32/64 channels
     int jac_lanes[4] = {8, 8, 8, 8};     // lanes per Jacobi column pair, classes 8/16/32/64
     // waves per projection workgroup, [steer class 1/2/4][SSL_FP32, SSL_BF16, SSL_FP16]
@@ -164,9 +165,10 @@ hipError_t launch_whiten_batch(const BlockDev *blk, const int2 *items, int n_ite
                                const int2 *chunks, const int *cblocks, int cls, hipStream_t st);
 int whiten_wg_per_cu(int cls);
 // Persistent: `grid` workgroups draw items from *queue (0 on entry, re-armed to 0 on exit).
+// sub_full >= 0: blocks with p = 2 stop once their noise subspace has converged (launch_jacobi).
 hipError_t launch_jacobi_batch(const BlockDev *blk, const int2 *items, int n_items, int cls,
                                int lanes, int max_sweeps, unsigned int *queue, int grid,
-                               hipStream_t st);
+                               hipStream_t st, int sub_full = -1);
 hipError_t launch_steer_batch(const BlockDev *blk, const int2 *items, int n_items,
                               const int2 *groups, const int *gblocks, int cls, int waves,
                               int max_dtiles, ssl_prec hprec, hipStream_t st);
@@ -222,10 +224,14 @@ inline int noise_class(int M) { return M <= 16 ? 16 : M <= 32 ? 32 : 64; }
 // lanes = lanes per column pair of the Jacobi variant (jacobi_variant_ok).
 // U (optional): all M sorted left singular vectors, [F][M][M] column-major per bin (identity for
 // a failed bin) -- the start of a warm-started solve (launch_jacobi_warm).
+// sub_full >= 0 (with sigma and U null, 1 <= Ns <= 8): E_n is an orthonormal basis of the noise
+// subspace, the solve stopping once that subspace has converged after sub_full full sweeps.
 hipError_t launch_jacobi(ssl_c64 *A, const int32_t *kstatus, int F, int M, int Ns,
                          int max_sweeps, int lanes, ssl_c64 *En, float *sigma,
                          int32_t *bin_status, int32_t *conv, hipStream_t st,
-                         ssl_c64 *U = nullptr);
+                         ssl_c64 *U = nullptr, int sub_full = -1);
+// Full sweeps before the subspace phase of the localization paths (p = 2).
+constexpr int kSubFullSweeps = 1;
 // Warm-started solve: U [F][M][M] (column-major per bin) holds a unitary start on entry (the
 // previous solve's sorted singular vectors) and this solve's on exit; A is read only.
 hipError_t launch_jacobi_warm(const ssl_c64 *A, const int32_t *kstatus, int F, int M, int Ns,

@@ -66,7 +66,13 @@ def steps_P(S, ctx, X, noise, Hd, prec, w):
     S.ssl_corr_accum(ctx, to_dev(X), 1.0 / X.shape[1], 0, prec, R)
     En = torch.zeros((F, M - Ns, M), dtype=torch.complex64, device="cuda:0")
     st = torch.zeros(F, dtype=torch.int32, device="cuda:0")
-    S.ssl_gsvd(ctx, R, noise, Ns, En, None, st, None, 0)
+    # the localization stops the Jacobi solve at the noise subspace (p = 2): so does ssl_gsvd
+    # without sigma under SSL_STOP_ALSO_GSVD, the same kernel on the same bytes
+    S.ssl_ctx_set_stop(ctx, S.SSL_STOP_ALSO_GSVD)
+    try:
+        S.ssl_gsvd(ctx, R, noise, Ns, En, None, st, None, 0)
+    finally:
+        S.ssl_ctx_set_stop(ctx, S.SSL_STOP_LOCALIZE)
     P = torch.zeros((F, D), dtype=torch.float32, device="cuda:0")
     Pbar = torch.zeros(D, dtype=torch.float32, device="cuda:0")
     S.ssl_music_spectrum(ctx, Hd, prec, En, Ns, 2, P, Pbar, st)
