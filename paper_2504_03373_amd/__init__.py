@@ -26,6 +26,8 @@ SSL_SVD_JACOBI, SSL_SVD_BIDIAG_QR = 0, 1
 SSL_SUBSPACE_GSVD, SSL_SUBSPACE_GEVD = 0, 1
 # ssl_stop
 SSL_STOP_NEVER, SSL_STOP_BATCH, SSL_STOP_LOCALIZE, SSL_STOP_ALSO_GSVD = 0, 1, 2, 3
+# ssl_projection
+SSL_PROJ_NOISE, SSL_PROJ_SIGNAL = 0, 1
 # fixed scratch of ssl_localize_noalloc (bytes, per device)
 SSL_NOALLOC_SCRATCH_BYTES = 64 << 20
 
@@ -43,7 +45,7 @@ EXPORTED = [
     "ssl_sliding_create", "ssl_sliding_destroy", "ssl_sliding_push", "ssl_sliding_frames",
     "ssl_sliding_corr", "ssl_sliding_localize", "ssl_ctx_set_svd", "ssl_ctx_get_svd",
     "ssl_ctx_set_subspace", "ssl_ctx_get_subspace", "ssl_noise_enable_gevd",
-    "ssl_ctx_set_stop", "ssl_ctx_get_stop",
+    "ssl_ctx_set_stop", "ssl_ctx_get_stop", "ssl_ctx_set_projection", "ssl_ctx_get_projection",
 ]
 
 
@@ -110,6 +112,8 @@ def lib() -> ctypes.CDLL:
         "ssl_noise_enable_gevd": (I, [P, P]),
         "ssl_ctx_set_stop": (I, [P, I]),
         "ssl_ctx_get_stop": (I, [P]),
+        "ssl_ctx_set_projection": (I, [P, I]),
+        "ssl_ctx_get_projection": (I, [P]),
         "ssl_sliding_create": (I, [P, I, I, I, ctypes.POINTER(P)]),
         "ssl_sliding_destroy": (None, [P]),
         "ssl_sliding_push": (I, [P, P, I, I64, I64, P]),
@@ -261,6 +265,14 @@ def ssl_ctx_set_stop(ctx, mode: int) -> None:
 
 def ssl_ctx_get_stop(ctx) -> int:
     return int(lib().ssl_ctx_get_stop(ctx))
+
+
+def ssl_ctx_set_projection(ctx, mode: int) -> None:
+    _check("ssl_ctx_set_projection", lib().ssl_ctx_set_projection(ctx, mode))
+
+
+def ssl_ctx_get_projection(ctx) -> int:
+    return int(lib().ssl_ctx_get_projection(ctx))
 
 
 def ssl_noise_enable_gevd(noise, stream=None) -> None:

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libssl_mi355x.so")
-SOURCES = ["abi.hip", "corr.hip", "noise.hip", "jacobi.hip", "steer.hip", "peaks.hip", "stft.hip", "tf.hip", "sliding.hip", "bidiag.hip", "gevd.hip"]
+SOURCES = ["abi.hip", "corr.hip", "noise.hip", "jacobi.hip", "steer.hip", "peaks.hip", "stft.hip", "tf.hip", "sliding.hip", "bidiag.hip", "gevd.hip", "steer_sig.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -146,16 +146,26 @@ int gk_max_steps(int M) { return 40 * M; }
 // bidiagonal one reads it only); U (Jacobi only) receives all sorted singular vectors.
 hipError_t launch_svd(ssl_ctx ctx, ssl_c64 *A, const int32_t *kst, int F, int M, int Ns,
                       int max_sweeps, ssl_c64 *En, float *sigma, int32_t *stt, int32_t *conv,
-                      hipStream_t st, ssl_c64 *U = nullptr, int sub_full = -1)
+                      hipStream_t st, ssl_c64 *U = nullptr, int sub_full = -1,
+                      ssl_c64 *Es = nullptr, ssl_c128 *Esl = nullptr)
 {
     if (ctx->svd == SSL_SVD_BIDIAG_QR)
         return launch_gk_svd(A, kst, F, M, Ns, gk_max_steps(M), En, sigma, stt, conv, st);
     return launch_jacobi(A, kst, F, M, Ns, max_sweeps, jac_lanes(ctx, M), En, sigma, stt, conv, st,
-                         U, sub_full);
+                         U, sub_full, Es, Esl);
 }
 // Whether a localization path stops the Jacobi solve at the noise subspace (p = 2: eq.5 reads only
 // its projector): the batched path from SSL_STOP_BATCH on, the one-block paths from
 // SSL_STOP_LOCALIZE on.
+// Whether eq.5 is evaluated through the signal subspace (FP64, steer_sig.hip): the FP32 path with
+// p = 2, the Jacobi backend, GSVD or SEVD (U unitary), Ns <= 3, unless the context asks for the
+// noise-vector projection.
+bool use_sig(ssl_ctx ctx, ssl_prec prec, int p, int Ns, bool gevd)
+{
+    return ctx->proj == SSL_PROJ_SIGNAL && prec == SSL_FP32 && p == 2 &&
+           ctx->svd == SSL_SVD_JACOBI && !gevd && Ns >= 1 && Ns <= 3;
+}
+
 int sub_full_for(ssl_ctx ctx, int p, bool batched)
 {
     const int need = batched ? SSL_STOP_BATCH : SSL_STOP_LOCALIZE;
@@ -267,7 +277,8 @@ ssl_status check_localize(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int M, in
 // Workspace of one block's path: R | A | En | P | Pbar | status, then (scratch only) the bin-sum
 // partials [chunks][D].
 struct LocalizeWs {
-    size_t bR, bE, bP, bB, bS, total, with_part;
+    size_t bR, bE, bP, bB, bS, bEs, bEl, total, with_part;
+    size_t off_es() const { return 2 * bR + bE + bP + bB + bS; }
 };
 
 LocalizeWs localize_ws(int F, int M, int Ns, int D)
@@ -278,7 +289,9 @@ LocalizeWs localize_ws(int F, int M, int Ns, int D)
     L.bP = align256((size_t)F * D * sizeof(float));
     L.bB = align256((size_t)D * sizeof(float));
     L.bS = align256((size_t)F * sizeof(int32_t));
-    L.total = 2 * L.bR + L.bE + L.bP + L.bB + L.bS;
+    L.bEs = align256((size_t)F * Ns * M * sizeof(ssl_c64));          // signal vectors
+    L.bEl = align256((size_t)F * 6 * sizeof(ssl_c128));              // their L^{-1}
+    L.total = 2 * L.bR + L.bE + L.bP + L.bB + L.bS + L.bEs + L.bEl;
     const size_t nch = (size_t)(F + SSL_BINSUM_CHUNK - 1) / SSL_BINSUM_CHUNK;
     L.with_part = L.total + align256(nch * (size_t)D * sizeof(float));
     return L;
@@ -317,9 +330,12 @@ ssl_status localize_enqueue(ssl_ctx ctx, bool may_time, char *w, const LocalizeW
     } else {
         A = R;                                   // SEVD-MUSIC: the decomposition of R itself
     }
+    const bool sig = use_sig(ctx, prec, p, Ns, gevd);
+    ssl_c64 *Es = sig ? reinterpret_cast<ssl_c64 *>(w + L.off_es()) : nullptr;
+    ssl_c128 *Esl = sig ? reinterpret_cast<ssl_c128 *>(w + L.off_es() + L.bEs) : nullptr;
     e = run(SSL_K_JACOBI, [&] {
         return launch_svd(ctx, A, K ? K->status : nullptr, F, M, Ns, SSL_DEFAULT_SWEEPS, En,
-                          nullptr, stt, nullptr, st, nullptr, sub_full_for(ctx, p, false));
+                          nullptr, stt, nullptr, st, nullptr, sub_full_for(ctx, p, false), Es, Esl);
     });
     if (e != hipSuccess) return hip_fail(e, "jacobi launch");
     if (gevd) {
@@ -327,6 +343,9 @@ ssl_status localize_enqueue(ssl_ctx ctx, bool may_time, char *w, const LocalizeW
         if (e != hipSuccess) return hip_fail(e, "GEVD back-transformation launch");
     }
     e = run(SSL_K_STEER, [&] {
+        if (sig)
+            return launch_steer_sig(static_cast<const ssl_c64 *>(H), Es, Esl, F, D, M, Ns, stt, P,
+                                    st);
         return launch_steer(H, prec, En, F, D, M, Ns, p, stt, P, st_waves(ctx, M, Ns, prec), st);
     });
     if (e != hipSuccess) return hip_fail(e, "steer launch");
@@ -1069,6 +1088,7 @@ int jacobi_queue(int cls) { return cls == 8 ? 0 : cls == 16 ? 1 : cls == 32 ? 2 
 struct Seg {
     int cls, start, count, extra;
     int waves = 0;                         // projection: waves per workgroup
+    bool sig = false;                      // projection: through the signal subspace
 };
 
 // Launch plan of one batch shape: per kernel, contiguous runs of items sharing a size class.
@@ -1076,6 +1096,7 @@ struct Plan {
     std::vector<Seg> corr, whiten, jac, steer;
     int nblocks = 0, n_items = 0, max_dc = 0, max_fc = 0;
     std::vector<Seg> gevd;                 // (block, bin) items of GEVD-MUSIC blocks, by class
+    int nsmax = 1;                         // largest Ns of the blocks projected by steer_sig
 };
 
 // Device tail of the descriptor buffer after the four item lists: steering groups (first, count)
@@ -1227,6 +1248,9 @@ hipError_t enqueue_batch(ssl_ctx ctx, const Plan &P, const BlockDev *blk, const 
     }
     for (const Seg &s : P.steer) {
         e = timed(ctx, SSL_K_STEER, st, [&] {
+            if (s.sig)
+                return launch_steer_sig_batch(blk, l_st + s.start, s.count, ga.groups, ga.gblocks,
+                                              s.extra, P.nsmax, st);
             return launch_steer_batch(blk, l_st + s.start, s.count, ga.groups, ga.gblocks, s.cls,
                                       s.waves, s.extra, prec, st);
         });
@@ -1541,6 +1565,22 @@ ssl_status ssl_ctx_set_stop(ssl_ctx ctx, ssl_stop mode)
 
 int ssl_ctx_get_stop(ssl_ctx ctx) { return ctx ? ctx->sub_stop : -1; }
 
+ssl_status ssl_ctx_set_projection(ssl_ctx ctx, ssl_projection mode)
+{
+    if (!ctx) {
+        ssl_set_error("ctx is NULL");
+        return SSL_ERR_ARG;
+    }
+    if (mode != SSL_PROJ_NOISE && mode != SSL_PROJ_SIGNAL) {
+        ssl_set_error("unknown projection %d", (int)mode);
+        return SSL_ERR_ARG;
+    }
+    ctx->proj = mode;
+    return SSL_OK;
+}
+
+int ssl_ctx_get_projection(ssl_ctx ctx) { return ctx ? ctx->proj : -1; }
+
 ssl_status ssl_ctx_use_graphs(ssl_ctx ctx, int enable)
 {
     if (!ctx) {
@@ -1573,6 +1613,8 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
     ssl_status s;
     size_t ws_total = 0;
     int64_t n_items = 0;
+    std::vector<char> sigb(nblocks);        // block projected through the signal subspace
+    int nsmax = 1;
     std::vector<int64_t> key;
     key.reserve(10 + 6 * (size_t)nblocks);
     key.push_back(nblocks);
@@ -1581,6 +1623,7 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
     for (int i = 0; i < 4; ++i) key.push_back(ctx->jac_lanes[i]);   // kernel variants captured
     key.push_back(ctx->svd);
     key.push_back(ctx->sub_stop);
+    key.push_back(ctx->proj);
     for (int c = 0; c < 3; ++c) key.push_back(ctx->steer_waves[c][prec]);
     for (int b = 0; b < nblocks; ++b) {
         const ssl_block_desc &d = descs[b];
@@ -1607,11 +1650,15 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
             return s;
         }
         key.push_back(d.K ? (use_gevd(ctx, d.K) ? 2 : 1) : 0);
+        sigb[b] = use_sig(ctx, prec, p, d.Ns, use_gevd(ctx, d.K)) ? 1 : 0;
+        if (sigb[b]) nsmax = std::max(nsmax, d.Ns);
+        key.push_back(sigb[b]);
         const size_t F = d.F, M = d.M, D = (size_t)d.n_az * d.n_el, Nn = d.M - d.Ns;
         const size_t nch = (F + SSL_BINSUM_CHUNK - 1) / SSL_BINSUM_CHUNK;
         ws_total += 2 * align256(F * M * M * sizeof(ssl_c64)) + align256(F * Nn * M * sizeof(ssl_c64)) +
                     align256(F * D * sizeof(float)) + align256(nch * D * sizeof(float)) +
-                    align256(F * sizeof(int32_t)) + align256(D * sizeof(float));
+                    align256(F * sizeof(int32_t)) + align256(D * sizeof(float)) +
+                    align256(F * d.Ns * M * sizeof(ssl_c64)) + align256(F * 6 * sizeof(ssl_c128));
         n_items += d.F;
         key.push_back(d.F);
         key.push_back(d.T);
@@ -1624,6 +1671,7 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
         ssl_set_error("batch too large");
         return SSL_ERR_ARG;
     }
+    key.push_back(nsmax);
     DeviceGuard dg(ctx->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const size_t desc_bytes = align256(sizeof(BlockDev) * nblocks);
@@ -1652,6 +1700,7 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
     Plan plan;
     plan.nblocks = nblocks;
     plan.n_items = (int)n_items;
+    plan.nsmax = nsmax;
     std::vector<int> c_corr(nblocks), c_wh(nblocks), c_jac(nblocks), c_st(nblocks), Fs(nblocks);
     char *w = static_cast<char *>(ctx->ws);
     for (int b = 0; b < nblocks; ++b) {
@@ -1690,6 +1739,10 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
         w += align256(F * sizeof(int32_t));
         B.Pbar = d.Pbar ? d.Pbar : reinterpret_cast<float *>(w);
         w += align256(D * sizeof(float));
+        B.Es = sigb[b] ? reinterpret_cast<float2 *>(w) : nullptr;
+        w += align256(F * d.Ns * M * sizeof(ssl_c64));
+        B.Esl = sigb[b] ? reinterpret_cast<double2 *>(w) : nullptr;
+        w += align256(F * 6 * sizeof(ssl_c128));
         B.peaks = d.peaks;
         B.peak_val = d.peak_val;
         c_corr[b] = corr_class(d.M);
@@ -1774,11 +1827,11 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
         int *hgb = reinterpret_cast<int *>(hg + 2 * nblocks);
         std::vector<int> first;                       // first block of each group
         std::vector<std::vector<int>> members;
-        std::map<std::tuple<int, const void *, int, int, int>, int> group_of;
+        std::map<std::tuple<int, const void *, int, int, int, int>, int> group_of;
         for (int b = 0; b < nblocks; ++b) {
             const BlockDev &B = hb[b];
-            const auto ins = group_of.emplace(std::make_tuple(c_st[b], B.H, B.F, B.D, B.M),
-                                              (int)first.size());
+            const auto ins = group_of.emplace(
+                std::make_tuple(c_st[b], B.H, B.F, B.D, B.M, (int)sigb[b]), (int)first.size());
             const int g = ins.first->second;
             if (ins.second) {
                 first.push_back(b);
@@ -1797,15 +1850,17 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
         classes.erase(std::unique(classes.begin(), classes.end()), classes.end());
         int2 *out = hl + 3 * n_items;
         int pos = 0;
-        for (int c : classes) {
-            Seg sg{c, pos, 0, 0};
-            for (size_t g = 0; g < members.size(); ++g) {
-                if (c_st[first[g]] != c) continue;
-                for (int f = 0; f < hb[first[g]].F; ++f) out[pos++] = make_int2((int)g, f);
+        for (int c : classes)
+            for (int kind = 0; kind < 2; ++kind) {         // noise-vector, then signal-subspace
+                Seg sg{c, pos, 0, 0};
+                sg.sig = kind == 1;
+                for (size_t g = 0; g < members.size(); ++g) {
+                    if (c_st[first[g]] != c || sigb[first[g]] != kind) continue;
+                    for (int f = 0; f < hb[first[g]].F; ++f) out[pos++] = make_int2((int)g, f);
+                }
+                sg.count = pos - sg.start;
+                if (sg.count) plan.steer.push_back(sg);
             }
-            sg.count = pos - sg.start;
-            plan.steer.push_back(sg);
-        }
     }
     for (Seg &sg : plan.jac)
         sg.extra = std::min(sg.count, ctx->cu_count * jacobi_persistent_wg_per_cu(
@@ -1815,7 +1870,8 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
         const int rows = steer_rows_per_block(sg.waves);
         int dt = 0;
         for (int b = 0; b < nblocks; ++b)
-            if (c_st[b] == sg.cls) dt = std::max(dt, (hb[b].D + rows - 1) / rows);
+            if (c_st[b] == sg.cls && sigb[b] == (sg.sig ? 1 : 0))
+                dt = std::max(dt, sg.sig ? steer_sig_tiles(hb[b].D) : (hb[b].D + rows - 1) / rows);
         sg.extra = dt;
     }
 

@@ -285,9 +285,10 @@ __device__ __forceinline__ bool jacobi_pair(float2 *Bs, int ci, int cj, int q, d
     return true;
 }
 
-// Subspace phase limits: signal sets of at most kSubMaxNs columns, at most kSubMaxSweeps sweeps
-// over their pairs before the solve returns to full sweeps.
-constexpr int kSubMaxNs = 8;
+// Subspace phase limits: signal sets of at most kSubMaxNs columns (their complement's reflectors
+// take three LDS arrays that are free by then), at most kSubMaxSweeps sweeps over their pairs
+// before the solve returns to full sweeps.
+constexpr int kSubMaxNs = 3;
 constexpr int kSubMaxSweeps = 4;
 
 // |x_c|^2 of the columns c < rk (sweep layout) into nrm[c], one lane group per column.
@@ -444,13 +445,20 @@ __device__ __forceinline__ float wave_sum(float v)
 // convf = (sweeps, rotations, numerical rank) or null.  sub_full >= 0 (only with sigf and Uf
 // null, 1 <= Ns <= kSubMaxNs) asks for the noise subspace alone: E_n is then an orthonormal basis
 // of the span of the M - Ns smallest left singular vectors (what eq.5 with p = 2 depends on), not
-// the singular vectors themselves; see the subspace phase below.
+// the singular vectors themselves; see the subspace phase below.  Esf ([Ns][M], or null) receives
+// the signal vectors: the Ns leading sorted singular vectors, or with the subspace stop an
+// orthonormal basis of their span (the normalised signal columns).  Lf ([6], with Esf, Ns <= 3,
+// or null): the inverse L^{-1} of the Cholesky factor of their Gram matrix E_s^H E_s, computed in
+// FP64 from the stored complex64 values, lower triangle by rows (00, 10, 11, 20, 21, 22), zero if
+// the bin failed: the projector onto span E_s is E_s (E_s^H E_s)^{-1} E_s^H exactly.
 template <int MP, int G>
 __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int M, int Ns,
                                            int max_sweeps, float2 *__restrict__ Enf,
                                            float *__restrict__ sigf, int32_t *__restrict__ stf,
                                            int32_t *__restrict__ convf,
-                                           float2 *__restrict__ Uf = nullptr, int sub_full = -1)
+                                           float2 *__restrict__ Uf = nullptr, int sub_full = -1,
+                                           float2 *__restrict__ Esf = nullptr,
+                                           double2 *__restrict__ Lf = nullptr)
 {
     typedef JacobiCfg<MP, G> C;
     constexpr int R = C::R;
@@ -934,11 +942,13 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         } else {
             // ---- 5'. noise subspace: the orthogonal complement of X_S -------------------------
             // Householder QR of the Ns columns of S (wave 0, one row per lane; S in ascending
-            // column order, listed in cinv): reflector k (rows k..rk-1) is stored in S's k-th
-            // slot and its tau in diag1[k].x.  Every other column c < rk takes the complement
-            // vector H_0 .. H_{Ns-1} e_kc (kc = Ns + its position among the non-S columns), an
-            // orthonormal basis of the complement of span X_S; columns rk.. stay the identity
-            // (null space).  The S slots are not used further (E_n excludes them).
+            // column order, listed in cinv): reflector k (rows k..rk-1) goes to the k-th of the
+            // arrays diag, vhead, diag1 (free since the transposes) and its tau to sig[k]; the S
+            // columns themselves are normalised in place (the signal vectors).  Every other
+            // column c < rk takes the complement vector H_0 .. H_{Ns-1} e_kc (kc = Ns + its
+            // position among the non-S columns), an orthonormal basis of the complement of
+            // span X_S; columns rk.. stay the identity (null space).
+            float2 *refl[kSubMaxNs] = {diag, vhead, diag1};
             if (tid < 64) {
                 const int r = tid;
                 float2 col[kSubMaxNs];
@@ -962,6 +972,14 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                 for (int k = 0; k < kSubMaxNs; ++k) {
                     if (k >= Ns) break;
                     const float2 x = col[k];
+                    const float n2 = wave_sum(fmaf(x.x, x.x, x.y * x.y));
+                    const float inv = n2 > 0.f ? rsqrt_refined(n2) : 0.0f;
+                    if (r < MP) Bs[at<MP>(sl[k], r)] = make_float2(x.x * inv, x.y * inv);
+                }
+#pragma unroll
+                for (int k = 0; k < kSubMaxNs; ++k) {
+                    if (k >= Ns) break;
+                    const float2 x = col[k];
                     const float a2 = wave_sum((r >= k && r < rk) ? fmaf(x.x, x.x, x.y * x.y) : 0.f);
                     const float xr = __shfl(x.x, k), xi = __shfl(x.y, k);
                     const float nx = sqrtf(a2);
@@ -971,9 +989,9 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                     const float tk = nx > 0.f ? __builtin_amdgcn_rcpf(nx * (nx + axk)) : 0.0f;
                     const float2 vk = make_float2(ph.x * (axk + nx), ph.y * (axk + nx));
                     const float2 v = (r > k && r < rk) ? x : ((r == k) ? vk : make_float2(0.f, 0.f));
-                    if (r < MP) Bs[at<MP>(sl[k], r)] = v;
+                    if (r < MP) refl[k][r] = v;
                     if (r == 0) {
-                        diag1[k] = make_float2(tk, 0.f);
+                        sig[k] = tk;
                         cinv[k] = sl[k];
                     }
 #pragma unroll
@@ -998,14 +1016,16 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
 #pragma unroll
                     for (int j = 0; j < R; ++j)
                         z[j] = make_float2(q + G * j == kc ? 1.f : 0.f, 0.f);
-                    for (int k = Ns - 1; k >= 0; --k) {
-                        const int sc = cinv[k];
-                        const float tk = diag1[k].x;
+#pragma unroll
+                    for (int k = kSubMaxNs - 1; k >= 0; --k) {
+                        if (k >= Ns) continue;
+                        const float2 *vk = refl[k];
+                        const float tk = sig[k];
                         float2 v[R];
                         float wr = 0.f, wi = 0.f;
 #pragma unroll
                         for (int j = 0; j < R; ++j) {
-                            v[j] = Bs[at<MP>(sc, q + G * j)];
+                            v[j] = vk[q + G * j];
                             wr = fmaf(v[j].x, z[j].x, fmaf(v[j].y, z[j].y, wr));
                             wi = fmaf(v[j].x, z[j].y, fmaf(-v[j].y, z[j].x, wi));
                         }
@@ -1094,6 +1114,83 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         const int c = e / MP, r = e % MP;
         if (r < M) Enf[c * M + r] = ok ? X[at<MP>(perm[Ns + c], r)] : make_float2(0.f, 0.f);
     }
+    if (Esf != nullptr)                                    // the signal vectors, [Ns][M]
+        for (int e = tid; e < Ns * MP; e += NT) {
+            const int c = e / MP, r = e % MP;
+            if (r < M) Esf[c * M + r] = ok ? X[at<MP>(perm[c], r)] : make_float2(0.f, 0.f);
+        }
+    if (Esf != nullptr && Lf != nullptr && Ns <= 3 && tid < 64) {
+        // Gram matrix of the stored signal vectors in FP64 (wave 0, one row per lane), then the
+        // inverse of its Cholesky factor on lane 0
+        const int r = tid;
+        double2 e[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float2 v = (ok && k < Ns && r < M) ? X[at<MP>(perm[k], r)] : make_float2(0.f, 0.f);
+            e[k] = make_double2(v.x, v.y);
+        }
+        double gr[6], gi[6];                       // Gamma_st = e_s^H e_t, index t (t + 1) / 2 + s
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+#pragma unroll
+            for (int s2 = 0; s2 <= t; ++s2) {
+                const int i = t * (t + 1) / 2 + s2;
+                double a = fma(e[s2].x, e[t].x, e[s2].y * e[t].y);
+                double b = fma(e[s2].x, e[t].y, -e[s2].y * e[t].x);
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    a += __shfl_xor(a, o);
+                    b += __shfl_xor(b, o);
+                }
+                gr[i] = a;
+                gi[i] = b;
+            }
+        if (r == 0) {
+            double2 out[6];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) out[i] = make_double2(0.0, 0.0);
+            // Gamma = L L^H: L_t0 = conj(Gamma_0t) / L00, ... (lower rows t, columns s)
+            const double l00 = sqrt(gr[0]);
+            bool pd = ok && gr[0] > 0.0;
+            double2 l10 = make_double2(0.0, 0.0), l20 = l10, l21 = l10;
+            double l11 = 1.0, l22 = 1.0;
+            if (Ns >= 2 && pd) {
+                l10 = make_double2(gr[1] / l00, -gi[1] / l00);
+                const double d = gr[2] - (l10.x * l10.x + l10.y * l10.y);
+                pd = d > 0.0;
+                l11 = sqrt(fmax(d, 0.0));
+            }
+            if (Ns >= 3 && pd) {
+                l20 = make_double2(gr[3] / l00, -gi[3] / l00);
+                // Gamma_21 = conj(Gamma_12) minus L20 conj(L10), over L11
+                const double2 g21 = make_double2(gr[4], -gi[4]);
+                const double2 t21 = make_double2(g21.x - (l20.x * l10.x + l20.y * l10.y),
+                                                 g21.y - (l20.y * l10.x - l20.x * l10.y));
+                l21 = make_double2(t21.x / l11, t21.y / l11);
+                const double d = gr[5] - (l20.x * l20.x + l20.y * l20.y) -
+                                 (l21.x * l21.x + l21.y * l21.y);
+                pd = d > 0.0;
+                l22 = sqrt(fmax(d, 0.0));
+            }
+            if (pd) {
+                const double i00 = 1.0 / l00, i11 = 1.0 / l11, i22 = 1.0 / l22;
+                // inverse of the lower triangular L, column by column
+                const double2 i10 = make_double2(-l10.x * i00 * i11, -l10.y * i00 * i11);
+                const double2 i21 = make_double2(-l21.x * i11 * i22, -l21.y * i11 * i22);
+                const double2 s20 = make_double2(l20.x * i00 + (l21.x * i10.x - l21.y * i10.y),
+                                                 l20.y * i00 + (l21.x * i10.y + l21.y * i10.x));
+                const double2 i20 = make_double2(-s20.x * i22, -s20.y * i22);
+                out[0] = make_double2(i00, 0.0);
+                out[1] = i10;
+                out[2] = make_double2(i11, 0.0);
+                out[3] = i20;
+                out[4] = i21;
+                out[5] = make_double2(i22, 0.0);
+            }
+#pragma unroll
+            for (int i = 0; i < 6; ++i) Lf[i] = out[i];
+        }
+    }
     if (sigf != nullptr)
         for (int k = tid; k < M; k += NT) sigf[k] = ok ? sig[perm[k]] : 0.0f;
     if (Uf != nullptr)                                     // all M sorted columns (identity if failed)
@@ -1117,13 +1214,15 @@ template <int MP, int G>
 __global__ __launch_bounds__((JacobiCfg<MP, G>::THREADS)) void jacobi_svd(
     float2 *__restrict__ A, const int32_t *__restrict__ kstatus, int M, int Ns, int max_sweeps,
     float2 *__restrict__ En, float *__restrict__ sigma, int32_t *__restrict__ bin_status,
-    int32_t *__restrict__ conv, float2 *__restrict__ U, int sub_full)
+    int32_t *__restrict__ conv, float2 *__restrict__ U, int sub_full, float2 *__restrict__ Es,
+    double2 *__restrict__ Esl)
 {
     const int f = blockIdx.x;
     jacobi_bin<MP, G>(A + (size_t)f * M * M, kstatus ? kstatus[f] : SSL_BIN_OK, M, Ns, max_sweeps,
                       En + (size_t)f * (M - Ns) * M, sigma ? sigma + (size_t)f * M : nullptr,
                       bin_status ? bin_status + f : nullptr, conv ? conv + 3 * f : nullptr,
-                      U ? U + (size_t)f * M * M : nullptr, sub_full);
+                      U ? U + (size_t)f * M * M : nullptr, sub_full,
+                      Es ? Es + (size_t)f * Ns * M : nullptr, Esl ? Esl + 6 * (size_t)f : nullptr);
 }
 
 // Persistent: a fixed grid of workgroups draws (block, bin) items from a device counter until the
@@ -1152,7 +1251,9 @@ __attribute__((amdgpu_waves_per_eu(JacobiCfg<MP, G>::WAVES_PER_EU))) void jacobi
         const int f = w.y, M = B.M, Ns = B.Ns;
         jacobi_bin<MP, G>(B.A + (size_t)f * M * M, B.kstatus ? B.kstatus[f] : SSL_BIN_OK, M, Ns,
                           max_sweeps, B.En + (size_t)f * (M - Ns) * M, nullptr, B.status + f,
-                          nullptr, nullptr, B.p == 2 ? sub_full : -1);
+                          nullptr, nullptr, B.p == 2 ? sub_full : -1,
+                          B.Es ? B.Es + (size_t)f * Ns * M : nullptr,
+                          B.Esl ? B.Esl + 6 * (size_t)f : nullptr);
     }
 }
 
@@ -1408,12 +1509,13 @@ __global__ __launch_bounds__((JacobiCfg<MP, G>::THREADS)) void jacobi_warm(
 template <int MP, int G>
 hipError_t launch_cfg(ssl_c64 *A, const int32_t *kstatus, int F, int M, int Ns, int max_sweeps,
                       ssl_c64 *En, float *sigma, int32_t *bin_status, int32_t *conv, ssl_c64 *U,
-                      int sub_full, hipStream_t st)
+                      int sub_full, ssl_c64 *Es, ssl_c128 *Esl, hipStream_t st)
 {
     hipLaunchKernelGGL((jacobi_svd<MP, G>), dim3(F), dim3(JacobiCfg<MP, G>::THREADS), 0, st,
                        reinterpret_cast<float2 *>(A), kstatus, M, Ns, max_sweeps,
                        reinterpret_cast<float2 *>(En), sigma, bin_status, conv,
-                       reinterpret_cast<float2 *>(U), sub_full);
+                       reinterpret_cast<float2 *>(U), sub_full, reinterpret_cast<float2 *>(Es),
+                       reinterpret_cast<double2 *>(Esl));
     return hipGetLastError();
 }
 
@@ -1486,12 +1588,12 @@ int jacobi_persistent_wg_per_cu(int cls, int lanes)
 
 hipError_t launch_jacobi(ssl_c64 *A, const int32_t *kstatus, int F, int M, int Ns, int max_sweeps,
                          int lanes, ssl_c64 *En, float *sigma, int32_t *bin_status, int32_t *conv,
-                         hipStream_t st, ssl_c64 *U, int sub_full)
+                         hipStream_t st, ssl_c64 *U, int sub_full, ssl_c64 *Es, ssl_c128 *Esl)
 {
     hipError_t e = hipErrorInvalidValue;
     dispatch(jacobi_class(M), lanes, [&]<int MP, int G>() {
         e = launch_cfg<MP, G>(A, kstatus, F, M, Ns, max_sweeps, En, sigma, bin_status, conv, U,
-                              sub_full, st);
+                              sub_full, Es, Esl, st);
     });
     return e;
 }

@@ -59,6 +59,7 @@ struct ssl_ctx_s {
     // subspace method for calls with a noise handle (ssl_ctx_set_subspace)
     int subspace = SSL_SUBSPACE_GSVD;
     int sub_stop = SSL_STOP_LOCALIZE;   // ssl_stop: where the Jacobi solve may stop at the subspace
+    int proj = SSL_PROJ_SIGNAL;         // ssl_projection: form of eq.5 on the FP32 path
     // Jacobi variant (lanes per column pair) per size class 8/16/32/64 channels
     int jac_lanes[4] = {8, 8, 8, 8};     // lanes per Jacobi column pair, classes 8/16/32/64
     // waves per projection workgroup, [steer class 1/2/4][SSL_FP32, SSL_BF16, SSL_FP16]
@@ -108,6 +109,8 @@ struct BlockDev {
     const int32_t *kstatus;
     const void *H;
     float2 *R, *A, *En;             // workspace slices
+    float2 *Es;                     // signal vectors [F][Ns][M] (workspace) or null
+    double2 *Esl;                   // per bin: L^{-1} of their Gram matrix's Cholesky factor, [F][6]
     float *P, *part;
     int32_t *peaks, *status;        // caller outputs
     float *peak_val, *Pbar;
@@ -169,6 +172,15 @@ int whiten_wg_per_cu(int cls);
 hipError_t launch_jacobi_batch(const BlockDev *blk, const int2 *items, int n_items, int cls,
                                int lanes, int max_sweeps, unsigned int *queue, int grid,
                                hipStream_t st, int sub_full = -1);
+// eq.5 (p = 2) through the signal subspace, FP64 (steer_sig.hip): Es [F][Ns][M] and Esl [F][6]
+// from the Jacobi solve, H complex64 [F][D][M], Ns <= 3; direction tiles of steer_sig_tiles(D).
+int steer_sig_tiles(int D);
+hipError_t launch_steer_sig(const ssl_c64 *H, const ssl_c64 *Es, const ssl_c128 *Esl, int F,
+                            int D, int M, int Ns, const int32_t *bin_status, float *P,
+                            hipStream_t st);
+hipError_t launch_steer_sig_batch(const BlockDev *blk, const int2 *items, int n_items,
+                                  const int2 *groups, const int *gblocks, int max_dtiles,
+                                  int nsmax, hipStream_t st);
 hipError_t launch_steer_batch(const BlockDev *blk, const int2 *items, int n_items,
                               const int2 *groups, const int *gblocks, int cls, int waves,
                               int max_dtiles, ssl_prec hprec, hipStream_t st);
@@ -224,12 +236,15 @@ inline int noise_class(int M) { return M <= 16 ? 16 : M <= 32 ? 32 : 64; }
 // lanes = lanes per column pair of the Jacobi variant (jacobi_variant_ok).
 // U (optional): all M sorted left singular vectors, [F][M][M] column-major per bin (identity for
 // a failed bin) -- the start of a warm-started solve (launch_jacobi_warm).
-// sub_full >= 0 (with sigma and U null, 1 <= Ns <= 8): E_n is an orthonormal basis of the noise
+// sub_full >= 0 (with sigma and U null, 1 <= Ns <= 3): E_n is an orthonormal basis of the noise
 // subspace, the solve stopping once that subspace has converged after sub_full full sweeps.
+// Es ([F][Ns][M], optional): the signal vectors; Esl ([F][6], with Es, Ns <= 3): the inverse
+// Cholesky factor of their FP64 Gram matrix (for the signal-subspace form of eq.5).
 hipError_t launch_jacobi(ssl_c64 *A, const int32_t *kstatus, int F, int M, int Ns,
                          int max_sweeps, int lanes, ssl_c64 *En, float *sigma,
                          int32_t *bin_status, int32_t *conv, hipStream_t st,
-                         ssl_c64 *U = nullptr, int sub_full = -1);
+                         ssl_c64 *U = nullptr, int sub_full = -1, ssl_c64 *Es = nullptr,
+                         ssl_c128 *Esl = nullptr);
 // Full sweeps before the subspace phase of the localization paths (p = 2).
 constexpr int kSubFullSweeps = 1;
 // Warm-started solve: U [F][M][M] (column-major per bin) holds a unitary start on entry (the

@@ -1,0 +1,230 @@
+// MUSIC pseudo-spectrum, eq.5 of arXiv 2504.03373 with p = 2, through the signal subspace.
+//
+// With U = [E_s E_n] unitary, sum over the noise vectors of |h^H e|^2 = |h|^2 - |E_s^H h|^2, so the
+// denominator needs the Ns signal vectors instead of the M - Ns noise vectors (2 instead of 58 on
+// the 60-channel workload).  The difference cancels where h lies close to the signal subspace --
+// at the peaks -- so it is formed in FP64 from FP64 products of the stored complex64 inputs, and
+// with the exact projector onto span E_s, E_s (E_s^H E_s)^{-1} E_s^H (the Jacobi solve supplies
+// L^{-1}, L the Cholesky factor of the Gram matrix in FP64), so that the O(2^-24) departure of the
+// stored vectors from orthonormality does not enter:
+//   g = E_s^H h (FP64),   den = |h|^2 - |L^{-1} g|^2,   P = |h|^2 / max(den, FLT_MIN).
+// What remains of the stored vectors' rounding is a rotation of their span, whose effect on den is
+// first order in sqrt(den), as for the noise-vector form (the solver's own subspace error enters
+// both forms the same way).
+//
+// Workgroup = 4 waves x 16 directions of one bin; a wave keeps its 16 rows of H in registers
+// (complex64) and computes g for 16 columns at once on v_mfma_f64_16x16x4f64 -- the signal vectors
+// of 16 / Ns_max blocks sharing the steering table, staged in LDS -- with
+//   Re g = sum a c + b d,   Im g = sum a d - b c     (h = a + ib, e = c + id, FP64 operands).
+// The 16 x 16 result goes through LDS so that each lane finishes whole (direction, block) items.
+#include "ssl_internal.h"
+
+namespace {
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kRows = 16 * kWaves;          // directions per workgroup
+constexpr int kCols = 16;                   // signal vectors per MFMA tile
+constexpr int kKq = SSL_MAX_M / 4;          // k-steps of 4 complex elements at M = 64
+constexpr int kEs = SSL_MAX_M + 2;          // complex64 stride of a staged signal vector
+
+// One workgroup: directions d0 .. d0 + 63 of bin f for nb blocks sharing the table Hf (the bin's
+// [D][M] complex64 rows).  blk(i, Es, L, ns, ok, P) gives block i's signal vectors and L^{-1} of
+// the bin, its Ns, whether the bin is valid, and its P row of the bin.
+template <class BlockAt>
+__device__ __forceinline__ void sig_tile(const float2 *__restrict__ Hf, int D, int M, int d0,
+                                         int nb, int nsmax, BlockAt &&blk)
+{
+    __shared__ float2 Es[kCols * kEs];
+    __shared__ double2 Gs[kWaves][16 * kCols];
+    __shared__ double2 Ls[kCols][6];
+    __shared__ float *Pp[kCols];
+    __shared__ const float2 *Ep[kCols];
+    __shared__ int Nsb[kCols];
+    __shared__ double nrm_s[kRows];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int KQ = (M + 3) >> 2;
+    const int bpt = kCols / nsmax;                           // blocks per tile
+
+    // this lane's A operands: row (lane & 15), complex elements 4 q + (lane >> 4)
+    const int row = d0 + 16 * wave + (lane & 15);
+    const float2 *hrow = Hf + (size_t)(row < D ? row : 0) * M;
+    float2 ha[kKq];
+    double hn = 0.0;
+#pragma unroll
+    for (int q = 0; q < kKq; ++q) {
+        const int m = 4 * q + (lane >> 4);
+        ha[q] = (q < KQ && m < M && row < D) ? gload(hrow + m) : make_float2(0.f, 0.f);
+        hn = fma((double)ha[q].x, (double)ha[q].x, fma((double)ha[q].y, (double)ha[q].y, hn));
+    }
+    hn += __shfl_xor(hn, 16);
+    hn += __shfl_xor(hn, 32);
+    if (lane < 16) nrm_s[16 * wave + lane] = hn;
+
+    for (int b0 = 0; b0 < nb; b0 += bpt) {
+        const int nt = min(bpt, nb - b0);
+        __syncthreads();                                     // the previous tile is finished
+        if (tid < kCols) {
+            const float2 *e;
+            const double2 *L;
+            float *P;
+            int ns = 0;
+            bool ok = false;
+            if (tid < nt) blk(b0 + tid, e, L, ns, ok, P);
+            Nsb[tid] = (tid < nt && ok) ? ns : 0;
+            Pp[tid] = tid < nt ? P : nullptr;
+            Ep[tid] = tid < nt ? e : nullptr;
+            if (tid < nt && ok)
+                for (int i = 0; i < 6; ++i) Ls[tid][i] = gload(L + i);
+        }
+        __syncthreads();
+        // signal vectors: column j = block j / nsmax, vector j % nsmax (zero if absent)
+        for (int x = tid; x < kCols * SSL_MAX_M; x += kThreads) {
+            const int j = x / SSL_MAX_M, m = x - j * SSL_MAX_M;
+            const int bi = j / nsmax, s = j - bi * nsmax;
+            float2 v = make_float2(0.f, 0.f);
+            if (bi < nt && m < M && s < Nsb[bi]) v = gload(Ep[bi] + (size_t)s * M + m);
+            Es[j * kEs + m] = v;
+        }
+        __syncthreads();
+        doublex4 gre = {0.0, 0.0, 0.0, 0.0}, gim = {0.0, 0.0, 0.0, 0.0};
+        const float2 *ecol = Es + (lane & 15) * kEs + (lane >> 4);
+#pragma unroll
+        for (int q = 0; q < kKq; ++q) {
+            if (q < KQ) {                                    // uniform
+                const float2 ev = ecol[4 * q];
+                const double a = ha[q].x, b = ha[q].y, c = ev.x, d = ev.y;
+                gre = __builtin_amdgcn_mfma_f64_16x16x4f64(a, c, gre, 0, 0, 0);
+                gre = __builtin_amdgcn_mfma_f64_16x16x4f64(b, d, gre, 0, 0, 0);
+                gim = __builtin_amdgcn_mfma_f64_16x16x4f64(a, d, gim, 0, 0, 0);
+                gim = __builtin_amdgcn_mfma_f64_16x16x4f64(-b, c, gim, 0, 0, 0);
+            }
+        }
+        // FP64 result layout: element e of lane l is row l / 16 + 4 e, column l % 16
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            Gs[wave][((lane >> 4) + 4 * e) * kCols + (lane & 15)] = make_double2(gre[e], gim[e]);
+        __syncthreads();
+        // items (direction row i of this wave, block bi): den = |h|^2 - |L^{-1} g|^2
+        for (int it = lane; it < 16 * nt; it += 64) {
+            const int i = it / nt, bi = it - i * nt;
+            const int d = d0 + 16 * wave + i;
+            float *P = Pp[bi];
+            if (d >= D || P == nullptr) continue;
+            const int ns = Nsb[bi];
+            const double hh = nrm_s[16 * wave + i];
+            float out = 0.0f;
+            if (ns > 0) {
+                const double2 *g = &Gs[wave][i * kCols + bi * nsmax];
+                const double2 *L = Ls[bi];
+                double2 y0 = make_double2(0.0, 0.0), y1 = y0, y2 = y0;
+                // y = L^{-1} g, L^{-1} lower triangular by rows (00, 10, 11, 20, 21, 22)
+                const double2 g0 = g[0];
+                y0 = make_double2(L[0].x * g0.x, L[0].x * g0.y);
+                double q2 = y0.x * y0.x + y0.y * y0.y;
+                if (ns >= 2) {
+                    const double2 g1 = g[1];
+                    y1 = make_double2(L[1].x * g0.x - L[1].y * g0.y + L[2].x * g1.x,
+                                      L[1].x * g0.y + L[1].y * g0.x + L[2].x * g1.y);
+                    q2 += y1.x * y1.x + y1.y * y1.y;
+                }
+                if (ns >= 3) {
+                    const double2 g1 = g[1], g2 = g[2];
+                    y2 = make_double2(L[3].x * g0.x - L[3].y * g0.y + L[4].x * g1.x -
+                                          L[4].y * g1.y + L[5].x * g2.x,
+                                      L[3].x * g0.y + L[3].y * g0.x + L[4].x * g1.y +
+                                          L[4].y * g1.x + L[5].x * g2.y);
+                    q2 += y2.x * y2.x + y2.y * y2.y;
+                }
+                const double den = fmax(hh - q2, 1.17549435e-38);
+                out = (float)(hh / den);
+            }
+            gstore(P + d, out);
+        }
+    }
+}
+
+// Workgroup -> (item, direction tile), dealt XCD by XCD as in the noise-vector projection.
+constexpr int kXcds = 8;
+__host__ __device__ inline int sig_grid(int n_items, int n_tiles)
+{
+    return kXcds * ((n_items + kXcds - 1) / kXcds) * n_tiles;
+}
+__device__ __forceinline__ bool sig_item(int n_items, int n_tiles, int &item, int &tile)
+{
+    const int w = blockIdx.x;
+    const int slot = w / kXcds;
+    item = (slot / n_tiles) * kXcds + w % kXcds;
+    tile = slot % n_tiles;
+    return item < n_items;
+}
+
+__global__ __launch_bounds__(kThreads) void steer_sig_single(
+    const float2 *__restrict__ H, const float2 *__restrict__ Es, const double2 *__restrict__ Esl,
+    const int32_t *__restrict__ bin_status, int F, int D, int M, int Ns, float *__restrict__ P,
+    int n_tiles)
+{
+    int f, tile;
+    if (!sig_item(F, n_tiles, f, tile)) return;
+    sig_tile(H + (size_t)f * D * M, D, M, tile * kRows, 1, Ns,
+             [&](int, const float2 *&e, const double2 *&L, int &ns, bool &ok, float *&Pf) {
+                 e = Es + (size_t)f * Ns * M;
+                 L = Esl + 6 * (size_t)f;
+                 ns = Ns;
+                 ok = bin_status == nullptr || bin_status[f] == SSL_BIN_OK;
+                 Pf = P + (size_t)f * D;
+             });
+}
+
+// Batched: item = (group, bin), groups[g] = (first, count) into gblocks, the blocks of one
+// steering table; nsmax = the largest Ns of the batch.
+__global__ __launch_bounds__(kThreads) void steer_sig_batch(
+    const BlockDev *__restrict__ blk, const int2 *__restrict__ items, int n_items, int n_tiles,
+    const int2 *__restrict__ groups, const int *__restrict__ gblocks, int nsmax)
+{
+    int ii, tile;
+    if (!sig_item(n_items, n_tiles, ii, tile)) return;
+    const int2 it = items[ii];
+    const int2 gr = groups[it.x];
+    const BlockDev &B0 = blk[gblocks[gr.x]];
+    const int d0 = tile * kRows;
+    if (d0 >= B0.D) return;
+    const int f = it.y, M = B0.M, D = B0.D;
+    sig_tile(static_cast<const float2 *>(B0.H) + (size_t)f * D * M, D, M, d0, gr.y, nsmax,
+             [&](int i, const float2 *&e, const double2 *&L, int &ns, bool &ok, float *&Pf) {
+                 const BlockDev &B = blk[gblocks[gr.x + i]];
+                 e = B.Es + (size_t)f * B.Ns * M;
+                 L = B.Esl + 6 * (size_t)f;
+                 ns = B.Ns;
+                 ok = gload(B.status + f) == SSL_BIN_OK;
+                 Pf = B.P + (size_t)f * D;
+             });
+}
+
+}  // namespace
+
+int steer_sig_tiles(int D) { return (D + kRows - 1) / kRows; }
+
+hipError_t launch_steer_sig(const ssl_c64 *H, const ssl_c64 *Es, const ssl_c128 *Esl, int F,
+                            int D, int M, int Ns, const int32_t *bin_status, float *P,
+                            hipStream_t st)
+{
+    const int nt = steer_sig_tiles(D);
+    hipLaunchKernelGGL(steer_sig_single, dim3(sig_grid(F, nt)), dim3(kThreads), 0, st,
+                       reinterpret_cast<const float2 *>(H), reinterpret_cast<const float2 *>(Es),
+                       reinterpret_cast<const double2 *>(Esl), bin_status, F, D, M, Ns, P, nt);
+    return hipGetLastError();
+}
+
+hipError_t launch_steer_sig_batch(const BlockDev *blk, const int2 *items, int n_items,
+                                  const int2 *groups, const int *gblocks, int max_dtiles,
+                                  int nsmax, hipStream_t st)
+{
+    if (n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(steer_sig_batch, dim3(sig_grid(n_items, max_dtiles)), dim3(kThreads), 0, st,
+                       blk, items, n_items, max_dtiles, groups, gblocks, nsmax);
+    return hipGetLastError();
+}

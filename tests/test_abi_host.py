@@ -70,11 +70,13 @@ def test_noalloc_scratch_limit_matches_header():
 
 def test_noalloc_scratch_bytes_host_only():
     import paper_2504_03373_amd as S
-    # R and A (F M^2 complex64 each), E_n, P, Pbar, status, bin-sum partials; 256-byte aligned
+    # R and A (F M^2 complex64 each), E_n, P, Pbar, status, the signal vectors (F Ns M
+    # complex64) and their inverse Cholesky factors (6 complex128 per bin), bin-sum partials;
+    # 256-byte aligned
     a = lambda n: (n + 255) // 256 * 256
     F, M, Ns, D = 257, 60, 2, 1368
     want = (2 * a(F * M * M * 8) + a(F * (M - Ns) * M * 8) + a(F * D * 4) + a(D * 4) + a(F * 4)
-            + a(((F + 15) // 16) * D * 4))
+            + a(F * Ns * M * 8) + a(F * 6 * 16) + a(((F + 15) // 16) * D * 4))
     assert S.ssl_localize_noalloc_bytes(F, M, Ns, D) == want
     assert want <= S.SSL_NOALLOC_SCRATCH_BYTES
     assert S.ssl_localize_noalloc_bytes(1100, 60, 2, 1368) > S.SSL_NOALLOC_SCRATCH_BYTES

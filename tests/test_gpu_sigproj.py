@@ -1,0 +1,172 @@
+"""eq.5 with p = 2 through the signal subspace (ssl_ctx_set_projection, the FP32 path's default):
+den = |h|^2 - |L^{-1} E_s^H h|^2 in FP64.  Against the noise-vector projection and the FP64
+oracle's eq.5 (a sum over the noise vectors): P-bar within the FP32 bar, the same peaks; batches
+mixing blocks that use it and blocks that cannot (Ns > 3, GEVD, SEVD) equal each block alone;
+failed bins contribute nothing.  MI355X only."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import peak_ambiguity, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    import paper_2504_03373_amd as S
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    S.lib()
+    return S
+
+
+@pytest.fixture(scope="module")
+def ctx(S):
+    c = S.ssl_ctx_create(0, 0)
+    yield c
+    S.ssl_ctx_destroy(c)
+
+
+def outs(w, Ns):
+    import torch
+    return dict(pk=torch.full((Ns,), -7, dtype=torch.int32, device="cuda:0"),
+                pv=torch.zeros(Ns, dtype=torch.float32, device="cuda:0"),
+                Pbar=torch.zeros(w.D, dtype=torch.float32, device="cuda:0"),
+                st=torch.full((w.F,), -7, dtype=torch.int32, device="cuda:0"))
+
+
+def single(S, ctx, w, Xd, n, Hd, Ns):
+    o = outs(w, Ns)
+    S.ssl_localize(ctx, Xd, n, Hd, S.SSL_FP32, w.grid.n_az, w.grid.n_el, Ns, 2, o["pk"], o["pv"],
+                   o["Pbar"], o["st"])
+    return {k: to_host(v) for k, v in o.items()}
+
+
+def noise_handle(S, ctx, w):
+    import torch
+    Xn = w.noise_frames()
+    Kd = torch.zeros((w.F, w.M, w.M), dtype=torch.complex128, device="cuda:0")
+    S.ssl_corr_accum(ctx, to_dev(Xn), 1.0 / Xn.shape[1], 0, S.SSL_FP64, Kd)
+    n = S.ssl_noise_create(ctx, w.F, w.M)
+    S.ssl_noise_set(n, Kd, S.SSL_FP64)
+    return n, oracle.noise_corr(Xn)
+
+
+@pytest.mark.parametrize("name,blocks", [("small", 6), ("paper", 6)])
+def test_signal_form_matches_noise_form_and_oracle(S, ctx, name, blocks):
+    w = synth.workload_small(n_blocks=blocks) if name == "small" else \
+        synth.workload_paper(n_blocks=blocks)
+    n, K = noise_handle(S, ctx, w)
+    H = w.steering_table()
+    Hd = to_dev(H)
+    assert S.ssl_ctx_get_projection(ctx) == S.SSL_PROJ_SIGNAL
+    worst = 0.0
+    for b in range(blocks):
+        X, dirs, _ = w.block(b)
+        Xd = to_dev(X)
+        g = single(S, ctx, w, Xd, n, Hd, w.Ns)
+        S.ssl_ctx_set_projection(ctx, S.SSL_PROJ_NOISE)
+        try:
+            gn = single(S, ctx, w, Xd, n, Hd, w.Ns)
+        finally:
+            S.ssl_ctx_set_projection(ctx, S.SSL_PROJ_SIGNAL)
+        r = oracle.localize(X, K, H, w.grid.n_az, w.grid.n_el, w.Ns, nthreads=16)
+        assert np.all(g["st"] == 0) and np.all(gn["st"] == 0)
+        rel = float(np.max(np.abs(g["Pbar"].astype(np.float64) - r["Pbar"]) / r["Pbar"]))
+        rel_n = float(np.max(np.abs(g["Pbar"].astype(np.float64) - gn["Pbar"]) / gn["Pbar"]))
+        amb = peak_ambiguity(r["Pbar"], w.grid.n_el, w.grid.n_az, w.Ns, max(rel, 1e-7))
+        say(f"  {name} block {b}: signal form vs oracle {rel:.2e}, vs noise form {rel_n:.2e}, "
+            f"peaks {g['pk']} {gn['pk']} ref {r['peaks']}")
+        worst = max(worst, rel)
+        assert rel <= 1e-4 and rel_n <= 1e-4
+        assert not amb
+        assert np.array_equal(g["pk"], r["peaks"]) and np.array_equal(gn["pk"], r["peaks"])
+        assert np.all(np.abs(g["pv"] - r["peak_val"]) <= 1e-4 * r["peak_val"])
+    say(f"  max Pbar relative error {worst:.3g}")
+    S.ssl_noise_destroy(n)
+
+
+@pytest.mark.parametrize("Ns", [1, 3])
+def test_signal_form_other_ns(S, ctx, Ns):
+    """Ns = 1 and 3 on the 60-channel workload (the workload's sources are 2: the form holds
+    whatever the split, the oracle decides with the same Ns)."""
+    w = synth.workload_paper(n_blocks=2)
+    n, K = noise_handle(S, ctx, w)
+    H = w.steering_table()
+    Hd = to_dev(H)
+    X, _, _ = w.block(0)
+    g = single(S, ctx, w, to_dev(X), n, Hd, Ns)
+    r = oracle.localize(X, K, H, w.grid.n_az, w.grid.n_el, Ns, nthreads=16)
+    rel = float(np.max(np.abs(g["Pbar"].astype(np.float64) - r["Pbar"]) / r["Pbar"]))
+    amb = peak_ambiguity(r["Pbar"], w.grid.n_el, w.grid.n_az, Ns, max(rel, 1e-7))
+    say(f"  Ns={Ns}: rel {rel:.2e} peaks {g['pk']} ref {r['peaks']} near-ties {amb}")
+    assert np.all(g["st"] == 0)
+    assert rel <= 1e-4
+    if not amb:
+        assert np.array_equal(g["pk"], r["peaks"])
+    S.ssl_noise_destroy(n)
+
+
+def test_batch_mixing_forms_equals_single(S, ctx):
+    """One steering table, blocks with Ns = 1, 2, 3 (signal form), Ns = 4 (noise form) and an SEVD
+    block (signal form): every block's outputs equal its single-block call bit for bit, twice (the
+    second call replays the captured batch).  GEVD blocks (noise form) mixed with SEVD blocks are
+    covered by the GEVD tests."""
+    import torch
+    w = synth.workload_paper(n_blocks=4)
+    n, _ = noise_handle(S, ctx, w)
+    Hd = to_dev(w.steering_table())
+    Xs = [to_dev(w.block(b)[0]) for b in range(4)]
+    plan = [(Xs[0], n, 1), (Xs[1], n, 2), (Xs[2], n, 3), (Xs[3], n, 4), (Xs[0], None, 2),
+            (Xs[1], n, 2)]
+    for rep in range(2):
+        bo = [outs(w, ns) for _, _, ns in plan]
+        descs = [S.block_desc(Xd, nh, Hd, w.grid.n_az, w.grid.n_el, ns, o["pk"], o["pv"],
+                              o["Pbar"], o["st"]) for (Xd, nh, ns), o in zip(plan, bo)]
+        S.ssl_localize_batch(ctx, descs, S.SSL_FP32, 2)
+        got = [{k: to_host(v) for k, v in o.items()} for o in bo]
+        for i, (Xd, nh, ns) in enumerate(plan):
+            ref = single(S, ctx, w, Xd, nh, Hd, ns)
+            for k in ("pk", "pv", "Pbar", "st"):
+                assert np.array_equal(got[i][k], ref[k]), (rep, i, k)
+    S.ssl_noise_destroy(n)
+
+
+def test_failed_bins_contribute_nothing(S, ctx):
+    """A bin whose K is not positive definite: status NOT_PD, P = 0 there in both forms, so the
+    two P-bars agree within the bar."""
+    import torch
+    w = synth.workload_small(n_blocks=2)
+    Xn = w.noise_frames()
+    K = oracle.noise_corr(Xn)
+    K[5] = np.diag(np.r_[1.0, -1.0, np.ones(w.M - 2)]).astype(complex)
+    n = S.ssl_noise_create(ctx, w.F, w.M)
+    S.ssl_noise_set(n, to_dev(K), S.SSL_FP64)
+    Hd = to_dev(w.steering_table())
+    Xd = to_dev(w.block(0)[0])
+    g = single(S, ctx, w, Xd, n, Hd, w.Ns)
+    S.ssl_ctx_set_projection(ctx, S.SSL_PROJ_NOISE)
+    try:
+        gn = single(S, ctx, w, Xd, n, Hd, w.Ns)
+    finally:
+        S.ssl_ctx_set_projection(ctx, S.SSL_PROJ_SIGNAL)
+    assert g["st"][5] == S.SSL_BIN_NOT_PD and np.sum(g["st"] != 0) == 1
+    rel = float(np.max(np.abs(g["Pbar"].astype(np.float64) - gn["Pbar"]) / gn["Pbar"]))
+    assert rel <= 1e-4
+    S.ssl_noise_destroy(n)
+
+
+def test_projection_mode_errors(S, ctx):
+    with pytest.raises(S.SSLError) as e:
+        S.ssl_ctx_set_projection(ctx, 2)
+    assert e.value.code == S.SSL_ERR_ARG
+    assert S.ssl_ctx_get_projection(ctx) == S.SSL_PROJ_SIGNAL
