@@ -154,9 +154,6 @@ hipError_t launch_svd(ssl_ctx ctx, ssl_c64 *A, const int32_t *kst, int F, int M,
     return launch_jacobi(A, kst, F, M, Ns, max_sweeps, jac_lanes(ctx, M), En, sigma, stt, conv, st,
                          U, sub_full, Es, Esl);
 }
-// Whether a localization path stops the Jacobi solve at the noise subspace (p = 2: eq.5 reads only
-// its projector): the batched path from SSL_STOP_BATCH on, the one-block paths from
-// SSL_STOP_LOCALIZE on.
 // Whether eq.5 is evaluated through the signal subspace (FP64, steer_sig.hip): the FP32 path with
 // p = 2, the Jacobi backend, GSVD or SEVD (U unitary), Ns <= 3, unless the context asks for the
 // noise-vector projection.
@@ -166,6 +163,9 @@ bool use_sig(ssl_ctx ctx, ssl_prec prec, int p, int Ns, bool gevd)
            ctx->svd == SSL_SVD_JACOBI && !gevd && Ns >= 1 && Ns <= 3;
 }
 
+// Whether a localization path stops the Jacobi solve at the noise subspace (p = 2: eq.5 reads only
+// its projector): the batched path from SSL_STOP_BATCH on, the one-block paths from
+// SSL_STOP_LOCALIZE on.
 int sub_full_for(ssl_ctx ctx, int p, bool batched)
 {
     const int need = batched ? SSL_STOP_BATCH : SSL_STOP_LOCALIZE;
@@ -334,8 +334,10 @@ ssl_status localize_enqueue(ssl_ctx ctx, bool may_time, char *w, const LocalizeW
     ssl_c64 *Es = sig ? reinterpret_cast<ssl_c64 *>(w + L.off_es()) : nullptr;
     ssl_c128 *Esl = sig ? reinterpret_cast<ssl_c128 *>(w + L.off_es() + L.bEs) : nullptr;
     e = run(SSL_K_JACOBI, [&] {
-        return launch_svd(ctx, A, K ? K->status : nullptr, F, M, Ns, SSL_DEFAULT_SWEEPS, En,
-                          nullptr, stt, nullptr, st, nullptr, sub_full_for(ctx, p, false), Es, Esl);
+        // through the signal subspace the noise vectors are neither formed nor stored
+        return launch_svd(ctx, A, K ? K->status : nullptr, F, M, Ns, SSL_DEFAULT_SWEEPS,
+                          sig ? nullptr : En, nullptr, stt, nullptr, st, nullptr,
+                          sub_full_for(ctx, p, false), Es, Esl);
     });
     if (e != hipSuccess) return hip_fail(e, "jacobi launch");
     if (gevd) {
@@ -1729,7 +1731,7 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
         w += align256(F * M * M * sizeof(ssl_c64));
         B.A = d.K ? reinterpret_cast<float2 *>(w) : B.R;   // SEVD-MUSIC: Jacobi on R
         w += align256(F * M * M * sizeof(ssl_c64));
-        B.En = reinterpret_cast<float2 *>(w);
+        B.En = sigb[b] ? nullptr : reinterpret_cast<float2 *>(w);   // not formed for eq.5 via E_s
         w += align256(F * Nn * M * sizeof(ssl_c64));
         B.P = reinterpret_cast<float *>(w);
         w += align256(F * D * sizeof(float));

@@ -431,6 +431,14 @@ __device__ __forceinline__ bool jacobi_pair_sorted(float2 *Bs, int cs, int cn, i
     return true;
 }
 
+// Orders a wave's LDS writes before its later LDS reads: the hardware completes one wave's LDS
+// instructions in issue order, so only the compiler has to be kept from moving accesses across.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // Sum over the 64 lanes of a wave; every lane gets the same bits.
 __device__ __forceinline__ float wave_sum(float v)
 {
@@ -441,7 +449,8 @@ __device__ __forceinline__ float wave_sum(float v)
 }
 
 // One bin: Af = its A (row-major M x M, overwritten), kst = upstream status of the bin (noise
-// factorisation), Enf = [M-Ns][M] output, sigf = [M] or null, stf = status or null,
+// factorisation), Enf = [M-Ns][M] output (null: only the signal vectors are formed, see Esf),
+// sigf = [M] or null, stf = status or null,
 // convf = (sweeps, rotations, numerical rank) or null.  sub_full >= 0 (only with sigf and Uf
 // null, 1 <= Ns <= kSubMaxNs) asks for the noise subspace alone: E_n is then an orthonormal basis
 // of the span of the M - Ns smallest left singular vectors (what eq.5 with p = 2 depends on), not
@@ -489,6 +498,9 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
     const int g = tid / G;              // lane group
     const int q = tid % G;              // lane in group
     const int Nn = M - Ns;
+    // only the signal vectors are wanted (eq.5 evaluated through them): no complement basis, and
+    // only their Ns columns pass through Q
+    const bool sig_only = Enf == nullptr;
 
     __syncthreads();                    // the previous bin of a persistent workgroup is done
     if (tid == 0) {
@@ -758,8 +770,12 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         // eq.5 with p = 2 reads.  A failed check, or kSubMaxSweeps subspace sweeps without
         // convergence, returns to full sweeps (the full solve); so does a bin whose weakest
         // signal column holds less than the other columns' energy at the switch.
+        // A subspace sweep runs in wave 0 alone: round t rotates signal column i against
+        // non-signal column (t + i) mod (rk - Ns), i < Ns (distinct partners: 2 Ns <= rk), then
+        // the pairs inside S one at a time; a wave's LDS accesses complete in issue order, so
+        // the rounds need no workgroup barrier.
         const bool sub = sub_full >= 0 && sigf == nullptr && Uf == nullptr && Ns >= 1 &&
-                         Ns <= kSubMaxNs && Ns < rk;
+                         Ns <= kSubMaxNs && 2 * Ns <= rk;
         int phase = 0;                               // 0 full, 1 subspace, 2 full after a fallback
         int sub_sweeps = 0;
         unsigned long long smask = 0ull;
@@ -809,7 +825,42 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
             }
             if (!settled) {
                 int rotated = 0;
-                for (int rd = 0; rd < n_rounds; ++rd) {
+                if (phase == 1) {
+                    if (tid < 64) {
+                        const int nn = rk - Ns;
+                        const bool act = g < Ns;
+                        const int cs = act ? cinv[g] : 0;
+                        int j = g;                           // partner slot (t + g) mod nn
+                        for (int t = 0; t < nn; ++t) {
+                            if (act) {
+                                const int cn = clist[j];
+                                const bool rot =
+                                    nr_lo ? jacobi_pair_sorted<MP, G, RLO>(Bs, cs, cn, q, tol2)
+                                          : jacobi_pair_sorted<MP, G, R>(Bs, cs, cn, q, tol2);
+                                if (rot) {
+                                    rotated = 1;
+                                    if (q == 0) ++my_rot;
+                                }
+                                if (++j == nn) j = 0;
+                            }
+                            wave_lds_sync();
+                        }
+                        for (int a = 0; a + 1 < Ns; ++a)
+                            for (int b = a + 1; b < Ns; ++b) {
+                                if (g == 0) {
+                                    const bool rot =
+                                        nr_lo ? jacobi_pair<MP, G, RLO>(Bs, cinv[a], cinv[b], q, tol2)
+                                              : jacobi_pair<MP, G, R>(Bs, cinv[a], cinv[b], q, tol2);
+                                    if (rot) {
+                                        rotated = 1;
+                                        if (q == 0) ++my_rot;
+                                    }
+                                }
+                                wave_lds_sync();
+                            }
+                    }
+                }
+                for (int rd = 0; rd < n_rounds && phase != 1; ++rd) {
                     int a = 0, b = 0;
                     bool play;
                     if (rd < Me - 1) {
@@ -835,21 +886,9 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                     if (play) {
                         const int ci = min(a, b), cj = max(a, b);
                         if (cj < rk) {
-                            bool rot = false;
-                            if (phase == 1) {
-                                const bool si = (smask >> ci) & 1ull, sj = (smask >> cj) & 1ull;
-                                if (si != sj) {
-                                    const int cs = si ? ci : cj, cn = si ? cj : ci;
-                                    rot = nr_lo ? jacobi_pair_sorted<MP, G, RLO>(Bs, cs, cn, q, tol2)
-                                                : jacobi_pair_sorted<MP, G, R>(Bs, cs, cn, q, tol2);
-                                } else if (si) {
-                                    rot = nr_lo ? jacobi_pair<MP, G, RLO>(Bs, ci, cj, q, tol2)
-                                                : jacobi_pair<MP, G, R>(Bs, ci, cj, q, tol2);
-                                }
-                            } else {
-                                rot = nr_lo ? jacobi_pair<MP, G, RLO>(Bs, ci, cj, q, tol2)
-                                            : jacobi_pair<MP, G, R>(Bs, ci, cj, q, tol2);
-                            }
+                            const bool rot =
+                                nr_lo ? jacobi_pair<MP, G, RLO>(Bs, ci, cj, q, tol2)
+                                      : jacobi_pair<MP, G, R>(Bs, ci, cj, q, tol2);
                             if (rot) {
                                 rotated = 1;
                                 if (q == 0) ++my_rot;
@@ -978,7 +1017,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                 }
 #pragma unroll
                 for (int k = 0; k < kSubMaxNs; ++k) {
-                    if (k >= Ns) break;
+                    if (k >= Ns || sig_only) break;
                     const float2 x = col[k];
                     const float a2 = wave_sum((r >= k && r < rk) ? fmaf(x.x, x.x, x.y * x.y) : 0.f);
                     const float xr = __shfl(x.x, k), xi = __shfl(x.y, k);
@@ -1008,7 +1047,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                 }
             }
             __syncthreads();
-            for (int c = g; c < MP && g < NG; c += NG) {
+            for (int c = g; c < MP && g < NG && !sig_only; c += NG) {
                 if (c < rk && ((smask >> c) & 1ull)) continue;
                 float2 z[R];
                 if (c < rk) {
@@ -1055,10 +1094,13 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         // ---- 6. U = Q U_R, reflectors applied last to first ----------------------------------
         // U's columns move to registers (a group owns at most two: c = g, g + NG), the reflectors
         // take the buffer (stored with zeros outside rows k..M-1, so their loads need no row
-        // test), and each group takes its columns through every reflector with no barrier.
+        // test), and each group takes its columns through every reflector with no barrier.  With
+        // sig_only group g < Ns takes signal vector g (column perm[g]) and the other groups idle.
         {
-            const int c0 = g, c1 = g + NG;
-            const bool h0 = g < NG && c0 < M, h1 = g < NG && c1 < M;
+            __syncthreads();                            // perm is complete
+            const int c0 = sig_only ? (g < Ns ? perm[g] : 0) : g, c1 = g + NG;
+            const bool h0 = sig_only ? g < Ns : (g < NG && c0 < M);
+            const bool h1 = !sig_only && g < NG && c1 < M;
             float2 x0[R], x1[R];
 #pragma unroll
             for (int j = 0; j < R; ++j) {
@@ -1071,7 +1113,8 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                 X[at<MP>(k, r)] = (r >= k && r < M) ? Af[k * M + r] : make_float2(0.f, 0.f);
             }
             __syncthreads();
-            for (int k = rk - 1; k >= 0; --k) {
+            const bool busy = !sig_only || __any(h0);   // uniform over the wave
+            for (int k = rk - 1; k >= 0 && busy; --k) {
                 const float tk = tau[k];
                 float2 v[R];
                 float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f;
@@ -1110,7 +1153,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
     // ---- outputs ------------------------------------------------------------------------------
     const bool ok = (flag == SSL_BIN_OK) && converged;
     const int st = (flag != SSL_BIN_OK) ? flag : (converged ? SSL_BIN_OK : SSL_BIN_NO_CONV);
-    for (int e = tid; e < Nn * MP; e += NT) {              // noise vector c = e / MP, row e % MP
+    for (int e = tid; e < Nn * MP && !sig_only; e += NT) { // noise vector c = e / MP, row e % MP
         const int c = e / MP, r = e % MP;
         if (r < M) Enf[c * M + r] = ok ? X[at<MP>(perm[Ns + c], r)] : make_float2(0.f, 0.f);
     }
@@ -1219,7 +1262,8 @@ __global__ __launch_bounds__((JacobiCfg<MP, G>::THREADS)) void jacobi_svd(
 {
     const int f = blockIdx.x;
     jacobi_bin<MP, G>(A + (size_t)f * M * M, kstatus ? kstatus[f] : SSL_BIN_OK, M, Ns, max_sweeps,
-                      En + (size_t)f * (M - Ns) * M, sigma ? sigma + (size_t)f * M : nullptr,
+                      En ? En + (size_t)f * (M - Ns) * M : nullptr,
+                      sigma ? sigma + (size_t)f * M : nullptr,
                       bin_status ? bin_status + f : nullptr, conv ? conv + 3 * f : nullptr,
                       U ? U + (size_t)f * M * M : nullptr, sub_full,
                       Es ? Es + (size_t)f * Ns * M : nullptr, Esl ? Esl + 6 * (size_t)f : nullptr);
@@ -1250,7 +1294,8 @@ __attribute__((amdgpu_waves_per_eu(JacobiCfg<MP, G>::WAVES_PER_EU))) void jacobi
         const BlockDev &B = blk[w.x];
         const int f = w.y, M = B.M, Ns = B.Ns;
         jacobi_bin<MP, G>(B.A + (size_t)f * M * M, B.kstatus ? B.kstatus[f] : SSL_BIN_OK, M, Ns,
-                          max_sweeps, B.En + (size_t)f * (M - Ns) * M, nullptr, B.status + f,
+                          max_sweeps, B.En ? B.En + (size_t)f * (M - Ns) * M : nullptr,
+                          nullptr, B.status + f,
                           nullptr, nullptr, B.p == 2 ? sub_full : -1,
                           B.Es ? B.Es + (size_t)f * Ns * M : nullptr,
                           B.Esl ? B.Esl + 6 * (size_t)f : nullptr);
