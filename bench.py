@@ -8,10 +8,11 @@ spectrum (eq.5), bin sum (eq.6) and peak search -- over one batch of `--batch` d
 ssl_localize_batch (all HIP kernels of the library).  Inputs (distinct seeded blocks, steering
 table, resident noise factor) are in HBM before any timed region starts.
 
-The headline path (`--prec`, default fp32) is the paper's arithmetic: correlation and projection
-on FP32 MFMA, K^{-1}R in FP64, the Jacobi SVD in FP32.  The mixed-precision paths (bf16 and fp16
-MFMA inputs with FP32 accumulation, the rest unchanged) are measured in the same run as secondary
-keys, batched and one block per call.
+The headline path (`--prec`, default fp32) is the paper's arithmetic: correlation on FP32 MFMA,
+K^{-1}R in FP64, the Jacobi SVD in FP32 and eq.5 through the signal subspace in FP64 (|h|^2 minus
+the squared projection on the Ns signal vectors, FP64 MFMA).  The mixed-precision paths (bf16 and
+fp16 MFMA inputs with FP32 accumulation for the correlation and the noise-vector projection, the
+rest unchanged) are measured in the same run as secondary keys, batched and one block per call.
 
 Timed regions per precision (each bracketed by torch.cuda.synchronize()):
   * main: `--steps` batch steps with per-kernel HIP events on the launch stream -> `value`, the
@@ -45,7 +46,8 @@ PEAK_HBM_GBS = 8000.0
 PEAK_MFMA_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0}
 
 
-def jacobi_flops(M: int, sweeps, rotations, rank, Ns: int = 0, sub: bool = False) -> float:
+def jacobi_flops(M: int, sweeps, rotations, rank, Ns: int = 0, sub: bool = False,
+                 sig: bool = False) -> float:
     """Algorithmic real flops of the SVD kernel summed over bins (rank r per bin).
     Pivoted QR: step k = 0..r-1 has trailing size n = M - k; each of the n - 1 remaining columns
     costs w = v^H x (8n), x -= v (tau w) (8n) and its trailing norm (4n): 20 n (n - 1).
@@ -54,10 +56,13 @@ def jacobi_flops(M: int, sweeps, rotations, rank, Ns: int = 0, sub: bool = False
     (16 r); each applied rotation rewrites two columns (20 r); pair visits = sweeps r(r-1)/2.
     Normalisation of W: 6 r per column.  U = Q U_R: reflector k applied to the M columns,
     16 (M - k) M.
-    sub: the solve stopped at the noise subspace (p = 2 localization): the first sweep visits
-    every pair, each later one the Ns (r - Ns) + Ns (Ns - 1) / 2 pairs with a member in the signal
-    set (a bin that fell back to full sweeps is counted the same way, which undercounts it); the
-    r - Ns complement vectors each pass Ns reflectors (16 r), and W is not normalised."""
+    sub: the solve stopped at the noise subspace (p = 2 localization), which switches to the
+    subspace sweeps before any full one: every sweep visits the Ns (r - Ns) + Ns (Ns - 1) / 2
+    pairs with a member in the signal set (a bin that fell back to full sweeps is counted the same
+    way, which undercounts it); the r - Ns complement vectors each pass Ns reflectors (16 r), and
+    W is not normalised.
+    sig: only the Ns signal vectors are formed (eq.5 through the signal subspace): no complement,
+    and the back-transformation U = Q U_R covers Ns columns, 16 (M - k) Ns per reflector."""
     import numpy as np
     total = 0.0
     for s, rot, r in zip(np.asarray(sweeps), np.asarray(rotations), np.asarray(rank)):
@@ -65,11 +70,11 @@ def jacobi_flops(M: int, sweeps, rotations, rank, Ns: int = 0, sub: bool = False
         k = np.arange(r, dtype=np.float64)
         n = M - k
         total += float(np.sum(20.0 * n * (n - 1)) + np.sum(16.0 * n * (r - k - 1))
-                       + np.sum(16.0 * n * M))
+                       + np.sum(16.0 * n * (Ns if sig else M)))
         if sub and r > Ns:
-            visits = min(float(s), 1.0) * r * (r - 1) / 2.0 + \
-                max(float(s) - 1.0, 0.0) * (Ns * (r - Ns) + Ns * (Ns - 1) / 2.0)
-            total += visits * 16.0 * r + float(rot) * 20.0 * r + (r - Ns) * Ns * 16.0 * r
+            visits = float(s) * (Ns * (r - Ns) + Ns * (Ns - 1) / 2.0)
+            total += visits * 16.0 * r + float(rot) * 20.0 * r + \
+                (0.0 if sig else (r - Ns) * Ns * 16.0 * r)
         else:
             total += float(s) * r * (r - 1) / 2.0 * 16.0 * r + float(rot) * 20.0 * r + 6.0 * r * r
     return total
@@ -601,7 +606,10 @@ def main() -> int:
             conv_all.append(conv_t.cpu().numpy().copy())
         S.ssl_ctx_set_stop(ctx, S.SSL_STOP_LOCALIZE)
         del R, En
-        jflops = float(sum(jacobi_flops(M, c[:, 0], c[:, 1], c[:, 2], Ns, True) for c in conv_all))
+        # FP32 with Ns <= 3: eq.5 through the signal subspace (the library's default projection)
+        sig = name == "fp32" and 1 <= Ns <= 3
+        jflops = float(sum(jacobi_flops(M, c[:, 0], c[:, 1], c[:, 2], Ns, True, sig)
+                           for c in conv_all))
         descs = [S.block_desc(Xs[b], noise, H, w.grid.n_az, w.grid.n_el, Ns, pk[b], pv[b],
                               Pbar[b], st[b]) for b in range(B)]
 
@@ -661,7 +669,9 @@ def main() -> int:
         sH = 8 if name == "fp32" else 4
         w_corr = B * (8.0 * F * T * M + 8.0 * F * M * M)
         w_white = B * 8.0 * F * M ** 3
-        w_steer = B * 8.0 * F * D * M * (M - Ns)
+        # projection: |E_n^H h|^2 (M - Ns noise vectors, MFMA at the table's precision), or
+        # through the signal subspace |E_s^H h|^2 (Ns vectors, FP64 MFMA)
+        w_steer = B * 8.0 * F * D * M * (Ns if sig else M - Ns)
         w_bins = B * (4.0 * F * D + 4.0 * D)
         rl = {
             "corr": {"bound": "hbm", "unit": "GB/s", "bytes_per_launch": w_corr,
@@ -671,8 +681,11 @@ def main() -> int:
                        "achieved": w_white / ms("whiten") / 1e12, "peak": PEAK_FP64_TFLOPS},
             "jacobi": {"bound": "alu", "unit": "TFLOP/s", "flops_per_launch": jflops,
                        "achieved": jflops / ms("jacobi") / 1e12, "peak": PEAK_FP32_VECTOR_TFLOPS},
-            "steer": {"bound": "mfma", "unit": "TFLOP/s", "flops_per_launch": w_steer,
-                      "achieved": w_steer / ms("steer") / 1e12, "peak": PEAK_MFMA_TFLOPS[name],
+            "steer": {"bound": "mfma", "mfma_dtype": "f64" if sig else name, "unit": "TFLOP/s",
+                      "flops_per_launch": w_steer,
+                      "achieved": w_steer / ms("steer") / 1e12,
+                      "peak": PEAK_FP64_TFLOPS if sig else PEAK_MFMA_TFLOPS[name],
+                      "form": "signal subspace" if sig else "noise vectors",
                       "table_bytes_per_element": sH},
             "binsum": {"bound": "hbm", "unit": "GB/s", "bytes_per_launch": w_bins,
                        "achieved": w_bins / ms("binsum") / 1e9, "peak": PEAK_HBM_GBS},
@@ -759,8 +772,11 @@ def main() -> int:
         "config": {"workload": w.name, "M": M, "F": F, "T": T, "D": D, "Ns": Ns, "p": 2,
                    "blocks_per_step": B, "path": "ssl_localize_batch",
                    "mfma_inputs": args.prec, "whitening": "fp64",
-                   "svd": "fp32 one-sided Jacobi (two-QR preconditioned), stopped at the noise "
-                          "subspace"},
+                   "svd": "fp32 one-sided Jacobi (two-QR preconditioned), stopped at the "
+                          "signal / noise split",
+                   "projection": ("eq.5 through the signal subspace, FP64 MFMA"
+                                  if args.prec == "fp32" and Ns <= 3 else
+                                  f"eq.5 over the noise vectors, {args.prec} MFMA")},
         "graph_value": round(main_r["graph_value"], 2),
         "per_block": {"value": round(main_r["per_block"], 2), "unit": "blocks/s",
                       "path": f"ssl_localize, one block per call, {args.prec}"},

@@ -20,9 +20,11 @@
 // sweep changes nothing; if then min_S |x|^2 exceeds the sum of |x|^2 over the other columns (a
 // bound on their largest squared singular value), X_S spans the Ns dominant singular vectors and
 // E_n is built as the orthogonal complement of X_S (Householder vectors of X_S) instead of from
-// the rotations that would still run inside the noise cluster.  On the 60-channel workload the
-// projector has converged after 1 full and about 2 such sweeps, against about 6 full sweeps for
-// the singular vectors; the noise vectors then are not singular vectors (sigma is not produced).
+// the rotations that would still run inside the noise cluster (or, for the signal-subspace form
+// of eq.5, only X_S's vectors are formed).  The localization paths switch before any full sweep
+// (sub_full = 0: the pivoted QR already grades X's column norms); on the 60-channel workload the
+// projector has then converged after about 2.4 such sweeps, against about 6 full sweeps for the
+// singular vectors; the noise vectors then are not singular vectors (sigma is not produced).
 //
 // GPU mapping (gfx950):
 //  * one workgroup per bin; one complex64 MP x MP column-major matrix in LDS (32 KB at MP = 64,
@@ -439,6 +441,93 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
+// One signal column's part of a subspace sweep, by one lane group: column cs against the non-signal
+// columns nlist[j0], nlist[j0 + 1], .. (cyclically, nn of them), each visit as jacobi_pair_sorted.
+// The signal column stays in registers for the whole pass; each partner is loaded one visit ahead
+// and written back after its rotation.  Other groups of the same wave run the same pass for the
+// other signal columns from starting slots at least two apart (cyclically), so no partner is
+// loaded ahead while another group still has to rotate it, and every write reaches the LDS before
+// the wave's later reads (issue order; see wave_lds_sync).  Returns the number of visits that
+// changed the columns.
+template <int MP, int G, int NR>
+__device__ __forceinline__ int sub_pass(float2 *Bs, int cs, const int *nlist, int nn, int j0, int q,
+                                        double tol2)
+{
+    float2 xs[NR], y[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) xs[k] = Bs[swx<MP>(cs, q + G * k)];
+    int j = j0;
+    int cn = nlist[j];
+    int changed = 0;
+    for (int t = 0; t < nn; ++t) {
+        int jn = j + 1;
+        if (jn == nn) jn = 0;
+        const int cnn = nlist[jn];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) y[k] = Bs[swx<MP>(cn, q + G * k)];
+        float al = 0.f, be = 0.f, gr = 0.f, gi = 0.f;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            al = fmaf(xs[k].x, xs[k].x, fmaf(xs[k].y, xs[k].y, al));
+            be = fmaf(y[k].x, y[k].x, fmaf(y[k].y, y[k].y, be));
+            gr = fmaf(xs[k].x, y[k].x, fmaf(xs[k].y, y[k].y, gr));
+            gi = fmaf(xs[k].x, y[k].y, fmaf(-xs[k].y, y[k].x, gi));
+        }
+        al = group_sum<G>(al);
+        be = group_sum<G>(be);
+        gr = group_sum<G>(gr);
+        gi = group_sum<G>(gi);
+        const bool swap = be > al;
+        const double g2 = (double)gr * gr + (double)gi * gi;
+        const double ab = (double)al * be;
+        if (g2 > tol2 * ab && ab > 0.0) {
+            const float g2f = (float)g2;
+            float rg;
+            if (g2f >= 1e-36f) {
+                rg = __builtin_amdgcn_rsqf(g2f);
+            } else {
+                const float ax = fabsf(gr), ay = fabsf(gi);
+                const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+                const float rt = mn * __builtin_amdgcn_rcpf(mx);
+                rg = __builtin_amdgcn_rcpf(mx * __builtin_amdgcn_sqrtf(fmaf(rt, rt, 1.0f)));
+            }
+            const float zeta = (be - al) * 0.5f * rg;
+            const float az = fminf(fabsf(zeta), 1e18f);
+            float tt = __builtin_amdgcn_rcpf(az + __builtin_amdgcn_sqrtf(fmaf(az, az, 1.0f)));
+            tt = copysignf(tt, zeta);
+            const float c = rsqrt_refined(fmaf(tt, tt, 1.0f));
+            const float sn = c * tt;
+            const float wr = sn * gr * rg;
+            const float wi = -sn * gi * rg;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                const float2 x = xs[k], v = y[k];
+                float2 ni, nj;
+                ni.x = fmaf(c, x.x, -fmaf(wr, v.x, -wi * v.y));
+                ni.y = fmaf(c, x.y, -fmaf(wr, v.y, wi * v.x));
+                nj.x = fmaf(c, v.x, fmaf(wr, x.x, wi * x.y));
+                nj.y = fmaf(c, v.y, fmaf(wr, x.y, -wi * x.x));
+                xs[k] = swap ? nj : ni;
+                Bs[swx<MP>(cn, q + G * k)] = swap ? ni : nj;
+            }
+            ++changed;
+        } else if (swap) {
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                Bs[swx<MP>(cn, q + G * k)] = xs[k];
+                xs[k] = y[k];
+            }
+            ++changed;
+        }
+        wave_lds_sync();
+        cn = cnn;
+        j = jn;
+    }
+#pragma unroll
+    for (int k = 0; k < NR; ++k) Bs[swx<MP>(cs, q + G * k)] = xs[k];
+    return changed;
+}
+
 // Sum over the 64 lanes of a wave; every lane gets the same bits.
 __device__ __forceinline__ float wave_sum(float v)
 {
@@ -770,12 +859,12 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         // eq.5 with p = 2 reads.  A failed check, or kSubMaxSweeps subspace sweeps without
         // convergence, returns to full sweeps (the full solve); so does a bin whose weakest
         // signal column holds less than the other columns' energy at the switch.
-        // A subspace sweep runs in wave 0 alone: round t rotates signal column i against
-        // non-signal column (t + i) mod (rk - Ns), i < Ns (distinct partners: 2 Ns <= rk), then
-        // the pairs inside S one at a time; a wave's LDS accesses complete in issue order, so
-        // the rounds need no workgroup barrier.
+        // A subspace sweep runs in wave 0 alone: lane group i < Ns takes signal column i against
+        // the non-signal columns from slot i floor((rk - Ns) / Ns) on (sub_pass; the starting
+        // slots are at least two apart when rk >= 3 Ns), then the pairs inside S one at a time;
+        // a wave's LDS accesses complete in issue order, so no workgroup barrier is needed.
         const bool sub = sub_full >= 0 && sigf == nullptr && Uf == nullptr && Ns >= 1 &&
-                         Ns <= kSubMaxNs && 2 * Ns <= rk;
+                         Ns <= kSubMaxNs && 3 * Ns <= rk;
         int phase = 0;                               // 0 full, 1 subspace, 2 full after a fallback
         int sub_sweeps = 0;
         unsigned long long smask = 0ull;
@@ -828,23 +917,17 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                 if (phase == 1) {
                     if (tid < 64) {
                         const int nn = rk - Ns;
-                        const bool act = g < Ns;
-                        const int cs = act ? cinv[g] : 0;
-                        int j = g;                           // partner slot (t + g) mod nn
-                        for (int t = 0; t < nn; ++t) {
-                            if (act) {
-                                const int cn = clist[j];
-                                const bool rot =
-                                    nr_lo ? jacobi_pair_sorted<MP, G, RLO>(Bs, cs, cn, q, tol2)
-                                          : jacobi_pair_sorted<MP, G, R>(Bs, cs, cn, q, tol2);
-                                if (rot) {
-                                    rotated = 1;
-                                    if (q == 0) ++my_rot;
-                                }
-                                if (++j == nn) j = 0;
+                        if (g < Ns) {
+                            const int cs = cinv[g], j0 = g * (nn / Ns);
+                            const int ch =
+                                nr_lo ? sub_pass<MP, G, RLO>(Bs, cs, clist, nn, j0, q, tol2)
+                                      : sub_pass<MP, G, R>(Bs, cs, clist, nn, j0, q, tol2);
+                            if (ch) {
+                                rotated = 1;
+                                if (q == 0) my_rot += ch;
                             }
-                            wave_lds_sync();
                         }
+                        wave_lds_sync();
                         for (int a = 0; a + 1 < Ns; ++a)
                             for (int b = a + 1; b < Ns; ++b) {
                                 if (g == 0) {

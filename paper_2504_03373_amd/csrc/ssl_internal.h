@@ -245,8 +245,13 @@ hipError_t launch_jacobi(ssl_c64 *A, const int32_t *kstatus, int F, int M, int N
                          int32_t *bin_status, int32_t *conv, hipStream_t st,
                          ssl_c64 *U = nullptr, int sub_full = -1, ssl_c64 *Es = nullptr,
                          ssl_c128 *Esl = nullptr);
-// Full sweeps before the subspace phase of the localization paths (p = 2).
-constexpr int kSubFullSweeps = 1;
+// Full sweeps before the subspace phase (p = 2): none.  The signal set is chosen on the column
+// norms of X = R1^H, which the pivoted QR already grades, and only the pairs with a signal column
+// are ever visited (about 2.4 subspace sweeps instead of one full sweep and 1.3 subspace sweeps on
+// the 60-channel workload; a launch of many bins per CU, bound by VALU issue, runs about 6%
+// faster, a one-block launch, bound by the latency of the serial subspace rounds, about 6% slower).
+// The same value on every path keeps batched and one-block results bit-identical.
+constexpr int kSubFullSweeps = 0;
 // Warm-started solve: U [F][M][M] (column-major per bin) holds a unitary start on entry (the
 // previous solve's sorted singular vectors) and this solve's on exit; A is read only.
 hipError_t launch_jacobi_warm(const ssl_c64 *A, const int32_t *kstatus, int F, int M, int Ns,
