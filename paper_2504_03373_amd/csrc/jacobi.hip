@@ -441,30 +441,41 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
-// One signal column's part of a subspace sweep, by one lane group: column cs against the non-signal
-// columns nlist[j0], nlist[j0 + 1], .. (cyclically, nn of them), each visit as jacobi_pair_sorted.
-// The signal column stays in registers for the whole pass; each partner is loaded one visit ahead
-// and written back after its rotation.  Other groups of the same wave run the same pass for the
-// other signal columns from starting slots at least two apart (cyclically), so no partner is
-// loaded ahead while another group still has to rotate it, and every write reaches the LDS before
-// the wave's later reads (issue order; see wave_lds_sync).  Returns the number of visits that
-// changed the columns.
-template <int MP, int G, int NR>
-__device__ __forceinline__ int sub_pass(float2 *Bs, int cs, const int *nlist, int nn, int j0, int q,
-                                        double tol2)
+// Sum over aligned groups of GS lanes (GS = 4, 8, 16, 32 or 64); all lanes of a group get
+// identical bits (the cross-row steps add a lane's value to its partner's, which commutes).
+template <int GS>
+__device__ __forceinline__ float lane_sum(float v)
 {
+    v = group_sum<(GS < 16 ? GS : 16)>(v);
+    if (GS >= 32) v += __shfl_xor(v, 16);
+    if (GS >= 64) v += __shfl_xor(v, 32);
+    return v;
+}
+
+// One signal column's part of a subspace sweep, by one group of GS lanes (qs = lane in group,
+// MP / GS rows each): column cs against the non-signal columns nlist[j0], nlist[j0 + 1], ..
+// (cyclically, nn of them), each visit as jacobi_pair_sorted.  The signal column stays in
+// registers for the whole pass; each partner is loaded, rotated and written back.  The other
+// groups of the same wave run the same pass for the other signal columns from starting slots at
+// least two apart (cyclically), so that no two groups visit a column in the same visit step, and
+// every write reaches the LDS before the wave's later reads (issue order; see wave_lds_sync).
+// A group spans 16 to 64 lanes (one wave holds all Ns <= 3 passes), so a visit costs few
+// instructions per lane.  Returns the number of visits that changed the columns.
+template <int MP, int GS>
+__device__ __forceinline__ int sub_pass(float2 *Bs, int cs, const int *nlist, int nn, int j0,
+                                        int qs, double tol2)
+{
+    constexpr int NR = MP / GS;
     float2 xs[NR], y[NR];
 #pragma unroll
-    for (int k = 0; k < NR; ++k) xs[k] = Bs[swx<MP>(cs, q + G * k)];
+    for (int k = 0; k < NR; ++k) xs[k] = Bs[swx<MP>(cs, qs + GS * k)];
     int j = j0;
-    int cn = nlist[j];
     int changed = 0;
     for (int t = 0; t < nn; ++t) {
-        int jn = j + 1;
-        if (jn == nn) jn = 0;
-        const int cnn = nlist[jn];
+        const int cn = nlist[j];
+        if (++j == nn) j = 0;
 #pragma unroll
-        for (int k = 0; k < NR; ++k) y[k] = Bs[swx<MP>(cn, q + G * k)];
+        for (int k = 0; k < NR; ++k) y[k] = Bs[swx<MP>(cn, qs + GS * k)];
         float al = 0.f, be = 0.f, gr = 0.f, gi = 0.f;
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
@@ -473,10 +484,10 @@ __device__ __forceinline__ int sub_pass(float2 *Bs, int cs, const int *nlist, in
             gr = fmaf(xs[k].x, y[k].x, fmaf(xs[k].y, y[k].y, gr));
             gi = fmaf(xs[k].x, y[k].y, fmaf(-xs[k].y, y[k].x, gi));
         }
-        al = group_sum<G>(al);
-        be = group_sum<G>(be);
-        gr = group_sum<G>(gr);
-        gi = group_sum<G>(gi);
+        al = lane_sum<GS>(al);
+        be = lane_sum<GS>(be);
+        gr = lane_sum<GS>(gr);
+        gi = lane_sum<GS>(gi);
         const bool swap = be > al;
         const double g2 = (double)gr * gr + (double)gi * gi;
         const double ab = (double)al * be;
@@ -508,23 +519,21 @@ __device__ __forceinline__ int sub_pass(float2 *Bs, int cs, const int *nlist, in
                 nj.x = fmaf(c, v.x, fmaf(wr, x.x, wi * x.y));
                 nj.y = fmaf(c, v.y, fmaf(wr, x.y, -wi * x.x));
                 xs[k] = swap ? nj : ni;
-                Bs[swx<MP>(cn, q + G * k)] = swap ? ni : nj;
+                Bs[swx<MP>(cn, qs + GS * k)] = swap ? ni : nj;
             }
             ++changed;
         } else if (swap) {
 #pragma unroll
             for (int k = 0; k < NR; ++k) {
-                Bs[swx<MP>(cn, q + G * k)] = xs[k];
+                Bs[swx<MP>(cn, qs + GS * k)] = xs[k];
                 xs[k] = y[k];
             }
             ++changed;
         }
         wave_lds_sync();
-        cn = cnn;
-        j = jn;
     }
 #pragma unroll
-    for (int k = 0; k < NR; ++k) Bs[swx<MP>(cs, q + G * k)] = xs[k];
+    for (int k = 0; k < NR; ++k) Bs[swx<MP>(cs, qs + GS * k)] = xs[k];
     return changed;
 }
 
@@ -859,10 +868,11 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         // eq.5 with p = 2 reads.  A failed check, or kSubMaxSweeps subspace sweeps without
         // convergence, returns to full sweeps (the full solve); so does a bin whose weakest
         // signal column holds less than the other columns' energy at the switch.
-        // A subspace sweep runs in wave 0 alone: lane group i < Ns takes signal column i against
-        // the non-signal columns from slot i floor((rk - Ns) / Ns) on (sub_pass; the starting
-        // slots are at least two apart when rk >= 3 Ns), then the pairs inside S one at a time;
-        // a wave's LDS accesses complete in issue order, so no workgroup barrier is needed.
+        // A subspace sweep runs in wave 0 alone: its lane group i < Ns (64 / 32 / 16 lanes for
+        // Ns = 1 / 2 / 3) takes signal column i against the non-signal columns from slot
+        // i floor((rk - Ns) / Ns) on (sub_pass; the starting slots are at least two apart when
+        // rk >= 3 Ns), then the pairs inside S one at a time; a wave's LDS accesses complete in
+        // issue order, so no workgroup barrier is needed.
         const bool sub = sub_full >= 0 && sigf == nullptr && Uf == nullptr && Ns >= 1 &&
                          Ns <= kSubMaxNs && 3 * Ns <= rk;
         int phase = 0;                               // 0 full, 1 subspace, 2 full after a fallback
@@ -916,15 +926,21 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                 int rotated = 0;
                 if (phase == 1) {
                     if (tid < 64) {
+                        // GS lanes per signal column: 64, 32 or 16 for Ns = 1, 2, 3 (at most MP)
+                        constexpr int G1 = MP < 64 ? MP : 64, G2 = MP < 32 ? MP : 32,
+                                      G3 = MP < 16 ? MP : 16;
                         const int nn = rk - Ns;
-                        if (g < Ns) {
-                            const int cs = cinv[g], j0 = g * (nn / Ns);
+                        const int gs = Ns == 1 ? G1 : (Ns == 2 ? G2 : G3);
+                        const int i = tid / gs, qs = tid % gs;
+                        if (i < Ns) {
+                            const int cs = cinv[i], j0 = i * (nn / Ns);
                             const int ch =
-                                nr_lo ? sub_pass<MP, G, RLO>(Bs, cs, clist, nn, j0, q, tol2)
-                                      : sub_pass<MP, G, R>(Bs, cs, clist, nn, j0, q, tol2);
+                                Ns == 1 ? sub_pass<MP, G1>(Bs, cs, clist, nn, j0, qs, tol2)
+                                : Ns == 2 ? sub_pass<MP, G2>(Bs, cs, clist, nn, j0, qs, tol2)
+                                          : sub_pass<MP, G3>(Bs, cs, clist, nn, j0, qs, tol2);
                             if (ch) {
                                 rotated = 1;
-                                if (q == 0) my_rot += ch;
+                                if (qs == 0) my_rot += ch;
                             }
                         }
                         wave_lds_sync();
