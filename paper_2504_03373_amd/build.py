@@ -21,11 +21,16 @@ FLAGS = [
     "-Wall", "-Wno-unused-function",
     "-I", os.path.join(ROOT, "include"),
 ]
+# Per-source flags.  jacobi.hip: LDS atomics stay one instruction per lane.  The compiler's default
+# rewrites an atomic max issued by several lanes of a wave (the pivot keys of the QR step: one lane
+# per column group) into a scalar loop over the active lanes with two readlanes each, which cost
+# more VALU issue than the LDS unit spends on the lanes' atomics (the Jacobi launch ran 11% longer).
+EXTRA = {"jacobi.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, src.replace(".hip", ".o"))
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:
