@@ -537,6 +537,37 @@ __device__ __forceinline__ int sub_pass(float2 *Bs, int cs, const int *nlist, in
     return changed;
 }
 
+// One vector x through the reflectors H_{rk-1} .. H_0 of the pivoted QR (U = Q u), by one group of
+// GS lanes, qs = lane in group, rows qs + GS j in x[j] (j < MP / GS; entries beyond are unused).
+// Reflector k is column k of V (zero outside rows k..M-1), tau[k] its factor.
+template <int MP, int GS, int NX>
+__device__ __forceinline__ void back_pass(const float2 *V, const float *tau, int rk, int qs,
+                                          float2 (&x)[NX])
+{
+    constexpr int NR = MP / GS;
+    static_assert(NR <= NX, "row slots");
+    for (int k = rk - 1; k >= 0; --k) {
+        const float tk = tau[k];
+        float2 v[NR];
+        float ar = 0.f, ai = 0.f;
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            if (GS * (j + 1) <= k) continue;         // slot entirely above the reflector
+            v[j] = V[at<MP>(k, qs + GS * j)];
+            ar = fmaf(v[j].x, x[j].x, fmaf(v[j].y, x[j].y, ar));
+            ai = fmaf(v[j].x, x[j].y, fmaf(-v[j].y, x[j].x, ai));
+        }
+        ar = lane_sum<GS>(ar) * tk;
+        ai = lane_sum<GS>(ai) * tk;
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            if (GS * (j + 1) <= k) continue;
+            x[j].x = fmaf(-v[j].x, ar, fmaf(v[j].y, ai, x[j].x));
+            x[j].y = fmaf(-v[j].x, ai, fmaf(-v[j].y, ar, x[j].y));
+        }
+    }
+}
+
 // Sum over the 64 lanes of a wave; every lane gets the same bits.
 __device__ __forceinline__ float wave_sum(float v)
 {
@@ -1194,12 +1225,11 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         // U's columns move to registers (a group owns at most two: c = g, g + NG), the reflectors
         // take the buffer (stored with zeros outside rows k..M-1, so their loads need no row
         // test), and each group takes its columns through every reflector with no barrier.  With
-        // sig_only group g < Ns takes signal vector g (column perm[g]) and the other groups idle.
-        {
-            __syncthreads();                            // perm is complete
-            const int c0 = sig_only ? (g < Ns ? perm[g] : 0) : g, c1 = g + NG;
-            const bool h0 = sig_only ? g < Ns : (g < NG && c0 < M);
-            const bool h1 = !sig_only && g < NG && c1 < M;
+        // sig_only the Ns signal vectors (columns perm[0 .. Ns)) alone pass, in wave 0 with 64 / 32
+        // / 16 lanes each (back_pass), the other waves idle.
+        if (!sig_only) {
+            const int c0 = g, c1 = g + NG;
+            const bool h0 = g < NG && c0 < M, h1 = g < NG && c1 < M;
             float2 x0[R], x1[R];
 #pragma unroll
             for (int j = 0; j < R; ++j) {
@@ -1212,8 +1242,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
                 X[at<MP>(k, r)] = (r >= k && r < M) ? Af[k * M + r] : make_float2(0.f, 0.f);
             }
             __syncthreads();
-            const bool busy = !sig_only || __any(h0);   // uniform over the wave
-            for (int k = rk - 1; k >= 0 && busy; --k) {
+            for (int k = rk - 1; k >= 0; --k) {
                 const float tk = tau[k];
                 float2 v[R];
                 float ar = 0.f, ai = 0.f, br = 0.f, bi = 0.f;
@@ -1244,6 +1273,38 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
             for (int j = 0; j < R; ++j) {
                 if (h0) X[at<MP>(c0, q + G * j)] = x0[j];
                 if (h1) X[at<MP>(c1, q + G * j)] = x1[j];
+            }
+            __syncthreads();
+        }
+        if (sig_only) {
+            __syncthreads();                            // perm is complete
+            constexpr int G1 = MP < 64 ? MP : 64, G2 = MP < 32 ? MP : 32, G3 = MP < 16 ? MP : 16;
+            const int gs = Ns == 1 ? G1 : (Ns == 2 ? G2 : G3);
+            const int i = tid / gs, qs = tid % gs;
+            const bool mine = tid < 64 && i < Ns;
+            const int c = mine ? perm[i] : 0;
+            float2 x[MP / G3];
+#pragma unroll
+            for (int j = 0; j < MP / G3; ++j) {
+                const int r = qs + gs * j;
+                x[j] = (mine && r < MP) ? X[at<MP>(c, r)] : make_float2(0.f, 0.f);
+            }
+            __syncthreads();
+            for (int e = tid; e < rk * MP; e += NT) {
+                const int k = e / MP, r = e - k * MP;
+                X[at<MP>(k, r)] = (r >= k && r < M) ? Af[k * M + r] : make_float2(0.f, 0.f);
+            }
+            __syncthreads();
+            if (mine) {
+                if (Ns == 1) back_pass<MP, G1, MP / G3>(X, tau, rk, qs, x);
+                else if (Ns == 2) back_pass<MP, G2, MP / G3>(X, tau, rk, qs, x);
+                else back_pass<MP, G3, MP / G3>(X, tau, rk, qs, x);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < MP / G3; ++j) {
+                const int r = qs + gs * j;
+                if (mine && r < MP) X[at<MP>(c, r)] = x[j];
             }
             __syncthreads();
         }
