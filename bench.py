@@ -578,6 +578,8 @@ def main() -> int:
     def measure(name: str, with_h2d: bool, conv: bool = True) -> dict:
         prec = PREC[name]
         H = table(name)
+        # FP32 with Ns <= 3: eq.5 through the signal subspace (the library's default projection)
+        sig = name == "fp32" and 1 <= Ns <= 3
         # Jacobi sweep / rotation counts for the flop model: same kernel variant, same inputs,
         # deterministic, so they are those of the timed launches.
         R = torch.zeros((F, M, M), dtype=torch.complex64, device=dev)
@@ -593,9 +595,11 @@ def main() -> int:
                 lanes, jms = S.ssl_autotune_jacobi(ctx, R, noise, Ns, nblocks=B, reps=2)
                 tuning["jacobi_lanes"] = lanes
                 tuning["jacobi_ms"] = {str(k): round(v, 4) for k, v in jms.items()}
-            waves, sms = S.ssl_autotune_steer(ctx, H, prec, En, Ns, p=2, nblocks=B, reps=3)
-            tuning.setdefault("steer_waves", {})[name] = waves
-            tuning.setdefault("steer_ms", {})[name] = {str(k): round(v, 4) for k, v in sms.items()}
+            if not sig:                  # the signal-subspace projection has no tile variants
+                waves, sms = S.ssl_autotune_steer(ctx, H, prec, En, Ns, p=2, nblocks=B, reps=3)
+                tuning.setdefault("steer_waves", {})[name] = waves
+                tuning.setdefault("steer_ms", {})[name] = {str(k): round(v, 4)
+                                                           for k, v in sms.items()}
         # ssl_gsvd without sigma under SSL_STOP_ALSO_GSVD runs the Jacobi solve exactly as the
         # p = 2 localization does (stopped at the noise subspace)
         conv_all = []
@@ -606,8 +610,6 @@ def main() -> int:
             conv_all.append(conv_t.cpu().numpy().copy())
         S.ssl_ctx_set_stop(ctx, S.SSL_STOP_LOCALIZE)
         del R, En
-        # FP32 with Ns <= 3: eq.5 through the signal subspace (the library's default projection)
-        sig = name == "fp32" and 1 <= Ns <= 3
         jflops = float(sum(jacobi_flops(M, c[:, 0], c[:, 1], c[:, 2], Ns, True, sig)
                            for c in conv_all))
         descs = [S.block_desc(Xs[b], noise, H, w.grid.n_az, w.grid.n_el, Ns, pk[b], pv[b],
