@@ -15,7 +15,8 @@
 // Workgroup = 4 waves x 16 directions of one bin; a wave keeps its 16 rows of H in registers
 // (complex64) and computes g for 16 columns at once on v_mfma_f64_16x16x4f64 -- the signal vectors
 // of 16 / Ns_max blocks sharing the steering table, staged in LDS -- with
-//   Re g = sum a c + b d,   Im g = sum a d - b c     (h = a + ib, e = c + id, FP64 operands).
+//   Re g = sum a c + b d,   Im g = sum b c - a d     (h = a + ib, e = c + id, FP64 operands:
+// g_s = e_s^H h, the conjugate of h^H e_s, so that y = L^{-1} g with L from E_s^H E_s = L L^H).
 // The 16 x 16 result goes through LDS so that each lane finishes whole (direction, block) items.
 #include "ssl_internal.h"
 
@@ -99,8 +100,8 @@ __device__ __forceinline__ void sig_tile(const float2 *__restrict__ Hf, int D, i
                 const double a = ha[q].x, b = ha[q].y, c = ev.x, d = ev.y;
                 gre = __builtin_amdgcn_mfma_f64_16x16x4f64(a, c, gre, 0, 0, 0);
                 gre = __builtin_amdgcn_mfma_f64_16x16x4f64(b, d, gre, 0, 0, 0);
-                gim = __builtin_amdgcn_mfma_f64_16x16x4f64(a, d, gim, 0, 0, 0);
-                gim = __builtin_amdgcn_mfma_f64_16x16x4f64(-b, c, gim, 0, 0, 0);
+                gim = __builtin_amdgcn_mfma_f64_16x16x4f64(b, c, gim, 0, 0, 0);
+                gim = __builtin_amdgcn_mfma_f64_16x16x4f64(-a, d, gim, 0, 0, 0);
             }
         }
         // FP64 result layout: element e of lane l is row l / 16 + 4 e, column l % 16

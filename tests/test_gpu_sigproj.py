@@ -170,3 +170,41 @@ def test_projection_mode_errors(S, ctx):
         S.ssl_ctx_set_projection(ctx, 2)
     assert e.value.code == S.SSL_ERR_ARG
     assert S.ssl_ctx_get_projection(ctx) == S.SSL_PROJ_SIGNAL
+
+
+@pytest.mark.parametrize("mode", ["gsvd", "sevd"])
+def test_signal_form_per_bin(S, ctx, mode):
+    """P of single bins (the table zero in every other bin, so that P-bar is that bin's P) against
+    the oracle's per-bin P, for both forms: a per-bin check sees what the sum over 257 bins can
+    average out (a wrong conjugation of E_s^H h left P-bar within 3e-7 but single bins at 2e-4).
+    Low bins, where the strongest source dominates (sigma_1 / sigma_2 up to about 370 in SEVD mode),
+    and a few others."""
+    import torch
+    w = synth.workload_paper(n_blocks=1)
+    X, _, _ = w.block(0)
+    H = w.steering_table()
+    if mode == "gsvd":
+        n, K = noise_handle(S, ctx, w)
+    else:
+        n, K = None, np.broadcast_to(np.eye(w.M, dtype=np.complex128), (w.F, w.M, w.M)).copy()
+    r = oracle.localize(X, K, H, w.grid.n_az, w.grid.n_el, w.Ns, nthreads=16, want_P=True)
+    Xd = to_dev(X)
+    worst = {}
+    for f in (1, 2, 7, 35, 183, 233):
+        Hm = np.zeros_like(H)
+        Hm[f] = H[f]
+        Hd = to_dev(Hm)
+        for form in ("signal", "noise"):
+            S.ssl_ctx_set_projection(ctx, S.SSL_PROJ_SIGNAL if form == "signal" else S.SSL_PROJ_NOISE)
+            try:
+                g = single(S, ctx, w, Xd, n, Hd, w.Ns)
+            finally:
+                S.ssl_ctx_set_projection(ctx, S.SSL_PROJ_SIGNAL)
+            assert np.all(g["st"] == 0)
+            rel = float(np.max(np.abs(g["Pbar"].astype(np.float64) - r["P"][f]) / r["P"][f]))
+            worst[form] = max(worst.get(form, 0.0), rel)
+            say(f"  {mode} bin {f} {form} form: P rel {rel:.2e}")
+            assert rel <= 1e-4, (f, form, rel)
+    say(f"  {mode}: worst per-bin P error {worst}")
+    if n is not None:
+        S.ssl_noise_destroy(n)
