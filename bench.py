@@ -61,20 +61,27 @@ def jacobi_flops(M: int, sweeps, rotations, rank, Ns: int = 0, sub: bool = False
     pairs with a member in the signal set (a bin that fell back to full sweeps is counted the same
     way, which undercounts it); the r - Ns complement vectors each pass Ns reflectors (16 r), and
     W is not normalised.
-    sig: only the Ns signal vectors are formed (eq.5 through the signal subspace): no complement,
-    and the back-transformation U = Q U_R covers Ns columns, 16 (M - k) Ns per reflector."""
+    sig: only the Ns signal vectors are formed (eq.5 through the signal subspace): the sweeps run
+    on Z = R~^H (M x r, no second QR, columns of length M: 16M per pair visit, 20M per rotation),
+    the signal vectors are A w_s (8 M^2 Ns), and neither the complement nor the back-transformation
+    runs."""
     import numpy as np
     total = 0.0
     for s, rot, r in zip(np.asarray(sweeps), np.asarray(rotations), np.asarray(rank)):
         r = int(r)
         k = np.arange(r, dtype=np.float64)
         n = M - k
+        if sig:
+            visits = float(s) * (Ns * (r - Ns) + Ns * (Ns - 1) / 2.0) if sub and r > Ns \
+                else float(s) * r * (r - 1) / 2.0
+            total += float(np.sum(20.0 * n * (n - 1))) + visits * 16.0 * M + \
+                float(rot) * 20.0 * M + 8.0 * M * M * Ns
+            continue
         total += float(np.sum(20.0 * n * (n - 1)) + np.sum(16.0 * n * (r - k - 1))
-                       + np.sum(16.0 * n * (Ns if sig else M)))
+                       + np.sum(16.0 * n * M))
         if sub and r > Ns:
             visits = float(s) * (Ns * (r - Ns) + Ns * (Ns - 1) / 2.0)
-            total += visits * 16.0 * r + float(rot) * 20.0 * r + \
-                (0.0 if sig else (r - Ns) * Ns * 16.0 * r)
+            total += visits * 16.0 * r + float(rot) * 20.0 * r + (r - Ns) * Ns * 16.0 * r
         else:
             total += float(s) * r * (r - 1) / 2.0 * 16.0 * r + float(rot) * 20.0 * r + 6.0 * r * r
     return total
@@ -580,8 +587,6 @@ def main() -> int:
         H = table(name)
         # FP32 with Ns <= 3: eq.5 through the signal subspace (the library's default projection)
         sig = name == "fp32" and 1 <= Ns <= 3
-        # Jacobi sweep / rotation counts for the flop model: same kernel variant, same inputs,
-        # deterministic, so they are those of the timed launches.
         R = torch.zeros((F, M, M), dtype=torch.complex64, device=dev)
         En = torch.zeros((F, M - Ns, M), dtype=torch.complex64, device=dev)
         conv_t = torch.zeros((F, 3), dtype=torch.int32, device=dev)
@@ -600,16 +605,18 @@ def main() -> int:
                 tuning.setdefault("steer_waves", {})[name] = waves
                 tuning.setdefault("steer_ms", {})[name] = {str(k): round(v, 4)
                                                            for k, v in sms.items()}
-        # ssl_gsvd without sigma under SSL_STOP_ALSO_GSVD runs the Jacobi solve exactly as the
-        # p = 2 localization does (stopped at the noise subspace)
-        conv_all = []
-        S.ssl_ctx_set_stop(ctx, S.SSL_STOP_ALSO_GSVD)
-        for b in range(B if conv else 0):
-            S.ssl_corr_accum(ctx, Xs[b], 1.0 / T, 0, prec, R)
-            S.ssl_gsvd(ctx, R, noise, Ns, En, None, None, conv_t, 0)
-            conv_all.append(conv_t.cpu().numpy().copy())
-        S.ssl_ctx_set_stop(ctx, S.SSL_STOP_LOCALIZE)
         del R, En
+        # Jacobi sweep / rotation counts for the flop model, from one untimed batch step with the
+        # per-bin statistics requested (same kernels, same inputs, deterministic: the counts of
+        # the timed launches)
+        conv_all = []
+        if conv:
+            cv = torch.zeros((B, F, 3), dtype=torch.int32, device=dev)
+            cdescs = [S.block_desc(Xs[b], noise, H, w.grid.n_az, w.grid.n_el, Ns, pk[b], pv[b],
+                                   Pbar[b], st[b], cv[b]) for b in range(B)]
+            S.ssl_localize_batch(ctx, cdescs, prec, 2)
+            conv_all = list(cv.cpu().numpy())
+            del cv, cdescs
         jflops = float(sum(jacobi_flops(M, c[:, 0], c[:, 1], c[:, 2], Ns, True, sig)
                            for c in conv_all))
         descs = [S.block_desc(Xs[b], noise, H, w.grid.n_az, w.grid.n_el, Ns, pk[b], pv[b],

@@ -333,6 +333,8 @@ typedef struct {
     float *peak_val;           /* [Ns] out */
     float *Pbar;               /* [D] out or NULL */
     int32_t *bin_status;       /* [F] out or NULL */
+    int32_t *conv;             /* [F][3] out or NULL: per bin the Jacobi solve's sweeps,
+                                  rotations and numerical rank (as ssl_gsvd's conv) */
 } ssl_block_desc;
 
 /* Whole path (as ssl_localize) for nblocks blocks of possibly different shapes, in one set of

@@ -55,7 +55,8 @@ class BlockDesc(ctypes.Structure):
                 ("F", ctypes.c_int), ("T", ctypes.c_int), ("M", ctypes.c_int), ("Ns", ctypes.c_int),
                 ("K", ctypes.c_void_p), ("H", ctypes.c_void_p), ("n_az", ctypes.c_int),
                 ("n_el", ctypes.c_int), ("peaks", ctypes.c_void_p), ("peak_val", ctypes.c_void_p),
-                ("Pbar", ctypes.c_void_p), ("bin_status", ctypes.c_void_p)]
+                ("Pbar", ctypes.c_void_p), ("bin_status", ctypes.c_void_p),
+                ("conv", ctypes.c_void_p)]
 KERNELS = ["corr", "noise", "whiten", "jacobi", "steer", "binsum"]
 
 
@@ -442,14 +443,16 @@ def ssl_localize_noalloc_bytes(F, M, Ns, D):
     return int(lib().ssl_localize_noalloc_bytes(F, M, Ns, D))
 
 
-def block_desc(X, noise, H, n_az, n_el, Ns, peaks, peak_val, Pbar=None, bin_status=None):
-    """One ssl_block_desc for ssl_localize_batch (X: complex64 device tensor [F][T][M])."""
+def block_desc(X, noise, H, n_az, n_el, Ns, peaks, peak_val, Pbar=None, bin_status=None,
+               conv=None):
+    """One ssl_block_desc for ssl_localize_batch (X: complex64 device tensor [F][T][M]; conv:
+    optional int32 [F][3] device tensor for the Jacobi statistics)."""
     F, T, M = X.shape
     sF, sT, sM = X.stride()
     if sM != 1:
         raise ValueError("X must be contiguous along M")
     return BlockDesc(_ptr(X), sF, sT, F, T, M, Ns, noise, _ptr(H), n_az, n_el, _ptr(peaks),
-                     _ptr(peak_val), _ptr(Pbar), _ptr(bin_status))
+                     _ptr(peak_val), _ptr(Pbar), _ptr(bin_status), _ptr(conv))
 
 
 def ssl_localize_batch(ctx, descs, prec, p, stream=None):

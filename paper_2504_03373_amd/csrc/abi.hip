@@ -1747,6 +1747,7 @@ ssl_status ssl_localize_batch(ssl_ctx ctx, const ssl_block_desc *descs, int nblo
         w += align256(F * 6 * sizeof(ssl_c128));
         B.peaks = d.peaks;
         B.peak_val = d.peak_val;
+        B.conv = d.conv;
         c_corr[b] = corr_class(d.M);
         c_wh[b] = whiten_class(d.M);
         c_jac[b] = jacobi_class(d.M);

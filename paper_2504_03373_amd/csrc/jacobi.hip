@@ -73,6 +73,15 @@ __device__ __forceinline__ float group_sum(float v)
     return v;
 }
 
+// The same in FP64 (cross-lane moves of both halves through __shfl_xor).
+template <int G>
+__device__ __forceinline__ double group_sum_f64(double v)
+{
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
 __device__ __forceinline__ bool finite2(float2 v) { return isfinite(v.x) && isfinite(v.y); }
 
 // 1/sqrt(x) for normal x > 0: hardware estimate plus one Newton-Raphson step.
@@ -537,37 +546,6 @@ __device__ __forceinline__ int sub_pass(float2 *Bs, int cs, const int *nlist, in
     return changed;
 }
 
-// One vector x through the reflectors H_{rk-1} .. H_0 of the pivoted QR (U = Q u), by one group of
-// GS lanes, qs = lane in group, rows qs + GS j in x[j] (j < MP / GS; entries beyond are unused).
-// Reflector k is column k of V (zero outside rows k..M-1), tau[k] its factor.
-template <int MP, int GS, int NX>
-__device__ __forceinline__ void back_pass(const float2 *V, const float *tau, int rk, int qs,
-                                          float2 (&x)[NX])
-{
-    constexpr int NR = MP / GS;
-    static_assert(NR <= NX, "row slots");
-    for (int k = rk - 1; k >= 0; --k) {
-        const float tk = tau[k];
-        float2 v[NR];
-        float ar = 0.f, ai = 0.f;
-#pragma unroll
-        for (int j = 0; j < NR; ++j) {
-            if (GS * (j + 1) <= k) continue;         // slot entirely above the reflector
-            v[j] = V[at<MP>(k, qs + GS * j)];
-            ar = fmaf(v[j].x, x[j].x, fmaf(v[j].y, x[j].y, ar));
-            ai = fmaf(v[j].x, x[j].y, fmaf(-v[j].y, x[j].x, ai));
-        }
-        ar = lane_sum<GS>(ar) * tk;
-        ai = lane_sum<GS>(ai) * tk;
-#pragma unroll
-        for (int j = 0; j < NR; ++j) {
-            if (GS * (j + 1) <= k) continue;
-            x[j].x = fmaf(-v[j].x, ar, fmaf(v[j].y, ai, x[j].x));
-            x[j].y = fmaf(-v[j].x, ai, fmaf(-v[j].y, ar, x[j].y));
-        }
-    }
-}
-
 // Sum over the 64 lanes of a wave; every lane gets the same bits.
 __device__ __forceinline__ float wave_sum(float v)
 {
@@ -584,8 +562,10 @@ __device__ __forceinline__ float wave_sum(float v)
 // null, 1 <= Ns <= kSubMaxNs) asks for the noise subspace alone: E_n is then an orthonormal basis
 // of the span of the M - Ns smallest left singular vectors (what eq.5 with p = 2 depends on), not
 // the singular vectors themselves; see the subspace phase below.  Esf ([Ns][M], or null) receives
-// the signal vectors: the Ns leading sorted singular vectors, or with the subspace stop an
-// orthonormal basis of their span (the normalised signal columns).  Lf ([6], with Esf, Ns <= 3,
+// the signal vectors: the Ns leading sorted singular vectors, or with the subspace stop a basis of
+// their span of unit vectors (orthogonal to the rotation tolerance); with Enf null (then Esf is
+// set and 1 <= Ns <= 3) unit vectors A w_s spanning that subspace, not orthogonal (see the
+// signal vectors without Q below).  Lf ([6], with Esf, Ns <= 3,
 // or null): the inverse L^{-1} of the Cholesky factor of their Gram matrix E_s^H E_s, computed in
 // FP64 from the stored complex64 values, lower triangle by rows (00, 10, 11, 20, 21, 22), zero if
 // the bin failed: the projector onto span E_s is E_s (E_s^H E_s)^{-1} E_s^H exactly.
@@ -771,7 +751,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         // Z[x][c] = conj(R[c][pos x]).  R[c][pos x] sits at (column x, row c), so Z is a masked
         // conjugate transpose: each thread exchanges the pair (c, x), (x, c) it owns.
         if (tid == 0) rank_s = rk;
-        for (int e = tid; e < rk * MP; e += NT) {          // reflector k = e / MP, row e % MP
+        for (int e = tid; e < rk * MP && !sig_only; e += NT) {   // reflector k = e / MP, row e % MP
             const int k = e / MP, r = e % MP;
             if (r >= k && r < M) Af[k * M + r] = (r == k) ? vhead[k] : X[at<MP>(colmap[k], r)];
         }
@@ -799,59 +779,63 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         // ---- 3. Z = Q1 R1 (Householder, no pivoting; Q1 is not needed), then X = R1^H --------
         // R = R1^H Q1^H, so R's left singular vectors are X's; X's column Gram X^H X = R1 R1^H
         // is closer still to diagonal than R R^H.  The trailing norm of the next column comes out
-        // of each update pass.
-        if (g == 0) {
-            float s = 0.f;
+        // of each update pass.  With sig_only none of this: the sweeps run on Z itself (see the
+        // signal vectors below).
+        if (!sig_only) {
+            if (g == 0) {
+                float s = 0.f;
 #pragma unroll
-            for (int j = 0; j < R; ++j) {
-                const float2 v = X[at<MP>(0, q + G * j)];
-                s = fmaf(v.x, v.x, fmaf(v.y, v.y, s));
-            }
-            s = group_sum<G>(s);
-            if (q == 0) nrm1[0] = s;
-        }
-        __syncthreads();
-        for (int k = 0; k < rk; ++k) {
-            const float nx = sqrtf(nrm1[k]);
-            const float2 xk = X[at<MP>(k, k)];
-            const float axk = sqrtf(fmaf(xk.x, xk.x, xk.y * xk.y));
-            const float rax = __builtin_amdgcn_rcpf(axk);
-            const float2 ph = axk > 0.f ? make_float2(xk.x * rax, xk.y * rax) : make_float2(1.f, 0.f);
-            const float tk = nx > 0.f ? __builtin_amdgcn_rcpf(nx * (nx + axk)) : 0.0f;
-            const float2 vk = make_float2(ph.x * (axk + nx), ph.y * (axk + nx));
-            if (tid == 0) diag1[k] = make_float2(-ph.x * nx, -ph.y * nx);
-            // columns k + 1 + g and k + 1 + g + NG, as in the pivoted QR
-            const int c0 = k + 1 + g;
-            if (g < NG && c0 < rk) {
-                const int c1 = c0 + NG;
-                const bool two = c1 < rk;
-                if (__any(two)) {
-                    float tn0, tn1;
-                    apply_reflector2<MP, G>(k, vk, k, tk, X, c0, two ? c1 : c0, two, q,
-                                            tn0, tn1);
-                    if (c0 == k + 1 && q == 0) nrm1[c0] = tn0;
-                } else {
-                    const float tn = apply_reflector<MP, G>(k, vk, k, tk, X, c0, M, q);
-                    if (c0 == k + 1 && q == 0) nrm1[c0] = tn;
+                for (int j = 0; j < R; ++j) {
+                    const float2 v = X[at<MP>(0, q + G * j)];
+                    s = fmaf(v.x, v.x, fmaf(v.y, v.y, s));
                 }
+                s = group_sum<G>(s);
+                if (q == 0) nrm1[0] = s;
+            }
+            __syncthreads();
+            for (int k = 0; k < rk; ++k) {
+                const float nx = sqrtf(nrm1[k]);
+                const float2 xk = X[at<MP>(k, k)];
+                const float axk = sqrtf(fmaf(xk.x, xk.x, xk.y * xk.y));
+                const float rax = __builtin_amdgcn_rcpf(axk);
+                const float2 ph = axk > 0.f ? make_float2(xk.x * rax, xk.y * rax)
+                                            : make_float2(1.f, 0.f);
+                const float tk = nx > 0.f ? __builtin_amdgcn_rcpf(nx * (nx + axk)) : 0.0f;
+                const float2 vk = make_float2(ph.x * (axk + nx), ph.y * (axk + nx));
+                if (tid == 0) diag1[k] = make_float2(-ph.x * nx, -ph.y * nx);
+                // columns k + 1 + g and k + 1 + g + NG, as in the pivoted QR
+                const int c0 = k + 1 + g;
+                if (g < NG && c0 < rk) {
+                    const int c1 = c0 + NG;
+                    const bool two = c1 < rk;
+                    if (__any(two)) {
+                        float tn0, tn1;
+                        apply_reflector2<MP, G>(k, vk, k, tk, X, c0, two ? c1 : c0, two, q,
+                                                tn0, tn1);
+                        if (c0 == k + 1 && q == 0) nrm1[c0] = tn0;
+                    } else {
+                        const float tn = apply_reflector<MP, G>(k, vk, k, tk, X, c0, M, q);
+                        if (c0 == k + 1 && q == 0) nrm1[c0] = tn;
+                    }
+                }
+                __syncthreads();
+            }
+            // X[i][c] = conj(R1[c][i]), R1[c][i] at (column i, row c) for i > c: masked transpose
+            for (int e = tid; e < MP * MP; e += NT) {
+                const int c = e / MP, i = e - c * MP;
+                if (c > i) continue;
+                const float2 o1 = X[at<MP>(i, c)], o2 = X[at<MP>(c, i)];
+                float2 n1 = make_float2(0.f, 0.f), n2 = make_float2(0.f, 0.f);
+                if (i < rk) {
+                    if (i > c) n1 = conj2(o1);               // X[i][c], below the diagonal
+                    else n1 = conj2(diag1[c]);               // i == c
+                }
+                (void)o2;                                    // X[c][i] (c < i) is above: zero
+                X[at<MP>(c, i)] = n1;
+                if (c != i) X[at<MP>(i, c)] = n2;
             }
             __syncthreads();
         }
-        // X[i][c] = conj(R1[c][i]), R1[c][i] at (column i, row c) for i > c: masked transpose
-        for (int e = tid; e < MP * MP; e += NT) {
-            const int c = e / MP, i = e - c * MP;
-            if (c > i) continue;
-            const float2 o1 = X[at<MP>(i, c)], o2 = X[at<MP>(c, i)];
-            float2 n1 = make_float2(0.f, 0.f), n2 = make_float2(0.f, 0.f);
-            if (i < rk) {
-                if (i > c) n1 = conj2(o1);               // X[i][c], below the diagonal
-                else n1 = conj2(diag1[c]);               // i == c
-            }
-            (void)o2;                                    // X[c][i] (c < i) is above: zero
-            X[at<MP>(c, i)] = n1;
-            if (c != i) X[at<MP>(i, c)] = n2;
-        }
-        __syncthreads();
 
         // ---- 4. one-sided Jacobi on X: X V = W, columns orthogonalised in place ----------------
         // The sweeps work on a swizzled copy of the layout (swx): each column's 8-row chunks are
@@ -886,7 +870,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         const int n_rounds = Me - 1 + (defer ? 3 : 0);
         // row slots per lane: R - 1 when they cover the rank (the 60-channel rank-50 case), else R
         constexpr int RLO = R > 1 ? R - 1 : 1;
-        const bool nr_lo = rk <= G * RLO;
+        const bool nr_lo = (sig_only ? M : rk) <= G * RLO;   // rows of X: rk, or M for Z
         // Subspace phase (sub_full >= 0): after sub_full full sweeps, S = the Ns columns of
         // largest norm; then only the pairs with a member in S are visited (jacobi_pair_sorted
         // for a signal / noise pair, so that S keeps the larger results), until such a sweep
@@ -1224,9 +1208,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         // ---- 6. U = Q U_R, reflectors applied last to first ----------------------------------
         // U's columns move to registers (a group owns at most two: c = g, g + NG), the reflectors
         // take the buffer (stored with zeros outside rows k..M-1, so their loads need no row
-        // test), and each group takes its columns through every reflector with no barrier.  With
-        // sig_only the Ns signal vectors (columns perm[0 .. Ns)) alone pass, in wave 0 with 64 / 32
-        // / 16 lanes each (back_pass), the other waves idle.
+        // test), and each group takes its columns through every reflector with no barrier.
         if (!sig_only) {
             const int c0 = g, c1 = g + NG;
             const bool h0 = g < NG && c0 < M, h1 = g < NG && c1 < M;
@@ -1276,35 +1258,55 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
             }
             __syncthreads();
         }
+        // ---- 6'. signal vectors without Q: E_s = A W_S --------------------------------------
+        // With sig_only the sweeps ran on Z = R~^H (R~ = R P^T: R's columns in physical order,
+        // A = Q R~): Z V = W makes W_S span the dominant right singular subspace of R~, A's (Q is
+        // unitary), so A W_S spans the Ns dominant left singular vectors of A, scaled by sigma^2
+        // (a step of power iteration: what the rotation tolerance leaves of the other directions
+        // is damped by their smaller singular values).  A is the input, still intact (nothing was
+        // parked in it), read row by row by groups of G lanes, scaled by 2^-ex as X was.  The
+        // sums run in FP64: A w_s for a weaker signal cancels the stronger ones' share of A, and
+        // FP32 sums would lose sigma_1 / sigma_s times the rounding of the result.  Each vector
+        // is normalised in FP32 (Lf below makes the projector exact); they go to diag, vhead,
+        // diag1, free by now.
         if (sig_only) {
             __syncthreads();                            // perm is complete
-            constexpr int G1 = MP < 64 ? MP : 64, G2 = MP < 32 ? MP : 32, G3 = MP < 16 ? MP : 16;
-            const int gs = Ns == 1 ? G1 : (Ns == 2 ? G2 : G3);
-            const int i = tid / gs, qs = tid % gs;
-            const bool mine = tid < 64 && i < Ns;
-            const int c = mine ? perm[i] : 0;
-            float2 x[MP / G3];
+            auto sv = [&](int k) -> float2 * { return k == 0 ? diag : (k == 1 ? vhead : diag1); };
+            const float sc = ldexpf(1.0f, -ex);
+            for (int r = g; r < M && g < NG; r += NG) {
+                double2 acc[kSubMaxNs];
 #pragma unroll
-            for (int j = 0; j < MP / G3; ++j) {
-                const int r = qs + gs * j;
-                x[j] = (mine && r < MP) ? X[at<MP>(c, r)] : make_float2(0.f, 0.f);
-            }
-            __syncthreads();
-            for (int e = tid; e < rk * MP; e += NT) {
-                const int k = e / MP, r = e - k * MP;
-                X[at<MP>(k, r)] = (r >= k && r < M) ? Af[k * M + r] : make_float2(0.f, 0.f);
-            }
-            __syncthreads();
-            if (mine) {
-                if (Ns == 1) back_pass<MP, G1, MP / G3>(X, tau, rk, qs, x);
-                else if (Ns == 2) back_pass<MP, G2, MP / G3>(X, tau, rk, qs, x);
-                else back_pass<MP, G3, MP / G3>(X, tau, rk, qs, x);
-            }
-            __syncthreads();
+                for (int k = 0; k < kSubMaxNs; ++k) acc[k] = make_double2(0.0, 0.0);
 #pragma unroll
-            for (int j = 0; j < MP / G3; ++j) {
-                const int r = qs + gs * j;
-                if (mine && r < MP) X[at<MP>(c, r)] = x[j];
+                for (int j = 0; j < R; ++j) {
+                    const int x = q + G * j;
+                    const float2 a = x < M ? Af[(size_t)r * M + x] : make_float2(0.f, 0.f);
+#pragma unroll
+                    for (int k = 0; k < kSubMaxNs; ++k) {
+                        if (k >= Ns) break;
+                        const float2 w = X[at<MP>(perm[k], x)];
+                        acc[k].x = fma((double)a.x, w.x, fma(-(double)a.y, w.y, acc[k].x));
+                        acc[k].y = fma((double)a.x, w.y, fma((double)a.y, w.x, acc[k].y));
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < kSubMaxNs; ++k) {
+                    if (k >= Ns) break;
+                    const double ar = group_sum_f64<G>(acc[k].x), ai = group_sum_f64<G>(acc[k].y);
+                    if (q == 0) sv(k)[r] = make_float2((float)(ar * sc), (float)(ai * sc));
+                }
+            }
+            __syncthreads();
+            if (tid < 64) {                             // wave 0: normalise, one row per lane
+                const int r = tid;
+#pragma unroll
+                for (int k = 0; k < kSubMaxNs; ++k) {
+                    if (k >= Ns) break;
+                    const float2 v = r < M ? sv(k)[r] : make_float2(0.f, 0.f);
+                    const float n2 = wave_sum(fmaf(v.x, v.x, v.y * v.y));
+                    const float inv = n2 > 0.f ? rsqrt_refined(n2) : 0.0f;
+                    if (r < MP) sv(k)[r] = make_float2(v.x * inv, v.y * inv);
+                }
             }
             __syncthreads();
         }
@@ -1317,10 +1319,15 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         const int c = e / MP, r = e % MP;
         if (r < M) Enf[c * M + r] = ok ? X[at<MP>(perm[Ns + c], r)] : make_float2(0.f, 0.f);
     }
-    if (Esf != nullptr)                                    // the signal vectors, [Ns][M]
+    // the signal vectors: diag, vhead, diag1 with sig_only, else columns perm[0 .. Ns) of U
+    auto sigvec = [&](int c, int r) -> float2 {
+        if (!sig_only) return X[at<MP>(perm[c], r)];
+        return c == 0 ? diag[r] : (c == 1 ? vhead[r] : diag1[r]);
+    };
+    if (Esf != nullptr)                                    // [Ns][M]
         for (int e = tid; e < Ns * MP; e += NT) {
             const int c = e / MP, r = e % MP;
-            if (r < M) Esf[c * M + r] = ok ? X[at<MP>(perm[c], r)] : make_float2(0.f, 0.f);
+            if (r < M) Esf[c * M + r] = ok ? sigvec(c, r) : make_float2(0.f, 0.f);
         }
     if (Esf != nullptr && Lf != nullptr && Ns <= 3 && tid < 64) {
         // Gram matrix of the stored signal vectors in FP64 (wave 0, one row per lane), then the
@@ -1329,7 +1336,7 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         double2 e[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const float2 v = (ok && k < Ns && r < M) ? X[at<MP>(perm[k], r)] : make_float2(0.f, 0.f);
+            const float2 v = (ok && k < Ns && r < M) ? sigvec(k, r) : make_float2(0.f, 0.f);
             e[k] = make_double2(v.x, v.y);
         }
         double gr[6], gi[6];                       // Gamma_st = e_s^H e_t, index t (t + 1) / 2 + s
@@ -1455,8 +1462,8 @@ __attribute__((amdgpu_waves_per_eu(JacobiCfg<MP, G>::WAVES_PER_EU))) void jacobi
         const int f = w.y, M = B.M, Ns = B.Ns;
         jacobi_bin<MP, G>(B.A + (size_t)f * M * M, B.kstatus ? B.kstatus[f] : SSL_BIN_OK, M, Ns,
                           max_sweeps, B.En ? B.En + (size_t)f * (M - Ns) * M : nullptr,
-                          nullptr, B.status + f,
-                          nullptr, nullptr, B.p == 2 ? sub_full : -1,
+                          nullptr, B.status + f, B.conv ? B.conv + 3 * (size_t)f : nullptr,
+                          nullptr, B.p == 2 ? sub_full : -1,
                           B.Es ? B.Es + (size_t)f * Ns * M : nullptr,
                           B.Esl ? B.Esl + 6 * (size_t)f : nullptr);
     }

@@ -114,6 +114,7 @@ struct BlockDev {
     float *P, *part;
     int32_t *peaks, *status;        // caller outputs
     float *peak_val, *Pbar;
+    int32_t *conv;                  // [F][3] Jacobi statistics or null
 };
 
 // Device view of one noise-handle update of ssl_noise_update_frames(_from): the noise-only

@@ -208,3 +208,43 @@ def test_signal_form_per_bin(S, ctx, mode):
     say(f"  {mode}: worst per-bin P error {worst}")
     if n is not None:
         S.ssl_noise_destroy(n)
+
+
+def test_batch_conv_statistics(S, ctx):
+    """ssl_block_desc.conv: the batch's per-bin Jacobi statistics.  With the noise-vector form the
+    batch runs the same solve as ssl_gsvd under SSL_STOP_ALSO_GSVD, so the counts agree bin for bin;
+    with the signal form (sweeps on R~^H, no second QR) every bin reports the numerical rank of the
+    pivoted QR and a sweep count within the limit."""
+    import torch
+    w = synth.workload_paper(n_blocks=1)
+    n, _ = noise_handle(S, ctx, w)
+    Hd = to_dev(w.steering_table())
+    Xd = to_dev(w.block(0)[0])
+    out = {}
+    for form in ("noise", "signal"):
+        o = outs(w, w.Ns)
+        cv = torch.full((w.F, 3), -7, dtype=torch.int32, device="cuda:0")
+        S.ssl_ctx_set_projection(ctx, S.SSL_PROJ_NOISE if form == "noise" else S.SSL_PROJ_SIGNAL)
+        try:
+            d = S.block_desc(Xd, n, Hd, w.grid.n_az, w.grid.n_el, w.Ns, o["pk"], o["pv"], o["Pbar"],
+                             o["st"], cv)
+            S.ssl_localize_batch(ctx, [d], S.SSL_FP32, 2)
+        finally:
+            S.ssl_ctx_set_projection(ctx, S.SSL_PROJ_SIGNAL)
+        out[form] = to_host(cv)
+    R = torch.zeros((w.F, w.M, w.M), dtype=torch.complex64, device="cuda:0")
+    S.ssl_corr_accum(ctx, Xd, 1.0 / w.T, 0, S.SSL_FP32, R)
+    En = torch.zeros((w.F, w.M - w.Ns, w.M), dtype=torch.complex64, device="cuda:0")
+    cg = torch.full((w.F, 3), -7, dtype=torch.int32, device="cuda:0")
+    S.ssl_ctx_set_stop(ctx, S.SSL_STOP_ALSO_GSVD)
+    try:
+        S.ssl_gsvd(ctx, R, n, w.Ns, En, None, None, cg, 0)
+    finally:
+        S.ssl_ctx_set_stop(ctx, S.SSL_STOP_LOCALIZE)
+    assert np.array_equal(out["noise"], to_host(cg))
+    sg = out["signal"]
+    say(f"  signal form: mean sweeps {sg[:, 0].mean():.2f} (noise form {out['noise'][:, 0].mean():.2f}), "
+        f"ranks {np.unique(sg[:, 2])}")
+    assert np.all(sg[:, 2] == out["noise"][:, 2])
+    assert np.all((sg[:, 0] >= 0) & (sg[:, 0] <= 20)) and np.all(sg[:, 1] >= 0)
+    S.ssl_noise_destroy(n)
