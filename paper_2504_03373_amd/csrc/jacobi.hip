@@ -26,6 +26,15 @@
 // projector has then converged after about 2.4 such sweeps, against about 6 full sweeps for the
 // singular vectors; the noise vectors then are not singular vectors (sigma is not produced).
 //
+// Signal vectors only (eq.5 through the signal subspace; no E_n wanted): neither the second QR
+// nor Q is used.  With A = Q R~ (R~ = R P^T), Z = R~^H has the singular values of A and its left
+// singular vectors are A's right ones, so the (subspace) sweeps run on Z itself (M x rk: the
+// pivoted QR grades its columns as it grades R's rows, about 3 subspace sweeps per bin on the
+// 60-channel workload), and A W_S -- the input A, untouched, times the signal columns of W = Z V
+// -- spans the Ns dominant left singular vectors of A, each direction scaled by its singular
+// value (a power step: the other directions that the rotation tolerance leaves in W_S shrink
+// relative to the signal).  The reflectors are then never parked, reloaded or applied.
+//
 // GPU mapping (gfx950):
 //  * one workgroup per bin; one complex64 MP x MP column-major matrix in LDS (32 KB at MP = 64,
 //    four bins per CU) holds A -> its QR -> R^H -> R1 -> X -> W -> U in turn (the two
