@@ -388,7 +388,7 @@ int ssl_ctx_get_svd(ssl_ctx ctx);
  * sweep changes nothing (X_S orthogonal to the rest to the rotation tolerance).  It then stops if min over S of |x|^2 exceeds the sum of |x|^2 over the
  * other columns, a bound on the rest's largest squared singular value, so that X_S spans the Ns
  * dominant singular vectors.  E_n is then an orthonormal basis of the complement of X_S
- * (Householder vectors), not the singular vectors.  A failed check, 4 such sweeps without
+ * (Householder vectors), not the singular vectors.  A failed check, 6 such sweeps without
  * convergence, or a weakest signal column holding less than the other columns' energy at
  * the switch keep the full solve.  Only for the Jacobi backend, 1 <= Ns <= 3 and a numerical
  * rank of at least 3 Ns.  On the 60-channel workload the stopped solve takes 2.4 sweeps over the

@@ -309,7 +309,7 @@ __device__ __forceinline__ bool jacobi_pair(float2 *Bs, int ci, int cj, int q, d
 // take three LDS arrays that are free by then), at most kSubMaxSweeps sweeps over their pairs
 // before the solve returns to full sweeps.
 constexpr int kSubMaxNs = 3;
-constexpr int kSubMaxSweeps = 4;
+constexpr int kSubMaxSweeps = 6;
 
 // |x_c|^2 of the columns c < rk (sweep layout) into nrm[c], one lane group per column.
 template <int MP, int G>
