@@ -156,8 +156,9 @@ ssl_status ssl_noise_update_frames(ssl_ctx ctx, int n, const ssl_noise *handles,
  * read (src[i] == dst[i] is the in-place update, bit-identical to ssl_noise_update_frames).  It
  * lets a stream keep two handles and blend into the one no batch is reading, so the update of
  * block n can run beside block n + 1 (which reads the other handle).  src[i] must be set (or be
- * the destination of an earlier entry) and have dst[i]'s F and M; dst[i] need not be set before.  Entries take effect in list order (an entry
- * that reads or writes a matrix an earlier entry writes, or writes one it reads, runs after it).
+ * the destination of an earlier entry) and have dst[i]'s F and M; dst[i] need not be set before.
+ * Entries take effect in list order (an entry that reads or writes a matrix an earlier entry
+ * writes, or writes one it reads, runs after it).
  * Errors (SSL_ERR_ARG / SSL_ERR_STATE, nothing launched): NULL arrays or entries, a source never
  * set, mismatched shapes or devices, T < 1, alpha outside [0, 1]. */
 ssl_status ssl_noise_update_frames_from(ssl_ctx ctx, int n, const ssl_noise *dst,
@@ -385,14 +386,15 @@ int ssl_ctx_get_svd(ssl_ctx ctx);
  * the noise singular vectors themselves.  From the start of the sweeps (the pivoted QR already
  * grades the column norms) the solve keeps the Ns columns of largest norm as the signal set S
  * and rotates only the pairs with a member in S, keeping the larger result in S, until such a
- * sweep changes nothing (X_S orthogonal to the rest to the rotation tolerance).  It then stops if min over S of |x|^2 exceeds the sum of |x|^2 over the
- * other columns, a bound on the rest's largest squared singular value, so that X_S spans the Ns
- * dominant singular vectors.  E_n is then an orthonormal basis of the complement of X_S
- * (Householder vectors), not the singular vectors.  A failed check, 6 such sweeps without
- * convergence, or a weakest signal column holding less than the other columns' energy at
- * the switch keep the full solve.  Only for the Jacobi backend, 1 <= Ns <= 3 and a numerical
- * rank of at least 3 Ns.  On the 60-channel workload the stopped solve takes 2.4 sweeps over the
- * signal pairs per bin on average, against 6.1 full sweeps.
+ * sweep changes nothing (X_S orthogonal to the rest to the rotation tolerance).  It then stops
+ * if min over S of |x|^2 exceeds the sum of |x|^2 over the other columns, a bound on the rest's
+ * largest squared singular value, so that X_S spans the Ns dominant singular vectors.  E_n is
+ * then an orthonormal basis of the complement of X_S (Householder vectors), not the singular
+ * vectors.  A failed check, 6 such sweeps without convergence, or a weakest signal column holding
+ * less than the other columns' energy at the switch keep the full solve.  Only for the Jacobi
+ * backend, 1 <= Ns <= 3 and a numerical rank of at least 3 Ns.  On the 60-channel workload the
+ * stopped solve takes 2.4 sweeps over the signal pairs per bin on average, against 6.1 full
+ * sweeps (3.2 for the signal-subspace form of eq.5, whose sweeps run without the second QR).
  *   SSL_STOP_NEVER       always the full SVD;
  *   SSL_STOP_BATCH       ssl_localize_batch with p = 2;
  *   SSL_STOP_LOCALIZE    (default) also ssl_localize and ssl_localize_noalloc with p = 2;
@@ -437,9 +439,10 @@ ssl_status ssl_ctx_use_graphs(ssl_ctx ctx, int enable);
 
 /* Jacobi SVD kernel variant per channel-count class (M <= 8, <= 16, <= 32, <= 64): the number of
  * lanes that cooperate on one column pair.  Available: 4 or 8 (M <= 8); 4, 8 or 16 (M <= 16);
- * 8 or 16 (M <= 32); 4, 8 or 16 (M <= 64).  Default 8 in every class.  A context applies its current choice to
- * every entry point, so batched and single-block results remain bit-identical; variants differ
- * from each other only by rounding.  Returns SSL_ERR_ARG for an unavailable variant. */
+ * 8 or 16 (M <= 32); 4, 8 or 16 (M <= 64).  Default 8 in every class.  A context applies its
+ * current choice to every entry point, so batched and single-block results remain
+ * bit-identical; variants differ from each other only by rounding.  Returns SSL_ERR_ARG for an
+ * unavailable variant. */
 ssl_status ssl_ctx_set_jacobi_lanes(ssl_ctx ctx, int M, int lanes);
 int ssl_ctx_get_jacobi_lanes(ssl_ctx ctx, int M);
 
