@@ -30,6 +30,7 @@ constexpr int kRows = 16 * kWaves;          // directions per workgroup
 constexpr int kCols = 16;                   // signal vectors per MFMA tile
 constexpr int kKq = SSL_MAX_M / 4;          // k-steps of 4 complex elements at M = 64
 constexpr int kEs = SSL_MAX_M + 2;          // complex64 stride of a staged signal vector
+constexpr int kChunk = kThreads;            // blocks whose descriptors are held in LDS at once
 
 // One workgroup: directions d0 .. d0 + 63 of bin f for nb blocks sharing the table Hf (the bin's
 // [D][M] complex64 rows).  blk(i, Es, L, ns, ok, P) gives block i's signal vectors and L^{-1} of
@@ -38,12 +39,13 @@ template <class BlockAt>
 __device__ __forceinline__ void sig_tile(const float2 *__restrict__ Hf, int D, int M, int d0,
                                          int nb, int nsmax, BlockAt &&blk)
 {
-    __shared__ float2 Es[kCols * kEs];
+    __shared__ float2 Es[2][kCols * kEs];                    // signal vectors, by tile parity
+    __shared__ double2 Ls[2][kCols][6];
     __shared__ double2 Gs[kWaves][16 * kCols];
-    __shared__ double2 Ls[kCols][6];
-    __shared__ float *Pp[kCols];
-    __shared__ const float2 *Ep[kCols];
-    __shared__ int Nsb[kCols];
+    __shared__ float *Pp[kChunk];                            // per block of the chunk
+    __shared__ const float2 *Ep[kChunk];
+    __shared__ const double2 *Lp[kChunk];
+    __shared__ int Nsb[kChunk];
     __shared__ double nrm_s[kRows];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -65,85 +67,117 @@ __device__ __forceinline__ void sig_tile(const float2 *__restrict__ Hf, int D, i
     hn += __shfl_xor(hn, 32);
     if (lane < 16) nrm_s[16 * wave + lane] = hn;
 
-    for (int b0 = 0; b0 < nb; b0 += bpt) {
-        const int nt = min(bpt, nb - b0);
-        __syncthreads();                                     // the previous tile is finished
-        if (tid < kCols) {
+    // One tile's operands into registers: thread x < kCols * SSL_MAX_M (kPer per thread) holds
+    // element m of column j = block j / nsmax, vector j % nsmax (zero if absent); threads below
+    // kCols * 6 hold one L^{-1} entry.  Loaded one tile ahead, so that the loads are in flight
+    // under the current tile's products and epilogue; stored to the other parity's buffers.
+    constexpr int kPer = kCols * SSL_MAX_M / kThreads;
+    float2 ev[kPer];
+    double2 lv;
+    auto load_tile = [&](int c0, int nt) {                   // c0: first block, chunk-relative
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int x = tid + kThreads * i;
+            const int j = x / SSL_MAX_M, m = x - j * SSL_MAX_M;
+            const int bi = j / nsmax, s = j - bi * nsmax;
+            ev[i] = (bi < nt && m < M && s < Nsb[c0 + bi]) ? gload(Ep[c0 + bi] + (size_t)s * M + m)
+                                                           : make_float2(0.f, 0.f);
+        }
+        const int bi = tid / 6, k = tid - bi * 6;
+        lv = (tid < kCols * 6 && bi < nt && Nsb[c0 + bi] > 0) ? gload(Lp[c0 + bi] + k)
+                                                              : make_double2(0.0, 0.0);
+    };
+    auto store_tile = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int x = tid + kThreads * i;
+            const int j = x / SSL_MAX_M, m = x - j * SSL_MAX_M;
+            Es[buf][j * kEs + m] = ev[i];
+        }
+        if (tid < kCols * 6) Ls[buf][tid / 6][tid % 6] = lv;
+    };
+
+    for (int h0 = 0; h0 < nb; h0 += kChunk) {               // chunks of the blocks' descriptors
+        const int nc = min(kChunk, nb - h0);
+        __syncthreads();                                     // the previous chunk is finished
+        if (tid < nc) {
             const float2 *e;
             const double2 *L;
             float *P;
             int ns = 0;
             bool ok = false;
-            if (tid < nt) blk(b0 + tid, e, L, ns, ok, P);
-            Nsb[tid] = (tid < nt && ok) ? ns : 0;
-            Pp[tid] = tid < nt ? P : nullptr;
-            Ep[tid] = tid < nt ? e : nullptr;
-            if (tid < nt && ok)
-                for (int i = 0; i < 6; ++i) Ls[tid][i] = gload(L + i);
+            blk(h0 + tid, e, L, ns, ok, P);
+            Nsb[tid] = ok ? ns : 0;
+            Pp[tid] = P;
+            Ep[tid] = e;
+            Lp[tid] = L;
         }
         __syncthreads();
-        // signal vectors: column j = block j / nsmax, vector j % nsmax (zero if absent)
-        for (int x = tid; x < kCols * SSL_MAX_M; x += kThreads) {
-            const int j = x / SSL_MAX_M, m = x - j * SSL_MAX_M;
-            const int bi = j / nsmax, s = j - bi * nsmax;
-            float2 v = make_float2(0.f, 0.f);
-            if (bi < nt && m < M && s < Nsb[bi]) v = gload(Ep[bi] + (size_t)s * M + m);
-            Es[j * kEs + m] = v;
-        }
+        const int ntiles = (nc + bpt - 1) / bpt;
+        load_tile(0, min(bpt, nc));
+        store_tile(0);
         __syncthreads();
-        doublex4 gre = {0.0, 0.0, 0.0, 0.0}, gim = {0.0, 0.0, 0.0, 0.0};
-        const float2 *ecol = Es + (lane & 15) * kEs + (lane >> 4);
+        for (int t = 0; t < ntiles; ++t) {
+            const int buf = t & 1, c0 = t * bpt, nt = min(bpt, nc - c0);
+            if (t + 1 < ntiles) load_tile(c0 + bpt, min(bpt, nc - c0 - bpt));
+            doublex4 gre = {0.0, 0.0, 0.0, 0.0}, gim = {0.0, 0.0, 0.0, 0.0};
+            const float2 *ecol = Es[buf] + (lane & 15) * kEs + (lane >> 4);
 #pragma unroll
-        for (int q = 0; q < kKq; ++q) {
-            if (q < KQ) {                                    // uniform
-                const float2 ev = ecol[4 * q];
-                const double a = ha[q].x, b = ha[q].y, c = ev.x, d = ev.y;
-                gre = __builtin_amdgcn_mfma_f64_16x16x4f64(a, c, gre, 0, 0, 0);
-                gre = __builtin_amdgcn_mfma_f64_16x16x4f64(b, d, gre, 0, 0, 0);
-                gim = __builtin_amdgcn_mfma_f64_16x16x4f64(b, c, gim, 0, 0, 0);
-                gim = __builtin_amdgcn_mfma_f64_16x16x4f64(-a, d, gim, 0, 0, 0);
+            for (int q = 0; q < kKq; ++q) {
+                if (q < KQ) {                                // uniform
+                    const float2 e = ecol[4 * q];
+                    const double a = ha[q].x, b = ha[q].y, c = e.x, d = e.y;
+                    gre = __builtin_amdgcn_mfma_f64_16x16x4f64(a, c, gre, 0, 0, 0);
+                    gre = __builtin_amdgcn_mfma_f64_16x16x4f64(b, d, gre, 0, 0, 0);
+                    gim = __builtin_amdgcn_mfma_f64_16x16x4f64(b, c, gim, 0, 0, 0);
+                    gim = __builtin_amdgcn_mfma_f64_16x16x4f64(-a, d, gim, 0, 0, 0);
+                }
             }
-        }
-        // FP64 result layout: element e of lane l is row l / 16 + 4 e, column l % 16
+            // FP64 result layout: element e of lane l is row l / 16 + 4 e, column l % 16
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-            Gs[wave][((lane >> 4) + 4 * e) * kCols + (lane & 15)] = make_double2(gre[e], gim[e]);
-        __syncthreads();
-        // items (direction row i of this wave, block bi): den = |h|^2 - |L^{-1} g|^2
-        for (int it = lane; it < 16 * nt; it += 64) {
-            const int i = it / nt, bi = it - i * nt;
-            const int d = d0 + 16 * wave + i;
-            float *P = Pp[bi];
-            if (d >= D || P == nullptr) continue;
-            const int ns = Nsb[bi];
-            const double hh = nrm_s[16 * wave + i];
-            float out = 0.0f;
-            if (ns > 0) {
-                const double2 *g = &Gs[wave][i * kCols + bi * nsmax];
-                const double2 *L = Ls[bi];
-                double2 y0 = make_double2(0.0, 0.0), y1 = y0, y2 = y0;
-                // y = L^{-1} g, L^{-1} lower triangular by rows (00, 10, 11, 20, 21, 22)
-                const double2 g0 = g[0];
-                y0 = make_double2(L[0].x * g0.x, L[0].x * g0.y);
-                double q2 = y0.x * y0.x + y0.y * y0.y;
-                if (ns >= 2) {
-                    const double2 g1 = g[1];
-                    y1 = make_double2(L[1].x * g0.x - L[1].y * g0.y + L[2].x * g1.x,
-                                      L[1].x * g0.y + L[1].y * g0.x + L[2].x * g1.y);
-                    q2 += y1.x * y1.x + y1.y * y1.y;
+            for (int e = 0; e < 4; ++e)
+                Gs[wave][((lane >> 4) + 4 * e) * kCols + (lane & 15)] =
+                    make_double2(gre[e], gim[e]);
+            __syncthreads();
+            // items (direction row i of this wave, block bi): den = |h|^2 - |L^{-1} g|^2
+            for (int it = lane; it < 16 * nt; it += 64) {
+                const int i = it / nt, bi = it - i * nt;
+                const int d = d0 + 16 * wave + i;
+                float *P = Pp[c0 + bi];
+                if (d >= D || P == nullptr) continue;
+                const int ns = Nsb[c0 + bi];
+                const double hh = nrm_s[16 * wave + i];
+                float out = 0.0f;
+                if (ns > 0) {
+                    const double2 *g = &Gs[wave][i * kCols + bi * nsmax];
+                    const double2 *L = Ls[buf][bi];
+                    double2 y0 = make_double2(0.0, 0.0), y1 = y0, y2 = y0;
+                    // y = L^{-1} g, L^{-1} lower triangular by rows (00, 10, 11, 20, 21, 22)
+                    const double2 g0 = g[0];
+                    y0 = make_double2(L[0].x * g0.x, L[0].x * g0.y);
+                    double q2 = y0.x * y0.x + y0.y * y0.y;
+                    if (ns >= 2) {
+                        const double2 g1 = g[1];
+                        y1 = make_double2(L[1].x * g0.x - L[1].y * g0.y + L[2].x * g1.x,
+                                          L[1].x * g0.y + L[1].y * g0.x + L[2].x * g1.y);
+                        q2 += y1.x * y1.x + y1.y * y1.y;
+                    }
+                    if (ns >= 3) {
+                        const double2 g1 = g[1], g2 = g[2];
+                        y2 = make_double2(L[3].x * g0.x - L[3].y * g0.y + L[4].x * g1.x -
+                                              L[4].y * g1.y + L[5].x * g2.x,
+                                          L[3].x * g0.y + L[3].y * g0.x + L[4].x * g1.y +
+                                              L[4].y * g1.x + L[5].x * g2.y);
+                        q2 += y2.x * y2.x + y2.y * y2.y;
+                    }
+                    const double den = fmax(hh - q2, 1.17549435e-38);
+                    out = (float)(hh / den);
                 }
-                if (ns >= 3) {
-                    const double2 g1 = g[1], g2 = g[2];
-                    y2 = make_double2(L[3].x * g0.x - L[3].y * g0.y + L[4].x * g1.x -
-                                          L[4].y * g1.y + L[5].x * g2.x,
-                                      L[3].x * g0.y + L[3].y * g0.x + L[4].x * g1.y +
-                                          L[4].y * g1.x + L[5].x * g2.y);
-                    q2 += y2.x * y2.x + y2.y * y2.y;
-                }
-                const double den = fmax(hh - q2, 1.17549435e-38);
-                out = (float)(hh / den);
+                gstore(P + d, out);
             }
-            gstore(P + d, out);
+            // the other parity was last read in the previous tile, before this tile's barrier
+            if (t + 1 < ntiles) store_tile(buf ^ 1);
+            __syncthreads();
         }
     }
 }
@@ -182,7 +216,9 @@ __global__ __launch_bounds__(kThreads) void steer_sig_single(
 
 // Batched: item = (group, bin), groups[g] = (first, count) into gblocks, the blocks of one
 // steering table; nsmax = the largest Ns of the batch.
-__global__ __launch_bounds__(kThreads) void steer_sig_batch(
+// (3 waves per SIMD: the next tile's operands in registers would otherwise cost one)
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(3))) void steer_sig_batch(
     const BlockDev *__restrict__ blk, const int2 *__restrict__ items, int n_items, int n_tiles,
     const int2 *__restrict__ groups, const int *__restrict__ gblocks, int nsmax)
 {
