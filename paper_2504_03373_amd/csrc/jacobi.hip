@@ -1270,8 +1270,9 @@ __device__ __forceinline__ void jacobi_bin(float2 *__restrict__ Af, int kst, int
         // ---- 6'. signal vectors without Q: E_s = A W_S --------------------------------------
         // With sig_only the sweeps ran on Z = R~^H (R~ = R P^T: R's columns in physical order,
         // A = Q R~): Z V = W makes W_S span the dominant right singular subspace of R~, A's (Q is
-        // unitary), so A W_S spans the Ns dominant left singular vectors of A, scaled by sigma^2
-        // (a step of power iteration: what the rotation tolerance leaves of the other directions
+        // unitary), so A W_S spans the Ns dominant left singular vectors of A (W_S's columns are
+        // unit vectors here, so each direction comes out scaled by its singular value: a step of
+        // power iteration, in which what the rotation tolerance leaves of the other directions
         // is damped by their smaller singular values).  A is the input, still intact (nothing was
         // parked in it), read row by row by groups of G lanes, scaled by 2^-ex as X was.  The
         // sums run in FP64: A w_s for a weaker signal cancels the stronger ones' share of A, and
