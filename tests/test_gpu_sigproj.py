@@ -248,3 +248,26 @@ def test_batch_conv_statistics(S, ctx):
     assert np.all(sg[:, 2] == out["noise"][:, 2])
     assert np.all((sg[:, 0] >= 0) & (sg[:, 0] <= 20)) and np.all(sg[:, 1] >= 0)
     S.ssl_noise_destroy(n)
+
+
+def test_batch_more_blocks_than_one_descriptor_chunk(S, ctx):
+    """300 blocks sharing one steering table: the projection reads the blocks' descriptors in
+    chunks of 256, so the second chunk's blocks must equal their single-block calls bit for bit,
+    like the first chunk's."""
+    import torch
+    nb = 300
+    w = synth.workload_small(n_blocks=4)
+    n, _ = noise_handle(S, ctx, w)
+    Hd = to_dev(w.steering_table())
+    Xs = [to_dev(w.block(b)[0]) for b in range(4)]
+    bo = [outs(w, w.Ns) for _ in range(nb)]
+    descs = [S.block_desc(Xs[b % 4], n, Hd, w.grid.n_az, w.grid.n_el, w.Ns, o["pk"], o["pv"],
+                          o["Pbar"], o["st"]) for b, o in enumerate(bo)]
+    S.ssl_localize_batch(ctx, descs, S.SSL_FP32, 2)
+    refs = [single(S, ctx, w, Xs[q], n, Hd, w.Ns) for q in range(4)]
+    for b in (0, 3, 255, 256, 257, 299):
+        got = {k: to_host(v) for k, v in bo[b].items()}
+        for k in ("pk", "pv", "Pbar", "st"):
+            assert np.array_equal(got[k], refs[b % 4][k]), (b, k)
+    say(f"  {nb} blocks in one steering group: chunk boundaries equal single-block calls")
+    S.ssl_noise_destroy(n)
