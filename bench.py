@@ -11,8 +11,9 @@ table, resident noise factor) are in HBM before any timed region starts.
 The headline path (`--prec`, default fp32) is the paper's arithmetic: correlation on FP32 MFMA,
 K^{-1}R in FP64, the Jacobi SVD in FP32 and eq.5 through the signal subspace in FP64 (|h|^2 minus
 the squared projection on the Ns signal vectors, FP64 MFMA).  The mixed-precision paths (bf16 and
-fp16 MFMA inputs with FP32 accumulation for the correlation and the noise-vector projection, the
-rest unchanged) are measured in the same run as secondary keys, batched and one block per call.
+fp16 MFMA inputs with FP32 accumulation for the correlation, a bf16 / fp16 steering table read by
+the same FP64 signal-subspace projection, the rest unchanged) are measured in the same run as
+secondary keys, batched and one block per call.
 
 Timed regions per precision (each bracketed by torch.cuda.synchronize()):
   * main: `--steps` batch steps with per-kernel HIP events on the launch stream -> `value`, the
@@ -585,8 +586,9 @@ def main() -> int:
     def measure(name: str, with_h2d: bool, conv: bool = True) -> dict:
         prec = PREC[name]
         H = table(name)
-        # FP32 with Ns <= 3: eq.5 through the signal subspace (the library's default projection)
-        sig = name == "fp32" and 1 <= Ns <= 3
+        # Ns <= 3: eq.5 through the signal subspace (the library's default projection, any table
+        # precision)
+        sig = 1 <= Ns <= 3
         R = torch.zeros((F, M, M), dtype=torch.complex64, device=dev)
         En = torch.zeros((F, M - Ns, M), dtype=torch.complex64, device=dev)
         conv_t = torch.zeros((F, 3), dtype=torch.int32, device=dev)
@@ -784,7 +786,7 @@ def main() -> int:
                    "svd": "fp32 one-sided Jacobi (two-QR preconditioned), stopped at the "
                           "signal / noise split",
                    "projection": ("eq.5 through the signal subspace, FP64 MFMA"
-                                  if args.prec == "fp32" and Ns <= 3 else
+                                  if Ns <= 3 else
                                   f"eq.5 over the noise vectors, {args.prec} MFMA")},
         "graph_value": round(main_r["graph_value"], 2),
         "per_block": {"value": round(main_r["per_block"], 2), "unit": "blocks/s",
@@ -824,9 +826,9 @@ def main() -> int:
                   "ms_per_step": round(1000.0 * r["elapsed"] / args.steps, 4),
                   "kernels": {k: round(v, 4) for k, v in r["avg"].items()},
                   "steer_roofline": r["rl"]["steer"], "corr_roofline": r["rl"]["corr"],
-                  "kind": f"{c} MFMA inputs for the correlation and the projection (FP32 "
-                          f"accumulation), FP64 whitening, FP32 Jacobi: batched, and one block "
-                          f"per call"}
+                  "kind": f"{c} MFMA inputs for the correlation (FP32 accumulation) and a {c} "
+                          f"steering table for the projection (through the signal subspace, "
+                          f"FP64), FP64 whitening, FP32 Jacobi: batched, and one block per call"}
     if f32 is not None:
         best = max([main_r] + list(sec.values()), key=lambda r: r["value"])
         out["speedup_vs_fp32_per_block"] = round(best["value"] / f32["per_block"], 3)

@@ -413,20 +413,22 @@ typedef enum {
 ssl_status ssl_ctx_set_stop(ssl_ctx ctx, ssl_stop mode);
 int ssl_ctx_get_stop(ssl_ctx ctx);
 
-/* Form of eq.5 (p = 2) on the FP32 path.  With U = [E_s E_n] unitary, the sum over the noise
- * vectors of |h^H e|^2 equals |h|^2 - |E_s^H h|^2, which needs the Ns signal vectors instead of the
- * M - Ns noise vectors.  That difference cancels near the peaks, so it is evaluated in FP64 from
- * FP64 products of the stored complex64 vectors (FP64 matrix cores), with the exact projector
- * E_s (E_s^H E_s)^{-1} E_s^H onto their span (the Jacobi solve returns the inverse Cholesky factor
- * of their FP64 Gram matrix): den = |h|^2 - |L^{-1} E_s^H h|^2, P = |h|^2 / max(den, FLT_MIN).
- *   SSL_PROJ_SIGNAL   (default) this form wherever it applies: SSL_FP32 tables, p = 2, the Jacobi
- *                     backend, GSVD or SEVD (not GEVD, whose noise vectors are not orthonormal),
- *                     1 <= Ns <= 3, in ssl_localize, ssl_localize_noalloc and ssl_localize_batch
- *                     (a batch uses it only if every block qualifies);
- *   SSL_PROJ_NOISE    always the noise-vector projection H^H E_n (FP32 MFMA), as
- *                     ssl_music_spectrum computes it.
- * The bf16 / fp16 paths, p = 1, ssl_sliding_localize and ssl_music_spectrum always use the
- * noise-vector projection.  The two forms agree within the parity bounds (rounding differs). */
+/* Form of eq.5 (p = 2).  With U = [E_s E_n] unitary, the sum over the noise vectors of |h^H e|^2
+ * equals |h|^2 - |E_s^H h|^2, which needs the Ns signal vectors instead of the M - Ns noise
+ * vectors.  That difference cancels near the peaks, so it is evaluated in FP64 from FP64
+ * products of the stored vectors and of the table's values (complex64, or bf16 / fp16 pairs
+ * widened exactly; FP64 matrix cores), with the exact projector E_s (E_s^H E_s)^{-1} E_s^H onto
+ * their span (the Jacobi solve returns the inverse Cholesky factor of their FP64 Gram matrix):
+ * den = |h|^2 - |L^{-1} E_s^H h|^2, P = |h|^2 / max(den, FLT_MIN).  The Jacobi solve then forms
+ * only the signal vectors.
+ *   SSL_PROJ_SIGNAL   (default) this form wherever it applies: p = 2, the Jacobi backend, GSVD or
+ *                     SEVD (not GEVD, whose noise vectors are not orthonormal), 1 <= Ns <= 3, any
+ *                     table precision, in ssl_localize, ssl_localize_noalloc and
+ *                     ssl_localize_batch (per block: a batch may mix blocks of both forms);
+ *   SSL_PROJ_NOISE    always the noise-vector projection H^H E_n (MFMA at the table's
+ *                     precision), as ssl_music_spectrum computes it.
+ * p = 1, ssl_sliding_localize and ssl_music_spectrum always use the noise-vector projection.  The
+ * two forms agree within the parity bounds (rounding differs). */
 typedef enum { SSL_PROJ_NOISE = 0, SSL_PROJ_SIGNAL = 1 } ssl_projection;
 ssl_status ssl_ctx_set_projection(ssl_ctx ctx, ssl_projection mode);
 int ssl_ctx_get_projection(ssl_ctx ctx);

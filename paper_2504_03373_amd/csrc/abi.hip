@@ -154,13 +154,14 @@ hipError_t launch_svd(ssl_ctx ctx, ssl_c64 *A, const int32_t *kst, int F, int M,
     return launch_jacobi(A, kst, F, M, Ns, max_sweeps, jac_lanes(ctx, M), En, sigma, stt, conv, st,
                          U, sub_full, Es, Esl);
 }
-// Whether eq.5 is evaluated through the signal subspace (FP64, steer_sig.hip): the FP32 path with
-// p = 2, the Jacobi backend, GSVD or SEVD (U unitary), Ns <= 3, unless the context asks for the
-// noise-vector projection.
+// Whether eq.5 is evaluated through the signal subspace (FP64, steer_sig.hip): p = 2, the Jacobi
+// backend, GSVD or SEVD (U unitary), Ns <= 3, any table precision, unless the context asks for
+// the noise-vector projection.
 bool use_sig(ssl_ctx ctx, ssl_prec prec, int p, int Ns, bool gevd)
 {
-    return ctx->proj == SSL_PROJ_SIGNAL && prec == SSL_FP32 && p == 2 &&
-           ctx->svd == SSL_SVD_JACOBI && !gevd && Ns >= 1 && Ns <= 3;
+    (void)prec;
+    return ctx->proj == SSL_PROJ_SIGNAL && p == 2 && ctx->svd == SSL_SVD_JACOBI && !gevd &&
+           Ns >= 1 && Ns <= 3;
 }
 
 // Whether a localization path stops the Jacobi solve at the noise subspace (p = 2: eq.5 reads only
@@ -346,8 +347,7 @@ ssl_status localize_enqueue(ssl_ctx ctx, bool may_time, char *w, const LocalizeW
     }
     e = run(SSL_K_STEER, [&] {
         if (sig)
-            return launch_steer_sig(static_cast<const ssl_c64 *>(H), Es, Esl, F, D, M, Ns, stt, P,
-                                    st);
+            return launch_steer_sig(H, prec, Es, Esl, F, D, M, Ns, stt, P, st);
         return launch_steer(H, prec, En, F, D, M, Ns, p, stt, P, st_waves(ctx, M, Ns, prec), st);
     });
     if (e != hipSuccess) return hip_fail(e, "steer launch");
@@ -1252,7 +1252,7 @@ hipError_t enqueue_batch(ssl_ctx ctx, const Plan &P, const BlockDev *blk, const 
         e = timed(ctx, SSL_K_STEER, st, [&] {
             if (s.sig)
                 return launch_steer_sig_batch(blk, l_st + s.start, s.count, ga.groups, ga.gblocks,
-                                              s.extra, P.nsmax, st);
+                                              s.extra, P.nsmax, prec, st);
             return launch_steer_batch(blk, l_st + s.start, s.count, ga.groups, ga.gblocks, s.cls,
                                       s.waves, s.extra, prec, st);
         });

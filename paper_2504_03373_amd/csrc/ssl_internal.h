@@ -174,14 +174,15 @@ hipError_t launch_jacobi_batch(const BlockDev *blk, const int2 *items, int n_ite
                                int lanes, int max_sweeps, unsigned int *queue, int grid,
                                hipStream_t st, int sub_full = -1);
 // eq.5 (p = 2) through the signal subspace, FP64 (steer_sig.hip): Es [F][Ns][M] and Esl [F][6]
-// from the Jacobi solve, H complex64 [F][D][M], Ns <= 3; direction tiles of steer_sig_tiles(D).
+// from the Jacobi solve, H [F][D][M] complex64 or [F][D][2M] bf16 / fp16 pairs (hprec),
+// Ns <= 3; direction tiles of steer_sig_tiles(D).
 int steer_sig_tiles(int D);
-hipError_t launch_steer_sig(const ssl_c64 *H, const ssl_c64 *Es, const ssl_c128 *Esl, int F,
-                            int D, int M, int Ns, const int32_t *bin_status, float *P,
-                            hipStream_t st);
+hipError_t launch_steer_sig(const void *H, ssl_prec hprec, const ssl_c64 *Es,
+                            const ssl_c128 *Esl, int F, int D, int M, int Ns,
+                            const int32_t *bin_status, float *P, hipStream_t st);
 hipError_t launch_steer_sig_batch(const BlockDev *blk, const int2 *items, int n_items,
                                   const int2 *groups, const int *gblocks, int max_dtiles,
-                                  int nsmax, hipStream_t st);
+                                  int nsmax, ssl_prec hprec, hipStream_t st);
 hipError_t launch_steer_batch(const BlockDev *blk, const int2 *items, int n_items,
                               const int2 *groups, const int *gblocks, int cls, int waves,
                               int max_dtiles, ssl_prec hprec, hipStream_t st);

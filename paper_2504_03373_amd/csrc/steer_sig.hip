@@ -32,12 +32,36 @@ constexpr int kKq = SSL_MAX_M / 4;          // k-steps of 4 complex elements at 
 constexpr int kEs = SSL_MAX_M + 2;          // complex64 stride of a staged signal vector
 constexpr int kChunk = kThreads;            // blocks whose descriptors are held in LDS at once
 
+// Steering-table readers: one complex element per word, complex64 (FP32 tables) or a pair of
+// 16-bit values (re at the lower address) for bf16 / fp16 tables, widened exactly to FP32.
+struct TabF32 {
+    typedef float2 W;
+    static __device__ __forceinline__ float2 get(const W *p) { return gload(p); }
+};
+struct TabBF16 {
+    typedef unsigned int W;
+    static __device__ __forceinline__ float2 get(const W *p)
+    {
+        const unsigned int w = gload(p);
+        return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
+    }
+};
+struct TabF16 {
+    typedef unsigned int W;
+    static __device__ __forceinline__ float2 get(const W *p)
+    {
+        const unsigned int w = gload(p);
+        return make_float2((float)__builtin_bit_cast(_Float16, (unsigned short)(w & 0xffffu)),
+                           (float)__builtin_bit_cast(_Float16, (unsigned short)(w >> 16)));
+    }
+};
+
 // One workgroup: directions d0 .. d0 + 63 of bin f for nb blocks sharing the table Hf (the bin's
 // [D][M] complex64 rows).  blk(i, Es, L, ns, ok, P) gives block i's signal vectors and L^{-1} of
 // the bin, its Ns, whether the bin is valid, and its P row of the bin.
-template <class BlockAt>
-__device__ __forceinline__ void sig_tile(const float2 *__restrict__ Hf, int D, int M, int d0,
-                                         int nb, int nsmax, BlockAt &&blk)
+template <class Tab, class BlockAt>
+__device__ __forceinline__ void sig_tile(const typename Tab::W *__restrict__ Hf, int D, int M,
+                                         int d0, int nb, int nsmax, BlockAt &&blk)
 {
     __shared__ float2 Es[2][kCols * kEs];                    // signal vectors, by tile parity
     __shared__ double2 Ls[2][kCols][6];
@@ -54,13 +78,13 @@ __device__ __forceinline__ void sig_tile(const float2 *__restrict__ Hf, int D, i
 
     // this lane's A operands: row (lane & 15), complex elements 4 q + (lane >> 4)
     const int row = d0 + 16 * wave + (lane & 15);
-    const float2 *hrow = Hf + (size_t)(row < D ? row : 0) * M;
+    const typename Tab::W *hrow = Hf + (size_t)(row < D ? row : 0) * M;
     float2 ha[kKq];
     double hn = 0.0;
 #pragma unroll
     for (int q = 0; q < kKq; ++q) {
         const int m = 4 * q + (lane >> 4);
-        ha[q] = (q < KQ && m < M && row < D) ? gload(hrow + m) : make_float2(0.f, 0.f);
+        ha[q] = (q < KQ && m < M && row < D) ? Tab::get(hrow + m) : make_float2(0.f, 0.f);
         hn = fma((double)ha[q].x, (double)ha[q].x, fma((double)ha[q].y, (double)ha[q].y, hn));
     }
     hn += __shfl_xor(hn, 16);
@@ -197,14 +221,16 @@ __device__ __forceinline__ bool sig_item(int n_items, int n_tiles, int &item, in
     return item < n_items;
 }
 
+template <class Tab>
 __global__ __launch_bounds__(kThreads) void steer_sig_single(
-    const float2 *__restrict__ H, const float2 *__restrict__ Es, const double2 *__restrict__ Esl,
+    const typename Tab::W *__restrict__ H, const float2 *__restrict__ Es,
+    const double2 *__restrict__ Esl,
     const int32_t *__restrict__ bin_status, int F, int D, int M, int Ns, float *__restrict__ P,
     int n_tiles)
 {
     int f, tile;
     if (!sig_item(F, n_tiles, f, tile)) return;
-    sig_tile(H + (size_t)f * D * M, D, M, tile * kRows, 1, Ns,
+    sig_tile<Tab>(H + (size_t)f * D * M, D, M, tile * kRows, 1, Ns,
              [&](int, const float2 *&e, const double2 *&L, int &ns, bool &ok, float *&Pf) {
                  e = Es + (size_t)f * Ns * M;
                  L = Esl + 6 * (size_t)f;
@@ -217,6 +243,7 @@ __global__ __launch_bounds__(kThreads) void steer_sig_single(
 // Batched: item = (group, bin), groups[g] = (first, count) into gblocks, the blocks of one
 // steering table; nsmax = the largest Ns of the batch.
 // (3 waves per SIMD: the next tile's operands in registers would otherwise cost one)
+template <class Tab>
 __global__ __launch_bounds__(kThreads)
 __attribute__((amdgpu_waves_per_eu(3))) void steer_sig_batch(
     const BlockDev *__restrict__ blk, const int2 *__restrict__ items, int n_items, int n_tiles,
@@ -230,7 +257,8 @@ __attribute__((amdgpu_waves_per_eu(3))) void steer_sig_batch(
     const int d0 = tile * kRows;
     if (d0 >= B0.D) return;
     const int f = it.y, M = B0.M, D = B0.D;
-    sig_tile(static_cast<const float2 *>(B0.H) + (size_t)f * D * M, D, M, d0, gr.y, nsmax,
+    sig_tile<Tab>(static_cast<const typename Tab::W *>(B0.H) + (size_t)f * D * M, D, M, d0, gr.y,
+                  nsmax,
              [&](int i, const float2 *&e, const double2 *&L, int &ns, bool &ok, float *&Pf) {
                  const BlockDev &B = blk[gblocks[gr.x + i]];
                  e = B.Es + (size_t)f * B.Ns * M;
@@ -241,27 +269,44 @@ __attribute__((amdgpu_waves_per_eu(3))) void steer_sig_batch(
              });
 }
 
+// Calls fn with the table reader of prec.
+template <class Fn>
+hipError_t with_table(ssl_prec prec, Fn &&fn)
+{
+    if (prec == SSL_BF16) return fn(TabBF16());
+    if (prec == SSL_FP16) return fn(TabF16());
+    return fn(TabF32());
+}
+
 }  // namespace
 
 int steer_sig_tiles(int D) { return (D + kRows - 1) / kRows; }
 
-hipError_t launch_steer_sig(const ssl_c64 *H, const ssl_c64 *Es, const ssl_c128 *Esl, int F,
-                            int D, int M, int Ns, const int32_t *bin_status, float *P,
-                            hipStream_t st)
+hipError_t launch_steer_sig(const void *H, ssl_prec hprec, const ssl_c64 *Es,
+                            const ssl_c128 *Esl, int F, int D, int M, int Ns,
+                            const int32_t *bin_status, float *P, hipStream_t st)
 {
     const int nt = steer_sig_tiles(D);
-    hipLaunchKernelGGL(steer_sig_single, dim3(sig_grid(F, nt)), dim3(kThreads), 0, st,
-                       reinterpret_cast<const float2 *>(H), reinterpret_cast<const float2 *>(Es),
-                       reinterpret_cast<const double2 *>(Esl), bin_status, F, D, M, Ns, P, nt);
-    return hipGetLastError();
+    return with_table(hprec, [&](auto tab) {
+        typedef decltype(tab) Tab;
+        hipLaunchKernelGGL(steer_sig_single<Tab>, dim3(sig_grid(F, nt)), dim3(kThreads), 0, st,
+                           static_cast<const typename Tab::W *>(H),
+                           reinterpret_cast<const float2 *>(Es),
+                           reinterpret_cast<const double2 *>(Esl), bin_status, F, D, M, Ns, P, nt);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_steer_sig_batch(const BlockDev *blk, const int2 *items, int n_items,
                                   const int2 *groups, const int *gblocks, int max_dtiles,
-                                  int nsmax, hipStream_t st)
+                                  int nsmax, ssl_prec hprec, hipStream_t st)
 {
     if (n_items <= 0) return hipSuccess;
-    hipLaunchKernelGGL(steer_sig_batch, dim3(sig_grid(n_items, max_dtiles)), dim3(kThreads), 0, st,
-                       blk, items, n_items, max_dtiles, groups, gblocks, nsmax);
-    return hipGetLastError();
+    return with_table(hprec, [&](auto tab) {
+        typedef decltype(tab) Tab;
+        hipLaunchKernelGGL(steer_sig_batch<Tab>, dim3(sig_grid(n_items, max_dtiles)),
+                           dim3(kThreads), 0, st, blk, items, n_items, max_dtiles, groups,
+                           gblocks, nsmax);
+        return hipGetLastError();
+    });
 }

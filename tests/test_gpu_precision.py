@@ -143,16 +143,13 @@ def test_noise_conditioning_sweep(S):
             g = localize(S, ctx, X, noise, Hd, prec, w)
             P, Pbar_steps, st = steps_P(S, ctx, X, noise, Hd, prec, w)
             # the step entry points run the same kernels as ssl_localize with the noise-vector
-            # projection (the FP32 path's default is the signal-subspace form)
-            if prec == S.SSL_FP32:
-                S.ssl_ctx_set_projection(ctx, S.SSL_PROJ_NOISE)
-                try:
-                    g_noise = localize(S, ctx, X, noise, Hd, prec, w)
-                finally:
-                    S.ssl_ctx_set_projection(ctx, S.SSL_PROJ_SIGNAL)
-                assert np.array_equal(Pbar_steps, g_noise["Pbar"])
-            else:
-                assert np.array_equal(Pbar_steps, g["Pbar"])
+            # projection (ssl_localize's default is the signal-subspace form)
+            S.ssl_ctx_set_projection(ctx, S.SSL_PROJ_NOISE)
+            try:
+                g_noise = localize(S, ctx, X, noise, Hd, prec, w)
+            finally:
+                S.ssl_ctx_set_projection(ctx, S.SSL_PROJ_SIGNAL)
+            assert np.array_equal(Pbar_steps, g_noise["Pbar"])
             rel, amb, pk_err = compare(g, r, w, pname)
             prel = np.abs(P - r["P"]) / r["P"]
             inv = np.abs(1.0 / P.astype(np.float64) - 1.0 / r["P"])

@@ -121,10 +121,12 @@ def test_steer_autotune(S):
 
 
 def test_steer_variant_applies_to_batch(S):
-    """Batched and single-block outputs stay bit-identical under a non-default tile shape."""
+    """Batched and single-block outputs stay bit-identical under a non-default tile shape (of the
+    noise-vector projection, which the tile variants belong to)."""
     import torch
     import synth
     ctx = S.ssl_ctx_create(0, 0)
+    S.ssl_ctx_set_projection(ctx, S.SSL_PROJ_NOISE)
     w = synth.workload_paper(n_blocks=4)
     Xn = w.noise_frames()
     Kd = torch.zeros((w.F, w.M, w.M), dtype=torch.complex128, device="cuda:0")
