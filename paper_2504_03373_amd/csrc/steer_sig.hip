@@ -16,7 +16,10 @@
 // (complex64) and computes g for 16 columns at once on v_mfma_f64_16x16x4f64 -- the signal vectors
 // of 16 / Ns_max blocks sharing the steering table, staged in LDS -- with
 //   Re g = sum a c + b d,   Im g = sum b c - a d     (h = a + ib, e = c + id, FP64 operands:
-// g_s = e_s^H h, the conjugate of h^H e_s, so that y = L^{-1} g with L from E_s^H E_s = L L^H).
+// g_s = e_s^H h, the conjugate of h^H e_s, so that y = L^{-1} g with L from E_s^H E_s = L L^H),
+// on three real products instead of four (Gauss's trick): P1 = sum a c, P2 = sum b (-d),
+// P3 = sum (a + b)(c - d), Re g = P1 - P2, Im g = P3 - P1 - P2.  a + b and c - d are sums of two
+// FP32-representable values, exact in FP64 unless their exponents differ by more than 29.
 // The 16 x 16 result goes through LDS so that each lane finishes whole (direction, block) items.
 #include "ssl_internal.h"
 
@@ -144,19 +147,19 @@ __device__ __forceinline__ void sig_tile(const typename Tab::W *__restrict__ Hf,
         for (int t = 0; t < ntiles; ++t) {
             const int buf = t & 1, c0 = t * bpt, nt = min(bpt, nc - c0);
             if (t + 1 < ntiles) load_tile(c0 + bpt, min(bpt, nc - c0 - bpt));
-            doublex4 gre = {0.0, 0.0, 0.0, 0.0}, gim = {0.0, 0.0, 0.0, 0.0};
+            doublex4 p1 = {0.0, 0.0, 0.0, 0.0}, p2 = {0.0, 0.0, 0.0, 0.0}, p3 = {0.0, 0.0, 0.0, 0.0};
             const float2 *ecol = Es[buf] + (lane & 15) * kEs + (lane >> 4);
 #pragma unroll
             for (int q = 0; q < kKq; ++q) {
                 if (q < KQ) {                                // uniform
                     const float2 e = ecol[4 * q];
                     const double a = ha[q].x, b = ha[q].y, c = e.x, d = e.y;
-                    gre = __builtin_amdgcn_mfma_f64_16x16x4f64(a, c, gre, 0, 0, 0);
-                    gre = __builtin_amdgcn_mfma_f64_16x16x4f64(b, d, gre, 0, 0, 0);
-                    gim = __builtin_amdgcn_mfma_f64_16x16x4f64(b, c, gim, 0, 0, 0);
-                    gim = __builtin_amdgcn_mfma_f64_16x16x4f64(-a, d, gim, 0, 0, 0);
+                    p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, c, p1, 0, 0, 0);
+                    p2 = __builtin_amdgcn_mfma_f64_16x16x4f64(b, -d, p2, 0, 0, 0);
+                    p3 = __builtin_amdgcn_mfma_f64_16x16x4f64(a + b, c - d, p3, 0, 0, 0);
                 }
             }
+            const doublex4 gre = p1 - p2, gim = p3 - p1 - p2;
             // FP64 result layout: element e of lane l is row l / 16 + 4 e, column l % 16
 #pragma unroll
             for (int e = 0; e < 4; ++e)
