@@ -148,12 +148,14 @@ __device__ __forceinline__ float apply_reflector(int pc, float2 vk, int k, float
     (void)M;
     float wr = 0.f, wi = 0.f;
     float2 x[R], v[R];
+    const int js = k / G;                         // the slot holding row k
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        if (G * (j + 1) <= k) continue;           // slot entirely above the reflector
+        if (j < js) continue;                     // slot entirely above the reflector
         const int r = q + G * j;
         const float2 raw = X[at<MP>(pc, r)];
-        v[j] = (r > k) ? raw : ((r == k) ? vk : make_float2(0.f, 0.f));
+        if (j == js) v[j] = (r > k) ? raw : ((r == k) ? vk : make_float2(0.f, 0.f));
+        else v[j] = raw;
         x[j] = X[at<MP>(c, r)];
         // conj(v) x
         wr = fmaf(v[j].x, x[j].x, fmaf(v[j].y, x[j].y, wr));
@@ -164,14 +166,15 @@ __device__ __forceinline__ float apply_reflector(int pc, float2 vk, int k, float
     float tn = 0.f;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        if (G * (j + 1) <= k) continue;
+        if (j < js) continue;
         const int r = q + G * j;
         // x -= v * (tau w)
         x[j].x = fmaf(-v[j].x, wr, fmaf(v[j].y, wi, x[j].x));
         x[j].y = fmaf(-v[j].x, wi, fmaf(-v[j].y, wr, x[j].y));
         X[at<MP>(c, r)] = x[j];
         const float n2 = fmaf(x[j].x, x[j].x, x[j].y * x[j].y);
-        tn += (r > k) ? n2 : 0.0f;
+        if (j == js) tn += (r > k) ? n2 : 0.0f;
+        else tn += n2;
     }
     return group_sum<G>(tn);
 }
@@ -187,12 +190,14 @@ __device__ __forceinline__ void apply_reflector2(int pc, float2 vk, int k, float
     constexpr int R = MP / G;
     float wr0 = 0.f, wi0 = 0.f, wr1 = 0.f, wi1 = 0.f;
     float2 x0[R], x1[R], v[R];
+    const int js = k / G;                         // the slot holding row k
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        if (G * (j + 1) <= k) continue;
+        if (j < js) continue;
         const int r = q + G * j;
         const float2 raw = X[at<MP>(pc, r)];
-        v[j] = (r > k) ? raw : ((r == k) ? vk : make_float2(0.f, 0.f));
+        if (j == js) v[j] = (r > k) ? raw : ((r == k) ? vk : make_float2(0.f, 0.f));
+        else v[j] = raw;
         x0[j] = X[at<MP>(c0, r)];
         x1[j] = X[at<MP>(c1, r)];
         wr0 = fmaf(v[j].x, x0[j].x, fmaf(v[j].y, x0[j].y, wr0));
@@ -207,7 +212,7 @@ __device__ __forceinline__ void apply_reflector2(int pc, float2 vk, int k, float
     float s0 = 0.f, s1 = 0.f;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        if (G * (j + 1) <= k) continue;
+        if (j < js) continue;
         const int r = q + G * j;
         x0[j].x = fmaf(-v[j].x, wr0, fmaf(v[j].y, wi0, x0[j].x));
         x0[j].y = fmaf(-v[j].x, wi0, fmaf(-v[j].y, wr0, x0[j].y));
@@ -217,8 +222,13 @@ __device__ __forceinline__ void apply_reflector2(int pc, float2 vk, int k, float
         if (two) X[at<MP>(c1, r)] = x1[j];
         const float n0 = fmaf(x0[j].x, x0[j].x, x0[j].y * x0[j].y);
         const float n1 = fmaf(x1[j].x, x1[j].x, x1[j].y * x1[j].y);
-        s0 += (r > k) ? n0 : 0.0f;
-        s1 += (r > k) ? n1 : 0.0f;
+        if (j == js) {
+            s0 += (r > k) ? n0 : 0.0f;
+            s1 += (r > k) ? n1 : 0.0f;
+        } else {
+            s0 += n0;
+            s1 += n1;
+        }
     }
     tn0 = group_sum<G>(s0);
     tn1 = group_sum<G>(s1);
