@@ -254,8 +254,10 @@ ssl_status ssl_steering_convert(ssl_ctx ctx, const ssl_c64 *H, int F, int D, int
 
 /* One block end to end: R = (1/T) sum X X^H (eq.2-3), A = K^{-1} R and E_n (eq.4), P (eq.5),
  * Pbar (eq.6), peaks.  X as in ssl_corr_accum; H as in ssl_music_spectrum with D = n_az*n_el;
- * prec selects the MFMA input type of the correlation and the projection (SSL_FP32, SSL_BF16 or
- * SSL_FP16; H must be stored in that type).  Pbar ([D]) and bin_status ([F]) may be NULL.
+ * prec selects the MFMA input type of the correlation and the storage type of H (SSL_FP32,
+ * SSL_BF16 or SSL_FP16; H must be stored in that type); the projection is eq.5's signal-subspace
+ * form in FP64 where it applies (see ssl_ctx_set_projection), else the noise-vector form on MFMA
+ * at that type.  Pbar ([D]) and bin_status ([F]) may be NULL.
  * K NULL selects SEVD-MUSIC (E_n from R itself, as in ssl_gsvd).
  * Uses the context's workspace (allocated on first use within the HBM budget). */
 ssl_status ssl_localize(ssl_ctx ctx, const ssl_c64 *X, int F, int T, int M, int64_t strideF,

@@ -1,4 +1,5 @@
-"""eq.5 with p = 2 through the signal subspace (ssl_ctx_set_projection, the FP32 path's default):
+"""eq.5 with p = 2 through the signal subspace (ssl_ctx_set_projection, the default at every table
+precision):
 den = |h|^2 - |L^{-1} E_s^H h|^2 in FP64.  Against the noise-vector projection and the FP64
 oracle's eq.5 (a sum over the noise vectors): P-bar within the FP32 bar, the same peaks; batches
 mixing blocks that use it and blocks that cannot (Ns > 3, GEVD, SEVD) equal each block alone;
@@ -208,6 +209,47 @@ def test_signal_form_per_bin(S, ctx, mode):
     say(f"  {mode}: worst per-bin P error {worst}")
     if n is not None:
         S.ssl_noise_destroy(n)
+
+
+@pytest.mark.parametrize("pname", ["bf16", "fp16"])
+def test_signal_form_16bit_table_per_bin(S, ctx, pname):
+    """The 16-bit paths on inputs that are exact in their type (X and H rounded to bf16 / fp16 on
+    the host, and the oracle given the same rounded values): the correlation's products are then
+    exact and the table's pairs widen exactly to FP64, so single bins must meet the FP32 bar (1e-4
+    per bin P), i.e. the 16-bit path adds no error beyond the rounding of its inputs."""
+    import torch
+    prec = S.SSL_BF16 if pname == "bf16" else S.SSL_FP16
+    dt = torch.bfloat16 if pname == "bf16" else torch.float16
+    w = synth.workload_paper(n_blocks=1)
+    X, _, _ = w.block(0)
+    H = w.steering_table()
+
+    def rounded(a):
+        r = torch.view_as_real(torch.from_numpy(np.ascontiguousarray(a))).to(dt).to(torch.float64)
+        return torch.view_as_complex(r.contiguous()).numpy()
+
+    Xr = rounded(X).astype(np.complex64)          # exact: 16-bit values are FP32 values
+    Hr = rounded(H).astype(np.complex64)
+    assert np.all(np.isfinite(Xr.view(np.float32))) and np.all(np.isfinite(Hr.view(np.float32)))
+    n, K = noise_handle(S, ctx, w)
+    r = oracle.localize(Xr, K, Hr, w.grid.n_az, w.grid.n_el, w.Ns, nthreads=16, want_P=True)
+    Xd = to_dev(Xr)
+    worst = 0.0
+    for f in (1, 7, 35, 183):
+        Hm = np.zeros_like(H)
+        Hm[f] = H[f]
+        Hd = torch.view_as_real(to_dev(Hm)).reshape(w.F, w.D, 2 * w.M).to(dt).contiguous()
+        o = outs(w, w.Ns)
+        S.ssl_localize(ctx, Xd, n, Hd, prec, w.grid.n_az, w.grid.n_el, w.Ns, 2, o["pk"], o["pv"],
+                       o["Pbar"], o["st"])
+        g = {k: to_host(v) for k, v in o.items()}
+        assert np.all(g["st"] == 0)
+        rel = float(np.max(np.abs(g["Pbar"].astype(np.float64) - r["P"][f]) / r["P"][f]))
+        worst = max(worst, rel)
+        say(f"  {pname} table, bin {f}: P rel {rel:.2e}")
+        assert rel <= 1e-4, (f, rel)
+    say(f"  {pname}: worst per-bin P error {worst:.2e} (exact 16-bit inputs)")
+    S.ssl_noise_destroy(n)
 
 
 def test_batch_conv_statistics(S, ctx):
