@@ -139,24 +139,27 @@ struct JacobiCfg {
 // v_k = vk, v_r = Vk[r] for r > k.  Rows >= M hold zeros in every column (so v_r = 0 there and
 // those rows stay zero), rows < k are left as they are (v_r = 0; rewritten unchanged).  Returns
 // the group-summed |x_r|^2 over rows > k of the result (the column's trailing norm for the next
-// step).
+// step).  A lane's rows are q + G j; the slots j < k / G lie above row k and are skipped, so the
+// loop runs over the slots from k / G on, numbered from 0: only the first of them holds rows <= k
+// and needs masks, and every access is an immediate offset from one base address per column.
 template <int MP, int G>
 __device__ __forceinline__ float apply_reflector(int pc, float2 vk, int k, float tau,
                                                  float2 *X, int c, int M, int q)
 {
     constexpr int R = MP / G;
     (void)M;
+    const int js = k / G, r0 = G * js + q;        // slot js holds row k; this lane's first row
+    const float2 *vp = X + at<MP>(pc, r0);
+    float2 *xp = X + at<MP>(c, r0);
     float wr = 0.f, wi = 0.f;
     float2 x[R], v[R];
-    const int js = k / G;                         // the slot holding row k
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        if (j < js) continue;                     // slot entirely above the reflector
-        const int r = q + G * j;
-        const float2 raw = X[at<MP>(pc, r)];
-        if (j == js) v[j] = (r > k) ? raw : ((r == k) ? vk : make_float2(0.f, 0.f));
-        else v[j] = raw;
-        x[j] = X[at<MP>(c, r)];
+        if (js + j >= R) break;                   // uniform
+        const float2 raw = vp[G * j];
+        if (j == 0) v[j] = (r0 > k) ? raw : ((r0 == k) ? vk : make_float2(0.f, 0.f));
+        else v[j] = raw;                          // rows > k
+        x[j] = xp[G * j];
         // conj(v) x
         wr = fmaf(v[j].x, x[j].x, fmaf(v[j].y, x[j].y, wr));
         wi = fmaf(v[j].x, x[j].y, fmaf(-v[j].y, x[j].x, wi));
@@ -166,14 +169,13 @@ __device__ __forceinline__ float apply_reflector(int pc, float2 vk, int k, float
     float tn = 0.f;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        if (j < js) continue;
-        const int r = q + G * j;
+        if (js + j >= R) break;
         // x -= v * (tau w)
         x[j].x = fmaf(-v[j].x, wr, fmaf(v[j].y, wi, x[j].x));
         x[j].y = fmaf(-v[j].x, wi, fmaf(-v[j].y, wr, x[j].y));
-        X[at<MP>(c, r)] = x[j];
+        xp[G * j] = x[j];
         const float n2 = fmaf(x[j].x, x[j].x, x[j].y * x[j].y);
-        if (j == js) tn += (r > k) ? n2 : 0.0f;
+        if (j == 0) tn += (r0 > k) ? n2 : 0.0f;
         else tn += n2;
     }
     return group_sum<G>(tn);
@@ -188,18 +190,20 @@ __device__ __forceinline__ void apply_reflector2(int pc, float2 vk, int k, float
                                                  float &tn0, float &tn1)
 {
     constexpr int R = MP / G;
+    const int js = k / G, r0 = G * js + q;
+    const float2 *vp = X + at<MP>(pc, r0);
+    float2 *xp0 = X + at<MP>(c0, r0);
+    float2 *xp1 = X + at<MP>(c1, r0);
     float wr0 = 0.f, wi0 = 0.f, wr1 = 0.f, wi1 = 0.f;
     float2 x0[R], x1[R], v[R];
-    const int js = k / G;                         // the slot holding row k
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        if (j < js) continue;
-        const int r = q + G * j;
-        const float2 raw = X[at<MP>(pc, r)];
-        if (j == js) v[j] = (r > k) ? raw : ((r == k) ? vk : make_float2(0.f, 0.f));
+        if (js + j >= R) break;
+        const float2 raw = vp[G * j];
+        if (j == 0) v[j] = (r0 > k) ? raw : ((r0 == k) ? vk : make_float2(0.f, 0.f));
         else v[j] = raw;
-        x0[j] = X[at<MP>(c0, r)];
-        x1[j] = X[at<MP>(c1, r)];
+        x0[j] = xp0[G * j];
+        x1[j] = xp1[G * j];
         wr0 = fmaf(v[j].x, x0[j].x, fmaf(v[j].y, x0[j].y, wr0));
         wi0 = fmaf(v[j].x, x0[j].y, fmaf(-v[j].y, x0[j].x, wi0));
         wr1 = fmaf(v[j].x, x1[j].x, fmaf(v[j].y, x1[j].y, wr1));
@@ -212,19 +216,18 @@ __device__ __forceinline__ void apply_reflector2(int pc, float2 vk, int k, float
     float s0 = 0.f, s1 = 0.f;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        if (j < js) continue;
-        const int r = q + G * j;
+        if (js + j >= R) break;
         x0[j].x = fmaf(-v[j].x, wr0, fmaf(v[j].y, wi0, x0[j].x));
         x0[j].y = fmaf(-v[j].x, wi0, fmaf(-v[j].y, wr0, x0[j].y));
         x1[j].x = fmaf(-v[j].x, wr1, fmaf(v[j].y, wi1, x1[j].x));
         x1[j].y = fmaf(-v[j].x, wi1, fmaf(-v[j].y, wr1, x1[j].y));
-        X[at<MP>(c0, r)] = x0[j];
-        if (two) X[at<MP>(c1, r)] = x1[j];
+        xp0[G * j] = x0[j];
+        if (two) xp1[G * j] = x1[j];
         const float n0 = fmaf(x0[j].x, x0[j].x, x0[j].y * x0[j].y);
         const float n1 = fmaf(x1[j].x, x1[j].x, x1[j].y * x1[j].y);
-        if (j == js) {
-            s0 += (r > k) ? n0 : 0.0f;
-            s1 += (r > k) ? n1 : 0.0f;
+        if (j == 0) {
+            s0 += (r0 > k) ? n0 : 0.0f;
+            s1 += (r0 > k) ? n1 : 0.0f;
         } else {
             s0 += n0;
             s1 += n1;
