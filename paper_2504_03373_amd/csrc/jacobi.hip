@@ -155,7 +155,10 @@ __device__ __forceinline__ float apply_reflector(int pc, float2 vk, int k, float
     float2 x[R], v[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        if (js + j >= R) break;                   // uniform
+        if (js + j >= R) {                        // uniform, and so for every later j
+            if constexpr (R <= 8) break;          // (R = 16 stays unrolled only with continue)
+            else continue;
+        }
         const float2 raw = vp[G * j];
         if (j == 0) v[j] = (r0 > k) ? raw : ((r0 == k) ? vk : make_float2(0.f, 0.f));
         else v[j] = raw;                          // rows > k
@@ -169,7 +172,10 @@ __device__ __forceinline__ float apply_reflector(int pc, float2 vk, int k, float
     float tn = 0.f;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        if (js + j >= R) break;
+        if (js + j >= R) {
+            if constexpr (R <= 8) break;
+            else continue;
+        }
         // x -= v * (tau w)
         x[j].x = fmaf(-v[j].x, wr, fmaf(v[j].y, wi, x[j].x));
         x[j].y = fmaf(-v[j].x, wi, fmaf(-v[j].y, wr, x[j].y));
@@ -198,7 +204,10 @@ __device__ __forceinline__ void apply_reflector2(int pc, float2 vk, int k, float
     float2 x0[R], x1[R], v[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        if (js + j >= R) break;
+        if (js + j >= R) {
+            if constexpr (R <= 8) break;
+            else continue;
+        }
         const float2 raw = vp[G * j];
         if (j == 0) v[j] = (r0 > k) ? raw : ((r0 == k) ? vk : make_float2(0.f, 0.f));
         else v[j] = raw;
@@ -216,7 +225,10 @@ __device__ __forceinline__ void apply_reflector2(int pc, float2 vk, int k, float
     float s0 = 0.f, s1 = 0.f;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        if (js + j >= R) break;
+        if (js + j >= R) {
+            if constexpr (R <= 8) break;
+            else continue;
+        }
         x0[j].x = fmaf(-v[j].x, wr0, fmaf(v[j].y, wi0, x0[j].x));
         x0[j].y = fmaf(-v[j].x, wi0, fmaf(-v[j].y, wr0, x0[j].y));
         x1[j].x = fmaf(-v[j].x, wr1, fmaf(v[j].y, wi1, x1[j].x));
