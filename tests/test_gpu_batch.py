@@ -2,7 +2,7 @@
 
 * every block's Pbar / peaks / status are bit-identical to ssl_localize on that block alone,
   with graphs on (first capture and later replays, interleaved with unrelated GPU work), with
-  graphs off and with per-kernel timing on;
+  graphs off and with per-kernel timing on, and at bf16 / fp16 (16-bit tables);
 * uneven blocks match the FP64 oracle (Pbar within 1e-4; no near-tie within the measured error
   and the returned peaks identical).
 """
@@ -118,6 +118,39 @@ def test_batch_bit_identical_to_single(env):
     kt = S.ssl_ctx_timing_read(ctx, reset=True)
     assert same(got, ref)
     assert kt["jacobi"][0] == len({min(64, max(8, 1 << (b["M"] - 1).bit_length())) for b in blocks})
+
+
+@pytest.mark.parametrize("pname", ["bf16", "fp16"])
+def test_batch_bit_identical_to_single_16bit(env, pname):
+    """The same uneven batch with 16-bit steering tables and correlation inputs (every block has
+    Ns <= 3, so all take the signal-subspace projection on a 16-bit table): bit-identical to
+    ssl_localize on each block alone at the same precision."""
+    import torch
+    S, ctx, blocks = env
+    prec = S.SSL_BF16 if pname == "bf16" else S.SSL_FP16
+    dt = torch.bfloat16 if pname == "bf16" else torch.float16
+    tabs = {}
+    for b in blocks:
+        key = (b["M"], b["F"])
+        if key not in tabs:
+            Hd = b["s"]["Hd"]
+            F, D, M = Hd.shape
+            tabs[key] = torch.view_as_real(Hd).reshape(F, D, 2 * M).to(dt).contiguous()
+    say(f"ssl_localize x{len(blocks)} at {pname} (single-block reference)")
+    ref_o = outputs(blocks)
+    for b, o in zip(blocks, ref_o):
+        S.ssl_localize(ctx, b["Xd"], b["s"]["noise"], tabs[(b["M"], b["F"])], prec, 72, 19,
+                       b["Ns"], 2, o["pk"], o["pv"], o["Pbar"], o["st"])
+    ref = [{k: to_host(v) for k, v in o.items()} for o in ref_o]
+    assert all(np.all(r["st"] == 0) for r in ref)
+    for rep in range(2):
+        say(f"ssl_localize_batch at {pname}, call {rep}")
+        outs = outputs(blocks)
+        descs = [S.block_desc(b["Xd"], b["s"]["noise"], tabs[(b["M"], b["F"])], 72, 19, b["Ns"],
+                              o["pk"], o["pv"], o["Pbar"], o["st"]) for b, o in zip(blocks, outs)]
+        S.ssl_localize_batch(ctx, descs, prec, 2)
+        got = [{k: to_host(v) for k, v in o.items()} for o in outs]
+        assert same(got, ref), rep
 
 
 def test_batch_subset_and_reorder(env):
